@@ -1,0 +1,362 @@
+"""Seeded synthetic workloads for the binned Poisson spectral fit.
+
+This module is shared by the CPU oracle tests and the GPU path.  It holds
+none of the likelihood arithmetic: it builds the *inputs* of a fit
+(true-energy spectra, reco binning, data histograms, windows, starting
+points) and simulates data with its own "nature" detector model.
+
+Nature versus the fitted model
+------------------------------
+The fitted model (section 2.3 and Eq.2 of the paper) evaluates the detector
+response at the reco-bin midpoint on the visible-energy x true-energy mesh.
+The data here are drawn from exact reco-bin integrals (CDF differences from
+scipy.special) of the same synthetic detector, with the quenched light
+yield obtained by Gauss-Legendre quadrature of Birks' law rather than a
+closed form.  So the data are statistically consistent with the model but
+come from different arithmetic; nothing here is compared against either
+implementation.
+
+Seeds: numpy SeedSequence([1812, 5686, config, stream, toy]) into PCG64,
+stream 0 = data counts, 1 = toy parameters / starting points, 2 = PSD shapes.
+
+Units: the Gaussian-in-energy family (GAUSS_E) uses keV on both axes; the
+photoelectron families use MeV on the true axis and photoelectrons (pe) on
+the reco axis.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy import special
+
+GAUSS_E, GAUSS_PE, GAMMA_PE = 0, 1, 2
+M_E = 0.51099895  # electron mass, MeV
+BIRKS_A = 2.0     # synthetic stopping-power constant, MeV^1.5/cm
+
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(16)
+
+
+@dataclass
+class Model:
+    """One fit problem: inputs of the likelihood plus the truth used to make it."""
+    name: str
+    family: int
+    n_true: int
+    e_lo: float
+    e_step: float
+    spectra: np.ndarray          # [S, n_true] float64, row sums 1 (zeros for line species)
+    line_energy: np.ndarray      # [S] float64, NaN for grid species
+    reco_edges: np.ndarray       # [n_reco + 1]
+    exposure: np.ndarray         # [D]
+    counts: np.ndarray           # [D, n_reco, max(n_psd, 1)]
+    win_lo: int
+    win_hi: int
+    pull_centre: np.ndarray      # [P]
+    pull_sigma: np.ndarray       # [P], <= 0 means no pull
+    theta_true: np.ndarray       # [P]
+    theta0: np.ndarray           # [P] starting point of fits
+    fd_scale: np.ndarray         # [P] parameter scales (FD steps, initial metric)
+    birks_A: float = BIRKS_A
+    psd_edges: np.ndarray | None = None   # [n_psd + 1]
+    psd_mix: np.ndarray | None = None     # [S, 5] = (w1, mean1, sigma1, mean2, sigma2)
+    species: list = field(default_factory=list)
+
+    @property
+    def n_species(self) -> int:
+        return self.spectra.shape[0]
+
+    @property
+    def n_reco(self) -> int:
+        return len(self.reco_edges) - 1
+
+    @property
+    def n_psd(self) -> int:
+        return 0 if self.psd_edges is None else len(self.psd_edges) - 1
+
+    @property
+    def n_datasets(self) -> int:
+        return len(self.exposure)
+
+    @property
+    def n_params(self) -> int:
+        return self.n_species + (2 if self.family == GAUSS_E else 5) + (3 if self.n_psd else 0)
+
+    def replace(self, **kw) -> "Model":
+        return dataclasses.replace(self, **kw)
+
+
+def _rng(config: int, stream: int, toy: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([1812, 5686, config, stream, toy])))
+
+
+# ---------------------------------------------------------------- spectra ---
+def cell_edges(n_true: int, e_lo: float, e_step: float) -> np.ndarray:
+    return e_lo + e_step * np.arange(n_true + 1, dtype=np.float64)
+
+
+def _normalise(w: np.ndarray) -> np.ndarray:
+    w = np.maximum(w, 0.0)
+    return w / w.sum()
+
+
+def spectrum_flat(edges):
+    return _normalise(np.diff(edges))
+
+
+def spectrum_exp(edges, slope):
+    return _normalise(slope * (np.exp(-edges[:-1] / slope) - np.exp(-edges[1:] / slope)))
+
+
+def spectrum_gauss(edges, mean, width):
+    return _normalise(special.ndtr((edges[1:] - mean) / width) - special.ndtr((edges[:-1] - mean) / width))
+
+
+def spectrum_beta(edges, q_value):
+    """Allowed beta shape p*E*(Q-T)^2 (T kinetic, E = T + m_e, no Fermi function),
+    integrated over each cell with 16-point Gauss-Legendre."""
+    a = np.minimum(edges[:-1], q_value)
+    b = np.minimum(edges[1:], q_value)
+    half = 0.5 * (b - a)
+    mid = 0.5 * (b + a)
+    t = mid[:, None] + half[:, None] * _GL_X[None, :]
+    e_tot = t + M_E
+    p = np.sqrt(np.maximum(t * (t + 2 * M_E), 0.0))
+    f = p * e_tot * (q_value - t) ** 2
+    return _normalise((f * _GL_W[None, :]).sum(axis=1) * half)
+
+
+# ------------------------------------------------------------------ nature ---
+def _nature_light(e_mev: np.ndarray, ly: float, kb: float, birks_a: float) -> np.ndarray:
+    """Quenched light LY * int_0^E dE'/(1 + kB*A/sqrt(E')) by Gauss-Legendre in u = sqrt(E')
+    (integrand 2u^2/(u + kB*A)), accumulated over [0, sqrt(E)]."""
+    c = kb * birks_a
+    u_hi = np.sqrt(np.asarray(e_mev, dtype=np.float64))
+    # split [0, u_hi] into 8 panels for accuracy at large u
+    out = np.zeros_like(u_hi)
+    for p in range(8):
+        lo = u_hi * p / 8.0
+        hi = u_hi * (p + 1) / 8.0
+        half = 0.5 * (hi - lo)
+        mid = 0.5 * (hi + lo)
+        u = mid[..., None] + half[..., None] * _GL_X
+        out += (2.0 * u * u / (u + c) * _GL_W).sum(axis=-1) * half
+    return ly * out
+
+
+def _nature_moments(model_family: int, e: np.ndarray, resp: np.ndarray, birks_a: float):
+    if model_family == GAUSS_E:
+        a, b = resp
+        return e.copy(), np.sqrt(a * a + b * e)
+    ly, kb, a, b, c = resp
+    m = _nature_light(e, ly, kb, birks_a)
+    return m, np.sqrt(a * a + b * m + c * c * m * m)
+
+
+def _nature_bin_probs(family: int, edges: np.ndarray, m: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """[n_reco, n_cells] probability that a deposit with response moments (m, s) lands in each bin."""
+    if family == GAMMA_PE:
+        k = (m / s) ** 2
+        th = s * s / m
+        cdf = special.gammainc(k[None, :], np.maximum(edges, 0.0)[:, None] / th[None, :])
+    else:
+        cdf = special.ndtr((edges[:, None] - m[None, :]) / s[None, :])
+    return np.diff(cdf, axis=0)
+
+
+def nature_species_hist(model: Model, resp: np.ndarray) -> np.ndarray:
+    """Expected reco histogram [n_reco, S] per unit rate for each species."""
+    centres = model.e_lo + model.e_step * (np.arange(model.n_true) + 0.5)
+    m, s = _nature_moments(model.family, centres, resp, model.birks_A)
+    # chunk the cells to bound memory
+    out = np.zeros((model.n_reco, model.n_species))
+    grid = np.isnan(model.line_energy)
+    for c0 in range(0, model.n_true, 1000):
+        sl = slice(c0, min(c0 + 1000, model.n_true))
+        pr = _nature_bin_probs(model.family, model.reco_edges, m[sl], s[sl])
+        out[:, grid] += pr @ model.spectra[grid][:, sl].T
+    for sp in np.nonzero(~grid)[0]:
+        ml, sl_ = _nature_moments(model.family, np.array([model.line_energy[sp]]), resp, model.birks_A)
+        out[:, sp] = _nature_bin_probs(model.family, model.reco_edges, ml, sl_)[:, 0]
+    return out
+
+
+def nature_psd_probs(psd_edges: np.ndarray, psd_mix: np.ndarray, nuis=(0.0, 1.0, 0.0)) -> np.ndarray:
+    """[S, n_psd] exact bin integrals of the two-Gaussian pulse-shape mixture, renormalised on the range."""
+    delta, kappa, eta = nuis
+    w1 = psd_mix[:, 0]
+    w1 = 1.0 / (1.0 + np.exp(-(np.log(w1 / (1 - w1)) + eta)))
+    out = np.zeros((psd_mix.shape[0], len(psd_edges) - 1))
+    for comp, w in ((1, w1), (3, 1.0 - w1)):
+        mu = psd_mix[:, comp] + delta
+        sg = psd_mix[:, comp + 1] * kappa
+        cdf = special.ndtr((psd_edges[None, :] - mu[:, None]) / sg[:, None])
+        out += w[:, None] * np.diff(cdf, axis=1)
+    return out / out.sum(axis=1, keepdims=True)
+
+
+def nature_expected(model: Model, theta: np.ndarray, species_hist: np.ndarray | None = None) -> np.ndarray:
+    """Nature's expected counts [D, n_reco, max(n_psd,1)] at parameters theta."""
+    S = model.n_species
+    nr = 2 if model.family == GAUSS_E else 5
+    if species_hist is None:
+        species_hist = nature_species_hist(model, theta[S:S + nr])
+    rates = theta[:S]
+    if model.n_psd:
+        P = nature_psd_probs(model.psd_edges, model.psd_mix, theta[S + nr:S + nr + 3])
+        mu1 = np.einsum("js,s,sk->jk", species_hist, rates, P)
+    else:
+        mu1 = (species_hist @ rates)[:, None]
+    return model.exposure[:, None, None] * mu1[None, :, :]
+
+
+def draw_counts(mu: np.ndarray, rng: np.random.Generator) -> np.ndarray:
+    return rng.poisson(mu).astype(np.float64)
+
+
+# ----------------------------------------------------------------- configs ---
+def _scales_pe(S, rates):
+    return np.concatenate([np.sqrt(rates), [5.0, 1e-3, 0.4, 0.05, 3e-3]])
+
+
+def config0() -> Model:
+    """Gaussian line + flat + exponential on a 500 x 5 keV true grid, Gaussian response
+    sigma^2 = a^2 + b*E, 200 reco bins of 10 keV (the paper's Gaussian-signal-plus-flat
+    example, section 4.1, with an exponential added)."""
+    edges_t = cell_edges(500, 0.0, 5.0)
+    spectra = np.stack([spectrum_gauss(edges_t, 862.0, 1.0), spectrum_flat(edges_t),
+                        spectrum_exp(edges_t, 300.0)])
+    rates = np.array([5e4, 2e4, 1e4])
+    theta = np.concatenate([rates, [10.0, 5.0]])
+    m = Model(name="c0", family=GAUSS_E, n_true=500, e_lo=0.0, e_step=5.0, spectra=spectra,
+              line_energy=np.full(3, np.nan), reco_edges=10.0 * np.arange(201.0),
+              exposure=np.ones(1), counts=np.zeros((1, 200, 1)), win_lo=0, win_hi=200,
+              pull_centre=theta.copy(), pull_sigma=np.zeros(5), theta_true=theta,
+              theta0=theta * np.array([1.1, 0.9, 1.1, 1.2, 0.8]),
+              fd_scale=np.concatenate([np.sqrt(rates), [1.0, 0.5]]),
+              species=["gauss862", "flat", "exp300"])
+    m.counts = draw_counts(nature_expected(m, theta), _rng(0, 0))
+    return m
+
+
+C1_LINES = [(0.250, 2e4), (0.862, 1e4), (1.460, 5e3), (2.615, 2e3)]
+C1_BETAS = [(0.200, 1e5), (0.760, 8e4), (1.320, 5e4), (1.880, 3e4), (2.440, 2e4), (3.000, 1e4)]
+C1_EXPS = [(0.150, 4e4), (0.600, 1e4)]
+C1_RESP = np.array([500.0, 0.011, 2.0, 1.15, 0.015])
+
+
+def _c1_shape(n_true=4000, e_step=0.00075, family=GAMMA_PE, lines=C1_LINES, betas=C1_BETAS, exps=C1_EXPS,
+              n_reco=900, bin_w=1.6):
+    edges_t = cell_edges(n_true, 0.0, e_step)
+    rows, le, rates, names = [], [], [], []
+    for e0, r in lines:
+        rows.append(np.zeros(n_true)); le.append(e0); rates.append(r); names.append(f"line{e0:g}")
+    for q, r in betas:
+        rows.append(spectrum_beta(edges_t, q)); le.append(np.nan); rates.append(r); names.append(f"beta{q:g}")
+    for sl, r in exps:
+        rows.append(spectrum_exp(edges_t, sl)); le.append(np.nan); rates.append(r); names.append(f"exp{sl:g}")
+    return np.stack(rows), np.array(le), np.array(rates), names, bin_w * np.arange(n_reco + 1.0)
+
+
+def config1(family: int = GAMMA_PE) -> Model:
+    """Borexino-scale: 12 species (4 lines, 6 betas, 2 exponentials) on 4000 x 0.75 keV,
+    light yield + Birks quenching + resolution (a, b, c) in photoelectrons, 900 bins of 1.6 pe."""
+    spectra, le, rates, names, edges = _c1_shape(family=family)
+    S = len(rates)
+    theta = np.concatenate([rates, C1_RESP])
+    ps = np.zeros(S + 5)
+    pc = theta.copy()
+    ps[S + 1] = 0.0011   # kB
+    ps[S + 2] = 0.4      # a
+    ps[S - 1] = 500.0    # rate of the 600 keV exponential background
+    m = Model(name="c1" if family == GAMMA_PE else "c1g", family=family, n_true=4000, e_lo=0.0,
+              e_step=0.00075, spectra=spectra, line_energy=le, reco_edges=edges,
+              exposure=np.ones(1), counts=np.zeros((1, 900, 1)), win_lo=0, win_hi=900,
+              pull_centre=pc, pull_sigma=ps, theta_true=theta,
+              theta0=theta * _rng(1, 1).uniform(0.9, 1.1, S + 5),
+              fd_scale=_scales_pe(S, rates), species=names)
+    m.counts = draw_counts(nature_expected(m, theta), _rng(1, 0))
+    return m
+
+
+def config2() -> Model:
+    """Config 1 in 2-D (900 energy x 50 pulse-shape bins), 3 datasets with exposures 1:0.6:0.3."""
+    base = config1()
+    S = base.n_species
+    g = _rng(2, 2)
+    mix = np.stack([g.uniform(0.3, 0.7, S), g.uniform(0.2, 0.8, S), g.uniform(0.05, 0.15, S),
+                    g.uniform(0.2, 0.8, S), g.uniform(0.05, 0.15, S)], axis=1)
+    theta = np.concatenate([base.theta_true, [0.0, 1.0, 0.0]])
+    pc = np.concatenate([base.pull_centre, [0.0, 1.0, 0.0]])
+    ps = np.concatenate([base.pull_sigma, np.zeros(3)])
+    m = base.replace(name="c2", psd_edges=np.linspace(0.0, 1.0, 51), psd_mix=mix,
+                     exposure=np.array([1.0, 0.6, 0.3]), counts=np.zeros((3, 900, 50)),
+                     pull_centre=pc, pull_sigma=ps, theta_true=theta,
+                     theta0=np.concatenate([base.theta0, [0.0, 1.0, 0.0]]),
+                     fd_scale=np.concatenate([base.fd_scale, [0.01, 0.01, 0.01]]))
+    m.counts = draw_counts(nature_expected(m, theta), _rng(2, 0))
+    return m
+
+
+def config3(n_toys: int = 4096, base: Model | None = None) -> list[Model]:
+    """Toys of config 1: rates drawn +-20% uniform around nominal, response at nominal,
+    own contiguous window of L ~ U{200..900} bins starting at lo ~ U{0..900-L}; fits start
+    at the config-1 nominal point.  The spectra and binning arrays are shared objects."""
+    base = config1() if base is None else base
+    S = base.n_species
+    hist = nature_species_hist(base, base.theta_true[S:])
+    toys = []
+    for t in range(n_toys):
+        g = _rng(3, 1, t)
+        th = base.theta_true.copy()
+        th[:S] *= g.uniform(0.8, 1.2, S)
+        L = int(g.integers(200, 901))
+        lo = int(g.integers(0, 900 - L + 1))
+        counts = draw_counts(nature_expected(base, th, hist), _rng(3, 0, t))
+        toys.append(base.replace(name=f"c3/{t}", counts=counts, win_lo=lo, win_hi=lo + L,
+                                 theta_true=th, theta0=base.theta_true.copy()))
+    return toys
+
+
+def asimov(model: Model, mu: np.ndarray) -> Model:
+    """Same model with data replaced by the given expectation (no fluctuation)."""
+    return model.replace(counts=np.asarray(mu, dtype=np.float64).reshape(model.counts.shape).copy())
+
+
+def small_gamma_model(n_true=300, n_reco=64, seed=7, n_psd=0, n_datasets=1, family=GAMMA_PE) -> Model:
+    """A small photoelectron-family model (lines, betas, exponentials) that the oracle
+    evaluates in milliseconds; used for oracle pins and ragged GPU parity cases."""
+    e_step = 3.0 / n_true
+    spectra, le, rates, names, _ = _c1_shape(n_true=n_true, e_step=e_step, family=family,
+                                             lines=[(0.862, 1e4), (1.46, 5e3)],
+                                             betas=[(0.76, 5e4), (1.88, 3e4)], exps=[(0.6, 1e4)])
+    edges = np.linspace(0.0, 1440.0, n_reco + 1)
+    S = len(rates)
+    theta = np.concatenate([rates, C1_RESP])
+    g = _rng(100 + seed, 2)
+    m = Model(name=f"small{seed}", family=family, n_true=n_true, e_lo=0.0, e_step=e_step,
+              spectra=spectra, line_energy=le, reco_edges=edges, exposure=np.ones(n_datasets),
+              counts=np.zeros((n_datasets, n_reco, max(n_psd, 1))), win_lo=0, win_hi=n_reco,
+              pull_centre=theta.copy(), pull_sigma=np.zeros(S + 5), theta_true=theta,
+              theta0=theta.copy(), fd_scale=_scales_pe(S, rates), species=names)
+    if n_psd:
+        mix = np.stack([g.uniform(0.3, 0.7, S), g.uniform(0.2, 0.8, S), g.uniform(0.05, 0.15, S),
+                        g.uniform(0.2, 0.8, S), g.uniform(0.05, 0.15, S)], axis=1)
+        m = m.replace(psd_edges=np.linspace(0.0, 1.0, n_psd + 1), psd_mix=mix,
+                      exposure=np.array([1.0, 0.6, 0.3][:n_datasets]),
+                      theta_true=np.concatenate([theta, [0.0, 1.0, 0.0]]),
+                      theta0=np.concatenate([theta, [0.0, 1.0, 0.0]]),
+                      pull_centre=np.concatenate([theta, [0.0, 1.0, 0.0]]),
+                      pull_sigma=np.zeros(S + 8),
+                      fd_scale=np.concatenate([_scales_pe(S, rates), [0.01, 0.01, 0.01]]))
+    else:
+        m = m.replace(exposure=np.array([1.0, 0.6, 0.3][:n_datasets]))
+    m.counts = draw_counts(nature_expected(m, m.theta_true), _rng(100 + seed, 0))
+    return m
+
+
+def offset_point(model: Model, sigma_mult: float = 2.0, seed: int = 0) -> np.ndarray:
+    """An off-minimum parameter point theta_true + sigma_mult * scale * u, u ~ U(-1, 1)."""
+    u = _rng(200 + seed, 1).uniform(-1.0, 1.0, model.n_params)
+    return model.theta_true + sigma_mult * model.fd_scale * u

@@ -1,0 +1,698 @@
+/* oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * The plain CPU definition of what the GPU library computes: the binned
+ * multi-observable Poisson negative log-likelihood of GooStats
+ * (arXiv:1812.05686), its gradient, and a BFGS fit driver.  Everything is
+ * plain nested loops in the order the definitions are written, in long
+ * double where the gamma-family exponent cancels.  Only tests, the smoke
+ * check and the CPU-baseline leg of the benchmark use it; it shares no
+ * code, header or table with the GPU library.
+ *
+ * Readings of points the paper leaves open (each is listed in the design doc):
+ *  R1  -ln L = sum (mu - n ln mu) + 1/2 sum ((p - c)/sigma)^2 (Eq.4 with the
+ *      sign fixed, ln n! dropped, and the factor 1/2 so that a change of 0.5
+ *      in -ln L is one standard deviation).
+ *  R2  n = 0 contributes mu (0 ln 0 = 0); mu < 0, or mu = 0 with n > 0, is a
+ *      domain error: -ln L = +inf and status DOMAIN.
+ *  R3  reco bin content = bin width x response at the bin midpoint (the
+ *      response evaluated on the visible x true energy mesh, section 2.5).
+ *  R4  true spectra are histograms on a uniform cell-centred grid with rows
+ *      summing to 1; a rate is the expected count at unit exposure.
+ *  R5  a monoenergetic (AnaPeak, section 4.3) species is a delta at exactly
+ *      its line energy.
+ *  R6  exposure multiplies all rates of a dataset (section 4.1 input list).
+ *  R7  quenching: Birks' law integrated with dE/dx = A/sqrt(E):
+ *      Q = 1 - 2/y + 2 ln(1+y)/y^2, y = sqrt(E)/(kB A); light m = LY Q E.
+ *  R8  response shapes (section 2.3 names the families without formulas):
+ *      Gaussian N(x; m, s^2), or the gamma density with the same mean and
+ *      variance (generalized gamma with unit power).
+ *  R9  resolution: s^2 = a^2 + b E (energy family), s^2 = a^2 + b m + c^2 m^2
+ *      (photoelectron families).
+ *  R12 secondary observable (section 2.4): per-species two-Gaussian mixture at
+ *      the bin midpoint, renormalised over the bins, with nuisances
+ *      (mean shift delta, width scale kappa, logit shift eta of weight 1).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef long double ld;
+static const ld PI_L = 3.141592653589793238462643383279502884L;
+
+static int n_resp(int fam) { return fam == ORC_GAUSS_E ? 2 : 5; }
+
+int32_t orc_num_params(const orc_model *M) {
+  return M->n_species + n_resp(M->family) + (M->n_psd > 0 ? 3 : 0);
+}
+
+/* ---------------------------------------------------------------- R7 ---- */
+/* Q(E) = (1/E) int_0^E dE' / (1 + kB A / sqrt(E')).  With u = sqrt(E')/(kB A)
+ * this is (2/y^2) int_0^y u^2/(1+u) du = 1 - 2/y + 2 ln(1+y)/y^2.  For tiny y
+ * the power series 2 sum_n (-1)^(n+1) y^n/(n+2) avoids the cancellation. */
+static ld quench_l(ld E, ld kB, ld A, ld *dQ_dkB) {
+  if (!(E > 0)) {
+    if (dQ_dkB) *dQ_dkB = 0;
+    return 0;
+  }
+  ld y = sqrtl(E) / (kB * A);
+  ld Q, dQdy;
+  if (y < 1e-3L) {
+    ld yn = 1;
+    Q = 0;
+    dQdy = 0;
+    for (int n = 1; n <= 12; n++) {
+      ld sgn = (n & 1) ? 1 : -1;
+      dQdy += sgn * 2.0L * n * yn / (n + 2);
+      yn *= y;
+      Q += sgn * 2.0L * yn / (n + 2);
+    }
+  } else {
+    ld L = log1pl(y);
+    Q = 1 - 2 / y + 2 * L / (y * y);
+    dQdy = 2 / (y * y) - 4 * L / (y * y * y) + 2 / (y * y * (1 + y));
+  }
+  if (dQ_dkB) *dQ_dkB = dQdy * (-y / kB); /* dy/dkB = -y/kB */
+  return Q;
+}
+
+double orc_quench(double e, double kB, double A) { return (double)quench_l(e, kB, A, NULL); }
+double orc_dquench_dkB(double e, double kB, double A) {
+  ld d;
+  quench_l(e, kB, A, &d);
+  return (double)d;
+}
+
+/* Digamma: recurrence psi(x) = psi(x+1) - 1/x up to x >= 10 (Abramowitz &
+ * Stegun 6.3.5), then the asymptotic series A&S 6.3.18 through x^-14. */
+static ld digamma_l(ld x) {
+  ld r = 0;
+  while (x < 10) {
+    r -= 1 / x;
+    x += 1;
+  }
+  ld f = 1 / (x * x);
+  ld tail = f * (1.0L / 12 - f * (1.0L / 120 - f * (1.0L / 252 - f * (1.0L / 240 - f * (1.0L / 132 - f * (691.0L / 32760 - f / 12))))));
+  return r + logl(x) - 0.5L / x - tail;
+}
+double orc_digamma(double x) { return (double)digamma_l(x); }
+
+/* ------------------------------------------------------- R7, R9 moments -- */
+typedef struct {
+  ld m, s;
+  ld dm[5], ds[5]; /* derivatives w.r.t. the response parameters */
+} mom_t;
+
+/* Mean m and width s of the response to a deposit of true energy E, with
+ * their derivatives (section 4.3: light yield, non-linearity and resolution
+ * are fit parameters).  Returns 0 when the parameters give no valid response. */
+static int moments_l(int fam, const double *resp, double A, ld E, mom_t *o) {
+  memset(o, 0, sizeof *o);
+  if (fam == ORC_GAUSS_E) {
+    ld a = resp[0], b = resp[1];
+    ld s2 = a * a + b * E;
+    if (!(s2 > 0) || !isfinite((double)s2)) return 0;
+    o->m = E;
+    o->s = sqrtl(s2);
+    o->ds[0] = a / o->s;
+    o->ds[1] = E / (2 * o->s);
+    return 1;
+  }
+  ld LY = resp[0], kB = resp[1], a = resp[2], b = resp[3], c = resp[4];
+  if (!(kB > 0)) return 0;
+  ld dQ;
+  ld Q = quench_l(E, kB, A, &dQ);
+  ld m = LY * Q * E;
+  ld s2 = a * a + b * m + c * c * m * m;
+  if (!(s2 > 0) || !isfinite((double)s2)) return 0;
+  if (fam == ORC_GAMMA_PE && !(m > 0)) return 0;
+  ld s = sqrtl(s2);
+  o->m = m;
+  o->s = s;
+  o->dm[0] = Q * E;
+  o->dm[1] = LY * E * dQ;
+  ld dsdm = (b + 2 * c * c * m) / (2 * s);
+  o->ds[0] = dsdm * o->dm[0];
+  o->ds[1] = dsdm * o->dm[1];
+  o->ds[2] = a / s;
+  o->ds[3] = m / (2 * s);
+  o->ds[4] = c * m * m / s;
+  return 1;
+}
+
+int32_t orc_moments(int32_t family, const double *resp, double A, double E, double *m, double *s) {
+  mom_t o;
+  int ok = moments_l(family, resp, A, E, &o);
+  *m = (double)o.m;
+  *s = (double)o.s;
+  return ok;
+}
+
+/* ------------------------------------------------------------ R8 shapes -- */
+/* Per-cell constants of the response density, computed once per true cell. */
+typedef struct {
+  ld m, s;
+  ld k, th, lgk, lth, psik; /* gamma family */
+  ld norm;                  /* Gaussian family: 1/(s sqrt(2 pi)) */
+} dens_t;
+
+static void dens_prep(int fam, ld m, ld s, dens_t *d) {
+  d->m = m;
+  d->s = s;
+  if (fam == ORC_GAMMA_PE) {
+    ld s2 = s * s;
+    d->k = m * m / s2;
+    d->th = s2 / m;
+    d->lgk = lgammal(d->k);
+    d->lth = logl(d->th);
+    d->psik = digamma_l(d->k);
+  } else {
+    d->norm = 1 / (s * sqrtl(2 * PI_L));
+  }
+}
+
+/* r(x | m, s) and d ln r / dm, d ln r / ds.  Gamma: shape k = m^2/s^2, scale
+ * th = s^2/m, r = x^(k-1) exp(-x/th) / (Gamma(k) th^k) for x > 0. */
+static ld dens_eval(int fam, const dens_t *d, ld x, ld lx, ld *dm, ld *ds) {
+  if (fam == ORC_GAMMA_PE) {
+    if (!(x > 0)) {
+      if (dm) *dm = *ds = 0;
+      return 0;
+    }
+    ld r = expl((d->k - 1) * lx - x / d->th - d->lgk - d->k * d->lth);
+    if (dm) {
+      ld s2 = d->s * d->s, m = d->m;
+      ld dk = lx - d->psik - d->lth;            /* d ln r / dk     */
+      ld dth = x / (d->th * d->th) - d->k / d->th; /* d ln r / dtheta */
+      *dm = dk * (2 * m / s2) + dth * (-s2 / (m * m));
+      *ds = dk * (-2 * m * m / (s2 * d->s)) + dth * (2 * d->s / m);
+    }
+    return r;
+  }
+  ld z = (x - d->m) / d->s;
+  if (dm) {
+    *dm = z / d->s;
+    *ds = (z * z - 1) / d->s;
+  }
+  return d->norm * expl(-0.5L * z * z);
+}
+
+double orc_density(int32_t family, double x, double m, double s) {
+  dens_t d;
+  dens_prep(family, m, s, &d);
+  return (double)dens_eval(family, &d, x, x > 0 ? logl(x) : 0, NULL, NULL);
+}
+
+void orc_density_dms(int32_t family, double x, double m, double s, double *dm, double *ds) {
+  dens_t d;
+  ld a, b;
+  dens_prep(family, m, s, &d);
+  dens_eval(family, &d, x, x > 0 ? logl(x) : 0, &a, &b);
+  *dm = (double)a;
+  *ds = (double)b;
+}
+
+/* ---------------------------------------------------------- fold (Eq.2) -- */
+/* K_ji = dx_j * r(xbar_j | m_i, s_i) on the visible x true mesh (section 2.5),
+ * then F[j][s] = sum_i w_si K_ji over the grid cells of species s; a line
+ * species is a single cell at its energy with weight 1 (R5).  If dF is given
+ * it receives d F[j][s] / d resp_p as dF[(j*S + s)*nr + p].  Returns 0 if the
+ * response is invalid somewhere on the grid. */
+static int fold_l(const orc_model *M, const double *theta, ld *F, ld *dF) {
+  const int S = M->n_species, J = M->n_reco, fam = M->family, nr = n_resp(fam);
+  const double *resp = theta + S;
+  memset(F, 0, sizeof(ld) * (size_t)J * S);
+  if (dF) memset(dF, 0, sizeof(ld) * (size_t)J * S * nr);
+  ld *xb = malloc(sizeof(ld) * J), *dx = malloc(sizeof(ld) * J), *lx = malloc(sizeof(ld) * J);
+  ld *w = malloc(sizeof(ld) * S);
+  for (int j = 0; j < J; j++) {
+    double c = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;
+    xb[j] = c;
+    dx[j] = (ld)M->reco_edges[j + 1] - (ld)M->reco_edges[j];
+    lx[j] = c > 0 ? logl(c) : 0;
+  }
+  int n_grid = 0;
+  for (int s = 0; s < S; s++) n_grid += isnan(M->line_energy[s]) ? 1 : 0;
+  int ok = 1;
+  /* cells 0..n_true-1 are the grid; then one cell per line species */
+  for (int i = 0; i < M->n_true + S && ok; i++) {
+    int line_s = -1;
+    ld E;
+    if (i < M->n_true) {
+      if (n_grid == 0) continue;
+      int any = 0;
+      for (int s = 0; s < S; s++) {
+        w[s] = isnan(M->line_energy[s]) ? (ld)M->spectra[(size_t)s * M->n_true + i] : 0;
+        any |= w[s] != 0;
+      }
+      if (!any) continue;
+      E = (ld)(M->e_lo + (i + 0.5) * M->e_step);
+    } else {
+      line_s = i - M->n_true;
+      if (isnan(M->line_energy[line_s])) continue;
+      for (int s = 0; s < S; s++) w[s] = s == line_s;
+      E = (ld)M->line_energy[line_s];
+    }
+    mom_t mo;
+    if (!moments_l(fam, resp, M->birks_A, E, &mo)) {
+      ok = 0;
+      break;
+    }
+    dens_t d;
+    dens_prep(fam, mo.m, mo.s, &d);
+    for (int j = 0; j < J; j++) {
+      ld dlm, dls;
+      ld K = dx[j] * dens_eval(fam, &d, xb[j], lx[j], dF ? &dlm : NULL, dF ? &dls : NULL);
+      for (int s = 0; s < S; s++) {
+        if (w[s] == 0) continue;
+        F[(size_t)j * S + s] += w[s] * K;
+        if (dF)
+          for (int p = 0; p < nr; p++)
+            dF[((size_t)j * S + s) * nr + p] += w[s] * K * (dlm * mo.dm[p] + dls * mo.ds[p]);
+      }
+    }
+  }
+  free(xb);
+  free(dx);
+  free(lx);
+  free(w);
+  return ok;
+}
+
+int32_t orc_species_fold(const orc_model *M, const double *theta, double *F) {
+  size_t n = (size_t)M->n_reco * M->n_species;
+  ld *f = malloc(sizeof(ld) * n);
+  int ok = fold_l(M, theta, f, NULL);
+  for (size_t i = 0; i < n; i++) F[i] = (double)f[i];
+  free(f);
+  return ok;
+}
+
+/* ------------------------------------------------ secondary obs. (R12) -- */
+/* P[s][k] = p_sk / sum_k' p_sk', p_sk = dy_k (w1' N(ybar_k; mu1+delta, (kappa s1)^2)
+ * + (1-w1') N(ybar_k; mu2+delta, (kappa s2)^2)), w1' = sigmoid(logit(w1) + eta).
+ * dP[(s*K + k)*3 + v] = d P_sk / d (delta, kappa, eta)_v. */
+static int psd_l(const orc_model *M, const double *nu, ld *P, ld *dP) {
+  const int S = M->n_species, K = M->n_psd;
+  ld delta = nu[0], kappa = nu[1], eta = nu[2];
+  if (!(kappa > 0)) return 0;
+  ld *p = malloc(sizeof(ld) * K), *dp = malloc(sizeof(ld) * K * 3);
+  int ok = 1;
+  for (int s = 0; s < S; s++) {
+    const double *mx = M->psd_mix + 5 * s;
+    ld w1 = mx[0];
+    if (!(w1 > 0 && w1 < 1)) {
+      ok = 0;
+      break;
+    }
+    ld wp = 1 / (1 + expl(-(logl(w1 / (1 - w1)) + eta)));
+    ld Z = 0, dZ[3] = {0, 0, 0};
+    for (int k = 0; k < K; k++) {
+      ld y = (M->psd_edges[k] + M->psd_edges[k + 1]) * 0.5;
+      ld dy = (ld)M->psd_edges[k + 1] - (ld)M->psd_edges[k];
+      ld Nc[2], dd[2], dk[2];
+      for (int c = 0; c < 2; c++) {
+        ld mu = mx[1 + 2 * c] + delta, sg = mx[2 + 2 * c] * kappa;
+        ld z = (y - mu) / sg;
+        Nc[c] = expl(-0.5L * z * z) / (sg * sqrtl(2 * PI_L));
+        dd[c] = Nc[c] * z / sg;
+        dk[c] = Nc[c] * (z * z - 1) / kappa;
+      }
+      p[k] = dy * (wp * Nc[0] + (1 - wp) * Nc[1]);
+      dp[3 * k + 0] = dy * (wp * dd[0] + (1 - wp) * dd[1]);
+      dp[3 * k + 1] = dy * (wp * dk[0] + (1 - wp) * dk[1]);
+      dp[3 * k + 2] = dy * wp * (1 - wp) * (Nc[0] - Nc[1]);
+      Z += p[k];
+      for (int v = 0; v < 3; v++) dZ[v] += dp[3 * k + v];
+    }
+    for (int k = 0; k < K; k++) {
+      P[(size_t)s * K + k] = p[k] / Z;
+      if (dP)
+        for (int v = 0; v < 3; v++)
+          dP[((size_t)s * K + k) * 3 + v] = (dp[3 * k + v] - p[k] / Z * dZ[v]) / Z;
+    }
+  }
+  free(p);
+  free(dp);
+  return ok;
+}
+
+int32_t orc_psd_probs(const orc_model *M, const double *theta, double *P) {
+  if (M->n_psd <= 0) return 0;
+  size_t n = (size_t)M->n_species * M->n_psd;
+  ld *q = malloc(sizeof(ld) * n);
+  int ok = psd_l(M, theta + M->n_species + n_resp(M->family), q, NULL);
+  for (size_t i = 0; i < n; i++) P[i] = (double)q[i];
+  free(q);
+  return ok;
+}
+
+/* ------------------------------------------------- expectation (Eq.2/3) -- */
+/* mu[d][j][k] = eps_d sum_s R_s F_js P_sk  (P = 1 in one dimension). */
+static void expected_l(const orc_model *M, const double *theta, const ld *F, const ld *P, ld *mu) {
+  const int S = M->n_species, J = M->n_reco, K = M->n_psd > 0 ? M->n_psd : 1;
+  for (int d = 0; d < M->n_datasets; d++)
+    for (int j = 0; j < J; j++)
+      for (int k = 0; k < K; k++) {
+        ld acc = 0;
+        for (int s = 0; s < S; s++)
+          acc += (ld)theta[s] * F[(size_t)j * S + s] * (P ? P[(size_t)s * K + k] : 1);
+        mu[((size_t)d * J + j) * K + k] = M->exposure[d] * acc;
+      }
+}
+
+static int theta_finite(const orc_model *M, const double *theta) {
+  int P = orc_num_params(M);
+  for (int p = 0; p < P; p++)
+    if (!isfinite(theta[p])) return 0;
+  return 1;
+}
+
+int32_t orc_expected(const orc_model *M, const double *theta, double *mu) {
+  const int S = M->n_species, J = M->n_reco, K = M->n_psd > 0 ? M->n_psd : 1;
+  size_t nb = (size_t)M->n_datasets * J * K;
+  ld *F = malloc(sizeof(ld) * (size_t)J * S), *P = NULL, *m = malloc(sizeof(ld) * nb);
+  int ok = theta_finite(M, theta) && fold_l(M, theta, F, NULL);
+  if (ok && M->n_psd > 0) {
+    P = malloc(sizeof(ld) * (size_t)S * K);
+    ok = psd_l(M, theta + S + n_resp(M->family), P, NULL);
+  }
+  if (ok) expected_l(M, theta, F, P, m);
+  for (size_t i = 0; i < nb; i++) mu[i] = ok ? (double)m[i] : NAN;
+  free(F);
+  free(P);
+  free(m);
+  return ok;
+}
+
+/* ------------------------------------------------------ -ln L (Eq.4) ----- */
+/* R1/R2 per-bin term. Returns 0 on a domain error. */
+static int poisson_term(ld mu, ld n, ld *term, ld *g) {
+  if (mu > 0) {
+    *term = n > 0 ? mu - n * logl(mu) : mu;
+    *g = 1 - n / mu;
+    return 1;
+  }
+  if (mu == 0 && n == 0) {
+    *term = 0;
+    *g = 1;
+    return 1;
+  }
+  return 0;
+}
+
+double orc_nll_grad(const orc_model *M, const double *theta, double *grad, uint32_t *st) {
+  const int S = M->n_species, J = M->n_reco, fam = M->family, nr = n_resp(fam);
+  const int K = M->n_psd > 0 ? M->n_psd : 1, Pn = orc_num_params(M);
+  *st = 0;
+  if (!theta_finite(M, theta)) {
+    *st = ORC_ST_NONFINITE;
+    if (grad)
+      for (int p = 0; p < Pn; p++) grad[p] = NAN;
+    return NAN;
+  }
+  ld *F = malloc(sizeof(ld) * (size_t)J * S);
+  ld *dF = grad ? malloc(sizeof(ld) * (size_t)J * S * nr) : NULL;
+  ld *P = NULL, *dP = NULL;
+  int ok = fold_l(M, theta, F, dF);
+  if (ok && M->n_psd > 0) {
+    P = malloc(sizeof(ld) * (size_t)S * K);
+    dP = malloc(sizeof(ld) * (size_t)S * K * 3);
+    ok = psd_l(M, theta + S + nr, P, dP);
+  }
+  ld nll = 0;
+  ld *gr = calloc((size_t)Pn, sizeof(ld));
+  for (int d = 0; d < M->n_datasets && ok; d++) {
+    ld eps = M->exposure[d];
+    for (int j = M->win_lo; j < M->win_hi && ok; j++)
+      for (int k = 0; k < K; k++) {
+        ld mu = 0;
+        for (int s = 0; s < S; s++) mu += (ld)theta[s] * F[(size_t)j * S + s] * (P ? P[(size_t)s * K + k] : 1);
+        /* mu is an FP64 quantity: round the long-double sum to double (so a tail
+         * that underflows in FP64 is exactly 0 here too) */
+        mu = (double)(eps * mu);
+        ld n = M->counts[((size_t)d * J + j) * K + k];
+        ld term, g;
+        if (!poisson_term(mu, n, &term, &g)) {
+          ok = 0;
+          break;
+        }
+        nll += term;
+        if (!grad) continue;
+        /* d mu / d theta, term by term */
+        for (int s = 0; s < S; s++) {
+          ld pk = P ? P[(size_t)s * K + k] : 1;
+          gr[s] += g * eps * F[(size_t)j * S + s] * pk;
+          for (int p = 0; p < nr; p++) gr[S + p] += g * eps * theta[s] * pk * dF[((size_t)j * S + s) * nr + p];
+          if (P)
+            for (int v = 0; v < 3; v++)
+              gr[S + nr + v] += g * eps * theta[s] * F[(size_t)j * S + s] * dP[((size_t)s * K + k) * 3 + v];
+        }
+      }
+  }
+  if (ok)
+    for (int p = 0; p < Pn; p++)
+      if (M->pull_sigma && M->pull_sigma[p] > 0) {
+        ld z = ((ld)theta[p] - M->pull_centre[p]) / M->pull_sigma[p];
+        nll += 0.5L * z * z;
+        gr[p] += z / M->pull_sigma[p];
+      }
+  if (!ok) *st = ORC_ST_DOMAIN;
+  if (grad)
+    for (int p = 0; p < Pn; p++) grad[p] = ok ? (double)gr[p] : NAN;
+  free(gr);
+  free(F);
+  free(dF);
+  free(P);
+  free(dP);
+  return ok ? (double)nll : INFINITY;
+}
+
+double orc_nll(const orc_model *M, const double *theta, uint32_t *st) {
+  return orc_nll_grad(M, theta, NULL, st);
+}
+
+/* ------------------------------------------------------------- BFGS ------ */
+/* The minimizer step (MINUIT's variable-metric role in section 3.2): BFGS on
+ * the inverse Hessian with a backtracking Armijo line search.  Gradient is
+ * either analytic or central finite differences with steps 1e-4 * scale. */
+typedef struct {
+  const orc_model *M;
+  const orc_fit_opts *o;
+  int P, nf;
+  int *idx;      /* free parameter indices */
+  double *full;  /* full parameter vector workspace */
+  int n_eval;
+} fitctx;
+
+static double f_eval(fitctx *c, const double *x, double *g, uint32_t *st) {
+  for (int q = 0; q < c->nf; q++) c->full[c->idx[q]] = x[q];
+  c->n_eval++;
+  if (!g) return orc_nll(c->M, c->full, st);
+  if (!c->o->use_fd) {
+    double *gf = malloc(sizeof(double) * c->P);
+    double f = orc_nll_grad(c->M, c->full, gf, st);
+    for (int q = 0; q < c->nf; q++) g[q] = gf[c->idx[q]];
+    free(gf);
+    return f;
+  }
+  double f = orc_nll(c->M, c->full, st);
+  for (int q = 0; q < c->nf; q++) {
+    int p = c->idx[q];
+    double h = 1e-4 * c->o->scale[p], x0 = c->full[p];
+    uint32_t s1, s2;
+    c->full[p] = x0 + h;
+    double fp = orc_nll(c->M, c->full, &s1);
+    c->full[p] = x0 - h;
+    double fm = orc_nll(c->M, c->full, &s2);
+    c->full[p] = x0;
+    c->n_eval += 2;
+    g[q] = (fp - fm) / (2 * h);
+    *st |= s1 | s2;
+  }
+  return f;
+}
+
+/* Gauss-Jordan inverse with partial pivoting of an n x n matrix. */
+static int invert(int n, double *a, double *inv) {
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) inv[i * n + j] = i == j;
+  for (int c = 0; c < n; c++) {
+    int piv = c;
+    for (int r = c + 1; r < n; r++)
+      if (fabs(a[r * n + c]) > fabs(a[piv * n + c])) piv = r;
+    if (a[piv * n + c] == 0) return 0;
+    for (int j = 0; j < n; j++) {
+      double t = a[c * n + j];
+      a[c * n + j] = a[piv * n + j];
+      a[piv * n + j] = t;
+      t = inv[c * n + j];
+      inv[c * n + j] = inv[piv * n + j];
+      inv[piv * n + j] = t;
+    }
+    double d = a[c * n + c];
+    for (int j = 0; j < n; j++) {
+      a[c * n + j] /= d;
+      inv[c * n + j] /= d;
+    }
+    for (int r = 0; r < n; r++)
+      if (r != c && a[r * n + c] != 0) {
+        double f = a[r * n + c];
+        for (int j = 0; j < n; j++) {
+          a[r * n + j] -= f * a[c * n + j];
+          inv[r * n + j] -= f * inv[c * n + j];
+        }
+      }
+  }
+  return 1;
+}
+
+int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o, double *theta_hat,
+                double *sigma, orc_fit_result *res) {
+  fitctx c = {M, o, orc_num_params(M), 0, NULL, NULL, 0};
+  c.idx = malloc(sizeof(int) * c.P);
+  c.full = malloc(sizeof(double) * c.P);
+  memcpy(c.full, theta0, sizeof(double) * c.P);
+  for (int p = 0; p < c.P; p++)
+    if (!o->free_mask || o->free_mask[p]) c.idx[c.nf++] = p;
+  const int n = c.nf;
+  double *x = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n), *H = malloc(sizeof(double) * n * n);
+  double *pd = malloc(sizeof(double) * n), *xn = malloc(sizeof(double) * n), *gn = malloc(sizeof(double) * n);
+  double *sv = malloc(sizeof(double) * n), *yv = malloc(sizeof(double) * n), *Hy = malloc(sizeof(double) * n);
+  for (int q = 0; q < n; q++) x[q] = theta0[c.idx[q]];
+  uint32_t st = 0, est;
+  double f = f_eval(&c, x, g, &est);
+  st |= est & ORC_ST_NONFINITE;
+#define RESET_H()                                                            \
+  for (int i = 0; i < n; i++)                                                \
+    for (int j = 0; j < n; j++) H[i * n + j] = i == j ? o->scale[c.idx[i]] * o->scale[c.idx[i]] : 0;
+  RESET_H();
+  int it = 0;
+  double edm = INFINITY;
+  if (!isfinite(f)) st |= est;
+  while (isfinite(f)) {
+    edm = 0;
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j < n; j++) edm += 0.5 * g[i] * H[i * n + j] * g[j];
+    if (edm < o->edm_tol) break;
+    if (it >= o->max_iter) {
+      st |= ORC_ST_MAXITER;
+      break;
+    }
+    double slope = 0;
+    for (int i = 0; i < n; i++) {
+      pd[i] = 0;
+      for (int j = 0; j < n; j++) pd[i] -= H[i * n + j] * g[j];
+      slope += g[i] * pd[i];
+    }
+    if (!(slope < 0)) {
+      RESET_H();
+      st |= ORC_ST_BFGS_RESET;
+      slope = 0;
+      for (int i = 0; i < n; i++) {
+        pd[i] = -H[i * n + i] * g[i];
+        slope += g[i] * pd[i];
+      }
+    }
+    double alpha = 1, fn = INFINITY;
+    int accepted = 0;
+    for (int ls = 0; ls < 40; ls++) {
+      for (int i = 0; i < n; i++) xn[i] = x[i] + alpha * pd[i];
+      fn = f_eval(&c, xn, NULL, &est);
+      if (isfinite(fn) && fn <= f + 1e-4 * alpha * slope + 1e-14 * fabs(f)) {
+        accepted = 1;
+        break;
+      }
+      if (isfinite(fn)) {
+        double aq = -slope * alpha * alpha / (2 * (fn - f - slope * alpha));
+        alpha = fmin(fmax(aq, 0.1 * alpha), 0.5 * alpha);
+      } else {
+        alpha *= 0.25;
+      }
+    }
+    if (!accepted) {
+      st |= ORC_ST_LS_FAIL;
+      break;
+    }
+    fn = f_eval(&c, xn, gn, &est);
+    double sy = 0, ss = 0, yy = 0;
+    for (int i = 0; i < n; i++) {
+      sv[i] = xn[i] - x[i];
+      yv[i] = gn[i] - g[i];
+      sy += sv[i] * yv[i];
+      ss += sv[i] * sv[i];
+      yy += yv[i] * yv[i];
+    }
+    if (sy > 1e-12 * sqrt(ss * yy)) {
+      /* H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T */
+      double rho = 1 / sy, yHy = 0;
+      for (int i = 0; i < n; i++) {
+        Hy[i] = 0;
+        for (int j = 0; j < n; j++) Hy[i] += H[i * n + j] * yv[j];
+        yHy += yv[i] * Hy[i];
+      }
+      for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++)
+          H[i * n + j] += -rho * (sv[i] * Hy[j] + Hy[i] * sv[j]) + (rho * rho * yHy + rho) * sv[i] * sv[j];
+    } else {
+      RESET_H();
+      st |= ORC_ST_BFGS_RESET;
+    }
+    memcpy(x, xn, sizeof(double) * n);
+    memcpy(g, gn, sizeof(double) * n);
+    f = fn;
+    it++;
+  }
+#undef RESET_H
+  for (int p = 0; p < c.P; p++) theta_hat[p] = theta0[p];
+  for (int q = 0; q < n; q++) theta_hat[c.idx[q]] = x[q];
+  if (sigma) {
+    for (int p = 0; p < c.P; p++) sigma[p] = 0;
+    if (o->hesse && isfinite(f)) {
+      /* Hessian by central differences of the analytic gradient, then inverse */
+      double *Hs = malloc(sizeof(double) * n * n), *Hi = malloc(sizeof(double) * n * n);
+      double *full = malloc(sizeof(double) * c.P), *gp = malloc(sizeof(double) * c.P), *gm = malloc(sizeof(double) * c.P);
+      memcpy(full, theta_hat, sizeof(double) * c.P);
+      for (int q = 0; q < n; q++) {
+        int p = c.idx[q];
+        double h = 1e-4 * o->scale[p], x0 = full[p];
+        uint32_t s1;
+        full[p] = x0 + h;
+        orc_nll_grad(M, full, gp, &s1);
+        full[p] = x0 - h;
+        orc_nll_grad(M, full, gm, &s1);
+        full[p] = x0;
+        for (int r = 0; r < n; r++) Hs[r * n + q] = (gp[c.idx[r]] - gm[c.idx[r]]) / (2 * h);
+      }
+      for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++) Hs[i * n + j] = Hs[j * n + i] = 0.5 * (Hs[i * n + j] + Hs[j * n + i]);
+      if (invert(n, Hs, Hi))
+        for (int q = 0; q < n; q++) sigma[c.idx[q]] = Hi[q * n + q] > 0 ? sqrt(Hi[q * n + q]) : NAN;
+      free(Hs);
+      free(Hi);
+      free(full);
+      free(gp);
+      free(gm);
+    } else {
+      for (int q = 0; q < n; q++) sigma[c.idx[q]] = sqrt(fmax(H[q * n + q], 0));
+    }
+  }
+  res->nll = f;
+  res->edm = edm;
+  res->iters = it;
+  res->n_eval = c.n_eval;
+  res->status = st;
+  free(c.idx);
+  free(c.full);
+  free(x);
+  free(g);
+  free(H);
+  free(pd);
+  free(xn);
+  free(gn);
+  free(sv);
+  free(yv);
+  free(Hy);
+  return isfinite(f) && !(st & (ORC_ST_LS_FAIL | ORC_ST_MAXITER));
+}

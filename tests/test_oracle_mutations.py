@@ -1,0 +1,65 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check that the pin
+suite rejects every one of them: a dropped term, a wrong sign, factor or index, a
+transposed operand."""
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = {
+    "gamma_exponent_sign": ("- d->lgk - d->k * d->lth", "- d->lgk + d->k * d->lth"),
+    "gamma_dk_factor": ("*dm = dk * (2 * m / s2)", "*dm = dk * (m / s2)"),
+    "gamma_shape_transposed": ("d->k = m * m / s2;", "d->k = s2 / m;"),
+    "quench_power": ("Q = 1 - 2 / y + 2 * L / (y * y);", "Q = 1 - 2 / y + 2 * L / y;"),
+    "quench_deriv_sign": ("*dQ_dkB = dQdy * (-y / kB);", "*dQ_dkB = dQdy * (y / kB);"),
+    "resolution_b_term": ("o->ds[3] = m / (2 * s);", "o->ds[3] = m / s;"),
+    "resolution_c_dropped": ("ld s2 = a * a + b * m + c * c * m * m;", "ld s2 = a * a + b * m;"),
+    "bin_width_dropped": ("ld K = dx[j] * dens_eval(", "ld K = dens_eval("),
+    "bin_centre_edge": ("double c = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;",
+                        "double c = M->reco_edges[j];"),
+    "psd_not_renormalised": ("P[(size_t)s * K + k] = p[k] / Z;", "P[(size_t)s * K + k] = p[k];"),
+    "psd_kappa_inverted": ("sg = mx[2 + 2 * c] * kappa;", "sg = mx[2 + 2 * c] / kappa;"),
+    "psd_eta_sign": ("logl(w1 / (1 - w1)) + eta", "logl(w1 / (1 - w1)) - eta"),
+    "empty_bin_term_dropped": ("*term = n > 0 ? mu - n * logl(mu) : mu;", "*term = n > 0 ? mu - n * logl(mu) : 0;"),
+    "pull_factor": ("nll += 0.5L * z * z;", "nll += z * z;"),
+    "rate_grad_no_exposure": ("gr[s] += g * eps * F[(size_t)j * S + s] * pk;", "gr[s] += g * F[(size_t)j * S + s] * pk;"),
+    "window_off_by_one": ("for (int j = M->win_lo; j < M->win_hi && ok; j++)",
+                          "for (int j = M->win_lo; j <= M->win_hi - 2 && ok; j++)"),
+    "digamma_tail_sign": ("return r + logl(x) - 0.5L / x - tail;", "return r + logl(x) - 0.5L / x + tail;"),
+    "line_at_grid_energy": ("E = (ld)M->line_energy[line_s];", "E = (ld)M->line_energy[line_s] + 0.5 * M->e_step;"),
+    "bfgs_update_sign": ("(rho * rho * yHy + rho) * sv[i] * sv[j]", "(rho * rho * yHy - rho) * sv[i] * sv[j]"),
+}
+
+
+def _run(name, tmp):
+    a, b = MUTANTS.get(name, ("", ""))
+    src = open(SRC).read()
+    assert name == "control" or src.count(a) == 1, name
+    d = os.path.join(tmp, name)
+    os.makedirs(d)
+    shutil.copy(os.path.join(ROOT, "oracle", "oracle.h"), d)
+    with open(os.path.join(d, "oracle.c"), "w") as f:
+        f.write(src.replace(a, b) if a else src)
+    lib = os.path.join(d, "liboracle.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, os.path.join(d, "oracle.c"), "-lm"])
+    env = dict(os.environ, GS_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+@pytest.mark.slow
+def test_every_planted_mistake_is_caught(tmp_path):
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        res = list(ex.map(lambda n: _run(n, str(tmp_path)), ["control"] + sorted(MUTANTS)))
+    assert res[0] == ("control", 0), "the unmutated copy must pass the pins"
+    res = res[1:]
+    survivors = [n for n, rc in res if rc == 0]
+    assert not survivors, f"pins did not catch: {survivors}"
