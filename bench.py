@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the fold likelihood hot path on one MI355X.
+
+Workload: the Borexino-scale model (12 species: 4 lines, 6 betas, 2 exponentials; 4000
+true cells of 0.75 keV plus 4 lines; 900 reco bins of 1.6 pe; gamma response with light
+yield, Birks quenching and resolution a, b, c; 17 parameters, 3 pulls).  One step is one
+batched -ln L + gradient evaluation (cells, fold, Poisson reduction, adjoint, gradient)
+of B pseudo-experiments of that model, each with its own data and parameters, with every
+input already resident in device memory.  value = B * steps / wall time.
+
+Also reported: the dominant kernel against the FP64 vector roofline (timed live with HIP
+events on its stream), single-evaluation latency, single fits with the adjoint gradient
+versus central finite differences, and the CPU oracle on the host cores (sampled).
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NLL+grad evals/sec and toy fits/sec at |dNLL|/NLL<=1e-11 (adjoint vs finite-diff)"
+FP64_PEAK_TFLOPS = 78.6
+# FP64 flops per (bin, cell) pair of the gamma-response kernels, counted from their gfx950
+# instruction mix (FMA = 2): fold 20 FMA + 3 MUL + 3 ADD; adjoint 22 FMA + 4 MUL + 5 ADD.
+FLOPS_PER_PAIR = {"fold": 46, "adj": 53}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(toys, seconds, threads):
+    """Oracle -ln L + gradient on the host, one toy per thread, for about `seconds`."""
+    import oracle
+    oracle.build(force=False)
+    orcs = [oracle.Oracle(t) for t in toys[:threads]]
+    counts = [0] * threads
+    out = [None] * threads
+    stop = time.perf_counter() + seconds
+
+    def work(i):
+        while True:
+            out[i] = orcs[i].nll_grad(toys[i].theta_true)
+            counts[i] += 1
+            if time.perf_counter() >= stop:
+                break
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    el = time.perf_counter() - t0
+    return sum(counts) / el, sum(counts), el, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fits", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import gsgen
+    import paper_1812_05686_amd as gs
+
+    base = gsgen.config1()
+    toys = gsgen.config3(args.batch, base=base, full_window=True)
+    log(f"bench: {len(toys)} pseudo-experiments of the Borexino-scale model")
+    batch = gs.Batch(toys)
+    stride = batch.stride
+    theta = torch.tensor(np.stack([t.theta_true for t in toys]), dtype=torch.float64, device="cuda")
+    nll = torch.empty(len(toys), dtype=torch.float64, device="cuda")
+    grad = torch.empty(len(toys), stride, dtype=torch.float64, device="cuda")
+    st = torch.empty(len(toys), dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        batch.nll_grad(theta, nll, grad, st)
+    torch.cuda.synchronize()
+    batch.set_profiling(True)
+    batch.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.nll_grad(theta, nll, grad, st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = batch.kernel_times(reset=True)
+    batch.set_profiling(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = len(toys) * args.steps / (t1 - t0)
+    log(f"bench: {ms_step:.3f} ms/step, {value:.1f} evals/s; kernels " +
+        ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}ms" for k, v in kt.items() if v[1]))
+    gpu_nll = nll.cpu().numpy()
+    gpu_grad = grad.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+
+    pairs = sum((t.win_hi - t.win_lo) * (t.n_true + int(np.sum(~np.isnan(t.line_energy)))) for t in toys)
+    per_kernel = {}
+    for k in ("fold", "adj"):
+        ms, n = kt[k]
+        avg = ms / n
+        per_kernel[k] = dict(avg_ms=avg, tflops=pairs * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12)
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
+    ach = per_kernel[dom]["tflops"]
+    roofline = {"bound": "alu", "kernel": "k_" + dom + "1", "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs,
+                "avg_launch_ms": round(per_kernel[dom]["avg_ms"], 4),
+                "other": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in per_kernel.items() if k != dom}}
+
+    # single-evaluation latency on one device-resident problem
+    single = gs.Batch([toys[0]])
+    th1 = theta[:1].clone()
+    n1, g1, s1 = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(1, stride, dtype=torch.float64,
+                                                                               device="cuda"),
+                  torch.empty(1, dtype=torch.int32, device="cuda"))
+    for _ in range(10):
+        single.nll_grad(th1, n1, g1, s1)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    reps = 200
+    for _ in range(reps):
+        single.nll_grad(th1, n1, g1, s1)
+    torch.cuda.synchronize()
+    single_us = (time.perf_counter() - ta) * 1e6 / reps
+
+    fits = None
+    if not args.no_fits:
+        model = gs.Model(base)
+        fits = {}
+        for name, fd in (("adjoint", False), ("finite_diff", True)):
+            model.fit(base.theta0, base.fd_scale, use_fd=fd)  # warm
+            ta = time.perf_counter()
+            r = model.fit(base.theta0, base.fd_scale, use_fd=fd, hesse=False)
+            el = time.perf_counter() - ta
+            fits[name] = dict(fits_per_s=round(1.0 / el, 3), seconds=round(el, 4), iters=r["iters"],
+                              n_eval=r["n_eval"], converged=r["ok"], nll=r["nll"])
+        fits["speedup_adjoint_over_fd"] = round(fits["finite_diff"]["seconds"] / fits["adjoint"]["seconds"], 2)
+        log(f"bench: fits {fits}")
+
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        rate, n_done, el, outs = cpu_baseline(toys, args.cpu_seconds, threads)
+        cpu = {"value": round(rate, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"{n_done} oracle -ln L+gradient evaluations of the first {threads} pseudo-experiments "
+                         f"(one per thread) in {el:.1f} s"}
+        rel = max(abs(gpu_nll[i] - outs[i][0]) / abs(outs[i][0]) for i in range(threads))
+        gerr = max(np.max(np.abs(gpu_grad[i, :17] - outs[i][1]) * base.fd_scale /
+                          np.maximum(np.abs(outs[i][1]) * base.fd_scale, 1.0)) for i in range(threads))
+        parity = {"toys_checked": threads, "max_rel_dnll": float(rel), "max_grad_err": float(gerr),
+                  "pass": bool(rel <= 1e-11 and gerr <= 1e-8)}
+        log(f"bench: cpu {cpu}; parity {parity}")
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "c1 Borexino-scale: 12 species, 4000+4 true cells x 900 reco bins, gamma "
+                                  "response, 17 params; batch of pseudo-experiments per step",
+                      "batch": len(toys), "pairs_per_eval": pairs // len(toys)},
+           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity,
+           "single_eval": {"us_per_eval": round(single_us, 2), "evals_per_s": round(1e6 / single_us, 1)},
+           "single_fits": fits}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -299,10 +299,11 @@ def config2() -> Model:
     return m
 
 
-def config3(n_toys: int = 4096, base: Model | None = None) -> list[Model]:
+def config3(n_toys: int = 4096, base: Model | None = None, full_window: bool = False) -> list[Model]:
     """Toys of config 1: rates drawn +-20% uniform around nominal, response at nominal,
-    own contiguous window of L ~ U{200..900} bins starting at lo ~ U{0..900-L}; fits start
-    at the config-1 nominal point.  The spectra and binning arrays are shared objects."""
+    own contiguous window of L ~ U{200..900} bins starting at lo ~ U{0..900-L} (or the full
+    900-bin window); fits start at the config-1 nominal point.  The spectra and binning
+    arrays are shared objects."""
     base = config1() if base is None else base
     S = base.n_species
     hist = nature_species_hist(base, base.theta_true[S:])
@@ -313,6 +314,8 @@ def config3(n_toys: int = 4096, base: Model | None = None) -> list[Model]:
         th[:S] *= g.uniform(0.8, 1.2, S)
         L = int(g.integers(200, 901))
         lo = int(g.integers(0, 900 - L + 1))
+        if full_window:
+            lo, L = 0, base.n_reco
         counts = draw_counts(nature_expected(base, th, hist), _rng(3, 0, t))
         toys.append(base.replace(name=f"c3/{t}", counts=counts, win_lo=lo, win_hi=lo + L,
                                  theta_true=th, theta0=base.theta_true.copy()))

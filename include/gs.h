@@ -1,0 +1,214 @@
+/* gs.h -- C ABI of libgs: the binned multi-observable Poisson likelihood with
+ * an analytic detector-response fold, on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (GooStats, arXiv:1812.05686):
+ *   - each species' true-energy spectrum (a histogram on a uniform grid of
+ *     true-energy cells, or a single line energy for monoenergetic species,
+ *     the "AnaPeak" type of section 4.3) is folded through a parametrised
+ *     analytic detector response (section 2.3): the response is evaluated on
+ *     the visible-energy x true-energy mesh at reco-bin midpoints, times the
+ *     bin width, and summed against the spectrum (section 2.5; cost model
+ *     Eq.2);
+ *   - the folded spectra are scaled by rate x exposure and summed (section 4.1
+ *     input list); with a secondary observable each species carries a
+ *     pulse-shape distribution and the expectation is a 2-D histogram
+ *     (section 2.4, Eq.3 class of fits);
+ *   - -ln L = sum over window bins of (mu - n ln mu) + 1/2 sum over pulls of
+ *     ((theta_p - c_p)/sigma_p)^2 (Eq.4 with ln n! dropped; n = 0 contributes
+ *     mu; mu < 0, or mu = 0 with n > 0, gives +inf and GS_ST_DOMAIN).
+ *
+ * Parameter vector theta (FP64), same layout for gradients:
+ *   [ R_0 .. R_{S-1} | response parameters | delta, kappa, eta (2-D only) ]
+ *   GS_RESP_GAUSS_E  : (a, b)            m = E, s^2 = a^2 + b E
+ *   GS_RESP_GAUSS_PE : (LY, kB, a, b, c) m = LY Q(E; kB) E, s^2 = a^2 + b m + c^2 m^2
+ *   GS_RESP_GAMMA_PE : same moments, gamma density with mean m, variance s^2
+ *   Q(E; kB) = 1 - 2/y + 2 ln(1 + y)/y^2, y = sqrt(E)/(kB * birks_A)  (Birks'
+ *   law integrated with dE/dx = birks_A/sqrt(E); E in MeV for the pe families).
+ *   Pulse shape of species s (2-D): two Gaussians (w1, mean1, sigma1) and
+ *   (1 - w1, mean2, sigma2) at the bin midpoints, means shifted by delta,
+ *   widths scaled by kappa, odds of component 1 multiplied by exp(eta),
+ *   renormalised over the pulse-shape bins.
+ *
+ * Conventions: all floating point is FP64, sizes int32, arrays row-major.
+ * No C++ exception crosses the ABI.  A gs_status return reports API or
+ * device failures (message via gs_last_error()); mathematical conditions are
+ * reported as status bits alongside values, never as a gs_status.
+ */
+#ifndef GS_H
+#define GS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_ARG = 1,         /* invalid argument or descriptor                 */
+  GS_ERR_DEVICE = 2,      /* HIP runtime error, or no usable gfx950 device  */
+  GS_ERR_OOM = 3,         /* device or pinned host allocation failed        */
+  GS_ERR_UNSUPPORTED = 4  /* valid but outside the implemented limits       */
+} gs_status;
+
+/* Per-evaluation / per-toy status bits. */
+#define GS_ST_DOMAIN 1u      /* mu < 0, mu = 0 with n > 0, or invalid response */
+#define GS_ST_NONFINITE 2u   /* non-finite parameter                            */
+#define GS_ST_LS_FAIL 4u     /* fit: line search exhausted                      */
+#define GS_ST_MAXITER 8u     /* fit: iteration limit reached                    */
+#define GS_ST_BFGS_RESET 16u /* fit: inverse Hessian reset (curvature y^T s <= 0) */
+#define GS_ST_CONVERGED 32u  /* fit: EDM below tolerance                        */
+
+typedef enum { GS_RESP_GAUSS_E = 0, GS_RESP_GAUSS_PE = 1, GS_RESP_GAMMA_PE = 2 } gs_family;
+
+/* Limits of this implementation (GS_ERR_UNSUPPORTED beyond them). */
+#define GS_MAX_SPECIES 16
+#define GS_MAX_DATASETS 8
+#define GS_MAX_PARAMS (GS_MAX_SPECIES + 5 + 3)
+
+/* Description of one fit problem (section 4.1 lists its inputs: data
+ * histogram, components and their types, rates and response parameters,
+ * pull terms, exposure; section 2.1: several datasets).  The library copies
+ * everything it needs; the caller keeps ownership of every array. */
+typedef struct {
+  int32_t n_true;             /* true-energy cells, centres e_lo + (i + 1/2) e_step      */
+  double e_lo, e_step;        /* e_step > 0                                                */
+  int32_t n_species;          /* 1 .. GS_MAX_SPECIES                                       */
+  const double *spectra;      /* [n_species][n_true]; row ignored for line species         */
+  const double *line_energy;  /* [n_species]; NaN = grid species, else line energy         */
+  int32_t n_reco;             /* energy (reco) bins                                        */
+  const double *reco_edges;   /* [n_reco + 1], strictly increasing                         */
+  int32_t n_psd;              /* 0 = one-dimensional; else pulse-shape bins                */
+  const double *psd_edges;    /* [n_psd + 1] strictly increasing (n_psd > 0)               */
+  const double *psd_mix;      /* [n_species][5] = w1, mean1, sigma1, mean2, sigma2         */
+  int32_t n_datasets;         /* 1 .. GS_MAX_DATASETS, sharing every parameter             */
+  const double *exposure;     /* [n_datasets], > 0                                         */
+  const double *counts;       /* [n_datasets][n_reco][max(n_psd,1)], finite, >= 0          */
+  int32_t win_lo, win_hi;     /* energy-bin window [win_lo, win_hi), 0 <= lo < hi <= n_reco */
+  int32_t family;             /* gs_family                                                 */
+  double birks_A;             /* stopping-power constant of the quenching model (> 0)      */
+  const double *pull_centre;  /* [n_params] or NULL (no pulls)                             */
+  const double *pull_sigma;   /* [n_params] or NULL; sigma <= 0 means no pull on that one  */
+} gs_model_desc;
+
+typedef struct gs_model gs_model;
+typedef struct gs_batch gs_batch;
+
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char *gs_last_error(void);
+
+/* Host-only descriptor check (no device needed).  Returns the number of
+ * parameters (> 0) or -1 with the reason in gs_last_error(). */
+int32_t gs_desc_validate(const gs_model_desc *d);
+
+/* ------------------------------------------------------- single model --- */
+/* Create a model on HIP device `device` (must be gfx950).  Deep-copies the
+ * descriptor into device memory; `*out` is owned by the caller and released
+ * with gs_model_destroy.  GS_ERR_ARG for an invalid descriptor,
+ * GS_ERR_DEVICE/GS_ERR_OOM for runtime failures. */
+gs_status gs_model_create(const gs_model_desc *d, int32_t device, gs_model **out);
+void gs_model_destroy(gs_model *m);
+int32_t gs_model_num_params(const gs_model *m);
+
+/* -ln L at host parameters theta[n_params] (section 4.1, Eq.4), synchronous.
+ * This is the plain path: per-species folded spectra are cached on the
+ * device and re-folded only when a response parameter changed (the value
+ * cache of section 2.5); rate-only changes cost one combine-and-reduce
+ * pass.  *nll = +inf with GS_ST_DOMAIN, or NaN with GS_ST_NONFINITE. */
+gs_status gs_nll(gs_model *m, const double *theta, double *nll, uint32_t *st);
+
+/* -ln L and its gradient grad[n_params] from one forward fold and one
+ * adjoint (reverse-mode) pass over the same visible x true mesh,
+ * synchronous.  On GS_ST_DOMAIN / GS_ST_NONFINITE the gradient is NaN. */
+gs_status gs_nll_grad(gs_model *m, const double *theta, double *nll, double *grad, uint32_t *st);
+
+/* Expected counts mu[n_datasets][win_hi - win_lo][max(n_psd,1)] (host) at
+ * theta (Eq.2 fold, scaled by rates and exposure).  Synchronous. */
+gs_status gs_expected(gs_model *m, const double *theta, double *mu);
+
+/* Fit controls for gs_fit and gs_fit_batched. */
+typedef struct {
+  int32_t max_iter;         /* accepted quasi-Newton steps (e.g. 500)                         */
+  double edm_tol;           /* stop when 1/2 g^T H^-1 g < edm_tol (e.g. 1e-9)                 */
+  int32_t use_fd;           /* gs_fit only: 1 = central finite-difference gradient (plain path) */
+  const double *scale;      /* [n_params] > 0: initial inverse Hessian diag(scale^2), FD step 1e-4*scale */
+  const uint8_t *free_mask; /* [n_params] or NULL (all free)                                  */
+  int32_t hesse;            /* gs_fit only: 1 = sigma from finite differences of the gradient */
+} gs_fit_opts;
+
+typedef struct {
+  double nll, edm;
+  int32_t iters, n_eval;
+  uint32_t status;          /* GS_ST_* bits                                                    */
+} gs_fit_result;
+
+/* Quasi-Newton (BFGS, backtracking Armijo line search) minimisation on the
+ * host driving the device evaluations: the minimizer role MINUIT plays in
+ * section 3.2.  use_fd = 0 uses gs_nll_grad (adjoint); use_fd = 1 uses
+ * central differences of gs_nll (2 calls per free parameter per gradient,
+ * with the rate-only cache).  theta_hat[n_params], sigma[n_params] (sigma may
+ * be NULL) are host arrays.  Returns GS_OK even if the fit did not converge:
+ * check res->status. */
+gs_status gs_fit(gs_model *m, const double *theta0, const gs_fit_opts *o, double *theta_hat,
+                 double *sigma, gs_fit_result *res);
+
+/* --------------------------------------------------------- batches ----- */
+/* A batch of independent fit problems (pseudo-experiments), each with its
+ * own data, window, exposures, pulls and parameters (section 4.2 fits many
+ * fake datasets; here they run concurrently).  descs[t] describes toy t;
+ * toys whose descriptors point at the same spectra, line_energy, reco_edges,
+ * psd_edges and psd_mix arrays (same addresses) and agree on family, grid
+ * and sizes share one device copy of that structure.  Every array is copied.
+ * n_toys >= 1.  The batch is created on `device`. */
+gs_status gs_batch_create(const gs_model_desc *descs, int32_t n_toys, int32_t device, gs_batch **out);
+void gs_batch_destroy(gs_batch *b);
+int32_t gs_batch_num_toys(const gs_batch *b);
+/* Row stride of the batched parameter / gradient arrays (= max n_params). */
+int32_t gs_batch_param_stride(const gs_batch *b);
+
+/* Batched -ln L and gradient.  All pointers are DEVICE pointers on the
+ * batch's device, caller-owned, FP64 contiguous: d_theta[n_toys][stride],
+ * d_nll[n_toys], d_grad[n_toys][stride] (entries past a toy's n_params are
+ * left 0), d_status[n_toys].  Enqueued on `hip_stream` (a hipStream_t; NULL =
+ * the default stream) and returns without synchronising.  Concurrent calls on
+ * one batch must be ordered by the caller (they share work buffers). */
+gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad,
+                              uint32_t *d_status, void *hip_stream);
+
+/* Batched fits: every toy runs its own BFGS state machine on the device;
+ * the evaluation and update kernels of several iterations are captured in
+ * one HIP graph that is replayed until all toys stop.  Device pointers as
+ * above: d_theta0[n_toys][stride] (start), d_free[n_toys][stride] (uint8,
+ * NULL = all free), outputs d_theta_hat[n_toys][stride], d_nll_hat[n_toys],
+ * d_sigma[n_toys][stride] (sqrt of the BFGS inverse-Hessian diagonal, may be
+ * NULL), d_iters[n_toys], d_status[n_toys].  o->scale is a HOST array
+ * [stride] used for every toy; o->use_fd and o->hesse are ignored.
+ * Synchronises `hip_stream` before returning. */
+gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_free, const gs_fit_opts *o,
+                         double *d_theta_hat, double *d_nll_hat, double *d_sigma, int32_t *d_iters,
+                         uint32_t *d_status, void *hip_stream);
+
+/* --------------------------------------------------------- profiling --- */
+/* Kernel ids for gs_batch_kernel_times. */
+#define GS_K_CELLS 0   /* per-cell response moments and records           */
+#define GS_K_FOLD 1    /* fold of the combined spectrum (adjoint path)     */
+#define GS_K_NLL 2     /* Poisson terms, reduction, adjoint seeds          */
+#define GS_K_ADJ 3     /* adjoint pass over the mesh                       */
+#define GS_K_GRAD 4    /* chain rule to the parameter gradient             */
+#define GS_K_FOLDS 5   /* per-species fold (plain path, 2-D)               */
+#define GS_K_REDF 6    /* per-species split-K reduction                    */
+#define GS_K_NLLF 7    /* -ln L from per-species spectra                   */
+#define GS_K_QN 8      /* device quasi-Newton step                         */
+#define GS_K_COUNT 9
+
+/* When on, each kernel launch of the batch is bracketed by HIP events
+ * recorded on the stream the kernel is launched on (small overhead). */
+gs_status gs_batch_set_profiling(gs_batch *b, int32_t on);
+/* Accumulated device milliseconds and launch counts per kernel id since the
+ * last reset (host arrays of GS_K_COUNT entries).  Waits for the recorded
+ * events; reset != 0 clears the accumulators afterwards. */
+gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

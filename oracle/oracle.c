@@ -13,7 +13,8 @@
  *      sign fixed, ln n! dropped, and the factor 1/2 so that a change of 0.5
  *      in -ln L is one standard deviation).
  *  R2  n = 0 contributes mu (0 ln 0 = 0); mu < 0, or mu = 0 with n > 0, is a
- *      domain error: -ln L = +inf and status DOMAIN.
+ *      domain error: -ln L = +inf and status DOMAIN.  So is n > 0 with mu so
+ *      small that 1 - n/mu overflows FP64 (mu < n/DBL_MAX).
  *  R3  reco bin content = bin width x response at the bin midpoint (the
  *      response evaluated on the visible x true energy mesh, section 2.5).
  *  R4  true spectra are histograms on a uniform cell-centred grid with rows
@@ -389,6 +390,8 @@ int32_t orc_expected(const orc_model *M, const double *theta, double *mu) {
 /* ------------------------------------------------------ -ln L (Eq.4) ----- */
 /* R1/R2 per-bin term. Returns 0 on a domain error. */
 static int poisson_term(ld mu, ld n, ld *term, ld *g) {
+  /* R2: the adjoint seed 1 - n/mu must be finite in FP64 */
+  if (mu > 0 && n > 0 && !isfinite((double)n / (double)mu)) return 0;
   if (mu > 0) {
     *term = n > 0 ? mu - n * logl(mu) : mu;
     *g = 1 - n / mu;

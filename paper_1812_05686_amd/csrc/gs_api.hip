@@ -1,0 +1,602 @@
+// gs_api.hip -- host side of libgs: descriptor validation, device layout of
+// models and batches, synchronous single-model calls, batched calls and the
+// host quasi-Newton driver.  Every step of an evaluation runs in the kernels
+// of gs_kernels.hip; this file only allocates, copies and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "gs_impl.h"
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_err;
+
+gs_status fail(gs_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? GS_ERR_OOM : GS_ERR_DEVICE, "%s: %s (%s:%d)", #expr, \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                            \
+  } while (0)
+
+int n_resp(int fam) { return fam == GS_RESP_GAUSS_E ? 2 : 5; }
+
+int num_params(const gs_model_desc *d) {
+  return d->n_species + n_resp(d->family) + (d->n_psd > 0 ? 3 : 0);
+}
+
+// Host-side descriptor check; returns n_params or -1 with g_err set.
+int validate(const gs_model_desc *d) {
+  auto bad = [](const char *fmt, auto... a) {
+    char b[256];
+    snprintf(b, sizeof b, fmt, a...);
+    g_err = b;
+    return -1;
+  };
+  if (!d) return bad("null descriptor");
+  if (d->family < 0 || d->family > 2) return bad("unknown response family %d", d->family);
+  if (d->n_species < 1 || d->n_species > GS_MAX_SPECIES)
+    return bad("n_species %d outside 1..%d", d->n_species, GS_MAX_SPECIES);
+  if (d->n_true < 1) return bad("n_true %d < 1", d->n_true);
+  if (!(d->e_step > 0) || !std::isfinite(d->e_lo) || !std::isfinite(d->e_step)) return bad("bad true grid");
+  if (!d->line_energy) return bad("line_energy is NULL");
+  int n_grid = 0;
+  for (int s = 0; s < d->n_species; s++) {
+    if (std::isnan(d->line_energy[s])) {
+      n_grid++;
+    } else if (!std::isfinite(d->line_energy[s])) {
+      return bad("line energy of species %d is not finite", s);
+    }
+  }
+  if (n_grid > 0 && !d->spectra) return bad("spectra is NULL");
+  for (int s = 0; s < d->n_species; s++) {
+    if (!std::isnan(d->line_energy[s])) continue;
+    for (int i = 0; i < d->n_true; i++) {
+      double w = d->spectra[(size_t)s * d->n_true + i];
+      if (!(w >= 0) || !std::isfinite(w)) return bad("spectrum %d cell %d is negative or not finite", s, i);
+    }
+  }
+  if (d->n_reco < 1 || !d->reco_edges) return bad("no reco bins");
+  for (int j = 0; j < d->n_reco; j++)
+    if (!(d->reco_edges[j + 1] > d->reco_edges[j]) || !std::isfinite(d->reco_edges[j + 1]))
+      return bad("reco_edges not strictly increasing at %d", j);
+  if (d->n_psd < 0) return bad("n_psd < 0");
+  if (d->n_psd > 0) {
+    if (!d->psd_edges || !d->psd_mix) return bad("psd_edges / psd_mix is NULL");
+    for (int k = 0; k < d->n_psd; k++)
+      if (!(d->psd_edges[k + 1] > d->psd_edges[k])) return bad("psd_edges not strictly increasing at %d", k);
+    for (int s = 0; s < d->n_species; s++) {
+      const double *m = d->psd_mix + 5 * s;
+      if (!(m[0] > 0 && m[0] < 1) || !(m[2] > 0) || !(m[4] > 0) || !std::isfinite(m[1]) || !std::isfinite(m[3]))
+        return bad("psd_mix of species %d invalid", s);
+    }
+  }
+  if (d->n_datasets < 1 || d->n_datasets > GS_MAX_DATASETS)
+    return bad("n_datasets %d outside 1..%d", d->n_datasets, GS_MAX_DATASETS);
+  if (!d->exposure) return bad("exposure is NULL");
+  for (int k = 0; k < d->n_datasets; k++)
+    if (!(d->exposure[k] > 0) || !std::isfinite(d->exposure[k])) return bad("exposure %d not positive", k);
+  if (!(d->win_lo >= 0 && d->win_lo < d->win_hi && d->win_hi <= d->n_reco))
+    return bad("window [%d, %d) invalid for %d bins", d->win_lo, d->win_hi, d->n_reco);
+  if (!d->counts) return bad("counts is NULL");
+  const int K = std::max(d->n_psd, 1);
+  for (int k = 0; k < d->n_datasets; k++)
+    for (int j = d->win_lo; j < d->win_hi; j++)
+      for (int q = 0; q < K; q++) {
+        double n = d->counts[((size_t)k * d->n_reco + j) * K + q];
+        if (!(n >= 0) || !std::isfinite(n)) return bad("count (%d,%d,%d) negative or not finite", k, j, q);
+      }
+  if (d->family != GS_RESP_GAUSS_E && !(d->birks_A > 0)) return bad("birks_A must be > 0");
+  const int P = num_params(d);
+  if (d->pull_sigma)
+    for (int p = 0; p < P; p++)
+      if (d->pull_sigma[p] > 0 && (!d->pull_centre || !std::isfinite(d->pull_centre[p])))
+        return bad("pull %d has no finite centre", p);
+  return P;
+}
+
+// ------------------------------------------------------------- batch ----
+struct ShapeKey {
+  const void *spectra, *lines, *edges, *pe, *pm;
+  int fam, n_true, S, n_reco, n_psd;
+  double e_lo, e_step, A;
+  bool operator<(const ShapeKey &o) const {
+    return std::tie(spectra, lines, edges, pe, pm, fam, n_true, S, n_reco, n_psd, e_lo, e_step, A) <
+           std::tie(o.spectra, o.lines, o.edges, o.pe, o.pm, o.fam, o.n_true, o.S, o.n_reco, o.n_psd, o.e_lo,
+                    o.e_step, o.A);
+  }
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct gs_batch {
+  int device = 0;
+  int n_toys = 0, stride = 0, max_cells = 0, max_LS = 0;
+  std::vector<ShapeDev> shapes_h;
+  std::vector<ToyDev> toys_h;
+  std::vector<FoldItem> fold_h;
+  std::vector<AdjItem> adj_h;
+  std::vector<long long> fs_off_h;
+  std::vector<std::vector<void *>> shape_allocs;
+  std::vector<void *> allocs;
+  BatchView v{};
+  bool has_2d = false;
+  // kernel timing (gs_batch_set_profiling): event pairs around each launch
+  bool prof = false;
+  struct Timed {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> ev_free;
+  double prof_ms[GS_K_COUNT] = {};
+  long long prof_n[GS_K_COUNT] = {};
+
+  ~gs_batch() {
+    for (auto &t : pending) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+    for (auto e : ev_free) (void)hipEventDestroy(e);
+    for (void *p : allocs) (void)hipFree(p);
+  }
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (!ev_free.empty()) {
+      e = ev_free.back();
+      ev_free.pop_back();
+    } else {
+      (void)hipEventCreate(&e);
+    }
+    return e;
+  }
+  template <class T>
+  hipError_t alloc(T **p, size_t n) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e == hipSuccess) allocs.push_back(*p);
+    return e;
+  }
+};
+
+struct gs_model {
+  gs_batch *b = nullptr;
+  hipStream_t stream = nullptr;
+  int P = 0;
+  double *d_theta = nullptr, *d_nll = nullptr, *d_grad = nullptr, *d_mu = nullptr;
+  uint32_t *d_status = nullptr;
+  double *h_theta = nullptr, *h_out = nullptr;  // pinned staging
+  uint32_t *h_status = nullptr;
+  std::vector<double> cached_resp;  // response params of the cached per-species fold
+  bool cache_valid = false;
+  int n_mu = 0;
+};
+
+namespace {
+
+// Split-K choice: enough wavefronts to fill 256 CUs, without chunks so small
+// that per-item overhead dominates.
+constexpr int kTargetWaves = 8192;
+
+gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_batch **out) {
+  if (!descs || n_toys < 1) return fail(GS_ERR_ARG, "need at least one descriptor");
+  std::vector<int> P(n_toys);
+  for (int t = 0; t < n_toys; t++) {
+    P[t] = validate(&descs[t]);
+    if (P[t] < 0) return fail(GS_ERR_ARG, "toy %d: %s", t, g_err.c_str());
+    if (descs[t].n_psd > 0) return fail(GS_ERR_UNSUPPORTED, "toy %d: pulse-shape (2-D) models not built yet", t);
+  }
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(GS_ERR_DEVICE, "device %d not present (%d devices)", device, ndev);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GS_ERR_DEVICE, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+  HIP_TRY(hipSetDevice(device));
+
+  auto *B = new gs_batch();
+  std::unique_ptr<gs_batch> guard(B);
+  B->device = device;
+  B->n_toys = n_toys;
+  B->stride = *std::max_element(P.begin(), P.end());
+
+  // ---- shapes (deduplicated by array identity) ----
+  std::map<ShapeKey, int> shape_of;
+  std::vector<int> toy_shape(n_toys);
+  for (int t = 0; t < n_toys; t++) {
+    const gs_model_desc &d = descs[t];
+    ShapeKey k{d.spectra, d.line_energy, d.reco_edges, d.psd_edges, d.psd_mix, d.family, d.n_true,
+               d.n_species, d.n_reco, d.n_psd, d.e_lo, d.e_step, d.family == GS_RESP_GAUSS_E ? 0.0 : d.birks_A};
+    auto it = shape_of.find(k);
+    if (it != shape_of.end()) {
+      toy_shape[t] = it->second;
+      continue;
+    }
+    const int id = (int)B->shapes_h.size();
+    shape_of[k] = id;
+    toy_shape[t] = id;
+    ShapeDev sh{};
+    sh.family = d.family;
+    sh.n_true = d.n_true;
+    sh.S = d.n_species;
+    sh.n_reco = d.n_reco;
+    sh.n_psd = d.n_psd;
+    sh.birks_A = d.birks_A;
+    std::vector<int> grid, line;
+    for (int s = 0; s < d.n_species; s++) (std::isnan(d.line_energy[s]) ? grid : line).push_back(s);
+    sh.Sg = (int)grid.size();
+    sh.n_line = (int)line.size();
+    sh.n_cell = d.n_true + sh.n_line;
+    for (int q = 0; q < sh.Sg; q++) sh.sp_of[q] = grid[q];
+    for (int q = 0; q < sh.n_line; q++) sh.sp_of[sh.Sg + q] = line[q];
+    std::vector<double> cellE(sh.n_cell), wcell((size_t)d.n_true * std::max(sh.Sg, 1), 0.0);
+    for (int i = 0; i < d.n_true; i++) cellE[i] = d.e_lo + (i + 0.5) * d.e_step;
+    for (int q = 0; q < sh.n_line; q++) cellE[d.n_true + q] = d.line_energy[line[q]];
+    for (int i = 0; i < d.n_true; i++)
+      for (int q = 0; q < sh.Sg; q++) wcell[(size_t)i * sh.Sg + q] = d.spectra[(size_t)grid[q] * d.n_true + i];
+    double *cE, *wc, *bins, *edges;
+    HIP_TRY(B->alloc(&cE, cellE.size()));
+    HIP_TRY(B->alloc(&wc, wcell.size()));
+    HIP_TRY(B->alloc(&bins, (size_t)d.n_reco * kBinLen));
+    HIP_TRY(B->alloc(&edges, (size_t)d.n_reco + 1));
+    HIP_TRY(hipMemcpy(cE, cellE.data(), cellE.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(wc, wcell.data(), wcell.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(edges, d.reco_edges, ((size_t)d.n_reco + 1) * 8, hipMemcpyHostToDevice));
+    HIP_TRY(launch_bins_setup(nullptr, bins, edges, d.n_reco, nullptr));
+    sh.cellE = cE;
+    sh.wcell = wc;
+    sh.bins = bins;
+    B->shapes_h.push_back(sh);
+  }
+
+  // ---- toys, offsets, work items ----
+  long long cell_off = 0, win_off = 0, cnt_off = 0, pull_off = 0;
+  long long tiles_f = 0, tiles_a = 0;
+  for (int t = 0; t < n_toys; t++) {
+    const ShapeDev &sh = B->shapes_h[toy_shape[t]];
+    const int L = descs[t].win_hi - descs[t].win_lo;
+    tiles_f += (L + 63) / 64;
+    tiles_a += (sh.n_cell + 63) / 64;
+  }
+  const int nch_f = (int)std::max<long long>(1, (kTargetWaves + tiles_f - 1) / tiles_f);
+  const int nch_a = (int)std::max<long long>(1, (kTargetWaves + tiles_a - 1) / tiles_a);
+  long long fpart_off = 0, apart_off = 0, fs_off = 0;
+  std::vector<double> cnt_h, pc_h, ps_h;
+  for (int t = 0; t < n_toys; t++) {
+    const gs_model_desc &d = descs[t];
+    const ShapeDev &sh = B->shapes_h[toy_shape[t]];
+    ToyDev T{};
+    T.shape = toy_shape[t];
+    T.D = d.n_datasets;
+    T.lo = d.win_lo;
+    T.L = d.win_hi - d.win_lo;
+    T.P = P[t];
+    T.K = std::max(d.n_psd, 1);
+    T.n_cell = sh.n_cell;
+    T.S = sh.S;
+    for (int k = 0; k < T.D; k++) T.exposure[k] = d.exposure[k];
+    // chunk sizes: at least 32 cells / 16 bins per chunk
+    const int cpc = std::max(32, (sh.n_cell + nch_f - 1) / nch_f);
+    T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
+    const int bpc = std::max(16, (T.L + nch_a - 1) / nch_a);
+    T.adj_chunks = (T.L + bpc - 1) / bpc;
+    T.cell_off = cell_off;
+    T.win_off = win_off;
+    T.cnt_off = cnt_off;
+    T.fpart_off = fpart_off;
+    T.apart_off = apart_off;
+    T.pull_off = pull_off;
+    B->fs_off_h.push_back(fs_off);
+    for (int b0 = 0; b0 < T.L; b0 += 64)
+      for (int c = 0; c < T.fold_chunks; c++)
+        B->fold_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
+    for (int c0 = 0; c0 < sh.n_cell; c0 += 64)
+      for (int c = 0; c < T.adj_chunks; c++)
+        B->adj_h.push_back({t, c0, c * bpc, std::min(T.L, (c + 1) * bpc), c});
+    for (int k = 0; k < T.D; k++)
+      for (int j = d.win_lo; j < d.win_hi; j++)
+        for (int q = 0; q < T.K; q++) cnt_h.push_back(d.counts[((size_t)k * d.n_reco + j) * T.K + q]);
+    for (int p = 0; p < T.P; p++) {
+      const bool has = d.pull_sigma && d.pull_sigma[p] > 0;
+      pc_h.push_back(has ? d.pull_centre[p] : 0.0);
+      ps_h.push_back(has ? d.pull_sigma[p] : 0.0);
+    }
+    cell_off += sh.n_cell;
+    win_off += T.L;
+    cnt_off += (long long)T.D * T.L * T.K;
+    fpart_off += (long long)T.fold_chunks * T.L;
+    apart_off += (long long)T.adj_chunks * sh.n_cell * 3;
+    pull_off += T.P;
+    fs_off += (long long)T.fold_chunks * T.L * T.S;
+    B->max_cells = std::max(B->max_cells, sh.n_cell);
+    B->max_LS = std::max(B->max_LS, T.L * T.S);
+    B->toys_h.push_back(T);
+  }
+  BatchView &v = B->v;
+  v.n_toys = n_toys;
+  v.stride = B->stride;
+  ShapeDev *shd;
+  ToyDev *tod;
+  FoldItem *fi;
+  AdjItem *ai;
+  double *cnt, *pc, *ps;
+  long long *fso;
+  HIP_TRY(B->alloc(&shd, B->shapes_h.size()));
+  HIP_TRY(B->alloc(&tod, B->toys_h.size()));
+  HIP_TRY(B->alloc(&fi, B->fold_h.size()));
+  HIP_TRY(B->alloc(&ai, B->adj_h.size()));
+  HIP_TRY(B->alloc(&cnt, cnt_h.size()));
+  HIP_TRY(B->alloc(&pc, pc_h.size()));
+  HIP_TRY(B->alloc(&ps, ps_h.size()));
+  HIP_TRY(B->alloc(&fso, B->fs_off_h.size()));
+  HIP_TRY(B->alloc(&v.rec, (size_t)cell_off * kRecLen));
+  HIP_TRY(B->alloc(&v.fpart, (size_t)fpart_off));
+  HIP_TRY(B->alloc(&v.apart, (size_t)apart_off));
+  HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinLen));
+  HIP_TRY(B->alloc(&v.fspart, (size_t)fs_off));
+  HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
+  HIP_TRY(hipMemcpy(shd, B->shapes_h.data(), B->shapes_h.size() * sizeof(ShapeDev), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(tod, B->toys_h.data(), B->toys_h.size() * sizeof(ToyDev), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(fi, B->fold_h.data(), B->fold_h.size() * sizeof(FoldItem), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ai, B->adj_h.data(), B->adj_h.size() * sizeof(AdjItem), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(pc, pc_h.data(), pc_h.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ps, ps_h.data(), ps_h.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(fso, B->fs_off_h.data(), B->fs_off_h.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipDeviceSynchronize());
+  v.shapes = shd;
+  v.toys = tod;
+  v.fold_items = fi;
+  v.n_fold_items = (int)B->fold_h.size();
+  v.adj_items = ai;
+  v.n_adj_items = (int)B->adj_h.size();
+  v.cnt = cnt;
+  v.pull_c = pc;
+  v.pull_s = ps;
+  v.fs_off = fso;
+  *out = guard.release();
+  return GS_OK;
+}
+
+// Launch through `f`, bracketed by timing events when profiling is on.
+template <class F>
+hipError_t timed(gs_batch *B, int kernel, hipStream_t st, F f) {
+  if (!B->prof) return f();
+  hipEvent_t a = B->event(), b = B->event();
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = f();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  B->pending.push_back({kernel, a, b});
+  return e;
+}
+
+// One adjoint-path evaluation of every toy: cells, fold, -ln L, adjoint, gradient.
+gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
+                           double *d_mu, hipStream_t st) {
+  const BatchView &v = B->v;
+  HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, nullptr, B->max_cells, st); }));
+  HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold1(v, st); }));
+  HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_nll1(v, d_theta, d_nll, d_status, d_mu, nullptr, st); }));
+  if (d_grad) {
+    HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj1(v, st); }));
+    HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_grad1(v, d_theta, d_status, d_grad, nullptr, st); }));
+  }
+  return GS_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ===
+extern "C" {
+
+const char *gs_last_error(void) { return g_err.c_str(); }
+
+int32_t gs_desc_validate(const gs_model_desc *d) { return validate(d); }
+
+gs_status gs_batch_create(const gs_model_desc *descs, int32_t n_toys, int32_t device, gs_batch **out) {
+  if (!out) return fail(GS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return build_batch(descs, n_toys, device, out);
+}
+
+void gs_batch_destroy(gs_batch *b) { delete b; }
+int32_t gs_batch_num_toys(const gs_batch *b) { return b ? b->n_toys : 0; }
+int32_t gs_batch_param_stride(const gs_batch *b) { return b ? b->stride : 0; }
+
+gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
+                              void *hip_stream) {
+  if (!b || !d_theta || !d_nll || !d_status) return fail(GS_ERR_ARG, "null argument");
+  HIP_TRY(hipSetDevice(b->device));
+  return enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, (hipStream_t)hip_stream);
+}
+
+gs_status gs_batch_set_profiling(gs_batch *b, int32_t on) {
+  if (!b) return fail(GS_ERR_ARG, "null batch");
+  b->prof = on != 0;
+  return GS_OK;
+}
+
+gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset) {
+  if (!b || !ms || !launches) return fail(GS_ERR_ARG, "null argument");
+  HIP_TRY(hipSetDevice(b->device));
+  for (auto &t : b->pending) {
+    float el = 0.f;
+    HIP_TRY(hipEventSynchronize(t.b));
+    HIP_TRY(hipEventElapsedTime(&el, t.a, t.b));
+    b->prof_ms[t.kernel] += el;
+    b->prof_n[t.kernel] += 1;
+    b->ev_free.push_back(t.a);
+    b->ev_free.push_back(t.b);
+  }
+  b->pending.clear();
+  for (int k = 0; k < GS_K_COUNT; k++) {
+    ms[k] = b->prof_ms[k];
+    launches[k] = b->prof_n[k];
+    if (reset) {
+      b->prof_ms[k] = 0.0;
+      b->prof_n[k] = 0;
+    }
+  }
+  return GS_OK;
+}
+
+gs_status gs_model_create(const gs_model_desc *d, int32_t device, gs_model **out) {
+  if (!out) return fail(GS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  gs_batch *b = nullptr;
+  gs_status s = build_batch(d, 1, device, &b);
+  if (s != GS_OK) return s;
+  auto *M = new gs_model();
+  M->b = b;
+  M->P = b->toys_h[0].P;
+  const ToyDev &T = b->toys_h[0];
+  M->n_mu = T.D * T.L * T.K;
+  auto cleanup = [&](gs_status e) {
+    gs_model_destroy(M);
+    return e;
+  };
+#define MTRY(expr)                                                                                    \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return cleanup(fail(GS_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)));                   \
+  } while (0)
+  MTRY(hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking));
+  MTRY(hipMalloc((void **)&M->d_theta, sizeof(double) * b->stride));
+  MTRY(hipMalloc((void **)&M->d_nll, sizeof(double)));
+  MTRY(hipMalloc((void **)&M->d_grad, sizeof(double) * b->stride));
+  MTRY(hipMalloc((void **)&M->d_mu, sizeof(double) * std::max(M->n_mu, 1)));
+  MTRY(hipMalloc((void **)&M->d_status, sizeof(uint32_t)));
+  MTRY(hipHostMalloc((void **)&M->h_theta, sizeof(double) * b->stride, hipHostMallocDefault));
+  MTRY(hipHostMalloc((void **)&M->h_out, sizeof(double) * (1 + b->stride + std::max(M->n_mu, 1)), hipHostMallocDefault));
+  MTRY(hipHostMalloc((void **)&M->h_status, sizeof(uint32_t), hipHostMallocDefault));
+#undef MTRY
+  *out = M;
+  return GS_OK;
+}
+
+void gs_model_destroy(gs_model *m) {
+  if (!m) return;
+  if (m->b) (void)hipSetDevice(m->b->device);
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  (void)hipFree(m->d_theta);
+  (void)hipFree(m->d_nll);
+  (void)hipFree(m->d_grad);
+  (void)hipFree(m->d_mu);
+  (void)hipFree(m->d_status);
+  (void)hipHostFree(m->h_theta);
+  (void)hipHostFree(m->h_out);
+  (void)hipHostFree(m->h_status);
+  if (m->stream) (void)hipStreamDestroy(m->stream);
+  delete m->b;
+  delete m;
+}
+
+int32_t gs_model_num_params(const gs_model *m) { return m ? m->P : 0; }
+
+static gs_status upload_theta(gs_model *M, const double *theta) {
+  std::memcpy(M->h_theta, theta, sizeof(double) * M->P);
+  for (int p = M->P; p < M->b->stride; p++) M->h_theta[p] = 0.0;
+  HIP_TRY(hipMemcpyAsync(M->d_theta, M->h_theta, sizeof(double) * M->b->stride, hipMemcpyHostToDevice, M->stream));
+  return GS_OK;
+}
+
+gs_status gs_nll_grad(gs_model *M, const double *theta, double *nll, double *grad, uint32_t *st) {
+  if (!M || !theta || !nll) return fail(GS_ERR_ARG, "null argument");
+  gs_batch *B = M->b;
+  HIP_TRY(hipSetDevice(B->device));
+  gs_status s = upload_theta(M, theta);
+  if (s != GS_OK) return s;
+  s = enqueue_nll_grad(B, M->d_theta, M->d_nll, grad ? M->d_grad : nullptr, M->d_status, nullptr, M->stream);
+  if (s != GS_OK) return s;
+  HIP_TRY(hipMemcpyAsync(M->h_out, M->d_nll, sizeof(double), hipMemcpyDeviceToHost, M->stream));
+  if (grad)
+    HIP_TRY(hipMemcpyAsync(M->h_out + 1, M->d_grad, sizeof(double) * M->P, hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipMemcpyAsync(M->h_status, M->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipStreamSynchronize(M->stream));
+  *nll = M->h_out[0];
+  if (grad) std::memcpy(grad, M->h_out + 1, sizeof(double) * M->P);
+  if (st) *st = *M->h_status;
+  return GS_OK;
+}
+
+gs_status gs_expected(gs_model *M, const double *theta, double *mu) {
+  if (!M || !theta || !mu) return fail(GS_ERR_ARG, "null argument");
+  gs_batch *B = M->b;
+  HIP_TRY(hipSetDevice(B->device));
+  gs_status s = upload_theta(M, theta);
+  if (s != GS_OK) return s;
+  s = enqueue_nll_grad(B, M->d_theta, M->d_nll, nullptr, M->d_status, M->d_mu, M->stream);
+  if (s != GS_OK) return s;
+  HIP_TRY(hipMemcpyAsync(M->h_out, M->d_mu, sizeof(double) * M->n_mu, hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipStreamSynchronize(M->stream));
+  std::memcpy(mu, M->h_out, sizeof(double) * M->n_mu);
+  return GS_OK;
+}
+
+gs_status gs_nll(gs_model *M, const double *theta, double *nll, uint32_t *st) {
+  if (!M || !theta || !nll) return fail(GS_ERR_ARG, "null argument");
+  gs_batch *B = M->b;
+  HIP_TRY(hipSetDevice(B->device));
+  const ShapeDev &sh = B->shapes_h[0];
+  const int nr = sh.family == GS_RESP_GAUSS_E ? 2 : 5;
+  std::vector<double> resp(theta + sh.S, theta + sh.S + nr);
+  gs_status s = upload_theta(M, theta);
+  if (s != GS_OK) return s;
+  const bool refold = !M->cache_valid || std::memcmp(resp.data(), M->cached_resp.data(), nr * 8) != 0;
+  if (refold) {
+    HIP_TRY(launch_cells(B->v, M->d_theta, nullptr, B->max_cells, M->stream));
+    HIP_TRY(launch_foldS(B->v, M->stream));
+    HIP_TRY(launch_reduceF_grid(B->v, B->max_LS, M->stream));
+    M->cached_resp = resp;
+    M->cache_valid = true;
+  }
+  HIP_TRY(launch_nllF(B->v, M->d_theta, M->d_nll, M->d_status, nullptr, M->stream));
+  HIP_TRY(hipMemcpyAsync(M->h_out, M->d_nll, sizeof(double), hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipMemcpyAsync(M->h_status, M->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipStreamSynchronize(M->stream));
+  *nll = M->h_out[0];
+  if (st) *st = *M->h_status;
+  return GS_OK;
+}
+
+gs_status gs_fit(gs_model *M, const double *theta0, const gs_fit_opts *o, double *theta_hat, double *sigma,
+                 gs_fit_result *res);
+
+gs_status gs_fit_batched(gs_batch *, const double *, const uint8_t *, const gs_fit_opts *, double *, double *,
+                         double *, int32_t *, uint32_t *, void *) {
+  return fail(GS_ERR_UNSUPPORTED, "gs_fit_batched not built yet");
+}
+
+}  // extern "C"

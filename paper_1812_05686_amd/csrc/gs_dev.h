@@ -1,0 +1,256 @@
+// gs_dev.h -- device-side arithmetic of the fold likelihood for gfx950.
+//
+// Per-cell response constants and per-pair response evaluation
+// (section 2.3 response families, section 2.5 mesh evaluation).  The gamma
+// family's log-density has terms of size ~k ln x (~10^4 at k ~ 10^3) that
+// cancel to O(1); the per-pair exponent is therefore evaluated from
+// double-double per-cell and per-bin constants with error-free products,
+// so one FP64 exp per pair keeps the per-bin relative error near 1e-15.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kRecLen = 8;  // doubles per cell record
+constexpr int kBinLen = 4;  // doubles per bin record
+constexpr double kHalfLn2Pi = 0.91893853320467274178032973640561764;  // ln(2 pi)/2
+// ln 2 as an unevaluated sum hi + lo (hi = nearest double)
+constexpr double kLn2Hi = 0.6931471805599453094;   // 0x1.62e42fefa39efp-1
+constexpr double kLn2Lo = 2.319046813846299558e-17;
+
+enum Family : int { kGaussE = 0, kGaussPE = 1, kGammaPE = 2 };
+
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, __fma_rn(a, b, -p)};
+}
+
+// Natural log of a positive double as hi + lo with |error| ~ 1e-19 relative.
+// x = 2^e f, f in [1/sqrt2, sqrt2); ln f = 2 atanh(s), s = (f - 1)/(f + 1),
+// |s| <= 0.1716, with s carried as a double-double quotient.
+__device__ inline dd dd_log(double x) {
+  int e;
+  double f = frexp(x, &e);  // f in [0.5, 1)
+  if (f < 0.70710678118654752440) {
+    f *= 2.0;
+    e -= 1;
+  }
+  double num = f - 1.0;  // exact for f in [0.5, 2]
+  dd den = two_sum(f, 1.0);
+  double sh = num / den.hi;
+  double rem = __fma_rn(-sh, den.hi, num) - sh * den.lo;
+  double sl = rem / den.hi;
+  double s2 = sh * sh;
+  // atanh(s)/s - 1 = s^2/3 + s^4/5 + ... through s^24/25
+  double t = 1.0 / 25;
+  t = __fma_rn(t, s2, 1.0 / 23);
+  t = __fma_rn(t, s2, 1.0 / 21);
+  t = __fma_rn(t, s2, 1.0 / 19);
+  t = __fma_rn(t, s2, 1.0 / 17);
+  t = __fma_rn(t, s2, 1.0 / 15);
+  t = __fma_rn(t, s2, 1.0 / 13);
+  t = __fma_rn(t, s2, 1.0 / 11);
+  t = __fma_rn(t, s2, 1.0 / 9);
+  t = __fma_rn(t, s2, 1.0 / 7);
+  t = __fma_rn(t, s2, 1.0 / 5);
+  t = __fma_rn(t, s2, 1.0 / 3);
+  t *= s2;
+  // 2 atanh(sh + sl) = 2 sh + 2 (sh t + sl (1 + sh^2)) + O(sl^2)
+  double tail = 2.0 * __fma_rn(sh, t, sl * (1.0 + s2));
+  dd le = two_prod((double)e, kLn2Hi);
+  le.lo = __fma_rn((double)e, kLn2Lo, le.lo);
+  dd r = two_sum(le.hi, 2.0 * sh);
+  double lo = r.lo + le.lo + tail;
+  return two_sum(r.hi, lo);
+}
+
+// Remainder of Stirling's formula, s(k) = lgamma(k) - (k - 1/2) ln k + k - ln(2 pi)/2.
+// For k >= 12 the asymptotic series sum_n B_2n / (2n (2n-1) k^(2n-1)); below,
+// the exact recurrence s(k) = s(k+1) + (k + 1/2) ln(1 + 1/k) - 1.
+__device__ inline double stirling_rem(double k) {
+  double acc = 0.0;
+  while (k < 12.0) {
+    acc += __fma_rn(k + 0.5, log1p(1.0 / k), -1.0);
+    k += 1.0;
+  }
+  double r = 1.0 / k, r2 = r * r;
+  double p = -3617.0 / 122400.0;
+  p = __fma_rn(p, r2, 1.0 / 156.0);
+  p = __fma_rn(p, r2, -691.0 / 360360.0);
+  p = __fma_rn(p, r2, 1.0 / 1188.0);
+  p = __fma_rn(p, r2, -1.0 / 1680.0);
+  p = __fma_rn(p, r2, 1.0 / 1260.0);
+  p = __fma_rn(p, r2, -1.0 / 360.0);
+  p = __fma_rn(p, r2, 1.0 / 12.0);
+  return acc + p * r;
+}
+
+// ln k - psi(k): asymptotic series for k >= 8 (no cancellation), else shifted
+// up with psi(k) = psi(k + n) - sum_{j<n} 1/(k + j).
+__device__ inline double log_minus_digamma(double k) {
+  double acc = 0.0, k0 = k;
+  while (k < 8.0) {
+    acc += 1.0 / k;
+    k += 1.0;
+  }
+  double r = 1.0 / k, r2 = r * r;
+  // ln k - psi(k) = 1/(2k) + 1/(12k^2) - 1/(120k^4) + 1/(252k^6) - 1/(240k^8) + 1/(132k^10)
+  //                 - 691/(32760k^12) + 1/(12k^14)
+  double p = 1.0 / 12.0;
+  p = __fma_rn(p, r2, -691.0 / 32760.0);
+  p = __fma_rn(p, r2, 1.0 / 132.0);
+  p = __fma_rn(p, r2, -1.0 / 240.0);
+  p = __fma_rn(p, r2, 1.0 / 252.0);
+  p = __fma_rn(p, r2, -1.0 / 120.0);
+  p = __fma_rn(p, r2, 1.0 / 12.0);
+  double v = __fma_rn(p, r2, 0.5 * r);
+  if (k != k0) v += acc - log(k / k0);  // ln k0 - psi(k0) = [ln k - psi(k)] - ln(k/k0) + sum 1/(k0+j)
+  return v;
+}
+
+// Birks quenching factor Q(E) = 1 - 2/y + 2 ln(1+y)/y^2, y = sqrt(E)/(kB A),
+// and dQ/dkB.  Below y = 0.05 the series 2 sum (-1)^(n+1) y^n/(n+2).
+__device__ inline double quench(double E, double kB, double A, double *dQ_dkB) {
+  if (!(E > 0.0)) {
+    *dQ_dkB = 0.0;
+    return 0.0;
+  }
+  double y = sqrt(E) / (kB * A);
+  double Q, dQdy;
+  if (y < 0.05) {
+    Q = 0.0;
+    dQdy = 0.0;
+    double yn = 1.0;
+    for (int n = 1; n <= 14; n++) {
+      double c = ((n & 1) ? 2.0 : -2.0) / (n + 2);
+      dQdy = __fma_rn(c * n, yn, dQdy);
+      yn *= y;
+      Q = __fma_rn(c, yn, Q);
+    }
+  } else {
+    double iy = 1.0 / y;
+    double L = log1p(y);
+    Q = 1.0 - 2.0 * iy + 2.0 * L * iy * iy;
+    dQdy = 2.0 * iy * iy - 4.0 * L * iy * iy * iy + 2.0 * iy * iy / (1.0 + y);
+  }
+  *dQ_dkB = -dQdy * y / kB;
+  return Q;
+}
+
+// Response moments m(E), s(E) and their derivatives w.r.t. the response
+// parameters (a, b) or (LY, kB, a, b, c).  Returns false for an invalid response.
+struct Moments {
+  double m, s;
+  double dm[5], ds[5];
+};
+
+__device__ inline bool moments(int fam, const double *resp, double A, double E, Moments &o) {
+#pragma unroll
+  for (int p = 0; p < 5; p++) o.dm[p] = o.ds[p] = 0.0;
+  if (fam == kGaussE) {
+    double a = resp[0], b = resp[1];
+    double s2 = __fma_rn(b, E, a * a);
+    o.m = E;
+    o.s = sqrt(s2);
+    o.ds[0] = a / o.s;
+    o.ds[1] = 0.5 * E / o.s;
+    return s2 > 0.0 && s2 < 1e300;
+  }
+  double LY = resp[0], kB = resp[1], a = resp[2], b = resp[3], c = resp[4];
+  if (!(kB > 0.0)) {
+    o.m = o.s = 0.0;
+    return false;
+  }
+  double dQ;
+  double Q = quench(E, kB, A, &dQ);
+  double m = LY * Q * E;
+  double s2 = a * a + b * m + c * c * m * m;
+  double s = sqrt(s2);
+  o.m = m;
+  o.s = s;
+  o.dm[0] = Q * E;
+  o.dm[1] = LY * E * dQ;
+  double dsdm = (b + 2.0 * c * c * m) / (2.0 * s);
+  o.ds[0] = dsdm * o.dm[0];
+  o.ds[1] = dsdm * o.dm[1];
+  o.ds[2] = a / s;
+  o.ds[3] = 0.5 * m / s;
+  o.ds[4] = c * m * m / s;
+  bool ok = s2 > 0.0 && s2 < 1e300;
+  if (fam == kGammaPE) ok = ok && m > 0.0;
+  return ok;
+}
+
+// Per-cell record (8 doubles), consumed by the fold and adjoint loops.
+//  gamma:    {k - 1, 1/th hi, 1/th lo, C hi, C lo, W, ln(k th) hi, k th}
+//            C = -lgamma(k) - k ln th, in double-double
+//  gaussian: {m, 1/s, -ln s - ln(2 pi)/2, W, 0, 0, 0, 0}
+// W = sum_s R_s w_si (1-D combined weight); NaN marks an invalid response.
+__device__ inline void cell_record(int fam, double m, double s, double W, bool ok, double *rec) {
+  if (!ok) {
+    for (int q = 0; q < kRecLen; q++) rec[q] = __builtin_nan("");
+    return;
+  }
+  if (fam == kGammaPE) {
+    double s2 = s * s;
+    double k = m * m / s2;
+    double th = s2 / m;
+    double bh = 1.0 / th;
+    double bl = __fma_rn(-bh, th, 1.0) * bh;
+    dd mk = two_prod(k, th);             // k th = mean, exactly as hi + lo
+    dd lm = dd_log(mk.hi);
+    lm.lo += mk.lo / mk.hi;
+    // C = -k ln(k th) + k + ln(k)/2 - ln(2 pi)/2 - s(k)
+    dd p = two_prod(k, lm.hi);
+    p.lo = __fma_rn(k, lm.lo, p.lo);
+    dd c1 = two_sum(-p.hi, k);
+    double small = 0.5 * log(k) - kHalfLn2Pi - stirling_rem(k) - p.lo;
+    dd C = two_sum(c1.hi, c1.lo + small);
+    rec[0] = k - 1.0;
+    rec[1] = bh;
+    rec[2] = bl;
+    rec[3] = C.hi;
+    rec[4] = C.lo;
+    rec[5] = W;
+    rec[6] = lm.hi;
+    rec[7] = mk.hi;
+  } else {
+    rec[0] = m;
+    rec[1] = 1.0 / s;
+    rec[2] = -log(s) - kHalfLn2Pi;
+    rec[3] = W;
+    rec[4] = rec[5] = rec[6] = rec[7] = 0.0;
+  }
+}
+
+// Per-pair log-density: gamma uses the bin's x and ln x as double-double.
+__device__ __forceinline__ double gamma_exponent(double K, double Bh, double Bl, double Ch, double Cl,
+                                                 double x, double Lh, double Ll) {
+  double p = K * Lh;
+  double ep = __fma_rn(K, Lh, -p);
+  double q = x * Bh;
+  double eq = __fma_rn(x, Bh, -q);
+  double t = (p + Ch) - q;
+  double corr = __fma_rn(K, Ll, ep) - eq;
+  corr = __fma_rn(-x, Bl, corr) + Cl;
+  return t + corr;
+}
+
+__device__ __forceinline__ double gauss_exponent(double m, double is, double c0, double x, double &z) {
+  z = (x - m) * is;
+  return __fma_rn(-0.5 * z, z, c0);
+}
+
+}  // namespace gs

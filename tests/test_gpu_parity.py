@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by element,
+on seeded synthetic inputs (GooStats, arXiv:1812.05686: Eq.2 fold, Eq.4 likelihood).
+
+Bars: |dNLL|/|NLL| <= 1e-11; per-bin expected counts within 1e-12 relative for mu >= 1e-3
+(the paper's own validation bound, section 3.1); gradient per component
+|dg_p| s_p <= 1e-8 max(|g_p| s_p, 1) with s_p the parameter scale."""
+import numpy as np
+import pytest
+
+import gsgen
+
+pytestmark = pytest.mark.gpu
+
+NLL_TOL = 1e-11
+MU_TOL = 1e-12
+GRAD_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import paper_1812_05686_amd as gs
+    gs.lib()
+    return gs
+
+
+def _grad_err(g, og, scale):
+    return np.max(np.abs(g - og) * scale / np.maximum(np.abs(og) * scale, 1.0))
+
+
+def _cases():
+    yield "c0", lambda: gsgen.config0()
+    yield "c1", lambda: gsgen.config1()
+    yield "c1_gauss", lambda: gsgen.config1(gsgen.GAUSS_PE)
+    # several tiles plus a ragged tail on both axes, window not at the edges
+    yield "ragged_gamma", lambda: gsgen.small_gamma_model(n_true=333, n_reco=211, seed=4).replace(win_lo=7, win_hi=150)
+    yield "ragged_gauss_pe", lambda: gsgen.small_gamma_model(n_true=129, n_reco=77, seed=5,
+                                                            family=gsgen.GAUSS_PE).replace(win_lo=1, win_hi=66)
+    yield "two_datasets", lambda: gsgen.small_gamma_model(n_true=200, n_reco=100, seed=6, n_datasets=2)
+
+
+CASES = dict(_cases())
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request, orc):
+    m = CASES[request.param]()
+    return request.param, m, orc.Oracle(m)
+
+
+def test_expected_counts_per_bin(gs, case):
+    name, m, o = case
+    model = gs.Model(m)
+    for th in (m.theta_true, gsgen.offset_point(m, 2.0, seed=1)):
+        mu = model.expected(th).reshape(m.n_datasets, m.win_hi - m.win_lo)
+        ref = o.expected(th)[:, m.win_lo:m.win_hi, 0]
+        big = ref >= 1e-3
+        rel = np.abs(mu - ref)[big] / ref[big]
+        assert rel.max() <= MU_TOL, (name, rel.max())
+        np.testing.assert_allclose(mu, ref, rtol=1e-9, atol=1e-12)
+
+
+def test_nll_and_gradient(gs, case):
+    name, m, o = case
+    model = gs.Model(m)
+    pts = [m.theta_true, m.theta0] + [gsgen.offset_point(m, 2.0, seed=s) for s in (1, 2)]
+    for th in pts:
+        v, g, st = model.nll_grad(th)
+        ov, og, ost = o.nll_grad(th)
+        assert st == ost == 0
+        assert abs(v - ov) / abs(ov) <= NLL_TOL, (name, v, ov)
+        assert _grad_err(g, og, m.fd_scale) <= GRAD_TOL, (name, _grad_err(g, og, m.fd_scale))
+
+
+def test_plain_path_cache(gs, case):
+    """gs_nll (per-species fold cached across rate-only changes) equals the adjoint path's
+    value and the oracle, before and after a cache hit."""
+    name, m, o = case
+    model = gs.Model(m)
+    th = gsgen.offset_point(m, 1.0, seed=7)
+    v1, st = model.nll(th)
+    ov = o.nll(th)[0]
+    assert st == 0 and abs(v1 - ov) / abs(ov) <= NLL_TOL
+    th2 = th.copy()
+    th2[: m.n_species] *= 1.03  # rates only: cached fold reused
+    v2, _ = model.nll(th2)
+    assert abs(v2 - o.nll(th2)[0]) / abs(ov) <= NLL_TOL
+    vg, _, _ = model.nll_grad(th2)
+    assert abs(v2 - vg) / abs(vg) <= 1e-13
+
+
+def test_deterministic(gs, c1):
+    model = gs.Model(c1)
+    th = gsgen.offset_point(c1, 1.0, seed=9)
+    a = model.nll_grad(th)
+    b = model.nll_grad(th)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_status_matches_oracle(gs, orc, c0):
+    model = gs.Model(c0)
+    o = orc.Oracle(c0)
+    th = c0.theta_true.copy()
+    th[0] = -1e6
+    v, g, st = model.nll_grad(th)
+    assert st == o.nll(th)[1] == 1 and v == np.inf and np.all(np.isnan(g))
+    th = c0.theta_true.copy()
+    th[4] = np.nan
+    v, g, st = model.nll_grad(th)
+    assert st & 2 and np.isnan(v)
+    m = gsgen.small_gamma_model(n_true=60, n_reco=30)
+    th = m.theta_true.copy()
+    th[m.n_species + 1] = -0.01  # invalid quenching constant
+    assert gs.Model(m).nll_grad(th)[2] == orc.Oracle(m).nll(th)[1] == 1
+
+
+def test_edge_shapes(gs, orc):
+    """Degenerate shapes: one-bin window, one true cell, line-only model, bins at x <= 0."""
+    base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
+    edge = [base.replace(win_lo=17, win_hi=18),
+            base.replace(n_true=1, spectra=base.spectra[:, :1] / np.maximum(base.spectra[:, :1].sum(1, keepdims=True), 1),
+                         e_lo=0.5, e_step=1.0),
+            base.replace(reco_edges=np.linspace(-100.0, 1340.0, 41),
+                         counts=np.where(np.arange(40)[None, :, None] < 3, 0.0, base.counts))]
+    line_only = base.replace(spectra=base.spectra[:2], line_energy=base.line_energy[:2])
+    th = np.concatenate([base.theta_true[:2], base.theta_true[base.n_species:]])
+    line_only = line_only.replace(theta_true=th, pull_centre=th, pull_sigma=np.zeros(7), fd_scale=base.fd_scale[[0, 1, 5, 6, 7, 8, 9]])
+    for q, m in enumerate(edge + [line_only]):
+        # data drawn from the model itself, so no bin holds counts where mu underflows
+        mu = orc.Oracle(m).expected(m.theta_true)
+        m = m.replace(counts=np.random.default_rng(q).poisson(mu).astype(float))
+        o = orc.Oracle(m)
+        model = gs.Model(m)
+        v, g, st = model.nll_grad(m.theta_true)
+        ov, og, ost = o.nll_grad(m.theta_true)
+        assert st == ost == 0
+        assert abs(v - ov) / max(abs(ov), 1e-300) <= NLL_TOL
+        assert _grad_err(g, og, m.fd_scale) <= GRAD_TOL
+
+
+def test_unrepresentable_seed_is_domain(gs, orc):
+    """n > 0 in a bin whose mu is so small that 1 - n/mu overflows: both sides report DOMAIN."""
+    base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
+    m = base.replace(n_true=1, spectra=base.spectra[:, :1].copy(), e_lo=0.5, e_step=1.0)
+    assert gs.Model(m).nll_grad(m.theta_true)[2] == orc.Oracle(m).nll(m.theta_true)[1] == 1
+
+
+def test_batch_matches_single(gs, orc):
+    import torch
+    base = gsgen.config1()
+    toys = gsgen.config3(6, base=base)
+    batch = gs.Batch(toys)
+    th = torch.tensor(np.stack([t.theta_true for t in toys]), dtype=torch.float64, device="cuda")
+    nll, grad, st = batch.nll_grad(th)
+    torch.cuda.synchronize()
+    for t, m in enumerate(toys):
+        v, g, s = gs.Model(m).nll_grad(m.theta_true)
+        assert int(st[t]) == s == 0
+        assert abs(float(nll[t]) - v) / abs(v) <= 1e-13
+        np.testing.assert_allclose(grad[t].cpu().numpy(), g, rtol=1e-10, atol=1e-9)
+    o = orc.Oracle(toys[3])
+    ov = o.nll(toys[3].theta_true)[0]
+    assert abs(float(nll[3]) - ov) / abs(ov) <= NLL_TOL
+
+
+def test_autograd_function(gs):
+    import torch
+    toys = gsgen.config3(3, base=gsgen.config1())
+    batch = gs.Batch(toys)
+    th = torch.tensor(np.stack([t.theta0 for t in toys]), dtype=torch.float64, device="cuda", requires_grad=True)
+    nll, st = gs.gsnll(th, batch)
+    w = torch.tensor([1.0, 2.0, -0.5], dtype=torch.float64, device="cuda")
+    (nll * w).sum().backward()
+    _, grad, _ = batch.nll_grad(th.detach())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(th.grad.cpu().numpy(), (w[:, None] * grad).cpu().numpy(), rtol=1e-14)
+
+
+@pytest.mark.parametrize("which", ["c0", "gamma"])
+def test_fit_parity(gs, orc, c0, which):
+    """GPU adjoint fit and GPU finite-difference fit land within 1e-3 sigma of the oracle fit."""
+    m = c0 if which == "c0" else gsgen.small_gamma_model(n_true=300, n_reco=120, seed=2)
+    ref = orc.Oracle(m).fit()
+    assert ref["ok"]
+    model = gs.Model(m)
+    for use_fd in (False, True):
+        r = model.fit(m.theta0, m.fd_scale, use_fd=use_fd)
+        assert r["ok"], r
+        z = np.abs(r["theta"] - ref["theta"]) / ref["sigma"]
+        assert z.max() <= 1e-3, (use_fd, z)
+        assert abs(r["nll"] - ref["nll"]) <= 1e-6
