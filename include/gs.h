@@ -64,6 +64,7 @@ typedef enum { GS_RESP_GAUSS_E = 0, GS_RESP_GAUSS_PE = 1, GS_RESP_GAMMA_PE = 2 }
 #define GS_MAX_SPECIES 16
 #define GS_MAX_DATASETS 8
 #define GS_MAX_PARAMS (GS_MAX_SPECIES + 5 + 3)
+#define GS_MAX_PSD 128
 
 /* Description of one fit problem (section 4.1 lists its inputs: data
  * histogram, components and their types, rates and response parameters,
@@ -124,6 +125,15 @@ gs_status gs_nll_grad(gs_model *m, const double *theta, double *nll, double *gra
 /* Expected counts mu[n_datasets][win_hi - win_lo][max(n_psd,1)] (host) at
  * theta (Eq.2 fold, scaled by rates and exposure).  Synchronous. */
 gs_status gs_expected(gs_model *m, const double *theta, double *mu);
+
+/* Per-species expected reco spectra at unit rate and exposure,
+ * F[win_hi - win_lo][n_species] (host), species in descriptor order: the
+ * folded component spectra that the expectation combines (Eq.2).  Synchronous. */
+gs_status gs_species_spectra(gs_model *m, const double *theta, double *F);
+
+/* Per-species pulse-shape bin probabilities P[n_species][n_psd] (host) at
+ * theta (2-D models only; GS_ERR_ARG otherwise).  Synchronous. */
+gs_status gs_psd_probs(gs_model *m, const double *theta, double *P);
 
 /* Fit controls for gs_fit and gs_fit_batched. */
 typedef struct {
@@ -187,6 +197,17 @@ gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_f
                          double *d_theta_hat, double *d_nll_hat, double *d_sigma, int32_t *d_iters,
                          uint32_t *d_status, void *hip_stream);
 
+/* ------------------------------------------------------- mesh banding --- */
+/* Pairs (reco bin j, true cell i) whose log-density ln r(xbar_j | E_i) is
+ * below log_cut are skipped (default -60).  Each cell's support, the bins
+ * where the log-density can exceed log_cut, is solved per evaluation, so the
+ * absolute error of every expected count is at most
+ * sum_s |R_s| eps_d dx_j exp(log_cut) (5.6e-21 counts for the 4000-cell,
+ * 900-bin model at its nominal rates).  -INFINITY evaluates the full mesh.
+ * The setting applies to later calls on the batch / model. */
+gs_status gs_batch_set_log_cut(gs_batch *b, double log_cut);
+gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
+
 /* --------------------------------------------------------- profiling --- */
 /* Kernel ids for gs_batch_kernel_times. */
 #define GS_K_CELLS 0   /* per-cell response moments and records           */
@@ -198,7 +219,8 @@ gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_f
 #define GS_K_REDF 6    /* per-species split-K reduction                    */
 #define GS_K_NLLF 7    /* -ln L from per-species spectra                   */
 #define GS_K_QN 8      /* device quasi-Newton step                         */
-#define GS_K_COUNT 9
+#define GS_K_FINISH 9  /* per-problem totals, pulls, status                */
+#define GS_K_COUNT 10
 
 /* When on, each kernel launch of the batch is bracketed by HIP events
  * recorded on the stream the kernel is launched on (small overhead). */
@@ -207,6 +229,11 @@ gs_status gs_batch_set_profiling(gs_batch *b, int32_t on);
  * last reset (host arrays of GS_K_COUNT entries).  Waits for the recorded
  * events; reset != 0 clears the accumulators afterwards. */
 gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset);
+/* Mesh pairs of the most recent evaluation of the batch: out[0] pairs the
+ * fold evaluated (64 lanes per visited cell and bin tile, idle lanes of a
+ * partial tile included), out[1] pairs the adjoint evaluated, out[2] the full
+ * mesh sum_t (window bins x cells).  Synchronises the device. */
+gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out);
 
 #ifdef __cplusplus
 }

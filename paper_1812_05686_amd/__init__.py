@@ -48,8 +48,9 @@ class gs_fit_result(C.Structure):
 EXPORTS = ["gs_last_error", "gs_desc_validate", "gs_model_create", "gs_model_destroy", "gs_model_num_params",
            "gs_nll", "gs_nll_grad", "gs_expected", "gs_fit", "gs_batch_create", "gs_batch_destroy",
            "gs_batch_num_toys", "gs_batch_param_stride", "gs_nll_grad_batched", "gs_fit_batched",
-           "gs_batch_set_profiling", "gs_batch_kernel_times"]
-KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn"]
+           "gs_batch_set_profiling", "gs_batch_kernel_times", "gs_batch_set_log_cut", "gs_model_set_log_cut",
+           "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs"]
+KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish"]
 
 _lib = None
 
@@ -103,6 +104,16 @@ def lib():
         L.gs_batch_set_profiling.argtypes = [vp, C.c_int32]
         L.gs_batch_kernel_times.restype = C.c_int
         L.gs_batch_kernel_times.argtypes = [vp, _dp, C.POINTER(C.c_int64), C.c_int32]
+        L.gs_batch_set_log_cut.restype = C.c_int
+        L.gs_batch_set_log_cut.argtypes = [vp, C.c_double]
+        L.gs_model_set_log_cut.restype = C.c_int
+        L.gs_model_set_log_cut.argtypes = [vp, C.c_double]
+        L.gs_species_spectra.restype = C.c_int
+        L.gs_species_spectra.argtypes = [vp, _dp, _dp]
+        L.gs_psd_probs.restype = C.c_int
+        L.gs_psd_probs.argtypes = [vp, _dp, _dp]
+        L.gs_batch_mesh_pairs.restype = C.c_int
+        L.gs_batch_mesh_pairs.argtypes = [vp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -165,6 +176,9 @@ class Model:
         except Exception:
             pass
 
+    def set_log_cut(self, log_cut: float):
+        _check(lib().gs_model_set_log_cut(self.h, float(log_cut)), "gs_model_set_log_cut")
+
     def nll(self, theta):
         th = _arr(theta)
         v, st = C.c_double(), C.c_uint32()
@@ -183,6 +197,18 @@ class Model:
         mu = np.zeros(self.n_mu)
         _check(lib().gs_expected(self.h, _ptr(th), _ptr(mu)), "gs_expected")
         return mu
+
+    def species_spectra(self, theta):
+        m = self.desc_src
+        F = np.zeros((m.win_hi - m.win_lo, m.spectra.shape[0]))
+        _check(lib().gs_species_spectra(self.h, _ptr(_arr(theta)), _ptr(F)), "gs_species_spectra")
+        return F
+
+    def psd_probs(self, theta):
+        m = self.desc_src
+        P = np.zeros((m.spectra.shape[0], len(m.psd_edges) - 1))
+        _check(lib().gs_psd_probs(self.h, _ptr(_arr(theta)), _ptr(P)), "gs_psd_probs")
+        return P
 
     def fit(self, theta0, scale, use_fd=False, max_iter=500, edm_tol=1e-9, free=None, hesse=True):
         th0, sc = _arr(theta0), _arr(scale)
@@ -259,6 +285,15 @@ class Batch:
                                          C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()),
                                          self._stream()), "gs_nll_grad_batched")
         return nll, grad, status
+
+    def set_log_cut(self, log_cut: float):
+        _check(lib().gs_batch_set_log_cut(self.h, float(log_cut)), "gs_batch_set_log_cut")
+
+    def mesh_pairs(self):
+        """(fold pairs, adjoint pairs, full-mesh pairs) of the most recent evaluation."""
+        out = (C.c_int64 * 3)()
+        _check(lib().gs_batch_mesh_pairs(self.h, out), "gs_batch_mesh_pairs")
+        return int(out[0]), int(out[1]), int(out[2])
 
     def set_profiling(self, on: bool):
         _check(lib().gs_batch_set_profiling(self.h, int(on)), "gs_batch_set_profiling")

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libgs.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["gs_kernels.hip", "gs_api.hip"]
+HIP_SOURCES = ["gs_kernels.hip", "gs_qn.hip", "gs_api.hip"]
 CXX_SOURCES = ["gs_qn_host.cpp"]
 HIPFLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
             # packed FP32 instructions are disabled for all device code

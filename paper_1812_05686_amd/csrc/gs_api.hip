@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "gs_impl.h"
+#include "gs_qn.h"
 
 using namespace gs;
 
@@ -141,13 +142,11 @@ struct DevBuf {
 
 struct gs_batch {
   int device = 0;
-  int n_toys = 0, stride = 0, max_cells = 0, max_LS = 0;
+  int n_toys = 0, stride = 0;
   std::vector<ShapeDev> shapes_h;
   std::vector<ToyDev> toys_h;
   std::vector<FoldItem> fold_h;
   std::vector<AdjItem> adj_h;
-  std::vector<long long> fs_off_h;
-  std::vector<std::vector<void *>> shape_allocs;
   std::vector<void *> allocs;
   BatchView v{};
   bool has_2d = false;
@@ -161,8 +160,24 @@ struct gs_batch {
   std::vector<hipEvent_t> ev_free;
   double prof_ms[GS_K_COUNT] = {};
   long long prof_n[GS_K_COUNT] = {};
+  // batched fits: device quasi-Newton state and the captured iteration graph
+  bool qn_ready = false;
+  QNView q{};
+  double *e_nll = nullptr, *e_grad = nullptr, *d_scale = nullptr;
+  uint32_t *e_st = nullptr;
+  int *d_count = nullptr, *h_count = nullptr;
+  hipStream_t fit_stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0, graph_max_iter = -1;
+  double graph_tol = -1.0;
 
   ~gs_batch() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (fit_stream) (void)hipStreamDestroy(fit_stream);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (h_count) (void)hipHostFree(h_count);
     for (auto &t : pending) {
       (void)hipEventDestroy(t.a);
       (void)hipEventDestroy(t.b);
@@ -204,9 +219,10 @@ struct gs_model {
 
 namespace {
 
-// Split-K choice: enough wavefronts to fill 256 CUs, without chunks so small
-// that per-item overhead dominates.
-constexpr int kTargetWaves = 8192;
+// Split-K choice: about 8 workgroups per CU when a batch is small; large
+// batches keep whole tiles (one chunk) so no partial sums are needed.
+constexpr int kTargetWG = 2048;
+constexpr double kDefaultLogCut = -60.0;
 
 gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_batch **out) {
   if (!descs || n_toys < 1) return fail(GS_ERR_ARG, "need at least one descriptor");
@@ -214,7 +230,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   for (int t = 0; t < n_toys; t++) {
     P[t] = validate(&descs[t]);
     if (P[t] < 0) return fail(GS_ERR_ARG, "toy %d: %s", t, g_err.c_str());
-    if (descs[t].n_psd > 0) return fail(GS_ERR_UNSUPPORTED, "toy %d: pulse-shape (2-D) models not built yet", t);
+    if (descs[t].n_psd > GS_MAX_PSD) return fail(GS_ERR_UNSUPPORTED, "toy %d: more than %d pulse-shape bins", t, GS_MAX_PSD);
   }
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
@@ -254,7 +270,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     sh.n_psd = d.n_psd;
     sh.birks_A = d.birks_A;
     std::vector<int> grid, line;
-    for (int s = 0; s < d.n_species; s++) (std::isnan(d.line_energy[s]) ? grid : line).push_back(s);
+    for (int q = 0; q < d.n_species; q++) (std::isnan(d.line_energy[q]) ? grid : line).push_back(q);
     sh.Sg = (int)grid.size();
     sh.n_line = (int)line.size();
     sh.n_cell = d.n_true + sh.n_line;
@@ -273,26 +289,42 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     HIP_TRY(hipMemcpy(cE, cellE.data(), cellE.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(wc, wcell.data(), wcell.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(edges, d.reco_edges, ((size_t)d.n_reco + 1) * 8, hipMemcpyHostToDevice));
-    HIP_TRY(launch_bins_setup(nullptr, bins, edges, d.n_reco, nullptr));
+    HIP_TRY(launch_bins_setup(bins, edges, d.n_reco, nullptr));
     sh.cellE = cE;
     sh.wcell = wc;
     sh.bins = bins;
+    if (d.n_psd > 0) {
+      std::vector<double> psd(2 * (size_t)d.n_psd), mix(5 * (size_t)d.n_species);
+      for (int k = 0; k < d.n_psd; k++) {
+        psd[2 * k] = (d.psd_edges[k] + d.psd_edges[k + 1]) * 0.5;
+        psd[2 * k + 1] = d.psd_edges[k + 1] - d.psd_edges[k];
+      }
+      for (int q = 0; q < d.n_species; q++)
+        for (int c = 0; c < 5; c++) mix[5 * q + c] = d.psd_mix[5 * sh.sp_of[q] + c];
+      double *pd, *mx;
+      HIP_TRY(B->alloc(&pd, psd.size()));
+      HIP_TRY(B->alloc(&mx, mix.size()));
+      HIP_TRY(hipMemcpy(pd, psd.data(), psd.size() * 8, hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(mx, mix.data(), mix.size() * 8, hipMemcpyHostToDevice));
+      sh.psd = pd;
+      sh.mix = mx;
+    }
     B->shapes_h.push_back(sh);
   }
 
   // ---- toys, offsets, work items ----
-  long long cell_off = 0, win_off = 0, cnt_off = 0, pull_off = 0;
   long long tiles_f = 0, tiles_a = 0;
   for (int t = 0; t < n_toys; t++) {
     const ShapeDev &sh = B->shapes_h[toy_shape[t]];
-    const int L = descs[t].win_hi - descs[t].win_lo;
-    tiles_f += (L + 63) / 64;
-    tiles_a += (sh.n_cell + 63) / 64;
+    tiles_f += (descs[t].win_hi - descs[t].win_lo + kTile - 1) / kTile;
+    tiles_a += (sh.n_cell + kTile - 1) / kTile;
   }
-  const int nch_f = (int)std::max<long long>(1, (kTargetWaves + tiles_f - 1) / tiles_f);
-  const int nch_a = (int)std::max<long long>(1, (kTargetWaves + tiles_a - 1) / tiles_a);
-  long long fpart_off = 0, apart_off = 0, fs_off = 0;
+  const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
+  const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
+  long long cell_off = 0, win_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
+  long long nllp_off = 0, gpart_off = 0, cflag_off = 0, gam_off = 0, psd_off = 0;
   std::vector<double> cnt_h, pc_h, ps_h;
+  BatchView &v = B->v;
   for (int t = 0; t < n_toys; t++) {
     const gs_model_desc &d = descs[t];
     const ShapeDev &sh = B->shapes_h[toy_shape[t]];
@@ -303,25 +335,41 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.L = d.win_hi - d.win_lo;
     T.P = P[t];
     T.K = std::max(d.n_psd, 1);
+    T.two_d = d.n_psd > 0 ? 1 : 0;
+    T.gam_off = gam_off;
+    T.psd_off = psd_off;
+    if (T.two_d) {
+      gam_off += (long long)T.L * T.K;
+      psd_off += (long long)sh.S * T.K;
+      v.has_2d = true;
+    } else {
+      v.has_1d = true;
+    }
     T.n_cell = sh.n_cell;
     T.S = sh.S;
     for (int k = 0; k < T.D; k++) T.exposure[k] = d.exposure[k];
-    // chunk sizes: at least 32 cells / 16 bins per chunk
-    const int cpc = std::max(32, (sh.n_cell + nch_f - 1) / nch_f);
+    // chunk sizes: at least 128 cells / 64 bins per chunk
+    const int cpc = std::max(128, (sh.n_cell + nch_f - 1) / nch_f);
     T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
-    const int bpc = std::max(16, (T.L + nch_a - 1) / nch_a);
+    const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
+    T.bin_blocks = (T.L + kBlock - 1) / kBlock;
+    T.cell_blocks = (sh.n_cell + kBlock - 1) / kBlock;
+    T.cflag_blocks = (sh.n_cell + kCellBlock - 1) / kCellBlock;
+    T.cflag_off = cflag_off;
     T.cell_off = cell_off;
     T.win_off = win_off;
     T.cnt_off = cnt_off;
     T.fpart_off = fpart_off;
+    T.fs_off = fs_off;
     T.apart_off = apart_off;
+    T.nllp_off = nllp_off;
+    T.gpart_off = gpart_off;
     T.pull_off = pull_off;
-    B->fs_off_h.push_back(fs_off);
-    for (int b0 = 0; b0 < T.L; b0 += 64)
+    for (int b0 = 0; b0 < T.L; b0 += kTile)
       for (int c = 0; c < T.fold_chunks; c++)
         B->fold_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
-    for (int c0 = 0; c0 < sh.n_cell; c0 += 64)
+    for (int c0 = 0; c0 < sh.n_cell; c0 += kTile)
       for (int c = 0; c < T.adj_chunks; c++)
         B->adj_h.push_back({t, c0, c * bpc, std::min(T.L, (c + 1) * bpc), c});
     for (int k = 0; k < T.D; k++)
@@ -336,22 +384,26 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     win_off += T.L;
     cnt_off += (long long)T.D * T.L * T.K;
     fpart_off += (long long)T.fold_chunks * T.L;
-    apart_off += (long long)T.adj_chunks * sh.n_cell * 3;
-    pull_off += T.P;
     fs_off += (long long)T.fold_chunks * T.L * T.S;
-    B->max_cells = std::max(B->max_cells, sh.n_cell);
-    B->max_LS = std::max(B->max_LS, T.L * T.S);
+    apart_off += (long long)T.adj_chunks * sh.n_cell * 3;
+    nllp_off += T.bin_blocks;
+    gpart_off += T.cell_blocks;
+    cflag_off += T.cflag_blocks;
+    pull_off += T.P;
+    v.max_cells = std::max(v.max_cells, sh.n_cell);
+    v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
+    v.max_cflag_blocks = std::max(v.max_cflag_blocks, T.cflag_blocks);
+    v.max_bin_blocks = std::max(v.max_bin_blocks, T.bin_blocks);
     B->toys_h.push_back(T);
   }
-  BatchView &v = B->v;
   v.n_toys = n_toys;
   v.stride = B->stride;
+  v.log_cut = kDefaultLogCut;
   ShapeDev *shd;
   ToyDev *tod;
   FoldItem *fi;
   AdjItem *ai;
   double *cnt, *pc, *ps;
-  long long *fso;
   HIP_TRY(B->alloc(&shd, B->shapes_h.size()));
   HIP_TRY(B->alloc(&tod, B->toys_h.size()));
   HIP_TRY(B->alloc(&fi, B->fold_h.size()));
@@ -359,13 +411,25 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&cnt, cnt_h.size()));
   HIP_TRY(B->alloc(&pc, pc_h.size()));
   HIP_TRY(B->alloc(&ps, ps_h.size()));
-  HIP_TRY(B->alloc(&fso, B->fs_off_h.size()));
   HIP_TRY(B->alloc(&v.rec, (size_t)cell_off * kRecLen));
+  HIP_TRY(B->alloc(&v.cflag, (size_t)cflag_off));
+  HIP_TRY(B->alloc(&v.sup, (size_t)cell_off));
+  HIP_TRY(B->alloc(&v.pflag, (size_t)n_toys));
+  if (v.has_2d) {
+    HIP_TRY(B->alloc(&v.H, (size_t)win_off * GS_MAX_SPECIES));
+    HIP_TRY(B->alloc(&v.Gam, (size_t)gam_off));
+    HIP_TRY(B->alloc(&v.P, (size_t)psd_off));
+    HIP_TRY(B->alloc(&v.dP, (size_t)psd_off * 3));
+    HIP_TRY(B->alloc(&v.vpart, (size_t)n_toys * GS_MAX_SPECIES * 4));
+  }
   HIP_TRY(B->alloc(&v.fpart, (size_t)fpart_off));
-  HIP_TRY(B->alloc(&v.apart, (size_t)apart_off));
-  HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinLen));
   HIP_TRY(B->alloc(&v.fspart, (size_t)fs_off));
   HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
+  HIP_TRY(B->alloc(&v.apart, (size_t)apart_off));
+  HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinLen));
+  HIP_TRY(B->alloc(&v.nllp, (size_t)nllp_off));
+  HIP_TRY(B->alloc(&v.badp, (size_t)nllp_off));
+  HIP_TRY(B->alloc(&v.gpart, (size_t)gpart_off * kGradLen));
   HIP_TRY(hipMemcpy(shd, B->shapes_h.data(), B->shapes_h.size() * sizeof(ShapeDev), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(tod, B->toys_h.data(), B->toys_h.size() * sizeof(ToyDev), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(fi, B->fold_h.data(), B->fold_h.size() * sizeof(FoldItem), hipMemcpyHostToDevice));
@@ -373,7 +437,6 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(pc, pc_h.data(), pc_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ps, ps_h.data(), ps_h.size() * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(fso, B->fs_off_h.data(), B->fs_off_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipDeviceSynchronize());
   v.shapes = shd;
   v.toys = tod;
@@ -384,7 +447,6 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   v.cnt = cnt;
   v.pull_c = pc;
   v.pull_s = ps;
-  v.fs_off = fso;
   *out = guard.release();
   return GS_OK;
 }
@@ -401,17 +463,32 @@ hipError_t timed(gs_batch *B, int kernel, hipStream_t st, F f) {
   return e;
 }
 
-// One adjoint-path evaluation of every toy: cells, fold, -ln L, adjoint, gradient.
+// One adjoint-path evaluation of every toy: cells, fold, -ln L, adjoint,
+// gradient.  One-dimensional toys fold with the combined weight; toys with a
+// secondary observable fold per species and expand over the pulse-shape bins.
 gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
-                           double *d_mu, hipStream_t st) {
+                           double *d_mu, hipStream_t st, const uint8_t *active = nullptr) {
+  B->v.theta_dev = d_theta;
   const BatchView &v = B->v;
-  HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, nullptr, B->max_cells, st); }));
-  HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold1(v, st); }));
-  HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_nll1(v, d_theta, d_nll, d_status, d_mu, nullptr, st); }));
-  if (d_grad) {
-    HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj1(v, st); }));
-    HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_grad1(v, d_theta, d_status, d_grad, nullptr, st); }));
+  HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, active, st); }));
+  if (v.has_1d) {
+    HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold(v, false, kOnly1D, active, st); }));
+    HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins1(v, d_mu, active, st); }));
   }
+  if (v.has_2d) {
+    HIP_TRY(timed(B, GS_K_FOLDS, st, [&] { return launch_fold(v, true, kOnly2D, active, st); }));
+    HIP_TRY(timed(B, GS_K_REDF, st, [&] { return launch_reduceF(v, kOnly2D, active, st); }));
+    HIP_TRY(launch_psd(v, d_theta, active, st));
+    HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins2(v, d_theta, d_mu, active, st); }));
+    if (d_grad) HIP_TRY(launch_vpart(v, active, st));
+  }
+  if (d_grad) {
+    if (v.has_1d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
+    if (v.has_2d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, true, active, st); }));
+    HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_cellgrad(v, d_theta, active, st); }));
+  }
+  HIP_TRY(timed(B, GS_K_FINISH, st,
+                [&] { return launch_finish(v, d_theta, d_nll, d_grad, d_status, active, st); }));
   return GS_OK;
 }
 
@@ -439,6 +516,52 @@ gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll,
   if (!b || !d_theta || !d_nll || !d_status) return fail(GS_ERR_ARG, "null argument");
   HIP_TRY(hipSetDevice(b->device));
   return enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, (hipStream_t)hip_stream);
+}
+
+gs_status gs_batch_set_log_cut(gs_batch *b, double log_cut) {
+  if (!b || std::isnan(log_cut)) return fail(GS_ERR_ARG, "bad argument");
+  b->v.log_cut = log_cut;
+  return GS_OK;
+}
+
+gs_status gs_model_set_log_cut(gs_model *m, double log_cut) {
+  if (!m) return fail(GS_ERR_ARG, "null model");
+  m->cache_valid = false;
+  return gs_batch_set_log_cut(m->b, log_cut);
+}
+
+gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
+  if (!b || !out) return fail(GS_ERR_ARG, "null argument");
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipDeviceSynchronize());
+  long long n_cells = 0;
+  for (const ToyDev &T : b->toys_h) n_cells = std::max(n_cells, T.cell_off + T.n_cell);
+  std::vector<int2> sup((size_t)n_cells);
+  HIP_TRY(hipMemcpy(sup.data(), b->v.sup, sizeof(int2) * (size_t)n_cells, hipMemcpyDeviceToHost));
+  long long fold = 0, adj = 0, full = 0;
+  for (const ToyDev &T : b->toys_h) full += (long long)T.L * T.n_cell;
+  for (const FoldItem &it : b->fold_h) {
+    const ToyDev &T = b->toys_h[it.toy];
+    const int j0 = T.lo + it.bin0, j1 = T.lo + std::min(it.bin0 + kTile, T.L);
+    for (int i = it.cell0; i < it.cell1; i++) {
+      const int2 s = sup[T.cell_off + i];
+      if (!(s.y <= j0 || s.x >= j1)) fold += kTile;
+    }
+  }
+  for (const AdjItem &it : b->adj_h) {
+    const ToyDev &T = b->toys_h[it.toy];
+    int lo = 0x7fffffff, hi = -1;
+    for (int i = it.cell0; i < std::min(it.cell0 + kTile, T.n_cell); i++) {
+      lo = std::min(lo, sup[T.cell_off + i].x);
+      hi = std::max(hi, sup[T.cell_off + i].y);
+    }
+    const int b0 = std::max(it.bin0, lo - T.lo), b1 = std::min(it.bin1, hi - T.lo);
+    if (b1 > b0) adj += (long long)(b1 - b0) * kTile;
+  }
+  out[0] = fold;
+  out[1] = adj;
+  out[2] = full;
+  return GS_OK;
 }
 
 gs_status gs_batch_set_profiling(gs_batch *b, int32_t on) {
@@ -565,6 +688,44 @@ gs_status gs_expected(gs_model *M, const double *theta, double *mu) {
   return GS_OK;
 }
 
+gs_status gs_species_spectra(gs_model *M, const double *theta, double *F) {
+  if (!M || !theta || !F) return fail(GS_ERR_ARG, "null argument");
+  gs_batch *B = M->b;
+  HIP_TRY(hipSetDevice(B->device));
+  gs_status s = upload_theta(M, theta);
+  if (s != GS_OK) return s;
+  const ToyDev &T = B->toys_h[0];
+  const ShapeDev &sh = B->shapes_h[0];
+  HIP_TRY(launch_cells(B->v, M->d_theta, nullptr, M->stream));
+  HIP_TRY(launch_fold(B->v, true, kAllToys, nullptr, M->stream));
+  HIP_TRY(launch_reduceF(B->v, kAllToys, nullptr, M->stream));
+  std::vector<double> f((size_t)T.L * T.S);
+  HIP_TRY(hipMemcpyAsync(f.data(), B->v.F, sizeof(double) * f.size(), hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipStreamSynchronize(M->stream));
+  M->cache_valid = false;
+  for (int b = 0; b < T.L; b++)
+    for (int q = 0; q < T.S; q++) F[(size_t)b * T.S + sh.sp_of[q]] = f[(size_t)b * T.S + q];
+  return GS_OK;
+}
+
+gs_status gs_psd_probs(gs_model *M, const double *theta, double *P) {
+  if (!M || !theta || !P) return fail(GS_ERR_ARG, "null argument");
+  gs_batch *B = M->b;
+  if (!B->v.has_2d) return fail(GS_ERR_ARG, "model has no secondary observable");
+  HIP_TRY(hipSetDevice(B->device));
+  gs_status s = upload_theta(M, theta);
+  if (s != GS_OK) return s;
+  const ToyDev &T = B->toys_h[0];
+  const ShapeDev &sh = B->shapes_h[0];
+  HIP_TRY(launch_psd(B->v, M->d_theta, nullptr, M->stream));
+  std::vector<double> p((size_t)T.S * T.K);
+  HIP_TRY(hipMemcpyAsync(p.data(), B->v.P, sizeof(double) * p.size(), hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipStreamSynchronize(M->stream));
+  for (int q = 0; q < T.S; q++)
+    for (int k = 0; k < T.K; k++) P[(size_t)sh.sp_of[q] * T.K + k] = p[(size_t)q * T.K + k];
+  return GS_OK;
+}
+
 gs_status gs_nll(gs_model *M, const double *theta, double *nll, uint32_t *st) {
   if (!M || !theta || !nll) return fail(GS_ERR_ARG, "null argument");
   gs_batch *B = M->b;
@@ -575,14 +736,24 @@ gs_status gs_nll(gs_model *M, const double *theta, double *nll, uint32_t *st) {
   gs_status s = upload_theta(M, theta);
   if (s != GS_OK) return s;
   const bool refold = !M->cache_valid || std::memcmp(resp.data(), M->cached_resp.data(), nr * 8) != 0;
+  B->v.theta_dev = M->d_theta;
   if (refold) {
-    HIP_TRY(launch_cells(B->v, M->d_theta, nullptr, B->max_cells, M->stream));
-    HIP_TRY(launch_foldS(B->v, M->stream));
-    HIP_TRY(launch_reduceF_grid(B->v, B->max_LS, M->stream));
+    HIP_TRY(timed(B, GS_K_CELLS, M->stream, [&] { return launch_cells(B->v, M->d_theta, nullptr, M->stream); }));
+    HIP_TRY(timed(B, GS_K_FOLDS, M->stream, [&] { return launch_fold(B->v, true, kAllToys, nullptr, M->stream); }));
+    HIP_TRY(timed(B, GS_K_REDF, M->stream, [&] { return launch_reduceF(B->v, kAllToys, nullptr, M->stream); }));
     M->cached_resp = resp;
     M->cache_valid = true;
   }
-  HIP_TRY(launch_nllF(B->v, M->d_theta, M->d_nll, M->d_status, nullptr, M->stream));
+  if (B->v.has_2d) {
+    HIP_TRY(launch_psd(B->v, M->d_theta, nullptr, M->stream));
+    HIP_TRY(timed(B, GS_K_NLLF, M->stream,
+                  [&] { return launch_bins2(B->v, M->d_theta, nullptr, nullptr, M->stream); }));
+  } else {
+    HIP_TRY(timed(B, GS_K_NLLF, M->stream, [&] { return launch_binsF(B->v, M->d_theta, nullptr, M->stream); }));
+  }
+  HIP_TRY(timed(B, GS_K_FINISH, M->stream, [&] {
+    return launch_finish(B->v, M->d_theta, M->d_nll, nullptr, M->d_status, nullptr, M->stream);
+  }));
   HIP_TRY(hipMemcpyAsync(M->h_out, M->d_nll, sizeof(double), hipMemcpyDeviceToHost, M->stream));
   HIP_TRY(hipMemcpyAsync(M->h_status, M->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, M->stream));
   HIP_TRY(hipStreamSynchronize(M->stream));
@@ -594,9 +765,114 @@ gs_status gs_nll(gs_model *M, const double *theta, double *nll, uint32_t *st) {
 gs_status gs_fit(gs_model *M, const double *theta0, const gs_fit_opts *o, double *theta_hat, double *sigma,
                  gs_fit_result *res);
 
-gs_status gs_fit_batched(gs_batch *, const double *, const uint8_t *, const gs_fit_opts *, double *, double *,
-                         double *, int32_t *, uint32_t *, void *) {
-  return fail(GS_ERR_UNSUPPORTED, "gs_fit_batched not built yet");
+static gs_status qn_setup(gs_batch *B) {
+  if (B->qn_ready) return GS_OK;
+  const int n = B->n_toys, P = B->stride;
+  QNView &q = B->q;
+  q.P = P;
+  q.stride = P;
+  HIP_TRY(B->alloc(&q.x, (size_t)n * P));
+  HIP_TRY(B->alloc(&q.xt, (size_t)n * P));
+  HIP_TRY(B->alloc(&q.g, (size_t)n * P));
+  HIP_TRY(B->alloc(&q.d, (size_t)n * P));
+  HIP_TRY(B->alloc(&q.h0, (size_t)n * P));
+  HIP_TRY(B->alloc(&q.H, (size_t)n * P * P));
+  HIP_TRY(B->alloc(&q.f, (size_t)n));
+  HIP_TRY(B->alloc(&q.edm, (size_t)n));
+  HIP_TRY(B->alloc(&q.alpha, (size_t)n));
+  HIP_TRY(B->alloc(&q.slope, (size_t)n));
+  HIP_TRY(B->alloc(&q.phase, (size_t)n));
+  HIP_TRY(B->alloc(&q.iter, (size_t)n));
+  HIP_TRY(B->alloc(&q.nls, (size_t)n));
+  HIP_TRY(B->alloc(&q.n_par, (size_t)n));
+  HIP_TRY(B->alloc(&q.status, (size_t)n));
+  HIP_TRY(B->alloc(&q.active, (size_t)n));
+  HIP_TRY(B->alloc(&q.freep, (size_t)n * P));
+  HIP_TRY(B->alloc(&B->e_nll, (size_t)n));
+  HIP_TRY(B->alloc(&B->e_grad, (size_t)n * P));
+  HIP_TRY(B->alloc(&B->e_st, (size_t)n));
+  HIP_TRY(B->alloc(&B->d_scale, (size_t)P));
+  HIP_TRY(B->alloc(&B->d_count, 1));
+  HIP_TRY(hipHostMalloc((void **)&B->h_count, sizeof(int), hipHostMallocDefault));
+  std::vector<int> np(n);
+  for (int t = 0; t < n; t++) np[t] = B->toys_h[t].P;
+  HIP_TRY(hipMemcpy(q.n_par, np.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  HIP_TRY(hipStreamCreateWithFlags(&B->fit_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+  B->qn_ready = true;
+  return GS_OK;
+}
+
+// Capture K iterations of [evaluate every active toy at its trial point,
+// quasi-Newton step] followed by a count of the active toys.
+static gs_status qn_graph(gs_batch *B, int K, double tol, int max_iter) {
+  if (B->graph && B->graph_k == K && B->graph_tol == tol && B->graph_max_iter == max_iter) return GS_OK;
+  if (B->graph) {
+    HIP_TRY(hipGraphExecDestroy(B->graph));
+    B->graph = nullptr;
+  }
+  const bool prof = B->prof;
+  B->prof = false;  // no timing events inside the graph
+  hipStream_t st = B->fit_stream;
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  gs_status s = GS_OK;
+  for (int k = 0; k < K && s == GS_OK; k++) {
+    s = enqueue_nll_grad(B, B->q.xt, B->e_nll, B->e_grad, B->e_st, nullptr, st, B->q.active);
+    if (s == GS_OK && launch_qn_step(B->q, B->n_toys, B->e_nll, B->e_grad, B->e_st, tol, max_iter, st) != hipSuccess)
+      s = fail(GS_ERR_DEVICE, "launch_qn_step failed during capture");
+  }
+  if (s == GS_OK && launch_qn_count(B->q.active, B->n_toys, B->d_count, st) != hipSuccess)
+    s = fail(GS_ERR_DEVICE, "launch_qn_count failed during capture");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  B->prof = prof;
+  if (s != GS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(GS_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(GS_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  B->graph_k = K;
+  B->graph_tol = tol;
+  B->graph_max_iter = max_iter;
+  return GS_OK;
+}
+
+gs_status gs_fit_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_free, const gs_fit_opts *o,
+                         double *d_theta_hat, double *d_nll_hat, double *d_sigma, int32_t *d_iters,
+                         uint32_t *d_status, void *hip_stream) {
+  if (!B || !d_theta0 || !o || !o->scale || !d_theta_hat || !d_nll_hat || !d_iters || !d_status)
+    return fail(GS_ERR_ARG, "null argument");
+  if (o->max_iter < 1 || !(o->edm_tol > 0)) return fail(GS_ERR_ARG, "max_iter >= 1 and edm_tol > 0 required");
+  for (int p = 0; p < B->stride; p++)
+    if (!(o->scale[p] > 0)) return fail(GS_ERR_ARG, "scale[%d] must be > 0", p);
+  HIP_TRY(hipSetDevice(B->device));
+  gs_status s = qn_setup(B);
+  if (s != GS_OK) return s;
+  hipStream_t caller = (hipStream_t)hip_stream, st = B->fit_stream;
+  HIP_TRY(hipMemcpyAsync(B->d_scale, o->scale, sizeof(double) * B->stride, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(B->ev_in, caller));
+  HIP_TRY(hipStreamWaitEvent(st, B->ev_in, 0));
+  HIP_TRY(launch_qn_init(B->q, B->n_toys, d_theta0, d_free, B->d_scale, st));
+  constexpr int K = 8;
+  s = qn_graph(B, K, o->edm_tol, o->max_iter);
+  if (s != GS_OK) return s;
+  // an iteration is one evaluation; a fit needs max_iter accepted steps plus line-search trials
+  const long long cap = 4LL * o->max_iter + 64;
+  for (long long done = 0; done < cap; done += K) {
+    HIP_TRY(hipGraphLaunch(B->graph, st));
+    HIP_TRY(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*B->h_count == 0) break;
+  }
+  HIP_TRY(launch_qn_final(B->q, B->n_toys, d_theta_hat, d_nll_hat, d_sigma, d_iters, d_status, st));
+  HIP_TRY(hipEventRecord(B->ev_out, st));
+  HIP_TRY(hipStreamWaitEvent(caller, B->ev_out, 0));
+  HIP_TRY(hipStreamSynchronize(caller));
+  return GS_OK;
 }
 
 }  // extern "C"

@@ -7,8 +7,22 @@
 // double-double per-cell and per-bin constants with error-free products,
 // so one FP64 exp per pair keeps the per-bin relative error near 1e-15.
 #pragma once
+#ifdef __HIPCC__
 #include <hip/hip_runtime.h>
+#endif
+#include <math.h>
 #include <stdint.h>
+
+#include "gs_exp.h"
+
+// The error-free transformations below (two_sum, the hi/lo splits of the
+// per-pair exponent) are only exact when every product and sum is rounded
+// on its own; contracting a product into a neighbouring add (allowed by the
+// device compiler's default) silently double-counts the rounding error
+// terms.  Contraction is therefore switched off in this header: the fused
+// operations it needs are written as explicit fma() calls.  The includer's
+// setting is restored at the end of the header.
+#pragma clang fp contract(off)
 
 namespace gs {
 
@@ -25,22 +39,22 @@ struct dd {
   double hi, lo;
 };
 
-__device__ __forceinline__ dd two_sum(double a, double b) {
+GS_HD inline dd two_sum(double a, double b) {
   double s = a + b;
   double bb = s - a;
   double e = (a - (s - bb)) + (b - bb);
   return {s, e};
 }
 
-__device__ __forceinline__ dd two_prod(double a, double b) {
+GS_HD inline dd two_prod(double a, double b) {
   double p = a * b;
-  return {p, __fma_rn(a, b, -p)};
+  return {p, fma(a, b, -p)};
 }
 
 // Natural log of a positive double as hi + lo with |error| ~ 1e-19 relative.
 // x = 2^e f, f in [1/sqrt2, sqrt2); ln f = 2 atanh(s), s = (f - 1)/(f + 1),
 // |s| <= 0.1716, with s carried as a double-double quotient.
-__device__ inline dd dd_log(double x) {
+GS_HD inline dd dd_log(double x) {
   int e;
   double f = frexp(x, &e);  // f in [0.5, 1)
   if (f < 0.70710678118654752440) {
@@ -50,27 +64,27 @@ __device__ inline dd dd_log(double x) {
   double num = f - 1.0;  // exact for f in [0.5, 2]
   dd den = two_sum(f, 1.0);
   double sh = num / den.hi;
-  double rem = __fma_rn(-sh, den.hi, num) - sh * den.lo;
+  double rem = fma(-sh, den.hi, num) - sh * den.lo;
   double sl = rem / den.hi;
   double s2 = sh * sh;
   // atanh(s)/s - 1 = s^2/3 + s^4/5 + ... through s^24/25
   double t = 1.0 / 25;
-  t = __fma_rn(t, s2, 1.0 / 23);
-  t = __fma_rn(t, s2, 1.0 / 21);
-  t = __fma_rn(t, s2, 1.0 / 19);
-  t = __fma_rn(t, s2, 1.0 / 17);
-  t = __fma_rn(t, s2, 1.0 / 15);
-  t = __fma_rn(t, s2, 1.0 / 13);
-  t = __fma_rn(t, s2, 1.0 / 11);
-  t = __fma_rn(t, s2, 1.0 / 9);
-  t = __fma_rn(t, s2, 1.0 / 7);
-  t = __fma_rn(t, s2, 1.0 / 5);
-  t = __fma_rn(t, s2, 1.0 / 3);
+  t = fma(t, s2, 1.0 / 23);
+  t = fma(t, s2, 1.0 / 21);
+  t = fma(t, s2, 1.0 / 19);
+  t = fma(t, s2, 1.0 / 17);
+  t = fma(t, s2, 1.0 / 15);
+  t = fma(t, s2, 1.0 / 13);
+  t = fma(t, s2, 1.0 / 11);
+  t = fma(t, s2, 1.0 / 9);
+  t = fma(t, s2, 1.0 / 7);
+  t = fma(t, s2, 1.0 / 5);
+  t = fma(t, s2, 1.0 / 3);
   t *= s2;
   // 2 atanh(sh + sl) = 2 sh + 2 (sh t + sl (1 + sh^2)) + O(sl^2)
-  double tail = 2.0 * __fma_rn(sh, t, sl * (1.0 + s2));
+  double tail = 2.0 * fma(sh, t, sl * (1.0 + s2));
   dd le = two_prod((double)e, kLn2Hi);
-  le.lo = __fma_rn((double)e, kLn2Lo, le.lo);
+  le.lo = fma((double)e, kLn2Lo, le.lo);
   dd r = two_sum(le.hi, 2.0 * sh);
   double lo = r.lo + le.lo + tail;
   return two_sum(r.hi, lo);
@@ -79,27 +93,27 @@ __device__ inline dd dd_log(double x) {
 // Remainder of Stirling's formula, s(k) = lgamma(k) - (k - 1/2) ln k + k - ln(2 pi)/2.
 // For k >= 12 the asymptotic series sum_n B_2n / (2n (2n-1) k^(2n-1)); below,
 // the exact recurrence s(k) = s(k+1) + (k + 1/2) ln(1 + 1/k) - 1.
-__device__ inline double stirling_rem(double k) {
+GS_HD inline double stirling_rem(double k) {
   double acc = 0.0;
   while (k < 12.0) {
-    acc += __fma_rn(k + 0.5, log1p(1.0 / k), -1.0);
+    acc += fma(k + 0.5, log1p(1.0 / k), -1.0);
     k += 1.0;
   }
   double r = 1.0 / k, r2 = r * r;
   double p = -3617.0 / 122400.0;
-  p = __fma_rn(p, r2, 1.0 / 156.0);
-  p = __fma_rn(p, r2, -691.0 / 360360.0);
-  p = __fma_rn(p, r2, 1.0 / 1188.0);
-  p = __fma_rn(p, r2, -1.0 / 1680.0);
-  p = __fma_rn(p, r2, 1.0 / 1260.0);
-  p = __fma_rn(p, r2, -1.0 / 360.0);
-  p = __fma_rn(p, r2, 1.0 / 12.0);
+  p = fma(p, r2, 1.0 / 156.0);
+  p = fma(p, r2, -691.0 / 360360.0);
+  p = fma(p, r2, 1.0 / 1188.0);
+  p = fma(p, r2, -1.0 / 1680.0);
+  p = fma(p, r2, 1.0 / 1260.0);
+  p = fma(p, r2, -1.0 / 360.0);
+  p = fma(p, r2, 1.0 / 12.0);
   return acc + p * r;
 }
 
 // ln k - psi(k): asymptotic series for k >= 8 (no cancellation), else shifted
 // up with psi(k) = psi(k + n) - sum_{j<n} 1/(k + j).
-__device__ inline double log_minus_digamma(double k) {
+GS_HD inline double log_minus_digamma(double k) {
   double acc = 0.0, k0 = k;
   while (k < 8.0) {
     acc += 1.0 / k;
@@ -109,20 +123,20 @@ __device__ inline double log_minus_digamma(double k) {
   // ln k - psi(k) = 1/(2k) + 1/(12k^2) - 1/(120k^4) + 1/(252k^6) - 1/(240k^8) + 1/(132k^10)
   //                 - 691/(32760k^12) + 1/(12k^14)
   double p = 1.0 / 12.0;
-  p = __fma_rn(p, r2, -691.0 / 32760.0);
-  p = __fma_rn(p, r2, 1.0 / 132.0);
-  p = __fma_rn(p, r2, -1.0 / 240.0);
-  p = __fma_rn(p, r2, 1.0 / 252.0);
-  p = __fma_rn(p, r2, -1.0 / 120.0);
-  p = __fma_rn(p, r2, 1.0 / 12.0);
-  double v = __fma_rn(p, r2, 0.5 * r);
+  p = fma(p, r2, -691.0 / 32760.0);
+  p = fma(p, r2, 1.0 / 132.0);
+  p = fma(p, r2, -1.0 / 240.0);
+  p = fma(p, r2, 1.0 / 252.0);
+  p = fma(p, r2, -1.0 / 120.0);
+  p = fma(p, r2, 1.0 / 12.0);
+  double v = fma(p, r2, 0.5 * r);
   if (k != k0) v += acc - log(k / k0);  // ln k0 - psi(k0) = [ln k - psi(k)] - ln(k/k0) + sum 1/(k0+j)
   return v;
 }
 
 // Birks quenching factor Q(E) = 1 - 2/y + 2 ln(1+y)/y^2, y = sqrt(E)/(kB A),
 // and dQ/dkB.  Below y = 0.05 the series 2 sum (-1)^(n+1) y^n/(n+2).
-__device__ inline double quench(double E, double kB, double A, double *dQ_dkB) {
+GS_HD inline double quench(double E, double kB, double A, double *dQ_dkB) {
   if (!(E > 0.0)) {
     *dQ_dkB = 0.0;
     return 0.0;
@@ -135,9 +149,9 @@ __device__ inline double quench(double E, double kB, double A, double *dQ_dkB) {
     double yn = 1.0;
     for (int n = 1; n <= 14; n++) {
       double c = ((n & 1) ? 2.0 : -2.0) / (n + 2);
-      dQdy = __fma_rn(c * n, yn, dQdy);
+      dQdy = fma(c * n, yn, dQdy);
       yn *= y;
-      Q = __fma_rn(c, yn, Q);
+      Q = fma(c, yn, Q);
     }
   } else {
     double iy = 1.0 / y;
@@ -156,12 +170,12 @@ struct Moments {
   double dm[5], ds[5];
 };
 
-__device__ inline bool moments(int fam, const double *resp, double A, double E, Moments &o) {
+GS_HD inline bool moments(int fam, const double *resp, double A, double E, Moments &o) {
 #pragma unroll
   for (int p = 0; p < 5; p++) o.dm[p] = o.ds[p] = 0.0;
   if (fam == kGaussE) {
     double a = resp[0], b = resp[1];
-    double s2 = __fma_rn(b, E, a * a);
+    double s2 = fma(b, E, a * a);
     o.m = E;
     o.s = sqrt(s2);
     o.ds[0] = a / o.s;
@@ -194,27 +208,27 @@ __device__ inline bool moments(int fam, const double *resp, double A, double E, 
 }
 
 // Per-cell record (8 doubles), consumed by the fold and adjoint loops.
-//  gamma:    {k - 1, 1/th hi, 1/th lo, C hi, C lo, W, ln(k th) hi, k th}
+//  gamma:    {k - 1, 1/th hi, 1/th lo, C hi, C lo, W, support, 0}
 //            C = -lgamma(k) - k ln th, in double-double
-//  gaussian: {m, 1/s, -ln s - ln(2 pi)/2, W, 0, 0, 0, 0}
-// W = sum_s R_s w_si (1-D combined weight); NaN marks an invalid response.
-__device__ inline void cell_record(int fam, double m, double s, double W, bool ok, double *rec) {
-  if (!ok) {
-    for (int q = 0; q < kRecLen; q++) rec[q] = __builtin_nan("");
-    return;
-  }
+//  gaussian: {m, 1/s, -ln s - ln(2 pi)/2, W, 0, 0, support, 0}
+// W = sum_s R_s w_si (1-D combined weight).  Slot 6 holds the cell's bin
+// support as two int32 (written by the caller).  Invalid responses are
+// flagged by the caller; their records are zeros.
+GS_HD inline void cell_record(int fam, double m, double s, double W, bool ok, double *rec) {
+  for (int q = 0; q < kRecLen; q++) rec[q] = 0.0;
+  if (!ok) return;
   if (fam == kGammaPE) {
     double s2 = s * s;
     double k = m * m / s2;
     double th = s2 / m;
     double bh = 1.0 / th;
-    double bl = __fma_rn(-bh, th, 1.0) * bh;
+    double bl = fma(-bh, th, 1.0) * bh;
     dd mk = two_prod(k, th);             // k th = mean, exactly as hi + lo
     dd lm = dd_log(mk.hi);
     lm.lo += mk.lo / mk.hi;
     // C = -k ln(k th) + k + ln(k)/2 - ln(2 pi)/2 - s(k)
     dd p = two_prod(k, lm.hi);
-    p.lo = __fma_rn(k, lm.lo, p.lo);
+    p.lo = fma(k, lm.lo, p.lo);
     dd c1 = two_sum(-p.hi, k);
     double small = 0.5 * log(k) - kHalfLn2Pi - stirling_rem(k) - p.lo;
     dd C = two_sum(c1.hi, c1.lo + small);
@@ -224,33 +238,32 @@ __device__ inline void cell_record(int fam, double m, double s, double W, bool o
     rec[3] = C.hi;
     rec[4] = C.lo;
     rec[5] = W;
-    rec[6] = lm.hi;
-    rec[7] = mk.hi;
   } else {
     rec[0] = m;
     rec[1] = 1.0 / s;
     rec[2] = -log(s) - kHalfLn2Pi;
     rec[3] = W;
-    rec[4] = rec[5] = rec[6] = rec[7] = 0.0;
   }
 }
 
 // Per-pair log-density: gamma uses the bin's x and ln x as double-double.
-__device__ __forceinline__ double gamma_exponent(double K, double Bh, double Bl, double Ch, double Cl,
+GS_HD inline double gamma_exponent(double K, double Bh, double Bl, double Ch, double Cl,
                                                  double x, double Lh, double Ll) {
   double p = K * Lh;
-  double ep = __fma_rn(K, Lh, -p);
+  double ep = fma(K, Lh, -p);
   double q = x * Bh;
-  double eq = __fma_rn(x, Bh, -q);
+  double eq = fma(x, Bh, -q);
   double t = (p + Ch) - q;
-  double corr = __fma_rn(K, Ll, ep) - eq;
-  corr = __fma_rn(-x, Bl, corr) + Cl;
+  double corr = fma(K, Ll, ep) - eq;
+  corr = fma(-x, Bl, corr) + Cl;
   return t + corr;
 }
 
-__device__ __forceinline__ double gauss_exponent(double m, double is, double c0, double x, double &z) {
+GS_HD inline double gauss_exponent(double m, double is, double c0, double x, double &z) {
   z = (x - m) * is;
-  return __fma_rn(-0.5 * z, z, c0);
+  return fma(-0.5 * z, z, c0);
 }
 
 }  // namespace gs
+
+#pragma clang fp contract(fast)

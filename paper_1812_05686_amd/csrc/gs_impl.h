@@ -8,6 +8,12 @@
 
 namespace gs {
 
+constexpr int kTile = 64;       // bins (fold) or cells (adjoint) per tile: one per lane
+constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
+constexpr int kBlock = 256;     // threads per reduction block
+constexpr int kGradLen = GS_MAX_PARAMS;
+constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response flag each)
+
 // Structure shared by every toy of one shape (spectra, grid, binning).
 // Species are stored in internal order: grid species first, then lines;
 // sp_of maps an internal species to its index in theta.
@@ -25,21 +31,30 @@ struct ShapeDev {
 // One toy (fit problem) of a batch; offsets index the batch-wide buffers.
 struct ToyDev {
   int shape, D, lo, L, P, K, n_cell, S;
+  int two_d;                    // 1: pulse-shape (secondary observable) model
   int fold_chunks, adj_chunks;
-  long long cell_off;   // cell records: rec[(cell_off + i) * kRecLen]
-  long long win_off;    // window bins: binrec[(win_off + b) * kBinLen], F[(win_off + b) * S]
+  int bin_blocks, cell_blocks;  // reduction blocks over window bins / cells (kBlock each)
+  int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
+  long long cell_off;   // rec[(cell_off + i) * kRecLen]
+  long long win_off;    // binrec[(win_off + b) * kBinLen], F[(win_off + b) * S]
   long long cnt_off;    // counts of the window: cnt[cnt_off + (d * L + b) * K + k]
-  long long fpart_off;  // fold partials
+  long long fpart_off;  // fold partials: fpart[fpart_off + chunk * L + b]
+  long long fs_off;     // per-species fold partials: fspart[fs_off + (chunk * L + b) * S + s]
   long long apart_off;  // adjoint partials: apart[apart_off + (chunk * n_cell + i) * 3 + q]
+  long long nllp_off;   // -ln L partials per bin block
+  long long gpart_off;  // per cell block: gpart[(gpart_off + blk) * kGradLen + p]
+  long long cflag_off;  // per k_cells block: cflag[cflag_off + blk]
   long long pull_off;   // pull centres / widths [P]
+  long long gam_off;    // 2-D: Gam[gam_off + b * K + k] = sum_d eps_d (1 - n/mu)
+  long long psd_off;    // 2-D: P[psd_off + s * K + k], dP[(psd_off + s * K + k) * 3 + v]
   double exposure[GS_MAX_DATASETS];
 };
 
-// One wavefront of the fold: 64 window bins of one toy against a cell range.
+// One workgroup of the fold: 64 window bins of one toy against a cell range.
 struct FoldItem {
   int toy, bin0, cell0, cell1, chunk;
 };
-// One wavefront of the adjoint: 64 cells of one toy against a window-bin range.
+// One workgroup of the adjoint: 64 cells of one toy against a window-bin range.
 struct AdjItem {
   int toy, cell0, bin0, bin1, chunk;
 };
@@ -47,36 +62,55 @@ struct AdjItem {
 // Device views of one batch, passed by value to the launchers.
 struct BatchView {
   int n_toys, stride;
+  int max_cells, max_cell_blocks, max_bin_blocks;
+  double log_cut;   // pairs whose log-density is below this are skipped
   const ToyDev *toys;
   const ShapeDev *shapes;
   double *rec;      // cell records
+  uint32_t *cflag;  // per k_cells block: an invalid response was met
+  int2 *sup;        // per cell: reco-bin support [x, y) (also in slot 6 of the record)
+  int max_cflag_blocks;
   double *fpart;    // fold partials (combined weight)
+  double *fspart;   // fold partials per species
+  double *F;        // per-species spectra of the window, bin width included
   double *apart;    // adjoint partials
-  double *binrec;   // per toy window bins: xbar, ln xbar hi, lo, G
+  double *binrec;   // window bins: xbar, ln xbar hi, lo, G
+  double *nllp;     // -ln L partials
+  double *gpart;    // gradient partials
+  uint32_t *badp;   // domain flags per bin block
   const double *cnt;
   const double *pull_c, *pull_s;
   const FoldItem *fold_items;
   int n_fold_items;
   const AdjItem *adj_items;
   int n_adj_items;
-  // per-species fold (plain path and 2-D)
-  double *fspart;   // [toy][chunk][L][S]
-  double *F;        // [toy][L][S], includes the bin width
-  long long *fs_off;  // per toy offset into fspart
+  // secondary observable (2-D) models
+  double *H;        // [win bins][S]: dx_j sum_k P_sk Gam_jk
+  double *Gam;      // [win bins][K]
+  double *P, *dP;   // pulse-shape probabilities and their nuisance derivatives
+  double *vpart;    // [toy][GS_MAX_SPECIES][4]: sum_k P V, sum_k dP_v V for v = 0..2
+  uint32_t *pflag;  // [toy]: invalid pulse-shape nuisance
+  const double *theta_dev;  // parameters of the evaluation in flight (per-species adjoint)
+  bool has_1d, has_2d;
 };
 
-// Launchers (gs_kernels.hip).  All enqueue on `st` and return hipSuccess or the launch error.
-hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, int max_cells, hipStream_t st);
-hipError_t launch_fold1(const BatchView &v, hipStream_t st);
-hipError_t launch_nll1(const BatchView &v, const double *theta, double *nll, uint32_t *status, double *mu_out,
-                       const uint8_t *active, hipStream_t st);
-hipError_t launch_adj1(const BatchView &v, hipStream_t st);
-hipError_t launch_grad1(const BatchView &v, const double *theta, const uint32_t *status, double *grad,
-                        const uint8_t *active, hipStream_t st);
-hipError_t launch_bins_setup(const ShapeDev *shape_d, double *bins, const double *edges, int n_reco, hipStream_t st);
-hipError_t launch_foldS(const BatchView &v, hipStream_t st);
-hipError_t launch_reduceF_grid(const BatchView &v, int max_LS, hipStream_t st);
-hipError_t launch_nllF(const BatchView &v, const double *theta, double *nll, uint32_t *status, double *mu_out,
-                       hipStream_t st);
+// Which toys a launch covers.
+enum ModeFilter : int { kAllToys = -1, kOnly1D = 0, kOnly2D = 1 };
+
+// Launchers (gs_kernels.hip).  All enqueue on `st` and return the launch status.
+hipError_t launch_bins_setup(double *bins, const double *edges, int n_reco, hipStream_t st);
+hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st);
+hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st);
+hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *active, hipStream_t st);
+hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *active, hipStream_t st);
+hipError_t launch_cellgrad(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st);
+hipError_t launch_finish(const BatchView &v, const double *theta, double *nll, double *grad, uint32_t *status,
+                         const uint8_t *active, hipStream_t st);
+hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st);
+hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out, hipStream_t st);
+hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st);
+hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
+                        hipStream_t st);
+hipError_t launch_vpart(const BatchView &v, const uint8_t *active, hipStream_t st);
 
 }  // namespace gs

@@ -2,24 +2,46 @@
 //
 // One evaluation (section 2.5: the response on the visible x true mesh is
 // evaluated and smeared against the true spectrum; Eq.2 cost ~ N_vis N_true):
-//   k_cells  per (toy, cell): response moments and the per-cell record
-//   k_fold1  per wave: 64 window bins (one per lane) x a cell range; the cell
-//            records are wave-uniform and come through scalar loads, so the
-//            VALU only does the per-pair exponent, one exp and one FMA
-//   k_nll1   per toy: split-K partial sums in fixed order, Poisson terms of
-//            Eq.4, adjoint seeds G_j = dx_j sum_d eps_d (1 - n_dj/mu_dj)
-//   k_adj1   per wave: 64 cells (one per lane) x a window-bin range; bins are
-//            wave-uniform; per-cell sums of G r {1, t1, t2}
-//   k_grad1  per toy: chain rule from per-cell sums to d(-ln L)/d theta
+//   k_cells     per (toy, cell): response moments, the per-cell record and the
+//               cell's support: the reco bins whose midpoint log-density
+//               exceeds log_cut (pairs outside it are skipped)
+//   k_fold      per workgroup: 64 window bins (one per lane) x a cell range,
+//               the 4 waves interleaving the cells; cell records and supports
+//               are wave-uniform (scalar loads, scalar skip test), so the VALU
+//               only does the per-pair exponent, one exp and the FMAs
+//   k_bins1     per (toy, 256 window bins): split-K partials in fixed order,
+//               Poisson terms of Eq.4, adjoint seeds G_j = dx_j sum_d eps_d
+//               (1 - n_dj/mu_dj), block partial of -ln L
+//   k_adj       per workgroup: 64 cells (one per lane) x the window bins inside
+//               the union of their supports, the 4 waves interleaving the bins;
+//               per-cell sums of G r {1, t1, t2}
+//   k_cellgrad  per (toy, 256 cells): chain rule from per-cell sums to
+//               d(-ln L)/d theta, block partials
+//   k_finish    per toy: -ln L and gradient from the block partials, pulls,
+//               status bits
 // No floating-point atomics: every reduction has a fixed order, so results
 // are bitwise reproducible for a fixed launch configuration.
+#include <math.h>
+
 #include "gs_impl.h"
 
 namespace gs {
 
+// Coefficients of exp_cw; read through scalar loads so they live in SGPRs.
+__constant__ double kExpC[16] = GS_EXP_COEFS;
+
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Deterministic block sum of one double per thread (blockDim.x = 256).
+// Workgroups are dispatched round-robin over the 8 XCDs; map block b to an
+// item so that each XCD works through a contiguous, toy-major range of items
+// and the cell records of one toy stay in one XCD's L2.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int per = (n + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+inline int xcd_grid(int n) { return ((n + 7) >> 3) * 8; }
+
+// Deterministic sum over a block of kBlock threads; result valid on thread 0.
 __device__ double block_sum(double v, double *lds) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -29,107 +51,315 @@ __device__ double block_sum(double v, double *lds) {
   double r = 0.0;
   if (threadIdx.x == 0)
     for (int i = 0; i < (int)(blockDim.x >> 6); i++) r += lds[i];
-  return r;  // valid on thread 0
+  return r;
 }
 
-// ------------------------------------------------------------ k_cells -----
-__global__ __launch_bounds__(256) void k_cells(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                               const double *__restrict__ theta, int stride,
-                                               const uint8_t *__restrict__ active, double *__restrict__ rec) {
+// ------------------------------------------------------------- supports ---
+__device__ int first_bin_at_or_above(const double *bins, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (bins[(size_t)mid * kBinLen] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ int first_bin_above(const double *bins, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (bins[(size_t)mid * kBinLen] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Interval [xl, xr] outside of which the gamma log-density
+// (k-1) ln x - x/th + C is below T.  The log-density is concave for k > 1
+// (increasing below the mode, decreasing above) and decreasing for k <= 1;
+// Newton's method from the far side of each root then approaches it
+// monotonically without crossing (the tangent of a concave function lies
+// above it), so every iterate is a valid conservative end point.
+__device__ bool gamma_support(double k, double th, double C, double T, double &xl, double &xr) {
+  auto E = [&](double x) { return (k - 1.0) * log(x) - x / th + C; };
+  auto dE = [&](double x) { return (k - 1.0) / x - 1.0 / th; };
+  const double sd = sqrt(k) * th;
+  double xm = 0.0, w = sd;
+  if (k > 1.0) {
+    xm = (k - 1.0) * th;
+    const double Em = E(xm);
+    if (!(Em > T)) return false;
+    w = sd * sqrt(2.0 * (Em - T)) + sd;
+  }
+  // iterate until a step is below tol: the end points only need bin-scale precision
+  const double tol = 1e-3 * sd;
+  double x = xm + w;
+  for (int i = 0; i < 80 && E(x) > T; i++) x = xm + 2.0 * (x - xm);
+  for (int i = 0; i < 30; i++) {
+    const double nx = x - (E(x) - T) / dE(x);
+    if (!(nx < x)) break;
+    const bool done = x - nx < tol;
+    x = nx;
+    if (done) break;
+  }
+  xr = x;
+  xl = -INFINITY;
+  if (k > 1.0) {
+    x = xm - w;
+    if (!(x > 0.0)) x = 0.5 * xm;
+    for (int i = 0; i < 64 && E(x) > T; i++) x *= 0.5;
+    if (E(x) <= T) {
+      for (int q = 0; q < 30; q++) {
+        const double nx = x - (E(x) - T) / dE(x);
+        if (!(nx > x) || !(nx < xm)) break;
+        const bool done = nx - x < tol;
+        x = nx;
+        if (done) break;
+      }
+      xl = x;
+    }
+  }
+  return true;
+}
+
+// Reco bins [x, y) whose midpoint log-density can exceed T for this cell.
+__device__ int2 cell_support(int fam, const double *rc, double m, double s, bool ok, const double *bins, int n_reco,
+                             double T) {
+  if (!ok) return make_int2(0, 0);
+  if (!(T > -INFINITY)) return make_int2(0, n_reco);
+  double xl, xr;
+  if (fam == kGammaPE) {
+    const double s2 = s * s;
+    if (!gamma_support(m * m / s2, s2 / m, rc[3] + rc[4], T, xl, xr)) return make_int2(0, 0);
+  } else {
+    const double c0 = rc[2];
+    if (!(c0 > T)) return make_int2(0, 0);
+    const double h = s * sqrt(2.0 * (c0 - T));
+    xl = m - h;
+    xr = m + h;
+  }
+  return make_int2(first_bin_at_or_above(bins, n_reco, xl), first_bin_above(bins, n_reco, xr));
+}
+
+// ------------------------------------------------------------- k_cells ----
+__device__ __forceinline__ void put_support(double *rc, int2 s) { *(int2 *)(rc + 6) = s; }
+__device__ __forceinline__ int2 get_support(const double *rc) { return *(const int2 *)(rc + 6); }
+
+__global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ theta, int stride, double log_cut,
+                                               const uint8_t *__restrict__ active, double *__restrict__ rec,
+                                               int2 *__restrict__ sup, uint32_t *__restrict__ cflag) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
+  if ((int)blockIdx.x >= T.cflag_blocks) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Sh.n_cell) return;
-  const double *th = theta + (size_t)t * stride;
-  Moments mo;
-  bool ok = moments(Sh.family, th + Sh.S, Sh.birks_A, Sh.cellE[i], mo);
-  double W = 0.0;
-  if (i < Sh.n_true) {
-    const double *w = Sh.wcell + (size_t)i * Sh.Sg;
-    for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[s], W);
-  } else {
-    W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
+  bool ok = true;
+  if (i < Sh.n_cell) {
+    const double *th = theta + (size_t)t * stride;
+    Moments mo;
+    ok = moments(Sh.family, th + Sh.S, Sh.birks_A, Sh.cellE[i], mo);
+    double W = 0.0;
+    if (i < Sh.n_true) {
+      const double *w = Sh.wcell + (size_t)i * Sh.Sg;
+      for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[s], W);
+    } else {
+      W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
+    }
+    ok = ok && isfinite(W);
+    double r[kRecLen];
+    cell_record(Sh.family, mo.m, mo.s, W, ok, r);
+    const int2 sp = ok ? cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, log_cut) : make_int2(0, 0);
+    put_support(r, sp);
+    double *rc = rec + (T.cell_off + i) * kRecLen;
+#pragma unroll
+    for (int q = 0; q < kRecLen; q++) rc[q] = r[q];
+    sup[T.cell_off + i] = sp;
   }
-  cell_record(Sh.family, mo.m, mo.s, W, ok, rec + (T.cell_off + i) * kRecLen);
+  const int bad = __syncthreads_or(!ok);
+  if (threadIdx.x == 0) cflag[T.cflag_off + blockIdx.x] = bad ? 1u : 0u;
 }
 
-hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, int max_cells, hipStream_t st) {
-  dim3 grid((max_cells + 255) / 256, v.n_toys);
-  hipLaunchKernelGGL(k_cells, grid, dim3(256), 0, st, v.toys, v.shapes, theta, v.stride, active, v.rec);
+hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
+  dim3 grid(v.max_cflag_blocks, v.n_toys);
+  hipLaunchKernelGGL(k_cells, grid, dim3(kCellBlock), 0, st, v.toys, v.shapes, theta, v.stride, v.log_cut, active,
+                     v.rec, v.sup, v.cflag);
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ k_fold1 -----
+// -------------------------------------------------------------- k_fold ----
+// Response of cell record p at the lane's bin.
 template <int FAM>
-__device__ __forceinline__ double fold_range(const double *__restrict__ R, int c0, int c1, double x, double Lh,
-                                             double Ll) {
-  double a0 = 0.0, a1 = 0.0;
-  int i = c0;
-  for (; i + 1 < c1; i += 2) {
-    const double *p = R + (size_t)i * kRecLen;
-    const double *q = p + kRecLen;
-    if (FAM == kGammaPE) {
-      double e0 = gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll);
-      double e1 = gamma_exponent(q[0], q[1], q[2], q[3], q[4], x, Lh, Ll);
-      a0 = __fma_rn(p[5], exp(e0), a0);
-      a1 = __fma_rn(q[5], exp(e1), a1);
-    } else {
-      double z0, z1;
-      double e0 = gauss_exponent(p[0], p[1], p[2], x, z0);
-      double e1 = gauss_exponent(q[0], q[1], q[2], x, z1);
-      a0 = __fma_rn(p[3], exp(e0), a0);
-      a1 = __fma_rn(q[3], exp(e1), a1);
-    }
-  }
-  if (i < c1) {
-    const double *p = R + (size_t)i * kRecLen;
-    if (FAM == kGammaPE) {
-      a0 = __fma_rn(p[5], exp(gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll)), a0);
-    } else {
-      double z;
-      a0 = __fma_rn(p[3], exp(gauss_exponent(p[0], p[1], p[2], x, z)), a0);
-    }
-  }
-  return a0 + a1;
+__device__ __forceinline__ double pair_density(const double *__restrict__ p, double x, double Lh, double Ll,
+                                               const double *ec) {
+  if (FAM == kGammaPE) return exp_cw(gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll), ec);
+  double z;
+  return exp_cw(gauss_exponent(p[0], p[1], p[2], x, z), ec);
 }
 
-__global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ items, int n_items,
-                                               const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                               const double *__restrict__ rec, const uint8_t *__restrict__ active,
-                                               double *__restrict__ fpart) {
-  const int w = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (w >= n_items) return;
-  const int lane = threadIdx.x & 63;
-  const FoldItem it = items[w];
+// One-dimensional fold with the combined weight W_i = sum_s R_s w_si.  The
+// next cell's record is fetched (scalar loads) while the current one is
+// evaluated.
+struct Rec8 {
+  double v[kRecLen];
+};
+__device__ __forceinline__ Rec8 load_rec(const double *__restrict__ p) {
+  Rec8 r;
+#pragma unroll
+  for (int q = 0; q < kRecLen; q++) r.v[q] = p[q];
+  return r;
+}
+
+template <int FAM>
+__device__ __forceinline__ double fold_cells_1(const double *__restrict__ R, int c0, int c1, int j0, int j1, double x,
+                                               double Lh, double Ll, const double *ec) {
+  double acc = 0.0;
+  if (c0 >= c1) return acc;
+  Rec8 cur = load_rec(R + (size_t)c0 * kRecLen);
+  for (int i = c0; i < c1; i += kWaves) {
+    const Rec8 nxt = load_rec(R + (size_t)min(i + kWaves, c1 - 1) * kRecLen);
+    const int2 s = get_support(cur.v);
+    if (!(s.y <= j0 || s.x >= j1))  // wave-uniform: the cell reaches this tile
+      acc = __fma_rn(FAM == kGammaPE ? cur.v[5] : cur.v[3], pair_density<FAM>(cur.v, x, Lh, Ll, ec), acc);
+    cur = nxt;
+  }
+  return acc;
+}
+
+// Per-species fold: grid cells add w_si r into species s < Sg, line cells into their own.
+template <int FAM>
+__device__ __forceinline__ void fold_cells_s(const double *__restrict__ R, const double *__restrict__ wc, int Sg,
+                                             int n_true, int c0, int c1, int j0, int j1, double x, double Lh,
+                                             double Ll, const double *ec, double (&acc)[GS_MAX_SPECIES]) {
+  for (int i = c0; i < c1; i += kWaves) {
+    const double *p = R + (size_t)i * kRecLen;
+    const int2 s = get_support(p);
+    if (s.y <= j0 || s.x >= j1) continue;
+    const double r = pair_density<FAM>(p, x, Lh, Ll, ec);
+    if (i < n_true) {
+      const double *w = wc + (size_t)i * Sg;
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++)
+        if (q < Sg) acc[q] = __fma_rn(w[q], r, acc[q]);
+    } else {
+      const int ql = Sg + (i - n_true);
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++)
+        if (q == ql) acc[q] += r;
+    }
+  }
+}
+
+template <bool PS>
+__global__ __launch_bounds__(256) void k_fold(const FoldItem *__restrict__ items, int n_items,
+                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                              const double *__restrict__ rec, const int2 *__restrict__ sup, int mode,
+                                              const uint8_t *__restrict__ active, double *__restrict__ out) {
+  __shared__ double red[PS ? kWaves * kTile * GS_MAX_SPECIES : kWaves * kTile];
+  __shared__ int rng[2 * kWaves];
+  const double *ec = kExpC;
+  const int w_item = xcd_item(blockIdx.x, n_items);
+  if (w_item >= n_items) return;
+  const FoldItem it = items[w_item];
   if (active && !active[it.toy]) return;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const ToyDev &T = toys[it.toy];
+  if (mode >= 0 && T.two_d != mode) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int b = it.bin0 + lane;
   const bool valid = b < T.L;
   const int j = T.lo + (valid ? b : T.L - 1);
   const double *bn = Sh.bins + (size_t)j * kBinLen;
   const double x = bn[0], Lh = bn[2], Ll = bn[3];
+  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kTile, T.L);
   const double *R = rec + T.cell_off * kRecLen;
-  double acc;
-  if (Sh.family == kGammaPE) {
-    acc = fold_range<kGammaPE>(R, it.cell0, it.cell1, x, Lh, Ll);
-    if (!(x > 0.0)) acc = 0.0;
-  } else {
-    acc = fold_range<kGaussE>(R, it.cell0, it.cell1, x, Lh, Ll);
+  const bool gamma = Sh.family == kGammaPE;
+  const bool zero = gamma && !(x > 0.0);  // outside the gamma support
+  // first and last grid cell of the chunk whose support reaches this bin tile;
+  // line cells (after the grid) are walked separately below
+  const int g_end = min(it.cell1, Sh.n_true), l_begin = max(it.cell0, Sh.n_true);
+  int first = 0x7fffffff, last = -1;
+  for (int i = it.cell0 + (int)threadIdx.x; i < g_end; i += kWaves * 64) {
+    const int2 s = sup[T.cell_off + i];
+    if (!(s.y <= j0 || s.x >= j1)) {
+      first = min(first, i);
+      last = max(last, i);
+    }
   }
-  if (valid) fpart[T.fpart_off + (long long)it.chunk * T.L + b] = acc;
+  for (int o = 32; o > 0; o >>= 1) {
+    first = min(first, __shfl_xor(first, o, 64));
+    last = max(last, __shfl_xor(last, o, 64));
+  }
+  if (lane == 0) {
+    rng[wave] = first;
+    rng[kWaves + wave] = last;
+  }
+  __syncthreads();
+  first = min(min(rng[0], rng[1]), min(rng[2], rng[3]));
+  last = max(max(rng[kWaves], rng[kWaves + 1]), max(rng[kWaves + 2], rng[kWaves + 3]));
+  // no cell of the chunk reaches the tile: empty range (never first + wave past INT_MAX)
+  const bool any = last >= 0;
+  first = any ? wave_uniform(first) : 0;
+  const int c_end = any ? wave_uniform(last) + 1 : 0;
+  if (!PS) {
+    double acc;
+    if (gamma)
+      acc = fold_cells_1<kGammaPE>(R, first + wave, c_end, j0, j1, x, Lh, Ll, ec) +
+            fold_cells_1<kGammaPE>(R, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec);
+    else
+      acc = fold_cells_1<kGaussE>(R, first + wave, c_end, j0, j1, x, Lh, Ll, ec) +
+            fold_cells_1<kGaussE>(R, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec);
+    red[wave * kTile + lane] = zero ? 0.0 : acc;
+    __syncthreads();
+    if (wave == 0 && valid) {
+      double s = red[lane];
+      for (int q = 1; q < kWaves; q++) s += red[q * kTile + lane];
+      out[T.fpart_off + (long long)it.chunk * T.L + b] = s;
+    }
+  } else {
+    double acc[GS_MAX_SPECIES];
+#pragma unroll
+    for (int q = 0; q < GS_MAX_SPECIES; q++) acc[q] = 0.0;
+    if (gamma) {
+      fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
+      fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
+    } else {
+      fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
+      fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < GS_MAX_SPECIES; q++) red[(wave * GS_MAX_SPECIES + q) * kTile + lane] = zero ? 0.0 : acc[q];
+    __syncthreads();
+    if (wave == 0 && valid) {
+      double *o = out + T.fs_off + ((long long)it.chunk * T.L + b) * T.S;
+      for (int q = 0; q < T.S; q++) {
+        double s = red[q * kTile + lane];
+        for (int ww = 1; ww < kWaves; ww++) s += red[(ww * GS_MAX_SPECIES + q) * kTile + lane];
+        o[q] = s;
+      }
+    }
+  }
 }
 
-hipError_t launch_fold1(const BatchView &v, hipStream_t st) {
+hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st) {
   if (v.n_fold_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold1, dim3((v.n_fold_items + 3) / 4), dim3(256), 0, st, v.fold_items, v.n_fold_items,
-                     v.toys, v.shapes, v.rec, (const uint8_t *)nullptr, v.fpart);
+  const dim3 grid(xcd_grid(v.n_fold_items));
+  if (per_species)
+    hipLaunchKernelGGL(k_fold<true>, grid, dim3(kWaves * 64), 0, st, v.fold_items, v.n_fold_items, v.toys, v.shapes,
+                       v.rec, v.sup, mode, active, v.fspart);
+  else
+    hipLaunchKernelGGL(k_fold<false>, grid, dim3(kWaves * 64), 0, st, v.fold_items, v.n_fold_items, v.toys, v.shapes,
+                       v.rec, v.sup, mode, active, v.fpart);
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ k_nll1 ------
+// ------------------------------------------------------------- k_bins1 ----
 // Poisson term of Eq.4 (ln n! dropped).  Returns false on a domain error.
 __device__ __forceinline__ bool poisson_term(double mu, double n, double &term, double &g) {
   if (mu > 0.0) {
@@ -142,53 +372,38 @@ __device__ __forceinline__ bool poisson_term(double mu, double n, double &term, 
   return mu == 0.0 && n == 0.0;
 }
 
-// Pulls, parameter finiteness, final status and -ln L of toy t (thread 0).
-__device__ void finish_nll(const ToyDev &T, const double *th, const double *pull_c, const double *pull_s,
-                           double sum, bool bad, double *nll, uint32_t *status, int t) {
-  uint32_t st = 0;
-  for (int p = 0; p < T.P; p++)
-    if (!isfinite(th[p])) st |= GS_ST_NONFINITE;
-  if (bad) st |= GS_ST_DOMAIN;
-  for (int p = 0; p < T.P; p++) {
-    double s = pull_s[T.pull_off + p];
-    if (s > 0.0) {
-      double z = (th[p] - pull_c[T.pull_off + p]) / s;
-      sum = __fma_rn(0.5 * z, z, sum);
-    }
-  }
-  if (st & GS_ST_NONFINITE)
-    sum = __builtin_nan("");
-  else if (st & GS_ST_DOMAIN)
-    sum = __builtin_inf();
-  nll[t] = sum;
-  status[t] = st;
-}
-
-__global__ __launch_bounds__(256) void k_nll1(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                              const double *__restrict__ theta, int stride,
-                                              const double *__restrict__ fpart, const double *__restrict__ cnt,
-                                              const double *__restrict__ pull_c, const double *__restrict__ pull_s,
-                                              const uint8_t *__restrict__ active, double *__restrict__ binrec,
-                                              double *__restrict__ nll, uint32_t *__restrict__ status,
-                                              double *__restrict__ mu_out) {
+__global__ __launch_bounds__(256) void k_bins1(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ fpart, const double *__restrict__ cnt,
+                                               const uint8_t *__restrict__ active, double *__restrict__ binrec,
+                                               double *__restrict__ nllp, uint32_t *__restrict__ badp,
+                                               double *__restrict__ mu_out) {
   __shared__ double lds[8];
   __shared__ int bad_s;
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
+  if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double sum = 0.0;
-  bool bad = false;
-  for (int b = threadIdx.x; b < T.L; b += blockDim.x) {
+  if (b < T.L) {
     const int j = T.lo + b;
     const double *bn = Sh.bins + (size_t)j * kBinLen;
     const double dx = bn[1];
+    const double *fp = fpart + T.fpart_off + b;
     double s1 = 0.0;
-    for (int c = 0; c < T.fold_chunks; c++) s1 += fpart[T.fpart_off + (long long)c * T.L + b];
+    int c = 0;
+    for (; c + 4 <= T.fold_chunks; c += 4) {
+      const double p0 = fp[(long long)c * T.L], p1 = fp[(long long)(c + 1) * T.L], p2 = fp[(long long)(c + 2) * T.L],
+                   p3 = fp[(long long)(c + 3) * T.L];
+      s1 = (((s1 + p0) + p1) + p2) + p3;
+    }
+    for (; c < T.fold_chunks; c++) s1 += fp[(long long)c * T.L];
     const double mu1 = dx * s1;
     double G = 0.0;
+    bool bad = false;
     for (int d = 0; d < T.D; d++) {
       const double mu = T.exposure[d] * mu1;
       const double n = cnt[T.cnt_off + (long long)d * T.L + b];
@@ -204,40 +419,82 @@ __global__ __launch_bounds__(256) void k_nll1(const ToyDev *__restrict__ toys, c
     br[1] = bn[2];
     br[2] = bn[3];
     br[3] = G * dx;
+    if (bad) bad_s = 1;  // benign race: every writer stores 1
   }
-  if (bad) bad_s = 1;  // benign race: every writer stores 1
-  double tot = block_sum(sum, lds);
+  const double tot = block_sum(sum, lds);
   __syncthreads();
-  if (threadIdx.x == 0)
-    finish_nll(T, theta + (size_t)t * stride, pull_c, pull_s, tot, bad_s != 0, nll, status, t);
+  if (threadIdx.x == 0) {
+    nllp[T.nllp_off + blockIdx.x] = tot;
+    badp[T.nllp_off + blockIdx.x] = bad_s;
+  }
 }
 
-hipError_t launch_nll1(const BatchView &v, const double *theta, double *nll, uint32_t *status, double *mu_out,
-                       const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_nll1, dim3(v.n_toys), dim3(256), 0, st, v.toys, v.shapes, theta, v.stride, v.fpart, v.cnt,
-                     v.pull_c, v.pull_s, active, v.binrec, nll, status, mu_out);
+hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *active, hipStream_t st) {
+  hipLaunchKernelGGL(k_bins1, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, v.fpart,
+                     v.cnt, active, v.binrec, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------- k_adj1 -----
+// --------------------------------------------------------------- k_adj ----
+// Per-cell sums over window bins of Gr = G_j r_ji times {1, t1, t2}:
+//  gamma:    t1 = ln x_j, t2 = x_j (shifted by ln m and m in k_cellgrad)
+//  gaussian: t1 = z_ji, t2 = z_ji^2 with z = (x - m)/s
 template <int FAM>
-__device__ __forceinline__ void adj_range(const double *__restrict__ rc, const double *__restrict__ BR, int b0,
-                                          int b1, double &A0, double &A1, double &A2) {
-  for (int b = b0; b < b1; b++) {
-    const double *br = BR + (size_t)b * kBinLen;
-    const double x = br[0], G = br[3];
+__device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR, int b0, int b1,
+                                         const double *ec, double &A0, double &A1, double &A2) {
+  if (b0 >= b1) return;
+  double x = BR[(size_t)b0 * kBinLen], Lh = BR[(size_t)b0 * kBinLen + 1], Ll = BR[(size_t)b0 * kBinLen + 2],
+         G = BR[(size_t)b0 * kBinLen + 3];
+  for (int b = b0; b < b1; b += kWaves) {
+    const double *bn = BR + (size_t)min(b + kWaves, b1 - 1) * kBinLen;  // next bin, fetched early
+    const double nx = bn[0], nLh = bn[1], nLl = bn[2], nG = bn[3];
     if (FAM == kGammaPE) {
-      if (!(G != 0.0)) continue;  // wave-uniform: bin outside the gamma support
-      double r = exp(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, br[1], br[2]));
-      double Gr = G * r;
-      A0 += Gr;
-      A1 = __fma_rn(Gr, br[1] - rc[6], A1);
-      A2 = __fma_rn(Gr, x - rc[7], A2);
+      if (G != 0.0) {  // wave-uniform: zero seed, or bin outside the gamma support
+        const double Gr = G * exp_cw(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
+        A0 += Gr;
+        A1 = __fma_rn(Gr, Lh, A1);
+        A2 = __fma_rn(Gr, x, A2);
+      }
     } else {
       double z;
-      double r = exp(gauss_exponent(rc[0], rc[1], rc[2], x, z));
-      double Gr = G * r;
-      double Grz = Gr * z;
+      const double Gr = G * exp_cw(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
+      const double Grz = Gr * z;
+      A0 += Gr;
+      A1 += Grz;
+      A2 = __fma_rn(Grz, z, A2);
+    }
+    x = nx;
+    Lh = nLh;
+    Ll = nLl;
+    G = nG;
+  }
+}
+
+// Per-species adjoint (secondary observable): the seed of pair (j, i) is
+// Z_ji = sum_s H_js R_s w_si with H_js = dx_j sum_k P_sk Gam_jk, so each lane
+// keeps R_s w_si of its cell and each bin brings its H row.
+template <int FAM>
+__device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
+                                           const double *__restrict__ BR, const double *__restrict__ HR, int b0, int b1,
+                                           const double *ec, double &A0, double &A1, double &A2) {
+  for (int b = b0; b < b1; b += kWaves) {
+    const double *br = BR + (size_t)b * kBinLen;
+    const double x = br[0], Lh = br[1], Ll = br[2];
+    if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
+    const double *h = HR + (size_t)b * S;
+    double Z = 0.0;
+#pragma unroll
+    for (int q = 0; q < GS_MAX_SPECIES; q++)
+      if (q < S) Z = __fma_rn(h[q], rw[q], Z);
+    if (FAM == kGammaPE) {
+      const double Gr = Z * exp_cw(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
+      A0 += Gr;
+      A1 = __fma_rn(Gr, Lh, A1);
+      A2 = __fma_rn(Gr, x, A2);
+    } else {
+      double z;
+      const double Gr = Z * exp_cw(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
+      const double Grz = Gr * z;
       A0 += Gr;
       A1 += Grz;
       A2 = __fma_rn(Grz, z, A2);
@@ -245,56 +502,102 @@ __device__ __forceinline__ void adj_range(const double *__restrict__ rc, const d
   }
 }
 
-__global__ __launch_bounds__(256) void k_adj1(const AdjItem *__restrict__ items, int n_items,
-                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                              const double *__restrict__ rec, const double *__restrict__ binrec,
-                                              const uint8_t *__restrict__ active, double *__restrict__ apart) {
-  const int w = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (w >= n_items) return;
-  const int lane = threadIdx.x & 63;
-  const AdjItem it = items[w];
+template <bool PS>
+__global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, int n_items,
+                                             const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                             const double *__restrict__ theta, int stride,
+                                             const double *__restrict__ rec, const double *__restrict__ binrec,
+                                             const double *__restrict__ H, const uint8_t *__restrict__ active,
+                                             double *__restrict__ apart) {
+  __shared__ double red[kWaves * kTile * 3];
+  const double *ec = kExpC;
+  const int w_item = xcd_item(blockIdx.x, n_items);
+  if (w_item >= n_items) return;
+  const AdjItem it = items[w_item];
   if (active && !active[it.toy]) return;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const ToyDev &T = toys[it.toy];
+  if (T.two_d != (PS ? 1 : 0)) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int i = it.cell0 + lane;
   const bool valid = i < T.n_cell;
-  const double *rp = rec + (T.cell_off + (valid ? i : T.n_cell - 1)) * kRecLen;
+  const int ic = valid ? i : T.n_cell - 1;
+  const double *rp = rec + (T.cell_off + ic) * kRecLen;
   double rc[kRecLen];
 #pragma unroll
   for (int q = 0; q < kRecLen; q++) rc[q] = rp[q];
+  // union of the 64 cells' supports, as window-relative bins, clipped to the chunk
+  const int2 s = get_support(rc);
+  int lo = valid ? s.x : 0x7fffffff, hi = valid ? s.y : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
   const double *BR = binrec + T.win_off * kBinLen;
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
-  if (Sh.family == kGammaPE)
-    adj_range<kGammaPE>(rc, BR, it.bin0, it.bin1, A0, A1, A2);
-  else
-    adj_range<kGaussE>(rc, BR, it.bin0, it.bin1, A0, A1, A2);
-  if (valid) {
+  if (!PS) {
+    if (Sh.family == kGammaPE)
+      adj_bins<kGammaPE>(rc, BR, b0 + wave, b1, ec, A0, A1, A2);
+    else
+      adj_bins<kGaussE>(rc, BR, b0 + wave, b1, ec, A0, A1, A2);
+  } else {
+    const double *th = theta + (size_t)it.toy * stride;
+    double rw[GS_MAX_SPECIES];
+#pragma unroll
+    for (int q = 0; q < GS_MAX_SPECIES; q++) rw[q] = 0.0;
+    if (ic < Sh.n_true) {
+      const double *w = Sh.wcell + (size_t)ic * Sh.Sg;
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++)
+        if (q < Sh.Sg) rw[q] = th[Sh.sp_of[q]] * w[q];
+    } else {
+      const int ql = Sh.Sg + (ic - Sh.n_true);
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++)
+        if (q == ql) rw[q] = th[Sh.sp_of[q]];
+    }
+    const double *HR = H + T.win_off * T.S;
+    if (Sh.family == kGammaPE)
+      adj_bins_s<kGammaPE>(rc, rw, T.S, BR, HR, b0 + wave, b1, ec, A0, A1, A2);
+    else
+      adj_bins_s<kGaussE>(rc, rw, T.S, BR, HR, b0 + wave, b1, ec, A0, A1, A2);
+  }
+  red[(wave * 3 + 0) * kTile + lane] = A0;
+  red[(wave * 3 + 1) * kTile + lane] = A1;
+  red[(wave * 3 + 2) * kTile + lane] = A2;
+  __syncthreads();
+  if (wave == 0 && valid) {
     double *o = apart + T.apart_off + ((long long)it.chunk * T.n_cell + i) * 3;
-    o[0] = A0;
-    o[1] = A1;
-    o[2] = A2;
+    for (int q = 0; q < 3; q++) {
+      double v = red[q * kTile + lane];
+      for (int ww = 1; ww < kWaves; ww++) v += red[(ww * 3 + q) * kTile + lane];
+      o[q] = v;
+    }
   }
 }
 
-hipError_t launch_adj1(const BatchView &v, hipStream_t st) {
+hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *active, hipStream_t st) {
   if (v.n_adj_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj1, dim3((v.n_adj_items + 3) / 4), dim3(256), 0, st, v.adj_items, v.n_adj_items, v.toys,
-                     v.shapes, v.rec, v.binrec, (const uint8_t *)nullptr, v.apart);
+  if (per_species)
+    hipLaunchKernelGGL(k_adj<true>, dim3(xcd_grid(v.n_adj_items)), dim3(kWaves * 64), 0, st, v.adj_items,
+                       v.n_adj_items, v.toys, v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
+  else
+    hipLaunchKernelGGL(k_adj<false>, dim3(xcd_grid(v.n_adj_items)), dim3(kWaves * 64), 0, st, v.adj_items,
+                       v.n_adj_items, v.toys, v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ k_grad1 -----
-__global__ __launch_bounds__(256) void k_grad1(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                               const double *__restrict__ theta, int stride,
-                                               const double *__restrict__ rec, const double *__restrict__ apart,
-                                               const double *__restrict__ pull_c, const double *__restrict__ pull_s,
-                                               const uint32_t *__restrict__ status, const uint8_t *__restrict__ active,
-                                               double *__restrict__ grad) {
+// ----------------------------------------------------------- k_cellgrad ---
+__global__ __launch_bounds__(256) void k_cellgrad(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                                  const double *__restrict__ theta, int stride,
+                                                  const double *__restrict__ rec, const double *__restrict__ apart,
+                                                  const uint8_t *__restrict__ active, double *__restrict__ gpart) {
   __shared__ double lds[8];
-  __shared__ double res[GS_MAX_PARAMS];
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
+  if ((int)blockIdx.x >= T.cell_blocks) return;
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
   const int fam = Sh.family, nr = fam == kGaussE ? 2 : 5;
@@ -303,7 +606,8 @@ __global__ __launch_bounds__(256) void k_grad1(const ToyDev *__restrict__ toys, 
   for (int s = 0; s < GS_MAX_SPECIES; s++) gR[s] = 0.0;
 #pragma unroll
   for (int p = 0; p < 5; p++) gP[p] = 0.0;
-  for (int i = threadIdx.x; i < Sh.n_cell; i += blockDim.x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Sh.n_cell) {
     double A0 = 0.0, A1 = 0.0, A2 = 0.0;
     for (int c = 0; c < T.adj_chunks; c++) {
       const double *a = apart + T.apart_off + ((long long)c * T.n_cell + i) * 3;
@@ -316,20 +620,24 @@ __global__ __launch_bounds__(256) void k_grad1(const ToyDev *__restrict__ toys, 
     const double *rc = rec + (T.cell_off + i) * kRecLen;
     double dNdm, dNds;
     if (fam == kGammaPE) {
-      const double W = rc[5], m = mo.m, s = mo.s, s2 = s * s;
-      const double k = m * m / s2, thg = s2 / m;
-      const double dk = W * __fma_rn(log_minus_digamma(k), A0, A1);  // d(-ln L)/dk
-      const double dth = W * A2 / (thg * thg);                       // d(-ln L)/dtheta
+      const double W = T.two_d ? 1.0 : rc[5], m = mo.m, s = mo.s, s2 = s * s;
+      const double k = m * m / s2, thg = s2 / m, mk = k * thg;
+      // shift the sums of ln x and x to ln x - ln(k th) and x - k th
+      const double B1 = __fma_rn(-log(mk), A0, A1), B2 = __fma_rn(-mk, A0, A2);
+      const double dk = W * __fma_rn(log_minus_digamma(k), A0, B1);  // d(-ln L)/dk
+      const double dth = W * B2 / (thg * thg);                       // d(-ln L)/dtheta
       dNdm = dk * (2.0 * m / s2) - dth * (s2 / (m * m));
       dNds = -dk * (2.0 * m * m / (s2 * s)) + dth * (2.0 * s / m);
     } else {
-      const double W = rc[3], is = 1.0 / mo.s;
+      const double W = T.two_d ? 1.0 : rc[3], is = 1.0 / mo.s;
       dNdm = W * A1 * is;
       dNds = W * (A2 - A0) * is;
     }
 #pragma unroll
     for (int p = 0; p < 5; p++) gP[p] = __fma_rn(dNdm, mo.dm[p], __fma_rn(dNds, mo.ds[p], gP[p]));
-    if (i < Sh.n_true) {
+    if (T.two_d) {
+      // rate gradients of 2-D models come from the pulse-shape contraction (k_vpart)
+    } else if (i < Sh.n_true) {
       const double *w = Sh.wcell + (size_t)i * Sh.Sg;
 #pragma unroll
       for (int s = 0; s < GS_MAX_SPECIES; s++)
@@ -341,32 +649,98 @@ __global__ __launch_bounds__(256) void k_grad1(const ToyDev *__restrict__ toys, 
         if (s == q) gR[s] += A0;
     }
   }
+  double *o = gpart + (T.gpart_off + blockIdx.x) * kGradLen;
   for (int s = 0; s < Sh.S; s++) {
-    double v = block_sum(gR[s], lds);
-    if (threadIdx.x == 0) res[Sh.sp_of[s]] = v;
+    const double v = block_sum(gR[s], lds);
+    if (threadIdx.x == 0) o[Sh.sp_of[s]] = v;
   }
   for (int p = 0; p < nr; p++) {
-    double v = block_sum(gP[p], lds);
-    if (threadIdx.x == 0) res[Sh.S + p] = v;
+    const double v = block_sum(gP[p], lds);
+    if (threadIdx.x == 0) o[Sh.S + p] = v;
+  }
+}
+
+hipError_t launch_cellgrad(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
+  hipLaunchKernelGGL(k_cellgrad, dim3(v.max_cell_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, theta,
+                     v.stride, v.rec, v.apart, active, v.gpart);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- k_finish ---
+// Thread p < stride: gradient entry p; thread 0 also -ln L and status.
+__global__ __launch_bounds__(64) void k_finish(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ theta, int stride,
+                                               const double *__restrict__ nllp, const uint32_t *__restrict__ badp,
+                                               const uint32_t *__restrict__ cflag, const double *__restrict__ gpart,
+                                               const double *__restrict__ vpart, const uint32_t *__restrict__ pflag,
+                                               const double *__restrict__ pull_c,
+                                               const double *__restrict__ pull_s, const uint8_t *__restrict__ active,
+                                               double *__restrict__ nll, double *__restrict__ grad,
+                                               uint32_t *__restrict__ status) {
+  __shared__ uint32_t st_s;
+  const int t = blockIdx.x;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  const ShapeDev &Sh = shapes[T.shape];
+  const double *th = theta + (size_t)t * stride;
+  const int p = threadIdx.x;
+  if (p == 0) {
+    uint32_t st = 0;
+    double sum = 0.0;
+    for (int b = 0; b < T.bin_blocks; b++) {
+      sum += nllp[T.nllp_off + b];
+      if (badp[T.nllp_off + b]) st |= GS_ST_DOMAIN;
+    }
+    for (int b = 0; b < T.cflag_blocks; b++)
+      if (cflag[T.cflag_off + b]) st |= GS_ST_DOMAIN;  // invalid response somewhere on the grid
+    if (T.two_d && pflag[t]) st |= GS_ST_DOMAIN;     // invalid pulse-shape nuisance
+    for (int q = 0; q < T.P; q++) {
+      if (!isfinite(th[q])) st |= GS_ST_NONFINITE;
+      const double s = pull_s[T.pull_off + q];
+      if (s > 0.0) {
+        const double z = (th[q] - pull_c[T.pull_off + q]) / s;
+        sum = __fma_rn(0.5 * z, z, sum);
+      }
+    }
+    if (st & GS_ST_NONFINITE) {
+      st = GS_ST_NONFINITE;  // a non-finite parameter explains every other symptom
+      sum = __builtin_nan("");
+    }
+    else if (st & GS_ST_DOMAIN)
+      sum = __builtin_inf();
+    nll[t] = sum;
+    status[t] = st;
+    st_s = st;
   }
   __syncthreads();
-  if (threadIdx.x < stride) {
-    const int p = threadIdx.x;
+  if (grad && p < stride) {
+    const int nr = Sh.family == kGaussE ? 2 : 5;
     double g = 0.0;
     if (p < T.P) {
-      g = p < Sh.S + nr ? res[p] : 0.0;
-      double s = pull_s[T.pull_off + p];
+      if (p < Sh.S + nr)
+        for (int b = 0; b < T.cell_blocks; b++) g += gpart[(T.gpart_off + b) * kGradLen + p];
+      if (T.two_d) {
+        const double *vp = vpart + (size_t)t * GS_MAX_SPECIES * 4;
+        if (p < Sh.S) {
+          for (int q = 0; q < Sh.S; q++)
+            if (Sh.sp_of[q] == p) g += vp[q * 4];
+        } else if (p >= Sh.S + nr) {
+          const int v = p - Sh.S - nr;
+          for (int q = 0; q < Sh.S; q++) g = __fma_rn(th[Sh.sp_of[q]], vp[q * 4 + 1 + v], g);
+        }
+      }
+      const double s = pull_s[T.pull_off + p];
       if (s > 0.0) g += (th[p] - pull_c[T.pull_off + p]) / (s * s);
-      if (status[t] & (GS_ST_DOMAIN | GS_ST_NONFINITE)) g = __builtin_nan("");
+      if (st_s & (GS_ST_DOMAIN | GS_ST_NONFINITE)) g = __builtin_nan("");
     }
     grad[(size_t)t * stride + p] = g;
   }
 }
 
-hipError_t launch_grad1(const BatchView &v, const double *theta, const uint32_t *status, double *grad,
-                        const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad1, dim3(v.n_toys), dim3(256), 0, st, v.toys, v.shapes, theta, v.stride, v.rec, v.apart,
-                     v.pull_c, v.pull_s, status, active, grad);
+hipError_t launch_finish(const BatchView &v, const double *theta, double *nll, double *grad, uint32_t *status,
+                         const uint8_t *active, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(v.n_toys), dim3(64), 0, st, v.toys, v.shapes, theta, v.stride, v.nllp, v.badp,
+                     v.cflag, v.gpart, v.vpart, v.pflag, v.pull_c, v.pull_s, active, nll, grad, status);
   return hipGetLastError();
 }
 
@@ -377,7 +751,7 @@ __global__ void k_bins_setup(const double *__restrict__ edges, int n_reco, doubl
   if (j >= n_reco) return;
   const double a = edges[j], b = edges[j + 1];
   const double x = (a + b) * 0.5;
-  dd L = x > 0.0 ? dd_log(x) : dd{0.0, 0.0};
+  const dd L = x > 0.0 ? dd_log(x) : dd{0.0, 0.0};
   double *o = bins + (size_t)j * kBinLen;
   o[0] = x;
   o[1] = b - a;
@@ -385,118 +759,59 @@ __global__ void k_bins_setup(const double *__restrict__ edges, int n_reco, doubl
   o[3] = L.lo;
 }
 
-hipError_t launch_bins_setup(const ShapeDev *, double *bins, const double *edges, int n_reco, hipStream_t st) {
+hipError_t launch_bins_setup(double *bins, const double *edges, int n_reco, hipStream_t st) {
   hipLaunchKernelGGL(k_bins_setup, dim3((n_reco + 255) / 256), dim3(256), 0, st, edges, n_reco, bins);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------- per-species fold ----
-// F_js = dx_j sum_i w_si r_ji for every species (plain path cache, 2-D).
-// Lanes are bins; grid cells add into Sg accumulators, line cells into their own.
-template <int FAM>
-__device__ __forceinline__ void folds_range(const double *__restrict__ R, const double *__restrict__ wc, int Sg,
-                                            int n_true, int c0, int c1, double x, double Lh, double Ll,
-                                            double (&acc)[GS_MAX_SPECIES]) {
-  for (int i = c0; i < c1; i++) {
-    const double *p = R + (size_t)i * kRecLen;
-    double r;
-    if (FAM == kGammaPE) {
-      r = exp(gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll));
-    } else {
-      double z;
-      r = exp(gauss_exponent(p[0], p[1], p[2], x, z));
-    }
-    if (i < n_true) {
-      const double *w = wc + (size_t)i * Sg;
-#pragma unroll
-      for (int s = 0; s < GS_MAX_SPECIES; s++)
-        if (s < Sg) acc[s] = __fma_rn(w[s], r, acc[s]);
-    } else {
-      const int q = Sg + (i - n_true);
-#pragma unroll
-      for (int s = 0; s < GS_MAX_SPECIES; s++)
-        if (s == q) acc[s] += r;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_foldS(const FoldItem *__restrict__ items, int n_items,
-                                               const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                               const double *__restrict__ rec, const long long *__restrict__ fs_off,
-                                               double *__restrict__ fspart) {
-  const int w = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (w >= n_items) return;
-  const int lane = threadIdx.x & 63;
-  const FoldItem it = items[w];
-  const ToyDev &T = toys[it.toy];
+// ---------------------------------------------- per-species (plain path) --
+// F[(win_off + b) * S + s] = dx_b * sum over chunks (fixed order).
+__global__ __launch_bounds__(256) void k_reduceF(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                                 const double *__restrict__ fspart, int mode,
+                                                 const uint8_t *__restrict__ active, double *__restrict__ F) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if (mode >= 0 && T.two_d != mode) return;
   const ShapeDev &Sh = shapes[T.shape];
-  const int b = it.bin0 + lane;
-  const bool valid = b < T.L;
-  const int j = T.lo + (valid ? b : T.L - 1);
-  const double *bn = Sh.bins + (size_t)j * kBinLen;
-  const double x = bn[0], Lh = bn[2], Ll = bn[3];
-  const double *R = rec + T.cell_off * kRecLen;
-  double acc[GS_MAX_SPECIES];
-#pragma unroll
-  for (int s = 0; s < GS_MAX_SPECIES; s++) acc[s] = 0.0;
-  if (Sh.family == kGammaPE) {
-    folds_range<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, it.cell0, it.cell1, x, Lh, Ll, acc);
-    if (!(x > 0.0))
-#pragma unroll
-      for (int s = 0; s < GS_MAX_SPECIES; s++) acc[s] = 0.0;
-  } else {
-    folds_range<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, it.cell0, it.cell1, x, Lh, Ll, acc);
-  }
-  if (valid) {
-    double *o = fspart + fs_off[it.toy] + ((long long)it.chunk * T.L + b) * T.S;
-#pragma unroll
-    for (int s = 0; s < GS_MAX_SPECIES; s++)
-      if (s < T.S) o[s] = acc[s];
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= T.L) return;
+  const double dx = Sh.bins[(size_t)(T.lo + b) * kBinLen + 1];
+  for (int s = 0; s < T.S; s++) {
+    double acc = 0.0;
+    for (int c = 0; c < T.fold_chunks; c++) acc += fspart[T.fs_off + ((long long)c * T.L + b) * T.S + s];
+    F[(T.win_off + b) * T.S + s] = dx * acc;
   }
 }
 
-hipError_t launch_foldS(const BatchView &v, hipStream_t st) {
-  if (v.n_fold_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_foldS, dim3((v.n_fold_items + 3) / 4), dim3(256), 0, st, v.fold_items, v.n_fold_items,
-                     v.toys, v.shapes, v.rec, v.fs_off, v.fspart);
+hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduceF, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, v.fspart,
+                     mode, active, v.F);
   return hipGetLastError();
 }
 
-// F[(win_off + b) * S + s] = dx_b * sum over chunks (fixed order).
-__global__ __launch_bounds__(256) void k_reduceF(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                                 const long long *__restrict__ fs_off,
-                                                 const double *__restrict__ fspart, double *__restrict__ F) {
-  const int t = blockIdx.y;
-  const ToyDev &T = toys[t];
-  const ShapeDev &Sh = shapes[T.shape];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= T.L * T.S) return;
-  const int b = e / T.S;
-  double acc = 0.0;
-  for (int c = 0; c < T.fold_chunks; c++) acc += fspart[fs_off[t] + (long long)c * T.L * T.S + e];
-  F[T.win_off * T.S + e] = Sh.bins[(size_t)(T.lo + b) * kBinLen + 1] * acc;
-}
-
-// -ln L from cached per-species spectra: mu_dj = eps_d sum_s R_s F_js.
-__global__ __launch_bounds__(256) void k_nllF(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                              const double *__restrict__ theta, int stride, const double *__restrict__ F,
-                                              const double *__restrict__ cnt, const double *__restrict__ pull_c,
-                                              const double *__restrict__ pull_s, double *__restrict__ nll,
-                                              uint32_t *__restrict__ status, double *__restrict__ mu_out) {
+// -ln L block partials from cached per-species spectra: mu_dj = eps_d sum_s R_s F_js.
+__global__ __launch_bounds__(256) void k_binsF(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ theta, int stride,
+                                               const double *__restrict__ F, const double *__restrict__ cnt,
+                                               double *__restrict__ nllp, uint32_t *__restrict__ badp,
+                                               double *__restrict__ mu_out) {
   __shared__ double lds[8];
   __shared__ int bad_s;
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
   const ToyDev &T = toys[t];
+  if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double sum = 0.0;
-  bool bad = false;
-  for (int b = threadIdx.x; b < T.L; b += blockDim.x) {
+  if (b < T.L) {
     const double *f = F + (T.win_off + b) * T.S;
     double mu1 = 0.0;
     for (int s = 0; s < Sh.S; s++) mu1 = __fma_rn(th[Sh.sp_of[s]], f[s], mu1);
+    bool bad = false;
     for (int d = 0; d < T.D; d++) {
       const double mu = T.exposure[d] * mu1;
       const double n = cnt[T.cnt_off + (long long)d * T.L + b];
@@ -505,23 +820,194 @@ __global__ __launch_bounds__(256) void k_nllF(const ToyDev *__restrict__ toys, c
       sum += term;
       if (mu_out) mu_out[(long long)d * T.L + b] = mu;
     }
+    if (bad) bad_s = 1;
   }
-  if (bad) bad_s = 1;
-  double tot = block_sum(sum, lds);
+  const double tot = block_sum(sum, lds);
   __syncthreads();
-  if (threadIdx.x == 0) finish_nll(T, th, pull_c, pull_s, tot, bad_s != 0, nll, status, t);
+  if (threadIdx.x == 0) {
+    nllp[T.nllp_off + blockIdx.x] = tot;
+    badp[T.nllp_off + blockIdx.x] = bad_s;
+  }
 }
 
-hipError_t launch_nllF(const BatchView &v, const double *theta, double *nll, uint32_t *status, double *mu_out,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_nllF, dim3(v.n_toys), dim3(256), 0, st, v.toys, v.shapes, theta, v.stride, v.F, v.cnt,
-                     v.pull_c, v.pull_s, nll, status, mu_out);
+hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_binsF, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, theta,
+                     v.stride, v.F, v.cnt, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
 
-hipError_t launch_reduceF_grid(const BatchView &v, int max_LS, hipStream_t st) {
-  dim3 grid((max_LS + 255) / 256, v.n_toys);
-  hipLaunchKernelGGL(k_reduceF, grid, dim3(256), 0, st, v.toys, v.shapes, v.fs_off, v.fspart, v.F);
+
+// ------------------------------------------- secondary observable (2-D) --
+// Pulse-shape probabilities of every species (section 2.4): a two-Gaussian
+// mixture at the bin midpoints, means shifted by delta, widths scaled by
+// kappa, odds of component 1 multiplied by exp(eta), renormalised over the
+// bins; with their derivatives w.r.t. (delta, kappa, eta).  One thread per species.
+__global__ __launch_bounds__(64) void k_psd(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                            const double *__restrict__ theta, int stride,
+                                            const uint8_t *__restrict__ active, double *__restrict__ P,
+                                            double *__restrict__ dP, uint32_t *__restrict__ pflag) {
+  const int t = blockIdx.x;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if (!T.two_d) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const double *nu = theta + (size_t)t * stride + Sh.S + (Sh.family == kGaussE ? 2 : 5);
+  const double delta = nu[0], kappa = nu[1], eta = nu[2];
+  const bool ok = kappa > 0.0 && isfinite(kappa) && isfinite(delta) && isfinite(eta);
+  if (threadIdx.x == 0) pflag[t] = ok ? 0u : 1u;
+  const int s = threadIdx.x;
+  if (!ok || s >= Sh.S) return;
+  const double *mx = Sh.mix + 5 * s;
+  const double w1 = mx[0];
+  const double wp = 1.0 / (1.0 + exp(-(log(w1 / (1.0 - w1)) + eta)));
+  const double inv_root2pi = 0.39894228040143267794;
+  auto comp = [&](double y, int c, double &N, double &dd, double &dk) {
+    const double sg = mx[2 + 2 * c] * kappa;
+    const double z = (y - (mx[1 + 2 * c] + delta)) / sg;
+    N = exp(-0.5 * z * z) * inv_root2pi / sg;
+    dd = N * z / sg;
+    dk = N * (z * z - 1.0) / kappa;
+  };
+  double Z = 0.0, dZ0 = 0.0, dZ1 = 0.0, dZ2 = 0.0;
+  for (int k = 0; k < Sh.n_psd; k++) {
+    const double y = Sh.psd[2 * k], dy = Sh.psd[2 * k + 1];
+    double N0, d0, k0, N1, d1, k1;
+    comp(y, 0, N0, d0, k0);
+    comp(y, 1, N1, d1, k1);
+    Z += dy * (wp * N0 + (1.0 - wp) * N1);
+    dZ0 += dy * (wp * d0 + (1.0 - wp) * d1);
+    dZ1 += dy * (wp * k0 + (1.0 - wp) * k1);
+    dZ2 += dy * wp * (1.0 - wp) * (N0 - N1);
+  }
+  const double iZ = 1.0 / Z;
+  for (int k = 0; k < Sh.n_psd; k++) {
+    const double y = Sh.psd[2 * k], dy = Sh.psd[2 * k + 1];
+    double N0, d0, k0, N1, d1, k1;
+    comp(y, 0, N0, d0, k0);
+    comp(y, 1, N1, d1, k1);
+    const double p = dy * (wp * N0 + (1.0 - wp) * N1);
+    const double pk = p * iZ;
+    const long long o = T.psd_off + (long long)s * T.K + k;
+    P[o] = pk;
+    dP[3 * o + 0] = (dy * (wp * d0 + (1.0 - wp) * d1) - pk * dZ0) * iZ;
+    dP[3 * o + 1] = (dy * (wp * k0 + (1.0 - wp) * k1) - pk * dZ1) * iZ;
+    dP[3 * o + 2] = (dy * wp * (1.0 - wp) * (N0 - N1) - pk * dZ2) * iZ;
+  }
+}
+
+hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
+  hipLaunchKernelGGL(k_psd, dim3(v.n_toys), dim3(64), 0, st, v.toys, v.shapes, theta, v.stride, active, v.P, v.dP,
+                     v.pflag);
+  return hipGetLastError();
+}
+
+// Per (toy, 256 energy bins): mu_djk = eps_d sum_s R_s F_js P_sk, Poisson terms,
+// Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), H_js = dx_j sum_k P_sk Gam_jk.
+__global__ __launch_bounds__(256) void k_bins2(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ theta, int stride,
+                                               const double *__restrict__ F, const double *__restrict__ P,
+                                               const double *__restrict__ cnt, const uint8_t *__restrict__ active,
+                                               double *__restrict__ binrec, double *__restrict__ H,
+                                               double *__restrict__ Gam, double *__restrict__ nllp,
+                                               uint32_t *__restrict__ badp, double *__restrict__ mu_out) {
+  __shared__ double lds[8];
+  __shared__ double Ps[GS_MAX_SPECIES * GS_MAX_PSD];
+  __shared__ int bad_s;
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if ((int)blockIdx.x >= T.bin_blocks || !T.two_d) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int S = T.S, K = T.K;
+  for (int e = threadIdx.x; e < S * K; e += blockDim.x) Ps[e] = P[T.psd_off + e];
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  const double *th = theta + (size_t)t * stride;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  double sum = 0.0;
+  if (b < T.L) {
+    const int j = T.lo + b;
+    const double *bn = Sh.bins + (size_t)j * kBinLen;
+    const double dx = bn[1];
+    double rf[GS_MAX_SPECIES], hs[GS_MAX_SPECIES];
+#pragma unroll
+    for (int q = 0; q < GS_MAX_SPECIES; q++) {
+      rf[q] = q < S ? th[Sh.sp_of[q]] * F[(T.win_off + b) * S + q] : 0.0;
+      hs[q] = 0.0;
+    }
+    bool bad = false;
+    for (int k = 0; k < K; k++) {
+      double M = 0.0;
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++)
+        if (q < S) M = __fma_rn(rf[q], Ps[q * K + k], M);
+      double gam = 0.0;
+      for (int d = 0; d < T.D; d++) {
+        const double mu = T.exposure[d] * M;
+        const double n = cnt[T.cnt_off + ((long long)d * T.L + b) * K + k];
+        double term, g;
+        if (!poisson_term(mu, n, term, g)) bad = true;
+        sum += term;
+        gam = __fma_rn(T.exposure[d], g, gam);
+        if (mu_out) mu_out[((long long)d * T.L + b) * K + k] = mu;
+      }
+      Gam[T.gam_off + (long long)b * K + k] = gam;
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++)
+        if (q < S) hs[q] = __fma_rn(Ps[q * K + k], gam, hs[q]);
+    }
+    const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
+    for (int q = 0; q < S; q++) H[(T.win_off + b) * S + q] = outside ? 0.0 : dx * hs[q];
+    double *br = binrec + (T.win_off + b) * kBinLen;
+    br[0] = bn[0];
+    br[1] = bn[2];
+    br[2] = bn[3];
+    br[3] = outside ? 0.0 : 1.0;
+    if (bad) bad_s = 1;
+  }
+  const double tot = block_sum(sum, lds);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    nllp[T.nllp_off + blockIdx.x] = tot;
+    badp[T.nllp_off + blockIdx.x] = bad_s;
+  }
+}
+
+hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, theta,
+                     v.stride, v.F, v.P, v.cnt, active, v.binrec, v.H, v.Gam, v.nllp, v.badp, mu_out);
+  return hipGetLastError();
+}
+
+// Per (toy, species s): V_sk = sum_j F_js Gam_jk, reduced to sum_k P_sk V_sk (the
+// rate gradient) and sum_k dP_sk/dnu V_sk (times R_s in k_finish: nuisance gradients).
+__global__ __launch_bounds__(64) void k_vpart(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                              const double *__restrict__ F, const double *__restrict__ Gam,
+                                              const double *__restrict__ P, const double *__restrict__ dP,
+                                              const uint8_t *__restrict__ active, double *__restrict__ vpart) {
+  const int t = blockIdx.y, s = blockIdx.x;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if (!T.two_d || s >= T.S) return;
+  const int K = T.K;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double V = 0.0;
+    for (int b = 0; b < T.L; b++) V = __fma_rn(F[(T.win_off + b) * T.S + s], Gam[T.gam_off + (long long)b * K + k], V);
+    const long long o = T.psd_off + (long long)s * K + k;
+    a[0] = __fma_rn(P[o], V, a[0]);
+    for (int v = 0; v < 3; v++) a[1 + v] = __fma_rn(dP[3 * o + v], V, a[1 + v]);
+  }
+  for (int q = 0; q < 4; q++)
+    for (int o = 32; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 64);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; q++) vpart[((size_t)t * GS_MAX_SPECIES + s) * 4 + q] = a[q];
+}
+
+hipError_t launch_vpart(const BatchView &v, const uint8_t *active, hipStream_t st) {
+  hipLaunchKernelGGL(k_vpart, dim3(GS_MAX_SPECIES, v.n_toys), dim3(64), 0, st, v.toys, v.shapes, v.F, v.Gam, v.P,
+                     v.dP, active, v.vpart);
   return hipGetLastError();
 }
 

@@ -1,0 +1,18 @@
+"""The device exponential (paper_1812_05686_amd/csrc/gs_exp.h) compiled for the host and checked
+against long-double expl: relative error within 2 ulp over the normal range, underflow
+handled, special values exact."""
+import json
+import os
+import subprocess
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exp_cw_accuracy(tmp_path):
+    exe = tmp_path / "exp_check"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1812_05686_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "exp_check.cpp"), "-o", str(exe)])
+    r = json.loads(subprocess.check_output([str(exe)]).decode())
+    assert r["bad_special"] == 0, r
+    assert r["max_rel"] <= 2.3e-16, r
+    assert r["max_subnormal_ulps"] <= 1.0, r
