@@ -113,20 +113,23 @@ def main():
     gpu_grad = grad.cpu().numpy()
     assert np.all(st.cpu().numpy() == 0)
 
-    fold_pairs, adj_pairs, full_pairs = batch.mesh_pairs()
+    fold_pairs, adj_pairs, full_pairs, band_pairs = batch.mesh_pairs()
+    # the unit of work is a banded-mesh pair: a (window bin, cell) pair whose bin lies in
+    # the cell's support; pairs a kernel evaluates beyond those are its own overhead
     executed = {"fold": fold_pairs, "adj": adj_pairs}
     per_kernel = {}
     for k in ("fold", "adj"):
         ms, n = kt[k]
         avg = ms / n
-        per_kernel[k] = dict(avg_ms=avg, tflops=executed[k] * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12,
-                             executed_fraction=executed[k] / full_pairs)
+        per_kernel[k] = dict(avg_ms=avg, tflops=band_pairs * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12,
+                             executed_over_banded=executed[k] / band_pairs)
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
     ach = per_kernel[dom]["tflops"]
-    roofline = {"bound": "alu", "kernel": "k_" + dom, "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": executed[dom],
-                "full_mesh_pairs": full_pairs, "executed_fraction": round(executed[dom] / full_pairs, 4),
+    roofline = {"bound": "alu", "kernel": "k_fold1" if dom == "fold" else "k_adj", "achieved": round(ach, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                "traffic": None, "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": band_pairs,
+                "executed_pairs": executed[dom], "full_mesh_pairs": full_pairs,
+                "banded_over_full": round(band_pairs / full_pairs, 4),
                 "avg_launch_ms": round(per_kernel[dom]["avg_ms"], 4),
                 "other": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in per_kernel.items() if k != dom}}
     pairs = full_pairs

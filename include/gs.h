@@ -229,10 +229,13 @@ gs_status gs_batch_set_profiling(gs_batch *b, int32_t on);
  * last reset (host arrays of GS_K_COUNT entries).  Waits for the recorded
  * events; reset != 0 clears the accumulators afterwards. */
 gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset);
-/* Mesh pairs of the most recent evaluation of the batch: out[0] pairs the
- * fold evaluated (64 lanes per visited cell and bin tile, idle lanes of a
- * partial tile included), out[1] pairs the adjoint evaluated, out[2] the full
- * mesh sum_t (window bins x cells).  Synchronises the device. */
+/* Mesh pairs (window bin x cell) of the most recent evaluation of the batch,
+ * host array of 4: out[0] pairs the 1-D fold evaluated (128 lanes per visited
+ * cell and bin tile, idle lanes of a partial tile included), out[1] pairs the
+ * adjoint evaluated, out[2] the full mesh sum_t (window bins x cells), out[3]
+ * the banded mesh: pairs whose bin lies in the cell's support, i.e. the
+ * pairs the method needs at the current log-density cut.  Synchronises the
+ * device. */
 gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out);
 
 #ifdef __cplusplus

@@ -290,10 +290,11 @@ class Batch:
         _check(lib().gs_batch_set_log_cut(self.h, float(log_cut)), "gs_batch_set_log_cut")
 
     def mesh_pairs(self):
-        """(fold pairs, adjoint pairs, full-mesh pairs) of the most recent evaluation."""
-        out = (C.c_int64 * 3)()
+        """(fold pairs, adjoint pairs, full-mesh pairs, banded-mesh pairs) of the most recent
+        evaluation."""
+        out = (C.c_int64 * 4)()
         _check(lib().gs_batch_mesh_pairs(self.h, out), "gs_batch_mesh_pairs")
-        return int(out[0]), int(out[1]), int(out[2])
+        return int(out[0]), int(out[1]), int(out[2]), int(out[3])
 
     def set_profiling(self, on: bool):
         _check(lib().gs_batch_set_profiling(self.h, int(on)), "gs_batch_set_profiling")

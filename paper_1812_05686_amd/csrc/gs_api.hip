@@ -316,13 +316,13 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   long long tiles_f = 0, tiles_a = 0;
   for (int t = 0; t < n_toys; t++) {
     const ShapeDev &sh = B->shapes_h[toy_shape[t]];
-    tiles_f += (descs[t].win_hi - descs[t].win_lo + kTile - 1) / kTile;
+    tiles_f += (descs[t].win_hi - descs[t].win_lo + kFoldTile - 1) / kFoldTile;
     tiles_a += (sh.n_cell + kTile - 1) / kTile;
   }
   const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
   const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
   long long cell_off = 0, win_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
-  long long nllp_off = 0, gpart_off = 0, cflag_off = 0, gam_off = 0, psd_off = 0;
+  long long nllp_off = 0, gpart_off = 0, cflag_off = 0, gam_off = 0, psd_off = 0, ghull_off = 0;
   std::vector<double> cnt_h, pc_h, ps_h;
   BatchView &v = B->v;
   for (int t = 0; t < n_toys; t++) {
@@ -348,8 +348,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.n_cell = sh.n_cell;
     T.S = sh.S;
     for (int k = 0; k < T.D; k++) T.exposure[k] = d.exposure[k];
-    // chunk sizes: at least 128 cells / 64 bins per chunk
-    const int cpc = std::max(128, (sh.n_cell + nch_f - 1) / nch_f);
+    // chunk sizes: at least 128 cells (a multiple of the hull group) / 64 bins per chunk
+    const int cpc = std::max(128, ((sh.n_cell + nch_f - 1) / nch_f + kGroup - 1) / kGroup * kGroup);
     T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
     const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
@@ -357,6 +357,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.cell_blocks = (sh.n_cell + kBlock - 1) / kBlock;
     T.cflag_blocks = (sh.n_cell + kCellBlock - 1) / kCellBlock;
     T.cflag_off = cflag_off;
+    T.ghull_off = ghull_off;
     T.cell_off = cell_off;
     T.win_off = win_off;
     T.cnt_off = cnt_off;
@@ -366,7 +367,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.nllp_off = nllp_off;
     T.gpart_off = gpart_off;
     T.pull_off = pull_off;
-    for (int b0 = 0; b0 < T.L; b0 += kTile)
+    for (int b0 = 0; b0 < T.L; b0 += kFoldTile)
       for (int c = 0; c < T.fold_chunks; c++)
         B->fold_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
     for (int c0 = 0; c0 < sh.n_cell; c0 += kTile)
@@ -389,6 +390,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     nllp_off += T.bin_blocks;
     gpart_off += T.cell_blocks;
     cflag_off += T.cflag_blocks;
+    ghull_off += (sh.n_true + kGroup - 1) / kGroup;
     pull_off += T.P;
     v.max_cells = std::max(v.max_cells, sh.n_cell);
     v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
@@ -414,6 +416,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.rec, (size_t)cell_off * kRecLen));
   HIP_TRY(B->alloc(&v.cflag, (size_t)cflag_off));
   HIP_TRY(B->alloc(&v.sup, (size_t)cell_off));
+  HIP_TRY(B->alloc(&v.ghull, (size_t)std::max<long long>(ghull_off, 1)));
   HIP_TRY(B->alloc(&v.pflag, (size_t)n_toys));
   if (v.has_2d) {
     HIP_TRY(B->alloc(&v.H, (size_t)win_off * GS_MAX_SPECIES));
@@ -538,15 +541,36 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
   for (const ToyDev &T : b->toys_h) n_cells = std::max(n_cells, T.cell_off + T.n_cell);
   std::vector<int2> sup((size_t)n_cells);
   HIP_TRY(hipMemcpy(sup.data(), b->v.sup, sizeof(int2) * (size_t)n_cells, hipMemcpyDeviceToHost));
-  long long fold = 0, adj = 0, full = 0;
-  for (const ToyDev &T : b->toys_h) full += (long long)T.L * T.n_cell;
+  long long fold = 0, adj = 0, full = 0, band = 0;
+  for (const ToyDev &T : b->toys_h) {
+    full += (long long)T.L * T.n_cell;
+    for (int i = 0; i < T.n_cell; i++) {
+      const int2 s = sup[T.cell_off + i];
+      const int x = std::max(s.x, T.lo), y = std::min(s.y, T.lo + T.L);
+      if (y > x) band += y - x;
+    }
+  }
+  // the 1-D fold evaluates every cell of the hull groups that meet its tile
+  // (partial groups padded to kGroup), plus the chunk's line cells, on all
+  // kFoldTile lanes
   for (const FoldItem &it : b->fold_h) {
     const ToyDev &T = b->toys_h[it.toy];
-    const int j0 = T.lo + it.bin0, j1 = T.lo + std::min(it.bin0 + kTile, T.L);
-    for (int i = it.cell0; i < it.cell1; i++) {
-      const int2 s = sup[T.cell_off + i];
-      if (!(s.y <= j0 || s.x >= j1)) fold += kTile;
+    const ShapeDev &Sh = b->shapes_h[T.shape];
+    const int j0 = T.lo + it.bin0, j1 = T.lo + std::min(it.bin0 + kFoldTile, T.L);
+    const int g_end = std::min(it.cell1, Sh.n_true);
+    long long cells = std::max(0, it.cell1 - std::max(it.cell0, Sh.n_true));
+    for (int g = it.cell0 / kGroup; g * kGroup < g_end; g++) {
+      int hx = 0x7fffffff, hy = -1;
+      for (int i = g * kGroup; i < std::min((g + 1) * kGroup, Sh.n_true); i++) {
+        const int2 s = sup[T.cell_off + i];
+        if (s.y > s.x) {
+          hx = std::min(hx, s.x);
+          hy = std::max(hy, s.y);
+        }
+      }
+      if (hx < j1 && hy > j0) cells += kGroup;
     }
+    fold += cells * kFoldTile;
   }
   for (const AdjItem &it : b->adj_h) {
     const ToyDev &T = b->toys_h[it.toy];
@@ -561,6 +585,7 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
   out[0] = fold;
   out[1] = adj;
   out[2] = full;
+  out[3] = band;
   return GS_OK;
 }
 

@@ -8,7 +8,10 @@
 
 namespace gs {
 
-constexpr int kTile = 64;       // bins (fold) or cells (adjoint) per tile: one per lane
+constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins per per-species fold tile
+constexpr int kFoldTile = 128;  // window bins per 1-D fold item: two per lane
+constexpr int kStage = 128;     // cell records staged in LDS per batch of the 1-D fold
+constexpr int kGroup = 16;      // grid cells per support hull
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
 constexpr int kBlock = 256;     // threads per reduction block
 constexpr int kGradLen = GS_MAX_PARAMS;
@@ -44,13 +47,15 @@ struct ToyDev {
   long long nllp_off;   // -ln L partials per bin block
   long long gpart_off;  // per cell block: gpart[(gpart_off + blk) * kGradLen + p]
   long long cflag_off;  // per k_cells block: cflag[cflag_off + blk]
+  long long ghull_off;  // per kGroup grid cells: union of their supports, ghull[ghull_off + g]
   long long pull_off;   // pull centres / widths [P]
   long long gam_off;    // 2-D: Gam[gam_off + b * K + k] = sum_d eps_d (1 - n/mu)
   long long psd_off;    // 2-D: P[psd_off + s * K + k], dP[(psd_off + s * K + k) * 3 + v]
   double exposure[GS_MAX_DATASETS];
 };
 
-// One workgroup of the fold: 64 window bins of one toy against a cell range.
+// One workgroup of the fold: kFoldTile window bins of one toy against a cell range
+// (the per-species fold splits it into two kTile halves).
 struct FoldItem {
   int toy, bin0, cell0, cell1, chunk;
 };
@@ -69,6 +74,7 @@ struct BatchView {
   double *rec;      // cell records
   uint32_t *cflag;  // per k_cells block: an invalid response was met
   int2 *sup;        // per cell: reco-bin support [x, y) (also in slot 6 of the record)
+  int2 *ghull;      // per kGroup grid cells: smallest x and largest y of their non-empty supports
   int max_cflag_blocks;
   double *fpart;    // fold partials (combined weight)
   double *fspart;   // fold partials per species

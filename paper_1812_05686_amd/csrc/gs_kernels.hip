@@ -153,7 +153,8 @@ __device__ __forceinline__ int2 get_support(const double *rc) { return *(const i
 __global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride, double log_cut,
                                                const uint8_t *__restrict__ active, double *__restrict__ rec,
-                                               int2 *__restrict__ sup, uint32_t *__restrict__ cflag) {
+                                               int2 *__restrict__ sup, int2 *__restrict__ ghull,
+                                               uint32_t *__restrict__ cflag) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, c
   const ShapeDev &Sh = shapes[T.shape];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool ok = true;
+  int hx = 0x7fffffff, hy = -1;  // this cell's contribution to its group's support hull
   if (i < Sh.n_cell) {
     const double *th = theta + (size_t)t * stride;
     Moments mo;
@@ -181,7 +183,17 @@ __global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, c
 #pragma unroll
     for (int q = 0; q < kRecLen; q++) rc[q] = r[q];
     sup[T.cell_off + i] = sp;
+    if (i < Sh.n_true && sp.y > sp.x) {
+      hx = sp.x;
+      hy = sp.y;
+    }
   }
+  // hull of each aligned group of kGroup grid cells (lines are not included)
+  for (int o = 1; o < kGroup; o <<= 1) {
+    hx = min(hx, __shfl_xor(hx, o, 64));
+    hy = max(hy, __shfl_xor(hy, o, 64));
+  }
+  if ((threadIdx.x & (kGroup - 1)) == 0 && i < Sh.n_true) ghull[T.ghull_off + i / kGroup] = make_int2(hx, hy);
   const int bad = __syncthreads_or(!ok);
   if (threadIdx.x == 0) cflag[T.cflag_off + blockIdx.x] = bad ? 1u : 0u;
 }
@@ -189,12 +201,12 @@ __global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, c
 hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
   dim3 grid(v.max_cflag_blocks, v.n_toys);
   hipLaunchKernelGGL(k_cells, grid, dim3(kCellBlock), 0, st, v.toys, v.shapes, theta, v.stride, v.log_cut, active,
-                     v.rec, v.sup, v.cflag);
+                     v.rec, v.sup, v.ghull, v.cflag);
   return hipGetLastError();
 }
 
 // -------------------------------------------------------------- k_fold ----
-// Response of cell record p at the lane's bin.
+// Response of a cell at one bin (record slots as written by cell_record).
 template <int FAM>
 __device__ __forceinline__ double pair_density(const double *__restrict__ p, double x, double Lh, double Ll,
                                                const double *ec) {
@@ -203,36 +215,238 @@ __device__ __forceinline__ double pair_density(const double *__restrict__ p, dou
   return exp_cw(gauss_exponent(p[0], p[1], p[2], x, z), ec);
 }
 
-// One-dimensional fold with the combined weight W_i = sum_s R_s w_si.  The
-// next cell's record is fetched (scalar loads) while the current one is
-// evaluated.
-struct Rec8 {
-  double v[kRecLen];
+// 1-D fold.  A workgroup owns kFoldTile window bins (lane l: bins l and
+// l + 64) and a range of cells.  The cell records it needs are staged
+// through LDS in batches of kStage cells; every lane of a wave reads the same
+// record (a broadcast), so the VALU only evaluates pairs.  The next batch is
+// fetched into registers while the current one is evaluated.  Only the 16-byte
+// parts of a record the pair loop reads are staged: {K, 1/th hi, lo, C hi,
+// lo, W} for gamma, {m, 1/s, c0, W} for the Gaussian families.
+template <int FAM>
+struct Stage {
+  static constexpr int kParts = FAM == kGammaPE ? 3 : 2;
+  static constexpr int kLen = 2 * kParts;  // doubles per staged record
 };
-__device__ __forceinline__ Rec8 load_rec(const double *__restrict__ p) {
-  Rec8 r;
-#pragma unroll
-  for (int q = 0; q < kRecLen; q++) r.v[q] = p[q];
-  return r;
-}
+
+struct Bin2 {
+  double x0, Lh0, Ll0, x1, Lh1, Ll1;
+};
 
 template <int FAM>
-__device__ __forceinline__ double fold_cells_1(const double *__restrict__ R, int c0, int c1, int j0, int j1, double x,
-                                               double Lh, double Ll, const double *ec) {
-  double acc = 0.0;
-  if (c0 >= c1) return acc;
-  Rec8 cur = load_rec(R + (size_t)c0 * kRecLen);
-  for (int i = c0; i < c1; i += kWaves) {
-    const Rec8 nxt = load_rec(R + (size_t)min(i + kWaves, c1 - 1) * kRecLen);
-    const int2 s = get_support(cur.v);
-    if (!(s.y <= j0 || s.x >= j1))  // wave-uniform: the cell reaches this tile
-      acc = __fma_rn(FAM == kGammaPE ? cur.v[5] : cur.v[3], pair_density<FAM>(cur.v, x, Lh, Ll, ec), acc);
-    cur = nxt;
-  }
-  return acc;
+__device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const Bin2 &bn, const double *ec, double &a0,
+                                           double &a1) {
+  const double W = FAM == kGammaPE ? p[5] : p[3];
+  a0 = __fma_rn(W, pair_density<FAM>(p, bn.x0, bn.Lh0, bn.Ll0, ec), a0);
+  a1 = __fma_rn(W, pair_density<FAM>(p, bn.x1, bn.Lh1, bn.Ll1, ec), a1);
 }
 
-// Per-species fold: grid cells add w_si r into species s < Sg, line cells into their own.
+// Cells wave, wave + kWaves, ... of a staged batch of nb cells.
+template <int FAM>
+__device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Bin2 &bn, const double *ec,
+                                           double &a0, double &a1) {
+  constexpr int L = Stage<FAM>::kLen;
+  int c = wave;
+  for (; c + kWaves < nb; c += 2 * kWaves) {
+    double p[L], q[L];
+#pragma unroll
+    for (int k = 0; k < L; k += 2) {
+      const double2 u = *(const double2 *)(srec + c * L + k), w = *(const double2 *)(srec + (c + kWaves) * L + k);
+      p[k] = u.x;
+      p[k + 1] = u.y;
+      q[k] = w.x;
+      q[k + 1] = w.y;
+    }
+    fold_pair2<FAM>(p, bn, ec, a0, a1);
+    fold_pair2<FAM>(q, bn, ec, a0, a1);
+  }
+  if (c < nb) {
+    double p[L];
+#pragma unroll
+    for (int k = 0; k < L; k += 2) {
+      const double2 u = *(const double2 *)(srec + c * L + k);
+      p[k] = u.x;
+      p[k + 1] = u.y;
+    }
+    fold_pair2<FAM>(p, bn, ec, a0, a1);
+  }
+}
+
+// All cells of [c_lo, c_hi) against the tile (block-uniform range; every
+// thread of the block calls this).  Staged part q of a batch is part q % P of
+// cell q / P, stored at srec[2q].
+template <int FAM>
+__device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_lo, int c_hi, double *srec, int wave,
+                                           const Bin2 &bn, const double *ec, double &a0, double &a1) {
+  constexpr int P = Stage<FAM>::kParts;
+  static_assert(kStage * P <= 2 * kWaves * 64, "two staged parts per thread");
+  const int tid = threadIdx.x;
+  double2 f0 = make_double2(0.0, 0.0), f1 = make_double2(0.0, 0.0);
+  auto fetch = [&](int base) {
+    const int n = min(kStage, c_hi - base) * P;
+    const int q0 = tid, q1 = tid + kWaves * 64;
+    if (q0 < n) f0 = *(const double2 *)(R + (size_t)(base + q0 / P) * kRecLen + 2 * (q0 % P));
+    if (q1 < n) f1 = *(const double2 *)(R + (size_t)(base + q1 / P) * kRecLen + 2 * (q1 % P));
+  };
+  if (c_lo < c_hi) fetch(c_lo);
+  for (int base = c_lo; base < c_hi; base += kStage) {
+    const int nb = min(kStage, c_hi - base);
+    __syncthreads();  // every wave is done with the previous batch
+    if (tid < nb * P) ((double2 *)srec)[tid] = f0;
+    if (tid + kWaves * 64 < nb * P) ((double2 *)srec)[tid + kWaves * 64] = f1;
+    __syncthreads();
+    if (base + kStage < c_hi) fetch(base + kStage);
+    fold_batch<FAM>(srec, nb, wave, bn, ec, a0, a1);
+  }
+}
+
+// Grid cells of a chunk whose support can reach window bins [j0, j1): the
+// span of the kGroup-cell groups whose hull meets the tile (block-uniform).
+__device__ __forceinline__ int2 grid_range(const int2 *__restrict__ hull, int c0, int c1, int j0, int j1, int *rng) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int first = 0x7fffffff, last = -1;
+  for (int g = c0 / kGroup + (int)threadIdx.x; g * kGroup < c1; g += kWaves * 64) {
+    const int2 h = hull[g];
+    if (h.x < j1 && h.y > j0) {
+      first = min(first, g);
+      last = max(last, g);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    first = min(first, __shfl_xor(first, o, 64));
+    last = max(last, __shfl_xor(last, o, 64));
+  }
+  __syncthreads();  // rng may still be read by a previous call
+  if (lane == 0) {
+    rng[wave] = first;
+    rng[kWaves + wave] = last;
+  }
+  __syncthreads();
+  first = min(min(rng[0], rng[1]), min(rng[2], rng[3]));
+  last = max(max(rng[kWaves], rng[kWaves + 1]), max(rng[kWaves + 2], rng[kWaves + 3]));
+  if (last < 0) return make_int2(0, 0);  // empty (first is never used past INT_MAX)
+  return make_int2(max(c0, first * kGroup), min(c1, (last + 1) * kGroup));
+}
+
+// Compacts, in increasing order, the groups g in [g0, g1) (at most one per
+// thread) whose hull meets window bins [j0, j1) into list[]; returns their
+// number (block-uniform; every thread of the block calls this).
+__device__ __forceinline__ int group_list(const int2 *__restrict__ hull, int g0, int g1, int j0, int j1, int *list,
+                                          int *cnt) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = g0 + (int)threadIdx.x;
+  bool hit = false;
+  if (g < g1) {
+    const int2 h = hull[g];
+    hit = h.x < j1 && h.y > j0;
+  }
+  const unsigned long long m = __ballot(hit);
+  __syncthreads();  // list and cnt of a previous call are no longer read
+  if (lane == 0) cnt[wave] = __popcll(m);
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wave; w++) off += cnt[w];
+  if (hit) list[off + __popcll(m & ((1ull << lane) - 1ull))] = g;
+  __syncthreads();
+  return cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+// All cells of the listed groups, clipped to [c_lo, c_hi), against the tile.
+// A batch holds kStage / kGroup groups; cells past the clip are staged as
+// zero records (weight 0).
+template <int FAM>
+__device__ __forceinline__ void fold_groups(const double *__restrict__ R, const int *list, int n_list, int c_lo,
+                                            int c_hi, double *srec, int wave, const Bin2 &bn, const double *ec,
+                                            double &a0, double &a1) {
+  constexpr int P = Stage<FAM>::kParts;
+  constexpr int kGPB = kStage / kGroup;
+  const int tid = threadIdx.x;
+  double2 f0, f1;
+  auto part = [&](int bi, int q) {
+    const int cs = q / P, gs = cs / kGroup, li = bi * kGPB + gs;
+    const int cell = li < n_list ? list[li] * kGroup + cs % kGroup : -1;
+    if (q < kStage * P && cell >= c_lo && cell < c_hi)
+      return *(const double2 *)(R + (size_t)cell * kRecLen + 2 * (q % P));
+    return make_double2(0.0, 0.0);
+  };
+  const int n_batch = (n_list + kGPB - 1) / kGPB;
+  if (n_batch > 0) {
+    f0 = part(0, tid);
+    f1 = part(0, tid + kWaves * 64);
+  }
+  for (int bi = 0; bi < n_batch; bi++) {
+    const int nb = min(kGPB, n_list - bi * kGPB) * kGroup;
+    __syncthreads();  // every wave is done with the previous batch
+    if (tid < nb * P) ((double2 *)srec)[tid] = f0;
+    if (tid + kWaves * 64 < nb * P) ((double2 *)srec)[tid + kWaves * 64] = f1;
+    __syncthreads();
+    if (bi + 1 < n_batch) {
+      f0 = part(bi + 1, tid);
+      f1 = part(bi + 1, tid + kWaves * 64);
+    }
+    fold_batch<FAM>(srec, nb, wave, bn, ec, a0, a1);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ items, int n_items,
+                                               const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ rec, const int2 *__restrict__ ghull,
+                                               const uint8_t *__restrict__ active, double *__restrict__ out) {
+  __shared__ __align__(16) double srec[kStage * 6];
+  __shared__ double red[kWaves * 2 * 64];
+  __shared__ int glist[kWaves * 64];
+  __shared__ int gcnt[kWaves];
+  const double *ec = kExpC;
+  const int w_item = xcd_item(blockIdx.x, n_items);
+  if (w_item >= n_items) return;
+  const FoldItem it = items[w_item];
+  if (active && !active[it.toy]) return;
+  const ToyDev &T = toys[it.toy];
+  if (T.two_d) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b0 = it.bin0 + lane, b1 = b0 + 64;
+  const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
+  const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
+  const Bin2 bn{bp0[0], bp0[2], bp0[3], bp1[0], bp1[2], bp1[3]};
+  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile, T.L);
+  const double *R = rec + T.cell_off * kRecLen;
+  // grid cells: the groups whose hull meets the tile, up to kWaves * 64 groups per pass
+  const int g_end = min(it.cell1, Sh.n_true);
+  const int l_lo = max(it.cell0, Sh.n_true), l_hi = it.cell1;  // line cells: few, all evaluated
+  const bool gamma = Sh.family == kGammaPE;
+  double a0 = 0.0, a1 = 0.0;
+  for (int gb = it.cell0 / kGroup; gb * kGroup < g_end; gb += kWaves * 64) {
+    const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
+                             glist, gcnt);
+    if (gamma)
+      fold_groups<kGammaPE>(R, glist, n, it.cell0, g_end, srec, wave, bn, ec, a0, a1);
+    else
+      fold_groups<kGaussE>(R, glist, n, it.cell0, g_end, srec, wave, bn, ec, a0, a1);
+  }
+  if (gamma) {
+    fold_range<kGammaPE>(R, l_lo, l_hi, srec, wave, bn, ec, a0, a1);
+    if (!(bn.x0 > 0.0)) a0 = 0.0;  // outside the gamma support
+    if (!(bn.x1 > 0.0)) a1 = 0.0;
+  } else {
+    fold_range<kGaussE>(R, l_lo, l_hi, srec, wave, bn, ec, a0, a1);
+  }
+  red[(wave * 2 + 0) * 64 + lane] = a0;
+  red[(wave * 2 + 1) * 64 + lane] = a1;
+  __syncthreads();
+  if (wave < 2) {  // wave h sums bin half h over the 4 waves in a fixed order
+    const int b = it.bin0 + wave * 64 + lane;
+    if (b < T.L && b < it.bin0 + kFoldTile) {
+      double s = red[wave * 64 + lane];
+      for (int q = 1; q < kWaves; q++) s += red[(q * 2 + wave) * 64 + lane];
+      out[T.fpart_off + (long long)it.chunk * T.L + b] = s;
+    }
+  }
+}
+
+// Per-species fold (plain path and the secondary-observable model): grid
+// cells add w_si r into species s < Sg, line cells into their own.  One
+// workgroup per kTile-bin half of a fold item; cells are interleaved over the
+// waves and read with scalar loads.
 template <int FAM>
 __device__ __forceinline__ void fold_cells_s(const double *__restrict__ R, const double *__restrict__ wc, int Sg,
                                              int n_true, int c0, int c1, int j0, int j1, double x, double Lh,
@@ -256,106 +470,65 @@ __device__ __forceinline__ void fold_cells_s(const double *__restrict__ R, const
   }
 }
 
-template <bool PS>
-__global__ __launch_bounds__(256) void k_fold(const FoldItem *__restrict__ items, int n_items,
-                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                              const double *__restrict__ rec, const int2 *__restrict__ sup, int mode,
-                                              const uint8_t *__restrict__ active, double *__restrict__ out) {
-  __shared__ double red[PS ? kWaves * kTile * GS_MAX_SPECIES : kWaves * kTile];
+__global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ items, int n_items,
+                                                const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                                const double *__restrict__ rec, const int2 *__restrict__ ghull,
+                                                int mode, const uint8_t *__restrict__ active,
+                                                double *__restrict__ out) {
+  __shared__ double red[kWaves * kTile * GS_MAX_SPECIES];
   __shared__ int rng[2 * kWaves];
   const double *ec = kExpC;
-  const int w_item = xcd_item(blockIdx.x, n_items);
-  if (w_item >= n_items) return;
-  const FoldItem it = items[w_item];
+  const int w_half = xcd_item(blockIdx.x, 2 * n_items);
+  if (w_half >= 2 * n_items) return;
+  const FoldItem it = items[w_half >> 1];
   if (active && !active[it.toy]) return;
-  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const ToyDev &T = toys[it.toy];
   if (mode >= 0 && T.two_d != mode) return;
+  const int bin0 = it.bin0 + (w_half & 1) * kTile;
+  if (bin0 >= T.L) return;
   const ShapeDev &Sh = shapes[T.shape];
-  const int b = it.bin0 + lane;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b = bin0 + lane;
   const bool valid = b < T.L;
-  const int j = T.lo + (valid ? b : T.L - 1);
-  const double *bn = Sh.bins + (size_t)j * kBinLen;
+  const double *bn = Sh.bins + (size_t)(T.lo + (valid ? b : T.L - 1)) * kBinLen;
   const double x = bn[0], Lh = bn[2], Ll = bn[3];
-  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kTile, T.L);
+  const int j0 = T.lo + bin0, j1 = T.lo + min(bin0 + kTile, T.L);
   const double *R = rec + T.cell_off * kRecLen;
   const bool gamma = Sh.family == kGammaPE;
   const bool zero = gamma && !(x > 0.0);  // outside the gamma support
-  // first and last grid cell of the chunk whose support reaches this bin tile;
-  // line cells (after the grid) are walked separately below
-  const int g_end = min(it.cell1, Sh.n_true), l_begin = max(it.cell0, Sh.n_true);
-  int first = 0x7fffffff, last = -1;
-  for (int i = it.cell0 + (int)threadIdx.x; i < g_end; i += kWaves * 64) {
-    const int2 s = sup[T.cell_off + i];
-    if (!(s.y <= j0 || s.x >= j1)) {
-      first = min(first, i);
-      last = max(last, i);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    first = min(first, __shfl_xor(first, o, 64));
-    last = max(last, __shfl_xor(last, o, 64));
-  }
-  if (lane == 0) {
-    rng[wave] = first;
-    rng[kWaves + wave] = last;
-  }
-  __syncthreads();
-  first = min(min(rng[0], rng[1]), min(rng[2], rng[3]));
-  last = max(max(rng[kWaves], rng[kWaves + 1]), max(rng[kWaves + 2], rng[kWaves + 3]));
-  // no cell of the chunk reaches the tile: empty range (never first + wave past INT_MAX)
-  const bool any = last >= 0;
-  first = any ? wave_uniform(first) : 0;
-  const int c_end = any ? wave_uniform(last) + 1 : 0;
-  if (!PS) {
-    double acc;
-    if (gamma)
-      acc = fold_cells_1<kGammaPE>(R, first + wave, c_end, j0, j1, x, Lh, Ll, ec) +
-            fold_cells_1<kGammaPE>(R, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec);
-    else
-      acc = fold_cells_1<kGaussE>(R, first + wave, c_end, j0, j1, x, Lh, Ll, ec) +
-            fold_cells_1<kGaussE>(R, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec);
-    red[wave * kTile + lane] = zero ? 0.0 : acc;
-    __syncthreads();
-    if (wave == 0 && valid) {
-      double s = red[lane];
-      for (int q = 1; q < kWaves; q++) s += red[q * kTile + lane];
-      out[T.fpart_off + (long long)it.chunk * T.L + b] = s;
-    }
+  const int2 gr = grid_range(ghull + T.ghull_off, it.cell0, min(it.cell1, Sh.n_true), j0, j1, rng);
+  const int first = wave_uniform(gr.x), c_end = wave_uniform(gr.y), l_begin = max(it.cell0, Sh.n_true);
+  double acc[GS_MAX_SPECIES];
+#pragma unroll
+  for (int q = 0; q < GS_MAX_SPECIES; q++) acc[q] = 0.0;
+  if (gamma) {
+    fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
+    fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
   } else {
-    double acc[GS_MAX_SPECIES];
+    fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
+    fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
+  }
 #pragma unroll
-    for (int q = 0; q < GS_MAX_SPECIES; q++) acc[q] = 0.0;
-    if (gamma) {
-      fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
-      fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
-    } else {
-      fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
-      fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
-    }
-#pragma unroll
-    for (int q = 0; q < GS_MAX_SPECIES; q++) red[(wave * GS_MAX_SPECIES + q) * kTile + lane] = zero ? 0.0 : acc[q];
-    __syncthreads();
-    if (wave == 0 && valid) {
-      double *o = out + T.fs_off + ((long long)it.chunk * T.L + b) * T.S;
-      for (int q = 0; q < T.S; q++) {
-        double s = red[q * kTile + lane];
-        for (int ww = 1; ww < kWaves; ww++) s += red[(ww * GS_MAX_SPECIES + q) * kTile + lane];
-        o[q] = s;
-      }
+  for (int q = 0; q < GS_MAX_SPECIES; q++) red[(wave * GS_MAX_SPECIES + q) * kTile + lane] = zero ? 0.0 : acc[q];
+  __syncthreads();
+  if (wave == 0 && valid) {
+    double *o = out + T.fs_off + ((long long)it.chunk * T.L + b) * T.S;
+    for (int q = 0; q < T.S; q++) {
+      double s = red[q * kTile + lane];
+      for (int ww = 1; ww < kWaves; ww++) s += red[(ww * GS_MAX_SPECIES + q) * kTile + lane];
+      o[q] = s;
     }
   }
 }
 
 hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st) {
   if (v.n_fold_items == 0) return hipSuccess;
-  const dim3 grid(xcd_grid(v.n_fold_items));
   if (per_species)
-    hipLaunchKernelGGL(k_fold<true>, grid, dim3(kWaves * 64), 0, st, v.fold_items, v.n_fold_items, v.toys, v.shapes,
-                       v.rec, v.sup, mode, active, v.fspart);
+    hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(2 * v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
+                       v.n_fold_items, v.toys, v.shapes, v.rec, v.ghull, mode, active, v.fspart);
   else
-    hipLaunchKernelGGL(k_fold<false>, grid, dim3(kWaves * 64), 0, st, v.fold_items, v.n_fold_items, v.toys, v.shapes,
-                       v.rec, v.sup, mode, active, v.fpart);
+    hipLaunchKernelGGL(k_fold1, dim3(xcd_grid(v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
+                       v.n_fold_items, v.toys, v.shapes, v.rec, v.ghull, active, v.fpart);
   return hipGetLastError();
 }
 
