@@ -230,7 +230,7 @@ gs_status gs_batch_set_profiling(gs_batch *b, int32_t on);
  * events; reset != 0 clears the accumulators afterwards. */
 gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset);
 /* Mesh pairs (window bin x cell) of the most recent evaluation of the batch,
- * host array of 4: out[0] pairs the 1-D fold evaluated (128 lanes per visited
+ * host array of 4: out[0] pairs the 1-D fold evaluated (64 bins per visited
  * cell and bin tile, idle lanes of a partial tile included), out[1] pairs the
  * adjoint evaluated, out[2] the full mesh sum_t (window bins x cells), out[3]
  * the banded mesh: pairs whose bin lies in the cell's support, i.e. the

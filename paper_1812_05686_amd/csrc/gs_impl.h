@@ -9,7 +9,7 @@
 namespace gs {
 
 constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins per per-species fold tile
-constexpr int kFoldTile = 128;  // window bins per 1-D fold item: two per lane
+constexpr int kFoldTile = 64;   // window bins per fold item (1-D fold: two per lane of each half-wave)
 constexpr int kStage = 128;     // cell records staged in LDS per batch of the 1-D fold
 constexpr int kGroup = 16;      // grid cells per support hull
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
@@ -54,8 +54,7 @@ struct ToyDev {
   double exposure[GS_MAX_DATASETS];
 };
 
-// One workgroup of the fold: kFoldTile window bins of one toy against a cell range
-// (the per-species fold splits it into two kTile halves).
+// One workgroup of the fold: kFoldTile window bins of one toy against a cell range.
 struct FoldItem {
   int toy, bin0, cell0, cell1, chunk;
 };

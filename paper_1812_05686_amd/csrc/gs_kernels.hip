@@ -215,13 +215,15 @@ __device__ __forceinline__ double pair_density(const double *__restrict__ p, dou
   return exp_cw(gauss_exponent(p[0], p[1], p[2], x, z), ec);
 }
 
-// 1-D fold.  A workgroup owns kFoldTile window bins (lane l: bins l and
-// l + 64) and a range of cells.  The cell records it needs are staged
-// through LDS in batches of kStage cells; every lane of a wave reads the same
-// record (a broadcast), so the VALU only evaluates pairs.  The next batch is
-// fetched into registers while the current one is evaluated.  Only the 16-byte
-// parts of a record the pair loop reads are staged: {K, 1/th hi, lo, C hi,
-// lo, W} for gamma, {m, 1/s, c0, W} for the Gaussian families.
+// 1-D fold.  A workgroup owns kFoldTile = 64 window bins and a set of cells.
+// Each half-wave covers the whole tile, two bins per lane (bins j and j + 32
+// for lane j of the half), and the two halves take alternate cells, so one
+// LDS read of a record feeds two pairs.  The cell records are staged through
+// LDS in batches of kStage cells; the next batch is fetched into registers
+// while the current one is evaluated, and the VALU only evaluates pairs.
+// Only the 16-byte parts of a record the pair loop reads are staged:
+// {K, 1/th hi, lo, C hi, lo, W} for gamma, {m, 1/s, c0, W} for the Gaussian
+// families.
 template <int FAM>
 struct Stage {
   static constexpr int kParts = FAM == kGammaPE ? 3 : 2;
@@ -240,32 +242,38 @@ __device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const B
   a1 = __fma_rn(W, pair_density<FAM>(p, bn.x1, bn.Lh1, bn.Ll1, ec), a1);
 }
 
-// Cells wave, wave + kWaves, ... of a staged batch of nb cells.
+// Cell pairs wave, wave + kWaves, ... of a staged batch of nb cells (nb even:
+// an odd batch is padded with a zero record); half h of the wave takes the
+// cell 2k + h of pair k.
 template <int FAM>
 __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Bin2 &bn, const double *ec,
                                            double &a0, double &a1) {
   constexpr int L = Stage<FAM>::kLen;
-  int c = wave;
-  for (; c + kWaves < nb; c += 2 * kWaves) {
+  const int h = (threadIdx.x >> 5) & 1;
+  const int np = nb >> 1;
+  const double *base = srec + h * L;
+  int k = wave;
+  for (; k + kWaves < np; k += 2 * kWaves) {
     double p[L], q[L];
 #pragma unroll
-    for (int k = 0; k < L; k += 2) {
-      const double2 u = *(const double2 *)(srec + c * L + k), w = *(const double2 *)(srec + (c + kWaves) * L + k);
-      p[k] = u.x;
-      p[k + 1] = u.y;
-      q[k] = w.x;
-      q[k + 1] = w.y;
+    for (int e = 0; e < L; e += 2) {
+      const double2 u = *(const double2 *)(base + 2 * k * L + e);
+      const double2 w = *(const double2 *)(base + 2 * (k + kWaves) * L + e);
+      p[e] = u.x;
+      p[e + 1] = u.y;
+      q[e] = w.x;
+      q[e + 1] = w.y;
     }
     fold_pair2<FAM>(p, bn, ec, a0, a1);
     fold_pair2<FAM>(q, bn, ec, a0, a1);
   }
-  if (c < nb) {
+  if (k < np) {
     double p[L];
 #pragma unroll
-    for (int k = 0; k < L; k += 2) {
-      const double2 u = *(const double2 *)(srec + c * L + k);
-      p[k] = u.x;
-      p[k + 1] = u.y;
+    for (int e = 0; e < L; e += 2) {
+      const double2 u = *(const double2 *)(base + 2 * k * L + e);
+      p[e] = u.x;
+      p[e + 1] = u.y;
     }
     fold_pair2<FAM>(p, bn, ec, a0, a1);
   }
@@ -284,12 +292,12 @@ __device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_l
   auto fetch = [&](int base) {
     const int n = min(kStage, c_hi - base) * P;
     const int q0 = tid, q1 = tid + kWaves * 64;
-    if (q0 < n) f0 = *(const double2 *)(R + (size_t)(base + q0 / P) * kRecLen + 2 * (q0 % P));
-    if (q1 < n) f1 = *(const double2 *)(R + (size_t)(base + q1 / P) * kRecLen + 2 * (q1 % P));
+    f0 = q0 < n ? *(const double2 *)(R + (size_t)(base + q0 / P) * kRecLen + 2 * (q0 % P)) : make_double2(0.0, 0.0);
+    f1 = q1 < n ? *(const double2 *)(R + (size_t)(base + q1 / P) * kRecLen + 2 * (q1 % P)) : make_double2(0.0, 0.0);
   };
   if (c_lo < c_hi) fetch(c_lo);
   for (int base = c_lo; base < c_hi; base += kStage) {
-    const int nb = min(kStage, c_hi - base);
+    const int nb = (min(kStage, c_hi - base) + 1) & ~1;  // padded to whole cell pairs
     __syncthreads();  // every wave is done with the previous batch
     if (tid < nb * P) ((double2 *)srec)[tid] = f0;
     if (tid + kWaves * 64 < nb * P) ((double2 *)srec)[tid + kWaves * 64] = f1;
@@ -404,7 +412,7 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   if (T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int b0 = it.bin0 + lane, b1 = b0 + 64;
+  const int b0 = it.bin0 + (lane & 31), b1 = b0 + 32;
   const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
   const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
   const Bin2 bn{bp0[0], bp0[2], bp0[3], bp1[0], bp1[2], bp1[3]};
@@ -433,11 +441,12 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   red[(wave * 2 + 0) * 64 + lane] = a0;
   red[(wave * 2 + 1) * 64 + lane] = a1;
   __syncthreads();
-  if (wave < 2) {  // wave h sums bin half h over the 4 waves in a fixed order
-    const int b = it.bin0 + wave * 64 + lane;
-    if (b < T.L && b < it.bin0 + kFoldTile) {
-      double s = red[wave * 64 + lane];
-      for (int q = 1; q < kWaves; q++) s += red[(q * 2 + wave) * 64 + lane];
+  if (wave == 0) {  // lane o: bin o of the tile, summed over waves and half-waves in a fixed order
+    const int sh = lane >> 5, j = lane & 31;
+    const int b = it.bin0 + lane;
+    if (b < T.L) {
+      double s = 0.0;
+      for (int q = 0; q < kWaves; q++) s += red[(q * 2 + sh) * 64 + j] + red[(q * 2 + sh) * 64 + 32 + j];
       out[T.fpart_off + (long long)it.chunk * T.L + b] = s;
     }
   }
@@ -445,7 +454,7 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
 
 // Per-species fold (plain path and the secondary-observable model): grid
 // cells add w_si r into species s < Sg, line cells into their own.  One
-// workgroup per kTile-bin half of a fold item; cells are interleaved over the
+// workgroup per fold item, one bin per lane; cells are interleaved over the
 // waves and read with scalar loads.
 template <int FAM>
 __device__ __forceinline__ void fold_cells_s(const double *__restrict__ R, const double *__restrict__ wc, int Sg,
@@ -478,14 +487,13 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   __shared__ double red[kWaves * kTile * GS_MAX_SPECIES];
   __shared__ int rng[2 * kWaves];
   const double *ec = kExpC;
-  const int w_half = xcd_item(blockIdx.x, 2 * n_items);
-  if (w_half >= 2 * n_items) return;
-  const FoldItem it = items[w_half >> 1];
+  const int w_item = xcd_item(blockIdx.x, n_items);
+  if (w_item >= n_items) return;
+  const FoldItem it = items[w_item];
   if (active && !active[it.toy]) return;
   const ToyDev &T = toys[it.toy];
   if (mode >= 0 && T.two_d != mode) return;
-  const int bin0 = it.bin0 + (w_half & 1) * kTile;
-  if (bin0 >= T.L) return;
+  const int bin0 = it.bin0;
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int b = bin0 + lane;
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
 hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st) {
   if (v.n_fold_items == 0) return hipSuccess;
   if (per_species)
-    hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(2 * v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
+    hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
                        v.n_fold_items, v.toys, v.shapes, v.rec, v.ghull, mode, active, v.fspart);
   else
     hipLaunchKernelGGL(k_fold1, dim3(xcd_grid(v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
