@@ -1,15 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the fold likelihood hot path on one MI355X.
 
-Workload: the Borexino-scale model (12 species: 4 lines, 6 betas, 2 exponentials; 4000
-true cells of 0.75 keV plus 4 lines; 900 reco bins of 1.6 pe; gamma response with light
-yield, Birks quenching and resolution a, b, c; 17 parameters, 3 pulls).  One step is one
-batched -ln L + gradient evaluation (cells, fold, Poisson reduction, adjoint, gradient)
-of B pseudo-experiments of that model, each with its own data and parameters, with every
-input already resident in device memory.  value = B * steps / wall time.
+Workload: 4096 pseudo-experiments of the Borexino-scale model (12 species: 4 lines, 6
+betas, 2 exponentials; 4000 true cells of 0.75 keV plus 4 lines; 900 reco bins of 1.6 pe;
+gamma response with light yield, Birks quenching and resolution a, b, c; 17 parameters,
+3 pulls), each with its own Poisson data, rates drawn +-20% around nominal and its own fit
+window of 200-900 bins.  One step is one batched -ln L + gradient evaluation of all toys
+(cells, fold, Poisson reduction, adjoint, gradient) with every input already resident in
+device memory; value = toys * steps / wall time.
 
-Also reported: the dominant kernel against the FP64 vector roofline (timed live with HIP
-events on its stream), single-evaluation latency, single fits with the adjoint gradient
+Also reported: toy fits per second (device BFGS over the same toys in captured graphs),
+the dominant kernel against the FP64 vector roofline (timed live with HIP events on its
+stream), single-evaluation latency, one Borexino-scale fit with the adjoint gradient
 versus central finite differences, and the CPU oracle on the host cores (sampled).
 """
 import argparse
@@ -68,10 +70,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--toys", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fits", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -80,12 +84,22 @@ def main():
 
     import torch
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration, "ok": bool(dst[-1].item() == n - 1)}))
+        return
+
     import gsgen
     import paper_1812_05686_amd as gs
 
     base = gsgen.config1()
-    toys = gsgen.config3(args.batch, base=base, full_window=True)
-    log(f"bench: {len(toys)} pseudo-experiments of the Borexino-scale model")
+    toys = gsgen.config3(args.toys, base=base)
+    log(f"bench: {len(toys)} pseudo-experiments of the Borexino-scale model, ragged windows")
     batch = gs.Batch(toys)
     stride = batch.stride
     theta = torch.tensor(np.stack([t.theta_true for t in toys]), dtype=torch.float64, device="cuda")
@@ -150,6 +164,24 @@ def main():
     torch.cuda.synchronize()
     single_us = (time.perf_counter() - ta) * 1e6 / reps
 
+    toy_fits = None
+    if not args.no_fits:
+        th0 = torch.tensor(np.stack([t.theta0 for t in toys]), dtype=torch.float64, device="cuda")
+        free = batch.free_masks(toys)
+        batch.fit(th0, base.fd_scale, free=free)  # warm: builds the captured graph
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = batch.fit(th0, base.fd_scale, free=free)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ta
+        stt = r["status"].cpu().numpy()
+        it = r["iters"].cpu().numpy()
+        toy_fits = {"fits_per_s": round(len(toys) / el, 2), "seconds": round(el, 4), "toys": len(toys),
+                    "fixed_rates": int(sum(int((~t.free).sum()) for t in toys)),
+                    "converged": int(np.sum(stt & 32 != 0)), "mean_iters": round(float(it.mean()), 2),
+                    "max_iters": int(it.max())}
+        log(f"bench: toy fits {toy_fits}")
+
     fits = None
     if not args.no_fits:
         model = gs.Model(base)
@@ -182,12 +214,14 @@ def main():
     out = {"metric": METRIC, "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "c1 Borexino-scale: 12 species, 4000+4 true cells x 900 reco bins, gamma "
-                                  "response, 17 params; batch of pseudo-experiments per step",
-                      "batch": len(toys), "pairs_per_eval": pairs // len(toys)},
-           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity,
+           "config": {"workload": "4096 pseudo-experiments of the Borexino-scale model (12 species, 4000+4 "
+                                  "true cells, 900 reco bins, gamma response, 17 params), own rates and "
+                                  "200-900-bin windows; one batched -lnL+gradient per step",
+                      "toys": len(toys), "mean_window_bins": round(float(np.mean([t.win_hi - t.win_lo for t in toys])), 1),
+                      "full_mesh_pairs_per_step": pairs},
+           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "toy_fits": toy_fits,
            "single_eval": {"us_per_eval": round(single_us, 2), "evals_per_s": round(1e6 / single_us, 1)},
-           "single_fits": fits}
+           "single_fit_borexino_scale": fits}
     print(json.dumps(out))
 
 

@@ -62,6 +62,7 @@ class Model:
     psd_edges: np.ndarray | None = None   # [n_psd + 1]
     psd_mix: np.ndarray | None = None     # [S, 5] = (w1, mean1, sigma1, mean2, sigma2)
     species: list = field(default_factory=list)
+    free: np.ndarray | None = None        # [P] bool, parameters a fit may move (None: all)
 
     @property
     def n_species(self) -> int:
@@ -85,6 +86,10 @@ class Model:
 
     def replace(self, **kw) -> "Model":
         return dataclasses.replace(self, **kw)
+
+    def free_mask(self) -> np.ndarray:
+        """[P] uint8: 1 for parameters a fit may move."""
+        return np.ones(self.n_params, np.uint8) if self.free is None else self.free.astype(np.uint8)
 
 
 def _rng(config: int, stream: int, toy: int = 0) -> np.random.Generator:
@@ -299,14 +304,68 @@ def config2() -> Model:
     return m
 
 
+def window_free_params(jac_win: np.ndarray, mu_win: np.ndarray, nominal: np.ndarray, pull_sigma: np.ndarray,
+                       max_rel: float = 0.5) -> np.ndarray:
+    """Which parameters a fit on this window can determine.
+
+    Rates are unbounded and the resolution only has to stay positive, so a parameter the
+    window barely constrains (a rate the window hardly sees; b against c^2 over a narrow
+    energy range) drifts until some bin's expectation or some cell's width reaches zero:
+    the minimum then lies on the edge of the domain, where a quasi-Newton fit cannot
+    converge.  From the Poisson Fisher information at the nominal point (plus the pull
+    terms), the parameter whose marginal sigma / |nominal| is largest is fixed while that
+    ratio exceeds max_rel.  jac_win: [L, P] d mu / d theta of the window bins; mu_win: [L]."""
+    P = len(nominal)
+    free = np.ones(P, bool)
+    w = 1.0 / np.maximum(mu_win, 1e-300)
+    pull = np.where(pull_sigma > 0, 1.0 / np.where(pull_sigma > 0, pull_sigma, 1.0) ** 2, 0.0)
+    while free.any():
+        idx = np.nonzero(free)[0]
+        A = jac_win[:, idx]
+        fisher = (A * w[:, None]).T @ A + np.diag(pull[idx])
+        try:
+            cov = np.linalg.inv(fisher)
+            rel = np.sqrt(np.maximum(np.diag(cov), 0.0)) / np.abs(nominal[idx])
+            rel[~np.isfinite(rel)] = np.inf
+        except np.linalg.LinAlgError:
+            rel = 1.0 / np.maximum(np.diag(fisher), 1e-300)
+        k = int(np.argmax(rel))
+        if rel[k] <= max_rel:
+            break
+        free[idx[k]] = False
+    return free
+
+
+def nominal_jacobian(model: Model) -> tuple[np.ndarray, np.ndarray]:
+    """Nature's expected 1-D counts mu [n_reco] at the nominal point and d mu / d theta
+    [n_reco, S + n_resp] (rates exactly; response parameters by central differences of
+    the nature histogram, relative step 1e-4)."""
+    S = model.n_species
+    th = model.theta_true
+    nr = 2 if model.family == GAUSS_E else 5
+    hist = nature_species_hist(model, th[S:S + nr])
+    mu = hist @ th[:S]
+    jac = np.zeros((model.n_reco, S + nr))
+    jac[:, :S] = hist
+    for q in range(nr):
+        h = 1e-4 * abs(th[S + q])
+        rp, rm = th[S:S + nr].copy(), th[S:S + nr].copy()
+        rp[q] += h
+        rm[q] -= h
+        jac[:, S + q] = (nature_species_hist(model, rp) @ th[:S] - nature_species_hist(model, rm) @ th[:S]) / (2 * h)
+    return mu, jac
+
+
 def config3(n_toys: int = 4096, base: Model | None = None, full_window: bool = False) -> list[Model]:
     """Toys of config 1: rates drawn +-20% uniform around nominal, response at nominal,
     own contiguous window of L ~ U{200..900} bins starting at lo ~ U{0..900-L} (or the full
-    900-bin window); fits start at the config-1 nominal point.  The spectra and binning
-    arrays are shared objects."""
+    900-bin window); fits start at the config-1 nominal point.  Parameters the window cannot
+    determine are fixed at the start value (`free`, see `window_free_params`).  The spectra
+    and binning arrays are shared objects."""
     base = config1() if base is None else base
     S = base.n_species
     hist = nature_species_hist(base, base.theta_true[S:])
+    mu_nom, jac = nominal_jacobian(base)
     toys = []
     for t in range(n_toys):
         g = _rng(3, 1, t)
@@ -317,8 +376,9 @@ def config3(n_toys: int = 4096, base: Model | None = None, full_window: bool = F
         if full_window:
             lo, L = 0, base.n_reco
         counts = draw_counts(nature_expected(base, th, hist), _rng(3, 0, t))
+        free = window_free_params(jac[lo:lo + L], mu_nom[lo:lo + L], base.theta_true, base.pull_sigma)
         toys.append(base.replace(name=f"c3/{t}", counts=counts, win_lo=lo, win_hi=lo + L,
-                                 theta_true=th, theta0=base.theta_true.copy()))
+                                 theta_true=th, theta0=base.theta_true.copy(), free=free))
     return toys
 
 

@@ -307,9 +307,22 @@ class Batch:
                "gs_batch_kernel_times")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
+    def free_masks(self, models, device="cuda"):
+        """uint8 [n, stride] device tensor of the models' free-parameter masks (padding fixed)."""
+        import torch
+        f = np.zeros((self.n, self.stride), np.uint8)
+        for t, m in enumerate(models):
+            fm = m.free_mask()
+            f[t, : len(fm)] = fm
+        return torch.tensor(f, device=device)
+
     def fit(self, theta0, scale, free=None, max_iter=500, edm_tol=1e-9):
+        """Device BFGS of every toy from theta0 [n, stride]; free is an optional uint8
+        [n, stride] device tensor (1 = parameter may move)."""
         import torch
         dev = theta0.device
+        if free is not None:
+            free = free.to(device=dev, dtype=torch.uint8).contiguous()
         th = torch.empty_like(theta0)
         nll = torch.empty(self.n, dtype=torch.float64, device=dev)
         sig = torch.empty_like(theta0)

@@ -429,7 +429,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.fspart, (size_t)fs_off));
   HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
   HIP_TRY(B->alloc(&v.apart, (size_t)apart_off));
-  HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinLen));
+  HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinRecLen));
   HIP_TRY(B->alloc(&v.nllp, (size_t)nllp_off));
   HIP_TRY(B->alloc(&v.badp, (size_t)nllp_off));
   HIP_TRY(B->alloc(&v.gpart, (size_t)gpart_off * kGradLen));

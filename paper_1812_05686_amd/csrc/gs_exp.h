@@ -39,14 +39,16 @@ namespace gs {
         1.4426950408889634074, 0.6931471805592082, 7.371002565167799e-13, 6755399441055744.0         \
   }
 
-GS_HD inline double exp_cw(double x, const double *c) {
+// c0 = c[0] and mg = c[15], passed separately so that a caller can hold them
+// in vector registers: an instruction may read only one scalar register, and
+// these two meet another scalar operand.
+GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
   x = fmax(x, -1000.0);
-  const double t = fma(x, c[12], c[15]);
-  const double n = t - c[15];
+  const double t = fma(x, c[12], mg);
+  const double n = t - mg;
   double r = fma(-n, c[13], x);
   r = fma(-n, c[14], r);
-  double p = c[0];
-  p = fma(p, r, c[1]);
+  double p = fma(c0, r, c[1]);
   p = fma(p, r, c[2]);
   p = fma(p, r, c[3]);
   p = fma(p, r, c[4]);
@@ -59,5 +61,7 @@ GS_HD inline double exp_cw(double x, const double *c) {
   p = fma(p, r, c[11]);
   return ldexp(p, (int)(unsigned)__builtin_bit_cast(unsigned long long, t));
 }
+
+GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[15]); }
 
 }  // namespace gs

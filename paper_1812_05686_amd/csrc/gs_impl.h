@@ -39,7 +39,7 @@ struct ToyDev {
   int bin_blocks, cell_blocks;  // reduction blocks over window bins / cells (kBlock each)
   int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
   long long cell_off;   // rec[(cell_off + i) * kRecLen]
-  long long win_off;    // binrec[(win_off + b) * kBinLen], F[(win_off + b) * S]
+  long long win_off;    // binrec[(win_off + b) * kBinRecLen], F[(win_off + b) * S]
   long long cnt_off;    // counts of the window: cnt[cnt_off + (d * L + b) * K + k]
   long long fpart_off;  // fold partials: fpart[fpart_off + chunk * L + b]
   long long fs_off;     // per-species fold partials: fspart[fs_off + (chunk * L + b) * S + s]
@@ -79,7 +79,7 @@ struct BatchView {
   double *fspart;   // fold partials per species
   double *F;        // per-species spectra of the window, bin width included
   double *apart;    // adjoint partials
-  double *binrec;   // window bins: xbar, ln xbar hi, lo, G
+  double *binrec;   // window bins: xbar, ln xbar hi, lo, G, G ln xbar, G xbar
   double *nllp;     // -ln L partials
   double *gpart;    // gradient partials
   uint32_t *badp;   // domain flags per bin block

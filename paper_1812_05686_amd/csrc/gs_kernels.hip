@@ -30,6 +30,22 @@ namespace gs {
 // Coefficients of exp_cw; read through scalar loads so they live in SGPRs.
 __constant__ double kExpC[16] = GS_EXP_COEFS;
 
+// exp_cw's coefficients as the pair loops use them: the table (scalar
+// registers) plus the two constants that meet another scalar operand, copied
+// once per thread into vector registers (the empty asm hides the copy from
+// the optimiser, which would otherwise rematerialise it inside the loop).
+struct ExpK {
+  const double *c;
+  double c0, mg;
+};
+__device__ __forceinline__ ExpK exp_consts() {
+  ExpK e{kExpC, kExpC[0], kExpC[15]};
+  asm volatile("" : "+v"(e.c0));
+  asm volatile("" : "+v"(e.mg));
+  return e;
+}
+__device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_cw(x, e.c, e.c0, e.mg); }
+
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; map block b to an
@@ -209,10 +225,10 @@ hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *
 // Response of a cell at one bin (record slots as written by cell_record).
 template <int FAM>
 __device__ __forceinline__ double pair_density(const double *__restrict__ p, double x, double Lh, double Ll,
-                                               const double *ec) {
-  if (FAM == kGammaPE) return exp_cw(gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll), ec);
+                                               const ExpK &ec) {
+  if (FAM == kGammaPE) return dexp(gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll), ec);
   double z;
-  return exp_cw(gauss_exponent(p[0], p[1], p[2], x, z), ec);
+  return dexp(gauss_exponent(p[0], p[1], p[2], x, z), ec);
 }
 
 // 1-D fold.  A workgroup owns kFoldTile = 64 window bins and a set of cells.
@@ -235,7 +251,7 @@ struct Bin2 {
 };
 
 template <int FAM>
-__device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const Bin2 &bn, const double *ec, double &a0,
+__device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const Bin2 &bn, const ExpK &ec, double &a0,
                                            double &a1) {
   const double W = FAM == kGammaPE ? p[5] : p[3];
   a0 = __fma_rn(W, pair_density<FAM>(p, bn.x0, bn.Lh0, bn.Ll0, ec), a0);
@@ -246,7 +262,7 @@ __device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const B
 // an odd batch is padded with a zero record); half h of the wave takes the
 // cell 2k + h of pair k.
 template <int FAM>
-__device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Bin2 &bn, const double *ec,
+__device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Bin2 &bn, const ExpK &ec,
                                            double &a0, double &a1) {
   constexpr int L = Stage<FAM>::kLen;
   const int h = (threadIdx.x >> 5) & 1;
@@ -284,7 +300,7 @@ __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave,
 // cell q / P, stored at srec[2q].
 template <int FAM>
 __device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_lo, int c_hi, double *srec, int wave,
-                                           const Bin2 &bn, const double *ec, double &a0, double &a1) {
+                                           const Bin2 &bn, const ExpK &ec, double &a0, double &a1) {
   constexpr int P = Stage<FAM>::kParts;
   static_assert(kStage * P <= 2 * kWaves * 64, "two staged parts per thread");
   const int tid = threadIdx.x;
@@ -363,7 +379,7 @@ __device__ __forceinline__ int group_list(const int2 *__restrict__ hull, int g0,
 // zero records (weight 0).
 template <int FAM>
 __device__ __forceinline__ void fold_groups(const double *__restrict__ R, const int *list, int n_list, int c_lo,
-                                            int c_hi, double *srec, int wave, const Bin2 &bn, const double *ec,
+                                            int c_hi, double *srec, int wave, const Bin2 &bn, const ExpK &ec,
                                             double &a0, double &a1) {
   constexpr int P = Stage<FAM>::kParts;
   constexpr int kGPB = kStage / kGroup;
@@ -403,7 +419,7 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   __shared__ double red[kWaves * 2 * 64];
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
-  const double *ec = kExpC;
+  const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
   const FoldItem it = items[w_item];
@@ -459,7 +475,7 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
 template <int FAM>
 __device__ __forceinline__ void fold_cells_s(const double *__restrict__ R, const double *__restrict__ wc, int Sg,
                                              int n_true, int c0, int c1, int j0, int j1, double x, double Lh,
-                                             double Ll, const double *ec, double (&acc)[GS_MAX_SPECIES]) {
+                                             double Ll, const ExpK &ec, double (&acc)[GS_MAX_SPECIES]) {
   for (int i = c0; i < c1; i += kWaves) {
     const double *p = R + (size_t)i * kRecLen;
     const int2 s = get_support(p);
@@ -486,7 +502,7 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
                                                 double *__restrict__ out) {
   __shared__ double red[kWaves * kTile * GS_MAX_SPECIES];
   __shared__ int rng[2 * kWaves];
-  const double *ec = kExpC;
+  const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
   const FoldItem it = items[w_item];
@@ -595,11 +611,14 @@ __global__ __launch_bounds__(256) void k_bins1(const ToyDev *__restrict__ toys, 
       if (mu_out) mu_out[(long long)d * T.L + b] = mu;
     }
     if (Sh.family == kGammaPE && !(bn[0] > 0.0)) G = 0.0;
-    double *br = binrec + (T.win_off + b) * kBinLen;
+    double *br = binrec + (T.win_off + b) * kBinRecLen;
+    const double Gd = G * dx;
     br[0] = bn[0];
     br[1] = bn[2];
     br[2] = bn[3];
-    br[3] = G * dx;
+    br[3] = Gd;
+    br[4] = Gd * bn[2];
+    br[5] = Gd * bn[0];
     if (bad) bad_s = 1;  // benign race: every writer stores 1
   }
   const double tot = block_sum(sum, lds);
@@ -622,23 +641,24 @@ hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *activ
 //  gaussian: t1 = z_ji, t2 = z_ji^2 with z = (x - m)/s
 template <int FAM>
 __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR, int b0, int b1,
-                                         const double *ec, double &A0, double &A1, double &A2) {
+                                         const ExpK &ec, double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
-  double x = BR[(size_t)b0 * kBinLen], Lh = BR[(size_t)b0 * kBinLen + 1], Ll = BR[(size_t)b0 * kBinLen + 2],
-         G = BR[(size_t)b0 * kBinLen + 3];
+  // bin record: x, ln x (hi, lo), G, G ln x, G x
+  const double *br = BR + (size_t)b0 * kBinRecLen;
+  double x = br[0], Lh = br[1], Ll = br[2], G = br[3], GL = br[4], GX = br[5];
   for (int b = b0; b < b1; b += kWaves) {
-    const double *bn = BR + (size_t)min(b + kWaves, b1 - 1) * kBinLen;  // next bin, fetched early
-    const double nx = bn[0], nLh = bn[1], nLl = bn[2], nG = bn[3];
+    const double *bn = BR + (size_t)min(b + kWaves, b1 - 1) * kBinRecLen;  // next bin, fetched early
+    const double nx = bn[0], nLh = bn[1], nLl = bn[2], nG = bn[3], nGL = bn[4], nGX = bn[5];
     if (FAM == kGammaPE) {
       if (G != 0.0) {  // wave-uniform: zero seed, or bin outside the gamma support
-        const double Gr = G * exp_cw(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
-        A0 += Gr;
-        A1 = __fma_rn(Gr, Lh, A1);
-        A2 = __fma_rn(Gr, x, A2);
+        const double r = dexp(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
+        A0 = __fma_rn(G, r, A0);
+        A1 = __fma_rn(GL, r, A1);
+        A2 = __fma_rn(GX, r, A2);
       }
     } else {
       double z;
-      const double Gr = G * exp_cw(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
+      const double Gr = G * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
       const double Grz = Gr * z;
       A0 += Gr;
       A1 += Grz;
@@ -648,6 +668,8 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
     Lh = nLh;
     Ll = nLl;
     G = nG;
+    GL = nGL;
+    GX = nGX;
   }
 }
 
@@ -657,9 +679,9 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
 template <int FAM>
 __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
                                            const double *__restrict__ BR, const double *__restrict__ HR, int b0, int b1,
-                                           const double *ec, double &A0, double &A1, double &A2) {
+                                           const ExpK &ec, double &A0, double &A1, double &A2) {
   for (int b = b0; b < b1; b += kWaves) {
-    const double *br = BR + (size_t)b * kBinLen;
+    const double *br = BR + (size_t)b * kBinRecLen;
     const double x = br[0], Lh = br[1], Ll = br[2];
     if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
     const double *h = HR + (size_t)b * S;
@@ -668,13 +690,13 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
     for (int q = 0; q < GS_MAX_SPECIES; q++)
       if (q < S) Z = __fma_rn(h[q], rw[q], Z);
     if (FAM == kGammaPE) {
-      const double Gr = Z * exp_cw(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
+      const double Gr = Z * dexp(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
       A0 += Gr;
       A1 = __fma_rn(Gr, Lh, A1);
       A2 = __fma_rn(Gr, x, A2);
     } else {
       double z;
-      const double Gr = Z * exp_cw(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
+      const double Gr = Z * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
       const double Grz = Gr * z;
       A0 += Gr;
       A1 += Grz;
@@ -691,7 +713,7 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
                                              const double *__restrict__ H, const uint8_t *__restrict__ active,
                                              double *__restrict__ apart) {
   __shared__ double red[kWaves * kTile * 3];
-  const double *ec = kExpC;
+  const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
   const AdjItem it = items[w_item];
@@ -715,7 +737,7 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
     hi = max(hi, __shfl_xor(hi, o, 64));
   }
   const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
-  const double *BR = binrec + T.win_off * kBinLen;
+  const double *BR = binrec + T.win_off * kBinRecLen;
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
   if (!PS) {
     if (Sh.family == kGammaPE)
@@ -1139,11 +1161,13 @@ __global__ __launch_bounds__(256) void k_bins2(const ToyDev *__restrict__ toys, 
     }
     const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
     for (int q = 0; q < S; q++) H[(T.win_off + b) * S + q] = outside ? 0.0 : dx * hs[q];
-    double *br = binrec + (T.win_off + b) * kBinLen;
+    double *br = binrec + (T.win_off + b) * kBinRecLen;
     br[0] = bn[0];
     br[1] = bn[2];
     br[2] = bn[3];
-    br[3] = outside ? 0.0 : 1.0;
+    br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
+    br[4] = 0.0;
+    br[5] = 0.0;
     if (bad) bad_s = 1;
   }
   const double tot = block_sum(sum, lds);

@@ -242,7 +242,7 @@ def test_banding_error_bound(gs, orc, which, cut):
         assert abs(v - ov) / abs(ov) <= NLL_TOL and _grad_err(g, og, m.fd_scale) <= GRAD_TOL
 
 
-def _batched_fit(gs, toys, scale):
+def _batched_fit(gs, toys, scale, free=False):
     import torch
     batch = gs.Batch(toys)
     th0 = np.zeros((len(toys), batch.stride))
@@ -250,7 +250,8 @@ def _batched_fit(gs, toys, scale):
         th0[t, : m.n_params] = m.theta0
     sc = np.ones(batch.stride)
     sc[: len(scale)] = scale
-    r = batch.fit(torch.tensor(th0, dtype=torch.float64, device="cuda"), sc)
+    r = batch.fit(torch.tensor(th0, dtype=torch.float64, device="cuda"), sc,
+                  free=batch.free_masks(toys) if free else None)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in r.items()}
 
@@ -259,10 +260,10 @@ def test_fit_batched_matches_host_fits(gs):
     """Device BFGS over a ragged batch of Borexino-scale toys lands where the host BFGS
     driving the same GPU evaluations lands, within 1e-3 sigma."""
     toys = gsgen.config3(6, base=gsgen.config1())
-    r = _batched_fit(gs, toys, toys[0].fd_scale)
+    r = _batched_fit(gs, toys, toys[0].fd_scale, free=True)
     for t, m in enumerate(toys):
         assert r["status"][t] & 32, (t, r["status"][t])
-        ref = gs.Model(m).fit(m.theta0, m.fd_scale)
+        ref = gs.Model(m).fit(m.theta0, m.fd_scale, free=m.free_mask())
         assert ref["ok"]
         # a species whose spectrum lies outside the toy's window leaves the likelihood flat
         # in its rate (no finite sigma): both fits must leave it where it started
