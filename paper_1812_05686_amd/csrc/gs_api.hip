@@ -293,6 +293,18 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     sh.cellE = cE;
     sh.wcell = wc;
     sh.bins = bins;
+    // uniform binning (midpoints within 1e-6 of a bin width of a lattice): the
+    // support search guesses bin indices arithmetically
+    sh.bx0 = 0.5 * (d.reco_edges[0] + d.reco_edges[1]);
+    sh.bw = 0.0;
+    if (d.n_reco > 1) {
+      const double xl = 0.5 * (d.reco_edges[d.n_reco - 1] + d.reco_edges[d.n_reco]);
+      const double w = (xl - sh.bx0) / (d.n_reco - 1);
+      bool uni = w > 0.0;
+      for (int j = 0; uni && j < d.n_reco; j++)
+        uni = std::fabs(0.5 * (d.reco_edges[j] + d.reco_edges[j + 1]) - (sh.bx0 + j * w)) <= 1e-6 * w;
+      if (uni) sh.bw = w;
+    }
     if (d.n_psd > 0) {
       std::vector<double> psd(2 * (size_t)d.n_psd), mix(5 * (size_t)d.n_species);
       for (int k = 0; k < d.n_psd; k++) {

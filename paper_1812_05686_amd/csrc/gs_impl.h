@@ -26,6 +26,7 @@ struct ShapeDev {
   const double *cellE;  // [n_cell]: grid-cell centres, then line energies
   const double *wcell;  // [n_true][Sg]: grid-species weights, cell-major
   const double *bins;   // [n_reco][kBinLen]: xbar, dx, ln xbar (hi, lo)
+  double bx0, bw;       // uniform binning: xbar_j = bx0 + j bw (bw = 0: not uniform)
   const double *psd;    // [n_psd][2]: ybar, dy
   const double *mix;    // [S][5], internal species order
   int sp_of[GS_MAX_SPECIES];

@@ -24,6 +24,7 @@
 #include <math.h>
 
 #include "gs_impl.h"
+#include "gs_support.h"
 
 namespace gs {
 
@@ -70,98 +71,6 @@ __device__ double block_sum(double v, double *lds) {
   return r;
 }
 
-// ------------------------------------------------------------- supports ---
-__device__ int first_bin_at_or_above(const double *bins, int n, double x) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (bins[(size_t)mid * kBinLen] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-__device__ int first_bin_above(const double *bins, int n, double x) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (bins[(size_t)mid * kBinLen] <= x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Interval [xl, xr] outside of which the gamma log-density
-// (k-1) ln x - x/th + C is below T.  The log-density is concave for k > 1
-// (increasing below the mode, decreasing above) and decreasing for k <= 1;
-// Newton's method from the far side of each root then approaches it
-// monotonically without crossing (the tangent of a concave function lies
-// above it), so every iterate is a valid conservative end point.
-__device__ bool gamma_support(double k, double th, double C, double T, double &xl, double &xr) {
-  auto E = [&](double x) { return (k - 1.0) * log(x) - x / th + C; };
-  auto dE = [&](double x) { return (k - 1.0) / x - 1.0 / th; };
-  const double sd = sqrt(k) * th;
-  double xm = 0.0, w = sd;
-  if (k > 1.0) {
-    xm = (k - 1.0) * th;
-    const double Em = E(xm);
-    if (!(Em > T)) return false;
-    w = sd * sqrt(2.0 * (Em - T)) + sd;
-  }
-  // iterate until a step is below tol: the end points only need bin-scale precision
-  const double tol = 1e-3 * sd;
-  double x = xm + w;
-  for (int i = 0; i < 80 && E(x) > T; i++) x = xm + 2.0 * (x - xm);
-  for (int i = 0; i < 30; i++) {
-    const double nx = x - (E(x) - T) / dE(x);
-    if (!(nx < x)) break;
-    const bool done = x - nx < tol;
-    x = nx;
-    if (done) break;
-  }
-  xr = x;
-  xl = -INFINITY;
-  if (k > 1.0) {
-    x = xm - w;
-    if (!(x > 0.0)) x = 0.5 * xm;
-    for (int i = 0; i < 64 && E(x) > T; i++) x *= 0.5;
-    if (E(x) <= T) {
-      for (int q = 0; q < 30; q++) {
-        const double nx = x - (E(x) - T) / dE(x);
-        if (!(nx > x) || !(nx < xm)) break;
-        const bool done = nx - x < tol;
-        x = nx;
-        if (done) break;
-      }
-      xl = x;
-    }
-  }
-  return true;
-}
-
-// Reco bins [x, y) whose midpoint log-density can exceed T for this cell.
-__device__ int2 cell_support(int fam, const double *rc, double m, double s, bool ok, const double *bins, int n_reco,
-                             double T) {
-  if (!ok) return make_int2(0, 0);
-  if (!(T > -INFINITY)) return make_int2(0, n_reco);
-  double xl, xr;
-  if (fam == kGammaPE) {
-    const double s2 = s * s;
-    if (!gamma_support(m * m / s2, s2 / m, rc[3] + rc[4], T, xl, xr)) return make_int2(0, 0);
-  } else {
-    const double c0 = rc[2];
-    if (!(c0 > T)) return make_int2(0, 0);
-    const double h = s * sqrt(2.0 * (c0 - T));
-    xl = m - h;
-    xr = m + h;
-  }
-  return make_int2(first_bin_at_or_above(bins, n_reco, xl), first_bin_above(bins, n_reco, xr));
-}
-
 // ------------------------------------------------------------- k_cells ----
 __device__ __forceinline__ void put_support(double *rc, int2 s) { *(int2 *)(rc + 6) = s; }
 __device__ __forceinline__ int2 get_support(const double *rc) { return *(const int2 *)(rc + 6); }
@@ -193,7 +102,8 @@ __global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, c
     ok = ok && isfinite(W);
     double r[kRecLen];
     cell_record(Sh.family, mo.m, mo.s, W, ok, r);
-    const int2 sp = ok ? cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, log_cut) : make_int2(0, 0);
+    const Span spn = cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, Sh.bx0, Sh.bw, log_cut);
+    const int2 sp = make_int2(spn.x, spn.y);
     put_support(r, sp);
     double *rc = rec + (T.cell_off + i) * kRecLen;
 #pragma unroll
