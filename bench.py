@@ -33,6 +33,23 @@ FP64_PEAK_TFLOPS = 78.6
 # 3 ADD), the exponential (13 FMA, MUL, MAX, RNDNE, LDEXP) and the accumulation (1 FMA in the
 # fold; 1 MUL, 1 ADD, 2 FMA in the adjoint).
 FLOPS_PER_PAIR = {"fold": 49, "adj": 53}
+# HBM bytes per launch on the default workload (4096 toys), from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
+# plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
+# kernel sources they were taken on: any change to those sources reports traffic as null.
+TRAFFIC = {"sources_sha256": None, "toys": 4096, "kernels": {}}
+
+
+def sources_sha256():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1812_05686_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -139,9 +156,14 @@ def main():
                              executed_over_banded=executed[k] / band_pairs)
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
     ach = per_kernel[dom]["tflops"]
-    roofline = {"bound": "alu", "kernel": "k_fold1" if dom == "fold" else "k_adj", "achieved": round(ach, 3),
+    kname = "k_fold1" if dom == "fold" else "k_adj"
+    traffic = None
+    if (TRAFFIC["sources_sha256"] == sources_sha256() and len(toys) == TRAFFIC["toys"]
+            and kname in TRAFFIC["kernels"]):
+        traffic = TRAFFIC["kernels"][kname]
+    roofline = {"bound": "alu", "kernel": kname, "achieved": round(ach, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": band_pairs,
+                "traffic": traffic, "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": band_pairs,
                 "executed_pairs": executed[dom], "full_mesh_pairs": full_pairs,
                 "banded_over_full": round(band_pairs / full_pairs, 4),
                 "avg_launch_ms": round(per_kernel[dom]["avg_ms"], 4),
@@ -176,10 +198,12 @@ def main():
         el = time.perf_counter() - ta
         stt = r["status"].cpu().numpy()
         it = r["iters"].cpu().numpy()
+        act, tms = batch.fit_trace()
         toy_fits = {"fits_per_s": round(len(toys) / el, 2), "seconds": round(el, 4), "toys": len(toys),
                     "fixed_rates": int(sum(int((~t.free).sum()) for t in toys)),
                     "converged": int(np.sum(stt & 32 != 0)), "mean_iters": round(float(it.mean()), 2),
-                    "max_iters": int(it.max())}
+                    "max_iters": int(it.max()), "graph_launches": int(len(act)),
+                    "ms_until_90pct_done": round(float(tms[np.argmax(act <= 0.1 * len(toys))]), 2) if len(act) else None}
         log(f"bench: toy fits {toy_fits}")
 
     fits = None

@@ -336,10 +336,25 @@ def window_free_params(jac_win: np.ndarray, mu_win: np.ndarray, nominal: np.ndar
     return free
 
 
+_JAC_CACHE: dict = {}
+
+
 def nominal_jacobian(model: Model) -> tuple[np.ndarray, np.ndarray]:
     """Nature's expected 1-D counts mu [n_reco] at the nominal point and d mu / d theta
     [n_reco, S + n_resp] (rates exactly; response parameters by central differences of
-    the nature histogram, relative step 1e-4)."""
+    the nature histogram, relative step 1e-4).  Cached per (shape arrays, nominal point)."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (model.spectra, model.line_energy, model.reco_edges, model.theta_true):
+        h.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+    key = (h.hexdigest(), model.family, model.birks_A, model.n_true, model.e_lo, model.e_step)
+    if key in _JAC_CACHE:
+        return _JAC_CACHE[key]
+    _JAC_CACHE[key] = out = _nominal_jacobian(model)
+    return out
+
+
+def _nominal_jacobian(model: Model) -> tuple[np.ndarray, np.ndarray]:
     S = model.n_species
     th = model.theta_true
     nr = 2 if model.family == GAUSS_E else 5
@@ -379,6 +394,146 @@ def config3(n_toys: int = 4096, base: Model | None = None, full_window: bool = F
         free = window_free_params(jac[lo:lo + L], mu_nom[lo:lo + L], base.theta_true, base.pull_sigma)
         toys.append(base.replace(name=f"c3/{t}", counts=counts, win_lo=lo, win_hi=lo + L,
                                  theta_true=th, theta0=base.theta_true.copy(), free=free))
+    return toys
+
+
+# ------------------------------------------------------- mixed batch (c4) ---
+C4_A_POOL = [("gauss862", 5e4), ("gauss1460", 2e4), ("flat", 2e4), ("exp300", 1e4), ("exp800", 1e4),
+             ("bump1800", 5e3)]
+C4_B_LINES = C1_LINES
+C4_B_BETAS = [(0.200, 1e5), (0.560, 6e4), (0.760, 8e4), (1.100, 4e4), (1.320, 5e4), (1.880, 3e4), (2.440, 2e4),
+              (3.000, 1e4)]
+C4_B_EXPS = [(0.150, 4e4), (0.300, 2e4), (0.600, 1e4), (1.000, 5e3)]
+C4_B_GRIDS = [(1000, 0.003), (2000, 0.0015), (4000, 0.00075)]
+
+
+def _c4_a_pool():
+    edges_t = cell_edges(500, 0.0, 5.0)
+    rows = [spectrum_gauss(edges_t, 862.0, 1.0), spectrum_gauss(edges_t, 1460.0, 2.0), spectrum_flat(edges_t),
+            spectrum_exp(edges_t, 300.0), spectrum_exp(edges_t, 800.0), spectrum_gauss(edges_t, 1800.0, 50.0)]
+    return np.stack(rows), np.array([r for _, r in C4_A_POOL]), [n for n, _ in C4_A_POOL]
+
+
+def _pool_jacobian(template: Model, resp: np.ndarray, approx_family: int) -> np.ndarray:
+    """d hist_s / d resp_q [n_reco, S, n_resp] by central differences (relative step 1e-4) of the
+    nature histogram, computed with approx_family's bin probabilities."""
+    t = template.replace(family=approx_family)
+    out = np.zeros((template.n_reco, template.n_species, len(resp)))
+    for q in range(len(resp)):
+        h = 1e-4 * abs(resp[q])
+        rp, rm = resp.copy(), resp.copy()
+        rp[q] += h
+        rm[q] -= h
+        out[:, :, q] = (nature_species_hist(t, rp) - nature_species_hist(t, rm)) / (2 * h)
+    return out
+
+
+def _free_from_pool(hist: np.ndarray, jac: np.ndarray, idx, rates_nom, resp_nom, lo, hi, pull_sigma, extra=0):
+    """window_free_params for a shape that takes species columns idx of a pool."""
+    hw = hist[lo:hi][:, idx]
+    jw = np.concatenate([hw, np.einsum("jsq,s->jq", jac[lo:hi][:, idx], rates_nom)], axis=1)
+    free = window_free_params(jw, hw @ rates_nom, np.concatenate([rates_nom, resp_nom]), pull_sigma[:jw.shape[1]])
+    return np.concatenate([free, np.ones(extra, bool)])
+
+
+def config4(n_toys: int = 16384, n_shapes_a: int = 8, n_shapes_b: int = 9, fractions=(0.5, 0.4, 0.1)) -> list[Model]:
+    """Large uneven batch mixing three kinds of fit problem (seeded class per toy):
+      A  small energy-family models: 3-5 species drawn from a 6-shape pool (Gaussian lines, a
+         bump, flat, two exponentials) on 500 x 5 keV cells, Gaussian response (a, b), own
+         window of 100-200 of 200 bins of 10 keV;
+      B  photoelectron-family models like config 1: 6-16 species drawn from a 16-shape pool
+         (4 lines, 8 betas, 4 exponentials) on 1000, 2000 or 4000 cells over 0-3 MeV, gamma
+         response, own window of 200-900 of 900 bins of 1.6 pe, pulls on kB and a;
+      C  the pulse-shape model of config 2 with 1-3 datasets (exposures 1, 0.6, 0.3), full
+         window: 45,000-135,000 bins.
+    Toys of a class share a pool of shapes (species subset, grid), so toys of one shape share
+    their spectra and binning arrays.  Rates are drawn +-20% uniform around nominal; fits start
+    at nominal; parameters a window cannot determine are fixed (window_free_params, with the
+    Fisher matrix's response derivatives from the Gaussian approximation of the response)."""
+    g = _rng(4, 1)
+    # --- class A pool
+    a_spec, a_rates, a_names = _c4_a_pool()
+    a_resp = np.array([10.0, 5.0])
+    a_tmpl = Model(name="c4a", family=GAUSS_E, n_true=500, e_lo=0.0, e_step=5.0, spectra=a_spec,
+                   line_energy=np.full(6, np.nan), reco_edges=10.0 * np.arange(201.0), exposure=np.ones(1),
+                   counts=np.zeros((1, 200, 1)), win_lo=0, win_hi=200, pull_centre=np.zeros(8),
+                   pull_sigma=np.zeros(8), theta_true=np.concatenate([a_rates, a_resp]),
+                   theta0=np.concatenate([a_rates, a_resp]), fd_scale=np.ones(8), species=a_names)
+    a_hist = nature_species_hist(a_tmpl, a_resp)
+    a_jac = _pool_jacobian(a_tmpl, a_resp, GAUSS_E)
+    a_shapes = []
+    for q in range(n_shapes_a):
+        idx = np.sort(g.choice(6, size=int(g.integers(3, 6)), replace=False))
+        a_shapes.append((idx, np.ascontiguousarray(a_spec[idx]), np.full(len(idx), np.nan), a_tmpl.reco_edges))
+    # --- class B pools, one per grid
+    b_pool = []
+    for n_true, step in C4_B_GRIDS:
+        spectra, le, rates, names, edges = _c1_shape(n_true=n_true, e_step=step, lines=C4_B_LINES, betas=C4_B_BETAS,
+                                                     exps=C4_B_EXPS)
+        S = len(rates)
+        tmpl = Model(name="c4b", family=GAMMA_PE, n_true=n_true, e_lo=0.0, e_step=step, spectra=spectra,
+                     line_energy=le, reco_edges=edges, exposure=np.ones(1), counts=np.zeros((1, 900, 1)), win_lo=0,
+                     win_hi=900, pull_centre=np.zeros(S + 5), pull_sigma=np.zeros(S + 5),
+                     theta_true=np.concatenate([rates, C1_RESP]), theta0=np.concatenate([rates, C1_RESP]),
+                     fd_scale=_scales_pe(S, rates), species=names)
+        b_pool.append((tmpl, nature_species_hist(tmpl, C1_RESP), _pool_jacobian(tmpl, C1_RESP, GAUSS_PE)))
+    b_shapes = []
+    for q in range(n_shapes_b):
+        gi = q % len(C4_B_GRIDS)
+        tmpl = b_pool[gi][0]
+        idx = np.sort(g.choice(16, size=int(g.integers(6, 17)), replace=False))
+        b_shapes.append((gi, idx, np.ascontiguousarray(tmpl.spectra[idx]), np.ascontiguousarray(tmpl.line_energy[idx])))
+    # --- class C: the pulse-shape model
+    c2 = config2()
+    S2 = c2.n_species
+    c_hist = nature_species_hist(c2, c2.theta_true[S2:S2 + 5])
+
+    cls = g.choice(3, size=n_toys, p=np.asarray(fractions) / np.sum(fractions))
+    toys = []
+    for t in range(n_toys):
+        gt = _rng(4, 1, 1 + t)
+        if cls[t] == 0:
+            idx, spec, le, edges = a_shapes[int(gt.integers(n_shapes_a))]
+            S = len(idx)
+            rates_nom = a_rates[idx]
+            theta = np.concatenate([rates_nom * gt.uniform(0.8, 1.2, S), a_resp])
+            L = int(gt.integers(100, 201))
+            lo = int(gt.integers(0, 200 - L + 1))
+            m = Model(name=f"c4/A/{t}", family=GAUSS_E, n_true=500, e_lo=0.0, e_step=5.0, spectra=spec,
+                      line_energy=le, reco_edges=edges, exposure=np.ones(1), counts=np.zeros((1, 200, 1)),
+                      win_lo=lo, win_hi=lo + L, pull_centre=np.concatenate([rates_nom, a_resp]),
+                      pull_sigma=np.zeros(S + 2), theta_true=theta, theta0=np.concatenate([rates_nom, a_resp]),
+                      fd_scale=np.concatenate([np.sqrt(rates_nom), [1.0, 0.5]]),
+                      species=[a_names[i] for i in idx])
+            m.free = _free_from_pool(a_hist, a_jac, idx, rates_nom, a_resp, lo, lo + L, m.pull_sigma)
+            m.counts = draw_counts(nature_expected(m, theta, a_hist[:, idx]), _rng(4, 0, t))
+        elif cls[t] == 1:
+            gi, idx, spec, le = b_shapes[int(gt.integers(n_shapes_b))]
+            tmpl, hist, jac = b_pool[gi]
+            S = len(idx)
+            rates_nom = tmpl.theta_true[:16][idx]
+            theta = np.concatenate([rates_nom * gt.uniform(0.8, 1.2, S), C1_RESP])
+            L = int(gt.integers(200, 901))
+            lo = int(gt.integers(0, 900 - L + 1))
+            ps = np.zeros(S + 5)
+            ps[S + 1] = 0.0011
+            ps[S + 2] = 0.4
+            m = Model(name=f"c4/B/{t}", family=GAMMA_PE, n_true=tmpl.n_true, e_lo=0.0, e_step=tmpl.e_step,
+                      spectra=spec, line_energy=le, reco_edges=tmpl.reco_edges, exposure=np.ones(1),
+                      counts=np.zeros((1, 900, 1)), win_lo=lo, win_hi=lo + L,
+                      pull_centre=np.concatenate([rates_nom, C1_RESP]), pull_sigma=ps, theta_true=theta,
+                      theta0=np.concatenate([rates_nom, C1_RESP]), fd_scale=_scales_pe(S, rates_nom),
+                      species=[tmpl.species[i] for i in idx])
+            m.free = _free_from_pool(hist, jac, idx, rates_nom, C1_RESP, lo, lo + L, ps)
+            m.counts = draw_counts(nature_expected(m, theta, hist[:, idx]), _rng(4, 0, t))
+        else:
+            D = int(gt.integers(1, 4))
+            theta = c2.theta_true.copy()
+            theta[:S2] *= gt.uniform(0.8, 1.2, S2)
+            m = c2.replace(name=f"c4/C/{t}", exposure=np.array([1.0, 0.6, 0.3][:D]),
+                           counts=np.zeros((D, 900, 50)), theta_true=theta, theta0=c2.theta_true.copy())
+            m.counts = draw_counts(nature_expected(m, theta, c_hist), _rng(4, 0, t))
+        toys.append(m)
     return toys
 
 

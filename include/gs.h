@@ -190,10 +190,14 @@ gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll,
  * above: d_theta0[n_toys][stride] (start), d_free[n_toys][stride] (uint8,
  * NULL = all free), outputs d_theta_hat[n_toys][stride], d_nll_hat[n_toys],
  * d_sigma[n_toys][stride] (sqrt of the BFGS inverse-Hessian diagonal, may be
- * NULL), d_iters[n_toys], d_status[n_toys].  o->scale is a HOST array
- * [stride] used for every toy; o->use_fd and o->hesse are ignored.
+ * NULL), d_iters[n_toys], d_status[n_toys].  Parameter scales (the initial
+ * metric is diag(scale^2)): d_scale[n_toys][stride] on the device, one row
+ * per toy, or, when d_scale is NULL, o->scale, a HOST array [stride] used for
+ * every toy (each entry > 0, else GS_ERR_ARG); a non-positive or non-finite
+ * entry of d_scale is taken as 1.  o->use_fd and o->hesse are ignored.
  * Synchronises `hip_stream` before returning. */
-gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_free, const gs_fit_opts *o,
+gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_free, const double *d_scale,
+                         const gs_fit_opts *o,
                          double *d_theta_hat, double *d_nll_hat, double *d_sigma, int32_t *d_iters,
                          uint32_t *d_status, void *hip_stream);
 
@@ -237,6 +241,12 @@ gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int3
  * pairs the method needs at the current log-density cut.  Synchronises the
  * device. */
 gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out);
+/* Convergence profile of the most recent gs_fit_batched on this batch: after
+ * each launch of the captured fit graph (a fixed number of evaluation + BFGS
+ * steps), the number of toys still running and the host milliseconds since
+ * the call began.  Copies min(cap, count) entries into the host arrays
+ * active[] and ms[] and sets *n to the full count. */
+gs_status gs_batch_fit_trace(gs_batch *b, int32_t *active, double *ms, int32_t cap, int32_t *n);
 
 #ifdef __cplusplus
 }

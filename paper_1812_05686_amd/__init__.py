@@ -49,7 +49,7 @@ EXPORTS = ["gs_last_error", "gs_desc_validate", "gs_model_create", "gs_model_des
            "gs_nll", "gs_nll_grad", "gs_expected", "gs_fit", "gs_batch_create", "gs_batch_destroy",
            "gs_batch_num_toys", "gs_batch_param_stride", "gs_nll_grad_batched", "gs_fit_batched",
            "gs_batch_set_profiling", "gs_batch_kernel_times", "gs_batch_set_log_cut", "gs_model_set_log_cut",
-           "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs"]
+           "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs", "gs_batch_fit_trace"]
 KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish"]
 
 _lib = None
@@ -99,7 +99,7 @@ def lib():
         L.gs_nll_grad_batched.restype = C.c_int
         L.gs_nll_grad_batched.argtypes = [vp, vp, vp, vp, vp, vp]
         L.gs_fit_batched.restype = C.c_int
-        L.gs_fit_batched.argtypes = [vp, vp, vp, C.POINTER(gs_fit_opts), vp, vp, vp, vp, vp, vp]
+        L.gs_fit_batched.argtypes = [vp, vp, vp, vp, C.POINTER(gs_fit_opts), vp, vp, vp, vp, vp, vp]
         L.gs_batch_set_profiling.restype = C.c_int
         L.gs_batch_set_profiling.argtypes = [vp, C.c_int32]
         L.gs_batch_kernel_times.restype = C.c_int
@@ -114,6 +114,9 @@ def lib():
         L.gs_psd_probs.argtypes = [vp, _dp, _dp]
         L.gs_batch_mesh_pairs.restype = C.c_int
         L.gs_batch_mesh_pairs.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.gs_batch_fit_trace.restype = C.c_int
+        L.gs_batch_fit_trace.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
+                                         C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -296,6 +299,14 @@ class Batch:
         _check(lib().gs_batch_mesh_pairs(self.h, out), "gs_batch_mesh_pairs")
         return int(out[0]), int(out[1]), int(out[2]), int(out[3])
 
+    def fit_trace(self):
+        """(active toys, host ms) after each graph launch of the most recent fit."""
+        n = C.c_int32(0)
+        _check(lib().gs_batch_fit_trace(self.h, None, None, 0, C.byref(n)), "gs_batch_fit_trace")
+        a, t = (C.c_int32 * max(n.value, 1))(), (C.c_double * max(n.value, 1))()
+        _check(lib().gs_batch_fit_trace(self.h, a, t, n.value, C.byref(n)), "gs_batch_fit_trace")
+        return np.array(a[: n.value]), np.array(t[: n.value])
+
     def set_profiling(self, on: bool):
         _check(lib().gs_batch_set_profiling(self.h, int(on)), "gs_batch_set_profiling")
 
@@ -316,13 +327,26 @@ class Batch:
             f[t, : len(fm)] = fm
         return torch.tensor(f, device=device)
 
+    def scales(self, models, device="cuda"):
+        """float64 [n, stride] device tensor of the models' parameter scales (padding 1)."""
+        import torch
+        sc = np.ones((self.n, self.stride))
+        for t, m in enumerate(models):
+            sc[t, : m.n_params] = m.fd_scale
+        return torch.tensor(sc, dtype=torch.float64, device=device)
+
     def fit(self, theta0, scale, free=None, max_iter=500, edm_tol=1e-9):
-        """Device BFGS of every toy from theta0 [n, stride]; free is an optional uint8
+        """Device BFGS of every toy from theta0 [n, stride].  scale: one host row [stride] for
+        every toy, or a [n, stride] device tensor (one row per toy).  free: optional uint8
         [n, stride] device tensor (1 = parameter may move)."""
         import torch
         dev = theta0.device
         if free is not None:
             free = free.to(device=dev, dtype=torch.uint8).contiguous()
+        d_scale = None
+        if isinstance(scale, torch.Tensor) and scale.dim() == 2:
+            d_scale = scale.to(device=dev, dtype=torch.float64).contiguous()
+            scale = np.ones(self.stride)
         th = torch.empty_like(theta0)
         nll = torch.empty(self.n, dtype=torch.float64, device=dev)
         sig = torch.empty_like(theta0)
@@ -331,7 +355,8 @@ class Batch:
         sc = _arr(scale)
         o = gs_fit_opts(max_iter, edm_tol, 0, _ptr(sc), None, 0)
         fp = C.c_void_p(free.data_ptr()) if free is not None else None
-        _check(lib().gs_fit_batched(self.h, C.c_void_p(theta0.data_ptr()), fp, C.byref(o), C.c_void_p(th.data_ptr()),
+        dsp = C.c_void_p(d_scale.data_ptr()) if d_scale is not None else None
+        _check(lib().gs_fit_batched(self.h, C.c_void_p(theta0.data_ptr()), fp, dsp, C.byref(o), C.c_void_p(th.data_ptr()),
                                     C.c_void_p(nll.data_ptr()), C.c_void_p(sig.data_ptr()),
                                     C.c_void_p(iters.data_ptr()), C.c_void_p(st.data_ptr()), self._stream()),
                "gs_fit_batched")

@@ -13,6 +13,7 @@
 #include <memory>
 #include <string>
 #include <tuple>
+#include <chrono>
 #include <vector>
 
 #include "gs_impl.h"
@@ -166,6 +167,8 @@ struct gs_batch {
   double *e_nll = nullptr, *e_grad = nullptr, *d_scale = nullptr;
   uint32_t *e_st = nullptr;
   int *d_count = nullptr, *h_count = nullptr;
+  std::vector<int> trace_active;  // last gs_fit_batched: toys still running after each graph launch
+  std::vector<double> trace_ms;   // and the host time since the call started
   hipStream_t fit_stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -601,6 +604,17 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
   return GS_OK;
 }
 
+gs_status gs_batch_fit_trace(gs_batch *b, int32_t *active, double *ms, int32_t cap, int32_t *n) {
+  if (!b || !n || cap < 0 || (cap > 0 && (!active || !ms))) return fail(GS_ERR_ARG, "bad argument");
+  const int m = (int)b->trace_active.size();
+  for (int i = 0; i < std::min(m, (int)cap); i++) {
+    active[i] = b->trace_active[i];
+    ms[i] = b->trace_ms[i];
+  }
+  *n = m;
+  return GS_OK;
+}
+
 gs_status gs_batch_set_profiling(gs_batch *b, int32_t on) {
   if (!b) return fail(GS_ERR_ARG, "null batch");
   b->prof = on != 0;
@@ -878,31 +892,39 @@ static gs_status qn_graph(gs_batch *B, int K, double tol, int max_iter) {
   return GS_OK;
 }
 
-gs_status gs_fit_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_free, const gs_fit_opts *o,
+gs_status gs_fit_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_free, const double *d_scale,
+                         const gs_fit_opts *o,
                          double *d_theta_hat, double *d_nll_hat, double *d_sigma, int32_t *d_iters,
                          uint32_t *d_status, void *hip_stream) {
-  if (!B || !d_theta0 || !o || !o->scale || !d_theta_hat || !d_nll_hat || !d_iters || !d_status)
+  if (!B || !d_theta0 || !o || (!o->scale && !d_scale) || !d_theta_hat || !d_nll_hat || !d_iters || !d_status)
     return fail(GS_ERR_ARG, "null argument");
   if (o->max_iter < 1 || !(o->edm_tol > 0)) return fail(GS_ERR_ARG, "max_iter >= 1 and edm_tol > 0 required");
-  for (int p = 0; p < B->stride; p++)
-    if (!(o->scale[p] > 0)) return fail(GS_ERR_ARG, "scale[%d] must be > 0", p);
+  if (!d_scale)
+    for (int p = 0; p < B->stride; p++)
+      if (!(o->scale[p] > 0)) return fail(GS_ERR_ARG, "scale[%d] must be > 0", p);
   HIP_TRY(hipSetDevice(B->device));
   gs_status s = qn_setup(B);
   if (s != GS_OK) return s;
   hipStream_t caller = (hipStream_t)hip_stream, st = B->fit_stream;
-  HIP_TRY(hipMemcpyAsync(B->d_scale, o->scale, sizeof(double) * B->stride, hipMemcpyHostToDevice, st));
+  if (!d_scale) HIP_TRY(hipMemcpyAsync(B->d_scale, o->scale, sizeof(double) * B->stride, hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(B->ev_in, caller));
   HIP_TRY(hipStreamWaitEvent(st, B->ev_in, 0));
-  HIP_TRY(launch_qn_init(B->q, B->n_toys, d_theta0, d_free, B->d_scale, st));
+  HIP_TRY(launch_qn_init(B->q, B->n_toys, d_theta0, d_free, d_scale ? d_scale : B->d_scale, d_scale ? B->stride : 0,
+                         st));
   constexpr int K = 8;
   s = qn_graph(B, K, o->edm_tol, o->max_iter);
   if (s != GS_OK) return s;
   // an iteration is one evaluation; a fit needs max_iter accepted steps plus line-search trials
   const long long cap = 4LL * o->max_iter + 64;
+  B->trace_active.clear();
+  B->trace_ms.clear();
+  const auto t0 = std::chrono::steady_clock::now();
   for (long long done = 0; done < cap; done += K) {
     HIP_TRY(hipGraphLaunch(B->graph, st));
     HIP_TRY(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    B->trace_active.push_back(*B->h_count);
+    B->trace_ms.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
     if (*B->h_count == 0) break;
   }
   HIP_TRY(launch_qn_final(B->q, B->n_toys, d_theta_hat, d_nll_hat, d_sigma, d_iters, d_status, st));

@@ -58,6 +58,12 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 }
 inline int xcd_grid(int n) { return ((n + 7) >> 3) * 8; }
 
+// Deterministic sum over a wavefront (xor butterfly); result valid on every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Deterministic sum over a block of kBlock threads; result valid on thread 0.
 __device__ double block_sum(double v, double *lds) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -706,7 +712,7 @@ __global__ __launch_bounds__(256) void k_cellgrad(const ToyDev *__restrict__ toy
                                                   const double *__restrict__ theta, int stride,
                                                   const double *__restrict__ rec, const double *__restrict__ apart,
                                                   const uint8_t *__restrict__ active, double *__restrict__ gpart) {
-  __shared__ double lds[8];
+  __shared__ double part[kBlock / 64][kGradLen];
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
@@ -762,14 +768,26 @@ __global__ __launch_bounds__(256) void k_cellgrad(const ToyDev *__restrict__ toy
         if (s == q) gR[s] += A0;
     }
   }
-  double *o = gpart + (T.gpart_off + blockIdx.x) * kGradLen;
-  for (int s = 0; s < Sh.S; s++) {
-    const double v = block_sum(gR[s], lds);
-    if (threadIdx.x == 0) o[Sh.sp_of[s]] = v;
-  }
-  for (int p = 0; p < nr; p++) {
-    const double v = block_sum(gP[p], lds);
-    if (threadIdx.x == 0) o[Sh.S + p] = v;
+  // every entry summed over the wave, then over the block's waves in a fixed order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < GS_MAX_SPECIES; s++)
+    if (s < Sh.S) {
+      const double v = wave_sum(gR[s]);
+      if (lane == 0) part[wv][s] = v;
+    }
+#pragma unroll
+  for (int p = 0; p < 5; p++)
+    if (p < nr) {
+      const double v = wave_sum(gP[p]);
+      if (lane == 0) part[wv][Sh.S + p] = v;
+    }
+  __syncthreads();
+  const int q = threadIdx.x;
+  if (q < Sh.S + nr) {
+    double v = part[0][q];
+    for (int w = 1; w < kBlock / 64; w++) v += part[w][q];
+    gpart[(T.gpart_off + blockIdx.x) * kGradLen + (q < Sh.S ? Sh.sp_of[q] : q)] = v;
   }
 }
 

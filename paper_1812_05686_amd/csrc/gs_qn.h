@@ -20,7 +20,7 @@ struct QNView {
 };
 
 hipError_t launch_qn_init(const QNView &q, int n, const double *theta0, const uint8_t *free_mask,
-                          const double *scale, hipStream_t st);
+                          const double *scale, int scale_stride, hipStream_t st);
 hipError_t launch_qn_step(const QNView &q, int n, const double *nll_eval, const double *grad_eval,
                           const uint32_t *st_eval, double edm_tol, int max_iter, hipStream_t st);
 hipError_t launch_qn_count(const uint8_t *active, int n, int *out, hipStream_t st);

@@ -17,17 +17,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// scale: row t at scale + t * scale_stride (scale_stride 0: one row for every
+// toy); a non-positive or non-finite entry is taken as 1.
 __global__ __launch_bounds__(64) void k_qn_init(QNView q, const double *__restrict__ theta0,
-                                                const uint8_t *__restrict__ free_mask, const double *__restrict__ scale) {
+                                                const uint8_t *__restrict__ free_mask, const double *__restrict__ scale,
+                                                int scale_stride) {
   const int t = blockIdx.x, p = threadIdx.x, P = q.P;
   const size_t r = (size_t)t * P;
   const bool fr = p < q.n_par[t] && (!free_mask || free_mask[r + p]);
   if (p < P) {
+    double sc = scale[(size_t)t * scale_stride + p];
+    if (!(sc > 0.0 && sc < INFINITY)) sc = 1.0;
     q.x[r + p] = theta0[r + p];
     q.xt[r + p] = theta0[r + p];
     q.freep[r + p] = fr ? 1 : 0;
-    q.h0[r + p] = fr ? scale[p] * scale[p] : 0.0;
-    for (int c = 0; c < P; c++) q.H[(r + p) * P + c] = (c == p && fr) ? scale[p] * scale[p] : 0.0;
+    q.h0[r + p] = fr ? sc * sc : 0.0;
+    for (int c = 0; c < P; c++) q.H[(r + p) * P + c] = (c == p && fr) ? sc * sc : 0.0;
   }
   if (p == 0) {
     q.phase[t] = kPhaseInit;
@@ -194,8 +199,8 @@ __global__ __launch_bounds__(64) void k_qn_final(QNView q, double *__restrict__ 
 }
 
 hipError_t launch_qn_init(const QNView &q, int n, const double *theta0, const uint8_t *free_mask,
-                          const double *scale, hipStream_t st) {
-  hipLaunchKernelGGL(k_qn_init, dim3(n), dim3(64), 0, st, q, theta0, free_mask, scale);
+                          const double *scale, int scale_stride, hipStream_t st) {
+  hipLaunchKernelGGL(k_qn_init, dim3(n), dim3(64), 0, st, q, theta0, free_mask, scale, scale_stride);
   return hipGetLastError();
 }
 

@@ -316,3 +316,66 @@ def test_fit_batched_statuses(gs):
     r = batch.fit(torch.tensor(np.stack([m.theta0 for m in toys]), dtype=torch.float64, device="cuda"),
                   toys[0].fd_scale, max_iter=1)
     assert np.all(r["status"].cpu().numpy() & 8)
+
+
+def _mixed_sample(toys, per_class=2):
+    seen, out = {}, []
+    for t, m in enumerate(toys):
+        c = m.name.split("/")[1]
+        if seen.get(c, 0) < per_class:
+            seen[c] = seen.get(c, 0) + 1
+            out.append(t)
+    return out
+
+
+def test_mixed_batch_matches_oracle(gs, orc):
+    """One batched evaluation of an uneven mix (energy-family toys with 3-5 species and
+    100-200 bins, gamma toys with 6-16 species on 1000-4000 cells, pulse-shape toys with 1-3
+    datasets): sampled toys of every class against the oracle at an off-minimum point."""
+    import torch
+    toys = gsgen.config4(48)
+    batch = gs.Batch(toys)
+    th = np.zeros((len(toys), batch.stride))
+    pts = []
+    for t, m in enumerate(toys):
+        p = m.theta_true + 0.5 * m.fd_scale * gsgen._rng(300, 1, t).uniform(-1, 1, m.n_params)
+        pts.append(p)
+        th[t, : m.n_params] = p
+    nll, grad, st = batch.nll_grad(torch.tensor(th, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    nll, grad, st = nll.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    sample = _mixed_sample(toys)
+    assert len(sample) == 6
+    for t in sample:
+        m = toys[t]
+        ov, og, ost = orc.Oracle(m).nll_grad(pts[t])
+        print(m.name, nll[t], ov, flush=True)
+        assert st[t] == ost == 0, (m.name, st[t], ost)
+        assert abs(nll[t] - ov) / abs(ov) <= NLL_TOL, (m.name, nll[t], ov)
+        assert _grad_err(grad[t, : m.n_params], og, m.fd_scale) <= GRAD_TOL, (m.name, _grad_err(grad[t, : m.n_params], og, m.fd_scale))
+
+
+def test_mixed_batch_fits(gs):
+    """Device BFGS over the uneven mix: every toy converges, and sampled toys of every class
+    land within 1e-3 sigma of the host BFGS on the same GPU evaluations."""
+    import torch
+    toys = gsgen.config4(48)
+    batch = gs.Batch(toys)
+    th0 = np.zeros((len(toys), batch.stride))
+    for t, m in enumerate(toys):
+        th0[t, : m.n_params] = m.theta0
+    r = batch.fit(torch.tensor(th0, dtype=torch.float64, device="cuda"), batch.scales(toys),
+                  free=batch.free_masks(toys))
+    torch.cuda.synchronize()
+    r = {k: v.cpu().numpy() for k, v in r.items()}
+    bad = [(m.name, int(r["status"][t])) for t, m in enumerate(toys) if not r["status"][t] & 32]
+    assert not bad, bad
+    for t in _mixed_sample(toys, 1):
+        m = toys[t]
+        ref = gs.Model(m).fit(m.theta0, m.fd_scale, free=m.free_mask())
+        assert ref["ok"], (m.name, ref["status"])
+        th = r["theta"][t, : m.n_params]
+        fin = np.isfinite(ref["sigma"]) & (ref["sigma"] > 0)
+        z = np.abs(th - ref["theta"])[fin] / ref["sigma"][fin]
+        print(m.name, z.max(), flush=True)
+        assert z.max() <= 1e-3, (m.name, z)
