@@ -174,6 +174,11 @@ struct gs_batch {
   hipGraphExec_t graph = nullptr;
   int graph_k = 0, graph_max_iter = -1;
   double graph_tol = -1.0;
+  bool graph_compact = false;  // the instantiated graph covers a compacted toy list
+  // compacted toy and work-item lists of a batched fit (device copies)
+  int *d_toy_list = nullptr;
+  FoldItem *d_fold_c = nullptr;
+  AdjItem *d_adj_c = nullptr;
 
   ~gs_batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -414,6 +419,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     B->toys_h.push_back(T);
   }
   v.n_toys = n_toys;
+  v.toy_list = nullptr;
+  v.n_list = n_toys;
   v.stride = B->stride;
   v.log_cut = kDefaultLogCut;
   ShapeDev *shd;
@@ -484,10 +491,13 @@ hipError_t timed(gs_batch *B, int kernel, hipStream_t st, F f) {
 // One adjoint-path evaluation of every toy: cells, fold, -ln L, adjoint,
 // gradient.  One-dimensional toys fold with the combined weight; toys with a
 // secondary observable fold per species and expand over the pulse-shape bins.
+// view: the batch's own (every toy) or a compacted copy of it.
 gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
-                           double *d_mu, hipStream_t st, const uint8_t *active = nullptr) {
+                           double *d_mu, hipStream_t st, const uint8_t *active = nullptr,
+                           const BatchView *view = nullptr) {
+  BatchView v = view ? *view : B->v;
+  v.theta_dev = d_theta;
   B->v.theta_dev = d_theta;
-  const BatchView &v = B->v;
   HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, active, st); }));
   if (v.has_1d) {
     HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold(v, false, kOnly1D, active, st); }));
@@ -845,6 +855,9 @@ static gs_status qn_setup(gs_batch *B) {
   HIP_TRY(B->alloc(&B->d_scale, (size_t)P));
   HIP_TRY(B->alloc(&B->d_count, 1));
   HIP_TRY(hipHostMalloc((void **)&B->h_count, sizeof(int), hipHostMallocDefault));
+  HIP_TRY(B->alloc(&B->d_toy_list, (size_t)n));
+  HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->fold_h.size(), 1)));
+  HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->adj_h.size(), 1)));
   std::vector<int> np(n);
   for (int t = 0; t < n; t++) np[t] = B->toys_h[t].P;
   HIP_TRY(hipMemcpy(q.n_par, np.data(), sizeof(int) * n, hipMemcpyHostToDevice));
@@ -857,8 +870,13 @@ static gs_status qn_setup(gs_batch *B) {
 
 // Capture K iterations of [evaluate every active toy at its trial point,
 // quasi-Newton step] followed by a count of the active toys.
-static gs_status qn_graph(gs_batch *B, int K, double tol, int max_iter) {
-  if (B->graph && B->graph_k == K && B->graph_tol == tol && B->graph_max_iter == max_iter) return GS_OK;
+// Captures K x [evaluate the trial points, BFGS step] plus the active count.
+// view == NULL: every toy; else a compacted view (toy list and work items of
+// the toys still running), captured afresh.
+static gs_status qn_graph(gs_batch *B, int K, double tol, int max_iter, const BatchView *view = nullptr) {
+  if (!view && B->graph && !B->graph_compact && B->graph_k == K && B->graph_tol == tol &&
+      B->graph_max_iter == max_iter)
+    return GS_OK;
   if (B->graph) {
     HIP_TRY(hipGraphExecDestroy(B->graph));
     B->graph = nullptr;
@@ -866,11 +884,14 @@ static gs_status qn_graph(gs_batch *B, int K, double tol, int max_iter) {
   const bool prof = B->prof;
   B->prof = false;  // no timing events inside the graph
   hipStream_t st = B->fit_stream;
+  const int n_rows = view ? view->n_list : B->n_toys;
+  const int *list = view ? view->toy_list : nullptr;
   HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   gs_status s = GS_OK;
   for (int k = 0; k < K && s == GS_OK; k++) {
-    s = enqueue_nll_grad(B, B->q.xt, B->e_nll, B->e_grad, B->e_st, nullptr, st, B->q.active);
-    if (s == GS_OK && launch_qn_step(B->q, B->n_toys, B->e_nll, B->e_grad, B->e_st, tol, max_iter, st) != hipSuccess)
+    s = enqueue_nll_grad(B, B->q.xt, B->e_nll, B->e_grad, B->e_st, nullptr, st, B->q.active, view);
+    if (s == GS_OK &&
+        launch_qn_step(B->q, n_rows, list, B->e_nll, B->e_grad, B->e_st, tol, max_iter, st) != hipSuccess)
       s = fail(GS_ERR_DEVICE, "launch_qn_step failed during capture");
   }
   if (s == GS_OK && launch_qn_count(B->q.active, B->n_toys, B->d_count, st) != hipSuccess)
@@ -889,6 +910,39 @@ static gs_status qn_graph(gs_batch *B, int K, double tol, int max_iter) {
   B->graph_k = K;
   B->graph_tol = tol;
   B->graph_max_iter = max_iter;
+  B->graph_compact = view != nullptr;
+  return GS_OK;
+}
+
+// The toys still running and their fold / adjoint items, uploaded to the
+// batch's compaction buffers; returns the view that covers only them.
+static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
+  std::vector<uint8_t> act((size_t)B->n_toys);
+  HIP_TRY(hipMemcpyAsync(act.data(), B->q.active, act.size(), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int> list;
+  for (int t = 0; t < B->n_toys; t++)
+    if (act[t]) list.push_back(t);
+  std::vector<FoldItem> fi;
+  std::vector<AdjItem> ai;
+  for (const FoldItem &it : B->fold_h)
+    if (act[it.toy]) fi.push_back(it);
+  for (const AdjItem &it : B->adj_h)
+    if (act[it.toy]) ai.push_back(it);
+  if (!list.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_toy_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, st));
+  if (!fi.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_fold_c, fi.data(), sizeof(FoldItem) * fi.size(), hipMemcpyHostToDevice, st));
+  if (!ai.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_adj_c, ai.data(), sizeof(AdjItem) * ai.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
+  out = B->v;
+  out.toy_list = B->d_toy_list;
+  out.n_list = (int)list.size();
+  out.fold_items = B->d_fold_c;
+  out.n_fold_items = (int)fi.size();
+  out.adj_items = B->d_adj_c;
+  out.n_adj_items = (int)ai.size();
   return GS_OK;
 }
 
@@ -912,6 +966,7 @@ gs_status gs_fit_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_f
   HIP_TRY(launch_qn_init(B->q, B->n_toys, d_theta0, d_free, d_scale ? d_scale : B->d_scale, d_scale ? B->stride : 0,
                          st));
   constexpr int K = 8;
+  constexpr int kCompactMin = 16;  // below this many toys a smaller graph no longer pays
   s = qn_graph(B, K, o->edm_tol, o->max_iter);
   if (s != GS_OK) return s;
   // an iteration is one evaluation; a fit needs max_iter accepted steps plus line-search trials
@@ -919,13 +974,23 @@ gs_status gs_fit_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_f
   B->trace_active.clear();
   B->trace_ms.clear();
   const auto t0 = std::chrono::steady_clock::now();
+  int rows = B->n_toys;  // toys the current graph's grids cover
   for (long long done = 0; done < cap; done += K) {
     HIP_TRY(hipGraphLaunch(B->graph, st));
     HIP_TRY(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    B->trace_active.push_back(*B->h_count);
+    const int running = *B->h_count;
+    B->trace_active.push_back(running);
     B->trace_ms.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
-    if (*B->h_count == 0) break;
+    if (running == 0) break;
+    // once half of the covered toys have stopped, re-capture the graph over the rest
+    if (2 * running <= rows && rows > kCompactMin) {
+      BatchView cv;
+      s = compact_view(B, st, cv);
+      if (s == GS_OK) s = qn_graph(B, K, o->edm_tol, o->max_iter, &cv);
+      if (s != GS_OK) return s;
+      rows = running;
+    }
   }
   HIP_TRY(launch_qn_final(B->q, B->n_toys, d_theta_hat, d_nll_hat, d_sigma, d_iters, d_status, st));
   HIP_TRY(hipEventRecord(B->ev_out, st));

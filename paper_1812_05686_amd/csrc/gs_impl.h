@@ -67,6 +67,8 @@ struct AdjItem {
 // Device views of one batch, passed by value to the launchers.
 struct BatchView {
   int n_toys, stride;
+  const int *toy_list;  // per-toy grids cover toy_list[0 .. n_list) (NULL: every toy, n_list = n_toys)
+  int n_list;
   int max_cells, max_cell_blocks, max_bin_blocks;
   double log_cut;   // pairs whose log-density is below this are skipped
   const ToyDev *toys;

@@ -49,6 +49,10 @@ __device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_cw(
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Toy handled by grid row b: every toy in order, or the b-th entry of a
+// compacted list of toys (batched fits drop finished toys from the grids).
+__device__ __forceinline__ int toy_of(const int *__restrict__ list, int b) { return list ? list[b] : b; }
+
 // Workgroups are dispatched round-robin over the 8 XCDs; map block b to an
 // item so that each XCD works through a contiguous, toy-major range of items
 // and the cell records of one toy stay in one XCD's L2.
@@ -81,12 +85,12 @@ __device__ double block_sum(double v, double *lds) {
 __device__ __forceinline__ void put_support(double *rc, int2 s) { *(int2 *)(rc + 6) = s; }
 __device__ __forceinline__ int2 get_support(const double *rc) { return *(const int2 *)(rc + 6); }
 
-__global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride, double log_cut,
                                                const uint8_t *__restrict__ active, double *__restrict__ rec,
                                                int2 *__restrict__ sup, int2 *__restrict__ ghull,
                                                uint32_t *__restrict__ cflag) {
-  const int t = blockIdx.y;
+  const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.cflag_blocks) return;
@@ -131,8 +135,8 @@ __global__ __launch_bounds__(64) void k_cells(const ToyDev *__restrict__ toys, c
 }
 
 hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
-  dim3 grid(v.max_cflag_blocks, v.n_toys);
-  hipLaunchKernelGGL(k_cells, grid, dim3(kCellBlock), 0, st, v.toys, v.shapes, theta, v.stride, v.log_cut, active,
+  dim3 grid(v.max_cflag_blocks, v.n_list);
+  hipLaunchKernelGGL(k_cells, grid, dim3(kCellBlock), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, v.log_cut, active,
                      v.rec, v.sup, v.ghull, v.cflag);
   return hipGetLastError();
 }
@@ -485,14 +489,14 @@ __device__ __forceinline__ bool poisson_term(double mu, double n, double &term, 
   return mu == 0.0 && n == 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_bins1(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ fpart, const double *__restrict__ cnt,
                                                const uint8_t *__restrict__ active, double *__restrict__ binrec,
                                                double *__restrict__ nllp, uint32_t *__restrict__ badp,
                                                double *__restrict__ mu_out) {
   __shared__ double lds[8];
   __shared__ int bad_s;
-  const int t = blockIdx.y;
+  const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(256) void k_bins1(const ToyDev *__restrict__ toys, 
 }
 
 hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_bins1, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, v.fpart,
+  hipLaunchKernelGGL(k_bins1, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, v.fpart,
                      v.cnt, active, v.binrec, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
@@ -708,12 +712,12 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
 }
 
 // ----------------------------------------------------------- k_cellgrad ---
-__global__ __launch_bounds__(256) void k_cellgrad(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                   const double *__restrict__ theta, int stride,
                                                   const double *__restrict__ rec, const double *__restrict__ apart,
                                                   const uint8_t *__restrict__ active, double *__restrict__ gpart) {
   __shared__ double part[kBlock / 64][kGradLen];
-  const int t = blockIdx.y;
+  const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.cell_blocks) return;
@@ -792,14 +796,14 @@ __global__ __launch_bounds__(256) void k_cellgrad(const ToyDev *__restrict__ toy
 }
 
 hipError_t launch_cellgrad(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_cellgrad, dim3(v.max_cell_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, theta,
+  hipLaunchKernelGGL(k_cellgrad, dim3(v.max_cell_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
                      v.stride, v.rec, v.apart, active, v.gpart);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------- k_finish ---
 // Thread p < stride: gradient entry p; thread 0 also -ln L and status.
-__global__ __launch_bounds__(64) void k_finish(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(64) void k_finish(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ nllp, const uint32_t *__restrict__ badp,
                                                const uint32_t *__restrict__ cflag, const double *__restrict__ gpart,
@@ -809,30 +813,35 @@ __global__ __launch_bounds__(64) void k_finish(const ToyDev *__restrict__ toys, 
                                                double *__restrict__ nll, double *__restrict__ grad,
                                                uint32_t *__restrict__ status) {
   __shared__ uint32_t st_s;
-  const int t = blockIdx.x;
+  const int t = toy_of(toy_list, blockIdx.x);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
   const int p = threadIdx.x;
+  // flags and pull terms spread over the lanes (no serial chain of loads)
+  bool dom = false, nonfin = false;
+  for (int b = p; b < T.bin_blocks; b += 64) dom = dom || badp[T.nllp_off + b] != 0;
+  for (int b = p; b < T.cflag_blocks; b += 64)
+    dom = dom || cflag[T.cflag_off + b] != 0;  // invalid response somewhere on the grid
+  double pull = 0.0;
+  if (p < T.P) {
+    nonfin = !isfinite(th[p]);
+    const double s = pull_s[T.pull_off + p];
+    if (s > 0.0) {
+      const double z = (th[p] - pull_c[T.pull_off + p]) / s;
+      pull = 0.5 * z * z;
+    }
+  }
+  pull = wave_sum(pull);
+  const bool any_dom = __ballot(dom) != 0ull, any_nonfin = __ballot(nonfin) != 0ull;
   if (p == 0) {
     uint32_t st = 0;
     double sum = 0.0;
-    for (int b = 0; b < T.bin_blocks; b++) {
-      sum += nllp[T.nllp_off + b];
-      if (badp[T.nllp_off + b]) st |= GS_ST_DOMAIN;
-    }
-    for (int b = 0; b < T.cflag_blocks; b++)
-      if (cflag[T.cflag_off + b]) st |= GS_ST_DOMAIN;  // invalid response somewhere on the grid
-    if (T.two_d && pflag[t]) st |= GS_ST_DOMAIN;     // invalid pulse-shape nuisance
-    for (int q = 0; q < T.P; q++) {
-      if (!isfinite(th[q])) st |= GS_ST_NONFINITE;
-      const double s = pull_s[T.pull_off + q];
-      if (s > 0.0) {
-        const double z = (th[q] - pull_c[T.pull_off + q]) / s;
-        sum = __fma_rn(0.5 * z, z, sum);
-      }
-    }
+    for (int b = 0; b < T.bin_blocks; b++) sum += nllp[T.nllp_off + b];
+    sum += pull;
+    if (any_dom || (T.two_d && pflag[t])) st |= GS_ST_DOMAIN;  // pflag: invalid pulse-shape nuisance
+    if (any_nonfin) st |= GS_ST_NONFINITE;
     if (st & GS_ST_NONFINITE) {
       st = GS_ST_NONFINITE;  // a non-finite parameter explains every other symptom
       sum = __builtin_nan("");
@@ -870,7 +879,7 @@ __global__ __launch_bounds__(64) void k_finish(const ToyDev *__restrict__ toys, 
 
 hipError_t launch_finish(const BatchView &v, const double *theta, double *nll, double *grad, uint32_t *status,
                          const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish, dim3(v.n_toys), dim3(64), 0, st, v.toys, v.shapes, theta, v.stride, v.nllp, v.badp,
+  hipLaunchKernelGGL(k_finish, dim3(v.n_list), dim3(64), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, v.nllp, v.badp,
                      v.cflag, v.gpart, v.vpart, v.pflag, v.pull_c, v.pull_s, active, nll, grad, status);
   return hipGetLastError();
 }
@@ -897,10 +906,10 @@ hipError_t launch_bins_setup(double *bins, const double *edges, int n_reco, hipS
 
 // ---------------------------------------------- per-species (plain path) --
 // F[(win_off + b) * S + s] = dx_b * sum over chunks (fixed order).
-__global__ __launch_bounds__(256) void k_reduceF(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                  const double *__restrict__ fspart, int mode,
                                                  const uint8_t *__restrict__ active, double *__restrict__ F) {
-  const int t = blockIdx.y;
+  const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if (mode >= 0 && T.two_d != mode) return;
@@ -916,20 +925,20 @@ __global__ __launch_bounds__(256) void k_reduceF(const ToyDev *__restrict__ toys
 }
 
 hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduceF, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, v.fspart,
+  hipLaunchKernelGGL(k_reduceF, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, v.fspart,
                      mode, active, v.F);
   return hipGetLastError();
 }
 
 // -ln L block partials from cached per-species spectra: mu_dj = eps_d sum_s R_s F_js.
-__global__ __launch_bounds__(256) void k_binsF(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256) void k_binsF(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ F, const double *__restrict__ cnt,
                                                double *__restrict__ nllp, uint32_t *__restrict__ badp,
                                                double *__restrict__ mu_out) {
   __shared__ double lds[8];
   __shared__ int bad_s;
-  const int t = blockIdx.y;
+  const int t = toy_of(toy_list, blockIdx.y);
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
@@ -962,7 +971,7 @@ __global__ __launch_bounds__(256) void k_binsF(const ToyDev *__restrict__ toys, 
 }
 
 hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_binsF, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, theta,
+  hipLaunchKernelGGL(k_binsF, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
                      v.stride, v.F, v.cnt, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
@@ -973,11 +982,11 @@ hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out,
 // mixture at the bin midpoints, means shifted by delta, widths scaled by
 // kappa, odds of component 1 multiplied by exp(eta), renormalised over the
 // bins; with their derivatives w.r.t. (delta, kappa, eta).  One thread per species.
-__global__ __launch_bounds__(64) void k_psd(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(64) void k_psd(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                             const double *__restrict__ theta, int stride,
                                             const uint8_t *__restrict__ active, double *__restrict__ P,
                                             double *__restrict__ dP, uint32_t *__restrict__ pflag) {
-  const int t = blockIdx.x;
+  const int t = toy_of(toy_list, blockIdx.x);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if (!T.two_d) return;
@@ -1027,14 +1036,14 @@ __global__ __launch_bounds__(64) void k_psd(const ToyDev *__restrict__ toys, con
 }
 
 hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_psd, dim3(v.n_toys), dim3(64), 0, st, v.toys, v.shapes, theta, v.stride, active, v.P, v.dP,
+  hipLaunchKernelGGL(k_psd, dim3(v.n_list), dim3(64), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, active, v.P, v.dP,
                      v.pflag);
   return hipGetLastError();
 }
 
 // Per (toy, 256 energy bins): mu_djk = eps_d sum_s R_s F_js P_sk, Poisson terms,
 // Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), H_js = dx_j sum_k P_sk Gam_jk.
-__global__ __launch_bounds__(256) void k_bins2(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ F, const double *__restrict__ P,
                                                const double *__restrict__ cnt, const uint8_t *__restrict__ active,
@@ -1044,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_bins2(const ToyDev *__restrict__ toys, 
   __shared__ double lds[8];
   __shared__ double Ps[GS_MAX_SPECIES * GS_MAX_PSD];
   __shared__ int bad_s;
-  const int t = blockIdx.y;
+  const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || !T.two_d) return;
@@ -1108,18 +1117,18 @@ __global__ __launch_bounds__(256) void k_bins2(const ToyDev *__restrict__ toys, 
 
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks, v.n_toys), dim3(kBlock), 0, st, v.toys, v.shapes, theta,
+  hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
                      v.stride, v.F, v.P, v.cnt, active, v.binrec, v.H, v.Gam, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
 
 // Per (toy, species s): V_sk = sum_j F_js Gam_jk, reduced to sum_k P_sk V_sk (the
 // rate gradient) and sum_k dP_sk/dnu V_sk (times R_s in k_finish: nuisance gradients).
-__global__ __launch_bounds__(64) void k_vpart(const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(64) void k_vpart(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                               const double *__restrict__ F, const double *__restrict__ Gam,
                                               const double *__restrict__ P, const double *__restrict__ dP,
                                               const uint8_t *__restrict__ active, double *__restrict__ vpart) {
-  const int t = blockIdx.y, s = blockIdx.x;
+  const int t = toy_of(toy_list, blockIdx.y), s = blockIdx.x;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if (!T.two_d || s >= T.S) return;
@@ -1139,7 +1148,7 @@ __global__ __launch_bounds__(64) void k_vpart(const ToyDev *__restrict__ toys, c
 }
 
 hipError_t launch_vpart(const BatchView &v, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_vpart, dim3(GS_MAX_SPECIES, v.n_toys), dim3(64), 0, st, v.toys, v.shapes, v.F, v.Gam, v.P,
+  hipLaunchKernelGGL(k_vpart, dim3(GS_MAX_SPECIES, v.n_list), dim3(64), 0, st, v.toy_list, v.toys, v.shapes, v.F, v.Gam, v.P,
                      v.dP, active, v.vpart);
   return hipGetLastError();
 }

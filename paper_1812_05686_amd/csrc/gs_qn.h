@@ -21,8 +21,10 @@ struct QNView {
 
 hipError_t launch_qn_init(const QNView &q, int n, const double *theta0, const uint8_t *free_mask,
                           const double *scale, int scale_stride, hipStream_t st);
-hipError_t launch_qn_step(const QNView &q, int n, const double *nll_eval, const double *grad_eval,
-                          const uint32_t *st_eval, double edm_tol, int max_iter, hipStream_t st);
+// Grid rows are toys 0 .. n-1, or toy_list[0 .. n) when toy_list is not NULL.
+hipError_t launch_qn_step(const QNView &q, int n, const int *toy_list, const double *nll_eval,
+                          const double *grad_eval, const uint32_t *st_eval, double edm_tol, int max_iter,
+                          hipStream_t st);
 hipError_t launch_qn_count(const uint8_t *active, int n, int *out, hipStream_t st);
 hipError_t launch_qn_final(const QNView &q, int n, double *theta_hat, double *nll, double *sigma, int32_t *iters,
                            uint32_t *status, hipStream_t st);

@@ -43,10 +43,11 @@ __global__ __launch_bounds__(64) void k_qn_init(QNView q, const double *__restri
   }
 }
 
-__global__ __launch_bounds__(64) void k_qn_step(QNView q, const double *__restrict__ nll_eval,
+__global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict__ toy_list,
+                                                const double *__restrict__ nll_eval,
                                                 const double *__restrict__ grad_eval,
                                                 const uint32_t *__restrict__ st_eval, double edm_tol, int max_iter) {
-  const int t = blockIdx.x, p = threadIdx.x, P = q.P;
+  const int t = toy_list ? toy_list[blockIdx.x] : (int)blockIdx.x, p = threadIdx.x, P = q.P;
   if (!q.active[t]) return;
   const size_t r = (size_t)t * P;
   const bool lane = p < P;
@@ -204,9 +205,11 @@ hipError_t launch_qn_init(const QNView &q, int n, const double *theta0, const ui
   return hipGetLastError();
 }
 
-hipError_t launch_qn_step(const QNView &q, int n, const double *nll_eval, const double *grad_eval,
-                          const uint32_t *st_eval, double edm_tol, int max_iter, hipStream_t st) {
-  hipLaunchKernelGGL(k_qn_step, dim3(n), dim3(64), 0, st, q, nll_eval, grad_eval, st_eval, edm_tol, max_iter);
+hipError_t launch_qn_step(const QNView &q, int n, const int *toy_list, const double *nll_eval,
+                          const double *grad_eval, const uint32_t *st_eval, double edm_tol, int max_iter,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_qn_step, dim3(n), dim3(64), 0, st, q, toy_list, nll_eval, grad_eval, st_eval, edm_tol,
+                     max_iter);
   return hipGetLastError();
 }
 

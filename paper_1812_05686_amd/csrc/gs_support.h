@@ -59,52 +59,75 @@ GS_HD inline int bin_above(const double *bins, int n, double x, double bx0, doub
 }
 
 // Interval [xl, xr] outside of which the gamma log-density
-// (k-1) ln x - x/th + C is at most T.  In u = ln x it reads
-// E(u) = (k-1) u - e^u/th + C, concave for every k (in x it is convex when
-// k < 1).  Newton's method on a concave function, started outside a root,
-// approaches the root monotonically without crossing it (the tangent lies
-// above the function), so every iterate is a conservative end point;
-// iterating stops once a step moves x by less than 2% of the standard
-// deviation, far below a bin at these widths.
-GS_HD inline bool gamma_support(double k, double th, double C, double T, double &xl, double &xr) {
-  auto E = [&](double u) { return (k - 1.0) * u - exp(u) / th + C; };
-  auto dE = [&](double u) { return (k - 1.0) - exp(u) / th; };
-  const double sd = sqrt(k) * th;
-  const double tol = 0.02 * sd;
-  double xm = 0.0, w = fmax(sd, th);
+// E(x) = (k-1) ln x - x/th + C is at most T; xl = -inf when the interval
+// reaches below x_lo (the smallest positive bin midpoint, or 0 if none).
+//
+// Newton's method on a concave function, started outside a root, approaches
+// the root monotonically without crossing it (the tangent lies above the
+// function), so every iterate is a conservative end point.  In u = ln x,
+// E = (k-1) u - e^u/th + C is concave for every k and nearly linear far to
+// the left; for k > 1 it is also concave in x and nearly linear far to the
+// right.  So the right end is found in x when k > 1, the left end (k > 1
+// only: for k <= 1 the density does not vanish at 0) and the k <= 1 right
+// end in u.  Iterating stops once a step moves x by less than 2% of the
+// standard deviation, far below a bin at these widths.
+GS_HD inline bool gamma_support(double k, double th, double C, double T, double x_lo, double &xl, double &xr) {
+  const double sd = sqrt(k) * th, tol = 0.02 * sd, ith = 1.0 / th;
+  auto Ex = [&](double x) { return (k - 1.0) * log(x) - x * ith + C; };
+  xl = -INFINITY;
   if (k > 1.0) {
-    xm = (k - 1.0) * th;
-    const double Em = E(log(xm));
+    const double xm = (k - 1.0) * th;
+    const double Em = Ex(xm);
     if (!(Em > T)) return false;
-    w = sd * sqrt(2.0 * (Em - T)) + sd;
+    const double w = sd * sqrt(2.0 * (Em - T)) + sd;
+    // right end, in x
+    double x = xm + w;
+    for (int i = 0; i < 80 && Ex(x) > T; i++) x = xm + 2.0 * (x - xm);
+    for (int i = 0; i < 40; i++) {
+      const double nx = x - (Ex(x) - T) / ((k - 1.0) / x - ith);
+      if (!(nx < x)) break;
+      const bool done = x - nx < tol;
+      x = nx;
+      if (done) break;
+    }
+    xr = x;
+    // left end, in u, from a point where E <= T that is not below the first bin
+    const double floor_x = x_lo > 0.0 ? x_lo : xm * 0x1p-64;
+    if (!(floor_x < xm) || Ex(floor_x) > T) return true;  // the support reaches the lowest bin
+    x = xm - w;
+    if (!(x > floor_x) || Ex(x) > T) x = floor_x;
+    double u = log(x), ex = x;
+    const double um = log(xm);
+    for (int q = 0; q < 40; q++) {
+      const double nu = u - ((k - 1.0) * u - ex * ith + C - T) / ((k - 1.0) - ex * ith);
+      if (!(nu > u) || !(nu < um)) break;
+      const double nex = exp(nu);
+      const bool done = nex - ex < tol;
+      u = nu;
+      ex = nex;
+      if (done) break;
+    }
+    xl = ex;
+    return true;
   }
-  // right end: E decreasing there
-  double u = log(xm + w);
-  for (int i = 0; i < 80 && E(u) > T; i++) u += 0.6931471805599453;
-  for (int i = 0; i < 40; i++) {
-    const double nu = u - (E(u) - T) / dE(u);
+  // k <= 1: right end, in u, from just outside x = th (C - T), where the
+  // decreasing density meets T if the log term is ignored
+  double u = log(th * fmax(C - T, 1.0) + sd);
+  double ex = exp(u);
+  for (int i = 0; i < 80 && (k - 1.0) * u - ex * ith + C > T; i++) {
+    u += 0.6931471805599453;
+    ex = exp(u);
+  }
+  for (int i = 0; i < 60; i++) {
+    const double nu = u - ((k - 1.0) * u - ex * ith + C - T) / ((k - 1.0) - ex * ith);
     if (!(nu < u)) break;
-    const bool done = exp(u) - exp(nu) < tol;
+    const double nex = exp(nu);
+    const bool done = ex - nex < tol;
     u = nu;
+    ex = nex;
     if (done) break;
   }
-  xr = exp(u);
-  xl = -INFINITY;
-  if (k > 1.0) {  // left end: E increasing below the mode (for k <= 1 the density has no left end)
-    const double um = log(xm);
-    u = xm - w > 0.0 ? log(xm - w) : um - 0.6931471805599453;
-    for (int i = 0; i < 1100 && E(u) > T; i++) u -= 0.6931471805599453;
-    if (E(u) <= T) {
-      for (int q = 0; q < 40; q++) {
-        const double nu = u - (E(u) - T) / dE(u);
-        if (!(nu > u) || !(nu < um)) break;
-        const bool done = exp(nu) - exp(u) < tol;
-        u = nu;
-        if (done) break;
-      }
-      xl = exp(u);
-    }
-  }
+  xr = ex;
   return true;
 }
 
@@ -118,7 +141,10 @@ GS_HD inline Span cell_support(int fam, const double *rc, double m, double s, bo
   double xl, xr;
   if (fam == kGammaPE) {
     const double s2 = s * s;
-    if (!gamma_support(m * m / s2, s2 / m, rc[3] + rc[4], T, xl, xr)) return {0, 0};
+    // smallest positive bin midpoint (the midpoints increase)
+    const int jp = bin_above(bins, n_reco, 0.0, bx0, bw);
+    const double x_lo = jp < n_reco ? bins[(size_t)jp * kBinLen] : 0.0;
+    if (!gamma_support(m * m / s2, s2 / m, rc[3] + rc[4], T, x_lo, xl, xr)) return {0, 0};
   } else {
     const double c0 = rc[2];
     if (!(c0 > T)) return {0, 0};
