@@ -740,10 +740,21 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
     }
     Moments mo;
     moments(fam, th + Sh.S, Sh.birks_A, Sh.cellE[i], mo);
-    const double *rc = rec + (T.cell_off + i) * kRecLen;
+    // the 1-D combined weight W_i = sum_s R_s w_si, recomputed from the shape's weights
+    // (shared by every toy of the shape) rather than read back from the cell record
+    double W = 1.0;
+    if (!T.two_d) {
+      if (i < Sh.n_true) {
+        const double *w = Sh.wcell + (size_t)i * Sh.Sg;
+        W = 0.0;
+        for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[s], W);
+      } else {
+        W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
+      }
+    }
     double dNdm, dNds;
     if (fam == kGammaPE) {
-      const double W = T.two_d ? 1.0 : rc[5], m = mo.m, s = mo.s, s2 = s * s;
+      const double m = mo.m, s = mo.s, s2 = s * s;
       const double k = m * m / s2, thg = s2 / m, mk = k * thg;
       // shift the sums of ln x and x to ln x - ln(k th) and x - k th
       const double B1 = __fma_rn(-log(mk), A0, A1), B2 = __fma_rn(-mk, A0, A2);
@@ -752,7 +763,7 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
       dNdm = dk * (2.0 * m / s2) - dth * (s2 / (m * m));
       dNds = -dk * (2.0 * m * m / (s2 * s)) + dth * (2.0 * s / m);
     } else {
-      const double W = T.two_d ? 1.0 : rc[3], is = 1.0 / mo.s;
+      const double is = 1.0 / mo.s;
       dNdm = W * A1 * is;
       dNds = W * (A2 - A0) * is;
     }
