@@ -84,6 +84,67 @@ def cpu_baseline(toys, seconds, threads):
     return sum(counts) / el, sum(counts), el, out
 
 
+def mixed_batch(gs, gsgen, torch, n_toys, steps, warmup, with_oracle):
+    """The large uneven batch: energy-family, Borexino-like and pulse-shape toys together.
+    Batched -ln L + gradient evaluations per second, toy fits per second, and the oracle's
+    error on two toys of every class."""
+    t0 = time.perf_counter()
+    toys = gsgen.config4(n_toys)
+    gen_s = time.perf_counter() - t0
+    batch = gs.Batch(toys)
+    th = np.zeros((len(toys), batch.stride))
+    for t, m in enumerate(toys):
+        th[t, : m.n_params] = m.theta_true
+    theta = torch.tensor(th, dtype=torch.float64, device="cuda")
+    nll = torch.empty(len(toys), dtype=torch.float64, device="cuda")
+    grad = torch.empty(len(toys), batch.stride, dtype=torch.float64, device="cuda")
+    st = torch.empty(len(toys), dtype=torch.int32, device="cuda")
+    for _ in range(warmup):
+        batch.nll_grad(theta, nll, grad, st)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
+        batch.nll_grad(theta, nll, grad, st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ta
+    classes = [m.name.split("/")[1] for m in toys]
+    out = {"toys": len(toys), "classes": {c: classes.count(c) for c in sorted(set(classes))},
+           "evals_per_s": round(len(toys) * steps / el, 1), "ms_per_step": round(el * 1e3 / steps, 3),
+           "generator_s": round(gen_s, 1), "status_nonzero": int((st != 0).sum().item())}
+    th0 = np.zeros_like(th)
+    for t, m in enumerate(toys):
+        th0[t, : m.n_params] = m.theta0
+    th0 = torch.tensor(th0, dtype=torch.float64, device="cuda")
+    free, scales = batch.free_masks(toys), batch.scales(toys)
+    batch.fit(th0, scales, free=free)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = batch.fit(th0, scales, free=free)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ta
+    stt = r["status"].cpu().numpy()
+    out["fits_per_s"] = round(len(toys) / el, 1)
+    out["fits_seconds"] = round(el, 3)
+    out["fits_converged"] = int(np.sum(stt & 32 != 0))
+    if with_oracle:
+        import oracle
+        oracle.build(force=False)
+        gn, gg = nll.cpu().numpy(), grad.cpu().numpy()
+        seen, worst_nll, worst_grad = {}, 0.0, 0.0
+        for t, m in enumerate(toys):
+            c = classes[t]
+            if seen.get(c, 0) >= 2:
+                continue
+            seen[c] = seen.get(c, 0) + 1
+            ov, og, _ = oracle.Oracle(m).nll_grad(m.theta_true)
+            worst_nll = max(worst_nll, abs(gn[t] - ov) / abs(ov))
+            worst_grad = max(worst_grad, float(np.max(np.abs(gg[t, : m.n_params] - og) * m.fd_scale /
+                                                      np.maximum(np.abs(og) * m.fd_scale, 1.0))))
+        out["oracle_sample"] = {"toys": sum(seen.values()), "max_rel_dnll": worst_nll, "max_grad_err": worst_grad,
+                                "pass": bool(worst_nll <= 1e-11 and worst_grad <= 1e-8)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +154,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fits", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 16384-toy mixed batch")
+    ap.add_argument("--mixed-toys", type=int, default=16384)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -222,6 +285,11 @@ def main():
         fits["speedup_adjoint_over_fd"] = round(fits["finite_diff"]["seconds"] / fits["adjoint"]["seconds"], 2)
         log(f"bench: fits {fits}")
 
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_batch(gs, gsgen, torch, args.mixed_toys, args.steps, args.warmup, not args.no_cpu)
+        log(f"bench: mixed {mixed}")
+
     cpu = None
     parity = None
     if not args.no_cpu:
@@ -247,7 +315,7 @@ def main():
                       "full_mesh_pairs_per_step": pairs},
            "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "toy_fits": toy_fits,
            "single_eval": {"us_per_eval": round(single_us, 2), "evals_per_s": round(1e6 / single_us, 1)},
-           "single_fit_borexino_scale": fits}
+           "single_fit_borexino_scale": fits, "mixed_batch": mixed}
     print(json.dumps(out))
 
 
