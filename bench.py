@@ -285,6 +285,27 @@ def main():
         fits["speedup_adjoint_over_fd"] = round(fits["finite_diff"]["seconds"] / fits["adjoint"]["seconds"], 2)
         log(f"bench: fits {fits}")
 
+    # the multi-observable model: 12 species x 900 energy x 50 pulse-shape bins x 3 datasets
+    two_d = None
+    if not args.no_fits:
+        c2 = gsgen.config2()
+        m2 = gs.Model(c2)
+        for _ in range(5):
+            m2.nll_grad(c2.theta0)
+        ta = time.perf_counter()
+        for _ in range(50):
+            m2.nll_grad(c2.theta0)
+        us2 = (time.perf_counter() - ta) * 1e6 / 50
+        two_d = {"bins": int(c2.counts.size), "us_per_eval": round(us2, 2)}
+        for name, fd in (("adjoint", False), ("finite_diff", True)):
+            m2.fit(c2.theta0, c2.fd_scale, use_fd=fd, hesse=False)
+            ta = time.perf_counter()
+            r = m2.fit(c2.theta0, c2.fd_scale, use_fd=fd, hesse=False)
+            el = time.perf_counter() - ta
+            two_d[name] = dict(seconds=round(el, 4), iters=r["iters"], n_eval=r["n_eval"], converged=r["ok"],
+                               nll=r["nll"])
+        log(f"bench: 2-D model {two_d}")
+
     mixed = None
     if not args.no_mixed:
         mixed = mixed_batch(gs, gsgen, torch, args.mixed_toys, args.steps, args.warmup, not args.no_cpu)
@@ -315,7 +336,7 @@ def main():
                       "full_mesh_pairs_per_step": pairs},
            "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "toy_fits": toy_fits,
            "single_eval": {"us_per_eval": round(single_us, 2), "evals_per_s": round(1e6 / single_us, 1)},
-           "single_fit_borexino_scale": fits, "mixed_batch": mixed}
+           "single_fit_borexino_scale": fits, "two_d_model": two_d, "mixed_batch": mixed}
     print(json.dumps(out))
 
 

@@ -176,7 +176,7 @@ struct gs_batch {
   double graph_tol = -1.0;
   bool graph_compact = false;  // the instantiated graph covers a compacted toy list
   // compacted toy and work-item lists of a batched fit (device copies)
-  int *d_toy_list = nullptr;
+  int *d_toy_list = nullptr, *d_list1 = nullptr, *d_list2 = nullptr;
   FoldItem *d_fold_c = nullptr;
   AdjItem *d_adj_c = nullptr;
 
@@ -231,6 +231,39 @@ namespace {
 // batches keep whole tiles (one chunk) so no partial sums are needed.
 constexpr int kTargetWG = 2048;
 constexpr double kDefaultLogCut = -60.0;
+
+// Splits work items by the kind of their toy (1-D first, then 2-D: items of a
+// toy stay contiguous and in order) and uploads them to dst; sets the view's
+// per-kind pointers into dst.
+static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, const std::vector<AdjItem> &ai,
+                              FoldItem *dst_f, AdjItem *dst_a, BatchView &v, hipStream_t st) {
+  std::vector<FoldItem> f;
+  std::vector<AdjItem> a;
+  for (int kind = 0; kind < 2; kind++) {
+    for (const FoldItem &it : fi)
+      if (B->toys_h[it.toy].two_d == kind) f.push_back(it);
+    for (const AdjItem &it : ai)
+      if (B->toys_h[it.toy].two_d == kind) a.push_back(it);
+    if (kind == 0) {
+      v.n_fold1 = (int)f.size();
+      v.n_adj1 = (int)a.size();
+    }
+  }
+  v.n_fold2 = (int)f.size() - v.n_fold1;
+  v.n_adj2 = (int)a.size() - v.n_adj1;
+  if (!f.empty()) HIP_TRY(hipMemcpyAsync(dst_f, f.data(), sizeof(FoldItem) * f.size(), hipMemcpyHostToDevice, st));
+  if (!a.empty()) HIP_TRY(hipMemcpyAsync(dst_a, a.data(), sizeof(AdjItem) * a.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));  // the host vectors go out of scope
+  v.fold_items = dst_f;
+  v.n_fold_items = (int)f.size();
+  v.adj_items = dst_a;
+  v.n_adj_items = (int)a.size();
+  v.fold1 = dst_f;
+  v.fold2 = dst_f + v.n_fold1;
+  v.adj1 = dst_a;
+  v.adj2 = dst_a + v.n_adj1;
+  return GS_OK;
+}
 
 gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_batch **out) {
   if (!descs || n_toys < 1) return fail(GS_ERR_ARG, "need at least one descriptor");
@@ -342,7 +375,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
   const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
   long long cell_off = 0, win_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
-  long long nllp_off = 0, gpart_off = 0, cflag_off = 0, gam_off = 0, psd_off = 0, ghull_off = 0;
+  long long nllp_off = 0, gpart_off = 0, cflag_off = 0, vpart_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0;
   std::vector<double> cnt_h, pc_h, ps_h;
   BatchView &v = B->v;
   for (int t = 0; t < n_toys; t++) {
@@ -356,10 +389,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.P = P[t];
     T.K = std::max(d.n_psd, 1);
     T.two_d = d.n_psd > 0 ? 1 : 0;
-    T.gam_off = gam_off;
     T.psd_off = psd_off;
     if (T.two_d) {
-      gam_off += (long long)T.L * T.K;
       psd_off += (long long)sh.S * T.K;
       v.has_2d = true;
     } else {
@@ -373,7 +404,14 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
     const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
-    T.bin_blocks = (T.L + kBlock - 1) / kBlock;
+    T.bin_blocks = T.two_d ? (int)(((long long)T.L * T.K + kBlock - 1) / kBlock) : (T.L + kBlock - 1) / kBlock;
+    T.hblocks = T.two_d ? (T.L + kHTile - 1) / kHTile : 0;
+    T.vpart_off = vpart_off;
+    T.gam_off = gam_off;
+    if (T.two_d) {
+      vpart_off += T.hblocks + T.bin_blocks;
+      gam_off += (long long)T.L * T.K;
+    }
     T.cell_blocks = (sh.n_cell + kBlock - 1) / kBlock;
     T.cflag_blocks = (sh.n_cell + kCellBlock - 1) / kCellBlock;
     T.cflag_off = cflag_off;
@@ -416,11 +454,19 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
     v.max_cflag_blocks = std::max(v.max_cflag_blocks, T.cflag_blocks);
     v.max_bin_blocks = std::max(v.max_bin_blocks, T.bin_blocks);
+    (T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1) =
+        std::max(T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1, T.bin_blocks);
+    v.max_ls_blocks = std::max(v.max_ls_blocks, (int)(((long long)T.L * T.S + kBlock - 1) / kBlock));
+    if (T.two_d) v.max_psd_sk = std::max(v.max_psd_sk, T.S * T.K);
+    v.max_hblocks = std::max(v.max_hblocks, T.hblocks);
     B->toys_h.push_back(T);
   }
   v.n_toys = n_toys;
   v.toy_list = nullptr;
   v.n_list = n_toys;
+  v.list1d = v.list2d = nullptr;
+  v.n1d = v.n2d = 0;
+  for (const ToyDev &T : B->toys_h) (T.two_d ? v.n2d : v.n1d)++;
   v.stride = B->stride;
   v.log_cut = kDefaultLogCut;
   ShapeDev *shd;
@@ -442,10 +488,10 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.pflag, (size_t)n_toys));
   if (v.has_2d) {
     HIP_TRY(B->alloc(&v.H, (size_t)win_off * GS_MAX_SPECIES));
-    HIP_TRY(B->alloc(&v.Gam, (size_t)gam_off));
     HIP_TRY(B->alloc(&v.P, (size_t)psd_off));
     HIP_TRY(B->alloc(&v.dP, (size_t)psd_off * 3));
-    HIP_TRY(B->alloc(&v.vpart, (size_t)n_toys * GS_MAX_SPECIES * 4));
+    HIP_TRY(B->alloc(&v.vpart, (size_t)vpart_off * kVLen));
+    HIP_TRY(B->alloc(&v.Gam, (size_t)gam_off));
   }
   HIP_TRY(B->alloc(&v.fpart, (size_t)fpart_off));
   HIP_TRY(B->alloc(&v.fspart, (size_t)fs_off));
@@ -457,18 +503,27 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.gpart, (size_t)gpart_off * kGradLen));
   HIP_TRY(hipMemcpy(shd, B->shapes_h.data(), B->shapes_h.size() * sizeof(ShapeDev), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(tod, B->toys_h.data(), B->toys_h.size() * sizeof(ToyDev), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(fi, B->fold_h.data(), B->fold_h.size() * sizeof(FoldItem), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(ai, B->adj_h.data(), B->adj_h.size() * sizeof(AdjItem), hipMemcpyHostToDevice));
+  {
+    gs_status us = upload_items(B, B->fold_h, B->adj_h, fi, ai, v, nullptr);
+    if (us != GS_OK) return us;
+  }
+  if (v.n1d > 0 && v.n2d > 0) {  // a mixed batch: kernels of one kind take their toys from a list
+    std::vector<int> l1, l2;
+    for (int t = 0; t < n_toys; t++) (B->toys_h[t].two_d ? l2 : l1).push_back(t);
+    int *d1, *d2;
+    HIP_TRY(B->alloc(&d1, l1.size()));
+    HIP_TRY(B->alloc(&d2, l2.size()));
+    HIP_TRY(hipMemcpy(d1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice));
+    v.list1d = d1;
+    v.list2d = d2;
+  }
   HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(pc, pc_h.data(), pc_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ps, ps_h.data(), ps_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipDeviceSynchronize());
   v.shapes = shd;
   v.toys = tod;
-  v.fold_items = fi;
-  v.n_fold_items = (int)B->fold_h.size();
-  v.adj_items = ai;
-  v.n_adj_items = (int)B->adj_h.size();
   v.cnt = cnt;
   v.pull_c = pc;
   v.pull_s = ps;
@@ -508,7 +563,6 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
     HIP_TRY(timed(B, GS_K_REDF, st, [&] { return launch_reduceF(v, kOnly2D, active, st); }));
     HIP_TRY(launch_psd(v, d_theta, active, st));
     HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins2(v, d_theta, d_mu, active, st); }));
-    if (d_grad) HIP_TRY(launch_vpart(v, active, st));
   }
   if (d_grad) {
     if (v.has_1d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
@@ -856,6 +910,8 @@ static gs_status qn_setup(gs_batch *B) {
   HIP_TRY(B->alloc(&B->d_count, 1));
   HIP_TRY(hipHostMalloc((void **)&B->h_count, sizeof(int), hipHostMallocDefault));
   HIP_TRY(B->alloc(&B->d_toy_list, (size_t)n));
+  HIP_TRY(B->alloc(&B->d_list1, (size_t)n));
+  HIP_TRY(B->alloc(&B->d_list2, (size_t)n));
   HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->fold_h.size(), 1)));
   HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->adj_h.size(), 1)));
   std::vector<int> np(n);
@@ -920,29 +976,32 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
   std::vector<uint8_t> act((size_t)B->n_toys);
   HIP_TRY(hipMemcpyAsync(act.data(), B->q.active, act.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  std::vector<int> list;
+  std::vector<int> list, l1, l2;
   for (int t = 0; t < B->n_toys; t++)
-    if (act[t]) list.push_back(t);
+    if (act[t]) {
+      list.push_back(t);
+      (B->toys_h[t].two_d ? l2 : l1).push_back(t);
+    }
   std::vector<FoldItem> fi;
   std::vector<AdjItem> ai;
   for (const FoldItem &it : B->fold_h)
     if (act[it.toy]) fi.push_back(it);
   for (const AdjItem &it : B->adj_h)
     if (act[it.toy]) ai.push_back(it);
+  out = B->v;
   if (!list.empty())
     HIP_TRY(hipMemcpyAsync(B->d_toy_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, st));
-  if (!fi.empty())
-    HIP_TRY(hipMemcpyAsync(B->d_fold_c, fi.data(), sizeof(FoldItem) * fi.size(), hipMemcpyHostToDevice, st));
-  if (!ai.empty())
-    HIP_TRY(hipMemcpyAsync(B->d_adj_c, ai.data(), sizeof(AdjItem) * ai.size(), hipMemcpyHostToDevice, st));
+  if (!l1.empty()) HIP_TRY(hipMemcpyAsync(B->d_list1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice, st));
+  if (!l2.empty()) HIP_TRY(hipMemcpyAsync(B->d_list2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
-  out = B->v;
+  gs_status us = upload_items(B, fi, ai, B->d_fold_c, B->d_adj_c, out, st);
+  if (us != GS_OK) return us;
   out.toy_list = B->d_toy_list;
   out.n_list = (int)list.size();
-  out.fold_items = B->d_fold_c;
-  out.n_fold_items = (int)fi.size();
-  out.adj_items = B->d_adj_c;
-  out.n_adj_items = (int)ai.size();
+  out.list1d = B->d_list1;
+  out.n1d = (int)l1.size();
+  out.list2d = B->d_list2;
+  out.n2d = (int)l2.size();
   return GS_OK;
 }
 

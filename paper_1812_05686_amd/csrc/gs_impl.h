@@ -12,8 +12,10 @@ constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins p
 constexpr int kFoldTile = 64;   // window bins per fold item (1-D fold: two per lane of each half-wave)
 constexpr int kStage = 128;     // cell records staged in LDS per batch of the 1-D fold
 constexpr int kGroup = 16;      // grid cells per support hull
+constexpr int kVLen = GS_MAX_SPECIES + 4;  // 2-D gradient partials per block: species, 3 nuisances, pad
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
 constexpr int kBlock = 256;     // threads per reduction block
+constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed block (2-D models)
 constexpr int kGradLen = GS_MAX_PARAMS;
 constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response flag each)
 
@@ -37,7 +39,8 @@ struct ToyDev {
   int shape, D, lo, L, P, K, n_cell, S;
   int two_d;                    // 1: pulse-shape (secondary observable) model
   int fold_chunks, adj_chunks;
-  int bin_blocks, cell_blocks;  // reduction blocks over window bins / cells (kBlock each)
+  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: over bin x pulse-shape cells) / cells
+  int hblocks;                  // 2-D: k_hseed blocks (kHTile window bins each)
   int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
   long long cell_off;   // rec[(cell_off + i) * kRecLen]
   long long win_off;    // binrec[(win_off + b) * kBinRecLen], F[(win_off + b) * S]
@@ -50,6 +53,7 @@ struct ToyDev {
   long long cflag_off;  // per k_cells block: cflag[cflag_off + blk]
   long long ghull_off;  // per kGroup grid cells: union of their supports, ghull[ghull_off + g]
   long long pull_off;   // pull centres / widths [P]
+  long long vpart_off;  // 2-D: vpart[(vpart_off + r) * kVLen + e], rows: hblocks of k_hseed, then bin_blocks of k_bins2
   long long gam_off;    // 2-D: Gam[gam_off + b * K + k] = sum_d eps_d (1 - n/mu)
   long long psd_off;    // 2-D: P[psd_off + s * K + k], dP[(psd_off + s * K + k) * 3 + v]
   double exposure[GS_MAX_DATASETS];
@@ -69,7 +73,14 @@ struct BatchView {
   int n_toys, stride;
   const int *toy_list;  // per-toy grids cover toy_list[0 .. n_list) (NULL: every toy, n_list = n_toys)
   int n_list;
+  // the same toys split by kind, for kernels of one kind (NULL list: toy_list / n_list)
+  const int *list1d, *list2d;
+  int n1d, n2d;
   int max_cells, max_cell_blocks, max_bin_blocks;
+  int max_bin_blocks1, max_bin_blocks2;  // the same over 1-D / 2-D toys
+  int max_ls_blocks;  // kBlock blocks over (window bin, species) pairs
+  int max_psd_sk;     // largest S x K of a 2-D toy (P, dP are staged in LDS)
+  int max_hblocks;    // k_hseed grid
   double log_cut;   // pairs whose log-density is below this are skipped
   const ToyDev *toys;
   const ShapeDev *shapes;
@@ -88,15 +99,19 @@ struct BatchView {
   uint32_t *badp;   // domain flags per bin block
   const double *cnt;
   const double *pull_c, *pull_s;
-  const FoldItem *fold_items;
+  const FoldItem *fold_items;  // every toy's items
   int n_fold_items;
   const AdjItem *adj_items;
   int n_adj_items;
+  // the same split by kind (1-D: k_fold1, k_adj<false>; 2-D: k_fold_s, k_adj<true>)
+  const FoldItem *fold1, *fold2;
+  const AdjItem *adj1, *adj2;
+  int n_fold1, n_fold2, n_adj1, n_adj2;
   // secondary observable (2-D) models
   double *H;        // [win bins][S]: dx_j sum_k P_sk Gam_jk
   double *Gam;      // [win bins][K]
   double *P, *dP;   // pulse-shape probabilities and their nuisance derivatives
-  double *vpart;    // [toy][GS_MAX_SPECIES][4]: sum_k P V, sum_k dP_v V for v = 0..2
+  double *vpart;    // per k_bins2 block: sum_j F_js sum_k P_sk Gam_jk (s), nuisance pieces
   uint32_t *pflag;  // [toy]: invalid pulse-shape nuisance
   const double *theta_dev;  // parameters of the evaluation in flight (per-species adjoint)
   bool has_1d, has_2d;
@@ -119,6 +134,5 @@ hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out,
 hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st);
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st);
-hipError_t launch_vpart(const BatchView &v, const uint8_t *active, hipStream_t st);
 
 }  // namespace gs

@@ -466,13 +466,18 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
 }
 
 hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st) {
-  if (v.n_fold_items == 0) return hipSuccess;
-  if (per_species)
-    hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
-                       v.n_fold_items, v.toys, v.shapes, v.rec, v.ghull, mode, active, v.fspart);
-  else
-    hipLaunchKernelGGL(k_fold1, dim3(xcd_grid(v.n_fold_items)), dim3(kWaves * 64), 0, st, v.fold_items,
-                       v.n_fold_items, v.toys, v.shapes, v.rec, v.ghull, active, v.fpart);
+  if (per_species) {
+    // the per-species fold serves the 2-D toys, or every toy (plain path)
+    const FoldItem *it = mode == kOnly2D ? v.fold2 : mode == kOnly1D ? v.fold1 : v.fold_items;
+    const int n = mode == kOnly2D ? v.n_fold2 : mode == kOnly1D ? v.n_fold1 : v.n_fold_items;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes, v.rec,
+                       v.ghull, mode, active, v.fspart);
+  } else {
+    if (v.n_fold1 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold1, dim3(xcd_grid(v.n_fold1)), dim3(kWaves * 64), 0, st, v.fold1, v.n_fold1, v.toys,
+                       v.shapes, v.rec, v.ghull, active, v.fpart);
+  }
   return hipGetLastError();
 }
 
@@ -550,7 +555,8 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
 }
 
 hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_bins1, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, v.fpart,
+  if (v.n1d == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bins1, dim3(v.max_bin_blocks1, v.n1d), dim3(kBlock), 0, st, v.list1d, v.toys, v.shapes, v.fpart,
                      v.cnt, active, v.binrec, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
@@ -701,13 +707,15 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
 }
 
 hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *active, hipStream_t st) {
-  if (v.n_adj_items == 0) return hipSuccess;
+  const AdjItem *it = per_species ? v.adj2 : v.adj1;
+  const int n = per_species ? v.n_adj2 : v.n_adj1;
+  if (n == 0) return hipSuccess;
   if (per_species)
-    hipLaunchKernelGGL(k_adj<true>, dim3(xcd_grid(v.n_adj_items)), dim3(kWaves * 64), 0, st, v.adj_items,
-                       v.n_adj_items, v.toys, v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
+    hipLaunchKernelGGL(k_adj<true>, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes,
+                       v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
   else
-    hipLaunchKernelGGL(k_adj<false>, dim3(xcd_grid(v.n_adj_items)), dim3(kWaves * 64), 0, st, v.adj_items,
-                       v.n_adj_items, v.toys, v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
+    hipLaunchKernelGGL(k_adj<false>, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes,
+                       v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
   return hipGetLastError();
 }
 
@@ -814,7 +822,7 @@ hipError_t launch_cellgrad(const BatchView &v, const double *theta, const uint8_
 
 // ------------------------------------------------------------- k_finish ---
 // Thread p < stride: gradient entry p; thread 0 also -ln L and status.
-__global__ __launch_bounds__(64) void k_finish(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ nllp, const uint32_t *__restrict__ badp,
                                                const uint32_t *__restrict__ cflag, const double *__restrict__ gpart,
@@ -824,62 +832,81 @@ __global__ __launch_bounds__(64) void k_finish(const int *__restrict__ toy_list,
                                                double *__restrict__ nll, double *__restrict__ grad,
                                                uint32_t *__restrict__ status) {
   __shared__ uint32_t st_s;
+  __shared__ double gsum[kGradLen];
   const int t = toy_of(toy_list, blockIdx.x);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
-  const int p = threadIdx.x;
-  // flags and pull terms spread over the lanes (no serial chain of loads)
-  bool dom = false, nonfin = false;
-  for (int b = p; b < T.bin_blocks; b += 64) dom = dom || badp[T.nllp_off + b] != 0;
-  for (int b = p; b < T.cflag_blocks; b += 64)
-    dom = dom || cflag[T.cflag_off + b] != 0;  // invalid response somewhere on the grid
-  double pull = 0.0;
-  if (p < T.P) {
-    nonfin = !isfinite(th[p]);
-    const double s = pull_s[T.pull_off + p];
-    if (s > 0.0) {
-      const double z = (th[p] - pull_c[T.pull_off + p]) / s;
-      pull = 0.5 * z * z;
+  // wave 0: -ln L and status; every wave: gradient entries wave, wave + 4, ...
+  // Every sum over block partials runs across the lanes (lane-strided, then a
+  // fixed butterfly), so no lane walks a long serial chain of loads.
+  const int p = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
+  if (grad) {
+    const int nr = Sh.family == kGaussE ? 2 : 5;
+    const double *vp = vpart + T.vpart_off * kVLen;
+    for (int pp = wave; pp < T.P; pp += kWaves) {  // wave-uniform
+      double a = 0.0;
+      if (pp < Sh.S + nr)
+        for (int b = p; b < T.cell_blocks; b += 64) a += gpart[(T.gpart_off + b) * kGradLen + pp];
+      if (T.two_d) {  // pieces that need no fold, from the 2-D block partials
+        int e = -1;
+        if (pp < Sh.S) {
+          for (int q = 0; q < Sh.S; q++)
+            if (Sh.sp_of[q] == pp) e = q;
+        } else if (pp >= Sh.S + nr) {
+          e = GS_MAX_SPECIES + (pp - Sh.S - nr);
+        }
+        if (e >= 0 && e < GS_MAX_SPECIES)  // rows of k_hseed
+          for (int blk = p; blk < T.hblocks; blk += 64) a += vp[(size_t)blk * kVLen + e];
+        else if (e >= 0)  // rows of k_bins2
+          for (int blk = p; blk < T.bin_blocks; blk += 64) a += vp[(size_t)(T.hblocks + blk) * kVLen + e];
+      }
+      a = wave_sum(a);
+      if (p == 0) gsum[pp] = a;
     }
   }
-  pull = wave_sum(pull);
-  const bool any_dom = __ballot(dom) != 0ull, any_nonfin = __ballot(nonfin) != 0ull;
-  if (p == 0) {
-    uint32_t st = 0;
-    double sum = 0.0;
-    for (int b = 0; b < T.bin_blocks; b++) sum += nllp[T.nllp_off + b];
-    sum += pull;
-    if (any_dom || (T.two_d && pflag[t])) st |= GS_ST_DOMAIN;  // pflag: invalid pulse-shape nuisance
-    if (any_nonfin) st |= GS_ST_NONFINITE;
-    if (st & GS_ST_NONFINITE) {
-      st = GS_ST_NONFINITE;  // a non-finite parameter explains every other symptom
-      sum = __builtin_nan("");
+  if (wave == 0) {
+    double part = 0.0;
+    for (int b = p; b < T.bin_blocks; b += 64) part += nllp[T.nllp_off + b];
+    const double nll_bins = wave_sum(part);
+    // flags and pull terms spread over the lanes (no serial chain of loads)
+    bool dom = false, nonfin = false;
+    for (int b = p; b < T.bin_blocks; b += 64) dom = dom || badp[T.nllp_off + b] != 0;
+    for (int b = p; b < T.cflag_blocks; b += 64)
+      dom = dom || cflag[T.cflag_off + b] != 0;  // invalid response somewhere on the grid
+    double pull = 0.0;
+    if (p < T.P) {
+      nonfin = !isfinite(th[p]);
+      const double s = pull_s[T.pull_off + p];
+      if (s > 0.0) {
+        const double z = (th[p] - pull_c[T.pull_off + p]) / s;
+        pull = 0.5 * z * z;
+      }
     }
-    else if (st & GS_ST_DOMAIN)
-      sum = __builtin_inf();
-    nll[t] = sum;
-    status[t] = st;
-    st_s = st;
+    pull = wave_sum(pull);
+    const bool any_dom = __ballot(dom) != 0ull, any_nonfin = __ballot(nonfin) != 0ull;
+    if (p == 0) {
+      uint32_t st = 0;
+      double sum = nll_bins + pull;
+      if (any_dom || (T.two_d && pflag[t])) st |= GS_ST_DOMAIN;  // pflag: invalid pulse-shape nuisance
+      if (any_nonfin) st |= GS_ST_NONFINITE;
+      if (st & GS_ST_NONFINITE) {
+        st = GS_ST_NONFINITE;  // a non-finite parameter explains every other symptom
+        sum = __builtin_nan("");
+      }
+      else if (st & GS_ST_DOMAIN)
+        sum = __builtin_inf();
+      nll[t] = sum;
+      status[t] = st;
+      st_s = st;
+    }
   }
   __syncthreads();
-  if (grad && p < stride) {
-    const int nr = Sh.family == kGaussE ? 2 : 5;
+  if (grad && threadIdx.x < stride) {
     double g = 0.0;
     if (p < T.P) {
-      if (p < Sh.S + nr)
-        for (int b = 0; b < T.cell_blocks; b++) g += gpart[(T.gpart_off + b) * kGradLen + p];
-      if (T.two_d) {
-        const double *vp = vpart + (size_t)t * GS_MAX_SPECIES * 4;
-        if (p < Sh.S) {
-          for (int q = 0; q < Sh.S; q++)
-            if (Sh.sp_of[q] == p) g += vp[q * 4];
-        } else if (p >= Sh.S + nr) {
-          const int v = p - Sh.S - nr;
-          for (int q = 0; q < Sh.S; q++) g = __fma_rn(th[Sh.sp_of[q]], vp[q * 4 + 1 + v], g);
-        }
-      }
+      g = gsum[p];
       const double s = pull_s[T.pull_off + p];
       if (s > 0.0) g += (th[p] - pull_c[T.pull_off + p]) / (s * s);
       if (st_s & (GS_ST_DOMAIN | GS_ST_NONFINITE)) g = __builtin_nan("");
@@ -890,7 +917,7 @@ __global__ __launch_bounds__(64) void k_finish(const int *__restrict__ toy_list,
 
 hipError_t launch_finish(const BatchView &v, const double *theta, double *nll, double *grad, uint32_t *status,
                          const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish, dim3(v.n_list), dim3(64), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, v.nllp, v.badp,
+  hipLaunchKernelGGL(k_finish, dim3(v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, v.nllp, v.badp,
                      v.cflag, v.gpart, v.vpart, v.pflag, v.pull_c, v.pull_s, active, nll, grad, status);
   return hipGetLastError();
 }
@@ -916,8 +943,9 @@ hipError_t launch_bins_setup(double *bins, const double *edges, int n_reco, hipS
 }
 
 // ---------------------------------------------- per-species (plain path) --
-// F[(win_off + b) * S + s] = dx_b * sum over chunks (fixed order).
-__global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+// F[(win_off + b) * S + s] = dx_b * sum over chunks (fixed order); one thread per (bin, species).
+__global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                                 const ShapeDev *__restrict__ shapes,
                                                  const double *__restrict__ fspart, int mode,
                                                  const uint8_t *__restrict__ active, double *__restrict__ F) {
   const int t = toy_of(toy_list, blockIdx.y);
@@ -925,18 +953,20 @@ __global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_lis
   const ToyDev &T = toys[t];
   if (mode >= 0 && T.two_d != mode) return;
   const ShapeDev &Sh = shapes[T.shape];
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= T.L) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T.L * T.S) return;
+  const int b = e / T.S, sp = e - b * T.S;
   const double dx = Sh.bins[(size_t)(T.lo + b) * kBinLen + 1];
-  for (int s = 0; s < T.S; s++) {
-    double acc = 0.0;
-    for (int c = 0; c < T.fold_chunks; c++) acc += fspart[T.fs_off + ((long long)c * T.L + b) * T.S + s];
-    F[(T.win_off + b) * T.S + s] = dx * acc;
-  }
+  double acc = 0.0;
+  for (int c = 0; c < T.fold_chunks; c++) acc += fspart[T.fs_off + ((long long)c * T.L + b) * T.S + sp];
+  F[(T.win_off + b) * T.S + sp] = dx * acc;
 }
 
 hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduceF, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, v.fspart,
+  const int *list = mode == kOnly2D ? v.list2d : mode == kOnly1D ? v.list1d : v.toy_list;
+  const int n = mode == kOnly2D ? v.n2d : mode == kOnly1D ? v.n1d : v.n_list;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduceF, dim3(v.max_ls_blocks, n), dim3(kBlock), 0, st, list, v.toys, v.shapes, v.fspart,
                      mode, active, v.F);
   return hipGetLastError();
 }
@@ -982,7 +1012,8 @@ __global__ __launch_bounds__(256) void k_binsF(const int *__restrict__ toy_list,
 }
 
 hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_binsF, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
+  if (v.n1d == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_binsF, dim3(v.max_bin_blocks1, v.n1d), dim3(kBlock), 0, st, v.list1d, v.toys, v.shapes, theta,
                      v.stride, v.F, v.cnt, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
@@ -992,12 +1023,13 @@ hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out,
 // Pulse-shape probabilities of every species (section 2.4): a two-Gaussian
 // mixture at the bin midpoints, means shifted by delta, widths scaled by
 // kappa, odds of component 1 multiplied by exp(eta), renormalised over the
-// bins; with their derivatives w.r.t. (delta, kappa, eta).  One thread per species.
-__global__ __launch_bounds__(64) void k_psd(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                            const double *__restrict__ theta, int stride,
-                                            const uint8_t *__restrict__ active, double *__restrict__ P,
+// bins; with their derivatives w.r.t. (delta, kappa, eta).  One wave per
+// (toy, species), lanes over the bins (at most GS_MAX_PSD = 2 x 64).
+__global__ __launch_bounds__(64) void k_psd(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                            const ShapeDev *__restrict__ shapes, const double *__restrict__ theta,
+                                            int stride, const uint8_t *__restrict__ active, double *__restrict__ P,
                                             double *__restrict__ dP, uint32_t *__restrict__ pflag) {
-  const int t = toy_of(toy_list, blockIdx.x);
+  const int t = toy_of(toy_list, blockIdx.y), s = blockIdx.x, lane = threadIdx.x;
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if (!T.two_d) return;
@@ -1005,8 +1037,7 @@ __global__ __launch_bounds__(64) void k_psd(const int *__restrict__ toy_list, co
   const double *nu = theta + (size_t)t * stride + Sh.S + (Sh.family == kGaussE ? 2 : 5);
   const double delta = nu[0], kappa = nu[1], eta = nu[2];
   const bool ok = kappa > 0.0 && isfinite(kappa) && isfinite(delta) && isfinite(eta);
-  if (threadIdx.x == 0) pflag[t] = ok ? 0u : 1u;
-  const int s = threadIdx.x;
+  if (s == 0 && lane == 0) pflag[t] = ok ? 0u : 1u;
   if (!ok || s >= Sh.S) return;
   const double *mx = Sh.mix + 5 * s;
   const double w1 = mx[0];
@@ -1019,148 +1050,199 @@ __global__ __launch_bounds__(64) void k_psd(const int *__restrict__ toy_list, co
     dd = N * z / sg;
     dk = N * (z * z - 1.0) / kappa;
   };
+  const int K = Sh.n_psd;
+  double p[2] = {0.0, 0.0}, q0[2] = {0.0, 0.0}, q1[2] = {0.0, 0.0}, q2[2] = {0.0, 0.0};
   double Z = 0.0, dZ0 = 0.0, dZ1 = 0.0, dZ2 = 0.0;
-  for (int k = 0; k < Sh.n_psd; k++) {
-    const double y = Sh.psd[2 * k], dy = Sh.psd[2 * k + 1];
-    double N0, d0, k0, N1, d1, k1;
-    comp(y, 0, N0, d0, k0);
-    comp(y, 1, N1, d1, k1);
-    Z += dy * (wp * N0 + (1.0 - wp) * N1);
-    dZ0 += dy * (wp * d0 + (1.0 - wp) * d1);
-    dZ1 += dy * (wp * k0 + (1.0 - wp) * k1);
-    dZ2 += dy * wp * (1.0 - wp) * (N0 - N1);
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int k = lane + 64 * h;
+    if (k < K) {
+      const double y = Sh.psd[2 * k], dy = Sh.psd[2 * k + 1];
+      double N0, d0, k0, N1, d1, k1;
+      comp(y, 0, N0, d0, k0);
+      comp(y, 1, N1, d1, k1);
+      p[h] = dy * (wp * N0 + (1.0 - wp) * N1);
+      q0[h] = dy * (wp * d0 + (1.0 - wp) * d1);
+      q1[h] = dy * (wp * k0 + (1.0 - wp) * k1);
+      q2[h] = dy * wp * (1.0 - wp) * (N0 - N1);
+      Z += p[h];
+      dZ0 += q0[h];
+      dZ1 += q1[h];
+      dZ2 += q2[h];
+    }
   }
+  Z = wave_sum(Z);
+  dZ0 = wave_sum(dZ0);
+  dZ1 = wave_sum(dZ1);
+  dZ2 = wave_sum(dZ2);
   const double iZ = 1.0 / Z;
-  for (int k = 0; k < Sh.n_psd; k++) {
-    const double y = Sh.psd[2 * k], dy = Sh.psd[2 * k + 1];
-    double N0, d0, k0, N1, d1, k1;
-    comp(y, 0, N0, d0, k0);
-    comp(y, 1, N1, d1, k1);
-    const double p = dy * (wp * N0 + (1.0 - wp) * N1);
-    const double pk = p * iZ;
-    const long long o = T.psd_off + (long long)s * T.K + k;
-    P[o] = pk;
-    dP[3 * o + 0] = (dy * (wp * d0 + (1.0 - wp) * d1) - pk * dZ0) * iZ;
-    dP[3 * o + 1] = (dy * (wp * k0 + (1.0 - wp) * k1) - pk * dZ1) * iZ;
-    dP[3 * o + 2] = (dy * wp * (1.0 - wp) * (N0 - N1) - pk * dZ2) * iZ;
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int k = lane + 64 * h;
+    if (k < K) {
+      const double pk = p[h] * iZ;
+      const long long o = T.psd_off + (long long)s * T.K + k;
+      P[o] = pk;
+      dP[3 * o + 0] = (q0[h] - pk * dZ0) * iZ;
+      dP[3 * o + 1] = (q1[h] - pk * dZ1) * iZ;
+      dP[3 * o + 2] = (q2[h] - pk * dZ2) * iZ;
+    }
   }
 }
 
 hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_psd, dim3(v.n_list), dim3(64), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, active, v.P, v.dP,
-                     v.pflag);
+  if (v.n2d == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_psd, dim3(GS_MAX_SPECIES, v.n2d), dim3(64), 0, st, v.list2d, v.toys, v.shapes, theta,
+                     v.stride, active, v.P, v.dP, v.pflag);
   return hipGetLastError();
 }
 
-// Per (toy, 256 energy bins): mu_djk = eps_d sum_s R_s F_js P_sk, Poisson terms,
-// Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), H_js = dx_j sum_k P_sk Gam_jk.
-__global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+// 2-D likelihood, one thread per (window bin j, pulse-shape bin k) of a toy:
+// mu_djk = eps_d sum_s R_s F_js P_sk, the Poisson terms (block partial of
+// -ln L), Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), and the block partial of
+// the nuisance-gradient pieces that need no fold,
+// sum_jk Gam_jk sum_s R_s F_js dP_sk/dnu.  P and dP are staged in LDS as
+// [s][k][4].
+__global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                               const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ F, const double *__restrict__ P,
-                                               const double *__restrict__ cnt, const uint8_t *__restrict__ active,
-                                               double *__restrict__ binrec, double *__restrict__ H,
-                                               double *__restrict__ Gam, double *__restrict__ nllp,
-                                               uint32_t *__restrict__ badp, double *__restrict__ mu_out) {
+                                               const double *__restrict__ dP, const double *__restrict__ cnt,
+                                               const uint8_t *__restrict__ active, double *__restrict__ Gam,
+                                               double *__restrict__ nllp, uint32_t *__restrict__ badp,
+                                               double *__restrict__ vpart, double *__restrict__ mu_out) {
+  extern __shared__ double pd[];  // [S][K][4]: P_sk, dP_sk/d(delta, kappa, eta)
+  __shared__ double ared[kWaves][3];
   __shared__ double lds[8];
-  __shared__ double Ps[GS_MAX_SPECIES * GS_MAX_PSD];
   __shared__ int bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || !T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
-  const int S = T.S, K = T.K;
-  for (int e = threadIdx.x; e < S * K; e += blockDim.x) Ps[e] = P[T.psd_off + e];
+  const int S = T.S, K = T.K, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x == 0) bad_s = 0;
+  for (int e = threadIdx.x; e < S * K; e += blockDim.x) {
+    const long long o = T.psd_off + e;
+    double *d = pd + (size_t)e * 4;
+    d[0] = P[o];
+    d[1] = dP[3 * o];
+    d[2] = dP[3 * o + 1];
+    d[3] = dP[3 * o + 2];
+  }
   __syncthreads();
   const double *th = theta + (size_t)t * stride;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  double sum = 0.0;
-  if (b < T.L) {
-    const int j = T.lo + b;
-    const double *bn = Sh.bins + (size_t)j * kBinLen;
-    const double dx = bn[1];
-    double rf[GS_MAX_SPECIES], hs[GS_MAX_SPECIES];
-#pragma unroll
-    for (int q = 0; q < GS_MAX_SPECIES; q++) {
-      rf[q] = q < S ? th[Sh.sp_of[q]] * F[(T.win_off + b) * S + q] : 0.0;
-      hs[q] = 0.0;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = e < (long long)T.L * K;
+  const int b = valid ? (int)(e / K) : 0, k = valid ? (int)(e - (long long)b * K) : 0;
+  double sum = 0.0, A0 = 0.0, A1 = 0.0, A2 = 0.0;
+  bool bad = false;
+  if (valid) {
+    const double *Fr = F + (T.win_off + b) * S;
+    double M = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
+    for (int q = 0; q < S; q++) {
+      const double rf = th[Sh.sp_of[q]] * Fr[q];
+      const double *c = pd + ((size_t)q * K + k) * 4;
+      const double2 u = *(const double2 *)c, w = *(const double2 *)(c + 2);
+      M = __fma_rn(rf, u.x, M);
+      D0 = __fma_rn(rf, u.y, D0);
+      D1 = __fma_rn(rf, w.x, D1);
+      D2 = __fma_rn(rf, w.y, D2);
     }
-    bool bad = false;
-    for (int k = 0; k < K; k++) {
-      double M = 0.0;
-#pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q < S) M = __fma_rn(rf[q], Ps[q * K + k], M);
-      double gam = 0.0;
-      for (int d = 0; d < T.D; d++) {
-        const double mu = T.exposure[d] * M;
-        const double n = cnt[T.cnt_off + ((long long)d * T.L + b) * K + k];
-        double term, g;
-        if (!poisson_term(mu, n, term, g)) bad = true;
-        sum += term;
-        gam = __fma_rn(T.exposure[d], g, gam);
-        if (mu_out) mu_out[((long long)d * T.L + b) * K + k] = mu;
-      }
-      Gam[T.gam_off + (long long)b * K + k] = gam;
-#pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q < S) hs[q] = __fma_rn(Ps[q * K + k], gam, hs[q]);
+    double gam = 0.0;
+    for (int d = 0; d < T.D; d++) {
+      const double mu = T.exposure[d] * M;
+      const double n = cnt[T.cnt_off + ((long long)d * T.L + b) * K + k];
+      double term, g;
+      if (!poisson_term(mu, n, term, g)) bad = true;
+      sum += term;
+      gam = __fma_rn(T.exposure[d], g, gam);
+      if (mu_out) mu_out[((long long)d * T.L + b) * K + k] = mu;
     }
-    const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
-    for (int q = 0; q < S; q++) H[(T.win_off + b) * S + q] = outside ? 0.0 : dx * hs[q];
-    double *br = binrec + (T.win_off + b) * kBinRecLen;
-    br[0] = bn[0];
-    br[1] = bn[2];
-    br[2] = bn[3];
-    br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
-    br[4] = 0.0;
-    br[5] = 0.0;
-    if (bad) bad_s = 1;
+    Gam[T.gam_off + (long long)b * K + k] = gam;
+    A0 = D0 * gam;
+    A1 = D1 * gam;
+    A2 = D2 * gam;
   }
-  const double tot = block_sum(sum, lds);
-  __syncthreads();
+  A0 = wave_sum(A0);
+  A1 = wave_sum(A1);
+  A2 = wave_sum(A2);
+  if (lane == 0) {
+    ared[wave][0] = A0;
+    ared[wave][1] = A1;
+    ared[wave][2] = A2;
+  }
+  if (bad) bad_s = 1;  // benign race: every writer stores 1
+  const double tot = block_sum(sum, lds);  // its barriers also order ared and bad_s
   if (threadIdx.x == 0) {
     nllp[T.nllp_off + blockIdx.x] = tot;
     badp[T.nllp_off + blockIdx.x] = bad_s;
+    double *vp = vpart + (T.vpart_off + T.hblocks + blockIdx.x) * kVLen + GS_MAX_SPECIES;
+    for (int v = 0; v < 3; v++) vp[v] = ared[0][v] + ared[1][v] + ared[2][v] + ared[3][v];
+  }
+}
+
+// 2-D adjoint seeds, one thread per (window bin j, species slot s) of a toy,
+// kHTile bins per block: h_js = sum_k P_sk Gam_jk, H_js = dx_j h_js, the bin
+// record, and the block partial of the rate-gradient piece sum_j F_js h_js.
+__global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                               const ShapeDev *__restrict__ shapes, const double *__restrict__ F,
+                                               const double *__restrict__ P, const double *__restrict__ Gam,
+                                               const uint8_t *__restrict__ active, double *__restrict__ binrec,
+                                               double *__restrict__ H, double *__restrict__ vpart) {
+  extern __shared__ double ps[];  // [S][K]
+  __shared__ double red[kHTile][GS_MAX_SPECIES];
+  const int t = toy_of(toy_list, blockIdx.y);
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if ((int)blockIdx.x >= T.hblocks || !T.two_d) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int S = T.S, K = T.K;
+  for (int e = threadIdx.x; e < S * K; e += blockDim.x) ps[e] = P[T.psd_off + e];
+  __syncthreads();
+  const int jj = threadIdx.x / GS_MAX_SPECIES, q = threadIdx.x % GS_MAX_SPECIES;
+  const int b = blockIdx.x * kHTile + jj;
+  const bool valid = b < T.L && q < S;
+  double a = 0.0;
+  if (valid) {
+    const double *g = Gam + T.gam_off + (long long)b * K;
+    const double *pq = ps + (size_t)q * K;
+    double h = 0.0;
+    for (int k = 0; k < K; k++) h = __fma_rn(pq[k], g[k], h);
+    const double *bn = Sh.bins + (size_t)(T.lo + b) * kBinLen;
+    const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
+    H[(T.win_off + b) * S + q] = outside ? 0.0 : bn[1] * h;
+    a = F[(T.win_off + b) * S + q] * h;
+    if (q == 0) {
+      double *br = binrec + (T.win_off + b) * kBinRecLen;
+      br[0] = bn[0];
+      br[1] = bn[2];
+      br[2] = bn[3];
+      br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
+      br[4] = 0.0;
+      br[5] = 0.0;
+    }
+  }
+  red[jj][q] = a;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double v = red[0][threadIdx.x];
+    for (int j = 1; j < kHTile; j++) v += red[j][threadIdx.x];
+    vpart[(T.vpart_off + blockIdx.x) * kVLen + threadIdx.x] = v;
   }
 }
 
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
-                     v.stride, v.F, v.P, v.cnt, active, v.binrec, v.H, v.Gam, v.nllp, v.badp, mu_out);
-  return hipGetLastError();
-}
-
-// Per (toy, species s): V_sk = sum_j F_js Gam_jk, reduced to sum_k P_sk V_sk (the
-// rate gradient) and sum_k dP_sk/dnu V_sk (times R_s in k_finish: nuisance gradients).
-__global__ __launch_bounds__(64) void k_vpart(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                              const double *__restrict__ F, const double *__restrict__ Gam,
-                                              const double *__restrict__ P, const double *__restrict__ dP,
-                                              const uint8_t *__restrict__ active, double *__restrict__ vpart) {
-  const int t = toy_of(toy_list, blockIdx.y), s = blockIdx.x;
-  if (active && !active[t]) return;
-  const ToyDev &T = toys[t];
-  if (!T.two_d || s >= T.S) return;
-  const int K = T.K;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    double V = 0.0;
-    for (int b = 0; b < T.L; b++) V = __fma_rn(F[(T.win_off + b) * T.S + s], Gam[T.gam_off + (long long)b * K + k], V);
-    const long long o = T.psd_off + (long long)s * K + k;
-    a[0] = __fma_rn(P[o], V, a[0]);
-    for (int v = 0; v < 3; v++) a[1 + v] = __fma_rn(dP[3 * o + v], V, a[1 + v]);
-  }
-  for (int q = 0; q < 4; q++)
-    for (int o = 32; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 64);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < 4; q++) vpart[((size_t)t * GS_MAX_SPECIES + s) * 4 + q] = a[q];
-}
-
-hipError_t launch_vpart(const BatchView &v, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_vpart, dim3(GS_MAX_SPECIES, v.n_list), dim3(64), 0, st, v.toy_list, v.toys, v.shapes, v.F, v.Gam, v.P,
-                     v.dP, active, v.vpart);
+  if (v.n2d == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), sizeof(double) * 4 * v.max_psd_sk, st,
+                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, active, v.Gam, v.nllp,
+                     v.badp, v.vpart, mu_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hseed, dim3(v.max_hblocks, v.n2d), dim3(kHTile * GS_MAX_SPECIES),
+                     sizeof(double) * v.max_psd_sk, st, v.list2d, v.toys, v.shapes, v.F, v.P, v.Gam, active,
+                     v.binrec, v.H, v.vpart);
   return hipGetLastError();
 }
 
