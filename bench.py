@@ -107,10 +107,17 @@ def mixed_batch(gs, gsgen, torch, n_toys, steps, warmup, with_oracle):
         batch.nll_grad(theta, nll, grad, st)
     torch.cuda.synchronize()
     el = time.perf_counter() - ta
+    batch.set_profiling(True)
+    batch.kernel_times(reset=True)
+    for _ in range(max(1, steps // 4)):
+        batch.nll_grad(theta, nll, grad, st)
+    kt = batch.kernel_times(reset=True)
+    batch.set_profiling(False)
     classes = [m.name.split("/")[1] for m in toys]
     out = {"toys": len(toys), "classes": {c: classes.count(c) for c in sorted(set(classes))},
            "evals_per_s": round(len(toys) * steps / el, 1), "ms_per_step": round(el * 1e3 / steps, 3),
-           "generator_s": round(gen_s, 1), "status_nonzero": int((st != 0).sum().item())}
+           "generator_s": round(gen_s, 1), "status_nonzero": int((st != 0).sum().item()),
+           "kernel_ms": {k: round(v[0] / v[1], 3) for k, v in kt.items() if v[1]}}
     th0 = np.zeros_like(th)
     for t, m in enumerate(toys):
         th0[t, : m.n_params] = m.theta0

@@ -388,30 +388,100 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   }
 }
 
-// Per-species fold (plain path and the secondary-observable model): grid
-// cells add w_si r into species s < Sg, line cells into their own.  One
-// workgroup per fold item, one bin per lane; cells are interleaved over the
-// waves and read with scalar loads.
+// Per-species fold (plain path and the secondary-observable model): F_js
+// needs one accumulator per species.  Same layout as the 1-D fold (kFoldTile
+// bins, half-waves on alternate cells, two bins per lane, compacted hull
+// groups, LDS-staged batches), with each staged cell also carrying its weight
+// vector over the species: w_si for grid cells, one-hot on its own species for
+// a line cell.
 template <int FAM>
-__device__ __forceinline__ void fold_cells_s(const double *__restrict__ R, const double *__restrict__ wc, int Sg,
-                                             int n_true, int c0, int c1, int j0, int j1, double x, double Lh,
-                                             double Ll, const ExpK &ec, double (&acc)[GS_MAX_SPECIES]) {
-  for (int i = c0; i < c1; i += kWaves) {
-    const double *p = R + (size_t)i * kRecLen;
-    const int2 s = get_support(p);
-    if (s.y <= j0 || s.x >= j1) continue;
-    const double r = pair_density<FAM>(p, x, Lh, Ll, ec);
-    if (i < n_true) {
-      const double *w = wc + (size_t)i * Sg;
+__device__ __forceinline__ void folds_batch(const double *srec, const double *swt, int S, int nb, int wave,
+                                            const Bin2 &bn, const ExpK &ec, double (&a0)[GS_MAX_SPECIES],
+                                            double (&a1)[GS_MAX_SPECIES]) {
+  constexpr int L = Stage<FAM>::kLen;
+  const int h = (threadIdx.x >> 5) & 1;
+  const int np = nb >> 1;
+  for (int k = wave; k < np; k += kWaves) {
+    const int c = 2 * k + h;
+    double p[L];
 #pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q < Sg) acc[q] = __fma_rn(w[q], r, acc[q]);
-    } else {
-      const int ql = Sg + (i - n_true);
-#pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q == ql) acc[q] += r;
+    for (int e = 0; e < L; e += 2) {
+      const double2 u = *(const double2 *)(srec + c * L + e);
+      p[e] = u.x;
+      p[e + 1] = u.y;
     }
+    const double r0 = pair_density<FAM>(p, bn.x0, bn.Lh0, bn.Ll0, ec);
+    const double r1 = pair_density<FAM>(p, bn.x1, bn.Lh1, bn.Ll1, ec);
+    const double *w = swt + c * GS_MAX_SPECIES;
+#pragma unroll
+    for (int q = 0; q < GS_MAX_SPECIES; q += 2) {
+      if (q < S) {
+        const double2 wq = *(const double2 *)(w + q);
+        a0[q] = __fma_rn(wq.x, r0, a0[q]);
+        a1[q] = __fma_rn(wq.x, r1, a1[q]);
+        a0[q + 1] = __fma_rn(wq.y, r0, a0[q + 1]);
+        a1[q + 1] = __fma_rn(wq.y, r1, a1[q + 1]);
+      }
+    }
+  }
+}
+
+// Weight vector of cell i over the internal species (grid species, then lines).
+__device__ __forceinline__ double cell_weight(const ShapeDev &Sh, int i, int q) {
+  if (i < Sh.n_true) return q < Sh.Sg ? Sh.wcell[(size_t)i * Sh.Sg + q] : 0.0;
+  return q == Sh.Sg + (i - Sh.n_true) ? 1.0 : 0.0;
+}
+
+// Cells of a staged batch: either the listed groups of grid cells (list !=
+// NULL, clipped to [c_lo, c_hi)) or the cell range [c_lo, c_hi).
+template <int FAM>
+__device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
+                                            int n_list, int c_lo, int c_hi, double *srec, double *swt, int wave,
+                                            const Bin2 &bn, const ExpK &ec, double (&a0)[GS_MAX_SPECIES],
+                                            double (&a1)[GS_MAX_SPECIES]) {
+  constexpr int P = Stage<FAM>::kParts;
+  constexpr int kGPB = kStage / kGroup;
+  constexpr int kT = kWaves * 64;
+  const int tid = threadIdx.x, S = Sh.S;
+  auto cell_of = [&](int bi, int cs) {  // cell at slot cs of batch bi, or -1
+    if (list) {
+      const int li = bi * kGPB + cs / kGroup;
+      const int cell = li < n_list ? list[li] * kGroup + cs % kGroup : -1;
+      return cell >= c_lo && cell < c_hi ? cell : -1;
+    }
+    const int cell = c_lo + bi * kStage + cs;
+    return cell < c_hi ? cell : -1;
+  };
+  const int n_batch = list ? (n_list + kGPB - 1) / kGPB : (c_hi - c_lo + kStage - 1) / kStage;
+  double2 f[2];
+  double wv[kStage * GS_MAX_SPECIES / kT];
+  auto fetch = [&](int bi) {
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      const int qp = tid + u * kT;
+      const int cell = qp < kStage * P ? cell_of(bi, qp / P) : -1;
+      f[u] = cell >= 0 ? *(const double2 *)(R + (size_t)cell * kRecLen + 2 * (qp % P)) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) {
+      const int e = tid + u * kT, cs = e / GS_MAX_SPECIES, q = e % GS_MAX_SPECIES;
+      const int cell = cell_of(bi, cs);
+      wv[u] = cell >= 0 && q < S ? cell_weight(Sh, cell, q) : 0.0;
+    }
+  };
+  if (n_batch > 0) fetch(0);
+  for (int bi = 0; bi < n_batch; bi++) {
+    const int rem = list ? (n_list - bi * kGPB) * kGroup : c_hi - c_lo - bi * kStage;
+    const int nb = (min(kStage, rem) + 1) & ~1;  // whole cell pairs; pad slots hold zeros
+    __syncthreads();  // every wave is done with the previous batch
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+      if (tid + u * kT < kStage * P) ((double2 *)srec)[tid + u * kT] = f[u];
+#pragma unroll
+    for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) swt[tid + u * kT] = wv[u];
+    __syncthreads();
+    if (bi + 1 < n_batch) fetch(bi + 1);
+    folds_batch<FAM>(srec, swt, S, nb, wave, bn, ec, a0, a1);
   }
 }
 
@@ -420,8 +490,11 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
                                                 const double *__restrict__ rec, const int2 *__restrict__ ghull,
                                                 int mode, const uint8_t *__restrict__ active,
                                                 double *__restrict__ out) {
-  __shared__ double red[kWaves * kTile * GS_MAX_SPECIES];
-  __shared__ int rng[2 * kWaves];
+  __shared__ __align__(16) double srec[kStage * 6];
+  __shared__ __align__(16) double swt[kStage * GS_MAX_SPECIES];
+  __shared__ double red[kFoldTile][GS_MAX_SPECIES];
+  __shared__ int glist[kWaves * 64];
+  __shared__ int gcnt[kWaves];
   const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
@@ -429,39 +502,52 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   if (active && !active[it.toy]) return;
   const ToyDev &T = toys[it.toy];
   if (mode >= 0 && T.two_d != mode) return;
-  const int bin0 = it.bin0;
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int b = bin0 + lane;
-  const bool valid = b < T.L;
-  const double *bn = Sh.bins + (size_t)(T.lo + (valid ? b : T.L - 1)) * kBinLen;
-  const double x = bn[0], Lh = bn[2], Ll = bn[3];
-  const int j0 = T.lo + bin0, j1 = T.lo + min(bin0 + kTile, T.L);
+  const int b0 = it.bin0 + (lane & 31), b1 = b0 + 32;
+  const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
+  const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
+  const Bin2 bn{bp0[0], bp0[2], bp0[3], bp1[0], bp1[2], bp1[3]};
+  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile, T.L);
   const double *R = rec + T.cell_off * kRecLen;
+  const int g_end = min(it.cell1, Sh.n_true);
+  const int l_lo = max(it.cell0, Sh.n_true), l_hi = it.cell1;  // line cells: few, all evaluated
   const bool gamma = Sh.family == kGammaPE;
-  const bool zero = gamma && !(x > 0.0);  // outside the gamma support
-  const int2 gr = grid_range(ghull + T.ghull_off, it.cell0, min(it.cell1, Sh.n_true), j0, j1, rng);
-  const int first = wave_uniform(gr.x), c_end = wave_uniform(gr.y), l_begin = max(it.cell0, Sh.n_true);
-  double acc[GS_MAX_SPECIES];
+  double a0[GS_MAX_SPECIES], a1[GS_MAX_SPECIES];
 #pragma unroll
-  for (int q = 0; q < GS_MAX_SPECIES; q++) acc[q] = 0.0;
-  if (gamma) {
-    fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
-    fold_cells_s<kGammaPE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
-  } else {
-    fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, first + wave, c_end, j0, j1, x, Lh, Ll, ec, acc);
-    fold_cells_s<kGaussE>(R, Sh.wcell, Sh.Sg, Sh.n_true, l_begin + wave, it.cell1, j0, j1, x, Lh, Ll, ec, acc);
+  for (int q = 0; q < GS_MAX_SPECIES; q++) a0[q] = a1[q] = 0.0;
+  for (int gb = it.cell0 / kGroup; gb * kGroup < g_end; gb += kWaves * 64) {
+    const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
+                             glist, gcnt);
+    if (gamma)
+      folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, bn, ec, a0, a1);
+    else
+      folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, bn, ec, a0, a1);
   }
+  if (gamma)
+    folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, bn, ec, a0, a1);
+  else
+    folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, bn, ec, a0, a1);
+  const bool z0 = gamma && !(bn.x0 > 0.0), z1 = gamma && !(bn.x1 > 0.0);  // outside the gamma support
+  // the two half-waves cover the same bins: combine them, then the waves in a fixed order
 #pragma unroll
-  for (int q = 0; q < GS_MAX_SPECIES; q++) red[(wave * GS_MAX_SPECIES + q) * kTile + lane] = zero ? 0.0 : acc[q];
-  __syncthreads();
-  if (wave == 0 && valid) {
-    double *o = out + T.fs_off + ((long long)it.chunk * T.L + b) * T.S;
-    for (int q = 0; q < T.S; q++) {
-      double s = red[q * kTile + lane];
-      for (int ww = 1; ww < kWaves; ww++) s += red[(ww * GS_MAX_SPECIES + q) * kTile + lane];
-      o[q] = s;
-    }
+  for (int q = 0; q < GS_MAX_SPECIES; q++) {
+    a0[q] = z0 ? 0.0 : a0[q] + __shfl_xor(a0[q], 32, 64);
+    a1[q] = z1 ? 0.0 : a1[q] + __shfl_xor(a1[q], 32, 64);
+  }
+  for (int w = 0; w < kWaves; w++) {
+    if (wave == w && lane < 32)
+#pragma unroll
+      for (int q = 0; q < GS_MAX_SPECIES; q++) {
+        red[lane][q] = w == 0 ? a0[q] : red[lane][q] + a0[q];
+        red[lane + 32][q] = w == 0 ? a1[q] : red[lane + 32][q] + a1[q];
+      }
+    __syncthreads();
+  }
+  const int S = T.S;
+  for (int e = threadIdx.x; e < kFoldTile * S; e += blockDim.x) {
+    const int bb = e / S, q = e - bb * S, b = it.bin0 + bb;
+    if (b < T.L) out[T.fs_off + ((long long)it.chunk * T.L + b) * S + q] = red[bb][q];
   }
 }
 
