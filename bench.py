@@ -38,8 +38,8 @@ FLOPS_PER_PAIR = {"fold": 49, "adj": 53}
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
 # kernel sources they were taken on: any change to those sources reports traffic as null.
 # Source: profiles/hbm_bytes_k_fold1_k_adj_borexino_4096toys.md.
-TRAFFIC = {"sources_sha256": "bd8320f8de009c717aad468994e878cb73c67f12f5dd736f41303621d28b90a4",
-           "toys": 4096, "kernels": {"k_fold1": 933116735, "k_adj": 1740737869}}
+TRAFFIC = {"sources_sha256": "15de73220685805e9c569d822a1960d62b0c8334624e7d4bd9128f8759e57bcf",
+           "toys": 4096, "kernels": {"k_fold1": 933133015, "k_adj": 1740735678}}
 
 
 def sources_sha256():
