@@ -234,8 +234,9 @@ gs_status gs_batch_set_profiling(gs_batch *b, int32_t on);
  * events; reset != 0 clears the accumulators afterwards. */
 gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset);
 /* Mesh pairs (window bin x cell) of the most recent evaluation of the batch,
- * host array of 4: out[0] pairs the 1-D fold evaluated (64 bins per visited
- * cell and bin tile, idle lanes of a partial tile included), out[1] pairs the
+ * host array of 4: out[0] pairs the fold evaluated (every bin of a tile per
+ * visited cell and tile: 32-bin tiles for 1-D toys, 64-bin tiles for
+ * secondary-observable toys, idle lanes of a partial tile included), out[1] pairs the
  * adjoint evaluated, out[2] the full mesh sum_t (window bins x cells), out[3]
  * the banded mesh: pairs whose bin lies in the cell's support, i.e. the
  * pairs the method needs at the current log-density cut.  Synchronises the

@@ -146,7 +146,8 @@ struct gs_batch {
   int n_toys = 0, stride = 0;
   std::vector<ShapeDev> shapes_h;
   std::vector<ToyDev> toys_h;
-  std::vector<FoldItem> fold_h;
+  std::vector<FoldItem> fold_h;   // per-species fold items, every toy
+  std::vector<FoldItem> fold1_h;  // 1-D fold items, 1-D toys
   std::vector<AdjItem> adj_h;
   std::vector<void *> allocs;
   BatchView v{};
@@ -234,9 +235,11 @@ constexpr double kDefaultLogCut = -60.0;
 
 // Splits work items by the kind of their toy (1-D first, then 2-D: items of a
 // toy stay contiguous and in order) and uploads them to dst; sets the view's
-// per-kind pointers into dst.
-static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, const std::vector<AdjItem> &ai,
-                              FoldItem *dst_f, AdjItem *dst_a, BatchView &v, hipStream_t st) {
+// per-kind pointers into dst.  fi: per-species fold items (every toy), fi1:
+// 1-D fold items (1-D toys), stored after them; dst_f holds both.
+static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, const std::vector<FoldItem> &fi1,
+                              const std::vector<AdjItem> &ai, FoldItem *dst_f, AdjItem *dst_a, BatchView &v,
+                              hipStream_t st) {
   std::vector<FoldItem> f;
   std::vector<AdjItem> a;
   for (int kind = 0; kind < 2; kind++) {
@@ -245,21 +248,24 @@ static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, cons
     for (const AdjItem &it : ai)
       if (B->toys_h[it.toy].two_d == kind) a.push_back(it);
     if (kind == 0) {
-      v.n_fold1 = (int)f.size();
+      v.n_fold1s = (int)f.size();
       v.n_adj1 = (int)a.size();
     }
   }
-  v.n_fold2 = (int)f.size() - v.n_fold1;
+  v.n_fold_items = (int)f.size();
+  v.n_fold2 = v.n_fold_items - v.n_fold1s;
   v.n_adj2 = (int)a.size() - v.n_adj1;
+  for (const FoldItem &it : fi1)
+    if (!B->toys_h[it.toy].two_d) f.push_back(it);
+  v.n_fold1 = (int)f.size() - v.n_fold_items;
   if (!f.empty()) HIP_TRY(hipMemcpyAsync(dst_f, f.data(), sizeof(FoldItem) * f.size(), hipMemcpyHostToDevice, st));
   if (!a.empty()) HIP_TRY(hipMemcpyAsync(dst_a, a.data(), sizeof(AdjItem) * a.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));  // the host vectors go out of scope
   v.fold_items = dst_f;
-  v.n_fold_items = (int)f.size();
   v.adj_items = dst_a;
   v.n_adj_items = (int)a.size();
-  v.fold1 = dst_f;
-  v.fold2 = dst_f + v.n_fold1;
+  v.fold2 = dst_f + v.n_fold1s;
+  v.fold1 = dst_f + v.n_fold_items;
   v.adj1 = dst_a;
   v.adj2 = dst_a + v.n_adj1;
   return GS_OK;
@@ -318,21 +324,28 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     for (int q = 0; q < sh.Sg; q++) sh.sp_of[q] = grid[q];
     for (int q = 0; q < sh.n_line; q++) sh.sp_of[sh.Sg + q] = line[q];
     std::vector<double> cellE(sh.n_cell), wcell((size_t)d.n_true * std::max(sh.Sg, 1), 0.0);
+    std::vector<double> wcellT(wcell.size(), 0.0);
     for (int i = 0; i < d.n_true; i++) cellE[i] = d.e_lo + (i + 0.5) * d.e_step;
     for (int q = 0; q < sh.n_line; q++) cellE[d.n_true + q] = d.line_energy[line[q]];
     for (int i = 0; i < d.n_true; i++)
-      for (int q = 0; q < sh.Sg; q++) wcell[(size_t)i * sh.Sg + q] = d.spectra[(size_t)grid[q] * d.n_true + i];
-    double *cE, *wc, *bins, *edges;
+      for (int q = 0; q < sh.Sg; q++) {
+        wcell[(size_t)i * sh.Sg + q] = d.spectra[(size_t)grid[q] * d.n_true + i];
+        wcellT[(size_t)q * d.n_true + i] = d.spectra[(size_t)grid[q] * d.n_true + i];
+      }
+    double *cE, *wc, *wct, *bins, *edges;
     HIP_TRY(B->alloc(&cE, cellE.size()));
     HIP_TRY(B->alloc(&wc, wcell.size()));
+    HIP_TRY(B->alloc(&wct, wcellT.size()));
     HIP_TRY(B->alloc(&bins, (size_t)d.n_reco * kBinLen));
     HIP_TRY(B->alloc(&edges, (size_t)d.n_reco + 1));
     HIP_TRY(hipMemcpy(cE, cellE.data(), cellE.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(wc, wcell.data(), wcell.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(wct, wcellT.data(), wcellT.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(edges, d.reco_edges, ((size_t)d.n_reco + 1) * 8, hipMemcpyHostToDevice));
     HIP_TRY(launch_bins_setup(bins, edges, d.n_reco, nullptr));
     sh.cellE = cE;
     sh.wcell = wc;
+    sh.wcellT = wct;
     sh.bins = bins;
     // uniform binning (midpoints within 1e-6 of a bin width of a lattice): the
     // support search guesses bin indices arithmetically
@@ -428,6 +441,10 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     for (int b0 = 0; b0 < T.L; b0 += kFoldTile)
       for (int c = 0; c < T.fold_chunks; c++)
         B->fold_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
+    if (!T.two_d)
+      for (int b0 = 0; b0 < T.L; b0 += kFoldTile1)
+        for (int c = 0; c < T.fold_chunks; c++)
+          B->fold1_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
     for (int c0 = 0; c0 < sh.n_cell; c0 += kTile)
       for (int c = 0; c < T.adj_chunks; c++)
         B->adj_h.push_back({t, c0, c * bpc, std::min(T.L, (c + 1) * bpc), c});
@@ -476,7 +493,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   double *cnt, *pc, *ps;
   HIP_TRY(B->alloc(&shd, B->shapes_h.size()));
   HIP_TRY(B->alloc(&tod, B->toys_h.size()));
-  HIP_TRY(B->alloc(&fi, B->fold_h.size()));
+  HIP_TRY(B->alloc(&fi, B->fold_h.size() + B->fold1_h.size()));
   HIP_TRY(B->alloc(&ai, B->adj_h.size()));
   HIP_TRY(B->alloc(&cnt, cnt_h.size()));
   HIP_TRY(B->alloc(&pc, pc_h.size()));
@@ -504,7 +521,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(hipMemcpy(shd, B->shapes_h.data(), B->shapes_h.size() * sizeof(ShapeDev), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(tod, B->toys_h.data(), B->toys_h.size() * sizeof(ToyDev), hipMemcpyHostToDevice));
   {
-    gs_status us = upload_items(B, B->fold_h, B->adj_h, fi, ai, v, nullptr);
+    gs_status us = upload_items(B, B->fold_h, B->fold1_h, B->adj_h, fi, ai, v, nullptr);
     if (us != GS_OK) return us;
   }
   if (v.n1d > 0 && v.n2d > 0) {  // a mixed batch: kernels of one kind take their toys from a list
@@ -629,13 +646,19 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
       if (y > x) band += y - x;
     }
   }
-  // the 1-D fold evaluates every cell of the hull groups that meet its tile
-  // (partial groups padded to kGroup), plus the chunk's line cells, on all
-  // kFoldTile lanes
-  for (const FoldItem &it : b->fold_h) {
+  // the fold evaluates every cell of the hull groups that meet its tile
+  // (partial groups padded to kGroup), plus the chunk's line cells, on every
+  // bin of the tile: kFoldTile1 bins for 1-D toys, kFoldTile for 2-D toys
+  std::vector<FoldItem> fitems;
+  for (const FoldItem &it : b->fold1_h)
+    if (!b->toys_h[it.toy].two_d) fitems.push_back(it);
+  for (const FoldItem &it : b->fold_h)
+    if (b->toys_h[it.toy].two_d) fitems.push_back(it);
+  for (const FoldItem &it : fitems) {
     const ToyDev &T = b->toys_h[it.toy];
     const ShapeDev &Sh = b->shapes_h[T.shape];
-    const int j0 = T.lo + it.bin0, j1 = T.lo + std::min(it.bin0 + kFoldTile, T.L);
+    const int tile = T.two_d ? kFoldTile : kFoldTile1;
+    const int j0 = T.lo + it.bin0, j1 = T.lo + std::min(it.bin0 + tile, T.L);
     const int g_end = std::min(it.cell1, Sh.n_true);
     long long cells = std::max(0, it.cell1 - std::max(it.cell0, Sh.n_true));
     for (int g = it.cell0 / kGroup; g * kGroup < g_end; g++) {
@@ -649,7 +672,7 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
       }
       if (hx < j1 && hy > j0) cells += kGroup;
     }
-    fold += cells * kFoldTile;
+    fold += cells * tile;
   }
   for (const AdjItem &it : b->adj_h) {
     const ToyDev &T = b->toys_h[it.toy];
@@ -912,7 +935,7 @@ static gs_status qn_setup(gs_batch *B) {
   HIP_TRY(B->alloc(&B->d_toy_list, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list1, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list2, (size_t)n));
-  HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->fold_h.size(), 1)));
+  HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->fold_h.size() + B->fold1_h.size(), 1)));
   HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->adj_h.size(), 1)));
   std::vector<int> np(n);
   for (int t = 0; t < n; t++) np[t] = B->toys_h[t].P;
@@ -982,10 +1005,12 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
       list.push_back(t);
       (B->toys_h[t].two_d ? l2 : l1).push_back(t);
     }
-  std::vector<FoldItem> fi;
+  std::vector<FoldItem> fi, fi1;
   std::vector<AdjItem> ai;
   for (const FoldItem &it : B->fold_h)
     if (act[it.toy]) fi.push_back(it);
+  for (const FoldItem &it : B->fold1_h)
+    if (act[it.toy]) fi1.push_back(it);
   for (const AdjItem &it : B->adj_h)
     if (act[it.toy]) ai.push_back(it);
   out = B->v;
@@ -994,7 +1019,7 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
   if (!l1.empty()) HIP_TRY(hipMemcpyAsync(B->d_list1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice, st));
   if (!l2.empty()) HIP_TRY(hipMemcpyAsync(B->d_list2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
-  gs_status us = upload_items(B, fi, ai, B->d_fold_c, B->d_adj_c, out, st);
+  gs_status us = upload_items(B, fi, fi1, ai, B->d_fold_c, B->d_adj_c, out, st);
   if (us != GS_OK) return us;
   out.toy_list = B->d_toy_list;
   out.n_list = (int)list.size();

@@ -9,7 +9,8 @@
 namespace gs {
 
 constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins per per-species fold tile
-constexpr int kFoldTile = 64;   // window bins per fold item (1-D fold: two per lane of each half-wave)
+constexpr int kFoldTile = 64;   // window bins per per-species fold item (two per lane of each half-wave)
+constexpr int kFoldTile1 = 32;  // window bins per 1-D fold item (two per lane of each quarter-wave)
 constexpr int kStage = 128;     // cell records staged in LDS per batch of the 1-D fold
 constexpr int kGroup = 16;      // grid cells per support hull
 constexpr int kVLen = GS_MAX_SPECIES + 4;  // 2-D gradient partials per block: species, 3 nuisances, pad
@@ -26,7 +27,8 @@ struct ShapeDev {
   int family, n_true, n_line, n_cell, S, Sg, n_reco, n_psd;
   double birks_A;
   const double *cellE;  // [n_cell]: grid-cell centres, then line energies
-  const double *wcell;  // [n_true][Sg]: grid-species weights, cell-major
+  const double *wcell;   // [n_true][Sg]: grid-species weights, cell-major
+  const double *wcellT;  // [Sg][n_true]: the same, species-major (lanes on consecutive cells read coalesced)
   const double *bins;   // [n_reco][kBinLen]: xbar, dx, ln xbar (hi, lo)
   double bx0, bw;       // uniform binning: xbar_j = bx0 + j bw (bw = 0: not uniform)
   const double *psd;    // [n_psd][2]: ybar, dy
@@ -59,7 +61,8 @@ struct ToyDev {
   double exposure[GS_MAX_DATASETS];
 };
 
-// One workgroup of the fold: kFoldTile window bins of one toy against a cell range.
+// One workgroup of the fold: kFoldTile (per-species fold) or kFoldTile1 (1-D
+// fold) window bins of one toy against a cell range.
 struct FoldItem {
   int toy, bin0, cell0, cell1, chunk;
 };
@@ -99,11 +102,11 @@ struct BatchView {
   uint32_t *badp;   // domain flags per bin block
   const double *cnt;
   const double *pull_c, *pull_s;
-  const FoldItem *fold_items;  // every toy's items
-  int n_fold_items;
+  const FoldItem *fold_items;  // every toy's per-species fold items (kFoldTile bins): 1-D toys first, then 2-D
+  int n_fold_items, n_fold1s;  // all of them / those of 1-D toys
   const AdjItem *adj_items;
   int n_adj_items;
-  // the same split by kind (1-D: k_fold1, k_adj<false>; 2-D: k_fold_s, k_adj<true>)
+  // by kind (1-D: k_fold1 on kFoldTile1-bin items, k_adj<false>; 2-D: k_fold_s, k_adj<true>)
   const FoldItem *fold1, *fold2;
   const AdjItem *adj1, *adj2;
   int n_fold1, n_fold2, n_adj1, n_adj2;

@@ -104,8 +104,8 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
     ok = moments(Sh.family, th + Sh.S, Sh.birks_A, Sh.cellE[i], mo);
     double W = 0.0;
     if (i < Sh.n_true) {
-      const double *w = Sh.wcell + (size_t)i * Sh.Sg;
-      for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[s], W);
+      const double *w = Sh.wcellT + i;
+      for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[(size_t)s * Sh.n_true], W);
     } else {
       W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
     }
@@ -151,10 +151,12 @@ __device__ __forceinline__ double pair_density(const double *__restrict__ p, dou
   return dexp(gauss_exponent(p[0], p[1], p[2], x, z), ec);
 }
 
-// 1-D fold.  A workgroup owns kFoldTile = 64 window bins and a set of cells.
-// Each half-wave covers the whole tile, two bins per lane (bins j and j + 32
-// for lane j of the half), and the two halves take alternate cells, so one
-// LDS read of a record feeds two pairs.  The cell records are staged through
+// 1-D fold.  A workgroup owns kFoldTile1 = 32 window bins and a set of cells.
+// Each quarter-wave covers the whole tile, two bins per lane (bins j and j + 16
+// for lane j of the quarter), and the 16 quarter-waves of the workgroup take
+// the cells in turn, so one LDS read of a record (a broadcast to 16 lanes)
+// feeds two pairs.  Narrow tiles keep the pairs evaluated outside the cells'
+// supports (at the support ends of the cells that meet a tile) few.  The cell records are staged through
 // LDS in batches of kStage cells; the next batch is fetched into registers
 // while the current one is evaluated, and the VALU only evaluates pairs.
 // Only the 16-byte parts of a record the pair loop reads are staged:
@@ -178,23 +180,23 @@ __device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const B
   a1 = __fma_rn(W, pair_density<FAM>(p, bn.x1, bn.Lh1, bn.Ll1, ec), a1);
 }
 
-// Cell pairs wave, wave + kWaves, ... of a staged batch of nb cells (nb even:
-// an odd batch is padded with a zero record); half h of the wave takes the
-// cell 2k + h of pair k.
+// Cell quads wave, wave + kWaves, ... of a staged batch of nb cells (nb a
+// multiple of 4: a batch is padded with zero records); quarter h of the wave
+// takes the cell 4k + h of quad k.
 template <int FAM>
 __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Bin2 &bn, const ExpK &ec,
                                            double &a0, double &a1) {
   constexpr int L = Stage<FAM>::kLen;
-  const int h = (threadIdx.x >> 5) & 1;
-  const int np = nb >> 1;
+  const int h = (threadIdx.x >> 4) & 3;
+  const int nq = nb >> 2;
   const double *base = srec + h * L;
   int k = wave;
-  for (; k + kWaves < np; k += 2 * kWaves) {
+  for (; k + kWaves < nq; k += 2 * kWaves) {
     double p[L], q[L];
 #pragma unroll
     for (int e = 0; e < L; e += 2) {
-      const double2 u = *(const double2 *)(base + 2 * k * L + e);
-      const double2 w = *(const double2 *)(base + 2 * (k + kWaves) * L + e);
+      const double2 u = *(const double2 *)(base + 4 * k * L + e);
+      const double2 w = *(const double2 *)(base + 4 * (k + kWaves) * L + e);
       p[e] = u.x;
       p[e + 1] = u.y;
       q[e] = w.x;
@@ -203,11 +205,11 @@ __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave,
     fold_pair2<FAM>(p, bn, ec, a0, a1);
     fold_pair2<FAM>(q, bn, ec, a0, a1);
   }
-  if (k < np) {
+  if (k < nq) {
     double p[L];
 #pragma unroll
     for (int e = 0; e < L; e += 2) {
-      const double2 u = *(const double2 *)(base + 2 * k * L + e);
+      const double2 u = *(const double2 *)(base + 4 * k * L + e);
       p[e] = u.x;
       p[e + 1] = u.y;
     }
@@ -233,7 +235,7 @@ __device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_l
   };
   if (c_lo < c_hi) fetch(c_lo);
   for (int base = c_lo; base < c_hi; base += kStage) {
-    const int nb = (min(kStage, c_hi - base) + 1) & ~1;  // padded to whole cell pairs
+    const int nb = (min(kStage, c_hi - base) + 3) & ~3;  // padded to whole cell quads
     __syncthreads();  // every wave is done with the previous batch
     if (tid < nb * P) ((double2 *)srec)[tid] = f0;
     if (tid + kWaves * 64 < nb * P) ((double2 *)srec)[tid + kWaves * 64] = f1;
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
                                                const double *__restrict__ rec, const int2 *__restrict__ ghull,
                                                const uint8_t *__restrict__ active, double *__restrict__ out) {
   __shared__ __align__(16) double srec[kStage * 6];
-  __shared__ double red[kWaves * 2 * 64];
+  __shared__ double red[kWaves * 4 * kFoldTile1];
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
   const ExpK ec = exp_consts();
@@ -348,11 +350,12 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   if (T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int b0 = it.bin0 + (lane & 31), b1 = b0 + 32;
+  constexpr int kHalf = kFoldTile1 / 2;
+  const int b0 = it.bin0 + (lane & (kHalf - 1)), b1 = b0 + kHalf;
   const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
   const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
   const Bin2 bn{bp0[0], bp0[2], bp0[3], bp1[0], bp1[2], bp1[3]};
-  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile, T.L);
+  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile1, T.L);
   const double *R = rec + T.cell_off * kRecLen;
   // grid cells: the groups whose hull meets the tile, up to kWaves * 64 groups per pass
   const int g_end = min(it.cell1, Sh.n_true);
@@ -374,15 +377,16 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   } else {
     fold_range<kGaussE>(R, l_lo, l_hi, srec, wave, bn, ec, a0, a1);
   }
-  red[(wave * 2 + 0) * 64 + lane] = a0;
-  red[(wave * 2 + 1) * 64 + lane] = a1;
+  // red[stream][bin]: stream = wave * 4 + quarter, bin of the tile
+  const int stream = threadIdx.x >> 4, j = lane & (kHalf - 1);
+  red[stream * kFoldTile1 + j] = a0;
+  red[stream * kFoldTile1 + kHalf + j] = a1;
   __syncthreads();
-  if (wave == 0) {  // lane o: bin o of the tile, summed over waves and half-waves in a fixed order
-    const int sh = lane >> 5, j = lane & 31;
-    const int b = it.bin0 + lane;
+  if (threadIdx.x < kFoldTile1) {  // thread o: bin o of the tile, summed over the streams in a fixed order
+    const int b = it.bin0 + (int)threadIdx.x;
     if (b < T.L) {
       double s = 0.0;
-      for (int q = 0; q < kWaves; q++) s += red[(q * 2 + sh) * 64 + j] + red[(q * 2 + sh) * 64 + 32 + j];
+      for (int q = 0; q < kWaves * 4; q++) s += red[q * kFoldTile1 + threadIdx.x];
       out[T.fpart_off + (long long)it.chunk * T.L + b] = s;
     }
   }
@@ -554,8 +558,8 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
 hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st) {
   if (per_species) {
     // the per-species fold serves the 2-D toys, or every toy (plain path)
-    const FoldItem *it = mode == kOnly2D ? v.fold2 : mode == kOnly1D ? v.fold1 : v.fold_items;
-    const int n = mode == kOnly2D ? v.n_fold2 : mode == kOnly1D ? v.n_fold1 : v.n_fold_items;
+    const FoldItem *it = mode == kOnly2D ? v.fold2 : v.fold_items;
+    const int n = mode == kOnly2D ? v.n_fold2 : mode == kOnly1D ? v.n_fold1s : v.n_fold_items;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes, v.rec,
                        v.ghull, mode, active, v.fspart);
@@ -762,10 +766,10 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
 #pragma unroll
     for (int q = 0; q < GS_MAX_SPECIES; q++) rw[q] = 0.0;
     if (ic < Sh.n_true) {
-      const double *w = Sh.wcell + (size_t)ic * Sh.Sg;
+      const double *w = Sh.wcellT + ic;
 #pragma unroll
       for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q < Sh.Sg) rw[q] = th[Sh.sp_of[q]] * w[q];
+        if (q < Sh.Sg) rw[q] = th[Sh.sp_of[q]] * w[(size_t)q * Sh.n_true];
     } else {
       const int ql = Sh.Sg + (ic - Sh.n_true);
 #pragma unroll
@@ -839,9 +843,9 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
     double W = 1.0;
     if (!T.two_d) {
       if (i < Sh.n_true) {
-        const double *w = Sh.wcell + (size_t)i * Sh.Sg;
+        const double *w = Sh.wcellT + i;
         W = 0.0;
-        for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[s], W);
+        for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[(size_t)s * Sh.n_true], W);
       } else {
         W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
       }
@@ -864,12 +868,12 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
 #pragma unroll
     for (int p = 0; p < 5; p++) gP[p] = __fma_rn(dNdm, mo.dm[p], __fma_rn(dNds, mo.ds[p], gP[p]));
     if (T.two_d) {
-      // rate gradients of 2-D models come from the pulse-shape contraction (k_vpart)
+      // rate gradients of 2-D models come from the pulse-shape contraction (k_hseed)
     } else if (i < Sh.n_true) {
-      const double *w = Sh.wcell + (size_t)i * Sh.Sg;
+      const double *w = Sh.wcellT + i;
 #pragma unroll
       for (int s = 0; s < GS_MAX_SPECIES; s++)
-        if (s < Sh.Sg) gR[s] = __fma_rn(w[s], A0, gR[s]);
+        if (s < Sh.Sg) gR[s] = __fma_rn(w[(size_t)s * Sh.n_true], A0, gR[s]);
     } else {
       const int q = Sh.Sg + (i - Sh.n_true);
 #pragma unroll
