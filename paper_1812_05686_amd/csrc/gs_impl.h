@@ -11,7 +11,8 @@ namespace gs {
 constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins per per-species fold tile
 constexpr int kFoldTile = 64;   // window bins per per-species fold item (two per lane of each half-wave)
 constexpr int kFoldTile1 = 32;  // window bins per 1-D fold item (two per lane of each quarter-wave)
-constexpr int kStage = 128;     // cell records staged in LDS per batch of the 1-D fold
+constexpr int kStage = 128;     // cell records staged in LDS per batch of the per-species fold
+constexpr int kStage1 = 256;    // cells staged in LDS per batch of the 1-D fold (one per thread)
 constexpr int kGroup = 16;      // grid cells per support hull
 constexpr int kVLen = GS_MAX_SPECIES + 4;  // 2-D gradient partials per block: species, 3 nuisances, pad
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile

@@ -151,17 +151,8 @@ __device__ __forceinline__ double pair_density(const double *__restrict__ p, dou
   return dexp(gauss_exponent(p[0], p[1], p[2], x, z), ec);
 }
 
-// 1-D fold.  A workgroup owns kFoldTile1 = 32 window bins and a set of cells.
-// Each quarter-wave covers the whole tile, two bins per lane (bins j and j + 16
-// for lane j of the quarter), and the 16 quarter-waves of the workgroup take
-// the cells in turn, so one LDS read of a record (a broadcast to 16 lanes)
-// feeds two pairs.  Narrow tiles keep the pairs evaluated outside the cells'
-// supports (at the support ends of the cells that meet a tile) few.  The cell records are staged through
-// LDS in batches of kStage cells; the next batch is fetched into registers
-// while the current one is evaluated, and the VALU only evaluates pairs.
-// Only the 16-byte parts of a record the pair loop reads are staged:
-// {K, 1/th hi, lo, C hi, lo, W} for gamma, {m, 1/s, c0, W} for the Gaussian
-// families.
+// Staged record parts of the per-species fold: {K, 1/th hi, lo, C hi, lo, W}
+// for gamma, {m, 1/s, c0, W} for the Gaussian families.
 template <int FAM>
 struct Stage {
   static constexpr int kParts = FAM == kGammaPE ? 3 : 2;
@@ -172,105 +163,114 @@ struct Bin2 {
   double x0, Lh0, Ll0, x1, Lh1, Ll1;
 };
 
-template <int FAM>
-__device__ __forceinline__ void fold_pair2(const double *__restrict__ p, const Bin2 &bn, const ExpK &ec, double &a0,
-                                           double &a1) {
-  const double W = FAM == kGammaPE ? p[5] : p[3];
-  a0 = __fma_rn(W, pair_density<FAM>(p, bn.x0, bn.Lh0, bn.Ll0, ec), a0);
-  a1 = __fma_rn(W, pair_density<FAM>(p, bn.x1, bn.Lh1, bn.Ll1, ec), a1);
+// ------------------------------------------------------------ 1-D fold ----
+// A workgroup owns kFoldTile1 = 32 window bins and a set of cells.  Each
+// quarter-wave covers the whole tile, two bins per lane (bins j and j + 16 for
+// lane j of the quarter), and the 16 quarter-waves of the workgroup take the
+// cells in turn, so one LDS read of a cell (a broadcast to 16 lanes) feeds two
+// pairs.  Narrow tiles keep the pairs evaluated outside the cells' supports
+// (at the support ends of the cells that meet a tile) few.
+//
+// Tile-relative exponent.  Within a tile the log-density of a cell is written
+// about a reference point xr of the tile (a bin midpoint):
+//   gamma:    E(x) = E(xr) + (k - 1) (ln x - ln xr) - (x - xr) / th
+//   Gaussian: E(x) = E(xr) + a (x - xr) + c (x - xr)^2,  a = (m - xr)/s^2, c = -1/(2 s^2)
+// i.e. E = Eref + A u + B v with per-lane bin offsets (u, v) and per-cell
+// staged values {A, B, Eref, W}.  Eref is evaluated once per cell and tile,
+// in double-double for gamma (its terms of size k ln x cancel), so a pair
+// costs two FMAs before the exponential.  The offsets are small (u = ln(x/xr)
+// spans a tile, not the whole range), and the rounding of A u + B v adds at
+// most ~3u (|A u| + |B v|) to E: below 1e-14 on every pair that contributes.
+struct Off2 {
+  double u0, v0, u1, v1;  // offsets of the lane's two bins
+};
+struct TileRef {
+  double x, Lh, Ll;  // reference midpoint and its logarithm (hi, lo)
+};
+
+__device__ __forceinline__ void fold_pair_ref(const double *__restrict__ p, const Off2 &o, const ExpK &ec, double &a0,
+                                              double &a1) {
+  a0 = __fma_rn(p[3], dexp(__fma_rn(p[0], o.u0, __fma_rn(p[1], o.v0, p[2])), ec), a0);
+  a1 = __fma_rn(p[3], dexp(__fma_rn(p[0], o.u1, __fma_rn(p[1], o.v1, p[2])), ec), a1);
 }
 
 // Cell quads wave, wave + kWaves, ... of a staged batch of nb cells (nb a
-// multiple of 4: a batch is padded with zero records); quarter h of the wave
-// takes the cell 4k + h of quad k.
-template <int FAM>
-__device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Bin2 &bn, const ExpK &ec,
+// multiple of 4: a batch is padded with zero cells); quarter h of the wave
+// takes the cell 4k + h of quad k.  A staged cell is 4 doubles.
+__device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Off2 &o, const ExpK &ec,
                                            double &a0, double &a1) {
-  constexpr int L = Stage<FAM>::kLen;
   const int h = (threadIdx.x >> 4) & 3;
   const int nq = nb >> 2;
-  const double *base = srec + h * L;
+  const double *base = srec + h * 4;
   int k = wave;
   for (; k + kWaves < nq; k += 2 * kWaves) {
-    double p[L], q[L];
-#pragma unroll
-    for (int e = 0; e < L; e += 2) {
-      const double2 u = *(const double2 *)(base + 4 * k * L + e);
-      const double2 w = *(const double2 *)(base + 4 * (k + kWaves) * L + e);
-      p[e] = u.x;
-      p[e + 1] = u.y;
-      q[e] = w.x;
-      q[e + 1] = w.y;
-    }
-    fold_pair2<FAM>(p, bn, ec, a0, a1);
-    fold_pair2<FAM>(q, bn, ec, a0, a1);
+    const double2 p0 = *(const double2 *)(base + 16 * k), p1 = *(const double2 *)(base + 16 * k + 2);
+    const double2 q0 = *(const double2 *)(base + 16 * (k + kWaves));
+    const double2 q1 = *(const double2 *)(base + 16 * (k + kWaves) + 2);
+    const double p[4] = {p0.x, p0.y, p1.x, p1.y}, q[4] = {q0.x, q0.y, q1.x, q1.y};
+    fold_pair_ref(p, o, ec, a0, a1);
+    fold_pair_ref(q, o, ec, a0, a1);
   }
   if (k < nq) {
-    double p[L];
-#pragma unroll
-    for (int e = 0; e < L; e += 2) {
-      const double2 u = *(const double2 *)(base + 4 * k * L + e);
-      p[e] = u.x;
-      p[e + 1] = u.y;
-    }
-    fold_pair2<FAM>(p, bn, ec, a0, a1);
+    const double2 p0 = *(const double2 *)(base + 16 * k), p1 = *(const double2 *)(base + 16 * k + 2);
+    const double p[4] = {p0.x, p0.y, p1.x, p1.y};
+    fold_pair_ref(p, o, ec, a0, a1);
   }
+}
+
+// The record parts a staged cell is formed from (zeros for cell < 0: a zero
+// record has weight 0).
+template <int FAM>
+__device__ __forceinline__ void stage_load(const double *__restrict__ R, int cell, double2 (&f)[3]) {
+  f[0] = f[1] = f[2] = make_double2(0.0, 0.0);
+  if (cell < 0) return;
+  const double2 *r = (const double2 *)(R + (size_t)cell * kRecLen);
+  f[0] = r[0];
+  f[1] = r[1];
+  if (FAM == kGammaPE) f[2] = r[2];
+}
+
+// Staged cell c = {A, B, Eref, W} about the tile's reference point.
+template <int FAM>
+__device__ __forceinline__ void stage_store(double *srec, int c, const double2 (&f)[3], const TileRef &ref) {
+  double A, B, E, W;
+  if (FAM == kGammaPE) {
+    // record {k - 1, 1/th hi, lo, C hi, lo, W}
+    E = gamma_exponent(f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, ref.x, ref.Lh, ref.Ll);
+    A = f[0].x;
+    B = -f[0].y;
+    W = f[2].y;
+  } else {
+    // record {m, 1/s, c0, W}
+    const double is = f[0].y, z = (ref.x - f[0].x) * is;
+    E = __fma_rn(-0.5 * z, z, f[1].x);
+    A = -z * is;
+    B = -0.5 * is * is;
+    W = f[1].y;
+  }
+  ((double2 *)srec)[2 * c] = make_double2(A, B);
+  ((double2 *)srec)[2 * c + 1] = make_double2(E, W);
 }
 
 // All cells of [c_lo, c_hi) against the tile (block-uniform range; every
-// thread of the block calls this).  Staged part q of a batch is part q % P of
-// cell q / P, stored at srec[2q].
+// thread of the block calls this), kStage1 cells per batch, one per thread.
 template <int FAM>
 __device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_lo, int c_hi, double *srec, int wave,
-                                           const Bin2 &bn, const ExpK &ec, double &a0, double &a1) {
-  constexpr int P = Stage<FAM>::kParts;
-  static_assert(kStage * P <= 2 * kWaves * 64, "two staged parts per thread");
+                                           const TileRef &ref, const Off2 &o, const ExpK &ec, double &a0,
+                                           double &a1) {
+  static_assert(kStage1 == kWaves * 64, "one staged cell per thread");
   const int tid = threadIdx.x;
-  double2 f0 = make_double2(0.0, 0.0), f1 = make_double2(0.0, 0.0);
-  auto fetch = [&](int base) {
-    const int n = min(kStage, c_hi - base) * P;
-    const int q0 = tid, q1 = tid + kWaves * 64;
-    f0 = q0 < n ? *(const double2 *)(R + (size_t)(base + q0 / P) * kRecLen + 2 * (q0 % P)) : make_double2(0.0, 0.0);
-    f1 = q1 < n ? *(const double2 *)(R + (size_t)(base + q1 / P) * kRecLen + 2 * (q1 % P)) : make_double2(0.0, 0.0);
-  };
-  if (c_lo < c_hi) fetch(c_lo);
-  for (int base = c_lo; base < c_hi; base += kStage) {
-    const int nb = (min(kStage, c_hi - base) + 3) & ~3;  // padded to whole cell quads
+  double2 f[3];
+  if (c_lo < c_hi) stage_load<FAM>(R, c_lo + tid < c_hi ? c_lo + tid : -1, f);
+  for (int base = c_lo; base < c_hi; base += kStage1) {
+    const int nb = (min(kStage1, c_hi - base) + 3) & ~3;  // padded to whole cell quads
     __syncthreads();  // every wave is done with the previous batch
-    if (tid < nb * P) ((double2 *)srec)[tid] = f0;
-    if (tid + kWaves * 64 < nb * P) ((double2 *)srec)[tid + kWaves * 64] = f1;
+    if (tid < nb) stage_store<FAM>(srec, tid, f, ref);
     __syncthreads();
-    if (base + kStage < c_hi) fetch(base + kStage);
-    fold_batch<FAM>(srec, nb, wave, bn, ec, a0, a1);
+    const int nxt = base + kStage1 + tid;
+    if (base + kStage1 < c_hi) stage_load<FAM>(R, nxt < c_hi ? nxt : -1, f);
+    fold_batch(srec, nb, wave, o, ec, a0, a1);
   }
-}
-
-// Grid cells of a chunk whose support can reach window bins [j0, j1): the
-// span of the kGroup-cell groups whose hull meets the tile (block-uniform).
-__device__ __forceinline__ int2 grid_range(const int2 *__restrict__ hull, int c0, int c1, int j0, int j1, int *rng) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int first = 0x7fffffff, last = -1;
-  for (int g = c0 / kGroup + (int)threadIdx.x; g * kGroup < c1; g += kWaves * 64) {
-    const int2 h = hull[g];
-    if (h.x < j1 && h.y > j0) {
-      first = min(first, g);
-      last = max(last, g);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    first = min(first, __shfl_xor(first, o, 64));
-    last = max(last, __shfl_xor(last, o, 64));
-  }
-  __syncthreads();  // rng may still be read by a previous call
-  if (lane == 0) {
-    rng[wave] = first;
-    rng[kWaves + wave] = last;
-  }
-  __syncthreads();
-  first = min(min(rng[0], rng[1]), min(rng[2], rng[3]));
-  last = max(max(rng[kWaves], rng[kWaves + 1]), max(rng[kWaves + 2], rng[kWaves + 3]));
-  if (last < 0) return make_int2(0, 0);  // empty (first is never used past INT_MAX)
-  return make_int2(max(c0, first * kGroup), min(c1, (last + 1) * kGroup));
 }
 
 // Compacts, in increasing order, the groups g in [g0, g1) (at most one per
@@ -297,39 +297,29 @@ __device__ __forceinline__ int group_list(const int2 *__restrict__ hull, int g0,
 }
 
 // All cells of the listed groups, clipped to [c_lo, c_hi), against the tile.
-// A batch holds kStage / kGroup groups; cells past the clip are staged as
-// zero records (weight 0).
+// A batch holds kStage1 / kGroup groups; cells past the clip are staged as
+// zero cells (weight 0).
 template <int FAM>
 __device__ __forceinline__ void fold_groups(const double *__restrict__ R, const int *list, int n_list, int c_lo,
-                                            int c_hi, double *srec, int wave, const Bin2 &bn, const ExpK &ec,
-                                            double &a0, double &a1) {
-  constexpr int P = Stage<FAM>::kParts;
-  constexpr int kGPB = kStage / kGroup;
+                                            int c_hi, double *srec, int wave, const TileRef &ref, const Off2 &o,
+                                            const ExpK &ec, double &a0, double &a1) {
+  constexpr int kGPB = kStage1 / kGroup;
   const int tid = threadIdx.x;
-  double2 f0, f1;
-  auto part = [&](int bi, int q) {
-    const int cs = q / P, gs = cs / kGroup, li = bi * kGPB + gs;
-    const int cell = li < n_list ? list[li] * kGroup + cs % kGroup : -1;
-    if (q < kStage * P && cell >= c_lo && cell < c_hi)
-      return *(const double2 *)(R + (size_t)cell * kRecLen + 2 * (q % P));
-    return make_double2(0.0, 0.0);
+  auto cell_of = [&](int bi) {
+    const int li = bi * kGPB + tid / kGroup;
+    const int cell = li < n_list ? list[li] * kGroup + tid % kGroup : -1;
+    return cell >= c_lo && cell < c_hi ? cell : -1;
   };
+  double2 f[3];
   const int n_batch = (n_list + kGPB - 1) / kGPB;
-  if (n_batch > 0) {
-    f0 = part(0, tid);
-    f1 = part(0, tid + kWaves * 64);
-  }
+  if (n_batch > 0) stage_load<FAM>(R, cell_of(0), f);
   for (int bi = 0; bi < n_batch; bi++) {
     const int nb = min(kGPB, n_list - bi * kGPB) * kGroup;
     __syncthreads();  // every wave is done with the previous batch
-    if (tid < nb * P) ((double2 *)srec)[tid] = f0;
-    if (tid + kWaves * 64 < nb * P) ((double2 *)srec)[tid + kWaves * 64] = f1;
+    if (tid < nb) stage_store<FAM>(srec, tid, f, ref);
     __syncthreads();
-    if (bi + 1 < n_batch) {
-      f0 = part(bi + 1, tid);
-      f1 = part(bi + 1, tid + kWaves * 64);
-    }
-    fold_batch<FAM>(srec, nb, wave, bn, ec, a0, a1);
+    if (bi + 1 < n_batch) stage_load<FAM>(R, cell_of(bi + 1), f);
+    fold_batch(srec, nb, wave, o, ec, a0, a1);
   }
 }
 
@@ -337,7 +327,7 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
                                                const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ rec, const int2 *__restrict__ ghull,
                                                const uint8_t *__restrict__ active, double *__restrict__ out) {
-  __shared__ __align__(16) double srec[kStage * 6];
+  __shared__ __align__(16) double srec[kStage1 * 4];
   __shared__ double red[kWaves * 4 * kFoldTile1];
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
@@ -351,31 +341,48 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int kHalf = kFoldTile1 / 2;
+  const bool gamma = Sh.family == kGammaPE;
+  const int last = min(it.bin0 + kFoldTile1, T.L) - 1;  // last window bin of the tile
   const int b0 = it.bin0 + (lane & (kHalf - 1)), b1 = b0 + kHalf;
-  const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
-  const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
-  const Bin2 bn{bp0[0], bp0[2], bp0[3], bp1[0], bp1[2], bp1[3]};
-  const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile1, T.L);
+  const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, last)) * kBinLen;
+  const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, last)) * kBinLen;
+  // reference point: the tile's middle bin (its last bin when the middle
+  // midpoint is not positive: the gamma density lives on x > 0)
+  const double *br = Sh.bins + (size_t)(T.lo + min(it.bin0 + kHalf, last)) * kBinLen;
+  if (gamma && !(br[0] > 0.0)) br = Sh.bins + (size_t)(T.lo + last) * kBinLen;
+  const TileRef ref{br[0], br[2], br[3]};
+  Off2 o;
+  if (gamma) {
+    o.u0 = (bp0[2] - ref.Lh) + (bp0[3] - ref.Ll);
+    o.v0 = bp0[0] - ref.x;
+    o.u1 = (bp1[2] - ref.Lh) + (bp1[3] - ref.Ll);
+    o.v1 = bp1[0] - ref.x;
+  } else {
+    o.u0 = bp0[0] - ref.x;
+    o.v0 = o.u0 * o.u0;
+    o.u1 = bp1[0] - ref.x;
+    o.v1 = o.u1 * o.u1;
+  }
+  const int j0 = T.lo + it.bin0, j1 = T.lo + last + 1;
   const double *R = rec + T.cell_off * kRecLen;
   // grid cells: the groups whose hull meets the tile, up to kWaves * 64 groups per pass
   const int g_end = min(it.cell1, Sh.n_true);
   const int l_lo = max(it.cell0, Sh.n_true), l_hi = it.cell1;  // line cells: few, all evaluated
-  const bool gamma = Sh.family == kGammaPE;
   double a0 = 0.0, a1 = 0.0;
   for (int gb = it.cell0 / kGroup; gb * kGroup < g_end; gb += kWaves * 64) {
     const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
                              glist, gcnt);
     if (gamma)
-      fold_groups<kGammaPE>(R, glist, n, it.cell0, g_end, srec, wave, bn, ec, a0, a1);
+      fold_groups<kGammaPE>(R, glist, n, it.cell0, g_end, srec, wave, ref, o, ec, a0, a1);
     else
-      fold_groups<kGaussE>(R, glist, n, it.cell0, g_end, srec, wave, bn, ec, a0, a1);
+      fold_groups<kGaussE>(R, glist, n, it.cell0, g_end, srec, wave, ref, o, ec, a0, a1);
   }
   if (gamma) {
-    fold_range<kGammaPE>(R, l_lo, l_hi, srec, wave, bn, ec, a0, a1);
-    if (!(bn.x0 > 0.0)) a0 = 0.0;  // outside the gamma support
-    if (!(bn.x1 > 0.0)) a1 = 0.0;
+    fold_range<kGammaPE>(R, l_lo, l_hi, srec, wave, ref, o, ec, a0, a1);
+    if (!(bp0[0] > 0.0)) a0 = 0.0;  // outside the gamma support
+    if (!(bp1[0] > 0.0)) a1 = 0.0;
   } else {
-    fold_range<kGaussE>(R, l_lo, l_hi, srec, wave, bn, ec, a0, a1);
+    fold_range<kGaussE>(R, l_lo, l_hi, srec, wave, ref, o, ec, a0, a1);
   }
   // red[stream][bin]: stream = wave * 4 + quarter, bin of the tile
   const int stream = threadIdx.x >> 4, j = lane & (kHalf - 1);
