@@ -387,7 +387,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   }
   const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
   const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
-  long long cell_off = 0, win_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
+  long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
   long long nllp_off = 0, gpart_off = 0, cflag_off = 0, vpart_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0;
   std::vector<double> cnt_h, pc_h, ps_h;
   BatchView &v = B->v;
@@ -431,6 +431,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.ghull_off = ghull_off;
     T.cell_off = cell_off;
     T.win_off = win_off;
+    T.bref_off = bref_off;
     T.cnt_off = cnt_off;
     T.fpart_off = fpart_off;
     T.fs_off = fs_off;
@@ -458,6 +459,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     }
     cell_off += sh.n_cell;
     win_off += T.L;
+    bref_off += (T.L + kABlock - 1) / kABlock;
     cnt_off += (long long)T.D * T.L * T.K;
     fpart_off += (long long)T.fold_chunks * T.L;
     fs_off += (long long)T.fold_chunks * T.L * T.S;
@@ -515,6 +517,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
   HIP_TRY(B->alloc(&v.apart, (size_t)apart_off));
   HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinRecLen));
+  HIP_TRY(B->alloc(&v.bref, (size_t)bref_off * 4));
   HIP_TRY(B->alloc(&v.nllp, (size_t)nllp_off));
   HIP_TRY(B->alloc(&v.badp, (size_t)nllp_off));
   HIP_TRY(B->alloc(&v.gpart, (size_t)gpart_off * kGradLen));

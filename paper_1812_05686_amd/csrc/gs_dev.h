@@ -28,7 +28,7 @@ namespace gs {
 
 constexpr int kRecLen = 8;  // doubles per cell record
 constexpr int kBinLen = 4;     // doubles per static bin record: xbar, dx, ln xbar (hi, lo)
-constexpr int kBinRecLen = 8;  // doubles per evaluated window bin: x, ln x (hi, lo), G, G ln x, G x, -, -
+constexpr int kBinRecLen = 8;  // doubles per evaluated window bin: x, ln x (hi, lo), G, G ln x, G x, u, v
 constexpr double kHalfLn2Pi = 0.91893853320467274178032973640561764;  // ln(2 pi)/2
 // ln 2 as an unevaluated sum hi + lo (hi = nearest double)
 constexpr double kLn2Hi = 0.6931471805599453094;   // 0x1.62e42fefa39efp-1

@@ -11,6 +11,7 @@ namespace gs {
 constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins per per-species fold tile
 constexpr int kFoldTile = 64;   // window bins per per-species fold item (two per lane of each half-wave)
 constexpr int kFoldTile1 = 32;  // window bins per 1-D fold item (two per lane of each quarter-wave)
+constexpr int kABlock = 32;     // window bins per adjoint exponent reference block
 constexpr int kStage = 128;     // cell records staged in LDS per batch of the per-species fold
 constexpr int kStage1 = 256;    // cells staged in LDS per batch of the 1-D fold (one per thread)
 constexpr int kGroup = 16;      // grid cells per support hull
@@ -47,6 +48,7 @@ struct ToyDev {
   int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
   long long cell_off;   // rec[(cell_off + i) * kRecLen]
   long long win_off;    // binrec[(win_off + b) * kBinRecLen], F[(win_off + b) * S]
+  long long bref_off;   // adjoint block references: bref[(bref_off + q) * 4], q = b / kABlock
   long long cnt_off;    // counts of the window: cnt[cnt_off + (d * L + b) * K + k]
   long long fpart_off;  // fold partials: fpart[fpart_off + chunk * L + b]
   long long fs_off;     // per-species fold partials: fspart[fs_off + (chunk * L + b) * S + s]
@@ -97,7 +99,8 @@ struct BatchView {
   double *fspart;   // fold partials per species
   double *F;        // per-species spectra of the window, bin width included
   double *apart;    // adjoint partials
-  double *binrec;   // window bins: xbar, ln xbar hi, lo, G, G ln xbar, G xbar
+  double *binrec;   // window bins: xbar, ln xbar hi, lo, G, G ln xbar, G xbar, block offsets u, v
+  double *bref;     // per block of kABlock window bins: reference xbar, ln xbar (hi, lo), 0
   double *nllp;     // -ln L partials
   double *gpart;    // gradient partials
   uint32_t *badp;   // domain flags per bin block

@@ -578,6 +578,38 @@ hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uin
   return hipGetLastError();
 }
 
+// -------------------------------------------- adjoint block references ---
+// The adjoint evaluates a cell's log-density relative to a reference point
+// per block of kABlock window bins (as the 1-D fold does per tile):
+// E(x) = E(xr) + (k - 1) u + (-1/th) v with u = ln x - ln xr, v = x - xr.
+// The bin offsets (u, v) go into the window-bin record (slots 6, 7) and the
+// reference itself into the block's row of bref; E(xr) is formed per cell
+// and block in double-double.  The reference is the block's middle bin, or
+// its last bin when that midpoint is not positive (the gamma density lives
+// on x > 0).
+__device__ __forceinline__ const double *block_ref(const ShapeDev &Sh, const ToyDev &T, int q) {
+  const int last = min((q + 1) * kABlock, T.L) - 1;
+  const double *r = Sh.bins + (size_t)(T.lo + min(q * kABlock + kABlock / 2, last)) * kBinLen;
+  if (Sh.family == kGammaPE && !(r[0] > 0.0)) r = Sh.bins + (size_t)(T.lo + last) * kBinLen;
+  return r;
+}
+
+// Offsets (u, v) of window bin b (shape bin record bn) from its block's
+// reference; the block's first bin also writes the block's bref row.
+__device__ __forceinline__ void block_offsets(const ShapeDev &Sh, const ToyDev &T, int b, const double *bn, double &u,
+                                              double &v, double *__restrict__ bref) {
+  const double *r = block_ref(Sh, T, b / kABlock);
+  u = (bn[2] - r[2]) + (bn[3] - r[3]);
+  v = bn[0] - r[0];
+  if (b % kABlock == 0) {
+    double *o = bref + (T.bref_off + b / kABlock) * 4;
+    o[0] = r[0];
+    o[1] = r[2];
+    o[2] = r[3];
+    o[3] = 0.0;
+  }
+}
+
 // ------------------------------------------------------------- k_bins1 ----
 // Poisson term of Eq.4 (ln n! dropped).  Returns false on a domain error.
 __device__ __forceinline__ bool poisson_term(double mu, double n, double &term, double &g) {
@@ -594,8 +626,8 @@ __device__ __forceinline__ bool poisson_term(double mu, double n, double &term, 
 __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ fpart, const double *__restrict__ cnt,
                                                const uint8_t *__restrict__ active, double *__restrict__ binrec,
-                                               double *__restrict__ nllp, uint32_t *__restrict__ badp,
-                                               double *__restrict__ mu_out) {
+                                               double *__restrict__ bref, double *__restrict__ nllp,
+                                               uint32_t *__restrict__ badp, double *__restrict__ mu_out) {
   __shared__ double lds[8];
   __shared__ int bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
@@ -641,6 +673,7 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
     br[3] = Gd;
     br[4] = Gd * bn[2];
     br[5] = Gd * bn[0];
+    block_offsets(Sh, T, b, bn, br[6], br[7], bref);
     if (bad) bad_s = 1;  // benign race: every writer stores 1
   }
   const double tot = block_sum(sum, lds);
@@ -654,7 +687,7 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
 hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *active, hipStream_t st) {
   if (v.n1d == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bins1, dim3(v.max_bin_blocks1, v.n1d), dim3(kBlock), 0, st, v.list1d, v.toys, v.shapes, v.fpart,
-                     v.cnt, active, v.binrec, v.nllp, v.badp, mu_out);
+                     v.cnt, active, v.binrec, v.bref, v.nllp, v.badp, mu_out);
   return hipGetLastError();
 }
 
@@ -662,37 +695,59 @@ hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *activ
 // Per-cell sums over window bins of Gr = G_j r_ji times {1, t1, t2}:
 //  gamma:    t1 = ln x_j, t2 = x_j (shifted by ln m and m in k_cellgrad)
 //  gaussian: t1 = z_ji, t2 = z_ji^2 with z = (x - m)/s
+// Wave w of the workgroup takes the bins b0 + w, b0 + w + kWaves, ... of
+// [b0, b1); a gamma cell's exponent is formed per kABlock block about the
+// block's reference point (see block_ref).
 template <int FAM>
-__device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR, int b0, int b1,
-                                         const ExpK &ec, double &A0, double &A1, double &A2) {
+__device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR,
+                                         const double *__restrict__ BF, int b0, int b1, int wave, const ExpK &ec,
+                                         double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
-  // bin record: x, ln x (hi, lo), G, G ln x, G x
-  const double *br = BR + (size_t)b0 * kBinRecLen;
-  double x = br[0], Lh = br[1], Ll = br[2], G = br[3], GL = br[4], GX = br[5];
-  for (int b = b0; b < b1; b += kWaves) {
-    const double *bn = BR + (size_t)min(b + kWaves, b1 - 1) * kBinRecLen;  // next bin, fetched early
-    const double nx = bn[0], nLh = bn[1], nLl = bn[2], nG = bn[3], nGL = bn[4], nGX = bn[5];
-    if (FAM == kGammaPE) {
-      if (G != 0.0) {  // wave-uniform: zero seed, or bin outside the gamma support
-        const double r = dexp(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
-        A0 = __fma_rn(G, r, A0);
-        A1 = __fma_rn(GL, r, A1);
-        A2 = __fma_rn(GX, r, A2);
+  if (FAM == kGammaPE) {
+    // A zero seed (also every bin outside the gamma support, x <= 0, whose
+    // offsets are finite) adds exactly zero: no test per bin.
+    const double K = rc[0], mB = -rc[1];
+    for (int q = b0 / kABlock; q * kABlock < b1; q++) {
+      const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
+      int b = lo + ((b0 + wave - lo) & (kWaves - 1));  // first bin of this wave in the block
+      if (b >= hi) continue;
+      const double *r = BF + (size_t)q * 4;
+      const double Eref = gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], r[0], r[1], r[2]);
+      for (; b + kWaves < hi; b += 2 * kWaves) {
+        // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
+        const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + kWaves * kBinRecLen;
+        const double r0 = dexp(__fma_rn(K, p[6], __fma_rn(mB, p[7], Eref)), ec);
+        const double r1 = dexp(__fma_rn(K, p2[6], __fma_rn(mB, p2[7], Eref)), ec);
+        A0 = __fma_rn(p[3], r0, A0);
+        A1 = __fma_rn(p[4], r0, A1);
+        A2 = __fma_rn(p[5], r0, A2);
+        A0 = __fma_rn(p2[3], r1, A0);
+        A1 = __fma_rn(p2[4], r1, A1);
+        A2 = __fma_rn(p2[5], r1, A2);
       }
-    } else {
-      double z;
-      const double Gr = G * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
-      const double Grz = Gr * z;
-      A0 += Gr;
-      A1 += Grz;
-      A2 = __fma_rn(Grz, z, A2);
+      if (b < hi) {
+        const double *p = BR + (size_t)b * kBinRecLen;
+        const double r0 = dexp(__fma_rn(K, p[6], __fma_rn(mB, p[7], Eref)), ec);
+        A0 = __fma_rn(p[3], r0, A0);
+        A1 = __fma_rn(p[4], r0, A1);
+        A2 = __fma_rn(p[5], r0, A2);
+      }
     }
+    return;
+  }
+  const double *br = BR + (size_t)(b0 + wave) * kBinRecLen;
+  double x = br[0], G = br[3];
+  for (int b = b0 + wave; b < b1; b += kWaves) {
+    const double *bn = BR + (size_t)min(b + kWaves, b1 - 1) * kBinRecLen;  // next bin, fetched early
+    const double nx = bn[0], nG = bn[3];
+    double z;
+    const double Gr = G * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
+    const double Grz = Gr * z;
+    A0 += Gr;
+    A1 += Grz;
+    A2 = __fma_rn(Grz, z, A2);
     x = nx;
-    Lh = nLh;
-    Ll = nLl;
     G = nG;
-    GL = nGL;
-    GX = nGX;
   }
 }
 
@@ -701,30 +756,48 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
 // keeps R_s w_si of its cell and each bin brings its H row.
 template <int FAM>
 __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
-                                           const double *__restrict__ BR, const double *__restrict__ HR, int b0, int b1,
-                                           const ExpK &ec, double &A0, double &A1, double &A2) {
-  for (int b = b0; b < b1; b += kWaves) {
+                                           const double *__restrict__ BR, const double *__restrict__ BF,
+                                           const double *__restrict__ HR, int b0, int b1, int wave, const ExpK &ec,
+                                           double &A0, double &A1, double &A2) {
+  if (b0 >= b1) return;
+  if (FAM == kGammaPE) {
+    for (int q = b0 / kABlock; q * kABlock < b1; q++) {
+      const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
+      int b = lo + ((b0 + wave - lo) & (kWaves - 1));
+      if (b >= hi) continue;
+      const double *r = BF + (size_t)q * 4;
+      const double Eref = gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], r[0], r[1], r[2]);
+      const double K = rc[0], mB = -rc[1];
+      for (; b < hi; b += kWaves) {
+        const double *br = BR + (size_t)b * kBinRecLen;
+        if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
+        const double *h = HR + (size_t)b * S;
+        double Z = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
+          if (q2 < S) Z = __fma_rn(h[q2], rw[q2], Z);
+        const double Gr = Z * dexp(__fma_rn(K, br[6], __fma_rn(mB, br[7], Eref)), ec);
+        A0 += Gr;
+        A1 = __fma_rn(Gr, br[1], A1);
+        A2 = __fma_rn(Gr, br[0], A2);
+      }
+    }
+    return;
+  }
+  for (int b = b0 + wave; b < b1; b += kWaves) {
     const double *br = BR + (size_t)b * kBinRecLen;
-    const double x = br[0], Lh = br[1], Ll = br[2];
-    if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
+    const double x = br[0];
     const double *h = HR + (size_t)b * S;
     double Z = 0.0;
 #pragma unroll
     for (int q = 0; q < GS_MAX_SPECIES; q++)
       if (q < S) Z = __fma_rn(h[q], rw[q], Z);
-    if (FAM == kGammaPE) {
-      const double Gr = Z * dexp(gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], x, Lh, Ll), ec);
-      A0 += Gr;
-      A1 = __fma_rn(Gr, Lh, A1);
-      A2 = __fma_rn(Gr, x, A2);
-    } else {
-      double z;
-      const double Gr = Z * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
-      const double Grz = Gr * z;
-      A0 += Gr;
-      A1 += Grz;
-      A2 = __fma_rn(Grz, z, A2);
-    }
+    double z;
+    const double Gr = Z * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
+    const double Grz = Gr * z;
+    A0 += Gr;
+    A1 += Grz;
+    A2 = __fma_rn(Grz, z, A2);
   }
 }
 
@@ -733,7 +806,8 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                              const double *__restrict__ theta, int stride,
                                              const double *__restrict__ rec, const double *__restrict__ binrec,
-                                             const double *__restrict__ H, const uint8_t *__restrict__ active,
+                                             const double *__restrict__ bref, const double *__restrict__ H,
+                                             const uint8_t *__restrict__ active,
                                              double *__restrict__ apart) {
   __shared__ double red[kWaves * kTile * 3];
   const ExpK ec = exp_consts();
@@ -760,13 +834,13 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
     hi = max(hi, __shfl_xor(hi, o, 64));
   }
   const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
-  const double *BR = binrec + T.win_off * kBinRecLen;
+  const double *BR = binrec + T.win_off * kBinRecLen, *BF = bref + T.bref_off * 4;
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
   if (!PS) {
     if (Sh.family == kGammaPE)
-      adj_bins<kGammaPE>(rc, BR, b0 + wave, b1, ec, A0, A1, A2);
+      adj_bins<kGammaPE>(rc, BR, BF, b0, b1, wave, ec, A0, A1, A2);
     else
-      adj_bins<kGaussE>(rc, BR, b0 + wave, b1, ec, A0, A1, A2);
+      adj_bins<kGaussE>(rc, BR, BF, b0, b1, wave, ec, A0, A1, A2);
   } else {
     const double *th = theta + (size_t)it.toy * stride;
     double rw[GS_MAX_SPECIES];
@@ -785,9 +859,9 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
     }
     const double *HR = H + T.win_off * T.S;
     if (Sh.family == kGammaPE)
-      adj_bins_s<kGammaPE>(rc, rw, T.S, BR, HR, b0 + wave, b1, ec, A0, A1, A2);
+      adj_bins_s<kGammaPE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, A0, A1, A2);
     else
-      adj_bins_s<kGaussE>(rc, rw, T.S, BR, HR, b0 + wave, b1, ec, A0, A1, A2);
+      adj_bins_s<kGaussE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, A0, A1, A2);
   }
   red[(wave * 3 + 0) * kTile + lane] = A0;
   red[(wave * 3 + 1) * kTile + lane] = A1;
@@ -809,10 +883,10 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
   if (n == 0) return hipSuccess;
   if (per_species)
     hipLaunchKernelGGL(k_adj<true>, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes,
-                       v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
+                       v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
   else
     hipLaunchKernelGGL(k_adj<false>, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes,
-                       v.theta_dev, v.stride, v.rec, v.binrec, v.H, active, v.apart);
+                       v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
   return hipGetLastError();
 }
 
@@ -1286,7 +1360,8 @@ __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list,
                                                const ShapeDev *__restrict__ shapes, const double *__restrict__ F,
                                                const double *__restrict__ P, const double *__restrict__ Gam,
                                                const uint8_t *__restrict__ active, double *__restrict__ binrec,
-                                               double *__restrict__ H, double *__restrict__ vpart) {
+                                               double *__restrict__ bref, double *__restrict__ H,
+                                               double *__restrict__ vpart) {
   extern __shared__ double ps[];  // [S][K]
   __shared__ double red[kHTile][GS_MAX_SPECIES];
   const int t = toy_of(toy_list, blockIdx.y);
@@ -1318,6 +1393,7 @@ __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list,
       br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
       br[4] = 0.0;
       br[5] = 0.0;
+      block_offsets(Sh, T, b, bn, br[6], br[7], bref);
     }
   }
   red[jj][q] = a;
@@ -1339,7 +1415,7 @@ hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hseed, dim3(v.max_hblocks, v.n2d), dim3(kHTile * GS_MAX_SPECIES),
                      sizeof(double) * v.max_psd_sk, st, v.list2d, v.toys, v.shapes, v.F, v.P, v.Gam, active,
-                     v.binrec, v.H, v.vpart);
+                     v.binrec, v.bref, v.H, v.vpart);
   return hipGetLastError();
 }
 
