@@ -265,6 +265,40 @@ GS_HD inline double gauss_exponent(double m, double is, double c0, double x, dou
   return fma(-0.5 * z, z, c0);
 }
 
+// Pair exponent relative to a reference point xr (a bin midpoint, with
+// ln xr as hi + lo), used where many pairs share xr (a fold tile, an adjoint
+// bin block):  E(x) = Eref + A u + B v  with
+//   gamma:    u = ln x - ln xr, v = x - xr;      A = k - 1, B = -1/th
+//   Gaussian: u = x - xr,      v = (x - xr)^2;   A = (m - xr)/s^2, B = -1/(2 s^2)
+// and Eref = E(xr), formed from the cell record (double-double for gamma).
+// With u and v small (xr within a tile or block of x), rounding adds about
+// u_64 (|A u| + |B v| + |E|) to E, instead of u_64 |(k - 1) ln x| for a
+// plain evaluation.
+struct RelCell {
+  double A, B, Eref;
+};
+
+GS_HD inline RelCell rel_cell(int fam, const double *rc, double xr, double Lhr, double Llr) {
+  if (fam == kGammaPE) return {rc[0], -rc[1], gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], xr, Lhr, Llr)};
+  const double is = rc[1], z = (xr - rc[0]) * is;
+  return {-z * is, -0.5 * is * is, fma(-0.5 * z, z, rc[2])};
+}
+
+GS_HD inline void rel_offsets(int fam, double x, double Lh, double Ll, double xr, double Lhr, double Llr, double &u,
+                              double &v) {
+  if (fam == kGammaPE) {
+    u = (Lh - Lhr) + (Ll - Llr);
+    v = x - xr;
+  } else {
+    u = x - xr;
+    v = u * u;
+  }
+}
+
+GS_HD inline double rel_exponent(double A, double B, double Eref, double u, double v) {
+  return fma(A, u, fma(B, v, Eref));
+}
+
 }  // namespace gs
 
 #pragma clang fp contract(fast)

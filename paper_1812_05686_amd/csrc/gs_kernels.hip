@@ -171,16 +171,12 @@ struct Bin2 {
 // pairs.  Narrow tiles keep the pairs evaluated outside the cells' supports
 // (at the support ends of the cells that meet a tile) few.
 //
-// Tile-relative exponent.  Within a tile the log-density of a cell is written
-// about a reference point xr of the tile (a bin midpoint):
-//   gamma:    E(x) = E(xr) + (k - 1) (ln x - ln xr) - (x - xr) / th
-//   Gaussian: E(x) = E(xr) + a (x - xr) + c (x - xr)^2,  a = (m - xr)/s^2, c = -1/(2 s^2)
-// i.e. E = Eref + A u + B v with per-lane bin offsets (u, v) and per-cell
-// staged values {A, B, Eref, W}.  Eref is evaluated once per cell and tile,
-// in double-double for gamma (its terms of size k ln x cancel), so a pair
-// costs two FMAs before the exponential.  The offsets are small (u = ln(x/xr)
-// spans a tile, not the whole range), and the rounding of A u + B v adds at
-// most ~3u (|A u| + |B v|) to E: below 1e-14 on every pair that contributes.
+// Tile-relative exponent (rel_cell, rel_offsets, rel_exponent): within a
+// tile the log-density of a cell is written about a reference point xr of the
+// tile (a bin midpoint) as E = Eref + A u + B v, with per-lane bin offsets
+// (u, v) and per-cell staged values {A, B, Eref, W}.  Eref is evaluated once
+// per cell and tile, in double-double for gamma (its terms of size k ln x
+// cancel), so a pair costs two FMAs before the exponential.
 struct Off2 {
   double u0, v0, u1, v1;  // offsets of the lane's two bins
 };
@@ -190,8 +186,8 @@ struct TileRef {
 
 __device__ __forceinline__ void fold_pair_ref(const double *__restrict__ p, const Off2 &o, const ExpK &ec, double &a0,
                                               double &a1) {
-  a0 = __fma_rn(p[3], dexp(__fma_rn(p[0], o.u0, __fma_rn(p[1], o.v0, p[2])), ec), a0);
-  a1 = __fma_rn(p[3], dexp(__fma_rn(p[0], o.u1, __fma_rn(p[1], o.v1, p[2])), ec), a1);
+  a0 = __fma_rn(p[3], dexp(rel_exponent(p[0], p[1], p[2], o.u0, o.v0), ec), a0);
+  a1 = __fma_rn(p[3], dexp(rel_exponent(p[0], p[1], p[2], o.u1, o.v1), ec), a1);
 }
 
 // Cell quads wave, wave + kWaves, ... of a staged batch of nb cells (nb a
@@ -233,23 +229,12 @@ __device__ __forceinline__ void stage_load(const double *__restrict__ R, int cel
 // Staged cell c = {A, B, Eref, W} about the tile's reference point.
 template <int FAM>
 __device__ __forceinline__ void stage_store(double *srec, int c, const double2 (&f)[3], const TileRef &ref) {
-  double A, B, E, W;
-  if (FAM == kGammaPE) {
-    // record {k - 1, 1/th hi, lo, C hi, lo, W}
-    E = gamma_exponent(f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, ref.x, ref.Lh, ref.Ll);
-    A = f[0].x;
-    B = -f[0].y;
-    W = f[2].y;
-  } else {
-    // record {m, 1/s, c0, W}
-    const double is = f[0].y, z = (ref.x - f[0].x) * is;
-    E = __fma_rn(-0.5 * z, z, f[1].x);
-    A = -z * is;
-    B = -0.5 * is * is;
-    W = f[1].y;
-  }
-  ((double2 *)srec)[2 * c] = make_double2(A, B);
-  ((double2 *)srec)[2 * c + 1] = make_double2(E, W);
+  // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W}
+  const double rc[6] = {f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, f[2].y};
+  const RelCell q = rel_cell(FAM, rc, ref.x, ref.Lh, ref.Ll);
+  const double W = FAM == kGammaPE ? f[2].y : f[1].y;
+  ((double2 *)srec)[2 * c] = make_double2(q.A, q.B);
+  ((double2 *)srec)[2 * c + 1] = make_double2(q.Eref, W);
 }
 
 // All cells of [c_lo, c_hi) against the tile (block-uniform range; every
@@ -352,17 +337,8 @@ __global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ item
   if (gamma && !(br[0] > 0.0)) br = Sh.bins + (size_t)(T.lo + last) * kBinLen;
   const TileRef ref{br[0], br[2], br[3]};
   Off2 o;
-  if (gamma) {
-    o.u0 = (bp0[2] - ref.Lh) + (bp0[3] - ref.Ll);
-    o.v0 = bp0[0] - ref.x;
-    o.u1 = (bp1[2] - ref.Lh) + (bp1[3] - ref.Ll);
-    o.v1 = bp1[0] - ref.x;
-  } else {
-    o.u0 = bp0[0] - ref.x;
-    o.v0 = o.u0 * o.u0;
-    o.u1 = bp1[0] - ref.x;
-    o.v1 = o.u1 * o.u1;
-  }
+  rel_offsets(Sh.family, bp0[0], bp0[2], bp0[3], ref.x, ref.Lh, ref.Ll, o.u0, o.v0);
+  rel_offsets(Sh.family, bp1[0], bp1[2], bp1[3], ref.x, ref.Lh, ref.Ll, o.u1, o.v1);
   const int j0 = T.lo + it.bin0, j1 = T.lo + last + 1;
   const double *R = rec + T.cell_off * kRecLen;
   // grid cells: the groups whose hull meets the tile, up to kWaves * 64 groups per pass
@@ -599,8 +575,7 @@ __device__ __forceinline__ const double *block_ref(const ShapeDev &Sh, const Toy
 __device__ __forceinline__ void block_offsets(const ShapeDev &Sh, const ToyDev &T, int b, const double *bn, double &u,
                                               double &v, double *__restrict__ bref) {
   const double *r = block_ref(Sh, T, b / kABlock);
-  u = (bn[2] - r[2]) + (bn[3] - r[3]);
-  v = bn[0] - r[0];
+  rel_offsets(kGammaPE, bn[0], bn[2], bn[3], r[0], r[2], r[3], u, v);
   if (b % kABlock == 0) {
     double *o = bref + (T.bref_off + b / kABlock) * 4;
     o[0] = r[0];
@@ -706,18 +681,17 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
   if (FAM == kGammaPE) {
     // A zero seed (also every bin outside the gamma support, x <= 0, whose
     // offsets are finite) adds exactly zero: no test per bin.
-    const double K = rc[0], mB = -rc[1];
     for (int q = b0 / kABlock; q * kABlock < b1; q++) {
       const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
       int b = lo + ((b0 + wave - lo) & (kWaves - 1));  // first bin of this wave in the block
       if (b >= hi) continue;
       const double *r = BF + (size_t)q * 4;
-      const double Eref = gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], r[0], r[1], r[2]);
+      const RelCell c = rel_cell(kGammaPE, rc, r[0], r[1], r[2]);
       for (; b + kWaves < hi; b += 2 * kWaves) {
         // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
         const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + kWaves * kBinRecLen;
-        const double r0 = dexp(__fma_rn(K, p[6], __fma_rn(mB, p[7], Eref)), ec);
-        const double r1 = dexp(__fma_rn(K, p2[6], __fma_rn(mB, p2[7], Eref)), ec);
+        const double r0 = dexp(rel_exponent(c.A, c.B, c.Eref, p[6], p[7]), ec);
+        const double r1 = dexp(rel_exponent(c.A, c.B, c.Eref, p2[6], p2[7]), ec);
         A0 = __fma_rn(p[3], r0, A0);
         A1 = __fma_rn(p[4], r0, A1);
         A2 = __fma_rn(p[5], r0, A2);
@@ -727,7 +701,7 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
       }
       if (b < hi) {
         const double *p = BR + (size_t)b * kBinRecLen;
-        const double r0 = dexp(__fma_rn(K, p[6], __fma_rn(mB, p[7], Eref)), ec);
+        const double r0 = dexp(rel_exponent(c.A, c.B, c.Eref, p[6], p[7]), ec);
         A0 = __fma_rn(p[3], r0, A0);
         A1 = __fma_rn(p[4], r0, A1);
         A2 = __fma_rn(p[5], r0, A2);
@@ -766,8 +740,7 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
       int b = lo + ((b0 + wave - lo) & (kWaves - 1));
       if (b >= hi) continue;
       const double *r = BF + (size_t)q * 4;
-      const double Eref = gamma_exponent(rc[0], rc[1], rc[2], rc[3], rc[4], r[0], r[1], r[2]);
-      const double K = rc[0], mB = -rc[1];
+      const RelCell c = rel_cell(kGammaPE, rc, r[0], r[1], r[2]);
       for (; b < hi; b += kWaves) {
         const double *br = BR + (size_t)b * kBinRecLen;
         if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
@@ -776,7 +749,7 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
 #pragma unroll
         for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
           if (q2 < S) Z = __fma_rn(h[q2], rw[q2], Z);
-        const double Gr = Z * dexp(__fma_rn(K, br[6], __fma_rn(mB, br[7], Eref)), ec);
+        const double Gr = Z * dexp(rel_exponent(c.A, c.B, c.Eref, br[6], br[7]), ec);
         A0 += Gr;
         A1 = __fma_rn(Gr, br[1], A1);
         A2 = __fma_rn(Gr, br[0], A2);
