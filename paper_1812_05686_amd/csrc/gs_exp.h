@@ -1,13 +1,18 @@
 // gs_exp.h -- FP64 exponential for the per-pair response evaluation.
 //
 // exp(x) = 2^n p(r), x = n ln2 + r, |r| <= ln2/2 (Cody & Waite argument
-// reduction): ln2 is split into a head with 40 significant bits, so n * head
-// is exact for |n| < 2^13, and a tail.  n is rounded by adding 1.5 * 2^52
-// to x / ln2 in one fused operation: the sum has unit spacing, so it holds
-// the nearest integer n, whose two's complement is its low 32 bits.  p is the degree-11 polynomial that
-// minimises the relative error of exp(r) on [-ln2/2, ln2/2], fitted with
-// the Remez exchange algorithm in 60-digit arithmetic (maximum relative
-// error 3.1e-18 before the coefficients are rounded to double).
+// reduction, with a one-term ln2): n is rounded by adding 1.5 * 2^52 to
+// x / ln2 in one fused operation (the sum has unit spacing, so it holds the
+// nearest integer n, whose two's complement is its low 32 bits), and
+// r = x - n ln2 is formed in one FMA with ln2 rounded to double.  The product
+// is exact inside the FMA; the rounding of ln2 (2.3e-17) shifts r by
+// |n| 2.3e-17, so the relative error grows with |x|: below 6e-16 + |n| 2.4e-17,
+// i.e. 2.6e-15 for the log-densities above -60 that a banded fold keeps and
+// 2.5e-14 at the bottom of the normal range.  Pair exponents never need more:
+// a bin's value is set by its largest pairs.  p is the degree-10 polynomial
+// that minimises the relative error of exp(r) on [-ln2/2, ln2/2], from the
+// Remez exchange algorithm in 80-digit arithmetic (remez_exp.py; 2.1e-16
+// before and 3.1e-16 after its coefficients are rounded to double).
 //
 // Arguments below -1000 are raised to -1000 (the result underflows to 0
 // either way), so far-tail exponents never reach a saturated integer
@@ -28,26 +33,25 @@
 
 namespace gs {
 
-// c[0..11]: polynomial coefficients of r^11 .. r^0 (Horner order);
-// c[12] = 1/ln2, c[13] = ln2 head, c[14] = ln2 tail, c[15] = 1.5 * 2^52.
-#define GS_EXP_COEFS                                                                                 \
-  {                                                                                                  \
-    2.499430488481720730096538e-8, 2.763229327945987537523749e-7, 2.755762253087225465714744e-6,    \
-        2.480148652142746394884348e-5, 1.984126943267923686630193e-4, 1.388888895122398829076301e-3, \
-        8.333333333559271335728342e-3, 4.166666666649276729475066e-2, 1.666666666666616866446141e-1, \
-        5.000000000000017685649359e-1, 1.000000000000000030360381e0, 9.999999999999999971003972e-1,  \
-        1.4426950408889634074, 0.6931471805592082, 7.371002565167799e-13, 6755399441055744.0         \
+// c[0..10]: polynomial coefficients of r^10 .. r^0 (Horner order);
+// c[11] = 1/ln2, c[12] = ln2 (rounded to double), c[13] = 1.5 * 2^52.
+#define GS_EXP_COEFS                                                                             \
+  {                                                                                              \
+    2.748844159545267e-07, 2.763976828264541e-06, 2.4801917693499152e-05, 0.00019841171384145565, \
+        0.0013888888499132617, 0.00833333338466586, 0.04166666666842604, 0.16666666666557742,     \
+        0.49999999999997286, 1.0000000000000064, 1.0, 1.4426950408889634074,                      \
+        0.69314718055994530942, 6755399441055744.0                                                \
   }
+#define GS_EXP_NCOEF 14
 
-// c0 = c[0] and mg = c[15], passed separately so that a caller can hold them
+// c0 = c[0] and mg = c[13], passed separately so that a caller can hold them
 // in vector registers: an instruction may read only one scalar register, and
 // these two meet another scalar operand.
 GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
   x = fmax(x, -1000.0);
-  const double t = fma(x, c[12], mg);
+  const double t = fma(x, c[11], mg);
   const double n = t - mg;
-  double r = fma(-n, c[13], x);
-  r = fma(-n, c[14], r);
+  const double r = fma(-n, c[12], x);
   double p = fma(c0, r, c[1]);
   p = fma(p, r, c[2]);
   p = fma(p, r, c[3]);
@@ -58,10 +62,9 @@ GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
   p = fma(p, r, c[8]);
   p = fma(p, r, c[9]);
   p = fma(p, r, c[10]);
-  p = fma(p, r, c[11]);
   return ldexp(p, (int)(unsigned)__builtin_bit_cast(unsigned long long, t));
 }
 
-GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[15]); }
+GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[13]); }
 
 }  // namespace gs

@@ -29,7 +29,7 @@
 namespace gs {
 
 // Coefficients of exp_cw; read through scalar loads so they live in SGPRs.
-__constant__ double kExpC[16] = GS_EXP_COEFS;
+__constant__ double kExpC[GS_EXP_NCOEF] = GS_EXP_COEFS;
 
 // exp_cw's coefficients as the pair loops use them: the table (scalar
 // registers) plus the two constants that meet another scalar operand, copied
@@ -40,7 +40,7 @@ struct ExpK {
   double c0, mg;
 };
 __device__ __forceinline__ ExpK exp_consts() {
-  ExpK e{kExpC, kExpC[0], kExpC[15]};
+  ExpK e{kExpC, kExpC[0], kExpC[13]};
   asm volatile("" : "+v"(e.c0));
   asm volatile("" : "+v"(e.mg));
   return e;
