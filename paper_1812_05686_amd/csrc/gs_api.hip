@@ -385,6 +385,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     tiles_f += (descs[t].win_hi - descs[t].win_lo + kFoldTile - 1) / kFoldTile;
     tiles_a += (sh.n_cell + kTile - 1) / kTile;
   }
+  long long grad_blocks = 0;
+  for (int t = 0; t < n_toys; t++) grad_blocks += (B->shapes_h[toy_shape[t]].n_cell + kBlock - 1) / kBlock;
+  B->v.grad_cells = grad_blocks >= kGradLargeBlocks ? kGradCellsLarge : kBlock;
   const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
   const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
   long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
@@ -425,7 +428,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
       vpart_off += T.hblocks + T.bin_blocks;
       gam_off += (long long)T.L * T.K;
     }
-    T.cell_blocks = (sh.n_cell + kBlock - 1) / kBlock;
+    T.cell_blocks = (sh.n_cell + v.grad_cells - 1) / v.grad_cells;
     T.cflag_blocks = (sh.n_cell + kCellBlock - 1) / kCellBlock;
     T.cflag_off = cflag_off;
     T.ghull_off = ghull_off;

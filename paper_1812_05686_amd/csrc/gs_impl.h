@@ -12,6 +12,7 @@ constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins p
 constexpr int kFoldTile = 64;   // window bins per per-species fold item (two per lane of each half-wave)
 constexpr int kFoldTile1 = 32;  // window bins per 1-D fold item (two per lane of each quarter-wave)
 constexpr int kABlock = 32;     // window bins per adjoint exponent reference block
+constexpr int kRefBlocks = 16;  // reference blocks whose per-cell exponents the adjoint stages in LDS at once
 constexpr int kStage = 128;     // cell records staged in LDS per batch of the per-species fold
 constexpr int kStage1 = 256;    // cells staged in LDS per batch of the 1-D fold (one per thread)
 constexpr int kGroup = 16;      // grid cells per support hull
@@ -21,6 +22,11 @@ constexpr int kBlock = 256;     // threads per reduction block
 constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed block (2-D models)
 constexpr int kGradLen = GS_MAX_PARAMS;
 constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response flag each)
+// cells per k_cellgrad block: kBlock (one per thread) for small batches, where
+// the grid must fill the GPU, 4 * kBlock for large ones (one reduction per
+// 1024 cells); BatchView::grad_cells holds the choice
+constexpr int kGradCellsLarge = 1024;
+constexpr int kGradLargeBlocks = 16384;  // batches with at least this many kBlock-cell blocks use kGradCellsLarge
 
 // Structure shared by every toy of one shape (spectra, grid, binning).
 // Species are stored in internal order: grid species first, then lines;
@@ -43,7 +49,7 @@ struct ToyDev {
   int shape, D, lo, L, P, K, n_cell, S;
   int two_d;                    // 1: pulse-shape (secondary observable) model
   int fold_chunks, adj_chunks;
-  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: over bin x pulse-shape cells) / cells
+  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: over bin x pulse-shape cells) / cells (k_cellgrad)
   int hblocks;                  // 2-D: k_hseed blocks (kHTile window bins each)
   int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
   long long cell_off;   // rec[(cell_off + i) * kRecLen]
@@ -83,6 +89,7 @@ struct BatchView {
   const int *list1d, *list2d;
   int n1d, n2d;
   int max_cells, max_cell_blocks, max_bin_blocks;
+  int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)
   int max_bin_blocks1, max_bin_blocks2;  // the same over 1-D / 2-D toys
   int max_ls_blocks;  // kBlock blocks over (window bin, species) pairs
   int max_psd_sk;     // largest S x K of a 2-D toy (P, dP are staged in LDS)

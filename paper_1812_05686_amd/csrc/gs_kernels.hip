@@ -673,38 +673,59 @@ hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *activ
 // Wave w of the workgroup takes the bins b0 + w, b0 + w + kWaves, ... of
 // [b0, b1); a gamma cell's exponent is formed per kABlock block about the
 // block's reference point (see block_ref).
+// Reference exponents E(x_r) of a lane's gamma cell for the bin blocks
+// [qa, qb) (at most kRefBlocks), formed once per cell and block: wave w takes
+// the blocks qa + w, qa + w + kWaves, ... and the workgroup shares them
+// through LDS.  Every thread of the workgroup calls this.
+__device__ __forceinline__ void stage_refs(const double *__restrict__ rc, const double *__restrict__ BF, int qa, int qb,
+                                           int wave, double (&sref)[kRefBlocks][kTile]) {
+  const int lane = threadIdx.x & 63;
+  __syncthreads();  // the previous round's rows are no longer read
+  for (int q = qa + wave; q < qb; q += kWaves) {
+    const double *r = BF + (size_t)q * 4;
+    sref[q - qa][lane] = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
+  }
+  __syncthreads();
+}
+
 template <int FAM>
 __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR,
                                          const double *__restrict__ BF, int b0, int b1, int wave, const ExpK &ec,
-                                         double &A0, double &A1, double &A2) {
+                                         double (&sref)[kRefBlocks][kTile], double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
   if (FAM == kGammaPE) {
     // A zero seed (also every bin outside the gamma support, x <= 0, whose
     // offsets are finite) adds exactly zero: no test per bin.
-    for (int q = b0 / kABlock; q * kABlock < b1; q++) {
-      const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
-      int b = lo + ((b0 + wave - lo) & (kWaves - 1));  // first bin of this wave in the block
-      if (b >= hi) continue;
-      const double *r = BF + (size_t)q * 4;
-      const RelCell c = rel_cell(kGammaPE, rc, r[0], r[1], r[2]);
-      for (; b + kWaves < hi; b += 2 * kWaves) {
-        // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
-        const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + kWaves * kBinRecLen;
-        const double r0 = dexp(rel_exponent(c.A, c.B, c.Eref, p[6], p[7]), ec);
-        const double r1 = dexp(rel_exponent(c.A, c.B, c.Eref, p2[6], p2[7]), ec);
-        A0 = __fma_rn(p[3], r0, A0);
-        A1 = __fma_rn(p[4], r0, A1);
-        A2 = __fma_rn(p[5], r0, A2);
-        A0 = __fma_rn(p2[3], r1, A0);
-        A1 = __fma_rn(p2[4], r1, A1);
-        A2 = __fma_rn(p2[5], r1, A2);
-      }
-      if (b < hi) {
-        const double *p = BR + (size_t)b * kBinRecLen;
-        const double r0 = dexp(rel_exponent(c.A, c.B, c.Eref, p[6], p[7]), ec);
-        A0 = __fma_rn(p[3], r0, A0);
-        A1 = __fma_rn(p[4], r0, A1);
-        A2 = __fma_rn(p[5], r0, A2);
+    const int lane = threadIdx.x & 63;
+    const double A = rc[0], B = -rc[1];
+    const int q_end = (b1 + kABlock - 1) / kABlock;
+    for (int qa = b0 / kABlock; qa < q_end; qa += kRefBlocks) {
+      const int qb = min(qa + kRefBlocks, q_end);
+      stage_refs(rc, BF, qa, qb, wave, sref);
+      for (int q = qa; q < qb; q++) {
+        const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
+        int b = lo + ((b0 + wave - lo) & (kWaves - 1));  // first bin of this wave in the block
+        if (b >= hi) continue;
+        const double Eref = sref[q - qa][lane];
+        for (; b + kWaves < hi; b += 2 * kWaves) {
+          // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
+          const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + kWaves * kBinRecLen;
+          const double r0 = dexp(rel_exponent(A, B, Eref, p[6], p[7]), ec);
+          const double r1 = dexp(rel_exponent(A, B, Eref, p2[6], p2[7]), ec);
+          A0 = __fma_rn(p[3], r0, A0);
+          A1 = __fma_rn(p[4], r0, A1);
+          A2 = __fma_rn(p[5], r0, A2);
+          A0 = __fma_rn(p2[3], r1, A0);
+          A1 = __fma_rn(p2[4], r1, A1);
+          A2 = __fma_rn(p2[5], r1, A2);
+        }
+        if (b < hi) {
+          const double *p = BR + (size_t)b * kBinRecLen;
+          const double r0 = dexp(rel_exponent(A, B, Eref, p[6], p[7]), ec);
+          A0 = __fma_rn(p[3], r0, A0);
+          A1 = __fma_rn(p[4], r0, A1);
+          A2 = __fma_rn(p[5], r0, A2);
+        }
       }
     }
     return;
@@ -732,27 +753,33 @@ template <int FAM>
 __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
                                            const double *__restrict__ BR, const double *__restrict__ BF,
                                            const double *__restrict__ HR, int b0, int b1, int wave, const ExpK &ec,
-                                           double &A0, double &A1, double &A2) {
+                                           double (&sref)[kRefBlocks][kTile], double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
   if (FAM == kGammaPE) {
-    for (int q = b0 / kABlock; q * kABlock < b1; q++) {
-      const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
-      int b = lo + ((b0 + wave - lo) & (kWaves - 1));
-      if (b >= hi) continue;
-      const double *r = BF + (size_t)q * 4;
-      const RelCell c = rel_cell(kGammaPE, rc, r[0], r[1], r[2]);
-      for (; b < hi; b += kWaves) {
-        const double *br = BR + (size_t)b * kBinRecLen;
-        if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
-        const double *h = HR + (size_t)b * S;
-        double Z = 0.0;
+    const int lane = threadIdx.x & 63;
+    const double A = rc[0], B = -rc[1];
+    const int q_end = (b1 + kABlock - 1) / kABlock;
+    for (int qa = b0 / kABlock; qa < q_end; qa += kRefBlocks) {
+      const int qb = min(qa + kRefBlocks, q_end);
+      stage_refs(rc, BF, qa, qb, wave, sref);
+      for (int q = qa; q < qb; q++) {
+        const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
+        int b = lo + ((b0 + wave - lo) & (kWaves - 1));
+        if (b >= hi) continue;
+        const double Eref = sref[q - qa][lane];
+        for (; b < hi; b += kWaves) {
+          const double *br = BR + (size_t)b * kBinRecLen;
+          if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
+          const double *h = HR + (size_t)b * S;
+          double Z = 0.0;
 #pragma unroll
-        for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
-          if (q2 < S) Z = __fma_rn(h[q2], rw[q2], Z);
-        const double Gr = Z * dexp(rel_exponent(c.A, c.B, c.Eref, br[6], br[7]), ec);
-        A0 += Gr;
-        A1 = __fma_rn(Gr, br[1], A1);
-        A2 = __fma_rn(Gr, br[0], A2);
+          for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
+            if (q2 < S) Z = __fma_rn(h[q2], rw[q2], Z);
+          const double Gr = Z * dexp(rel_exponent(A, B, Eref, br[6], br[7]), ec);
+          A0 += Gr;
+          A1 = __fma_rn(Gr, br[1], A1);
+          A2 = __fma_rn(Gr, br[0], A2);
+        }
       }
     }
     return;
@@ -783,6 +810,7 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
                                              const uint8_t *__restrict__ active,
                                              double *__restrict__ apart) {
   __shared__ double red[kWaves * kTile * 3];
+  __shared__ double sref[kRefBlocks][kTile];
   const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
@@ -811,9 +839,9 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
   if (!PS) {
     if (Sh.family == kGammaPE)
-      adj_bins<kGammaPE>(rc, BR, BF, b0, b1, wave, ec, A0, A1, A2);
+      adj_bins<kGammaPE>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
     else
-      adj_bins<kGaussE>(rc, BR, BF, b0, b1, wave, ec, A0, A1, A2);
+      adj_bins<kGaussE>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
   } else {
     const double *th = theta + (size_t)it.toy * stride;
     double rw[GS_MAX_SPECIES];
@@ -832,9 +860,9 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
     }
     const double *HR = H + T.win_off * T.S;
     if (Sh.family == kGammaPE)
-      adj_bins_s<kGammaPE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, A0, A1, A2);
+      adj_bins_s<kGammaPE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
     else
-      adj_bins_s<kGaussE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, A0, A1, A2);
+      adj_bins_s<kGaussE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
   }
   red[(wave * 3 + 0) * kTile + lane] = A0;
   red[(wave * 3 + 1) * kTile + lane] = A1;
@@ -867,7 +895,8 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
 __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                   const double *__restrict__ theta, int stride,
                                                   const double *__restrict__ rec, const double *__restrict__ apart,
-                                                  const uint8_t *__restrict__ active, double *__restrict__ gpart) {
+                                                  int grad_cells, const uint8_t *__restrict__ active,
+                                                  double *__restrict__ gpart) {
   __shared__ double part[kBlock / 64][kGradLen];
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
@@ -881,8 +910,9 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
   for (int s = 0; s < GS_MAX_SPECIES; s++) gR[s] = 0.0;
 #pragma unroll
   for (int p = 0; p < 5; p++) gP[p] = 0.0;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < Sh.n_cell) {
+  // grad_cells consecutive cells per block, cells threadIdx.x, + kBlock, ... per thread
+  const int i_end = min(Sh.n_cell, ((int)blockIdx.x + 1) * grad_cells);
+  for (int i = blockIdx.x * grad_cells + threadIdx.x; i < i_end; i += kBlock) {
     double A0 = 0.0, A1 = 0.0, A2 = 0.0;
     for (int c = 0; c < T.adj_chunks; c++) {
       const double *a = apart + T.apart_off + ((long long)c * T.n_cell + i) * 3;
@@ -960,7 +990,7 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
 
 hipError_t launch_cellgrad(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
   hipLaunchKernelGGL(k_cellgrad, dim3(v.max_cell_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
-                     v.stride, v.rec, v.apart, active, v.gpart);
+                     v.stride, v.rec, v.apart, v.grad_cells, active, v.gpart);
   return hipGetLastError();
 }
 
