@@ -62,15 +62,45 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 }
 inline int xcd_grid(int n) { return ((n + 7) >> 3) * 8; }
 
+// Lane l's value of v at lane (l ^ o), through the LDS crossbar; addr = (l ^ o) * 4
+// is formed once per butterfly step and shared by every value reduced in it.
+__device__ __forceinline__ double xor_fetch(double v, int addr) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
 // Deterministic sum over a wavefront (xor butterfly); result valid on every lane.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = lane_id();
+  for (int o = 32; o > 0; o >>= 1) v += xor_fetch(v, (lane ^ o) << 2);
   return v;
+}
+
+// The same for the first n of N values (n wave-uniform): the six butterfly
+// addresses are formed once and shared; the values go one after another, so
+// only one value's partial sums are live at a time.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N], int n) {
+  const int lane = lane_id();
+  int addr[6];
+#pragma unroll
+  for (int k = 0; k < 6; k++) addr[k] = (lane ^ (32 >> k)) << 2;
+#pragma unroll
+  for (int q = 0; q < N; q++)
+    if (q < n) {
+      double x = v[q];
+#pragma unroll
+      for (int k = 0; k < 6; k++) x += xor_fetch(x, addr[k]);
+      v[q] = x;
+    }
 }
 
 // Deterministic sum over a block of kBlock threads; result valid on thread 0.
 __device__ double block_sum(double v, double *lds) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) lds[w] = v;
@@ -892,11 +922,11 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
 }
 
 // ----------------------------------------------------------- k_cellgrad ---
+template <int CPT>
 __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                   const double *__restrict__ theta, int stride,
                                                   const double *__restrict__ rec, const double *__restrict__ apart,
-                                                  int grad_cells, const uint8_t *__restrict__ active,
-                                                  double *__restrict__ gpart) {
+                                                  const uint8_t *__restrict__ active, double *__restrict__ gpart) {
   __shared__ double part[kBlock / 64][kGradLen];
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
@@ -910,9 +940,10 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
   for (int s = 0; s < GS_MAX_SPECIES; s++) gR[s] = 0.0;
 #pragma unroll
   for (int p = 0; p < 5; p++) gP[p] = 0.0;
-  // grad_cells consecutive cells per block, cells threadIdx.x, + kBlock, ... per thread
-  const int i_end = min(Sh.n_cell, ((int)blockIdx.x + 1) * grad_cells);
-  for (int i = blockIdx.x * grad_cells + threadIdx.x; i < i_end; i += kBlock) {
+  // CPT * kBlock consecutive cells per block: cells threadIdx.x, + kBlock, ... per thread
+  for (int c = 0; c < CPT; c++) {
+    const int i = (blockIdx.x * CPT + c) * kBlock + threadIdx.x;
+    if (i >= Sh.n_cell) break;
     double A0 = 0.0, A1 = 0.0, A2 = 0.0;
     for (int c = 0; c < T.adj_chunks; c++) {
       const double *a = apart + T.apart_off + ((long long)c * T.n_cell + i) * 3;
@@ -967,18 +998,16 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
   }
   // every entry summed over the wave, then over the block's waves in a fixed order
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  wave_sum_n(gR, Sh.S);
+  wave_sum_n(gP, nr);
+  if (lane == 0) {
 #pragma unroll
-  for (int s = 0; s < GS_MAX_SPECIES; s++)
-    if (s < Sh.S) {
-      const double v = wave_sum(gR[s]);
-      if (lane == 0) part[wv][s] = v;
-    }
+    for (int s = 0; s < GS_MAX_SPECIES; s++)
+      if (s < Sh.S) part[wv][s] = gR[s];
 #pragma unroll
-  for (int p = 0; p < 5; p++)
-    if (p < nr) {
-      const double v = wave_sum(gP[p]);
-      if (lane == 0) part[wv][Sh.S + p] = v;
-    }
+    for (int p = 0; p < 5; p++)
+      if (p < nr) part[wv][Sh.S + p] = gP[p];
+  }
   __syncthreads();
   const int q = threadIdx.x;
   if (q < Sh.S + nr) {
@@ -989,8 +1018,14 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
 }
 
 hipError_t launch_cellgrad(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_cellgrad, dim3(v.max_cell_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys, v.shapes, theta,
-                     v.stride, v.rec, v.apart, v.grad_cells, active, v.gpart);
+  // one cell per thread keeps the kernel's registers low (no accumulators
+  // carried across cells); four per thread amortise the block reductions
+  if (v.grad_cells == kBlock)
+    hipLaunchKernelGGL(k_cellgrad<1>, dim3(v.max_cell_blocks, v.n_list), dim3(kBlock), 0, st, v.toy_list, v.toys,
+                       v.shapes, theta, v.stride, v.rec, v.apart, active, v.gpart);
+  else
+    hipLaunchKernelGGL(k_cellgrad<kGradCellsLarge / kBlock>, dim3(v.max_cell_blocks, v.n_list), dim3(kBlock), 0, st,
+                       v.toy_list, v.toys, v.shapes, theta, v.stride, v.rec, v.apart, active, v.gpart);
   return hipGetLastError();
 }
 
