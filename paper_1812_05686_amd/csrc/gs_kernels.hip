@@ -338,7 +338,7 @@ __device__ __forceinline__ void fold_groups(const double *__restrict__ R, const 
   }
 }
 
-__global__ __launch_bounds__(256) void k_fold1(const FoldItem *__restrict__ items, int n_items,
+__global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ items, int n_items,
                                                const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ rec, const int2 *__restrict__ ghull,
                                                const uint8_t *__restrict__ active, double *__restrict__ out) {
