@@ -71,36 +71,66 @@ GS_HD inline int bin_above(const double *bins, int n, double x, double bx0, doub
 // only: for k <= 1 the density does not vanish at 0) and the k <= 1 right
 // end in u.  Iterating stops once a step moves x by less than 2% of the
 // standard deviation, far below a bin at these widths.
+//
+// For k > 1 the iterations start from the Wilson-Hilferty approximation: the
+// cube root of x / (k th) is close to normal with mean 1 - 1/(9k) and
+// variance 1/(9k), so the level T lies near z = sqrt(2 (E(mode) - T)) standard
+// deviations of it; half a deviation is added outwards, and a start that
+// still lies inside is moved outwards (doubling its distance from the mode)
+// until E <= T.  From there one or two Newton steps reach the tolerance.
 GS_HD inline bool gamma_support(double k, double th, double C, double T, double x_lo, double &xl, double &xr) {
   const double sd = sqrt(k) * th, tol = 0.02 * sd, ith = 1.0 / th;
-  auto Ex = [&](double x) { return (k - 1.0) * log(x) - x * ith + C; };
+  auto El = [&](double x, double lx) { return (k - 1.0) * lx - x * ith + C; };  // lx = ln x
   xl = -INFINITY;
   if (k > 1.0) {
-    const double xm = (k - 1.0) * th;
-    const double Em = Ex(xm);
+    const double xm = (k - 1.0) * th, lxm = log(xm);
+    const double Em = El(xm, lxm);
     if (!(Em > T)) return false;
-    const double w = sd * sqrt(2.0 * (Em - T)) + sd;
+    const double s3 = 1.0 / (3.0 * sqrt(k)), mu3 = 1.0 - s3 * s3, kt = k * th;
+    const double z = sqrt(2.0 * (Em - T)) + 0.5;
     // right end, in x
-    double x = xm + w;
-    for (int i = 0; i < 80 && Ex(x) > T; i++) x = xm + 2.0 * (x - xm);
+    double y = mu3 + z * s3;
+    double x = fmax(kt * y * y * y, xm + sd), lx = log(x), E = El(x, lx);
+    for (int i = 0; i < 80 && E > T; i++) {
+      x = xm + 2.0 * (x - xm);
+      lx = log(x);
+      E = El(x, lx);
+    }
     for (int i = 0; i < 40; i++) {
-      const double nx = x - (Ex(x) - T) / ((k - 1.0) / x - ith);
+      const double nx = x - (E - T) / ((k - 1.0) / x - ith);
       if (!(nx < x)) break;
       const bool done = x - nx < tol;
       x = nx;
       if (done) break;
+      lx = log(x);
+      E = El(x, lx);
     }
     xr = x;
     // left end, in u, from a point where E <= T that is not below the first bin
     const double floor_x = x_lo > 0.0 ? x_lo : xm * 0x1p-64;
-    if (!(floor_x < xm) || Ex(floor_x) > T) return true;  // the support reaches the lowest bin
-    x = xm - w;
-    if (!(x > floor_x) || Ex(x) > T) x = floor_x;
-    double u = log(x), ex = x;
-    const double um = log(xm);
+    if (!(floor_x < xm)) return true;  // the support reaches the lowest bin
+    const double lf = log(floor_x), Ef = El(floor_x, lf);
+    if (Ef > T) return true;
+    y = mu3 - z * s3;
+    x = y > 0.0 ? fmin(kt * y * y * y, xm - sd) : floor_x;
+    if (x > floor_x) {
+      lx = log(x);
+      E = El(x, lx);
+      for (int i = 0; i < 80 && E > T; i++) {
+        x = xm - 2.0 * (xm - x);
+        if (!(x > floor_x)) break;
+        lx = log(x);
+        E = El(x, lx);
+      }
+    }
+    if (!(x > floor_x) || E > T) {
+      x = floor_x;
+      lx = lf;
+    }
+    double u = lx, ex = x;
     for (int q = 0; q < 40; q++) {
       const double nu = u - ((k - 1.0) * u - ex * ith + C - T) / ((k - 1.0) - ex * ith);
-      if (!(nu > u) || !(nu < um)) break;
+      if (!(nu > u) || !(nu < lxm)) break;
       const double nex = exp(nu);
       const bool done = nex - ex < tol;
       u = nu;
