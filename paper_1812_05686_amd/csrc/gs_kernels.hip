@@ -172,27 +172,6 @@ hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *
 }
 
 // -------------------------------------------------------------- k_fold ----
-// Response of a cell at one bin (record slots as written by cell_record).
-template <int FAM>
-__device__ __forceinline__ double pair_density(const double *__restrict__ p, double x, double Lh, double Ll,
-                                               const ExpK &ec) {
-  if (FAM == kGammaPE) return dexp(gamma_exponent(p[0], p[1], p[2], p[3], p[4], x, Lh, Ll), ec);
-  double z;
-  return dexp(gauss_exponent(p[0], p[1], p[2], x, z), ec);
-}
-
-// Staged record parts of the per-species fold: {K, 1/th hi, lo, C hi, lo, W}
-// for gamma, {m, 1/s, c0, W} for the Gaussian families.
-template <int FAM>
-struct Stage {
-  static constexpr int kParts = FAM == kGammaPE ? 3 : 2;
-  static constexpr int kLen = 2 * kParts;  // doubles per staged record
-};
-
-struct Bin2 {
-  double x0, Lh0, Ll0, x1, Lh1, Ll1;
-};
-
 // ------------------------------------------------------------ 1-D fold ----
 // A workgroup owns kFoldTile1 = 32 window bins and a set of cells.  Each
 // quarter-wave covers the whole tile, two bins per lane (bins j and j + 16 for
@@ -213,6 +192,16 @@ struct Off2 {
 struct TileRef {
   double x, Lh, Ll;  // reference midpoint and its logarithm (hi, lo)
 };
+
+// Reference point of the window bins [first, first + n) of a toy (clipped to
+// the window, at least one bin): the middle bin, or the last one when the
+// middle midpoint is not positive (the gamma density lives on x > 0).
+__device__ __forceinline__ TileRef tile_ref(const ShapeDev &Sh, const ToyDev &T, int first, int n) {
+  const int last = max(min(first + n, T.L) - 1, 0);
+  const double *r = Sh.bins + (size_t)(T.lo + min(first + n / 2, last)) * kBinLen;
+  if (Sh.family == kGammaPE && !(r[0] > 0.0)) r = Sh.bins + (size_t)(T.lo + last) * kBinLen;
+  return {r[0], r[2], r[3]};
+}
 
 __device__ __forceinline__ void fold_pair_ref(const double *__restrict__ p, const Off2 &o, const ExpK &ec, double &a0,
                                               double &a1) {
@@ -361,11 +350,7 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   const int b0 = it.bin0 + (lane & (kHalf - 1)), b1 = b0 + kHalf;
   const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, last)) * kBinLen;
   const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, last)) * kBinLen;
-  // reference point: the tile's middle bin (its last bin when the middle
-  // midpoint is not positive: the gamma density lives on x > 0)
-  const double *br = Sh.bins + (size_t)(T.lo + min(it.bin0 + kHalf, last)) * kBinLen;
-  if (gamma && !(br[0] > 0.0)) br = Sh.bins + (size_t)(T.lo + last) * kBinLen;
-  const TileRef ref{br[0], br[2], br[3]};
+  const TileRef ref = tile_ref(Sh, T, it.bin0, kFoldTile1);
   Off2 o;
   rel_offsets(Sh.family, bp0[0], bp0[2], bp0[3], ref.x, ref.Lh, ref.Ll, o.u0, o.v0);
   rel_offsets(Sh.family, bp1[0], bp1[2], bp1[3], ref.x, ref.Lh, ref.Ll, o.u1, o.v1);
@@ -406,29 +391,26 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
 }
 
 // Per-species fold (plain path and the secondary-observable model): F_js
-// needs one accumulator per species.  Same layout as the 1-D fold (kFoldTile
-// bins, half-waves on alternate cells, two bins per lane, compacted hull
-// groups, LDS-staged batches), with each staged cell also carrying its weight
-// vector over the species: w_si for grid cells, one-hot on its own species for
-// a line cell.
-template <int FAM>
+// needs one accumulator per species.  kFoldTile bins per workgroup, half-waves
+// on alternate cells, two bins per lane (j and j + 32), compacted hull groups
+// and LDS-staged batches as in the 1-D fold, with each staged cell also
+// carrying its weight vector over the species: w_si for grid cells, one-hot on
+// its own species for a line cell.  The pair exponent is tile-relative as in
+// the 1-D fold, with one reference point per half-tile (each half spans the
+// 32 bins the 1-D fold's tiles span): a staged cell is {A lower, B,
+// Eref lower, A upper, Eref upper, 0} (A depends on the reference point for
+// the Gaussian families, B never does).
 __device__ __forceinline__ void folds_batch(const double *srec, const double *swt, int S, int nb, int wave,
-                                            const Bin2 &bn, const ExpK &ec, double (&a0)[GS_MAX_SPECIES],
+                                            const Off2 &o, const ExpK &ec, double (&a0)[GS_MAX_SPECIES],
                                             double (&a1)[GS_MAX_SPECIES]) {
-  constexpr int L = Stage<FAM>::kLen;
   const int h = (threadIdx.x >> 5) & 1;
   const int np = nb >> 1;
   for (int k = wave; k < np; k += kWaves) {
     const int c = 2 * k + h;
-    double p[L];
-#pragma unroll
-    for (int e = 0; e < L; e += 2) {
-      const double2 u = *(const double2 *)(srec + c * L + e);
-      p[e] = u.x;
-      p[e + 1] = u.y;
-    }
-    const double r0 = pair_density<FAM>(p, bn.x0, bn.Lh0, bn.Ll0, ec);
-    const double r1 = pair_density<FAM>(p, bn.x1, bn.Lh1, bn.Ll1, ec);
+    const double2 p0 = *(const double2 *)(srec + 6 * c), p1 = *(const double2 *)(srec + 6 * c + 2);
+    const double2 p2 = *(const double2 *)(srec + 6 * c + 4);
+    const double r0 = dexp(rel_exponent(p0.x, p0.y, p1.x, o.u0, o.v0), ec);
+    const double r1 = dexp(rel_exponent(p1.y, p0.y, p2.x, o.u1, o.v1), ec);
     const double *w = swt + c * GS_MAX_SPECIES;
 #pragma unroll
     for (int q = 0; q < GS_MAX_SPECIES; q += 2) {
@@ -450,55 +432,60 @@ __device__ __forceinline__ double cell_weight(const ShapeDev &Sh, int i, int q) 
 }
 
 // Cells of a staged batch: either the listed groups of grid cells (list !=
-// NULL, clipped to [c_lo, c_hi)) or the cell range [c_lo, c_hi).
+// NULL, clipped to [c_lo, c_hi)) or the cell range [c_lo, c_hi).  Thread t
+// stages cell t % kStage against the reference of half-tile t / kStage.
 template <int FAM>
 __device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
                                             int n_list, int c_lo, int c_hi, double *srec, double *swt, int wave,
-                                            const Bin2 &bn, const ExpK &ec, double (&a0)[GS_MAX_SPECIES],
-                                            double (&a1)[GS_MAX_SPECIES]) {
-  constexpr int P = Stage<FAM>::kParts;
+                                            const TileRef (&ref)[2], const Off2 &o, const ExpK &ec,
+                                            double (&a0)[GS_MAX_SPECIES], double (&a1)[GS_MAX_SPECIES]) {
+  static_assert(2 * kStage == kWaves * 64, "one staged cell and half-tile per thread");
   constexpr int kGPB = kStage / kGroup;
   constexpr int kT = kWaves * 64;
-  const int tid = threadIdx.x, S = Sh.S;
-  auto cell_of = [&](int bi, int cs) {  // cell at slot cs of batch bi, or -1
+  const int tid = threadIdx.x, S = Sh.S, cs = tid % kStage, half = tid / kStage;
+  auto cell_of = [&](int bi, int c) {  // cell at slot c of batch bi, or -1
     if (list) {
-      const int li = bi * kGPB + cs / kGroup;
-      const int cell = li < n_list ? list[li] * kGroup + cs % kGroup : -1;
+      const int li = bi * kGPB + c / kGroup;
+      const int cell = li < n_list ? list[li] * kGroup + c % kGroup : -1;
       return cell >= c_lo && cell < c_hi ? cell : -1;
     }
-    const int cell = c_lo + bi * kStage + cs;
+    const int cell = c_lo + bi * kStage + c;
     return cell < c_hi ? cell : -1;
   };
   const int n_batch = list ? (n_list + kGPB - 1) / kGPB : (c_hi - c_lo + kStage - 1) / kStage;
-  double2 f[2];
+  double2 f[3];
   double wv[kStage * GS_MAX_SPECIES / kT];
   auto fetch = [&](int bi) {
-#pragma unroll
-    for (int u = 0; u < 2; u++) {
-      const int qp = tid + u * kT;
-      const int cell = qp < kStage * P ? cell_of(bi, qp / P) : -1;
-      f[u] = cell >= 0 ? *(const double2 *)(R + (size_t)cell * kRecLen + 2 * (qp % P)) : make_double2(0.0, 0.0);
-    }
+    stage_load<FAM>(R, cell_of(bi, cs), f);
 #pragma unroll
     for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) {
-      const int e = tid + u * kT, cs = e / GS_MAX_SPECIES, q = e % GS_MAX_SPECIES;
-      const int cell = cell_of(bi, cs);
+      const int e = tid + u * kT, c = e / GS_MAX_SPECIES, q = e % GS_MAX_SPECIES;
+      const int cell = cell_of(bi, c);
       wv[u] = cell >= 0 && q < S ? cell_weight(Sh, cell, q) : 0.0;
     }
   };
   if (n_batch > 0) fetch(0);
   for (int bi = 0; bi < n_batch; bi++) {
     const int rem = list ? (n_list - bi * kGPB) * kGroup : c_hi - c_lo - bi * kStage;
-    const int nb = (min(kStage, rem) + 1) & ~1;  // whole cell pairs; pad slots hold zeros
+    const int nb = (min(kStage, rem) + 1) & ~1;  // whole cell pairs; pad slots hold zero cells
     __syncthreads();  // every wave is done with the previous batch
-#pragma unroll
-    for (int u = 0; u < 2; u++)
-      if (tid + u * kT < kStage * P) ((double2 *)srec)[tid + u * kT] = f[u];
+    {
+      // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W}
+      const double rc[6] = {f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, f[2].y};
+      const RelCell q = rel_cell(FAM, rc, ref[half].x, ref[half].Lh, ref[half].Ll);
+      if (half == 0) {
+        ((double2 *)srec)[3 * cs] = make_double2(q.A, q.B);
+        srec[6 * cs + 2] = q.Eref;
+      } else {
+        srec[6 * cs + 3] = q.A;
+        ((double2 *)srec)[3 * cs + 2] = make_double2(q.Eref, 0.0);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) swt[tid + u * kT] = wv[u];
     __syncthreads();
     if (bi + 1 < n_batch) fetch(bi + 1);
-    folds_batch<FAM>(srec, swt, S, nb, wave, bn, ec, a0, a1);
+    folds_batch(srec, swt, S, nb, wave, o, ec, a0, a1);
   }
 }
 
@@ -524,12 +511,16 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   const int b0 = it.bin0 + (lane & 31), b1 = b0 + 32;
   const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
   const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
-  const Bin2 bn{bp0[0], bp0[2], bp0[3], bp1[0], bp1[2], bp1[3]};
+  const TileRef ref[2] = {tile_ref(Sh, T, it.bin0, kFoldTile / 2), tile_ref(Sh, T, it.bin0 + kFoldTile / 2, kFoldTile / 2)};
+  Off2 o;
+  rel_offsets(Sh.family, bp0[0], bp0[2], bp0[3], ref[0].x, ref[0].Lh, ref[0].Ll, o.u0, o.v0);
+  rel_offsets(Sh.family, bp1[0], bp1[2], bp1[3], ref[1].x, ref[1].Lh, ref[1].Ll, o.u1, o.v1);
   const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile, T.L);
   const double *R = rec + T.cell_off * kRecLen;
   const int g_end = min(it.cell1, Sh.n_true);
   const int l_lo = max(it.cell0, Sh.n_true), l_hi = it.cell1;  // line cells: few, all evaluated
   const bool gamma = Sh.family == kGammaPE;
+  const bool z0 = gamma && !(bp0[0] > 0.0), z1 = gamma && !(bp1[0] > 0.0);  // outside the gamma support
   double a0[GS_MAX_SPECIES], a1[GS_MAX_SPECIES];
 #pragma unroll
   for (int q = 0; q < GS_MAX_SPECIES; q++) a0[q] = a1[q] = 0.0;
@@ -537,15 +528,14 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
     const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
                              glist, gcnt);
     if (gamma)
-      folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, bn, ec, a0, a1);
+      folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, ref, o, ec, a0, a1);
     else
-      folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, bn, ec, a0, a1);
+      folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, ref, o, ec, a0, a1);
   }
   if (gamma)
-    folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, bn, ec, a0, a1);
+    folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, ref, o, ec, a0, a1);
   else
-    folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, bn, ec, a0, a1);
-  const bool z0 = gamma && !(bn.x0 > 0.0), z1 = gamma && !(bn.x1 > 0.0);  // outside the gamma support
+    folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, ref, o, ec, a0, a1);
   // the two half-waves cover the same bins: combine them, then the waves in a fixed order
 #pragma unroll
   for (int q = 0; q < GS_MAX_SPECIES; q++) {
