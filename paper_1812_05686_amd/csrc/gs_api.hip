@@ -388,6 +388,11 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   long long grad_blocks = 0;
   for (int t = 0; t < n_toys; t++) grad_blocks += (B->shapes_h[toy_shape[t]].n_cell + kBlock - 1) / kBlock;
   B->v.grad_cells = grad_blocks >= kGradLargeBlocks ? kGradCellsLarge : kBlock;
+  long long bins2_blocks = 0;
+  for (int t = 0; t < n_toys; t++)
+    if (descs[t].n_psd > 0)
+      bins2_blocks += ((long long)(descs[t].win_hi - descs[t].win_lo) * descs[t].n_psd + kBlock - 1) / kBlock;
+  B->v.iter2 = bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1;
   const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
   const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
   long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
@@ -420,8 +425,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
     const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
-    T.bin_blocks = T.two_d ? (int)(((long long)T.L * T.K + kBlock - 1) / kBlock) : (T.L + kBlock - 1) / kBlock;
-    T.hblocks = T.two_d ? (T.L + kHTile - 1) / kHTile : 0;
+    const long long c2 = (long long)kBlock * v.iter2;
+    T.bin_blocks = T.two_d ? (int)(((long long)T.L * T.K + c2 - 1) / c2) : (T.L + kBlock - 1) / kBlock;
+    T.hblocks = T.two_d ? (T.L + kHTile * v.iter2 - 1) / (kHTile * v.iter2) : 0;
     T.vpart_off = vpart_off;
     T.gam_off = gam_off;
     if (T.two_d) {

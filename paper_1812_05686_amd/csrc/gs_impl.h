@@ -19,7 +19,12 @@ constexpr int kGroup = 16;      // grid cells per support hull
 constexpr int kVLen = GS_MAX_SPECIES + 4;  // 2-D gradient partials per block: species, 3 nuisances, pad
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
 constexpr int kBlock = 256;     // threads per reduction block
-constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed block (2-D models)
+constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed round (2-D models)
+// k_bins2 and k_hseed rounds per block (BatchView::iter2): each block stages
+// the toy's pulse-shape table, so large batches give a block kIter2Large
+// rounds (kBlock (bin, pulse-shape bin) cells, or kHTile bins, each) to pay for
+// it; small ones one round, so that one model still fills the GPU
+constexpr int kIter2Large = 8;
 constexpr int kGradLen = GS_MAX_PARAMS;
 constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response flag each)
 // cells per k_cellgrad block: kBlock (one per thread) for small batches, where
@@ -49,7 +54,7 @@ struct ToyDev {
   int shape, D, lo, L, P, K, n_cell, S;
   int two_d;                    // 1: pulse-shape (secondary observable) model
   int fold_chunks, adj_chunks;
-  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: over bin x pulse-shape cells) / cells (k_cellgrad)
+  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: iter2 * kBlock bin x pulse-shape cells each) / cells (k_cellgrad)
   int hblocks;                  // 2-D: k_hseed blocks (kHTile window bins each)
   int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
   long long cell_off;   // rec[(cell_off + i) * kRecLen]
@@ -90,6 +95,7 @@ struct BatchView {
   int n1d, n2d;
   int max_cells, max_cell_blocks, max_bin_blocks;
   int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)
+  int iter2;       // rounds per k_bins2 / k_hseed block (1 or kIter2Large)
   int max_bin_blocks1, max_bin_blocks2;  // the same over 1-D / 2-D toys
   int max_ls_blocks;  // kBlock blocks over (window bin, species) pairs
   int max_psd_sk;     // largest S x K of a 2-D toy (P, dP are staged in LDS)

@@ -1296,7 +1296,8 @@ hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *ac
   return hipGetLastError();
 }
 
-// 2-D likelihood, one thread per (window bin j, pulse-shape bin k) of a toy:
+// 2-D likelihood over the (window bin j, pulse-shape bin k) cells of a toy,
+// iter2 * kBlock per block, cells threadIdx.x, + kBlock, ... per thread:
 // mu_djk = eps_d sum_s R_s F_js P_sk, the Poisson terms (block partial of
 // -ln L), Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), and the block partial of
 // the nuisance-gradient pieces that need no fold,
@@ -1307,9 +1308,10 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ F, const double *__restrict__ P,
                                                const double *__restrict__ dP, const double *__restrict__ cnt,
-                                               const uint8_t *__restrict__ active, double *__restrict__ Gam,
-                                               double *__restrict__ nllp, uint32_t *__restrict__ badp,
-                                               double *__restrict__ vpart, double *__restrict__ mu_out) {
+                                               int iter2, const uint8_t *__restrict__ active,
+                                               double *__restrict__ Gam, double *__restrict__ nllp,
+                                               uint32_t *__restrict__ badp, double *__restrict__ vpart,
+                                               double *__restrict__ mu_out) {
   extern __shared__ double pd[];  // [S][K][4]: P_sk, dP_sk/d(delta, kappa, eta)
   __shared__ double ared[kWaves][3];
   __shared__ double lds[8];
@@ -1331,18 +1333,19 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
   }
   __syncthreads();
   const double *th = theta + (size_t)t * stride;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = e < (long long)T.L * K;
-  const int b = valid ? (int)(e / K) : 0, k = valid ? (int)(e - (long long)b * K) : 0;
   double sum = 0.0, A0 = 0.0, A1 = 0.0, A2 = 0.0;
   bool bad = false;
-  if (valid) {
+  const long long n_e = (long long)T.L * K;
+  for (int c = 0; c < iter2; c++) {
+    const long long e = ((long long)blockIdx.x * iter2 + c) * kBlock + threadIdx.x;
+    if (e >= n_e) break;
+    const int b = (int)(e / K), k = (int)(e - (long long)b * K);
     const double *Fr = F + (T.win_off + b) * S;
     double M = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
     for (int q = 0; q < S; q++) {
       const double rf = th[Sh.sp_of[q]] * Fr[q];
-      const double *c = pd + ((size_t)q * K + k) * 4;
-      const double2 u = *(const double2 *)c, w = *(const double2 *)(c + 2);
+      const double *cq = pd + ((size_t)q * K + k) * 4;
+      const double2 u = *(const double2 *)cq, w = *(const double2 *)(cq + 2);
       M = __fma_rn(rf, u.x, M);
       D0 = __fma_rn(rf, u.y, D0);
       D1 = __fma_rn(rf, w.x, D1);
@@ -1359,9 +1362,9 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
       if (mu_out) mu_out[((long long)d * T.L + b) * K + k] = mu;
     }
     Gam[T.gam_off + (long long)b * K + k] = gam;
-    A0 = D0 * gam;
-    A1 = D1 * gam;
-    A2 = D2 * gam;
+    A0 = __fma_rn(D0, gam, A0);
+    A1 = __fma_rn(D1, gam, A1);
+    A2 = __fma_rn(D2, gam, A2);
   }
   A0 = wave_sum(A0);
   A1 = wave_sum(A1);
@@ -1382,14 +1385,14 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
 }
 
 // 2-D adjoint seeds, one thread per (window bin j, species slot s) of a toy,
-// kHTile bins per block: h_js = sum_k P_sk Gam_jk, H_js = dx_j h_js, the bin
+// iter2 rounds of kHTile bins per block: h_js = sum_k P_sk Gam_jk, H_js = dx_j h_js, the bin
 // record, and the block partial of the rate-gradient piece sum_j F_js h_js.
 __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
                                                const ShapeDev *__restrict__ shapes, const double *__restrict__ F,
                                                const double *__restrict__ P, const double *__restrict__ Gam,
-                                               const uint8_t *__restrict__ active, double *__restrict__ binrec,
-                                               double *__restrict__ bref, double *__restrict__ H,
-                                               double *__restrict__ vpart) {
+                                               int iter2, const uint8_t *__restrict__ active,
+                                               double *__restrict__ binrec, double *__restrict__ bref,
+                                               double *__restrict__ H, double *__restrict__ vpart) {
   extern __shared__ double ps[];  // [S][K]
   __shared__ double red[kHTile][GS_MAX_SPECIES];
   const int t = toy_of(toy_list, blockIdx.y);
@@ -1401,10 +1404,10 @@ __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list,
   for (int e = threadIdx.x; e < S * K; e += blockDim.x) ps[e] = P[T.psd_off + e];
   __syncthreads();
   const int jj = threadIdx.x / GS_MAX_SPECIES, q = threadIdx.x % GS_MAX_SPECIES;
-  const int b = blockIdx.x * kHTile + jj;
-  const bool valid = b < T.L && q < S;
   double a = 0.0;
-  if (valid) {
+  for (int c = 0; c < iter2; c++) {
+    const int b = (blockIdx.x * iter2 + c) * kHTile + jj;
+    if (!(b < T.L && q < S)) continue;
     const double *g = Gam + T.gam_off + (long long)b * K;
     const double *pq = ps + (size_t)q * K;
     double h = 0.0;
@@ -1412,7 +1415,7 @@ __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list,
     const double *bn = Sh.bins + (size_t)(T.lo + b) * kBinLen;
     const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
     H[(T.win_off + b) * S + q] = outside ? 0.0 : bn[1] * h;
-    a = F[(T.win_off + b) * S + q] * h;
+    a = __fma_rn(F[(T.win_off + b) * S + q], h, a);
     if (q == 0) {
       double *br = binrec + (T.win_off + b) * kBinRecLen;
       br[0] = bn[0];
@@ -1437,12 +1440,12 @@ hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out,
                         hipStream_t st) {
   if (v.n2d == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), sizeof(double) * 4 * v.max_psd_sk, st,
-                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, active, v.Gam, v.nllp,
+                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, v.iter2, active, v.Gam, v.nllp,
                      v.badp, v.vpart, mu_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hseed, dim3(v.max_hblocks, v.n2d), dim3(kHTile * GS_MAX_SPECIES),
-                     sizeof(double) * v.max_psd_sk, st, v.list2d, v.toys, v.shapes, v.F, v.P, v.Gam, active,
+                     sizeof(double) * v.max_psd_sk, st, v.list2d, v.toys, v.shapes, v.F, v.P, v.Gam, v.iter2, active,
                      v.binrec, v.bref, v.H, v.vpart);
   return hipGetLastError();
 }
