@@ -196,6 +196,9 @@ def main():
     nll = torch.empty(len(toys), dtype=torch.float64, device="cuda")
     grad = torch.empty(len(toys), stride, dtype=torch.float64, device="cuda")
     st = torch.empty(len(toys), dtype=torch.int32, device="cuda")
+    # the batch scheduler's autotuner picks the work layout the timed steps use
+    tune = batch.autotune(theta, reps=3)
+    log(f"bench: autotune {tune}")
     for _ in range(args.warmup):
         batch.nll_grad(theta, nll, grad, st)
     torch.cuda.synchronize()
@@ -342,7 +345,7 @@ def main():
                                   "200-900-bin windows; one batched -lnL+gradient per step",
                       "toys": len(toys), "mean_window_bins": round(float(np.mean([t.win_hi - t.win_lo for t in toys])), 1),
                       "full_mesh_pairs_per_step": pairs},
-           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "toy_fits": toy_fits,
+           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "autotune": tune, "toy_fits": toy_fits,
            "single_eval": {"us_per_eval": round(single_us, 2), "evals_per_s": round(1e6 / single_us, 1)},
            "single_fit_borexino_scale": fits, "two_d_model": two_d, "mixed_batch": mixed}
     print(json.dumps(out))

@@ -49,7 +49,8 @@ EXPORTS = ["gs_last_error", "gs_desc_validate", "gs_model_create", "gs_model_des
            "gs_nll", "gs_nll_grad", "gs_expected", "gs_fit", "gs_batch_create", "gs_batch_destroy",
            "gs_batch_num_toys", "gs_batch_param_stride", "gs_nll_grad_batched", "gs_fit_batched",
            "gs_batch_set_profiling", "gs_batch_kernel_times", "gs_batch_set_log_cut", "gs_model_set_log_cut",
-           "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs", "gs_batch_fit_trace"]
+           "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs", "gs_batch_fit_trace",
+           "gs_batch_set_layout", "gs_batch_autotune", "gs_batch_layout"]
 KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish"]
 
 _lib = None
@@ -117,6 +118,12 @@ def lib():
         L.gs_batch_fit_trace.restype = C.c_int
         L.gs_batch_fit_trace.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                          C.POINTER(C.c_int32)]
+        L.gs_batch_set_layout.restype = C.c_int
+        L.gs_batch_set_layout.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.gs_batch_autotune.restype = C.c_int
+        L.gs_batch_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, _dp]
+        L.gs_batch_layout.restype = C.c_int
+        L.gs_batch_layout.argtypes = [vp, C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -291,6 +298,31 @@ class Batch:
 
     def set_log_cut(self, log_cut: float):
         _check(lib().gs_batch_set_log_cut(self.h, float(log_cut)), "gs_batch_set_log_cut")
+
+    def layout(self):
+        """The work layout in force: {target_wg, grad_cells, iter2, candidates}."""
+        out = (C.c_int32 * 4)()
+        _check(lib().gs_batch_layout(self.h, out), "gs_batch_layout")
+        return dict(target_wg=int(out[0]), grad_cells=int(out[1]), iter2=int(out[2]), candidates=int(out[3]))
+
+    def set_layout(self, target_wg: int, grad_cells: int, iter2: int):
+        _check(lib().gs_batch_set_layout(self.h, int(target_wg), int(grad_cells), int(iter2)), "gs_batch_set_layout")
+
+    def autotune(self, theta, reps: int = 3):
+        """Times the batched evaluation at theta under every candidate layout and keeps the
+        fastest; returns {target_wg, grad_cells, iter2, ms_per_eval}."""
+        import torch
+        assert theta.dtype == torch.float64 and theta.is_cuda and theta.is_contiguous()
+        assert tuple(theta.shape) == (self.n, self.stride)
+        dev = theta.device
+        nll = torch.empty(self.n, dtype=torch.float64, device=dev)
+        grad = torch.empty(self.n, self.stride, dtype=torch.float64, device=dev)
+        status = torch.empty(self.n, dtype=torch.int32, device=dev)
+        ch = np.zeros(4)
+        _check(lib().gs_batch_autotune(self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(nll.data_ptr()),
+                                       C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()), int(reps),
+                                       self._stream(), _ptr(ch)), "gs_batch_autotune")
+        return dict(target_wg=int(ch[0]), grad_cells=int(ch[1]), iter2=int(ch[2]), ms_per_eval=float(ch[3]))
 
     def mesh_pairs(self):
         """(fold pairs, adjoint pairs, full-mesh pairs, banded-mesh pairs) of the most recent

@@ -141,6 +141,18 @@ struct DevBuf {
 
 }  // namespace
 
+// Layout knobs of a batch: the split-K target (work-groups the fold and the
+// adjoint aim for when the batch alone is smaller), cells per k_cellgrad block,
+// and rounds per k_bins2 / k_hseed block.
+struct Knobs {
+  int target_wg, grad_cells, iter2;
+};
+// Work-buffer sizes (elements) and item counts a layout needs.
+struct LayoutSizes {
+  long long fpart, fspart, apart, nllp, gpart, vpart;
+  size_t n_fold, n_adj;
+};
+
 struct gs_batch {
   int device = 0;
   int n_toys = 0, stride = 0;
@@ -149,6 +161,14 @@ struct gs_batch {
   std::vector<FoldItem> fold_h;   // per-species fold items, every toy
   std::vector<FoldItem> fold1_h;  // 1-D fold items, 1-D toys
   std::vector<AdjItem> adj_h;
+  // layout knobs in force, the candidates the autotuner tries, and the
+  // capacities (largest candidate) the work buffers and item arrays hold
+  Knobs knobs{};
+  std::vector<Knobs> candidates;
+  LayoutSizes cap{};
+  FoldItem *d_fold_items = nullptr;
+  AdjItem *d_adj_items = nullptr;
+  ToyDev *d_toys = nullptr;
   std::vector<void *> allocs;
   BatchView v{};
   bool has_2d = false;
@@ -271,6 +291,107 @@ static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, cons
   return GS_OK;
 }
 
+// The layout knobs the autotuner tries: split-K targets, one or four cells per
+// k_cellgrad thread, one or kIter2Large rounds per 2-D block (2-D batches).
+static std::vector<Knobs> layout_candidates(const gs_batch *B) {
+  std::vector<Knobs> c;
+  for (int wg : {1024, 2048, 4096, 8192})
+    for (int gc : {kBlock, kGradCellsLarge})
+      for (int it : {1, kIter2Large}) {
+        if (it != 1 && !B->v.has_2d) continue;
+        c.push_back({wg, gc, it});
+      }
+  return c;
+}
+
+// The default layout: a split-K target of kTargetWG work-groups, four cells per
+// k_cellgrad thread and kIter2Large 2-D rounds once the batch gives at least
+// kGradLargeBlocks blocks of kBlock cells (so one model still fills the GPU).
+static Knobs default_knobs(const gs_batch *B) {
+  long long grad_blocks = 0, bins2_blocks = 0;
+  for (const ToyDev &T : B->toys_h) {
+    grad_blocks += (T.n_cell + kBlock - 1) / kBlock;
+    if (T.two_d) bins2_blocks += ((long long)T.L * T.K + kBlock - 1) / kBlock;
+  }
+  return {kTargetWG, grad_blocks >= kGradLargeBlocks ? kGradCellsLarge : kBlock,
+          bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1};
+}
+
+static void grow(LayoutSizes &a, const LayoutSizes &b) {
+  a.fpart = std::max(a.fpart, b.fpart);
+  a.fspart = std::max(a.fspart, b.fspart);
+  a.apart = std::max(a.apart, b.apart);
+  a.nllp = std::max(a.nllp, b.nllp);
+  a.gpart = std::max(a.gpart, b.gpart);
+  a.vpart = std::max(a.vpart, b.vpart);
+  a.n_fold = std::max(a.n_fold, b.n_fold);
+  a.n_adj = std::max(a.n_adj, b.n_adj);
+}
+
+// Lays the batch out for knobs k on the host: every toy's chunk and block
+// counts and partial-buffer offsets, the work items, and the view's largest
+// grid sizes.  Returns the buffer sizes and item counts this layout needs.
+static LayoutSizes layout(gs_batch *B, const Knobs &k) {
+  BatchView &v = B->v;
+  long long tiles_f = 0, tiles_a = 0;
+  for (const ToyDev &T : B->toys_h) {
+    tiles_f += (T.L + kFoldTile - 1) / kFoldTile;
+    tiles_a += (T.n_cell + kTile - 1) / kTile;
+  }
+  const int nch_f = (int)std::max<long long>(1, (k.target_wg + tiles_f - 1) / tiles_f);
+  const int nch_a = (int)std::max<long long>(1, (k.target_wg + tiles_a - 1) / tiles_a);
+  v.grad_cells = k.grad_cells;
+  v.iter2 = k.iter2;
+  v.max_cell_blocks = v.max_bin_blocks = v.max_bin_blocks1 = v.max_bin_blocks2 = v.max_hblocks = 0;
+  B->fold_h.clear();
+  B->fold1_h.clear();
+  B->adj_h.clear();
+  LayoutSizes z{};
+  for (int t = 0; t < (int)B->toys_h.size(); t++) {
+    ToyDev &T = B->toys_h[t];
+    const ShapeDev &sh = B->shapes_h[T.shape];
+    // chunk sizes: at least 128 cells (a multiple of the hull group) / 64 bins per chunk
+    const int cpc = std::max(128, ((sh.n_cell + nch_f - 1) / nch_f + kGroup - 1) / kGroup * kGroup);
+    T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
+    const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
+    T.adj_chunks = (T.L + bpc - 1) / bpc;
+    const long long c2 = (long long)kBlock * k.iter2;
+    T.bin_blocks = T.two_d ? (int)(((long long)T.L * T.K + c2 - 1) / c2) : (T.L + kBlock - 1) / kBlock;
+    T.hblocks = T.two_d ? (T.L + kHTile * k.iter2 - 1) / (kHTile * k.iter2) : 0;
+    T.cell_blocks = (sh.n_cell + k.grad_cells - 1) / k.grad_cells;
+    T.vpart_off = z.vpart;
+    T.fpart_off = z.fpart;
+    T.fs_off = z.fspart;
+    T.apart_off = z.apart;
+    T.nllp_off = z.nllp;
+    T.gpart_off = z.gpart;
+    for (int b0 = 0; b0 < T.L; b0 += kFoldTile)
+      for (int c = 0; c < T.fold_chunks; c++)
+        B->fold_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
+    if (!T.two_d)
+      for (int b0 = 0; b0 < T.L; b0 += kFoldTile1)
+        for (int c = 0; c < T.fold_chunks; c++)
+          B->fold1_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
+    for (int c0 = 0; c0 < sh.n_cell; c0 += kTile)
+      for (int c = 0; c < T.adj_chunks; c++)
+        B->adj_h.push_back({t, c0, c * bpc, std::min(T.L, (c + 1) * bpc), c});
+    if (T.two_d) z.vpart += T.hblocks + T.bin_blocks;
+    z.fpart += (long long)T.fold_chunks * T.L;
+    z.fspart += (long long)T.fold_chunks * T.L * T.S;
+    z.apart += (long long)T.adj_chunks * sh.n_cell * 3;
+    z.nllp += T.bin_blocks;
+    z.gpart += T.cell_blocks;
+    v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
+    v.max_bin_blocks = std::max(v.max_bin_blocks, T.bin_blocks);
+    (T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1) =
+        std::max(T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1, T.bin_blocks);
+    v.max_hblocks = std::max(v.max_hblocks, T.hblocks);
+  }
+  z.n_fold = B->fold_h.size() + B->fold1_h.size();
+  z.n_adj = B->adj_h.size();
+  return z;
+}
+
 gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_batch **out) {
   if (!descs || n_toys < 1) return fail(GS_ERR_ARG, "need at least one descriptor");
   std::vector<int> P(n_toys);
@@ -378,25 +499,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     B->shapes_h.push_back(sh);
   }
 
-  // ---- toys, offsets, work items ----
-  long long tiles_f = 0, tiles_a = 0;
-  for (int t = 0; t < n_toys; t++) {
-    const ShapeDev &sh = B->shapes_h[toy_shape[t]];
-    tiles_f += (descs[t].win_hi - descs[t].win_lo + kFoldTile - 1) / kFoldTile;
-    tiles_a += (sh.n_cell + kTile - 1) / kTile;
-  }
-  long long grad_blocks = 0;
-  for (int t = 0; t < n_toys; t++) grad_blocks += (B->shapes_h[toy_shape[t]].n_cell + kBlock - 1) / kBlock;
-  B->v.grad_cells = grad_blocks >= kGradLargeBlocks ? kGradCellsLarge : kBlock;
-  long long bins2_blocks = 0;
-  for (int t = 0; t < n_toys; t++)
-    if (descs[t].n_psd > 0)
-      bins2_blocks += ((long long)(descs[t].win_hi - descs[t].win_lo) * descs[t].n_psd + kBlock - 1) / kBlock;
-  B->v.iter2 = bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1;
-  const int nch_f = (int)std::max<long long>(1, (kTargetWG + tiles_f - 1) / tiles_f);
-  const int nch_a = (int)std::max<long long>(1, (kTargetWG + tiles_a - 1) / tiles_a);
-  long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0, fpart_off = 0, apart_off = 0, fs_off = 0;
-  long long nllp_off = 0, gpart_off = 0, cflag_off = 0, vpart_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0;
+  // ---- toys: the fields and offsets that do not depend on the layout knobs ----
+  long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0;
+  long long cflag_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0;
   std::vector<double> cnt_h, pc_h, ps_h;
   BatchView &v = B->v;
   for (int t = 0; t < n_toys; t++) {
@@ -420,21 +525,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.n_cell = sh.n_cell;
     T.S = sh.S;
     for (int k = 0; k < T.D; k++) T.exposure[k] = d.exposure[k];
-    // chunk sizes: at least 128 cells (a multiple of the hull group) / 64 bins per chunk
-    const int cpc = std::max(128, ((sh.n_cell + nch_f - 1) / nch_f + kGroup - 1) / kGroup * kGroup);
-    T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
-    const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
-    T.adj_chunks = (T.L + bpc - 1) / bpc;
-    const long long c2 = (long long)kBlock * v.iter2;
-    T.bin_blocks = T.two_d ? (int)(((long long)T.L * T.K + c2 - 1) / c2) : (T.L + kBlock - 1) / kBlock;
-    T.hblocks = T.two_d ? (T.L + kHTile * v.iter2 - 1) / (kHTile * v.iter2) : 0;
-    T.vpart_off = vpart_off;
     T.gam_off = gam_off;
-    if (T.two_d) {
-      vpart_off += T.hblocks + T.bin_blocks;
-      gam_off += (long long)T.L * T.K;
-    }
-    T.cell_blocks = (sh.n_cell + v.grad_cells - 1) / v.grad_cells;
+    if (T.two_d) gam_off += (long long)T.L * T.K;
     T.cflag_blocks = (sh.n_cell + kCellBlock - 1) / kCellBlock;
     T.cflag_off = cflag_off;
     T.ghull_off = ghull_off;
@@ -442,22 +534,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.win_off = win_off;
     T.bref_off = bref_off;
     T.cnt_off = cnt_off;
-    T.fpart_off = fpart_off;
-    T.fs_off = fs_off;
-    T.apart_off = apart_off;
-    T.nllp_off = nllp_off;
-    T.gpart_off = gpart_off;
     T.pull_off = pull_off;
-    for (int b0 = 0; b0 < T.L; b0 += kFoldTile)
-      for (int c = 0; c < T.fold_chunks; c++)
-        B->fold_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
-    if (!T.two_d)
-      for (int b0 = 0; b0 < T.L; b0 += kFoldTile1)
-        for (int c = 0; c < T.fold_chunks; c++)
-          B->fold1_h.push_back({t, b0, c * cpc, std::min(sh.n_cell, (c + 1) * cpc), c});
-    for (int c0 = 0; c0 < sh.n_cell; c0 += kTile)
-      for (int c = 0; c < T.adj_chunks; c++)
-        B->adj_h.push_back({t, c0, c * bpc, std::min(T.L, (c + 1) * bpc), c});
     for (int k = 0; k < T.D; k++)
       for (int j = d.win_lo; j < d.win_hi; j++)
         for (int q = 0; q < T.K; q++) cnt_h.push_back(d.counts[((size_t)k * d.n_reco + j) * T.K + q]);
@@ -470,25 +547,22 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     win_off += T.L;
     bref_off += (T.L + kABlock - 1) / kABlock;
     cnt_off += (long long)T.D * T.L * T.K;
-    fpart_off += (long long)T.fold_chunks * T.L;
-    fs_off += (long long)T.fold_chunks * T.L * T.S;
-    apart_off += (long long)T.adj_chunks * sh.n_cell * 3;
-    nllp_off += T.bin_blocks;
-    gpart_off += T.cell_blocks;
     cflag_off += T.cflag_blocks;
     ghull_off += (sh.n_true + kGroup - 1) / kGroup;
     pull_off += T.P;
     v.max_cells = std::max(v.max_cells, sh.n_cell);
-    v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
     v.max_cflag_blocks = std::max(v.max_cflag_blocks, T.cflag_blocks);
-    v.max_bin_blocks = std::max(v.max_bin_blocks, T.bin_blocks);
-    (T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1) =
-        std::max(T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1, T.bin_blocks);
     v.max_ls_blocks = std::max(v.max_ls_blocks, (int)(((long long)T.L * T.S + kBlock - 1) / kBlock));
     if (T.two_d) v.max_psd_sk = std::max(v.max_psd_sk, T.S * T.K);
-    v.max_hblocks = std::max(v.max_hblocks, T.hblocks);
     B->toys_h.push_back(T);
   }
+  // ---- layout: the work buffers hold the largest candidate layout; the default is in force ----
+  B->candidates = layout_candidates(B);
+  B->knobs = default_knobs(B);
+  LayoutSizes cap{};
+  for (const Knobs &k : B->candidates) grow(cap, layout(B, k));
+  grow(cap, layout(B, B->knobs));
+  B->cap = cap;
   v.n_toys = n_toys;
   v.toy_list = nullptr;
   v.n_list = n_toys;
@@ -504,8 +578,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   double *cnt, *pc, *ps;
   HIP_TRY(B->alloc(&shd, B->shapes_h.size()));
   HIP_TRY(B->alloc(&tod, B->toys_h.size()));
-  HIP_TRY(B->alloc(&fi, B->fold_h.size() + B->fold1_h.size()));
-  HIP_TRY(B->alloc(&ai, B->adj_h.size()));
+  HIP_TRY(B->alloc(&fi, cap.n_fold));
+  HIP_TRY(B->alloc(&ai, cap.n_adj));
   HIP_TRY(B->alloc(&cnt, cnt_h.size()));
   HIP_TRY(B->alloc(&pc, pc_h.size()));
   HIP_TRY(B->alloc(&ps, ps_h.size()));
@@ -518,20 +592,23 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     HIP_TRY(B->alloc(&v.H, (size_t)win_off * GS_MAX_SPECIES));
     HIP_TRY(B->alloc(&v.P, (size_t)psd_off));
     HIP_TRY(B->alloc(&v.dP, (size_t)psd_off * 3));
-    HIP_TRY(B->alloc(&v.vpart, (size_t)vpart_off * kVLen));
+    HIP_TRY(B->alloc(&v.vpart, (size_t)cap.vpart * kVLen));
     HIP_TRY(B->alloc(&v.Gam, (size_t)gam_off));
   }
-  HIP_TRY(B->alloc(&v.fpart, (size_t)fpart_off));
-  HIP_TRY(B->alloc(&v.fspart, (size_t)fs_off));
+  HIP_TRY(B->alloc(&v.fpart, (size_t)cap.fpart));
+  HIP_TRY(B->alloc(&v.fspart, (size_t)cap.fspart));
   HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
-  HIP_TRY(B->alloc(&v.apart, (size_t)apart_off));
+  HIP_TRY(B->alloc(&v.apart, (size_t)cap.apart));
   HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinRecLen));
   HIP_TRY(B->alloc(&v.bref, (size_t)bref_off * 4));
-  HIP_TRY(B->alloc(&v.nllp, (size_t)nllp_off));
-  HIP_TRY(B->alloc(&v.badp, (size_t)nllp_off));
-  HIP_TRY(B->alloc(&v.gpart, (size_t)gpart_off * kGradLen));
+  HIP_TRY(B->alloc(&v.nllp, (size_t)cap.nllp));
+  HIP_TRY(B->alloc(&v.badp, (size_t)cap.nllp));
+  HIP_TRY(B->alloc(&v.gpart, (size_t)cap.gpart * kGradLen));
   HIP_TRY(hipMemcpy(shd, B->shapes_h.data(), B->shapes_h.size() * sizeof(ShapeDev), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(tod, B->toys_h.data(), B->toys_h.size() * sizeof(ToyDev), hipMemcpyHostToDevice));
+  B->d_toys = tod;
+  B->d_fold_items = fi;
+  B->d_adj_items = ai;
   {
     gs_status us = upload_items(B, B->fold_h, B->fold1_h, B->adj_h, fi, ai, v, nullptr);
     if (us != GS_OK) return us;
@@ -627,6 +704,86 @@ gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll,
   if (!b || !d_theta || !d_nll || !d_status) return fail(GS_ERR_ARG, "null argument");
   HIP_TRY(hipSetDevice(b->device));
   return enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, (hipStream_t)hip_stream);
+}
+
+// Puts layout k in force: host layout, then the toys and work items uploaded
+// (synchronously); a captured fit graph, which holds the old layout, is dropped.
+static gs_status apply_layout(gs_batch *B, const Knobs &k) {
+  const LayoutSizes z = layout(B, k);
+  if (z.fpart > B->cap.fpart || z.fspart > B->cap.fspart || z.apart > B->cap.apart || z.nllp > B->cap.nllp ||
+      z.gpart > B->cap.gpart || z.vpart > B->cap.vpart || z.n_fold > B->cap.n_fold || z.n_adj > B->cap.n_adj)
+    return fail(GS_ERR_ARG, "layout exceeds the batch's work buffers");
+  HIP_TRY(hipMemcpy(B->d_toys, B->toys_h.data(), B->toys_h.size() * sizeof(ToyDev), hipMemcpyHostToDevice));
+  gs_status us = upload_items(B, B->fold_h, B->fold1_h, B->adj_h, B->d_fold_items, B->d_adj_items, B->v, nullptr);
+  if (us != GS_OK) return us;
+  B->knobs = k;
+  if (B->graph) {
+    HIP_TRY(hipGraphExecDestroy(B->graph));
+    B->graph = nullptr;
+  }
+  return GS_OK;
+}
+
+gs_status gs_batch_set_layout(gs_batch *b, int32_t target_wg, int32_t grad_cells, int32_t iter2) {
+  if (!b) return fail(GS_ERR_ARG, "null batch");
+  HIP_TRY(hipSetDevice(b->device));
+  for (const Knobs &k : b->candidates)
+    if (k.target_wg == target_wg && k.grad_cells == grad_cells && k.iter2 == iter2) {
+      HIP_TRY(hipDeviceSynchronize());  // no evaluation of the old layout may still run
+      return apply_layout(b, k);
+    }
+  return fail(GS_ERR_ARG, "layout (%d, %d, %d) is not one of the batch's candidates", target_wg, grad_cells, iter2);
+}
+
+gs_status gs_batch_autotune(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
+                            int32_t reps, void *hip_stream, double *choice) {
+  if (!b || !d_theta || !d_nll || !d_status || reps < 1) return fail(GS_ERR_ARG, "bad argument");
+  HIP_TRY(hipSetDevice(b->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipDeviceSynchronize());
+  hipEvent_t e0 = b->event(), e1 = b->event();
+  Knobs best = b->knobs;
+  double best_ms = INFINITY;
+  gs_status s = GS_OK;
+  for (const Knobs &k : b->candidates) {
+    s = apply_layout(b, k);
+    if (s == GS_OK) s = enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, st);  // warm-up
+    if (s != GS_OK) break;
+    hipError_t e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && s == GS_OK && e == hipSuccess; r++)
+      s = enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) s = fail(GS_ERR_DEVICE, "autotune timing: %s", hipGetErrorString(e));
+    if (s != GS_OK) break;
+    if (ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best = k;
+    }
+  }
+  b->ev_free.push_back(e0);
+  b->ev_free.push_back(e1);
+  if (s != GS_OK) return s;
+  s = apply_layout(b, best);
+  if (s != GS_OK) return s;
+  if (choice) {
+    choice[0] = best.target_wg;
+    choice[1] = best.grad_cells;
+    choice[2] = best.iter2;
+    choice[3] = best_ms;
+  }
+  return GS_OK;
+}
+
+gs_status gs_batch_layout(const gs_batch *b, int32_t *out) {
+  if (!b || !out) return fail(GS_ERR_ARG, "null argument");
+  out[0] = b->knobs.target_wg;
+  out[1] = b->knobs.grad_cells;
+  out[2] = b->knobs.iter2;
+  out[3] = (int32_t)b->candidates.size();
+  return GS_OK;
 }
 
 gs_status gs_batch_set_log_cut(gs_batch *b, double log_cut) {
@@ -947,8 +1104,8 @@ static gs_status qn_setup(gs_batch *B) {
   HIP_TRY(B->alloc(&B->d_toy_list, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list1, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list2, (size_t)n));
-  HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->fold_h.size() + B->fold1_h.size(), 1)));
-  HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->adj_h.size(), 1)));
+  HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->cap.n_fold, 1)));
+  HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->cap.n_adj, 1)));
   std::vector<int> np(n);
   for (int t = 0; t < n; t++) np[t] = B->toys_h[t].P;
   HIP_TRY(hipMemcpy(q.n_par, np.data(), sizeof(int) * n, hipMemcpyHostToDevice));

@@ -379,3 +379,56 @@ def test_mixed_batch_fits(gs):
         z = np.abs(th - ref["theta"])[fin] / ref["sigma"][fin]
         print(m.name, z.max(), flush=True)
         assert z.max() <= 1e-3, (m.name, z)
+
+
+def test_layouts_and_autotune(gs):
+    """Batch scheduler knobs: every candidate work layout (split-K target, cells per gradient
+    block, secondary-observable rounds) gives the default layout's values up to the order of
+    floating-point sums; the autotuner puts the fastest candidate in force, and evaluations
+    and a batched fit (whose graph is rebuilt for the new layout) stay correct after it."""
+    import torch
+    toys = gsgen.config4(48)
+    batch = gs.Batch(toys)
+    th = np.zeros((len(toys), batch.stride))
+    for t, m in enumerate(toys):
+        th[t, : m.n_params] = m.theta_true + 0.5 * m.fd_scale * gsgen._rng(300, 1, t).uniform(-1, 1, m.n_params)
+    T = torch.tensor(th, dtype=torch.float64, device="cuda")
+    sc = batch.scales(toys).cpu().numpy()
+
+    def evaluate():
+        n, g, s = batch.nll_grad(T)
+        torch.cuda.synchronize()
+        return n.cpu().numpy(), g.cpu().numpy(), s.cpu().numpy()
+
+    lay0 = batch.layout()
+    assert lay0["candidates"] == 16 and lay0["target_wg"] == 2048, lay0
+    n0, g0, s0 = evaluate()
+    assert (s0 == 0).all()
+
+    def same(n, g, s, what):
+        assert (s == 0).all(), what
+        assert np.max(np.abs(n - n0) / np.abs(n0)) <= 1e-12, what
+        for t in range(len(toys)):
+            assert _grad_err(g[t], g0[t], sc[t]) <= 1e-10, (what, t)
+
+    for wg in (1024, 8192):
+        for gc in (256, 1024):
+            for it in (1, 8):
+                batch.set_layout(wg, gc, it)
+                assert batch.layout()["target_wg"] == wg
+                same(*evaluate(), (wg, gc, it))
+    with pytest.raises(gs.GSError):
+        batch.set_layout(3000, 256, 1)
+    ch = batch.autotune(T, reps=1)
+    lay = batch.layout()
+    assert (lay["target_wg"], lay["grad_cells"], lay["iter2"]) == (ch["target_wg"], ch["grad_cells"], ch["iter2"])
+    assert ch["ms_per_eval"] > 0
+    same(*evaluate(), "autotuned")
+    th0 = np.zeros((len(toys), batch.stride))
+    for t, m in enumerate(toys):
+        th0[t, : m.n_params] = m.theta0
+    r = batch.fit(torch.tensor(th0, dtype=torch.float64, device="cuda"), batch.scales(toys),
+                  free=batch.free_masks(toys))
+    torch.cuda.synchronize()
+    st = r["status"].cpu().numpy()
+    assert all(st[t] & 32 for t in range(len(toys))), st
