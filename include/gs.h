@@ -226,28 +226,30 @@ gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
 #define GS_K_FINISH 9  /* per-problem totals, pulls, status                */
 #define GS_K_COUNT 10
 
-/* Work layout of a batch (the batch scheduler's tuning knobs): the split-K
- * target (work-groups the fold and the adjoint aim for, by splitting each
- * toy's cells / bins into chunks when the batch alone gives fewer), cells per
- * gradient-kernel block (256: one per thread, or 1024: four per thread), and
- * rounds per block of the secondary-observable likelihood and seed kernels
- * (1 or 8).  The work buffers are sized at creation for every candidate in
- * the product {1024, 2048, 4096, 8192} x {256, 1024} x {1, 8 (secondary-
- * observable batches only)}; the default is target 2048 with the other two
- * chosen from the batch's size.  Results do not depend on the layout beyond
- * the order of floating-point sums.
+/* Work layout of a batch (the batch scheduler's tuning knobs for the toy
+ * studies of section 4.2): the split-K target (work-groups the fold and the
+ * adjoint aim for, by splitting each toy's cells / bins into chunks when the
+ * batch alone gives fewer), cells per gradient-kernel block (256: one per
+ * thread, or 1024: four per thread), rounds per block of the secondary-
+ * observable likelihood and seed kernels (1 or 8), and waves per adjoint
+ * workgroup (1 or 4).  The work buffers are sized at creation for every
+ * candidate in the product {1024, 2048, 4096, 8192} x {256, 1024} x {1, 8
+ * (secondary-observable batches only)} x {1, 4}; the default is target 2048
+ * with the other three chosen from the batch's size.  Results do not depend
+ * on the layout beyond the order of floating-point sums.
  *
  * gs_batch_set_layout puts one candidate in force (GS_ERR_ARG if it is not a
  * candidate).  gs_batch_autotune times gs_nll_grad_batched at d_theta under
  * every candidate (one warm-up and `reps` timed evaluations each, HIP events
  * on `hip_stream`; the outputs d_nll, d_grad, d_status as for
  * gs_nll_grad_batched hold the last evaluation's values) and puts the fastest
- * in force; choice (host, 4 entries, may be NULL) receives its target, cells
- * per gradient block, rounds, and mean milliseconds per evaluation.
- * gs_batch_layout reports the layout in force and the number of candidates
- * (host, 4 entries).  All three synchronise the device; a captured batched-
+ * in force; choice (host, 5 entries, may be NULL) receives its target, cells
+ * per gradient block, rounds, adjoint waves, and mean milliseconds per
+ * evaluation.  gs_batch_layout reports the layout in force (the same four
+ * knobs) and the number of candidates (host, 5 entries).  All three synchronise the device; a captured batched-
  * fit graph is rebuilt on the next gs_fit_batched. */
-gs_status gs_batch_set_layout(gs_batch *b, int32_t target_wg, int32_t grad_cells, int32_t iter2);
+gs_status gs_batch_set_layout(gs_batch *b, int32_t target_wg, int32_t grad_cells, int32_t iter2,
+                              int32_t adj_waves);
 gs_status gs_batch_autotune(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
                             int32_t reps, void *hip_stream, double *choice);
 gs_status gs_batch_layout(const gs_batch *b, int32_t *out);

@@ -119,7 +119,7 @@ def lib():
         L.gs_batch_fit_trace.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                          C.POINTER(C.c_int32)]
         L.gs_batch_set_layout.restype = C.c_int
-        L.gs_batch_set_layout.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.gs_batch_set_layout.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.gs_batch_autotune.restype = C.c_int
         L.gs_batch_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, _dp]
         L.gs_batch_layout.restype = C.c_int
@@ -300,17 +300,19 @@ class Batch:
         _check(lib().gs_batch_set_log_cut(self.h, float(log_cut)), "gs_batch_set_log_cut")
 
     def layout(self):
-        """The work layout in force: {target_wg, grad_cells, iter2, candidates}."""
-        out = (C.c_int32 * 4)()
+        """The work layout in force: {target_wg, grad_cells, iter2, adj_waves, candidates}."""
+        out = (C.c_int32 * 5)()
         _check(lib().gs_batch_layout(self.h, out), "gs_batch_layout")
-        return dict(target_wg=int(out[0]), grad_cells=int(out[1]), iter2=int(out[2]), candidates=int(out[3]))
+        return dict(target_wg=int(out[0]), grad_cells=int(out[1]), iter2=int(out[2]), adj_waves=int(out[3]),
+                    candidates=int(out[4]))
 
-    def set_layout(self, target_wg: int, grad_cells: int, iter2: int):
-        _check(lib().gs_batch_set_layout(self.h, int(target_wg), int(grad_cells), int(iter2)), "gs_batch_set_layout")
+    def set_layout(self, target_wg: int, grad_cells: int, iter2: int, adj_waves: int):
+        _check(lib().gs_batch_set_layout(self.h, int(target_wg), int(grad_cells), int(iter2), int(adj_waves)),
+               "gs_batch_set_layout")
 
     def autotune(self, theta, reps: int = 3):
         """Times the batched evaluation at theta under every candidate layout and keeps the
-        fastest; returns {target_wg, grad_cells, iter2, ms_per_eval}."""
+        fastest; returns {target_wg, grad_cells, iter2, adj_waves, ms_per_eval}."""
         import torch
         assert theta.dtype == torch.float64 and theta.is_cuda and theta.is_contiguous()
         assert tuple(theta.shape) == (self.n, self.stride)
@@ -318,11 +320,12 @@ class Batch:
         nll = torch.empty(self.n, dtype=torch.float64, device=dev)
         grad = torch.empty(self.n, self.stride, dtype=torch.float64, device=dev)
         status = torch.empty(self.n, dtype=torch.int32, device=dev)
-        ch = np.zeros(4)
+        ch = np.zeros(5)
         _check(lib().gs_batch_autotune(self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(nll.data_ptr()),
                                        C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()), int(reps),
                                        self._stream(), _ptr(ch)), "gs_batch_autotune")
-        return dict(target_wg=int(ch[0]), grad_cells=int(ch[1]), iter2=int(ch[2]), ms_per_eval=float(ch[3]))
+        return dict(target_wg=int(ch[0]), grad_cells=int(ch[1]), iter2=int(ch[2]), adj_waves=int(ch[3]),
+                    ms_per_eval=float(ch[4]))
 
     def mesh_pairs(self):
         """(fold pairs, adjoint pairs, full-mesh pairs, banded-mesh pairs) of the most recent

@@ -143,9 +143,9 @@ struct DevBuf {
 
 // Layout knobs of a batch: the split-K target (work-groups the fold and the
 // adjoint aim for when the batch alone is smaller), cells per k_cellgrad block,
-// and rounds per k_bins2 / k_hseed block.
+// rounds per k_bins2 / k_hseed block, and waves per adjoint workgroup.
 struct Knobs {
-  int target_wg, grad_cells, iter2;
+  int target_wg, grad_cells, iter2, adj_waves;
 };
 // Work-buffer sizes (elements) and item counts a layout needs.
 struct LayoutSizes {
@@ -292,29 +292,33 @@ static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, cons
 }
 
 // The layout knobs the autotuner tries: split-K targets, one or four cells per
-// k_cellgrad thread, one or kIter2Large rounds per 2-D block (2-D batches).
+// k_cellgrad thread, one or kIter2Large rounds per 2-D block (2-D batches),
+// one or kWaves waves per adjoint workgroup.
 static std::vector<Knobs> layout_candidates(const gs_batch *B) {
   std::vector<Knobs> c;
   for (int wg : {1024, 2048, 4096, 8192})
     for (int gc : {kBlock, kGradCellsLarge})
-      for (int it : {1, kIter2Large}) {
-        if (it != 1 && !B->v.has_2d) continue;
-        c.push_back({wg, gc, it});
-      }
+      for (int it : {1, kIter2Large})
+        for (int aw : {1, kWaves}) {
+          if (it != 1 && !B->v.has_2d) continue;
+          c.push_back({wg, gc, it, aw});
+        }
   return c;
 }
 
-// The default layout: a split-K target of kTargetWG work-groups, four cells per
-// k_cellgrad thread and kIter2Large 2-D rounds once the batch gives at least
-// kGradLargeBlocks blocks of kBlock cells (so one model still fills the GPU).
+// The default layout: a split-K target of kTargetWG work-groups; four cells per
+// k_cellgrad thread, kIter2Large 2-D rounds and one-wave adjoint workgroups
+// once the batch gives at least kGradLargeBlocks blocks of kBlock cells, cell
+// tiles of the adjoint (so one model still fills the GPU).
 static Knobs default_knobs(const gs_batch *B) {
-  long long grad_blocks = 0, bins2_blocks = 0;
+  long long grad_blocks = 0, bins2_blocks = 0, adj_tiles = 0;
   for (const ToyDev &T : B->toys_h) {
     grad_blocks += (T.n_cell + kBlock - 1) / kBlock;
+    adj_tiles += (T.n_cell + kTile - 1) / kTile;
     if (T.two_d) bins2_blocks += ((long long)T.L * T.K + kBlock - 1) / kBlock;
   }
   return {kTargetWG, grad_blocks >= kGradLargeBlocks ? kGradCellsLarge : kBlock,
-          bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1};
+          bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1, adj_tiles >= kGradLargeBlocks ? 1 : kWaves};
 }
 
 static void grow(LayoutSizes &a, const LayoutSizes &b) {
@@ -342,6 +346,7 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
   const int nch_a = (int)std::max<long long>(1, (k.target_wg + tiles_a - 1) / tiles_a);
   v.grad_cells = k.grad_cells;
   v.iter2 = k.iter2;
+  v.adj_waves = k.adj_waves;
   v.max_cell_blocks = v.max_bin_blocks = v.max_bin_blocks1 = v.max_bin_blocks2 = v.max_hblocks = 0;
   B->fold_h.clear();
   B->fold1_h.clear();
@@ -724,15 +729,17 @@ static gs_status apply_layout(gs_batch *B, const Knobs &k) {
   return GS_OK;
 }
 
-gs_status gs_batch_set_layout(gs_batch *b, int32_t target_wg, int32_t grad_cells, int32_t iter2) {
+gs_status gs_batch_set_layout(gs_batch *b, int32_t target_wg, int32_t grad_cells, int32_t iter2,
+                              int32_t adj_waves) {
   if (!b) return fail(GS_ERR_ARG, "null batch");
   HIP_TRY(hipSetDevice(b->device));
   for (const Knobs &k : b->candidates)
-    if (k.target_wg == target_wg && k.grad_cells == grad_cells && k.iter2 == iter2) {
+    if (k.target_wg == target_wg && k.grad_cells == grad_cells && k.iter2 == iter2 && k.adj_waves == adj_waves) {
       HIP_TRY(hipDeviceSynchronize());  // no evaluation of the old layout may still run
       return apply_layout(b, k);
     }
-  return fail(GS_ERR_ARG, "layout (%d, %d, %d) is not one of the batch's candidates", target_wg, grad_cells, iter2);
+  return fail(GS_ERR_ARG, "layout (%d, %d, %d, %d) is not one of the batch's candidates", target_wg, grad_cells,
+              iter2, adj_waves);
 }
 
 gs_status gs_batch_autotune(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
@@ -772,7 +779,8 @@ gs_status gs_batch_autotune(gs_batch *b, const double *d_theta, double *d_nll, d
     choice[0] = best.target_wg;
     choice[1] = best.grad_cells;
     choice[2] = best.iter2;
-    choice[3] = best_ms;
+    choice[3] = best.adj_waves;
+    choice[4] = best_ms;
   }
   return GS_OK;
 }
@@ -782,7 +790,8 @@ gs_status gs_batch_layout(const gs_batch *b, int32_t *out) {
   out[0] = b->knobs.target_wg;
   out[1] = b->knobs.grad_cells;
   out[2] = b->knobs.iter2;
-  out[3] = (int32_t)b->candidates.size();
+  out[3] = b->knobs.adj_waves;
+  out[4] = (int32_t)b->candidates.size();
   return GS_OK;
 }
 

@@ -96,6 +96,7 @@ struct BatchView {
   int max_cells, max_cell_blocks, max_bin_blocks;
   int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)
   int iter2;       // rounds per k_bins2 / k_hseed block (1 or kIter2Large)
+  int adj_waves;   // waves per adjoint workgroup (1 or kWaves)
   int max_bin_blocks1, max_bin_blocks2;  // the same over 1-D / 2-D toys
   int max_ls_blocks;  // kBlock blocks over (window bin, species) pairs
   int max_psd_sk;     // largest S x K of a 2-D toy (P, dP are staged in LDS)

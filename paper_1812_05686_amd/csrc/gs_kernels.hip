@@ -695,23 +695,24 @@ hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *activ
 // block's reference point (see block_ref).
 // Reference exponents E(x_r) of a lane's gamma cell for the bin blocks
 // [qa, qb) (at most kRefBlocks), formed once per cell and block: wave w takes
-// the blocks qa + w, qa + w + kWaves, ... and the workgroup shares them
-// through LDS.  Every thread of the workgroup calls this.
+// the blocks qa + w, qa + w + NW, ... of the NW waves and the workgroup shares
+// them through LDS.  Every thread of the workgroup calls this.
+template <int NW>
 __device__ __forceinline__ void stage_refs(const double *__restrict__ rc, const double *__restrict__ BF, int qa, int qb,
-                                           int wave, double (&sref)[kRefBlocks][kTile]) {
+                                           int wave, double (*sref)[kTile]) {
   const int lane = threadIdx.x & 63;
   __syncthreads();  // the previous round's rows are no longer read
-  for (int q = qa + wave; q < qb; q += kWaves) {
+  for (int q = qa + wave; q < qb; q += NW) {
     const double *r = BF + (size_t)q * 4;
     sref[q - qa][lane] = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
   }
   __syncthreads();
 }
 
-template <int FAM>
+template <int FAM, int NW>
 __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR,
                                          const double *__restrict__ BF, int b0, int b1, int wave, const ExpK &ec,
-                                         double (&sref)[kRefBlocks][kTile], double &A0, double &A1, double &A2) {
+                                         double (*sref)[kTile], double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
   if (FAM == kGammaPE) {
     // A zero seed (also every bin outside the gamma support, x <= 0, whose
@@ -721,15 +722,21 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
     const int q_end = (b1 + kABlock - 1) / kABlock;
     for (int qa = b0 / kABlock; qa < q_end; qa += kRefBlocks) {
       const int qb = min(qa + kRefBlocks, q_end);
-      stage_refs(rc, BF, qa, qb, wave, sref);
+      if (NW > 1) stage_refs<NW>(rc, BF, qa, qb, wave, sref);
       for (int q = qa; q < qb; q++) {
         const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
-        int b = lo + ((b0 + wave - lo) & (kWaves - 1));  // first bin of this wave in the block
+        int b = lo + ((b0 + wave - lo) & (NW - 1));  // first bin of this wave in the block
         if (b >= hi) continue;
-        const double Eref = sref[q - qa][lane];
-        for (; b + kWaves < hi; b += 2 * kWaves) {
+        double Eref;
+        if (NW > 1) {
+          Eref = sref[q - qa][lane];
+        } else {  // a wave on its own forms its references itself
+          const double *r = BF + (size_t)q * 4;
+          Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
+        }
+        for (; b + NW < hi; b += 2 * NW) {
           // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
-          const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + kWaves * kBinRecLen;
+          const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + NW * kBinRecLen;
           const double r0 = dexp(rel_exponent(A, B, Eref, p[6], p[7]), ec);
           const double r1 = dexp(rel_exponent(A, B, Eref, p2[6], p2[7]), ec);
           A0 = __fma_rn(p[3], r0, A0);
@@ -752,8 +759,8 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
   }
   const double *br = BR + (size_t)(b0 + wave) * kBinRecLen;
   double x = br[0], G = br[3];
-  for (int b = b0 + wave; b < b1; b += kWaves) {
-    const double *bn = BR + (size_t)min(b + kWaves, b1 - 1) * kBinRecLen;  // next bin, fetched early
+  for (int b = b0 + wave; b < b1; b += NW) {
+    const double *bn = BR + (size_t)min(b + NW, b1 - 1) * kBinRecLen;  // next bin, fetched early
     const double nx = bn[0], nG = bn[3];
     double z;
     const double Gr = G * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
@@ -769,11 +776,11 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
 // Per-species adjoint (secondary observable): the seed of pair (j, i) is
 // Z_ji = sum_s H_js R_s w_si with H_js = dx_j sum_k P_sk Gam_jk, so each lane
 // keeps R_s w_si of its cell and each bin brings its H row.
-template <int FAM>
+template <int FAM, int NW>
 __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
                                            const double *__restrict__ BR, const double *__restrict__ BF,
                                            const double *__restrict__ HR, int b0, int b1, int wave, const ExpK &ec,
-                                           double (&sref)[kRefBlocks][kTile], double &A0, double &A1, double &A2) {
+                                           double (*sref)[kTile], double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
   if (FAM == kGammaPE) {
     const int lane = threadIdx.x & 63;
@@ -781,13 +788,19 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
     const int q_end = (b1 + kABlock - 1) / kABlock;
     for (int qa = b0 / kABlock; qa < q_end; qa += kRefBlocks) {
       const int qb = min(qa + kRefBlocks, q_end);
-      stage_refs(rc, BF, qa, qb, wave, sref);
+      if (NW > 1) stage_refs<NW>(rc, BF, qa, qb, wave, sref);
       for (int q = qa; q < qb; q++) {
         const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
-        int b = lo + ((b0 + wave - lo) & (kWaves - 1));
+        int b = lo + ((b0 + wave - lo) & (NW - 1));
         if (b >= hi) continue;
-        const double Eref = sref[q - qa][lane];
-        for (; b < hi; b += kWaves) {
+        double Eref;
+        if (NW > 1) {
+          Eref = sref[q - qa][lane];
+        } else {
+          const double *r = BF + (size_t)q * 4;
+          Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
+        }
+        for (; b < hi; b += NW) {
           const double *br = BR + (size_t)b * kBinRecLen;
           if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
           const double *h = HR + (size_t)b * S;
@@ -804,7 +817,7 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
     }
     return;
   }
-  for (int b = b0 + wave; b < b1; b += kWaves) {
+  for (int b = b0 + wave; b < b1; b += NW) {
     const double *br = BR + (size_t)b * kBinRecLen;
     const double x = br[0];
     const double *h = HR + (size_t)b * S;
@@ -821,22 +834,28 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
   }
 }
 
-template <bool PS>
-__global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, int n_items,
+// NW waves of a workgroup share one item (interleaving its bins), or, for
+// NW = 1, each of the kWaves waves takes an item of its own and walks all of
+// its bins (no LDS and no barrier).
+template <bool PS, int NW>
+__global__ __launch_bounds__(kWaves * 64) void k_adj(const AdjItem *__restrict__ items, int n_items,
                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                              const double *__restrict__ theta, int stride,
                                              const double *__restrict__ rec, const double *__restrict__ binrec,
                                              const double *__restrict__ bref, const double *__restrict__ H,
                                              const uint8_t *__restrict__ active,
                                              double *__restrict__ apart) {
-  __shared__ double red[kWaves * kTile * 3];
-  __shared__ double sref[kRefBlocks][kTile];
+  __shared__ double red[NW * kTile * 3];
+  __shared__ double sref[NW > 1 ? kRefBlocks : 1][kTile];
   const ExpK ec = exp_consts();
-  const int w_item = xcd_item(blockIdx.x, n_items);
+  const int lane = threadIdx.x & 63;
+  const int w_item = NW > 1 ? xcd_item(blockIdx.x, n_items)
+                            : xcd_item(blockIdx.x, (n_items + kWaves - 1) / kWaves) * kWaves +
+                                  wave_uniform(threadIdx.x >> 6);
   if (w_item >= n_items) return;
   const AdjItem it = items[w_item];
   if (active && !active[it.toy]) return;
-  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int wave = NW > 1 ? wave_uniform(threadIdx.x >> 6) : 0;  // this wave's place within its item
   const ToyDev &T = toys[it.toy];
   if (T.two_d != (PS ? 1 : 0)) return;
   const ShapeDev &Sh = shapes[T.shape];
@@ -859,9 +878,9 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
   if (!PS) {
     if (Sh.family == kGammaPE)
-      adj_bins<kGammaPE>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
+      adj_bins<kGammaPE, NW>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
     else
-      adj_bins<kGaussE>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
+      adj_bins<kGaussE, NW>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
   } else {
     const double *th = theta + (size_t)it.toy * stride;
     double rw[GS_MAX_SPECIES];
@@ -880,9 +899,18 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
     }
     const double *HR = H + T.win_off * T.S;
     if (Sh.family == kGammaPE)
-      adj_bins_s<kGammaPE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
+      adj_bins_s<kGammaPE, NW>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
     else
-      adj_bins_s<kGaussE>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
+      adj_bins_s<kGaussE, NW>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
+  }
+  if (NW == 1) {
+    if (valid) {
+      double *o = apart + T.apart_off + ((long long)it.chunk * T.n_cell + i) * 3;
+      o[0] = A0;
+      o[1] = A1;
+      o[2] = A2;
+    }
+    return;
   }
   red[(wave * 3 + 0) * kTile + lane] = A0;
   red[(wave * 3 + 1) * kTile + lane] = A1;
@@ -892,7 +920,7 @@ __global__ __launch_bounds__(256) void k_adj(const AdjItem *__restrict__ items, 
     double *o = apart + T.apart_off + ((long long)it.chunk * T.n_cell + i) * 3;
     for (int q = 0; q < 3; q++) {
       double v = red[q * kTile + lane];
-      for (int ww = 1; ww < kWaves; ww++) v += red[(ww * 3 + q) * kTile + lane];
+      for (int ww = 1; ww < NW; ww++) v += red[(ww * 3 + q) * kTile + lane];
       o[q] = v;
     }
   }
@@ -902,12 +930,25 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
   const AdjItem *it = per_species ? v.adj2 : v.adj1;
   const int n = per_species ? v.n_adj2 : v.n_adj1;
   if (n == 0) return hipSuccess;
-  if (per_species)
-    hipLaunchKernelGGL(k_adj<true>, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes,
-                       v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
-  else
-    hipLaunchKernelGGL(k_adj<false>, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes,
-                       v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
+  // one wave per item walks all bins of its cells (large batches: the fixed
+  // per-wave work spreads over four times the pairs); kWaves waves interleave
+  // an item's bins (small batches, where the grid must fill the GPU)
+  const int groups = (n + kWaves - 1) / kWaves;
+  if (per_species) {
+    if (v.adj_waves == 1)
+      hipLaunchKernelGGL((k_adj<true, 1>), dim3(xcd_grid(groups)), dim3(kWaves * 64), 0, st, it, n, v.toys,
+                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
+    else
+      hipLaunchKernelGGL((k_adj<true, kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys,
+                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
+  } else {
+    if (v.adj_waves == 1)
+      hipLaunchKernelGGL((k_adj<false, 1>), dim3(xcd_grid(groups)), dim3(kWaves * 64), 0, st, it, n, v.toys,
+                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
+    else
+      hipLaunchKernelGGL((k_adj<false, kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys,
+                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
+  }
   return hipGetLastError();
 }
 

@@ -383,7 +383,7 @@ def test_mixed_batch_fits(gs):
 
 def test_layouts_and_autotune(gs):
     """Batch scheduler knobs: every candidate work layout (split-K target, cells per gradient
-    block, secondary-observable rounds) gives the default layout's values up to the order of
+    block, secondary-observable rounds, adjoint waves) gives the default layout's values up to the order of
     floating-point sums; the autotuner puts the fastest candidate in force, and evaluations
     and a batched fit (whose graph is rebuilt for the new layout) stay correct after it."""
     import torch
@@ -401,7 +401,7 @@ def test_layouts_and_autotune(gs):
         return n.cpu().numpy(), g.cpu().numpy(), s.cpu().numpy()
 
     lay0 = batch.layout()
-    assert lay0["candidates"] == 16 and lay0["target_wg"] == 2048, lay0
+    assert lay0["candidates"] == 32 and lay0["target_wg"] == 2048, lay0
     n0, g0, s0 = evaluate()
     assert (s0 == 0).all()
 
@@ -414,14 +414,16 @@ def test_layouts_and_autotune(gs):
     for wg in (1024, 8192):
         for gc in (256, 1024):
             for it in (1, 8):
-                batch.set_layout(wg, gc, it)
-                assert batch.layout()["target_wg"] == wg
-                same(*evaluate(), (wg, gc, it))
+                for aw in (1, 4):
+                    batch.set_layout(wg, gc, it, aw)
+                    assert batch.layout()["target_wg"] == wg
+                    same(*evaluate(), (wg, gc, it, aw))
     with pytest.raises(gs.GSError):
-        batch.set_layout(3000, 256, 1)
+        batch.set_layout(3000, 256, 1, 1)
     ch = batch.autotune(T, reps=1)
     lay = batch.layout()
-    assert (lay["target_wg"], lay["grad_cells"], lay["iter2"]) == (ch["target_wg"], ch["grad_cells"], ch["iter2"])
+    keys = ("target_wg", "grad_cells", "iter2", "adj_waves")
+    assert tuple(lay[k] for k in keys) == tuple(ch[k] for k in keys)
     assert ch["ms_per_eval"] > 0
     same(*evaluate(), "autotuned")
     th0 = np.zeros((len(toys), batch.stride))
