@@ -434,3 +434,48 @@ def test_layouts_and_autotune(gs):
     torch.cuda.synchronize()
     st = r["status"].cpu().numpy()
     assert all(st[t] & 32 for t in range(len(toys))), st
+
+
+def _sampled_oracle_check(orc, toys, nll, grad, st, sample):
+    for t in sample:
+        m = toys[t]
+        ov, og, ost = orc.Oracle(m).nll_grad(m.theta_true)
+        assert st[t] == ost == 0, (t, m.name, st[t], ost)
+        assert abs(nll[t] - ov) / abs(ov) <= NLL_TOL, (t, m.name, nll[t], ov)
+        err = _grad_err(grad[t, : m.n_params], og, m.fd_scale)
+        assert err <= GRAD_TOL, (t, m.name, err)
+
+
+def test_full_size_borexino_batch(gs, orc):
+    """The benchmark workload at its full size and in the launch configuration the benchmark
+    times (4096 Borexino-scale pseudo-experiments with ragged windows, one batched evaluation
+    under the autotuned layout): every status clean, and sampled toys (the first, the last and
+    seeded others) against the oracle one by one."""
+    import torch
+    toys = gsgen.config3(4096, base=gsgen.config1())
+    batch = gs.Batch(toys)
+    th = torch.tensor(np.stack([t.theta_true for t in toys]), dtype=torch.float64, device="cuda")
+    batch.autotune(th, reps=1)
+    nll, grad, st = batch.nll_grad(th)
+    torch.cuda.synchronize()
+    nll, grad, st = nll.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all() and np.isfinite(nll).all()
+    rng = np.random.default_rng(1812)
+    sample = sorted({0, 1, 4095, *rng.choice(4096, 5, replace=False).tolist()})
+    _sampled_oracle_check(orc, toys, nll, grad, st, sample)
+
+
+def test_full_size_mixed_batch(gs, orc):
+    """The full 16384-toy uneven mix in one batched evaluation: every status clean, and one
+    sampled toy of every class (energy-family, Borexino-like, pulse-shape) against the oracle."""
+    import torch
+    toys = gsgen.config4(16384)
+    batch = gs.Batch(toys)
+    th = np.zeros((len(toys), batch.stride))
+    for t, m in enumerate(toys):
+        th[t, : m.n_params] = m.theta_true
+    nll, grad, st = batch.nll_grad(torch.tensor(th, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    nll, grad, st = nll.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all() and np.isfinite(nll).all()
+    _sampled_oracle_check(orc, toys, nll, grad, st, _mixed_sample(toys, 1))
