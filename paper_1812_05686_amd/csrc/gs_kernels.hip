@@ -443,6 +443,8 @@ __device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__
   constexpr int kGPB = kStage / kGroup;
   constexpr int kT = kWaves * 64;
   const int tid = threadIdx.x, S = Sh.S, cs = tid % kStage, half = tid / kStage;
+  // grid cells weigh only the grid species (a line cell one species of its own)
+  const int nq = list ? Sh.Sg : S;
   auto cell_of = [&](int bi, int c) {  // cell at slot c of batch bi, or -1
     if (list) {
       const int li = bi * kGPB + c / kGroup;
@@ -485,7 +487,7 @@ __device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__
     for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) swt[tid + u * kT] = wv[u];
     __syncthreads();
     if (bi + 1 < n_batch) fetch(bi + 1);
-    folds_batch(srec, swt, S, nb, wave, o, ec, a0, a1);
+    folds_batch(srec, swt, nq, nb, wave, o, ec, a0, a1);
   }
 }
 
@@ -778,7 +780,7 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
 // keeps R_s w_si of its cell and each bin brings its H row.
 template <int FAM, int NW>
 __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
-                                           const double *__restrict__ BR, const double *__restrict__ BF,
+                                           int nq, const double *__restrict__ BR, const double *__restrict__ BF,
                                            const double *__restrict__ HR, int b0, int b1, int wave, const ExpK &ec,
                                            double (*sref)[kTile], double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
@@ -807,7 +809,7 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
           double Z = 0.0;
 #pragma unroll
           for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
-            if (q2 < S) Z = __fma_rn(h[q2], rw[q2], Z);
+            if (q2 < nq) Z = __fma_rn(h[q2], rw[q2], Z);
           const double Gr = Z * dexp(rel_exponent(A, B, Eref, br[6], br[7]), ec);
           A0 += Gr;
           A1 = __fma_rn(Gr, br[1], A1);
@@ -824,7 +826,7 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
     double Z = 0.0;
 #pragma unroll
     for (int q = 0; q < GS_MAX_SPECIES; q++)
-      if (q < S) Z = __fma_rn(h[q], rw[q], Z);
+      if (q < nq) Z = __fma_rn(h[q], rw[q], Z);
     double z;
     const double Gr = Z * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
     const double Grz = Gr * z;
@@ -898,10 +900,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj(const AdjItem *__restrict__
         if (q == ql) rw[q] = th[Sh.sp_of[q]];
     }
     const double *HR = H + T.win_off * T.S;
+    // a tile of grid cells only: their weights cover the grid species alone
+    const int nq = it.cell0 + kTile <= Sh.n_true ? Sh.Sg : T.S;
     if (Sh.family == kGammaPE)
-      adj_bins_s<kGammaPE, NW>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
+      adj_bins_s<kGammaPE, NW>(rc, rw, T.S, nq, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
     else
-      adj_bins_s<kGaussE, NW>(rc, rw, T.S, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
+      adj_bins_s<kGaussE, NW>(rc, rw, T.S, nq, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
   }
   if (NW == 1) {
     if (valid) {
