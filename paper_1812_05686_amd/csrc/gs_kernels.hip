@@ -802,9 +802,29 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
           const double *r = BF + (size_t)q * 4;
           Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
         }
-        for (; b < hi; b += NW) {
+        // a bin outside the gamma support (x <= 0) has H = 0 and finite offsets,
+        // so it adds exactly zero: no test per bin
+        for (; b + NW < hi; b += 2 * NW) {
+          const double *br = BR + (size_t)b * kBinRecLen, *br2 = br + NW * kBinRecLen;
+          const double *h = HR + (size_t)b * S, *h2 = h + NW * S;
+          double Z = 0.0, Z2 = 0.0;
+#pragma unroll
+          for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
+            if (q2 < nq) {
+              Z = __fma_rn(h[q2], rw[q2], Z);
+              Z2 = __fma_rn(h2[q2], rw[q2], Z2);
+            }
+          const double Gr = Z * dexp(rel_exponent(A, B, Eref, br[6], br[7]), ec);
+          const double Gr2 = Z2 * dexp(rel_exponent(A, B, Eref, br2[6], br2[7]), ec);
+          A0 += Gr;
+          A1 = __fma_rn(Gr, br[1], A1);
+          A2 = __fma_rn(Gr, br[0], A2);
+          A0 += Gr2;
+          A1 = __fma_rn(Gr2, br2[1], A1);
+          A2 = __fma_rn(Gr2, br2[0], A2);
+        }
+        if (b < hi) {
           const double *br = BR + (size_t)b * kBinRecLen;
-          if (!(br[3] != 0.0)) continue;  // wave-uniform: bin outside the gamma support
           const double *h = HR + (size_t)b * S;
           double Z = 0.0;
 #pragma unroll
