@@ -240,10 +240,12 @@ gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
  *
  * gs_batch_set_layout puts one candidate in force (GS_ERR_ARG if it is not a
  * candidate).  gs_batch_autotune times gs_nll_grad_batched at d_theta under
- * every candidate (one warm-up and `reps` timed evaluations each, HIP events
- * on `hip_stream`; the outputs d_nll, d_grad, d_status as for
- * gs_nll_grad_batched hold the last evaluation's values) and puts the fastest
- * in force; choice (host, 5 entries, may be NULL) receives its target, cells
+ * every candidate (after three warm-up evaluations: two passes, the second in
+ * reverse order, of one warm-up and `reps` timed evaluations each, HIP events
+ * on `hip_stream`, each candidate's faster pass kept; the outputs d_nll,
+ * d_grad, d_status as for gs_nll_grad_batched hold the last evaluation's
+ * values) and puts the fastest in force, or the default layout when no
+ * candidate beats it by more than 1%; choice (host, 5 entries, may be NULL) receives its target, cells
  * per gradient block, rounds, adjoint waves, and mean milliseconds per
  * evaluation.  gs_batch_layout reports the layout in force (the same four
  * knobs) and the number of candidates (host, 5 entries).  All three synchronise the device; a captured batched-

@@ -1367,7 +1367,7 @@ hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *ac
 // -ln L), Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), and the block partial of
 // the nuisance-gradient pieces that need no fold,
 // sum_jk Gam_jk sum_s R_s F_js dP_sk/dnu.  P and dP are staged in LDS as
-// [s][k][4].
+// [s][4][k].
 __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
                                                const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
@@ -1377,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
                                                double *__restrict__ Gam, double *__restrict__ nllp,
                                                uint32_t *__restrict__ badp, double *__restrict__ vpart,
                                                double *__restrict__ mu_out) {
-  extern __shared__ double pd[];  // [S][K][4]: P_sk, dP_sk/d(delta, kappa, eta)
+  extern __shared__ double pd[];  // [S][4][K]: P_sk, dP_sk/d(delta, kappa, eta); lanes on consecutive k read consecutive doubles
   __shared__ double ared[kWaves][3];
   __shared__ double lds[8];
   __shared__ int bad_s;
@@ -1390,11 +1390,12 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
   if (threadIdx.x == 0) bad_s = 0;
   for (int e = threadIdx.x; e < S * K; e += blockDim.x) {
     const long long o = T.psd_off + e;
-    double *d = pd + (size_t)e * 4;
+    const int q = e / K, k = e - q * K;
+    double *d = pd + (size_t)q * 4 * K + k;
     d[0] = P[o];
-    d[1] = dP[3 * o];
-    d[2] = dP[3 * o + 1];
-    d[3] = dP[3 * o + 2];
+    d[K] = dP[3 * o];
+    d[2 * K] = dP[3 * o + 1];
+    d[3 * K] = dP[3 * o + 2];
   }
   __syncthreads();
   const double *th = theta + (size_t)t * stride;
@@ -1409,12 +1410,11 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
     double M = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
     for (int q = 0; q < S; q++) {
       const double rf = th[Sh.sp_of[q]] * Fr[q];
-      const double *cq = pd + ((size_t)q * K + k) * 4;
-      const double2 u = *(const double2 *)cq, w = *(const double2 *)(cq + 2);
-      M = __fma_rn(rf, u.x, M);
-      D0 = __fma_rn(rf, u.y, D0);
-      D1 = __fma_rn(rf, w.x, D1);
-      D2 = __fma_rn(rf, w.y, D2);
+      const double *cq = pd + (size_t)q * 4 * K + k;
+      M = __fma_rn(rf, cq[0], M);
+      D0 = __fma_rn(rf, cq[K], D0);
+      D1 = __fma_rn(rf, cq[2 * K], D1);
+      D2 = __fma_rn(rf, cq[3 * K], D2);
     }
     double gam = 0.0;
     for (int d = 0; d < T.D; d++) {
