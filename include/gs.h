@@ -233,9 +233,10 @@ gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
  * thread, or 1024: four per thread), rounds per block of the secondary-
  * observable likelihood and seed kernels (1 or 8), and waves per adjoint
  * workgroup (1 or 4).  The work buffers are sized at creation for every
- * candidate in the product {1024, 2048, 4096, 8192} x {256, 1024} x {1, 8
- * (secondary-observable batches only)} x {1, 4}; the default is target 2048
- * with the other three chosen from the batch's size.  Results do not depend
+ * candidate in the product {2048, 1024, 4096, 8192} x {256, 1024} x {1, 8
+ * (secondary-observable batches only)} x {1, 4}, where a target that splits
+ * the batch into the same chunk counts as an earlier one is left out; the
+ * default is target 2048 with the other three chosen from the batch's size.  Results do not depend
  * on the layout beyond the order of floating-point sums.
  *
  * gs_batch_set_layout puts one candidate in force (GS_ERR_ARG if it is not a

@@ -295,14 +295,27 @@ static gs_status upload_items(gs_batch *B, const std::vector<FoldItem> &fi, cons
 // k_cellgrad thread, one or kIter2Large rounds per 2-D block (2-D batches),
 // one or kWaves waves per adjoint workgroup.
 static std::vector<Knobs> layout_candidates(const gs_batch *B) {
+  // split-K targets that give the same chunk counts as an earlier one give the
+  // same layout: only the first (the default target comes first) is kept
+  long long tiles_f = 0, tiles_a = 0;
+  for (const ToyDev &T : B->toys_h) {
+    tiles_f += (T.L + kFoldTile - 1) / kFoldTile;
+    tiles_a += (T.n_cell + kTile - 1) / kTile;
+  }
+  std::vector<std::pair<long long, long long>> seen;
   std::vector<Knobs> c;
-  for (int wg : {1024, 2048, 4096, 8192})
+  for (int wg : {kTargetWG, 1024, 4096, 8192}) {
+    const std::pair<long long, long long> nch{std::max<long long>(1, (wg + tiles_f - 1) / tiles_f),
+                                              std::max<long long>(1, (wg + tiles_a - 1) / tiles_a)};
+    if (std::find(seen.begin(), seen.end(), nch) != seen.end()) continue;
+    seen.push_back(nch);
     for (int gc : {kBlock, kGradCellsLarge})
       for (int it : {1, kIter2Large})
         for (int aw : {1, kWaves}) {
           if (it != 1 && !B->v.has_2d) continue;
           c.push_back({wg, gc, it, aw});
         }
+  }
   return c;
 }
 

@@ -411,7 +411,7 @@ def test_layouts_and_autotune(gs):
         for t in range(len(toys)):
             assert _grad_err(g[t], g0[t], sc[t]) <= 1e-10, (what, t)
 
-    for wg in (1024, 8192):
+    for wg in (1024, 8192):  # both split this mix differently from 2048
         for gc in (256, 1024):
             for it in (1, 8):
                 for aw in (1, 4):
