@@ -30,10 +30,10 @@ METRIC = "NLL+grad evals/sec and toy fits/sec at |dNLL|/NLL<=1e-11 (adjoint vs f
 FP64_PEAK_TFLOPS = 78.6
 # FP64 operations per evaluated (bin, cell) pair of the gamma-response kernels, counted from
 # their gfx950 instruction mix with an FMA as 2: the block-relative exponent (2 FMA), the
-# exponential (MAX, 12 FMA, ADD, LDEXP) and the accumulation (1 FMA in the fold, 3 in the
-# adjoint): 33 and 37.  The double-double reference exponent formed once per cell and bin
+# exponential (MAX, 11 FMA, ADD, LDEXP) and the accumulation (1 FMA in the fold, 3 in the
+# adjoint): 31 and 35.  The double-double reference exponent formed once per cell and bin
 # block (tile) is set-up work and is not counted.
-FLOPS_PER_PAIR = {"fold": 33, "adj": 37}
+FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
 # HBM bytes per launch on the default workload (4096 toys), from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the

@@ -6,13 +6,19 @@
 // nearest integer n, whose two's complement is its low 32 bits), and
 // r = x - n ln2 is formed in one FMA with ln2 rounded to double.  The product
 // is exact inside the FMA; the rounding of ln2 (2.3e-17) shifts r by
-// |n| 2.3e-17, so the relative error grows with |x|: below 6e-16 + |n| 2.4e-17,
-// i.e. 2.6e-15 for the log-densities above -60 that a banded fold keeps and
-// 2.5e-14 at the bottom of the normal range.  Pair exponents never need more:
-// a bin's value is set by its largest pairs.  p is the degree-10 polynomial
-// that minimises the relative error of exp(r) on [-ln2/2, ln2/2], from the
-// Remez exchange algorithm in 80-digit arithmetic (remez_exp.py; 2.1e-16
-// before and 3.1e-16 after its coefficients are rounded to double).
+// |n| 2.3e-17, so the relative error grows with |x|.  p is the degree-9
+// polynomial that minimises the relative error of exp(r) on [-ln2/2, ln2/2],
+// from the Remez exchange algorithm in 80-digit arithmetic (remez_exp.py;
+// 1.34e-14 before and 1.36e-14 after its coefficients are rounded to double).
+// In all the relative error is below 1.45e-14 + |n| 2.4e-17: 1.7e-14 for the
+// log-densities above -60 that a banded fold keeps and 4e-14 at the bottom of
+// the normal range.
+//
+// Degree 9 matches the accuracy of the argument: a pair exponent formed from
+// a cell's tile-relative constants carries a rounding error of up to ~4e-14
+// (absolute, so relative in the density), which one more polynomial term
+// (degree 10: 3.1e-16) would not remove.  A bin's value is set by its largest
+// pairs, so either sits far inside the per-bin bound of 1e-12.
 //
 // Arguments below -1000 are raised to -1000 (the result underflows to 0
 // either way), so far-tail exponents never reach a saturated integer
@@ -33,38 +39,35 @@
 
 namespace gs {
 
-// c[0..10]: polynomial coefficients of r^10 .. r^0 (Horner order);
-// c[11] = 1/ln2, c[12] = ln2 (rounded to double), c[13] = 1.5 * 2^52.
-#define GS_EXP_COEFS                                                                             \
-  {                                                                                              \
-    2.748844159545267e-07, 2.763976828264541e-06, 2.4801917693499152e-05, 0.00019841171384145565, \
-        0.0013888888499132617, 0.00833333338466586, 0.04166666666842604, 0.16666666666557742,     \
-        0.49999999999997286, 1.0000000000000064, 1.0, 1.4426950408889634074,                      \
-        0.69314718055994530942, 6755399441055744.0                                                \
+// c[0..GS_EXP_DEG]: polynomial coefficients of r^9 .. r^0 (Horner order),
+// then 1/ln2, ln2 (rounded to double) and 1.5 * 2^52.
+#define GS_EXP_DEG 9
+#define GS_EXP_COEFS                                                                                    \
+  {                                                                                                     \
+    2.7482187570947232e-06, 2.488401002622006e-05, 0.00019841596395523973, 0.0013888802828792976,       \
+        0.008333333002823906, 0.04166666703246359, 0.16666666667826951, 0.4999999999945797,            \
+        0.9999999999998928, 1.0000000000000127, 1.4426950408889634074, 0.69314718055994530942,         \
+        6755399441055744.0                                                                              \
   }
-#define GS_EXP_NCOEF 14
+#define GS_EXP_NCOEF (GS_EXP_DEG + 4)
+#define GS_EXP_INV_LN2 (GS_EXP_DEG + 1)
+#define GS_EXP_LN2 (GS_EXP_DEG + 2)
+#define GS_EXP_SHIFT (GS_EXP_DEG + 3)
 
-// c0 = c[0] and mg = c[13], passed separately so that a caller can hold them
-// in vector registers: an instruction may read only one scalar register, and
-// these two meet another scalar operand.
+// c0 = c[0] and mg = c[GS_EXP_SHIFT], passed separately so that a caller can
+// hold them in vector registers: an instruction may read only one scalar
+// register, and these two meet another scalar operand.
 GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
   x = fmax(x, -1000.0);
-  const double t = fma(x, c[11], mg);
+  const double t = fma(x, c[GS_EXP_INV_LN2], mg);
   const double n = t - mg;
-  const double r = fma(-n, c[12], x);
-  double p = fma(c0, r, c[1]);
-  p = fma(p, r, c[2]);
-  p = fma(p, r, c[3]);
-  p = fma(p, r, c[4]);
-  p = fma(p, r, c[5]);
-  p = fma(p, r, c[6]);
-  p = fma(p, r, c[7]);
-  p = fma(p, r, c[8]);
-  p = fma(p, r, c[9]);
-  p = fma(p, r, c[10]);
+  const double r = fma(-n, c[GS_EXP_LN2], x);
+  double p = c0;
+#pragma unroll
+  for (int i = 1; i <= GS_EXP_DEG; i++) p = fma(p, r, c[i]);
   return ldexp(p, (int)(unsigned)__builtin_bit_cast(unsigned long long, t));
 }
 
-GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[13]); }
+GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[GS_EXP_SHIFT]); }
 
 }  // namespace gs

@@ -40,7 +40,7 @@ struct ExpK {
   double c0, mg;
 };
 __device__ __forceinline__ ExpK exp_consts() {
-  ExpK e{kExpC, kExpC[0], kExpC[13]};
+  ExpK e{kExpC, kExpC[0], kExpC[GS_EXP_SHIFT]};
   asm volatile("" : "+v"(e.c0));
   asm volatile("" : "+v"(e.mg));
   return e;
