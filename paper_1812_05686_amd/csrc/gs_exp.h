@@ -54,11 +54,18 @@ namespace gs {
 #define GS_EXP_LN2 (GS_EXP_DEG + 2)
 #define GS_EXP_SHIFT (GS_EXP_DEG + 3)
 
+// Arguments at or above kExpNoClampMin may skip the lower clamp: there
+// x / ln2 rounds to an integer of magnitude below 2^31 (the low 32 bits of t
+// are that integer) and the result already underflows to 0 below about -745.
+// A caller that can show every argument of a loop is finite and at least
+// kExpNoClampMin (a concave exponent checked at the ends of its range) uses
+// exp_cw_unclamped; the two agree bit for bit there.
+constexpr double kExpNoClampMin = -1.0e9;
+
 // c0 = c[0] and mg = c[GS_EXP_SHIFT], passed separately so that a caller can
 // hold them in vector registers: an instruction may read only one scalar
 // register, and these two meet another scalar operand.
-GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
-  x = fmax(x, -1000.0);
+GS_HD inline double exp_cw_unclamped(double x, const double *c, double c0, double mg) {
   const double t = fma(x, c[GS_EXP_INV_LN2], mg);
   const double n = t - mg;
   const double r = fma(-n, c[GS_EXP_LN2], x);
@@ -66,6 +73,10 @@ GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
 #pragma unroll
   for (int i = 1; i <= GS_EXP_DEG; i++) p = fma(p, r, c[i]);
   return ldexp(p, (int)(unsigned)__builtin_bit_cast(unsigned long long, t));
+}
+
+GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
+  return exp_cw_unclamped(fmax(x, -1000.0), c, c0, mg);
 }
 
 GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[GS_EXP_SHIFT]); }

@@ -46,6 +46,21 @@ __device__ __forceinline__ ExpK exp_consts() {
   return e;
 }
 __device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_cw(x, e.c, e.c0, e.mg); }
+// CLAMP = false: every argument is known to be finite and >= kExpNoClampMin.
+template <bool CLAMP>
+__device__ __forceinline__ double dexp(double x, const ExpK &e) {
+  return CLAMP ? exp_cw(x, e.c, e.c0, e.mg) : exp_cw_unclamped(x, e.c, e.c0, e.mg);
+}
+
+// Whether a pair exponent E = Eref + A u + B v stays finite and at or above
+// kExpNoClampMin over bins whose offsets run from (uf, vf) to (ul, vl) in
+// increasing x.  E is concave in x or monotone on the bins in between (gamma
+// with k >= 1: (k-1) ln x - x/th; k < 1: decreasing; Gaussian families: a
+// downward parabola), so its minimum over them is at one of the two ends.
+__device__ __forceinline__ bool exp_args_bounded(double A, double B, double Eref, double uf, double vf, double ul,
+                                                 double vl) {
+  return rel_exponent(A, B, Eref, uf, vf) >= kExpNoClampMin && rel_exponent(A, B, Eref, ul, vl) >= kExpNoClampMin;
+}
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -203,15 +218,17 @@ __device__ __forceinline__ TileRef tile_ref(const ShapeDev &Sh, const ToyDev &T,
   return {r[0], r[2], r[3]};
 }
 
+template <bool CLAMP>
 __device__ __forceinline__ void fold_pair_ref(const double *__restrict__ p, const Off2 &o, const ExpK &ec, double &a0,
                                               double &a1) {
-  a0 = __fma_rn(p[3], dexp(rel_exponent(p[0], p[1], p[2], o.u0, o.v0), ec), a0);
-  a1 = __fma_rn(p[3], dexp(rel_exponent(p[0], p[1], p[2], o.u1, o.v1), ec), a1);
+  a0 = __fma_rn(p[3], dexp<CLAMP>(rel_exponent(p[0], p[1], p[2], o.u0, o.v0), ec), a0);
+  a1 = __fma_rn(p[3], dexp<CLAMP>(rel_exponent(p[0], p[1], p[2], o.u1, o.v1), ec), a1);
 }
 
 // Cell quads wave, wave + kWaves, ... of a staged batch of nb cells (nb a
 // multiple of 4: a batch is padded with zero cells); quarter h of the wave
 // takes the cell 4k + h of quad k.  A staged cell is 4 doubles.
+template <bool CLAMP>
 __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave, const Off2 &o, const ExpK &ec,
                                            double &a0, double &a1) {
   const int h = (threadIdx.x >> 4) & 3;
@@ -223,14 +240,26 @@ __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave,
     const double2 q0 = *(const double2 *)(base + 16 * (k + kWaves));
     const double2 q1 = *(const double2 *)(base + 16 * (k + kWaves) + 2);
     const double p[4] = {p0.x, p0.y, p1.x, p1.y}, q[4] = {q0.x, q0.y, q1.x, q1.y};
-    fold_pair_ref(p, o, ec, a0, a1);
-    fold_pair_ref(q, o, ec, a0, a1);
+    fold_pair_ref<CLAMP>(p, o, ec, a0, a1);
+    fold_pair_ref<CLAMP>(q, o, ec, a0, a1);
   }
   if (k < nq) {
     const double2 p0 = *(const double2 *)(base + 16 * k), p1 = *(const double2 *)(base + 16 * k + 2);
     const double p[4] = {p0.x, p0.y, p1.x, p1.y};
-    fold_pair_ref(p, o, ec, a0, a1);
+    fold_pair_ref<CLAMP>(p, o, ec, a0, a1);
   }
+}
+
+// The staged batch's pairs, through the unclamped exponential unless a cell
+// staged into this workgroup so far may reach an exponent below
+// kExpNoClampMin on the tile (the LDS flag set by stage_store, read after the
+// barrier that follows staging, so the branch is uniform).
+__device__ __forceinline__ void fold_batch_any(const double *srec, int nb, int wave, const Off2 &o, const ExpK &ec,
+                                               const int *sclamp, double &a0, double &a1) {
+  if (wave_uniform(*sclamp))
+    fold_batch<true>(srec, nb, wave, o, ec, a0, a1);
+  else
+    fold_batch<false>(srec, nb, wave, o, ec, a0, a1);
 }
 
 // The record parts a staged cell is formed from (zeros for cell < 0: a zero
@@ -245,23 +274,38 @@ __device__ __forceinline__ void stage_load(const double *__restrict__ R, int cel
   if (FAM == kGammaPE) f[2] = r[2];
 }
 
-// Staged cell c = {A, B, Eref, W} about the tile's reference point.
+// Offsets of the tile's first and last bins (wave-uniform), for the check of
+// the exponent's range at staging.
+struct TileEnds {
+  double uf, vf, ul, vl;
+};
+__device__ __forceinline__ double read_lane(double x, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, l), hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Staged cell c = {A, B, Eref, W} about the tile's reference point.  Sets
+// *sclamp when the cell's exponent may leave [kExpNoClampMin, inf) on the
+// tile.
 template <int FAM>
-__device__ __forceinline__ void stage_store(double *srec, int c, const double2 (&f)[3], const TileRef &ref) {
+__device__ __forceinline__ void stage_store(double *srec, int c, const double2 (&f)[3], const TileRef &ref,
+                                            const TileEnds &te, int *sclamp) {
   // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W}
   const double rc[6] = {f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, f[2].y};
   const RelCell q = rel_cell(FAM, rc, ref.x, ref.Lh, ref.Ll);
   const double W = FAM == kGammaPE ? f[2].y : f[1].y;
   ((double2 *)srec)[2 * c] = make_double2(q.A, q.B);
   ((double2 *)srec)[2 * c + 1] = make_double2(q.Eref, W);
+  if (!exp_args_bounded(q.A, q.B, q.Eref, te.uf, te.vf, te.ul, te.vl)) *sclamp = 1;  // every writer stores 1
 }
 
 // All cells of [c_lo, c_hi) against the tile (block-uniform range; every
 // thread of the block calls this), kStage1 cells per batch, one per thread.
 template <int FAM>
 __device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_lo, int c_hi, double *srec, int wave,
-                                           const TileRef &ref, const Off2 &o, const ExpK &ec, double &a0,
-                                           double &a1) {
+                                           const TileRef &ref, const TileEnds &te, int *sclamp, const Off2 &o,
+                                           const ExpK &ec, double &a0, double &a1) {
   static_assert(kStage1 == kWaves * 64, "one staged cell per thread");
   const int tid = threadIdx.x;
   double2 f[3];
@@ -269,11 +313,11 @@ __device__ __forceinline__ void fold_range(const double *__restrict__ R, int c_l
   for (int base = c_lo; base < c_hi; base += kStage1) {
     const int nb = (min(kStage1, c_hi - base) + 3) & ~3;  // padded to whole cell quads
     __syncthreads();  // every wave is done with the previous batch
-    if (tid < nb) stage_store<FAM>(srec, tid, f, ref);
+    if (tid < nb) stage_store<FAM>(srec, tid, f, ref, te, sclamp);
     __syncthreads();
     const int nxt = base + kStage1 + tid;
     if (base + kStage1 < c_hi) stage_load<FAM>(R, nxt < c_hi ? nxt : -1, f);
-    fold_batch(srec, nb, wave, o, ec, a0, a1);
+    fold_batch_any(srec, nb, wave, o, ec, sclamp, a0, a1);
   }
 }
 
@@ -305,8 +349,8 @@ __device__ __forceinline__ int group_list(const int2 *__restrict__ hull, int g0,
 // zero cells (weight 0).
 template <int FAM>
 __device__ __forceinline__ void fold_groups(const double *__restrict__ R, const int *list, int n_list, int c_lo,
-                                            int c_hi, double *srec, int wave, const TileRef &ref, const Off2 &o,
-                                            const ExpK &ec, double &a0, double &a1) {
+                                            int c_hi, double *srec, int wave, const TileRef &ref, const TileEnds &te,
+                                            int *sclamp, const Off2 &o, const ExpK &ec, double &a0, double &a1) {
   constexpr int kGPB = kStage1 / kGroup;
   const int tid = threadIdx.x;
   auto cell_of = [&](int bi) {
@@ -320,10 +364,10 @@ __device__ __forceinline__ void fold_groups(const double *__restrict__ R, const 
   for (int bi = 0; bi < n_batch; bi++) {
     const int nb = min(kGPB, n_list - bi * kGPB) * kGroup;
     __syncthreads();  // every wave is done with the previous batch
-    if (tid < nb) stage_store<FAM>(srec, tid, f, ref);
+    if (tid < nb) stage_store<FAM>(srec, tid, f, ref, te, sclamp);
     __syncthreads();
     if (bi + 1 < n_batch) stage_load<FAM>(R, cell_of(bi + 1), f);
-    fold_batch(srec, nb, wave, o, ec, a0, a1);
+    fold_batch_any(srec, nb, wave, o, ec, sclamp, a0, a1);
   }
 }
 
@@ -335,6 +379,7 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   __shared__ double red[kWaves * 4 * kFoldTile1];
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
+  __shared__ int sclamp;
   const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
@@ -342,6 +387,7 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   if (active && !active[it.toy]) return;
   const ToyDev &T = toys[it.toy];
   if (T.two_d) return;
+  if (threadIdx.x == 0) sclamp = 0;  // first read after the barriers of group_list or staging
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int kHalf = kFoldTile1 / 2;
@@ -354,6 +400,8 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   Off2 o;
   rel_offsets(Sh.family, bp0[0], bp0[2], bp0[3], ref.x, ref.Lh, ref.Ll, o.u0, o.v0);
   rel_offsets(Sh.family, bp1[0], bp1[2], bp1[3], ref.x, ref.Lh, ref.Ll, o.u1, o.v1);
+  // lane 0 holds the tile's first bin, lane kHalf - 1 its last (b1 clipped to last)
+  const TileEnds te{read_lane(o.u0, 0), read_lane(o.v0, 0), read_lane(o.u1, kHalf - 1), read_lane(o.v1, kHalf - 1)};
   const int j0 = T.lo + it.bin0, j1 = T.lo + last + 1;
   const double *R = rec + T.cell_off * kRecLen;
   // grid cells: the groups whose hull meets the tile, up to kWaves * 64 groups per pass
@@ -364,16 +412,16 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
     const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
                              glist, gcnt);
     if (gamma)
-      fold_groups<kGammaPE>(R, glist, n, it.cell0, g_end, srec, wave, ref, o, ec, a0, a1);
+      fold_groups<kGammaPE>(R, glist, n, it.cell0, g_end, srec, wave, ref, te, &sclamp, o, ec, a0, a1);
     else
-      fold_groups<kGaussE>(R, glist, n, it.cell0, g_end, srec, wave, ref, o, ec, a0, a1);
+      fold_groups<kGaussE>(R, glist, n, it.cell0, g_end, srec, wave, ref, te, &sclamp, o, ec, a0, a1);
   }
   if (gamma) {
-    fold_range<kGammaPE>(R, l_lo, l_hi, srec, wave, ref, o, ec, a0, a1);
+    fold_range<kGammaPE>(R, l_lo, l_hi, srec, wave, ref, te, &sclamp, o, ec, a0, a1);
     if (!(bp0[0] > 0.0)) a0 = 0.0;  // outside the gamma support
     if (!(bp1[0] > 0.0)) a1 = 0.0;
   } else {
-    fold_range<kGaussE>(R, l_lo, l_hi, srec, wave, ref, o, ec, a0, a1);
+    fold_range<kGaussE>(R, l_lo, l_hi, srec, wave, ref, te, &sclamp, o, ec, a0, a1);
   }
   // red[stream][bin]: stream = wave * 4 + quarter, bin of the tile
   const int stream = threadIdx.x >> 4, j = lane & (kHalf - 1);
@@ -711,14 +759,48 @@ __device__ __forceinline__ void stage_refs(const double *__restrict__ rc, const 
   __syncthreads();
 }
 
+// A lane's gamma cell against the bins b, b + NW, ... of [b, hi) within one
+// kABlock block (Eref formed about the block's reference point).  A zero seed
+// (also every bin outside the gamma support, x <= 0, whose offsets are
+// finite) adds exactly zero: no test per bin.
+template <bool CLAMP, int NW>
+__device__ __forceinline__ void adj_block(const double *__restrict__ BR, int b, int hi, double A, double B, double Eref,
+                                          const ExpK &ec, double &A0, double &A1, double &A2) {
+  for (; b + NW < hi; b += 2 * NW) {
+    // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
+    const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + NW * kBinRecLen;
+    const double r0 = dexp<CLAMP>(rel_exponent(A, B, Eref, p[6], p[7]), ec);
+    const double r1 = dexp<CLAMP>(rel_exponent(A, B, Eref, p2[6], p2[7]), ec);
+    A0 = __fma_rn(p[3], r0, A0);
+    A1 = __fma_rn(p[4], r0, A1);
+    A2 = __fma_rn(p[5], r0, A2);
+    A0 = __fma_rn(p2[3], r1, A0);
+    A1 = __fma_rn(p2[4], r1, A1);
+    A2 = __fma_rn(p2[5], r1, A2);
+  }
+  if (b < hi) {
+    const double *p = BR + (size_t)b * kBinRecLen;
+    const double r0 = dexp<CLAMP>(rel_exponent(A, B, Eref, p[6], p[7]), ec);
+    A0 = __fma_rn(p[3], r0, A0);
+    A1 = __fma_rn(p[4], r0, A1);
+    A2 = __fma_rn(p[5], r0, A2);
+  }
+}
+
+// Whether any lane's exponent may leave [kExpNoClampMin, inf) on the bins
+// [lo, hi) of a block (wave-uniform): checked at the two end bins.
+__device__ __forceinline__ bool block_needs_clamp(const double *__restrict__ BR, int lo, int hi, double A, double B,
+                                                  double Eref) {
+  const double *pl = BR + (size_t)lo * kBinRecLen, *ph = BR + (size_t)(hi - 1) * kBinRecLen;
+  return __ballot(!exp_args_bounded(A, B, Eref, pl[6], pl[7], ph[6], ph[7])) != 0ull;
+}
+
 template <int FAM, int NW>
 __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const double *__restrict__ BR,
                                          const double *__restrict__ BF, int b0, int b1, int wave, const ExpK &ec,
                                          double (*sref)[kTile], double &A0, double &A1, double &A2) {
   if (b0 >= b1) return;
   if (FAM == kGammaPE) {
-    // A zero seed (also every bin outside the gamma support, x <= 0, whose
-    // offsets are finite) adds exactly zero: no test per bin.
     const int lane = threadIdx.x & 63;
     const double A = rc[0], B = -rc[1];
     const int q_end = (b1 + kABlock - 1) / kABlock;
@@ -736,25 +818,10 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
           const double *r = BF + (size_t)q * 4;
           Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
         }
-        for (; b + NW < hi; b += 2 * NW) {
-          // bin record: x, ln x (hi, lo), G, G ln x, G x, u, v
-          const double *p = BR + (size_t)b * kBinRecLen, *p2 = p + NW * kBinRecLen;
-          const double r0 = dexp(rel_exponent(A, B, Eref, p[6], p[7]), ec);
-          const double r1 = dexp(rel_exponent(A, B, Eref, p2[6], p2[7]), ec);
-          A0 = __fma_rn(p[3], r0, A0);
-          A1 = __fma_rn(p[4], r0, A1);
-          A2 = __fma_rn(p[5], r0, A2);
-          A0 = __fma_rn(p2[3], r1, A0);
-          A1 = __fma_rn(p2[4], r1, A1);
-          A2 = __fma_rn(p2[5], r1, A2);
-        }
-        if (b < hi) {
-          const double *p = BR + (size_t)b * kBinRecLen;
-          const double r0 = dexp(rel_exponent(A, B, Eref, p[6], p[7]), ec);
-          A0 = __fma_rn(p[3], r0, A0);
-          A1 = __fma_rn(p[4], r0, A1);
-          A2 = __fma_rn(p[5], r0, A2);
-        }
+        if (block_needs_clamp(BR, lo, hi, A, B, Eref))
+          adj_block<true, NW>(BR, b, hi, A, B, Eref, ec, A0, A1, A2);
+        else
+          adj_block<false, NW>(BR, b, hi, A, B, Eref, ec, A0, A1, A2);
       }
     }
     return;

@@ -2,11 +2,13 @@
 // the relative error over the log-densities a banded fold keeps ([-60, 1]), its
 // growth with |n| (x = n ln2 + r) over the whole normal range against the bound
 // 1.45e-14 + |n| 2.4e-17 the header states, the subnormal range (that bound plus
-// the rounding to a subnormal, in units of the smallest subnormal), and
-// special values.
+// the rounding to a subnormal, in units of the smallest subnormal), special
+// values, and that the unclamped variant agrees with it bit for bit on
+// [kExpNoClampMin, 709].
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <random>
 
 #include "gs_exp.h"
@@ -48,9 +50,22 @@ int main() {
   if (gs::exp_cw(-1.0e30, c) != 0.0) n_bad_special++;
   if (!(std::fabs(gs::exp_cw(0.0, c) - 1.0) <= 1.45e-14)) n_bad_special++;
   if (!std::isinf(gs::exp_cw(710.0, c))) n_bad_special++;
+  // the unclamped variant on its stated domain, including far below the underflow
+  long n_unclamped_diff = 0;
+  std::uniform_real_distribution<double> W(gs::kExpNoClampMin, 709.0), Z(-1.0e6, -700.0);
+  auto same = [&](double x) {
+    const double a = gs::exp_cw(x, c), b = gs::exp_cw_unclamped(x, c, c[0], c[GS_EXP_SHIFT]);
+    if (std::memcmp(&a, &b, sizeof a) != 0) n_unclamped_diff++;
+  };
+  for (int i = 0; i < 1000000; i++) same(W(rng));
+  for (int i = 0; i < 1000000; i++) same(Z(rng));
+  for (int i = 0; i < 1000000; i++) same(K(rng));
+  same(gs::kExpNoClampMin);
+  same(-1000.0);
+  same(0.0);
   printf(
       "{\"n\": %ld, \"max_rel\": %.6e, \"worst_x\": %.17g, \"max_rel_kept\": %.6e, \"max_bound_ratio\": %.3f, "
-      "\"max_subnormal_ulps\": %.3f, \"bad_special\": %ld}\n",
-      n, max_rel, worst, max_rel_kept, max_ratio, max_sub, n_bad_special);
+      "\"max_subnormal_ulps\": %.3f, \"bad_special\": %ld, \"unclamped_diff\": %ld}\n",
+      n, max_rel, worst, max_rel_kept, max_ratio, max_sub, n_bad_special, n_unclamped_diff);
   return 0;
 }

@@ -1,7 +1,8 @@
 """The device exponential (paper_1812_05686_amd/csrc/gs_exp.h) compiled for the host and checked
 against long-double expl: relative error below 1.7e-14 over the log-densities a banded fold keeps
 ([-60, 1]), within the stated bound 1.45e-14 + |n| 2.4e-17 over the normal range, underflow handled,
-special values right (exp(0) within the polynomial's error of 1)."""
+special values right (exp(0) within the polynomial's error of 1), and the unclamped variant equal
+to it bit for bit on its domain [-1e9, 709]."""
 import json
 import os
 import subprocess
@@ -15,6 +16,7 @@ def test_exp_cw_accuracy(tmp_path):
                            os.path.join(ROOT, "tests", "exp_check.cpp"), "-o", str(exe)])
     r = json.loads(subprocess.check_output([str(exe)]).decode())
     assert r["bad_special"] == 0, r
+    assert r["unclamped_diff"] == 0, r
     assert r["max_rel_kept"] <= 1.7e-14, r
     assert r["max_bound_ratio"] <= 1.0, r
     assert r["max_rel"] <= 4.0e-14, r

@@ -163,6 +163,42 @@ def test_edge_shapes(gs, orc):
         assert _grad_err(g, og, m.fd_scale) <= GRAD_TOL
 
 
+def test_sharp_response_exponent_range(gs, orc):
+    """A response so sharp (sigma = 5 eV on 10 keV bins) that pair exponents fall below -1e9
+    inside a tile: the fold's range check must route those tiles through the clamped
+    exponential (an unclamped one would wrap the exponent's integer part and return inf or
+    garbage).  The tile-relative Gaussian exponent cancels terms of size (w/sigma)^2 there, so
+    the bar is its rounding bound, 4.4e-14 (w/sigma)^2 relative per bin (w the bin width),
+    which also bounds the NLL's relative error; the gradient is only required to be finite
+    there.  An ordinary resolution (sigma = w) takes the unclamped path at the usual bars."""
+    base = gsgen.config0()
+    # reco midpoints on the true-cell centres (7.5 + 10 j), so the sharp lines land in bins
+    edges = 2.5 + 10.0 * np.arange(201.0)
+    sharp_tol = 4.4e-14 * (10.0 / 0.005) ** 2
+    for a, mu_tol, nll_tol, grad_tol in ((0.005, sharp_tol, sharp_tol, None), (10.0, MU_TOL, NLL_TOL, GRAD_TOL)):
+        th = base.theta_true.copy()
+        th[3:] = (a, 0.0)
+        m = base.replace(reco_edges=edges, theta_true=th, pull_centre=th.copy())
+        mu_true = orc.Oracle(m).expected(th)
+        m = m.replace(counts=np.random.default_rng(11).poisson(mu_true).astype(float))
+        o = orc.Oracle(m)
+        model = gs.Model(m)
+        ref = o.expected(th)[:, m.win_lo:m.win_hi, :]
+        mu = model.expected(th).reshape(ref.shape)
+        assert np.all(np.isfinite(mu))
+        big = ref >= 1e-3
+        assert big.sum() > 20
+        assert np.max(np.abs(mu - ref)[big] / ref[big]) <= mu_tol, a
+        assert np.all(np.abs(mu - ref)[~big] <= 1e-12 + mu_tol * 1e-3), a
+        v, g, st = model.nll_grad(th)
+        ov, og, ost = o.nll_grad(th)
+        assert st == ost == 0
+        assert abs(v - ov) / max(abs(ov), 1e-300) <= nll_tol, a
+        assert np.all(np.isfinite(g))
+        if grad_tol is not None:
+            assert _grad_err(g, og, m.fd_scale) <= grad_tol, a
+
+
 def test_unrepresentable_seed_is_domain(gs, orc):
     """n > 0 in a bin whose mu is so small that 1 - n/mu overflows: both sides report DOMAIN."""
     base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
