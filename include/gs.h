@@ -203,11 +203,12 @@ gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_f
 
 /* ------------------------------------------------------- mesh banding --- */
 /* Pairs (reco bin j, true cell i) whose log-density ln r(xbar_j | E_i) is
- * below log_cut are skipped (default -60).  Each cell's support, the bins
+ * below log_cut are skipped (default -52).  Each cell's support, the bins
  * where the log-density can exceed log_cut, is solved per evaluation, so the
  * absolute error of every expected count is at most
- * sum_s |R_s| eps_d dx_j exp(log_cut) (5.6e-21 counts for the 4000-cell,
- * 900-bin model at its nominal rates).  -INFINITY evaluates the full mesh.
+ * sum_s |R_s| eps_d dx_j exp(log_cut) (1.6e-17 counts for the 4000-cell,
+ * 900-bin model at its nominal rates: 1.6e-14 of a bin holding 1e-3 counts,
+ * the smallest the 1e-12 relative bound applies to).  -INFINITY evaluates the full mesh.
  * The setting applies to later calls on the batch / model. */
 gs_status gs_batch_set_log_cut(gs_batch *b, double log_cut);
 gs_status gs_model_set_log_cut(gs_model *m, double log_cut);

@@ -10,9 +10,9 @@
 // polynomial that minimises the relative error of exp(r) on [-ln2/2, ln2/2],
 // from the Remez exchange algorithm in 80-digit arithmetic (remez_exp.py;
 // 1.34e-14 before and 1.36e-14 after its coefficients are rounded to double).
-// In all the relative error is below 1.45e-14 + |n| 2.4e-17: 1.7e-14 for the
-// log-densities above -60 that a banded fold keeps and 4e-14 at the bottom of
-// the normal range.
+// In all the relative error is below 1.45e-14 + |n| 2.4e-17: 1.7e-14 for
+// log-densities above -60 (a banded fold keeps those above its cut, -52 by
+// default) and 4e-14 at the bottom of the normal range.
 //
 // Degree 9 matches the accuracy of the argument: a pair exponent formed from
 // a cell's tile-relative constants carries a rounding error of up to ~4e-14
