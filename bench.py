@@ -327,9 +327,12 @@ def main():
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))
         rate, n_done, el, outs = cpu_baseline(toys, args.cpu_seconds, threads)
+        rate1, n1, el1, _ = cpu_baseline(toys, max(2.0, args.cpu_seconds / 3), 1)
         cpu = {"value": round(rate, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"{n_done} oracle -ln L+gradient evaluations of the first {threads} pseudo-experiments "
-                         f"(one per thread) in {el:.1f} s"}
+                         f"(one per thread) in {el:.1f} s",
+               "one_thread": {"value": round(rate1, 4), "unit": "evals/s",
+                              "sample": f"{n1} evaluations of the first pseudo-experiment in {el1:.1f} s"}}
         rel = max(abs(gpu_nll[i] - outs[i][0]) / abs(outs[i][0]) for i in range(threads))
         gerr = max(np.max(np.abs(gpu_grad[i, :17] - outs[i][1]) * base.fd_scale /
                           np.maximum(np.abs(outs[i][1]) * base.fd_scale, 1.0)) for i in range(threads))
