@@ -11,7 +11,7 @@ namespace gs {
 constexpr int kTile = 64;       // cells per adjoint tile (one per lane); bins per per-species fold tile
 constexpr int kFoldTile = 64;   // window bins per per-species fold item (two per lane of each half-wave)
 constexpr int kFoldTile1 = 32;  // window bins per 1-D fold item (two per lane of each quarter-wave)
-constexpr int kABlock = 32;     // window bins per adjoint exponent reference block
+constexpr int kABlock = 64;     // window bins per adjoint exponent reference block
 constexpr int kRefBlocks = 16;  // reference blocks whose per-cell exponents the adjoint stages in LDS at once
 constexpr int kStage = 128;     // cell records staged in LDS per batch of the per-species fold
 constexpr int kStage1 = 256;    // cells staged in LDS per batch of the 1-D fold (one per thread)

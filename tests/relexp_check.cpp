@@ -2,7 +2,8 @@
 // rel_exponent in paper_1812_05686_amd/csrc/gs_dev.h) that the 1-D fold and
 // the adjoint evaluate per (bin, cell) pair.  For every cell of a response
 // grid and every bin of the reco range, with the reference at the middle bin
-// of the bin's 32-bin tile (as the kernels place it), the relative exponent
+// of the bin's 32-bin tile (the fold) and, for gamma, of its 64-bin block (the
+// adjoint), as the kernels place them, the relative exponent
 // is compared with the exponent the cell record defines, evaluated in
 // quadruple precision (__float128; the gamma terms K ln x reach ~5e5 and
 // cancel to O(10), beyond what long double resolves):
@@ -29,7 +30,7 @@ struct Res {
 };
 
 static void run(int fam, const double *resp, double A, int n_true, double e_step, const std::vector<double> &edges,
-                Res &r) {
+                Res &r, int W) {
   const int n = (int)edges.size() - 1;
   std::vector<double> x(n), Lh(n), Ll(n);
   for (int j = 0; j < n; j++) {
@@ -55,8 +56,8 @@ static void run(int fam, const double *resp, double A, int n_true, double e_step
         Es = (qd)rc[2] - (qd)0.5 * z * z;
       }
       if (!(Es > (qd)-60.0)) continue;
-      const int t0 = j / 32 * 32, last = (t0 + 32 < n ? t0 + 32 : n) - 1;
-      int jr = t0 + 16 < last ? t0 + 16 : last;
+      const int t0 = j / W * W, last = (t0 + W < n ? t0 + W : n) - 1;
+      int jr = t0 + W / 2 < last ? t0 + W / 2 : last;
       if (fam == kGammaPE && !(x[jr] > 0.0)) jr = last;
       const RelCell c = rel_cell(fam, rc, x[jr], Lh[jr], Ll[jr]);
       double u, v;
@@ -89,12 +90,16 @@ int main() {
   for (int j = 0; j <= 900; j++) u900[j] = 1.6 * j;
   for (int j = 0; j <= 300; j++) nonu[j] = 1440.0 * std::pow(j / 300.0, 1.5);
   for (int j = 0; j <= 200; j++) u200[j] = 10.0 * j;
-  run(kGammaPE, pe, 2.0, 4000, 0.00075, u900, g);
-  run(kGammaPE, pe2, 2.0, 1000, 0.003, u900, g);
-  run(kGammaPE, pe, 2.0, 1000, 0.003, nonu, g);
   const double ke[2] = {10.0, 5.0};
-  run(kGaussE, ke, 0.0, 500, 5.0, u200, k);
-  run(kGaussPE, pe, 2.0, 1000, 0.003, u900, k);
+  // gamma: the fold's tiles and the adjoint's blocks; the Gaussian families use the
+  // relative form in the fold only (the adjoint forms their exponent per pair)
+  for (int W : {32, 64}) {
+    run(kGammaPE, pe, 2.0, 4000, 0.00075, u900, g, W);
+    run(kGammaPE, pe2, 2.0, 1000, 0.003, u900, g, W);
+    run(kGammaPE, pe, 2.0, 1000, 0.003, nonu, g, W);
+  }
+  run(kGaussE, ke, 0.0, 500, 5.0, u200, k, 32);
+  run(kGaussPE, pe, 2.0, 1000, 0.003, u900, k, 32);
   std::printf(
       "{\"gamma\": {\"pairs\": %ld, \"max_err\": %.3e, \"max_ratio\": %.3f, \"max_err_dd\": %.3e, "
       "\"max_rel_density\": %.3e}, \"gauss\": {\"pairs\": %ld, \"max_err\": %.3e, \"max_ratio\": %.3f, "
