@@ -39,8 +39,8 @@ FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
 # kernel sources they were taken on: any change to those sources reports traffic as null.
 # Source: profiles/hbm_bytes_k_fold1_k_adj_borexino_4096toys.md.
-TRAFFIC = {"sources_sha256": "f4aa85f96d5b7812bcaebdafdf360dc3ef57b66988b9d6fed76d736d8c7f4114",
-           "toys": 4096, "kernels": {"k_fold1": 1071688273, "k_adj": 1758619578}}
+TRAFFIC = {"sources_sha256": "4f526d81edf7062c7a30dcc981764ef5a72f84d71022d6f2b02f95b53caad335",
+           "toys": 4096, "kernels": {"k_fold1": 1071681537, "k_adj": 1755529963}}
 
 
 def sources_sha256():
