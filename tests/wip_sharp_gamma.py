@@ -4,7 +4,6 @@ import numpy as np
 import pytest
 
 import gsgen
-from test_gpu_parity import _grad_err  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
