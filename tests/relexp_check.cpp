@@ -25,8 +25,11 @@ using namespace gs;
 typedef __float128 qd;
 
 struct Res {
-  long pairs = 0;
+  long pairs = 0, tiles = 0;
   double max_err = 0.0, max_ratio = 0.0, max_err_dd = 0.0, max_rel_density = 0.0;
+  // worst amount by which a bin inside a tile falls below the lower of the
+  // tile's two end bins, in units of u (|A u| + |B v| + |Eref|) of that bin
+  double max_below_ends = 0.0;
 };
 
 static void run(int fam, const double *resp, double A, int n_true, double e_step, const std::vector<double> &edges,
@@ -46,6 +49,28 @@ static void run(int fam, const double *resp, double A, int n_true, double e_step
     if (!moments(fam, resp, A, E, mo)) continue;
     double rc[kRecLen];
     cell_record(fam, mo.m, mo.s, 1.0, true, rc);
+    // the pair loops' range check: within a tile the relative exponent is lowest
+    // at one of the two end bins (checked on every tile of positive midpoints)
+    for (int t0 = 0; t0 < n; t0 += W) {
+      const int t1 = t0 + W < n ? t0 + W : n;
+      if (fam == kGammaPE && !(x[t0] > 0.0)) continue;
+      const int jr = t0 + W / 2 < t1 - 1 ? t0 + W / 2 : t1 - 1;
+      const RelCell c = rel_cell(fam, rc, x[jr], Lh[jr], Ll[jr]);
+      auto Eat = [&](int j, double &scale) {
+        double u, v;
+        rel_offsets(fam, x[j], Lh[j], Ll[j], x[jr], Lh[jr], Ll[jr], u, v);
+        scale = u64 * (std::fabs(c.A * u) + std::fabs(c.B * v) + std::fabs(c.Eref)) + 1e-300;
+        return rel_exponent(c.A, c.B, c.Eref, u, v);
+      };
+      double sf, sl;
+      const double ends = std::fmin(Eat(t0, sf), Eat(t1 - 1, sl));
+      for (int j = t0 + 1; j < t1 - 1; j++) {
+        double sc;
+        const double Ej = Eat(j, sc);
+        if (ends - Ej > 0.0 && (ends - Ej) / sc > r.max_below_ends) r.max_below_ends = (ends - Ej) / sc;
+      }
+      r.tiles++;
+    }
     for (int j = 0; j < n; j++) {
       if (fam == kGammaPE && !(x[j] > 0.0)) continue;
       qd Es;
@@ -102,9 +127,10 @@ int main() {
   run(kGaussPE, pe, 2.0, 1000, 0.003, u900, k, 32);
   std::printf(
       "{\"gamma\": {\"pairs\": %ld, \"max_err\": %.3e, \"max_ratio\": %.3f, \"max_err_dd\": %.3e, "
-      "\"max_rel_density\": %.3e}, \"gauss\": {\"pairs\": %ld, \"max_err\": %.3e, \"max_ratio\": %.3f, "
-      "\"max_err_dd\": %.3e, \"max_rel_density\": %.3e}}\n",
-      g.pairs, g.max_err, g.max_ratio, g.max_err_dd, g.max_rel_density, k.pairs, k.max_err, k.max_ratio,
-      k.max_err_dd, k.max_rel_density);
+      "\"max_rel_density\": %.3e, \"tiles\": %ld, \"max_below_ends\": %.3f}, \"gauss\": {\"pairs\": %ld, "
+      "\"max_err\": %.3e, \"max_ratio\": %.3f, \"max_err_dd\": %.3e, \"max_rel_density\": %.3e, "
+      "\"tiles\": %ld, \"max_below_ends\": %.3f}}\n",
+      g.pairs, g.max_err, g.max_ratio, g.max_err_dd, g.max_rel_density, g.tiles, g.max_below_ends, k.pairs,
+      k.max_err, k.max_ratio, k.max_err_dd, k.max_rel_density, k.tiles, k.max_below_ends);
   return 0;
 }

@@ -1,7 +1,9 @@
 """The tile-relative pair exponent of the 1-D fold and the adjoint (rel_cell, rel_offsets,
 rel_exponent in paper_1812_05686_amd/csrc/gs_dev.h), compiled for the host and compared with
 the exponent a cell record defines, evaluated in quadruple precision, on every pair that a
-banded fold keeps (log-density above -60) for Borexino-scale and sharper responses."""
+banded fold keeps (log-density above -60) for Borexino-scale and sharper responses.  Also the
+property the pair loops' range check rests on: within a tile (or an adjoint block) the relative
+exponent of a cell is lowest at one of the two end bins, up to rounding."""
 import json
 import os
 import subprocess
@@ -22,3 +24,5 @@ def test_relative_exponent_error(tmp_path):
         # relative error of every kept density: far inside the 1e-12 per-bin bound
         assert q["max_rel_density"] <= 1e-13, r
         assert q["max_err"] <= 1e-13, r
+        # no interior bin of a tile below the lower end bin by more than its rounding
+        assert q["tiles"] > 10000 and q["max_below_ends"] <= 4.0, r
