@@ -199,6 +199,35 @@ def test_sharp_response_exponent_range(gs, orc):
             assert _grad_err(g, og, m.fd_scale) <= grad_tol, a
 
 
+def test_sharp_gamma_response_exponent_range(gs, orc):
+    """The gamma family with sigma = 0.01 pe on 36-pe bins (cell means on the bin midpoints:
+    LY 1200 pe/MeV on 30-keV cells, kB ~ 0): pair exponents reach about -7e9 inside a fold
+    tile and an adjoint block, so both kernels must take their clamped exponentials (the
+    fold by its staging flag, the adjoint by its per-block wave vote).  The tile-relative
+    exponent then carries u64 k |ln x - ln x_r| of rounding (k up to 2e10), which sets the
+    bar; the gradient is only required to be finite."""
+    base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
+    th = base.theta_true.copy()
+    th[base.n_species:] = (1200.0, 1e-12, 0.01, 0.0, 0.0)
+    m = base.replace(theta_true=th, pull_centre=th.copy(), pull_sigma=np.zeros(len(th)))
+    m = m.replace(counts=np.random.default_rng(11).poisson(orc.Oracle(m).expected(th)).astype(float))
+    o = orc.Oracle(m)
+    x = 0.5 * (m.reco_edges[1:] + m.reco_edges[:-1])
+    tol = 3.0 * 2.0 ** -53 * (x.max() / 0.01) ** 2 * np.log(x.max() / x.min())
+    model = gs.Model(m)
+    ref = o.expected(th)[:, m.win_lo:m.win_hi, :]
+    mu = model.expected(th).reshape(ref.shape)
+    assert np.all(np.isfinite(mu))
+    big = ref >= 1e-3
+    assert big.sum() >= 30
+    assert np.max(np.abs(mu - ref)[big] / ref[big]) <= tol
+    v, g, st = model.nll_grad(th)
+    ov, og, ost = o.nll_grad(th)
+    assert st == ost == 0
+    assert abs(v - ov) / abs(ov) <= tol
+    assert np.all(np.isfinite(g))
+
+
 def test_unrepresentable_seed_is_domain(gs, orc):
     """n > 0 in a bin whose mu is so small that 1 - n/mu overflows: both sides report DOMAIN."""
     base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
