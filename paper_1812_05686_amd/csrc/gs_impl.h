@@ -18,6 +18,7 @@ constexpr int kStage1 = 256;    // cells staged in LDS per batch of the 1-D fold
 constexpr int kGroup = 16;      // grid cells per support hull
 constexpr int kVLen = GS_MAX_SPECIES + 4;  // 2-D gradient partials per block: species, 3 nuisances, pad
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
+constexpr int kAdjGroupWaves = 2;  // workgroup size of the adjoint that gives each wave its own item
 constexpr int kBlock = 256;     // threads per reduction block
 constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed round (2-D models)
 // k_bins2 and k_hseed rounds per block (BatchView::iter2): each block stages

@@ -927,7 +927,7 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
 // NW = 1, each of the kWaves waves takes an item of its own and walks all of
 // its bins (no LDS and no barrier).
 template <bool PS, int NW>
-__global__ __launch_bounds__(kWaves * 64) void k_adj(const AdjItem *__restrict__ items, int n_items,
+__global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj(const AdjItem *__restrict__ items, int n_items,
                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                              const double *__restrict__ theta, int stride,
                                              const double *__restrict__ rec, const double *__restrict__ binrec,
@@ -939,7 +939,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj(const AdjItem *__restrict__
   const ExpK ec = exp_consts();
   const int lane = threadIdx.x & 63;
   const int w_item = NW > 1 ? xcd_item(blockIdx.x, n_items)
-                            : xcd_item(blockIdx.x, (n_items + kWaves - 1) / kWaves) * kWaves +
+                            : xcd_item(blockIdx.x, (n_items + kAdjGroupWaves - 1) / kAdjGroupWaves) * kAdjGroupWaves +
                                   wave_uniform(threadIdx.x >> 6);
   if (w_item >= n_items) return;
   const AdjItem it = items[w_item];
@@ -1021,20 +1021,21 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
   const AdjItem *it = per_species ? v.adj2 : v.adj1;
   const int n = per_species ? v.n_adj2 : v.n_adj1;
   if (n == 0) return hipSuccess;
-  // one wave per item walks all bins of its cells (large batches: the fixed
-  // per-wave work spreads over four times the pairs); kWaves waves interleave
-  // an item's bins (small batches, where the grid must fill the GPU)
-  const int groups = (n + kWaves - 1) / kWaves;
+  // one wave per item walks all bins of its cells, kAdjGroupWaves items per
+  // workgroup (large batches: the fixed per-wave work spreads over four times
+  // the pairs); kWaves waves interleave an item's bins (small batches, where
+  // the grid must fill the GPU)
+  const int groups = (n + kAdjGroupWaves - 1) / kAdjGroupWaves;
   if (per_species) {
     if (v.adj_waves == 1)
-      hipLaunchKernelGGL((k_adj<true, 1>), dim3(xcd_grid(groups)), dim3(kWaves * 64), 0, st, it, n, v.toys,
+      hipLaunchKernelGGL((k_adj<true, 1>), dim3(xcd_grid(groups)), dim3(kAdjGroupWaves * 64), 0, st, it, n, v.toys,
                          v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
     else
       hipLaunchKernelGGL((k_adj<true, kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys,
                          v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
   } else {
     if (v.adj_waves == 1)
-      hipLaunchKernelGGL((k_adj<false, 1>), dim3(xcd_grid(groups)), dim3(kWaves * 64), 0, st, it, n, v.toys,
+      hipLaunchKernelGGL((k_adj<false, 1>), dim3(xcd_grid(groups)), dim3(kAdjGroupWaves * 64), 0, st, it, n, v.toys,
                          v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
     else
       hipLaunchKernelGGL((k_adj<false, kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys,
