@@ -39,8 +39,8 @@ FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
 # kernel sources they were taken on: any change to those sources reports traffic as null.
 # Source: profiles/hbm_bytes_k_fold1_k_adj_borexino_4096toys.md.
-TRAFFIC = {"sources_sha256": "4f526d81edf7062c7a30dcc981764ef5a72f84d71022d6f2b02f95b53caad335",
-           "toys": 4096, "kernels": {"k_fold1": 1071681537, "k_adj": 1755529963}}
+TRAFFIC = {"sources_sha256": "65ee8bcfd46088f34df1c2b500926d141f92e7d35a8454aa5dcf6fad8b0b9241",
+           "toys": 4096, "kernels": {"k_fold1": 1071768923, "k_adj": 1756752076}}
 
 
 def sources_sha256():
