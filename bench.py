@@ -39,19 +39,60 @@ FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
 # kernel sources they were taken on: any change to those sources reports traffic as null.
 # Source: profiles/hbm_bytes_k_fold1_k_adj_borexino_4096toys.md.
-TRAFFIC = {"sources_sha256": "65ee8bcfd46088f34df1c2b500926d141f92e7d35a8454aa5dcf6fad8b0b9241",
+TRAFFIC = {"sources_sha256": "36aa6cccefecae825eaa8e83df49fa181a6a571bae53e53d3f64a4fd462e8f0e",
            "toys": 4096, "kernels": {"k_fold1": 1071768923, "k_adj": 1756752076}}
 
 
+def strip_c_comments(text):
+    """C/C++ source without its // and /* */ comments (string and character literals kept),
+    with every run of whitespace outside literals reduced to one newline (if it held one) or
+    one space, so that edits to comments alone leave it unchanged."""
+    out, i, n = [], 0, len(text)
+    ws = ""  # pending whitespace outside literals
+
+    def flush():
+        nonlocal ws
+        if ws:
+            out.append("\n" if "\n" in ws else " ")
+            ws = ""
+
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            flush()
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            ws += " "
+        elif c.isspace():
+            ws += c
+            i += 1
+        else:
+            flush()
+            out.append(c)
+            i += 1
+    return "".join(out).strip()
+
+
 def sources_sha256():
+    """sha256 of the kernel sources (paper_1812_05686_amd/csrc: .hip, .h, .cpp) with comments
+    removed: the key under which HBM traffic measured for a build is reused."""
     import hashlib
     d = os.path.join(ROOT, "paper_1812_05686_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
         if name.endswith((".hip", ".h", ".cpp")):
             h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+            with open(os.path.join(d, name), encoding="utf-8") as f:
+                h.update(strip_c_comments(f.read()).encode())
     return h.hexdigest()
 
 

@@ -740,9 +740,10 @@ hipError_t launch_bins1(const BatchView &v, double *mu_out, const uint8_t *activ
 // Per-cell sums over window bins of Gr = G_j r_ji times {1, t1, t2}:
 //  gamma:    t1 = ln x_j, t2 = x_j (shifted by ln m and m in k_cellgrad)
 //  gaussian: t1 = z_ji, t2 = z_ji^2 with z = (x - m)/s
-// Wave w of the workgroup takes the bins b0 + w, b0 + w + kWaves, ... of
-// [b0, b1); a gamma cell's exponent is formed per kABlock block about the
-// block's reference point (see block_ref).
+// When NW waves share an item, wave w takes the bins b0 + w, b0 + w + NW, ...
+// of [b0, b1); a wave with an item of its own (NW = 1) takes them all.  A
+// gamma cell's exponent is formed per kABlock block about the block's
+// reference point (see block_ref).
 // Reference exponents E(x_r) of a lane's gamma cell for the bin blocks
 // [qa, qb) (at most kRefBlocks), formed once per cell and block: wave w takes
 // the blocks qa + w, qa + w + NW, ... of the NW waves and the workgroup shares
@@ -923,9 +924,9 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
   }
 }
 
-// NW waves of a workgroup share one item (interleaving its bins), or, for
-// NW = 1, each of the kWaves waves takes an item of its own and walks all of
-// its bins (no LDS and no barrier).
+// NW = kWaves waves of a workgroup share one item (interleaving its bins), or,
+// for NW = 1, each of the kAdjGroupWaves waves takes an item of its own and
+// walks all of its bins (no LDS and no barrier).
 template <bool PS, int NW>
 __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj(const AdjItem *__restrict__ items, int n_items,
                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
