@@ -322,6 +322,24 @@ def main():
                     "max_iters": int(it.max()), "graph_launches": int(len(act)),
                     "ms_until_90pct_done": round(float(tms[np.argmax(act <= 0.1 * len(toys))]), 2) if len(act) else None}
         log(f"bench: toy fits {toy_fits}")
+        # the same toys fitted one at a time by the host BFGS over single-model evaluations,
+        # with central-difference gradients (the plain path) and with the adjoint
+        n_one = 16
+        models = [gs.Model(t) for t in toys[:n_one]]
+        models[0].fit(toys[0].theta0, base.fd_scale, free=toys[0].free_mask(), hesse=False)  # warm
+        bnll = r["nll"].cpu().numpy()
+        one = {"toys": n_one}
+        for name, fd in (("adjoint", False), ("finite_diff", True)):
+            ta = time.perf_counter()
+            res = [mdl.fit(t.theta0, base.fd_scale, use_fd=fd, free=t.free_mask(), hesse=False)
+                   for mdl, t in zip(models, toys[:n_one])]
+            el = time.perf_counter() - ta
+            one[name] = {"fits_per_s": round(n_one / el, 2), "seconds": round(el, 3),
+                         "converged": int(sum(bool(q["ok"]) for q in res)),
+                         "max_rel_dnll_vs_batched": float(max(abs(q["nll"] - bnll[i]) / abs(bnll[i])
+                                                              for i, q in enumerate(res)))}
+        toy_fits["one_at_a_time_host"] = one
+        log(f"bench: toy fits one at a time {one}")
 
     fits = None
     if not args.no_fits:
