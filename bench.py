@@ -175,6 +175,28 @@ def mixed_batch(gs, gsgen, torch, n_toys, steps, warmup, with_oracle):
     out["fits_per_s"] = round(len(toys) / el, 1)
     out["fits_seconds"] = round(el, 3)
     out["fits_converged"] = int(np.sum(stt & 32 != 0))
+    # each class of the mix as a batch of its own (same toys): batched evaluations per second
+    per_class = {}
+    for c in sorted(set(classes)):
+        idx = [t for t in range(len(toys)) if classes[t] == c]
+        sub = [toys[t] for t in idx]
+        b_c = gs.Batch(sub)
+        th_c = theta[idx, : b_c.stride].contiguous()
+        n_c = torch.empty(len(sub), dtype=torch.float64, device="cuda")
+        g_c = torch.empty(len(sub), b_c.stride, dtype=torch.float64, device="cuda")
+        s_c = torch.empty(len(sub), dtype=torch.int32, device="cuda")
+        for _ in range(warmup):
+            b_c.nll_grad(th_c, n_c, g_c, s_c)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(steps):
+            b_c.nll_grad(th_c, n_c, g_c, s_c)
+        torch.cuda.synchronize()
+        el_c = time.perf_counter() - ta
+        per_class[c] = {"toys": len(sub), "evals_per_s": round(len(sub) * steps / el_c, 1),
+                        "ms_per_step": round(el_c * 1e3 / steps, 3), "status_nonzero": int((s_c != 0).sum().item())}
+        del b_c
+    out["per_class"] = per_class
     if with_oracle:
         import oracle
         oracle.build(force=False)
