@@ -387,8 +387,13 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   if (active && !active[it.toy]) return;
   const ToyDev &T = toys[it.toy];
   if (T.two_d) return;
-  if (threadIdx.x == 0) sclamp = 0;  // first read after the barriers of group_list or staging
   const ShapeDev &Sh = shapes[T.shape];
+  // A gamma tile whose first bin lies at x <= 0 always takes the clamped
+  // exponential: such a bin's offsets stand in for ln x = 0, so the exponent
+  // there is not the concave function the end-bin check relies on.  The flag
+  // is first read after the barriers of group_list or staging.
+  if (threadIdx.x == 0)
+    sclamp = Sh.family == kGammaPE && !(Sh.bins[(size_t)(T.lo + it.bin0) * kBinLen] > 0.0) ? 1 : 0;
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int kHalf = kFoldTile1 / 2;
   const bool gamma = Sh.family == kGammaPE;
@@ -641,11 +646,16 @@ __device__ __forceinline__ const double *block_ref(const ShapeDev &Sh, const Toy
 }
 
 // Offsets (u, v) of window bin b (shape bin record bn) from its block's
-// reference; the block's first bin also writes the block's bref row.
+// reference; the block's first bin also writes the block's bref row.  A bin
+// at x <= 0 (outside the gamma support, zero seed) gets v = 1e300: with
+// B = -1/th < 0 its exponent is far below -1000, so the clamped exponential
+// gives exactly 0 and the zero seed adds exactly zero (an exponent from the
+// ln x = 0 stand-in alone can overflow, and 0 * inf is NaN).
 __device__ __forceinline__ void block_offsets(const ShapeDev &Sh, const ToyDev &T, int b, const double *bn, double &u,
                                               double &v, double *__restrict__ bref) {
   const double *r = block_ref(Sh, T, b / kABlock);
   rel_offsets(kGammaPE, bn[0], bn[2], bn[3], r[0], r[2], r[3], u, v);
+  if (!(bn[0] > 0.0)) v = 1e300;
   if (b % kABlock == 0) {
     double *o = bref + (T.bref_off + b / kABlock) * 4;
     o[0] = r[0];
@@ -762,8 +772,9 @@ __device__ __forceinline__ void stage_refs(const double *__restrict__ rc, const 
 
 // A lane's gamma cell against the bins b, b + NW, ... of [b, hi) within one
 // kABlock block (Eref formed about the block's reference point).  A zero seed
-// (also every bin outside the gamma support, x <= 0, whose offsets are
-// finite) adds exactly zero: no test per bin.
+// adds exactly zero, so there is no test per bin; a bin outside the gamma
+// support (x <= 0) has a zero seed and offsets whose exponent underflows (see
+// block_offsets), and a block holding one takes the clamped exponential.
 template <bool CLAMP, int NW>
 __device__ __forceinline__ void adj_block(const double *__restrict__ BR, int b, int hi, double A, double B, double Eref,
                                           const ExpK &ec, double &A0, double &A1, double &A2) {
@@ -788,11 +799,14 @@ __device__ __forceinline__ void adj_block(const double *__restrict__ BR, int b, 
   }
 }
 
-// Whether any lane's exponent may leave [kExpNoClampMin, inf) on the bins
-// [lo, hi) of a block (wave-uniform): checked at the two end bins.
+// Whether any lane's gamma exponent may leave [kExpNoClampMin, inf) on the
+// bins [lo, hi) of a block (wave-uniform): checked at the two end bins.  A
+// block starting at x <= 0 always needs the clamp: offsets there stand in for
+// ln x = 0, so the exponent at that end is not the concave function.
 __device__ __forceinline__ bool block_needs_clamp(const double *__restrict__ BR, int lo, int hi, double A, double B,
                                                   double Eref) {
   const double *pl = BR + (size_t)lo * kBinRecLen, *ph = BR + (size_t)(hi - 1) * kBinRecLen;
+  if (!(pl[0] > 0.0)) return true;
   return __ballot(!exp_args_bounded(A, B, Eref, pl[6], pl[7], ph[6], ph[7])) != 0ull;
 }
 
@@ -870,8 +884,9 @@ __device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const 
           const double *r = BF + (size_t)q * 4;
           Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
         }
-        // a bin outside the gamma support (x <= 0) has H = 0 and finite offsets,
-        // so it adds exactly zero: no test per bin
+        // a bin outside the gamma support (x <= 0) has H = 0 and offsets whose
+        // exponent underflows (see block_offsets), so it adds exactly zero: no
+        // test per bin
         for (; b + NW < hi; b += 2 * NW) {
           const double *br = BR + (size_t)b * kBinRecLen, *br2 = br + NW * kBinRecLen;
           const double *h = HR + (size_t)b * S, *h2 = h + NW * S;

@@ -228,6 +228,39 @@ def test_sharp_gamma_response_exponent_range(gs, orc):
     assert np.all(np.isfinite(g))
 
 
+def test_sharp_gamma_with_bins_at_negative_x(gs, orc):
+    """The sharp gamma response of the test above, with one more reco bin, [-2000, 0) pe, below
+    the others.  That bin's offsets stand in for ln x = 0, so its exponent is no end point of
+    the concave function: a tile or block starting there must take the clamped exponential,
+    or cells peaking at the top of the first tile (exponent ~ -5e10 at x = 18 pe) would come
+    out as garbage.  Same bar as the test above; the bin at x < 0 holds nothing on both sides."""
+    base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
+    th = base.theta_true.copy()
+    th[base.n_species:] = (1200.0, 1e-12, 0.01, 0.0, 0.0)
+    edges = np.concatenate([[-2000.0], base.reco_edges])
+    counts = np.concatenate([np.zeros((base.counts.shape[0], 1, base.counts.shape[2])), base.counts], axis=1)
+    m = base.replace(reco_edges=edges, counts=counts, win_lo=0, win_hi=len(edges) - 1,
+                     theta_true=th, pull_centre=th.copy(), pull_sigma=np.zeros(len(th)))
+    m = m.replace(counts=np.random.default_rng(11).poisson(orc.Oracle(m).expected(th)).astype(float))
+    o = orc.Oracle(m)
+    x = 0.5 * (m.reco_edges[1:] + m.reco_edges[:-1])
+    xp = x[x > 0]
+    tol = 3.0 * 2.0 ** -53 * (xp.max() / 0.01) ** 2 * np.log(xp.max() / xp.min())
+    model = gs.Model(m)
+    ref = o.expected(th)[:, m.win_lo:m.win_hi, :]
+    mu = model.expected(th).reshape(ref.shape)
+    assert np.all(np.isfinite(mu))
+    assert ref[:, 0, :].max() == 0.0 and mu[:, 0, :].max() == 0.0
+    big = ref >= 1e-3
+    assert big.sum() >= 30
+    assert np.max(np.abs(mu - ref)[big] / ref[big]) <= tol
+    v, g, st = model.nll_grad(th)
+    ov, og, ost = o.nll_grad(th)
+    assert st == ost == 0
+    assert abs(v - ov) / abs(ov) <= tol
+    assert np.all(np.isfinite(g))
+
+
 def test_unrepresentable_seed_is_domain(gs, orc):
     """n > 0 in a bin whose mu is so small that 1 - n/mu overflows: both sides report DOMAIN."""
     base = gsgen.small_gamma_model(n_true=100, n_reco=40, seed=8)
