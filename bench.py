@@ -39,8 +39,8 @@ FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
 # kernel sources they were taken on: any change to those sources reports traffic as null.
 # Source: profiles/hbm_bytes_k_fold1_k_adj_borexino_4096toys.md.
-TRAFFIC = {"sources_sha256": "36aa6cccefecae825eaa8e83df49fa181a6a571bae53e53d3f64a4fd462e8f0e",
-           "toys": 4096, "kernels": {"k_fold1": 1071768923, "k_adj": 1756752076}}
+TRAFFIC = {"sources_sha256": "a29e2632daf14d6c3656bd1017f632e34e1cea0ca6fdc33810aee63fbbb61525",
+           "toys": 4096, "kernels": {"k_fold1": 1071554480, "k_adj": 1756266072}}
 
 
 def strip_c_comments(text):
