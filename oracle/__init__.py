@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
-ST_DOMAIN, ST_NONFINITE, ST_LS_FAIL, ST_MAXITER, ST_BFGS_RESET = 1, 2, 4, 8, 16
+ST_DOMAIN, ST_NONFINITE, ST_LS_FAIL, ST_MAXITER, ST_BFGS_RESET, ST_GRAD_RANGE = 1, 2, 4, 8, 16, 64
 
 
 def build(force: bool = True, src: str | None = None, out: str | None = None) -> str:

@@ -13,8 +13,11 @@
  *      sign fixed, ln n! dropped, and the factor 1/2 so that a change of 0.5
  *      in -ln L is one standard deviation).
  *  R2  n = 0 contributes mu (0 ln 0 = 0); mu < 0, or mu = 0 with n > 0, is a
- *      domain error: -ln L = +inf and status DOMAIN.  So is n > 0 with mu so
- *      small that 1 - n/mu overflows FP64 (mu < n/DBL_MAX).
+ *      domain error: -ln L = +inf and status DOMAIN.  Every mu > 0 gives the
+ *      finite Eq.4 term, however small mu is.  Where n > 0 and the FP64 seed
+ *      1 - n/mu of the gradient overflows (n/mu above DBL_MAX, decided in FP64
+ *      from the bin's FP64 mu) the gradient has no FP64 value: status
+ *      GRAD_RANGE, gradient NaN, -ln L still finite.
  *  R3  reco bin content = bin width x response at the bin midpoint (the
  *      response evaluated on the visible x true energy mesh, section 2.5).
  *  R4  true spectra are histograms on a uniform cell-centred grid with rows
@@ -388,13 +391,13 @@ int32_t orc_expected(const orc_model *M, const double *theta, double *mu) {
 }
 
 /* ------------------------------------------------------ -ln L (Eq.4) ----- */
-/* R1/R2 per-bin term. Returns 0 on a domain error. */
-static int poisson_term(ld mu, ld n, ld *term, ld *g) {
-  /* R2: the adjoint seed 1 - n/mu must be finite in FP64 */
-  if (mu > 0 && n > 0 && !isfinite((double)n / (double)mu)) return 0;
+/* R1/R2 per-bin term.  Returns 0 on a domain error; *range is set when n > 0
+ * and the FP64 value of n/mu (mu is the bin's FP64 expectation) overflows. */
+static int poisson_term(ld mu, ld n, ld *term, ld *g, int *range) {
   if (mu > 0) {
     *term = n > 0 ? mu - n * logl(mu) : mu;
     *g = 1 - n / mu;
+    if (n > 0 && !isfinite((double)n / (double)mu)) *range = 1;
     return 1;
   }
   if (mu == 0 && n == 0) {
@@ -425,6 +428,7 @@ double orc_nll_grad(const orc_model *M, const double *theta, double *grad, uint3
     ok = psd_l(M, theta + S + nr, P, dP);
   }
   ld nll = 0;
+  int range = 0;
   ld *gr = calloc((size_t)Pn, sizeof(ld));
   for (int d = 0; d < M->n_datasets && ok; d++) {
     ld eps = M->exposure[d];
@@ -437,7 +441,7 @@ double orc_nll_grad(const orc_model *M, const double *theta, double *grad, uint3
         mu = (double)(eps * mu);
         ld n = M->counts[((size_t)d * J + j) * K + k];
         ld term, g;
-        if (!poisson_term(mu, n, &term, &g)) {
+        if (!poisson_term(mu, n, &term, &g, &range)) {
           ok = 0;
           break;
         }
@@ -462,8 +466,9 @@ double orc_nll_grad(const orc_model *M, const double *theta, double *grad, uint3
         gr[p] += z / M->pull_sigma[p];
       }
   if (!ok) *st = ORC_ST_DOMAIN;
+  else if (range) *st = ORC_ST_GRAD_RANGE;
   if (grad)
-    for (int p = 0; p < Pn; p++) grad[p] = ok ? (double)gr[p] : NAN;
+    for (int p = 0; p < Pn; p++) grad[p] = ok && !range ? (double)gr[p] : NAN;
   free(gr);
   free(F);
   free(dF);
@@ -566,7 +571,9 @@ int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o,
   for (int q = 0; q < n; q++) x[q] = theta0[c.idx[q]];
   uint32_t st = 0, est;
   double f = f_eval(&c, x, g, &est);
-  st |= est & ORC_ST_NONFINITE;
+  st |= est & (ORC_ST_NONFINITE | ORC_ST_GRAD_RANGE);
+  /* a start without an FP64 gradient (R2) cannot begin a quasi-Newton step */
+  const int no_grad = (est & ORC_ST_GRAD_RANGE) != 0;
 #define RESET_H()                                                            \
   for (int i = 0; i < n; i++)                                                \
     for (int j = 0; j < n; j++) H[i * n + j] = i == j ? o->scale[c.idx[i]] * o->scale[c.idx[i]] : 0;
@@ -574,7 +581,7 @@ int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o,
   int it = 0;
   double edm = INFINITY;
   if (!isfinite(f)) st |= est;
-  while (isfinite(f)) {
+  while (isfinite(f) && !no_grad) {
     edm = 0;
     for (int i = 0; i < n; i++)
       for (int j = 0; j < n; j++) edm += 0.5 * g[i] * H[i * n + j] * g[j];
@@ -603,11 +610,13 @@ int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o,
     for (int ls = 0; ls < 40; ls++) {
       for (int i = 0; i < n; i++) xn[i] = x[i] + alpha * pd[i];
       fn = f_eval(&c, xn, NULL, &est);
-      if (isfinite(fn) && fn <= f + 1e-4 * alpha * slope + 1e-14 * fabs(f)) {
+      /* a trial point whose gradient has no FP64 value (R2) is not taken */
+      const int usable = isfinite(fn) && !(est & ORC_ST_GRAD_RANGE);
+      if (usable && fn <= f + 1e-4 * alpha * slope + 1e-14 * fabs(f)) {
         accepted = 1;
         break;
       }
-      if (isfinite(fn)) {
+      if (usable) {
         double aq = -slope * alpha * alpha / (2 * (fn - f - slope * alpha));
         alpha = fmin(fmax(aq, 0.1 * alpha), 0.5 * alpha);
       } else {
@@ -697,5 +706,5 @@ int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o,
   free(sv);
   free(yv);
   free(Hy);
-  return isfinite(f) && !(st & (ORC_ST_LS_FAIL | ORC_ST_MAXITER));
+  return isfinite(f) && !no_grad && !(st & (ORC_ST_LS_FAIL | ORC_ST_MAXITER));
 }

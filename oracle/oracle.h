@@ -24,7 +24,7 @@ extern "C" {
 
 enum { ORC_GAUSS_E = 0, ORC_GAUSS_PE = 1, ORC_GAMMA_PE = 2 };
 enum { ORC_ST_DOMAIN = 1u, ORC_ST_NONFINITE = 2u, ORC_ST_LS_FAIL = 4u,
-       ORC_ST_MAXITER = 8u, ORC_ST_BFGS_RESET = 16u };
+       ORC_ST_MAXITER = 8u, ORC_ST_BFGS_RESET = 16u, ORC_ST_GRAD_RANGE = 64u };
 
 typedef struct {
   int32_t n_true;            /* true-energy cells, centres e_lo + (i + 1/2) e_step   */

@@ -33,6 +33,8 @@ MUTANTS = {
                           "for (int j = M->win_lo; j <= M->win_hi - 2 && ok; j++)"),
     "digamma_tail_sign": ("return r + logl(x) - 0.5L / x - tail;", "return r + logl(x) - 0.5L / x + tail;"),
     "line_at_grid_energy": ("E = (ld)M->line_energy[line_s];", "E = (ld)M->line_energy[line_s] + 0.5 * M->e_step;"),
+    "tiny_mu_domain": ("if (n > 0 && !isfinite((double)n / (double)mu)) *range = 1;",
+                       "if (n > 0 && !isfinite((double)n / (double)mu)) return 0;"),
     "bfgs_update_sign": ("(rho * rho * yHy + rho) * sv[i] * sv[j]", "(rho * rho * yHy - rho) * sv[i] * sv[j]"),
 }
 

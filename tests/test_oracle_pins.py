@@ -342,6 +342,50 @@ def test_domain_and_status(orc, c0):
     assert orc.Oracle(M).nll(th)[1] == 1
 
 
+def tiny_mu_model(rate):
+    """One line at 500 keV, Gaussian response of 10 keV, bins of 10 keV on [0, 1000), one
+    count in each of the bins at 565 and 575 keV (6.5 and 7.5 sigma from the line): at
+    rate 1e-300 their expectations are ~2.7e-310 and ~2.5e-313, below FP64's normal range."""
+    M = _line_model(GAUSS_E, 500.0, np.array([10.0, 0.0]), np.linspace(0.0, 1000.0, 101), rate=rate)
+    cnt = np.zeros_like(M.counts)
+    cnt[0, 56, 0] = cnt[0, 57, 0] = 1.0
+    return M.replace(counts=cnt)
+
+
+@pytest.mark.parametrize("rate", [1e-300, 1e-290])
+def test_tiny_mu_gives_the_finite_poisson_term(orc, rate):
+    """Eq.4 (reading R2): every mu > 0 contributes mu - n ln mu, however small mu is.  At
+    rate 1e-300 two bins with one count hold mu ~ 1e-310: -ln L is finite and equals the
+    sum written out in 60-digit arithmetic from the oracle's own FP64 expectations (which
+    are themselves checked against scipy's normal density); the FP64 gradient seed 1 - n/mu
+    overflows there, so the status is GRAD_RANGE and the gradient NaN.  At rate 1e-290 the
+    seeds fit FP64 and the rate gradient is the closed form sum_j F_j - sum_j n_j / R (rate
+    linearity)."""
+    M = tiny_mu_model(rate)
+    o = orc.Oracle(M)
+    th = M.theta_true
+    mu = o.expected(th)[0, :, 0]
+    x = np.arange(100) * 10.0 + 5.0
+    ref_mu = rate * 10.0 * stats.norm.pdf(x, 500.0, 10.0)
+    big = ref_mu > 1e-320
+    assert np.max(np.abs(mu[big] - ref_mu[big]) / ref_mu[big]) <= 1e-12
+    mpmath.mp.dps = 60
+    n = M.counts[0, :, 0]
+    ref = mpmath.fsum(mpmath.mpf(float(u)) - (mpmath.mpf(float(k)) * mpmath.log(mpmath.mpf(float(u))) if k else 0)
+                      for u, k in zip(mu, n))
+    v, g, st = o.nll_grad(th)
+    assert np.isfinite(v) and abs(v - float(ref)) <= 1e-15 * abs(float(ref))
+    assert o.nll(th) == (v, st)
+    if rate == 1e-300:
+        assert mu[56] < 1e-308 and mu[57] < 1e-308
+        assert st == orc.ST_GRAD_RANGE and np.all(np.isnan(g))
+        assert 1420 < v < 1440
+    else:
+        assert st == 0
+        F = mu / rate
+        assert g[0] == pytest.approx(F.sum() - n.sum() / rate, rel=1e-12)
+
+
 # ------------------------------------------------------------ gradient -------
 def _richardson(f, th, p, h):
     def d(hh):
