@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the fold likelihood hot path on one MI355X.
 
-Workload: 4096 pseudo-experiments of the Borexino-scale model (12 species: 4 lines, 6
-betas, 2 exponentials; 4000 true cells of 0.75 keV plus 4 lines; 900 reco bins of 1.6 pe;
-gamma response with light yield, Birks quenching and resolution a, b, c; 17 parameters,
-3 pulls), each with its own Poisson data, rates drawn +-20% around nominal and its own fit
-window of 200-900 bins.  One step is one batched -ln L + gradient evaluation of all toys
-(cells, fold, Poisson reduction, adjoint, gradient) with every input already resident in
-device memory; value = toys * steps / wall time.
+Headline workload (value): the large uneven batch of 16384 pseudo-experiments, a seeded mix of
+  A  energy-family models: 3-5 species on 500 true cells, Gaussian response, 100-200 bins;
+  B  Borexino-like models: 6-16 species on 1000-4000 true cells, gamma response with light
+     yield, Birks quenching and resolution (a, b, c), 200-900 bins;
+  C  the pulse-shape model: 12 species, 900 energy x 50 pulse-shape bins x 1-3 datasets.
+One step is one batched -ln L + gradient evaluation of every toy (cells, fold, Poisson
+reduction, adjoint, gradient), inputs resident in device memory; value = toys x steps / wall
+time, after the batch scheduler's autotuner has picked the work layout.
 
-Also reported: toy fits per second (device BFGS over the same toys in captured graphs),
-the dominant kernel against the FP64 vector roofline (timed live with HIP events on its
-stream), single-evaluation latency, one Borexino-scale fit with the adjoint gradient
-versus central finite differences, and the CPU oracle on the host cores (sampled).
+Also reported: the dominant kernel of that step against the FP64 vector roofline (timed live
+with HIP events on its stream; algorithmic flops from the banded-mesh pair counts), toy fits per
+second of the mix, each class as a batch of its own, the 4096-toy Borexino-scale toy study
+(evaluations, kernels, fits, fits one at a time by the host driver), the single 1-D fit, the
+single Borexino-scale fit and the pulse-shape model with adjoint versus central finite-difference
+gradients, and the CPU oracle on the host cores (a bounded per-class sample of the mix).
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import threading
 import time
@@ -28,19 +32,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NLL+grad evals/sec and toy fits/sec at |dNLL|/NLL<=1e-11 (adjoint vs finite-diff)"
 FP64_PEAK_TFLOPS = 78.6
-# FP64 operations per evaluated (bin, cell) pair of the gamma-response kernels, counted from
-# their gfx950 instruction mix with an FMA as 2: the block-relative exponent (2 FMA), the
-# exponential (MAX, 11 FMA, ADD, LDEXP) and the accumulation (1 FMA in the fold, 3 in the
-# adjoint): 31 and 35.  The double-double reference exponent formed once per cell and bin
-# block (tile) is set-up work and is not counted.
-FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
-# HBM bytes per launch on the default workload (4096 toys), from two rocprofv3 --pmc runs
+# Algorithmic FP64 work per banded-mesh pair (a window bin inside a cell's support), for one
+# direction: 26.5 operations, half of the 53 per pair for the forward fold plus the adjoint
+# with an exponential counted at ~20 (the cost model of the analytic fit, Eq.2, priced per
+# pair).  The per-species kernels of the pulse-shape toys add one multiply-add (2 operations)
+# per species the pair's cell carries: the weighting in the fold, the seed contraction in the
+# adjoint.
+ALGO_FLOPS_PER_PAIR = 26.5
+# The same, counted from the kernels' own gfx950 instruction mix with an FMA as 2 (fold: tile-
+# relative exponent 2 FMA, exponential 11 FMA + MAX + SUB + LDEXP, accumulation 1 FMA; adjoint:
+# 3 accumulating FMAs): context only.
+INSTR_FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
+KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj<false>", "folds": "k_fold_s", "adj_s": "k_adj<true>"}
+# HBM bytes per launch on the 4096-toy Borexino-scale batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
 # kernel sources they were taken on: any change to those sources reports traffic as null.
-# Source: profiles/hbm_bytes_k_fold1_k_adj_borexino_4096toys.md.
 TRAFFIC = {"sources_sha256": "a29e2632daf14d6c3656bd1017f632e34e1cea0ca6fdc33810aee63fbbb61525",
-           "toys": 4096, "kernels": {"k_fold1": 1071554480, "k_adj": 1756266072}}
+           "workload": "c3", "kernels": {"k_fold1": 1071554480, "k_adj<false>": 1756266072}}
 
 
 def strip_c_comments(text):
@@ -100,119 +109,280 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(toys, seconds, threads):
-    """Oracle -ln L + gradient on the host, one toy per thread, for about `seconds`."""
-    import oracle
-    oracle.build(force=False)
-    orcs = [oracle.Oracle(t) for t in toys[:threads]]
-    counts = [0] * threads
-    out = [None] * threads
-    stop = time.perf_counter() + seconds
-
-    def work(i):
-        while True:
-            out[i] = orcs[i].nll_grad(toys[i].theta_true)
-            counts[i] += 1
-            if time.perf_counter() >= stop:
-                break
-
-    t0 = time.perf_counter()
-    th = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
-    el = time.perf_counter() - t0
-    return sum(counts) / el, sum(counts), el, out
+def host_info():
+    """Host CPU as the oracle baseline ran on: logical CPUs, the ones this process may use,
+    and the model / sockets lscpu reports."""
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[k.strip()] = v.strip()
+    except Exception as e:  # lscpu missing: keep the counts
+        info["lscpu"] = repr(e)
+    return info
 
 
-def mixed_batch(gs, gsgen, torch, n_toys, steps, warmup, with_oracle):
-    """The large uneven batch: energy-family, Borexino-like and pulse-shape toys together.
-    Batched -ln L + gradient evaluations per second, toy fits per second, and the oracle's
-    error on two toys of every class."""
-    t0 = time.perf_counter()
-    toys = gsgen.config4(n_toys)
-    gen_s = time.perf_counter() - t0
-    batch = gs.Batch(toys)
-    th = np.zeros((len(toys), batch.stride))
-    for t, m in enumerate(toys):
-        th[t, : m.n_params] = m.theta_true
-    theta = torch.tensor(th, dtype=torch.float64, device="cuda")
-    nll = torch.empty(len(toys), dtype=torch.float64, device="cuda")
-    grad = torch.empty(len(toys), batch.stride, dtype=torch.float64, device="cuda")
-    st = torch.empty(len(toys), dtype=torch.int32, device="cuda")
+def kernel_rooflines(kt, counts):
+    """Achieved TFLOP/s and fraction of the FP64 vector peak of the pair kernels, from their
+    average launch time (HIP events) and the algorithmic work of one launch: banded pairs x
+    26.5 (+ 2 per species of the pair's cell for the per-species kernels)."""
+    fold_p, adj_p, full, band, band2, band2s = counts
+    band1 = band - band2
+    work = {"fold": (band1, band1 * ALGO_FLOPS_PER_PAIR), "adj": (band1, band1 * ALGO_FLOPS_PER_PAIR),
+            "folds": (band2, band2 * ALGO_FLOPS_PER_PAIR + 2.0 * band2s),
+            "adj_s": (band2, band2 * ALGO_FLOPS_PER_PAIR + 2.0 * band2s)}
+    out = {}
+    for k, (pairs, flops) in work.items():
+        ms, n = kt.get(k, (0.0, 0))
+        if not n or pairs <= 0:
+            continue
+        avg = ms / n
+        tf = flops / (avg * 1e-3) / 1e12
+        out[k] = {"kernel": KERNEL_NAMES[k], "avg_launch_ms": round(avg, 4), "pairs_per_launch": pairs,
+                  "flops_per_launch": flops, "achieved_tflops": round(tf, 3),
+                  "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
+    return out
+
+
+def timed_steps(batch, theta, nll, grad, st, steps, warmup, torch):
     for _ in range(warmup):
         batch.nll_grad(theta, nll, grad, st)
     torch.cuda.synchronize()
-    ta = time.perf_counter()
+    t0 = time.perf_counter()
     for _ in range(steps):
         batch.nll_grad(theta, nll, grad, st)
     torch.cuda.synchronize()
-    el = time.perf_counter() - ta
+    return time.perf_counter() - t0
+
+
+def profiled_kernels(batch, theta, nll, grad, st, reps, torch):
     batch.set_profiling(True)
     batch.kernel_times(reset=True)
-    for _ in range(max(1, steps // 4)):
+    for _ in range(reps):
         batch.nll_grad(theta, nll, grad, st)
     kt = batch.kernel_times(reset=True)
     batch.set_profiling(False)
-    classes = [m.name.split("/")[1] for m in toys]
-    out = {"toys": len(toys), "classes": {c: classes.count(c) for c in sorted(set(classes))},
-           "evals_per_s": round(len(toys) * steps / el, 1), "ms_per_step": round(el * 1e3 / steps, 3),
-           "generator_s": round(gen_s, 1), "status_nonzero": int((st != 0).sum().item()),
-           "kernel_ms": {k: round(v[0] / v[1], 3) for k, v in kt.items() if v[1]}}
-    th0 = np.zeros_like(th)
+    torch.cuda.synchronize()
+    return kt
+
+
+def buffers(n, stride, torch):
+    return (torch.empty(n, dtype=torch.float64, device="cuda"),
+            torch.empty(n, stride, dtype=torch.float64, device="cuda"),
+            torch.empty(n, dtype=torch.int32, device="cuda"))
+
+
+def theta_of(toys, stride, which="theta_true"):
+    th = np.zeros((len(toys), stride))
     for t, m in enumerate(toys):
-        th0[t, : m.n_params] = m.theta0
-    th0 = torch.tensor(th0, dtype=torch.float64, device="cuda")
-    free, scales = batch.free_masks(toys), batch.scales(toys)
-    batch.fit(th0, scales, free=free)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    r = batch.fit(th0, scales, free=free)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - ta
-    stt = r["status"].cpu().numpy()
-    out["fits_per_s"] = round(len(toys) / el, 1)
-    out["fits_seconds"] = round(el, 3)
-    out["fits_converged"] = int(np.sum(stt & 32 != 0))
-    # each class of the mix as a batch of its own (same toys): batched evaluations per second
+        th[t, : m.n_params] = getattr(m, which)
+    return th
+
+
+def cpu_baseline_mix(toys, classes, gpu_nll, gpu_grad, seconds, threads):
+    """The oracle's -ln L + gradient on the host, one toy per thread, per class of the mix for a
+    bounded time each; the mix's rate is its toy count over the time the measured per-class
+    rates need for one evaluation of every toy.  The evaluated toys double as a parity sample
+    against the GPU values at the same points."""
+    import oracle
+    oracle.build(force=False)
+    per_class, parity = {}, {"toys": 0, "max_rel_dnll": 0.0, "max_grad_err": 0.0}
+    share = {"A": 0.15, "B": 0.35, "C": 0.5}
+    for c in sorted(set(classes)):
+        idx = [t for t in range(len(toys)) if classes[t] == c][:threads]
+        orcs = [oracle.Oracle(toys[t]) for t in idx]
+        counts = [0] * len(idx)
+        first = [None] * len(idx)
+        stop = time.perf_counter() + seconds * share.get(c, 0.3)
+
+        def work(i):
+            while True:
+                r = orcs[i].nll_grad(toys[idx[i]].theta_true)
+                if first[i] is None:
+                    first[i] = r
+                counts[i] += 1
+                if time.perf_counter() >= stop:
+                    break
+
+        t0 = time.perf_counter()
+        th = [threading.Thread(target=work, args=(i,)) for i in range(len(idx))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        el = time.perf_counter() - t0
+        per_class[c] = {"evals_per_s": round(sum(counts) / el, 3), "evals": sum(counts), "seconds": round(el, 2),
+                        "threads": len(idx)}
+        for i, t in enumerate(idx):
+            m = toys[t]
+            ov, og, _ = first[i]
+            parity["toys"] += 1
+            parity["max_rel_dnll"] = max(parity["max_rel_dnll"], abs(gpu_nll[t] - ov) / abs(ov))
+            parity["max_grad_err"] = max(parity["max_grad_err"], float(np.max(
+                np.abs(gpu_grad[t, : m.n_params] - og) * m.fd_scale / np.maximum(np.abs(og) * m.fd_scale, 1.0))))
+    n_of = {c: classes.count(c) for c in per_class}
+    t_mix = sum(n_of[c] / per_class[c]["evals_per_s"] for c in per_class)
+    parity["pass"] = bool(parity["max_rel_dnll"] <= 1e-11 and parity["max_grad_err"] <= 1e-8)
+    return len(toys) / t_mix, per_class, parity
+
+
+def one_thread_rate(toy, seconds):
+    import oracle
+    o = oracle.Oracle(toy)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.nll_grad(toy.theta_true)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    return n / (time.perf_counter() - t0), n
+
+
+def mixed_batch(gs, gsgen, torch, args):
+    """The headline: the 16384-toy uneven mix as one batch."""
+    t0 = time.perf_counter()
+    toys = gsgen.config4(args.mixed_toys)
+    gen_s = time.perf_counter() - t0
+    classes = [m.name.split("/")[1] for m in toys]
+    batch = gs.Batch(toys)
+    theta = torch.tensor(theta_of(toys, batch.stride), dtype=torch.float64, device="cuda")
+    nll, grad, st = buffers(len(toys), batch.stride, torch)
+    tune = batch.autotune(theta, reps=2)
+    log(f"bench: mix autotune {tune}")
+    el = timed_steps(batch, theta, nll, grad, st, args.steps, args.warmup, torch)
+    kt = profiled_kernels(batch, theta, nll, grad, st, max(2, args.steps // 4), torch)
+    counts = batch.mesh_counts()
+    roof = kernel_rooflines(kt, counts)
+    out = {"toys": len(toys), "classes": {c: classes.count(c) for c in sorted(set(classes))},
+           "evals_per_s": len(toys) * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
+           "generator_s": round(gen_s, 1), "status_nonzero": int((st != 0).sum().item()), "autotune": tune,
+           "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in kt.items() if v[1]}, "kernels": roof,
+           "mesh": dict(zip(("fold_pairs", "adj_pairs", "full_mesh", "banded", "banded_2d", "banded_2d_species"),
+                            counts)),
+           "fixed_params_per_toy": round(float(np.mean([int((~m.free).sum()) if m.free is not None else 0
+                                                        for m in toys])), 2)}
+    gpu_nll, gpu_grad = nll.cpu().numpy(), grad.cpu().numpy()
+    if not args.no_fits:
+        th0 = torch.tensor(theta_of(toys, batch.stride, "theta0"), dtype=torch.float64, device="cuda")
+        free, scales = batch.free_masks(toys), batch.scales(toys)
+        batch.fit(th0, scales, free=free)  # warm: builds the captured graph
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = batch.fit(th0, scales, free=free)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ta
+        stt = r["status"].cpu().numpy()
+        out["fits"] = {"fits_per_s": round(len(toys) / el, 1), "seconds": round(el, 3),
+                       "converged": int(np.sum(stt & 32 != 0)),
+                       "per_class_converged": {c: int(sum(1 for t in range(len(toys)) if classes[t] == c and stt[t] & 32))
+                                               for c in out["classes"]}}
+    # each class of the mix as a batch of its own (same toys)
     per_class = {}
     for c in sorted(set(classes)):
         idx = [t for t in range(len(toys)) if classes[t] == c]
         sub = [toys[t] for t in idx]
         b_c = gs.Batch(sub)
         th_c = theta[idx, : b_c.stride].contiguous()
-        n_c = torch.empty(len(sub), dtype=torch.float64, device="cuda")
-        g_c = torch.empty(len(sub), b_c.stride, dtype=torch.float64, device="cuda")
-        s_c = torch.empty(len(sub), dtype=torch.int32, device="cuda")
-        for _ in range(warmup):
-            b_c.nll_grad(th_c, n_c, g_c, s_c)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(steps):
-            b_c.nll_grad(th_c, n_c, g_c, s_c)
-        torch.cuda.synchronize()
-        el_c = time.perf_counter() - ta
-        per_class[c] = {"toys": len(sub), "evals_per_s": round(len(sub) * steps / el_c, 1),
-                        "ms_per_step": round(el_c * 1e3 / steps, 3), "status_nonzero": int((s_c != 0).sum().item())}
+        n_c, g_c, s_c = buffers(len(sub), b_c.stride, torch)
+        el_c = timed_steps(b_c, th_c, n_c, g_c, s_c, args.steps, args.warmup, torch)
+        kt_c = profiled_kernels(b_c, th_c, n_c, g_c, s_c, 2, torch)
+        per_class[c] = {"toys": len(sub), "evals_per_s": round(len(sub) * args.steps / el_c, 1),
+                        "ms_per_step": round(el_c * 1e3 / args.steps, 3),
+                        "status_nonzero": int((s_c != 0).sum().item()),
+                        "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in kt_c.items() if v[1]},
+                        "kernels": kernel_rooflines(kt_c, b_c.mesh_counts())}
         del b_c
     out["per_class"] = per_class
-    if with_oracle:
-        import oracle
-        oracle.build(force=False)
-        gn, gg = nll.cpu().numpy(), grad.cpu().numpy()
-        seen, worst_nll, worst_grad = {}, 0.0, 0.0
-        for t, m in enumerate(toys):
-            c = classes[t]
-            if seen.get(c, 0) >= 2:
-                continue
-            seen[c] = seen.get(c, 0) + 1
-            ov, og, _ = oracle.Oracle(m).nll_grad(m.theta_true)
-            worst_nll = max(worst_nll, abs(gn[t] - ov) / abs(ov))
-            worst_grad = max(worst_grad, float(np.max(np.abs(gg[t, : m.n_params] - og) * m.fd_scale /
-                                                      np.maximum(np.abs(og) * m.fd_scale, 1.0))))
-        out["oracle_sample"] = {"toys": sum(seen.values()), "max_rel_dnll": worst_nll, "max_grad_err": worst_grad,
-                                "pass": bool(worst_nll <= 1e-11 and worst_grad <= 1e-8)}
+    return out, toys, classes, gpu_nll, gpu_grad
+
+
+def toy_study(gs, gsgen, torch, args):
+    """The 4096-toy Borexino-scale study: evaluations, kernels, fits."""
+    base = gsgen.config1()
+    toys = gsgen.config3(args.toys, base=base)
+    batch = gs.Batch(toys)
+    theta = torch.tensor(np.stack([t.theta_true for t in toys]), dtype=torch.float64, device="cuda")
+    nll, grad, st = buffers(len(toys), batch.stride, torch)
+    tune = batch.autotune(theta, reps=3)
+    el = timed_steps(batch, theta, nll, grad, st, args.steps, args.warmup, torch)
+    kt = profiled_kernels(batch, theta, nll, grad, st, args.steps, torch)
+    counts = batch.mesh_counts()
+    roof = kernel_rooflines(kt, counts)
+    for k in ("fold", "adj"):
+        if k in roof:
+            roof[k]["instr_flops_per_pair"] = INSTR_FLOPS_PER_PAIR[k]
+            roof[k]["executed_over_banded"] = round(counts[0 if k == "fold" else 1] / counts[3], 4)
+    traffic = None
+    if TRAFFIC["sources_sha256"] == sources_sha256() and len(toys) == 4096:
+        traffic = TRAFFIC["kernels"]
+    fixed = [int((~t.free).sum()) for t in toys]
+    out = {"toys": len(toys), "evals_per_s": round(len(toys) * args.steps / el, 1),
+           "ms_per_step": round(el * 1e3 / args.steps, 4), "autotune": tune,
+           "mean_window_bins": round(float(np.mean([t.win_hi - t.win_lo for t in toys])), 1),
+           "fixed_params_per_toy": round(float(np.mean(fixed)), 2), "params_per_toy": int(toys[0].n_params),
+           "full_mesh_pairs": counts[2], "banded_pairs": counts[3], "kernels": roof, "hbm_bytes_per_launch": traffic,
+           "status_nonzero": int((st != 0).sum().item())}
+    if args.no_fits:
+        return out
+    th0 = torch.tensor(np.stack([t.theta0 for t in toys]), dtype=torch.float64, device="cuda")
+    free = batch.free_masks(toys)
+    batch.fit(th0, base.fd_scale, free=free)  # warm: builds the captured graph
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = batch.fit(th0, base.fd_scale, free=free)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ta
+    stt, it = r["status"].cpu().numpy(), r["iters"].cpu().numpy()
+    act, tms = batch.fit_trace()
+    out["fits"] = {"fits_per_s": round(len(toys) / el, 2), "seconds": round(el, 4),
+                   "converged": int(np.sum(stt & 32 != 0)), "mean_iters": round(float(it.mean()), 2),
+                   "max_iters": int(it.max()), "graph_launches": int(len(act)),
+                   "ms_until_90pct_done": round(float(tms[np.argmax(act <= 0.1 * len(toys))]), 2) if len(act) else None}
+    # the same toys fitted one at a time by the host driver over single-model evaluations,
+    # with central-difference gradients (the plain path) and with the adjoint
+    n_one = 16
+    models = [gs.Model(t) for t in toys[:n_one]]
+    models[0].fit(toys[0].theta0, base.fd_scale, free=toys[0].free_mask(), hesse=False)  # warm
+    bnll = r["nll"].cpu().numpy()
+    one = {"toys": n_one}
+    for name, fd in (("adjoint", False), ("finite_diff", True)):
+        ta = time.perf_counter()
+        res = [mdl.fit(t.theta0, base.fd_scale, use_fd=fd, free=t.free_mask(), hesse=False)
+               for mdl, t in zip(models, toys[:n_one])]
+        el = time.perf_counter() - ta
+        one[name] = {"fits_per_s": round(n_one / el, 2), "seconds": round(el, 3),
+                     "converged": int(sum(bool(q["ok"]) for q in res)),
+                     "max_rel_dnll_vs_batched": float(max(abs(q["nll"] - bnll[i]) / abs(bnll[i])
+                                                          for i, q in enumerate(res)))}
+    out["fits_one_at_a_time_host"] = one
+    return out
+
+
+def single_model(gs, torch, m, reps=200, fits=True):
+    """One model: device-resident evaluation latency (a batch of one), per-kernel times, and
+    one fit with the adjoint versus central finite differences (host driver)."""
+    b = gs.Batch([m])
+    th = torch.tensor(theta_of([m], b.stride), dtype=torch.float64, device="cuda")
+    n1, g1, s1 = buffers(1, b.stride, torch)
+    el = timed_steps(b, th, n1, g1, s1, reps, 10, torch)
+    kt = profiled_kernels(b, th, n1, g1, s1, 20, torch)
+    out = {"us_per_eval": round(el * 1e6 / reps, 2), "evals_per_s": round(reps / el, 1),
+           "kernel_us": {k: round(v[0] * 1e3 / v[1], 2) for k, v in kt.items() if v[1]},
+           "kernels": kernel_rooflines(kt, b.mesh_counts())}
+    del b
+    if fits:
+        model = gs.Model(m)
+        for name, fd in (("adjoint", False), ("finite_diff", True)):
+            model.fit(m.theta0, m.fd_scale, use_fd=fd, hesse=False)  # warm
+            ta = time.perf_counter()
+            r = model.fit(m.theta0, m.fd_scale, use_fd=fd, hesse=False)
+            el = time.perf_counter() - ta
+            out[name] = dict(fits_per_s=round(1.0 / el, 3), seconds=round(el, 5), iters=r["iters"],
+                             n_eval=r["n_eval"], converged=r["ok"], nll=r["nll"])
+        out["speedup_adjoint_over_fd"] = round(out["finite_diff"]["seconds"] / out["adjoint"]["seconds"], 2)
+        model.close()
     return out
 
 
@@ -221,12 +391,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--toys", type=int, default=4096)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--toys", type=int, default=4096, help="pseudo-experiments of the Borexino-scale toy study")
+    ap.add_argument("--mixed-toys", type=int, default=16384, help="toys of the uneven mix (the headline)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fits", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the 16384-toy mixed batch")
-    ap.add_argument("--mixed-toys", type=int, default=16384)
+    ap.add_argument("--no-study", action="store_true", help="skip the 4096-toy study and the single models")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -250,188 +420,63 @@ def main():
     import gsgen
     import paper_1812_05686_amd as gs
 
-    base = gsgen.config1()
-    toys = gsgen.config3(args.toys, base=base)
-    log(f"bench: {len(toys)} pseudo-experiments of the Borexino-scale model, ragged windows")
-    batch = gs.Batch(toys)
-    stride = batch.stride
-    theta = torch.tensor(np.stack([t.theta_true for t in toys]), dtype=torch.float64, device="cuda")
-    nll = torch.empty(len(toys), dtype=torch.float64, device="cuda")
-    grad = torch.empty(len(toys), stride, dtype=torch.float64, device="cuda")
-    st = torch.empty(len(toys), dtype=torch.int32, device="cuda")
-    # the batch scheduler's autotuner picks the work layout the timed steps use
-    tune = batch.autotune(theta, reps=3)
-    log(f"bench: autotune {tune}")
-    for _ in range(args.warmup):
-        batch.nll_grad(theta, nll, grad, st)
-    torch.cuda.synchronize()
-    batch.set_profiling(True)
-    batch.kernel_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.nll_grad(theta, nll, grad, st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = batch.kernel_times(reset=True)
-    batch.set_profiling(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = len(toys) * args.steps / (t1 - t0)
-    log(f"bench: {ms_step:.3f} ms/step, {value:.1f} evals/s; kernels " +
-        ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}ms" for k, v in kt.items() if v[1]))
-    gpu_nll = nll.cpu().numpy()
-    gpu_grad = grad.cpu().numpy()
-    assert np.all(st.cpu().numpy() == 0)
+    log(f"bench: {args.mixed_toys}-toy uneven mix (headline)")
+    mix, toys, classes, gpu_nll, gpu_grad = mixed_batch(gs, gsgen, torch, args)
+    log(f"bench: mix {json.dumps(mix)}")
+    dom = max(mix["kernels"], key=lambda k: mix["kernels"][k]["avg_launch_ms"])
+    dk = mix["kernels"][dom]
+    roofline = {"bound": "alu", "kernel": dk["kernel"], "achieved": dk["achieved_tflops"], "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": dk["frac"], "traffic": None,
+                "flops_per_launch": dk["flops_per_launch"], "pairs_per_launch": dk["pairs_per_launch"],
+                "algo_flops_per_pair": ALGO_FLOPS_PER_PAIR, "avg_launch_ms": dk["avg_launch_ms"],
+                "other_kernels": {v["kernel"]: {"frac": v["frac"], "avg_launch_ms": v["avg_launch_ms"]}
+                                  for k, v in mix["kernels"].items() if k != dom}}
 
-    fold_pairs, adj_pairs, full_pairs, band_pairs = batch.mesh_pairs()
-    # the unit of work is a banded-mesh pair: a (window bin, cell) pair whose bin lies in
-    # the cell's support; pairs a kernel evaluates beyond those are its own overhead
-    executed = {"fold": fold_pairs, "adj": adj_pairs}
-    per_kernel = {}
-    for k in ("fold", "adj"):
-        ms, n = kt[k]
-        avg = ms / n
-        per_kernel[k] = dict(avg_ms=avg, tflops=band_pairs * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12,
-                             executed_over_banded=executed[k] / band_pairs)
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
-    ach = per_kernel[dom]["tflops"]
-    kname = "k_fold1" if dom == "fold" else "k_adj"
-    traffic = None
-    if (TRAFFIC["sources_sha256"] == sources_sha256() and len(toys) == TRAFFIC["toys"]
-            and kname in TRAFFIC["kernels"]):
-        traffic = TRAFFIC["kernels"][kname]
-    roofline = {"bound": "alu", "kernel": kname, "achieved": round(ach, 3),
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                "traffic": traffic, "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": band_pairs,
-                "executed_pairs": executed[dom], "full_mesh_pairs": full_pairs,
-                "banded_over_full": round(band_pairs / full_pairs, 4),
-                "avg_launch_ms": round(per_kernel[dom]["avg_ms"], 4),
-                "other": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in per_kernel.items() if k != dom}}
-    pairs = full_pairs
+    study = singles = None
+    if not args.no_study:
+        log("bench: 4096-toy Borexino-scale study")
+        study = toy_study(gs, gsgen, torch, args)
+        log(f"bench: study {json.dumps(study)}")
+        singles = {}
+        for key, fn in (("c0_energy_family", gsgen.config0), ("c1_borexino_scale", gsgen.config1),
+                        ("c2_pulse_shape", gsgen.config2)):
+            singles[key] = single_model(gs, torch, fn(), fits=not args.no_fits)
+            log(f"bench: {key} {json.dumps(singles[key])}")
 
-    # single-evaluation latency on one device-resident problem
-    single = gs.Batch([toys[0]])
-    th1 = theta[:1].clone()
-    n1, g1, s1 = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(1, stride, dtype=torch.float64,
-                                                                               device="cuda"),
-                  torch.empty(1, dtype=torch.int32, device="cuda"))
-    for _ in range(10):
-        single.nll_grad(th1, n1, g1, s1)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    reps = 200
-    for _ in range(reps):
-        single.nll_grad(th1, n1, g1, s1)
-    torch.cuda.synchronize()
-    single_us = (time.perf_counter() - ta) * 1e6 / reps
-
-    toy_fits = None
-    if not args.no_fits:
-        th0 = torch.tensor(np.stack([t.theta0 for t in toys]), dtype=torch.float64, device="cuda")
-        free = batch.free_masks(toys)
-        batch.fit(th0, base.fd_scale, free=free)  # warm: builds the captured graph
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        r = batch.fit(th0, base.fd_scale, free=free)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - ta
-        stt = r["status"].cpu().numpy()
-        it = r["iters"].cpu().numpy()
-        act, tms = batch.fit_trace()
-        toy_fits = {"fits_per_s": round(len(toys) / el, 2), "seconds": round(el, 4), "toys": len(toys),
-                    "fixed_rates": int(sum(int((~t.free).sum()) for t in toys)),
-                    "converged": int(np.sum(stt & 32 != 0)), "mean_iters": round(float(it.mean()), 2),
-                    "max_iters": int(it.max()), "graph_launches": int(len(act)),
-                    "ms_until_90pct_done": round(float(tms[np.argmax(act <= 0.1 * len(toys))]), 2) if len(act) else None}
-        log(f"bench: toy fits {toy_fits}")
-        # the same toys fitted one at a time by the host BFGS over single-model evaluations,
-        # with central-difference gradients (the plain path) and with the adjoint
-        n_one = 16
-        models = [gs.Model(t) for t in toys[:n_one]]
-        models[0].fit(toys[0].theta0, base.fd_scale, free=toys[0].free_mask(), hesse=False)  # warm
-        bnll = r["nll"].cpu().numpy()
-        one = {"toys": n_one}
-        for name, fd in (("adjoint", False), ("finite_diff", True)):
-            ta = time.perf_counter()
-            res = [mdl.fit(t.theta0, base.fd_scale, use_fd=fd, free=t.free_mask(), hesse=False)
-                   for mdl, t in zip(models, toys[:n_one])]
-            el = time.perf_counter() - ta
-            one[name] = {"fits_per_s": round(n_one / el, 2), "seconds": round(el, 3),
-                         "converged": int(sum(bool(q["ok"]) for q in res)),
-                         "max_rel_dnll_vs_batched": float(max(abs(q["nll"] - bnll[i]) / abs(bnll[i])
-                                                              for i, q in enumerate(res)))}
-        toy_fits["one_at_a_time_host"] = one
-        log(f"bench: toy fits one at a time {one}")
-
-    fits = None
-    if not args.no_fits:
-        model = gs.Model(base)
-        fits = {}
-        for name, fd in (("adjoint", False), ("finite_diff", True)):
-            model.fit(base.theta0, base.fd_scale, use_fd=fd)  # warm
-            ta = time.perf_counter()
-            r = model.fit(base.theta0, base.fd_scale, use_fd=fd, hesse=False)
-            el = time.perf_counter() - ta
-            fits[name] = dict(fits_per_s=round(1.0 / el, 3), seconds=round(el, 4), iters=r["iters"],
-                              n_eval=r["n_eval"], converged=r["ok"], nll=r["nll"])
-        fits["speedup_adjoint_over_fd"] = round(fits["finite_diff"]["seconds"] / fits["adjoint"]["seconds"], 2)
-        log(f"bench: fits {fits}")
-
-    # the multi-observable model: 12 species x 900 energy x 50 pulse-shape bins x 3 datasets
-    two_d = None
-    if not args.no_fits:
-        c2 = gsgen.config2()
-        m2 = gs.Model(c2)
-        for _ in range(5):
-            m2.nll_grad(c2.theta0)
-        ta = time.perf_counter()
-        for _ in range(50):
-            m2.nll_grad(c2.theta0)
-        us2 = (time.perf_counter() - ta) * 1e6 / 50
-        two_d = {"bins": int(c2.counts.size), "us_per_eval": round(us2, 2)}
-        for name, fd in (("adjoint", False), ("finite_diff", True)):
-            m2.fit(c2.theta0, c2.fd_scale, use_fd=fd, hesse=False)
-            ta = time.perf_counter()
-            r = m2.fit(c2.theta0, c2.fd_scale, use_fd=fd, hesse=False)
-            el = time.perf_counter() - ta
-            two_d[name] = dict(seconds=round(el, 4), iters=r["iters"], n_eval=r["n_eval"], converged=r["ok"],
-                               nll=r["nll"])
-        log(f"bench: 2-D model {two_d}")
-
-    mixed = None
-    if not args.no_mixed:
-        mixed = mixed_batch(gs, gsgen, torch, args.mixed_toys, args.steps, args.warmup, not args.no_cpu)
-        log(f"bench: mixed {mixed}")
-
-    cpu = None
-    parity = None
+    cpu = parity = None
     if not args.no_cpu:
-        threads = max(1, min(16, os.cpu_count() or 1))
-        rate, n_done, el, outs = cpu_baseline(toys, args.cpu_seconds, threads)
-        rate1, n1, el1, _ = cpu_baseline(toys, max(2.0, args.cpu_seconds / 3), 1)
-        cpu = {"value": round(rate, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
-               "sample": f"{n_done} oracle -ln L+gradient evaluations of the first {threads} pseudo-experiments "
-                         f"(one per thread) in {el:.1f} s",
-               "one_thread": {"value": round(rate1, 4), "unit": "evals/s",
-                              "sample": f"{n1} evaluations of the first pseudo-experiment in {el1:.1f} s"}}
-        rel = max(abs(gpu_nll[i] - outs[i][0]) / abs(outs[i][0]) for i in range(threads))
-        gerr = max(np.max(np.abs(gpu_grad[i, :17] - outs[i][1]) * base.fd_scale /
-                          np.maximum(np.abs(outs[i][1]) * base.fd_scale, 1.0)) for i in range(threads))
-        parity = {"toys_checked": threads, "max_rel_dnll": float(rel), "max_grad_err": float(gerr),
-                  "pass": bool(rel <= 1e-11 and gerr <= 1e-8)}
+        aff = len(os.sched_getaffinity(0))
+        threads = max(1, min(16, aff))  # a one-GPU machine's CPU share is 16
+        rate, per_class, parity = cpu_baseline_mix(toys, classes, gpu_nll, gpu_grad, args.cpu_seconds, threads)
+        b_toy = next(m for m, c in zip(toys, classes) if c == "B")
+        r1, n1 = one_thread_rate(b_toy, max(2.0, args.cpu_seconds / 4))
+        cpu = {"value": round(rate, 3), "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": (f"oracle -ln L+gradient of the mix's toys at their true parameters, one toy per thread, "
+                          f"{threads} threads: per class " + ", ".join(
+                              f"{c} {v['evals']} evaluations in {v['seconds']} s" for c, v in per_class.items()) +
+                          "; the mix's rate = toys / sum over classes of (toys of the class / class rate)"),
+               "per_class": per_class, "one_thread_class_B": {"value": round(r1, 3), "evals": n1},
+               "host": host_info()}
         log(f"bench: cpu {cpu}; parity {parity}")
 
-    out = {"metric": METRIC, "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "4096 pseudo-experiments of the Borexino-scale model (12 species, 4000+4 "
-                                  "true cells, 900 reco bins, gamma response, 17 params), own rates and "
-                                  "200-900-bin windows; one batched -lnL+gradient per step",
-                      "toys": len(toys), "mean_window_bins": round(float(np.mean([t.win_hi - t.win_lo for t in toys])), 1),
-                      "full_mesh_pairs_per_step": pairs},
-           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "autotune": tune, "toy_fits": toy_fits,
-           "single_eval": {"us_per_eval": round(single_us, 2), "evals_per_s": round(1e6 / single_us, 1)},
-           "single_fit_borexino_scale": fits, "two_d_model": two_d, "mixed_batch": mixed}
+    fixed = mix["fixed_params_per_toy"]
+    out = {"metric": METRIC, "value": round(mix["evals_per_s"], 1), "unit": "evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(mix["ms_per_step"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": (f"{mix['toys']} pseudo-experiments in one batch, a seeded uneven mix: "
+                                   f"{mix['classes'].get('A', 0)} energy-family toys (3-5 species, 500 cells, 100-200 "
+                                   f"bins), {mix['classes'].get('B', 0)} Borexino-like toys (6-16 species, 1000-4000 "
+                                   f"cells, gamma response, 200-900 bins), {mix['classes'].get('C', 0)} pulse-shape "
+                                   f"toys (12 species, 900 x 50 bins x 1-3 datasets); one batched -lnL+gradient of "
+                                   f"every toy per step; parameters a toy's window cannot determine are fixed "
+                                   f"({fixed} per toy on average)"),
+                      "toys": mix["toys"], "classes": mix["classes"],
+                      "toy_study_4096": None if study is None else {
+                          "evals_per_s": study["evals_per_s"], "ms_per_step": study["ms_per_step"],
+                          "fixed_params_per_toy": study["fixed_params_per_toy"],
+                          "params_per_toy": study["params_per_toy"]}},
+           "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity,
+           "toy_fits": mix.get("fits"), "mixed_batch": mix, "toy_study": study, "single_models": singles}
     print(json.dumps(out))
 
 

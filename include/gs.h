@@ -15,7 +15,25 @@
  *     (section 2.4, Eq.3 class of fits);
  *   - -ln L = sum over window bins of (mu - n ln mu) + 1/2 sum over pulls of
  *     ((theta_p - c_p)/sigma_p)^2 (Eq.4 with ln n! dropped; n = 0 contributes
- *     mu; mu < 0, or mu = 0 with n > 0, gives +inf and GS_ST_DOMAIN).
+ *     mu; mu < 0, or mu = 0 with n > 0, gives +inf and GS_ST_DOMAIN; every
+ *     mu > 0 gives the finite term, however small).
+ *
+ * Admitted responses: the pair evaluation holds the per-bin bound (1e-12
+ * relative for expected counts >= 1e-3) only for responses that FP64 can
+ * resolve on the binning.  With m and s the mean and width of a cell's
+ * response and w the largest width of the reco bins its response covers (the
+ * bins where its log-density is above the banding cut; for the gamma family
+ * those at x > 0), every cell whose response reaches the fit window must
+ * satisfy
+ *   GAUSS_E:   s >= w / 4.5
+ *   GAUSS_PE:  s >= w / 4.5 and m <= 600 s
+ *   GAMMA_PE:  m <= 300 s   and w m <= 300 s^2
+ * (set from the measured error of the tile-relative exponent, which grows as
+ * (w/s)^2 for the Gaussian families and with w m / s^2 for gamma, and of the
+ * density's conditioning on an FP64 mean, ~1e-15 m/s; the Borexino-scale
+ * model has s >= 2 pe = 1.25 w, m/s <= 31 and w m / s^2 <= 1.2).  Outside it
+ * the evaluation is refused: -ln L and the gradient are NaN with
+ * GS_ST_UNRESOLVED.
  *
  * Parameter vector theta (FP64), same layout for gradients:
  *   [ R_0 .. R_{S-1} | response parameters | delta, kappa, eta (2-D only) ]
@@ -51,12 +69,19 @@ typedef enum {
 } gs_status;
 
 /* Per-evaluation / per-toy status bits. */
-#define GS_ST_DOMAIN 1u      /* mu < 0, mu = 0 with n > 0, or invalid response */
-#define GS_ST_NONFINITE 2u   /* non-finite parameter                            */
-#define GS_ST_LS_FAIL 4u     /* fit: line search exhausted                      */
-#define GS_ST_MAXITER 8u     /* fit: iteration limit reached                    */
-#define GS_ST_BFGS_RESET 16u /* fit: inverse Hessian reset (curvature y^T s <= 0) */
-#define GS_ST_CONVERGED 32u  /* fit: EDM below tolerance                        */
+#define GS_ST_DOMAIN 1u      /* mu < 0, mu = 0 with n > 0, or invalid response: -ln L = +inf */
+#define GS_ST_NONFINITE 2u   /* non-finite parameter: -ln L = NaN                              */
+#define GS_ST_LS_FAIL 4u     /* fit: line search exhausted                                     */
+#define GS_ST_MAXITER 8u     /* fit: iteration limit reached                                   */
+#define GS_ST_BFGS_RESET 16u /* fit: inverse Hessian reset (curvature y^T s <= 0)              */
+#define GS_ST_CONVERGED 32u  /* fit: EDM below tolerance                                       */
+/* A bin with n > 0 has mu so small that the gradient seed 1 - n/mu overflows
+ * FP64 (n/mu > DBL_MAX, decided in FP64): -ln L is finite and valid, the
+ * gradient has no FP64 value and is NaN.  Fits do not step to such points. */
+#define GS_ST_GRAD_RANGE 64u
+/* A response outside the admitted range (see above) reaches the window: the
+ * evaluation is refused, -ln L and the gradient are NaN. */
+#define GS_ST_UNRESOLVED 128u
 
 typedef enum { GS_RESP_GAUSS_E = 0, GS_RESP_GAUSS_PE = 1, GS_RESP_GAMMA_PE = 2 } gs_family;
 
@@ -77,9 +102,9 @@ typedef struct {
   const double *spectra;      /* [n_species][n_true]; row ignored for line species         */
   const double *line_energy;  /* [n_species]; NaN = grid species, else line energy         */
   int32_t n_reco;             /* energy (reco) bins                                        */
-  const double *reco_edges;   /* [n_reco + 1], strictly increasing                         */
+  const double *reco_edges;   /* [n_reco + 1], finite, strictly increasing                 */
   int32_t n_psd;              /* 0 = one-dimensional; else pulse-shape bins                */
-  const double *psd_edges;    /* [n_psd + 1] strictly increasing (n_psd > 0)               */
+  const double *psd_edges;    /* [n_psd + 1] finite, strictly increasing (n_psd > 0)       */
   const double *psd_mix;      /* [n_species][5] = w1, mean1, sigma1, mean2, sigma2         */
   int32_t n_datasets;         /* 1 .. GS_MAX_DATASETS, sharing every parameter             */
   const double *exposure;     /* [n_datasets], > 0                                         */
@@ -119,11 +144,13 @@ gs_status gs_nll(gs_model *m, const double *theta, double *nll, uint32_t *st);
 
 /* -ln L and its gradient grad[n_params] from one forward fold and one
  * adjoint (reverse-mode) pass over the same visible x true mesh,
- * synchronous.  On GS_ST_DOMAIN / GS_ST_NONFINITE the gradient is NaN. */
+ * synchronous.  On GS_ST_DOMAIN / GS_ST_NONFINITE / GS_ST_UNRESOLVED /
+ * GS_ST_GRAD_RANGE the gradient is NaN. */
 gs_status gs_nll_grad(gs_model *m, const double *theta, double *nll, double *grad, uint32_t *st);
 
 /* Expected counts mu[n_datasets][win_hi - win_lo][max(n_psd,1)] (host) at
- * theta (Eq.2 fold, scaled by rates and exposure).  Synchronous. */
+ * theta (Eq.2 fold, scaled by rates and exposure).  Synchronous.  NaN where
+ * gs_nll_grad would report GS_ST_UNRESOLVED or GS_ST_NONFINITE. */
 gs_status gs_expected(gs_model *m, const double *theta, double *mu);
 
 /* Per-species expected reco spectra at unit rate and exposure,
@@ -218,14 +245,15 @@ gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
 #define GS_K_CELLS 0   /* per-cell response moments and records           */
 #define GS_K_FOLD 1    /* fold of the combined spectrum (adjoint path)     */
 #define GS_K_NLL 2     /* Poisson terms, reduction, adjoint seeds          */
-#define GS_K_ADJ 3     /* adjoint pass over the mesh                       */
+#define GS_K_ADJ 3     /* adjoint pass over the mesh (one-dimensional toys) */
 #define GS_K_GRAD 4    /* chain rule to the parameter gradient             */
 #define GS_K_FOLDS 5   /* per-species fold (plain path, 2-D)               */
 #define GS_K_REDF 6    /* per-species split-K reduction                    */
 #define GS_K_NLLF 7    /* -ln L from per-species spectra                   */
 #define GS_K_QN 8      /* device quasi-Newton step                         */
 #define GS_K_FINISH 9  /* per-problem totals, pulls, status                */
-#define GS_K_COUNT 10
+#define GS_K_ADJS 10   /* per-species adjoint (secondary-observable toys)   */
+#define GS_K_COUNT 11
 
 /* Work layout of a batch (the batch scheduler's tuning knobs for the toy
  * studies of section 4.2): the split-K target (work-groups the fold and the
@@ -265,13 +293,16 @@ gs_status gs_batch_set_profiling(gs_batch *b, int32_t on);
  * events; reset != 0 clears the accumulators afterwards. */
 gs_status gs_batch_kernel_times(gs_batch *b, double *ms, int64_t *launches, int32_t reset);
 /* Mesh pairs (window bin x cell) of the most recent evaluation of the batch,
- * host array of 4: out[0] pairs the fold evaluated (every bin of a tile per
+ * host array of 6: out[0] pairs the fold evaluated (every bin of a tile per
  * visited cell and tile: 32-bin tiles for 1-D toys, 64-bin tiles for
  * secondary-observable toys, idle lanes of a partial tile included), out[1] pairs the
  * adjoint evaluated, out[2] the full mesh sum_t (window bins x cells), out[3]
  * the banded mesh: pairs whose bin lies in the cell's support, i.e. the
- * pairs the method needs at the current log-density cut.  Synchronises the
- * device. */
+ * pairs the method needs at the current log-density cut; out[4] the banded
+ * pairs of secondary-observable toys (folded per species), out[5] those pairs
+ * weighted by the number of species their cell carries (the grid species for
+ * a grid cell, 1 for a line): the per-species contraction's multiply-adds.
+ * Synchronises the device. */
 gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out);
 /* Convergence profile of the most recent gs_fit_batched on this batch: after
  * each launch of the captured fit graph (a fixed number of evaluation + BFGS

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libgs.so")
 
 GS_OK, GS_ERR_ARG, GS_ERR_DEVICE, GS_ERR_OOM, GS_ERR_UNSUPPORTED = range(5)
 ST_DOMAIN, ST_NONFINITE, ST_LS_FAIL, ST_MAXITER, ST_BFGS_RESET, ST_CONVERGED = 1, 2, 4, 8, 16, 32
+ST_GRAD_RANGE, ST_UNRESOLVED = 64, 128
 GAUSS_E, GAUSS_PE, GAMMA_PE = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -51,7 +52,7 @@ EXPORTS = ["gs_last_error", "gs_desc_validate", "gs_model_create", "gs_model_des
            "gs_batch_set_profiling", "gs_batch_kernel_times", "gs_batch_set_log_cut", "gs_model_set_log_cut",
            "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs", "gs_batch_fit_trace",
            "gs_batch_set_layout", "gs_batch_autotune", "gs_batch_layout"]
-KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish"]
+KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish", "adj_s"]
 
 _lib = None
 
@@ -330,9 +331,15 @@ class Batch:
     def mesh_pairs(self):
         """(fold pairs, adjoint pairs, full-mesh pairs, banded-mesh pairs) of the most recent
         evaluation."""
-        out = (C.c_int64 * 4)()
+        return self.mesh_counts()[:4]
+
+    def mesh_counts(self):
+        """The six counts of gs_batch_mesh_pairs: fold pairs, adjoint pairs, full mesh, banded
+        mesh, banded pairs of secondary-observable toys, and those weighted by their cells'
+        species count."""
+        out = (C.c_int64 * 6)()
         _check(lib().gs_batch_mesh_pairs(self.h, out), "gs_batch_mesh_pairs")
-        return int(out[0]), int(out[1]), int(out[2]), int(out[3])
+        return tuple(int(out[i]) for i in range(6))
 
     def fit_trace(self):
         """(active toys, host ms) after each graph launch of the most recent fit."""

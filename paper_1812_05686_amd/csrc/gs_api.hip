@@ -81,12 +81,15 @@ int validate(const gs_model_desc *d) {
     }
   }
   if (d->n_reco < 1 || !d->reco_edges) return bad("no reco bins");
+  if (!std::isfinite(d->reco_edges[0])) return bad("reco_edges[0] is not finite");
   for (int j = 0; j < d->n_reco; j++)
     if (!(d->reco_edges[j + 1] > d->reco_edges[j]) || !std::isfinite(d->reco_edges[j + 1]))
       return bad("reco_edges not strictly increasing at %d", j);
   if (d->n_psd < 0) return bad("n_psd < 0");
   if (d->n_psd > 0) {
     if (!d->psd_edges || !d->psd_mix) return bad("psd_edges / psd_mix is NULL");
+    if (!std::isfinite(d->psd_edges[0]) || !std::isfinite(d->psd_edges[d->n_psd]))
+      return bad("psd_edges not finite");
     for (int k = 0; k < d->n_psd; k++)
       if (!(d->psd_edges[k + 1] > d->psd_edges[k])) return bad("psd_edges not strictly increasing at %d", k);
     for (int s = 0; s < d->n_species; s++) {
@@ -693,7 +696,7 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
   }
   if (d_grad) {
     if (v.has_1d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
-    if (v.has_2d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, true, active, st); }));
+    if (v.has_2d) HIP_TRY(timed(B, GS_K_ADJS, st, [&] { return launch_adj(v, true, active, st); }));
     HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_cellgrad(v, d_theta, active, st); }));
   }
   HIP_TRY(timed(B, GS_K_FINISH, st,
@@ -845,13 +848,19 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
   for (const ToyDev &T : b->toys_h) n_cells = std::max(n_cells, T.cell_off + T.n_cell);
   std::vector<int2> sup((size_t)n_cells);
   HIP_TRY(hipMemcpy(sup.data(), b->v.sup, sizeof(int2) * (size_t)n_cells, hipMemcpyDeviceToHost));
-  long long fold = 0, adj = 0, full = 0, band = 0;
+  long long fold = 0, adj = 0, full = 0, band = 0, band2 = 0, band2s = 0;
   for (const ToyDev &T : b->toys_h) {
+    const ShapeDev &Sh = b->shapes_h[T.shape];
     full += (long long)T.L * T.n_cell;
     for (int i = 0; i < T.n_cell; i++) {
       const int2 s = sup[T.cell_off + i];
       const int x = std::max(s.x, T.lo), y = std::min(s.y, T.lo + T.L);
-      if (y > x) band += y - x;
+      if (y <= x) continue;
+      band += y - x;
+      if (T.two_d) {
+        band2 += y - x;
+        band2s += (long long)(y - x) * (i < Sh.n_true ? Sh.Sg : 1);
+      }
     }
   }
   // the fold evaluates every cell of the hull groups that meet its tile
@@ -896,6 +905,8 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
   out[1] = adj;
   out[2] = full;
   out[3] = band;
+  out[4] = band2;
+  out[5] = band2s;
   return GS_OK;
 }
 
@@ -1005,6 +1016,7 @@ gs_status gs_nll_grad(gs_model *M, const double *theta, double *nll, double *gra
   if (!M || !theta || !nll) return fail(GS_ERR_ARG, "null argument");
   gs_batch *B = M->b;
   HIP_TRY(hipSetDevice(B->device));
+  if (B->v.has_2d) M->cache_valid = false;  // the per-species fold below overwrites gs_nll's cached F
   gs_status s = upload_theta(M, theta);
   if (s != GS_OK) return s;
   s = enqueue_nll_grad(B, M->d_theta, M->d_nll, grad ? M->d_grad : nullptr, M->d_status, nullptr, M->stream);
@@ -1024,13 +1036,17 @@ gs_status gs_expected(gs_model *M, const double *theta, double *mu) {
   if (!M || !theta || !mu) return fail(GS_ERR_ARG, "null argument");
   gs_batch *B = M->b;
   HIP_TRY(hipSetDevice(B->device));
+  if (B->v.has_2d) M->cache_valid = false;  // the per-species fold below overwrites gs_nll's cached F
   gs_status s = upload_theta(M, theta);
   if (s != GS_OK) return s;
   s = enqueue_nll_grad(B, M->d_theta, M->d_nll, nullptr, M->d_status, M->d_mu, M->stream);
   if (s != GS_OK) return s;
   HIP_TRY(hipMemcpyAsync(M->h_out, M->d_mu, sizeof(double) * M->n_mu, hipMemcpyDeviceToHost, M->stream));
+  HIP_TRY(hipMemcpyAsync(M->h_status, M->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, M->stream));
   HIP_TRY(hipStreamSynchronize(M->stream));
-  std::memcpy(mu, M->h_out, sizeof(double) * M->n_mu);
+  // a refused evaluation (response outside the admitted range) claims no value
+  const bool refused = (*M->h_status & (GS_ST_UNRESOLVED | GS_ST_NONFINITE)) != 0;
+  for (int i = 0; i < M->n_mu; i++) mu[i] = refused ? NAN : M->h_out[i];
   return GS_OK;
 }
 

@@ -127,6 +127,27 @@ __device__ double block_sum(double v, double *lds) {
 }
 
 // ------------------------------------------------------------- k_cells ----
+// Responses the FP64 pair evaluation resolves to the per-bin bound on bins of
+// width up to w (gs.h states the range).  Measured against the oracle: the
+// tile-relative Gaussian exponent cancels terms of relative size (w/s)^2
+// (per-bin error 4e-13 at w/s = 4.8, 2e-12 at 10); an FP64 mean carries a
+// density error of about 5e-16 m/s (Gaussian) and 1.2e-15 m/s (gamma, through
+// its shape k = (m/s)^2); the gamma tile term grows with w m/s^2.  A cell
+// outside the range whose response reaches the fit window refuses the
+// evaluation.
+constexpr double kAdmitGaussW = 4.5;      // s >= w / 4.5 (Gaussian families)
+constexpr double kAdmitCondGauss = 600.0; // m <= 600 s (GAUSS_PE)
+constexpr double kAdmitCondGamma = 300.0; // m <= 300 s (GAMMA_PE)
+constexpr double kAdmitGammaW = 300.0;    // w m <= 300 s^2 (GAMMA_PE)
+__device__ __forceinline__ bool admitted(int fam, double m, double s, double w) {
+  if (fam == kGammaPE) return m <= kAdmitCondGamma * s && w * m <= kAdmitGammaW * s * s;
+  if (fam == kGaussPE) return kAdmitGaussW * s >= w && m <= kAdmitCondGauss * s;
+  return kAdmitGaussW * s >= w;
+}
+
+// Per-block flags of k_cells (cflag): an invalid response, a refused one.
+constexpr uint32_t kCellInvalid = 1u, kCellUnresolved = 2u;
+
 __device__ __forceinline__ void put_support(double *rc, int2 s) { *(int2 *)(rc + 6) = s; }
 __device__ __forceinline__ int2 get_support(const double *rc) { return *(const int2 *)(rc + 6); }
 
@@ -141,7 +162,7 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
   if ((int)blockIdx.x >= T.cflag_blocks) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool ok = true;
+  bool ok = true, unresolved = false;
   int hx = 0x7fffffff, hy = -1;  // this cell's contribution to its group's support hull
   if (i < Sh.n_cell) {
     const double *th = theta + (size_t)t * stride;
@@ -159,6 +180,18 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
     cell_record(Sh.family, mo.m, mo.s, W, ok, r);
     const Span spn = cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, Sh.bx0, Sh.bw, log_cut);
     const int2 sp = make_int2(spn.x, spn.y);
+    if (ok && sp.y > T.lo && sp.x < T.lo + T.L) {  // the response reaches the window
+      // the widths of the bins the response covers (the binning's width if uniform)
+      double w = Sh.bw;
+      if (!(w > 0.0)) {
+        w = 0.0;
+        for (int j = sp.x; j < sp.y; j++) {
+          const double *bn = Sh.bins + (size_t)j * kBinLen;
+          if (Sh.family != kGammaPE || bn[0] > 0.0) w = fmax(w, bn[1]);  // a gamma density is 0 at x <= 0
+        }
+      }
+      unresolved = !admitted(Sh.family, mo.m, mo.s, w);
+    }
     put_support(r, sp);
     double *rc = rec + (T.cell_off + i) * kRecLen;
 #pragma unroll
@@ -175,8 +208,8 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
     hy = max(hy, __shfl_xor(hy, o, 64));
   }
   if ((threadIdx.x & (kGroup - 1)) == 0 && i < Sh.n_true) ghull[T.ghull_off + i / kGroup] = make_int2(hx, hy);
-  const int bad = __syncthreads_or(!ok);
-  if (threadIdx.x == 0) cflag[T.cflag_off + blockIdx.x] = bad ? 1u : 0u;
+  const int bad = __syncthreads_or(!ok), unres = __syncthreads_or(unresolved);
+  if (threadIdx.x == 0) cflag[T.cflag_off + blockIdx.x] = (bad ? kCellInvalid : 0u) | (unres ? kCellUnresolved : 0u);
 }
 
 hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
@@ -666,16 +699,22 @@ __device__ __forceinline__ void block_offsets(const ShapeDev &Sh, const ToyDev &
 }
 
 // ------------------------------------------------------------- k_bins1 ----
-// Poisson term of Eq.4 (ln n! dropped).  Returns false on a domain error.
-__device__ __forceinline__ bool poisson_term(double mu, double n, double &term, double &g) {
+// Poisson term of Eq.4 (ln n! dropped) and the adjoint seed g = 1 - n/mu.
+// Returns a flag: 0, kBadDomain (mu < 0, or mu = 0 with n > 0: no term), or
+// kBadRange (n > 0 with n/mu above DBL_MAX: the term is finite, the seed has
+// no FP64 value and is returned as 0).
+constexpr uint32_t kBadDomain = 1u, kBadRange = 2u;
+__device__ __forceinline__ uint32_t poisson_term(double mu, double n, double &term, double &g) {
   if (mu > 0.0) {
     term = n > 0.0 ? __fma_rn(-n, log(mu), mu) : mu;
     g = 1.0 - n / mu;
-    return isfinite(g);  // mu < n/DBL_MAX: the seed is not representable
+    if (isfinite(g)) return 0u;
+    g = 0.0;
+    return kBadRange;
   }
   term = 0.0;
   g = 1.0;
-  return mu == 0.0 && n == 0.0;
+  return mu == 0.0 && n == 0.0 ? 0u : kBadDomain;
 }
 
 __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
@@ -684,13 +723,13 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
                                                double *__restrict__ bref, double *__restrict__ nllp,
                                                uint32_t *__restrict__ badp, double *__restrict__ mu_out) {
   __shared__ double lds[8];
-  __shared__ int bad_s;
+  __shared__ uint32_t bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
-  if (threadIdx.x == 0) bad_s = 0;
+  if (threadIdx.x == 0) bad_s = 0u;
   __syncthreads();
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double sum = 0.0;
@@ -709,12 +748,12 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
     for (; c < T.fold_chunks; c++) s1 += fp[(long long)c * T.L];
     const double mu1 = dx * s1;
     double G = 0.0;
-    bool bad = false;
+    uint32_t bad = 0u;
     for (int d = 0; d < T.D; d++) {
       const double mu = T.exposure[d] * mu1;
       const double n = cnt[T.cnt_off + (long long)d * T.L + b];
       double term, g;
-      if (!poisson_term(mu, n, term, g)) bad = true;
+      bad |= poisson_term(mu, n, term, g);
       sum += term;
       G = __fma_rn(T.exposure[d], g, G);
       if (mu_out) mu_out[(long long)d * T.L + b] = mu;
@@ -729,7 +768,7 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
     br[4] = Gd * bn[2];
     br[5] = Gd * bn[0];
     block_offsets(Sh, T, b, bn, br[6], br[7], bref);
-    if (bad) bad_s = 1;  // benign race: every writer stores 1
+    if (bad) atomicOr(&bad_s, bad);
   }
   const double tot = block_sum(sum, lds);
   __syncthreads();
@@ -1219,10 +1258,12 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
     for (int b = p; b < T.bin_blocks; b += 64) part += nllp[T.nllp_off + b];
     const double nll_bins = wave_sum(part);
     // flags and pull terms spread over the lanes (no serial chain of loads)
-    bool dom = false, nonfin = false;
-    for (int b = p; b < T.bin_blocks; b += 64) dom = dom || badp[T.nllp_off + b] != 0;
-    for (int b = p; b < T.cflag_blocks; b += 64)
-      dom = dom || cflag[T.cflag_off + b] != 0;  // invalid response somewhere on the grid
+    bool nonfin = false;
+    uint32_t bb = 0u, cf = 0u;
+    for (int b = p; b < T.bin_blocks; b += 64) bb |= badp[T.nllp_off + b];
+    for (int b = p; b < T.cflag_blocks; b += 64) cf |= cflag[T.cflag_off + b];
+    const bool dom = (bb & kBadDomain) || (cf & kCellInvalid);  // kCellInvalid: invalid response on the grid
+    const bool range = bb & kBadRange, unres = cf & kCellUnresolved;
     double pull = 0.0;
     if (p < T.P) {
       nonfin = !isfinite(th[p]);
@@ -1234,17 +1275,22 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
     }
     pull = wave_sum(pull);
     const bool any_dom = __ballot(dom) != 0ull, any_nonfin = __ballot(nonfin) != 0ull;
+    const bool any_range = __ballot(range) != 0ull, any_unres = __ballot(unres) != 0ull;
     if (p == 0) {
       uint32_t st = 0;
       double sum = nll_bins + pull;
       if (any_dom || (T.two_d && pflag[t])) st |= GS_ST_DOMAIN;  // pflag: invalid pulse-shape nuisance
       if (any_nonfin) st |= GS_ST_NONFINITE;
+      if (any_unres) st |= GS_ST_UNRESOLVED;
+      if (any_range) st |= GS_ST_GRAD_RANGE;
       if (st & GS_ST_NONFINITE) {
         st = GS_ST_NONFINITE;  // a non-finite parameter explains every other symptom
         sum = __builtin_nan("");
-      }
-      else if (st & GS_ST_DOMAIN)
+      } else if (st & GS_ST_UNRESOLVED) {
+        sum = __builtin_nan("");  // refused: no value is claimed
+      } else if (st & GS_ST_DOMAIN) {
         sum = __builtin_inf();
+      }
       nll[t] = sum;
       status[t] = st;
       st_s = st;
@@ -1257,7 +1303,7 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
       g = gsum[p];
       const double s = pull_s[T.pull_off + p];
       if (s > 0.0) g += (th[p] - pull_c[T.pull_off + p]) / (s * s);
-      if (st_s & (GS_ST_DOMAIN | GS_ST_NONFINITE)) g = __builtin_nan("");
+      if (st_s & (GS_ST_DOMAIN | GS_ST_NONFINITE | GS_ST_UNRESOLVED | GS_ST_GRAD_RANGE)) g = __builtin_nan("");
     }
     grad[(size_t)t * stride + p] = g;
   }
@@ -1326,13 +1372,13 @@ __global__ __launch_bounds__(256) void k_binsF(const int *__restrict__ toy_list,
                                                double *__restrict__ nllp, uint32_t *__restrict__ badp,
                                                double *__restrict__ mu_out) {
   __shared__ double lds[8];
-  __shared__ int bad_s;
+  __shared__ uint32_t bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
-  if (threadIdx.x == 0) bad_s = 0;
+  if (threadIdx.x == 0) bad_s = 0u;
   __syncthreads();
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double sum = 0.0;
@@ -1340,16 +1386,16 @@ __global__ __launch_bounds__(256) void k_binsF(const int *__restrict__ toy_list,
     const double *f = F + (T.win_off + b) * T.S;
     double mu1 = 0.0;
     for (int s = 0; s < Sh.S; s++) mu1 = __fma_rn(th[Sh.sp_of[s]], f[s], mu1);
-    bool bad = false;
+    uint32_t bad = 0u;
     for (int d = 0; d < T.D; d++) {
       const double mu = T.exposure[d] * mu1;
       const double n = cnt[T.cnt_off + (long long)d * T.L + b];
       double term, g;
-      if (!poisson_term(mu, n, term, g)) bad = true;
+      bad |= poisson_term(mu, n, term, g);
       sum += term;
       if (mu_out) mu_out[(long long)d * T.L + b] = mu;
     }
-    if (bad) bad_s = 1;
+    if (bad) atomicOr(&bad_s, bad);
   }
   const double tot = block_sum(sum, lds);
   __syncthreads();
@@ -1464,14 +1510,14 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
   extern __shared__ double pd[];  // [S][4][K]: P_sk, dP_sk/d(delta, kappa, eta); lanes on consecutive k read consecutive doubles
   __shared__ double ared[kWaves][3];
   __shared__ double lds[8];
-  __shared__ int bad_s;
+  __shared__ uint32_t bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || !T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int S = T.S, K = T.K, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) bad_s = 0;
+  if (threadIdx.x == 0) bad_s = 0u;
   for (int e = threadIdx.x; e < S * K; e += blockDim.x) {
     const long long o = T.psd_off + e;
     const int q = e / K, k = e - q * K;
@@ -1484,7 +1530,7 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
   __syncthreads();
   const double *th = theta + (size_t)t * stride;
   double sum = 0.0, A0 = 0.0, A1 = 0.0, A2 = 0.0;
-  bool bad = false;
+  uint32_t bad = 0u;
   const long long n_e = (long long)T.L * K;
   for (int c = 0; c < iter2; c++) {
     const long long e = ((long long)blockIdx.x * iter2 + c) * kBlock + threadIdx.x;
@@ -1505,7 +1551,7 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
       const double mu = T.exposure[d] * M;
       const double n = cnt[T.cnt_off + ((long long)d * T.L + b) * K + k];
       double term, g;
-      if (!poisson_term(mu, n, term, g)) bad = true;
+      bad |= poisson_term(mu, n, term, g);
       sum += term;
       gam = __fma_rn(T.exposure[d], g, gam);
       if (mu_out) mu_out[((long long)d * T.L + b) * K + k] = mu;
@@ -1523,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
     ared[wave][1] = A1;
     ared[wave][2] = A2;
   }
-  if (bad) bad_s = 1;  // benign race: every writer stores 1
+  if (bad) atomicOr(&bad_s, bad);
   const double tot = block_sum(sum, lds);  // its barriers also order ared and bad_s
   if (threadIdx.x == 0) {
     nllp[T.nllp_off + blockIdx.x] = tot;

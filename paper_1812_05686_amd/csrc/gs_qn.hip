@@ -60,10 +60,12 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
   uint32_t status = q.status[t];
   int phase = q.phase[t], iter = q.iter[t];
   bool new_direction = false;
+  // a point whose gradient has no FP64 value (GS_ST_GRAD_RANGE) is not taken
+  const bool usable = isfinite(ft) && !(st_eval[t] & GS_ST_GRAD_RANGE);
   if (phase == kPhaseInit) {
-    if (!isfinite(ft)) {
+    if (!usable) {
       if (p == 0) {
-        q.status[t] = status | (st_eval[t] & (GS_ST_DOMAIN | GS_ST_NONFINITE));
+        q.status[t] = status | (st_eval[t] & (GS_ST_DOMAIN | GS_ST_NONFINITE | GS_ST_UNRESOLVED | GS_ST_GRAD_RANGE));
         q.active[t] = 0;
       }
       return;
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
     new_direction = true;
   } else {
     const double alpha = q.alpha[t], slope = q.slope[t];
-    if (isfinite(ft) && ft <= f + 1e-4 * alpha * slope + 1e-14 * fabs(f)) {
+    if (usable && ft <= f + 1e-4 * alpha * slope + 1e-14 * fabs(f)) {
       // accept the trial point; BFGS update of the inverse Hessian
       const double s = fr ? xtp - xp : 0.0, y = fr ? gtp - gp : 0.0;
       const double sy = wave_sum(s * y), ss = wave_sum(s * s), yy = wave_sum(y * y);
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
         return;
       }
       double a;
-      if (isfinite(ft)) {
+      if (usable) {
         const double aq = -slope * alpha * alpha / (2.0 * (ft - f - slope * alpha));
         a = fmin(fmax(aq, 0.1 * alpha), 0.5 * alpha);
       } else {

@@ -113,10 +113,12 @@ extern "C" gs_status gs_fit(gs_model *M, const double *theta0, const gs_fit_opts
   H = H0;
   uint32_t st = 0, est = 0;
   double f = evaluate(c, x.data(), g.data(), est);
-  st |= est & (GS_ST_NONFINITE | GS_ST_DOMAIN);
+  st |= est & (GS_ST_NONFINITE | GS_ST_DOMAIN | GS_ST_UNRESOLVED | GS_ST_GRAD_RANGE);
+  // a start without an FP64 gradient cannot begin a quasi-Newton step
+  const bool no_grad = (est & GS_ST_GRAD_RANGE) != 0;
   double edm = INFINITY;
   int it = 0;
-  while (std::isfinite(f) && c.err == GS_OK) {
+  while (std::isfinite(f) && !no_grad && c.err == GS_OK) {
     edm = 0.0;
     for (int i = 0; i < n; i++) {
       double hg = 0.0;
@@ -151,11 +153,13 @@ extern "C" gs_status gs_fit(gs_model *M, const double *theta0, const gs_fit_opts
       have_g = !o->use_fd;
       ft = evaluate(c, xt.data(), have_g ? gt.data() : nullptr, est);
       if (c.err != GS_OK) break;
-      if (std::isfinite(ft) && ft <= f + 1e-4 * alpha * slope + 1e-14 * std::fabs(f)) {
+      // a trial point whose gradient has no FP64 value is not taken
+      const bool usable = std::isfinite(ft) && !(est & GS_ST_GRAD_RANGE);
+      if (usable && ft <= f + 1e-4 * alpha * slope + 1e-14 * std::fabs(f)) {
         ok = true;
         break;
       }
-      if (std::isfinite(ft)) {
+      if (usable) {
         const double aq = -slope * alpha * alpha / (2.0 * (ft - f - slope * alpha));
         alpha = std::fmin(std::fmax(aq, 0.1 * alpha), 0.5 * alpha);
       } else {
