@@ -893,13 +893,18 @@ gs_status gs_batch_mesh_pairs(gs_batch *b, int64_t *out) {
   }
   for (const AdjItem &it : b->adj_h) {
     const ToyDev &T = b->toys_h[it.toy];
-    int lo = 0x7fffffff, hi = -1;
-    for (int i = it.cell0; i < std::min(it.cell0 + kTile, T.n_cell); i++) {
-      lo = std::min(lo, sup[T.cell_off + i].x);
-      hi = std::max(hi, sup[T.cell_off + i].y);
+    // 1-D toys: one walk over the union of the item's 64 cells' supports; 2-D toys: one walk
+    // per 16 cells, in whole steps of 16 bins (the per-species adjoint's matrix tiles)
+    const int per = T.two_d ? 16 : kTile;
+    for (int c0 = it.cell0; c0 < std::min(it.cell0 + kTile, T.n_cell); c0 += per) {
+      int lo = 0x7fffffff, hi = -1;
+      for (int i = c0; i < std::min(c0 + per, T.n_cell); i++) {
+        lo = std::min(lo, sup[T.cell_off + i].x);
+        hi = std::max(hi, sup[T.cell_off + i].y);
+      }
+      const int b0 = std::max(it.bin0, lo - T.lo), b1 = std::min(it.bin1, hi - T.lo);
+      if (b1 > b0) adj += (long long)(T.two_d ? (b1 - (b0 & ~15) + 15) / 16 * 16 : b1 - b0) * per;
     }
-    const int b0 = std::max(it.bin0, lo - T.lo), b1 = std::min(it.bin1, hi - T.lo);
-    if (b1 > b0) adj += (long long)(b1 - b0) * kTile;
   }
   out[0] = fold;
   out[1] = adj;

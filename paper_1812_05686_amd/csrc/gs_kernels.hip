@@ -476,39 +476,36 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   }
 }
 
-// Per-species fold (plain path and the secondary-observable model): F_js
-// needs one accumulator per species.  kFoldTile bins per workgroup, half-waves
-// on alternate cells, two bins per lane (j and j + 32), compacted hull groups
-// and LDS-staged batches as in the 1-D fold, with each staged cell also
-// carrying its weight vector over the species: w_si for grid cells, one-hot on
-// its own species for a line cell.  The pair exponent is tile-relative as in
-// the 1-D fold, with one reference point per half-tile (each half spans the
-// 32 bins the 1-D fold's tiles span): a staged cell is {A lower, B,
-// Eref lower, A upper, Eref upper, 0} (A depends on the reference point for
-// the Gaussian families, B never does).
-__device__ __forceinline__ void folds_batch(const double *srec, const double *swt, int S, int nb, int wave,
-                                            const Off2 &o, const ExpK &ec, double (&a0)[GS_MAX_SPECIES],
-                                            double (&a1)[GS_MAX_SPECIES]) {
-  const int h = (threadIdx.x >> 5) & 1;
-  const int np = nb >> 1;
-  for (int k = wave; k < np; k += kWaves) {
-    const int c = 2 * k + h;
-    const double2 p0 = *(const double2 *)(srec + 6 * c), p1 = *(const double2 *)(srec + 6 * c + 2);
-    const double2 p2 = *(const double2 *)(srec + 6 * c + 4);
-    const double r0 = dexp(rel_exponent(p0.x, p0.y, p1.x, o.u0, o.v0), ec);
-    const double r1 = dexp(rel_exponent(p1.y, p0.y, p2.x, o.u1, o.v1), ec);
-    const double *w = swt + c * GS_MAX_SPECIES;
-#pragma unroll
-    for (int q = 0; q < GS_MAX_SPECIES; q += 2) {
-      if (q < S) {
-        const double2 wq = *(const double2 *)(w + q);
-        a0[q] = __fma_rn(wq.x, r0, a0[q]);
-        a1[q] = __fma_rn(wq.x, r1, a1[q]);
-        a0[q + 1] = __fma_rn(wq.y, r0, a0[q + 1]);
-        a1[q + 1] = __fma_rn(wq.y, r1, a1[q + 1]);
-      }
-    }
+// Per-species fold (plain path and the secondary-observable model):
+// F_js = sum_i K_ji w_si, a dense contraction over the cells, runs on the FP64
+// matrix cores.  A workgroup owns kFoldTile = 64 window bins and its 4 waves
+// 16 bins each.  Per step of v_mfma_f64_16x16x4f64 the VALU forms the
+// response of the wave's 16 bins x 4 cells, one pair per lane, as the A
+// operand (lane l: bin l % 16, cell l / 16 of the step); the B operand holds
+// the 4 cells' species weights (lane l: species l % 16 of cell l / 16: w_si
+// for a grid cell, one-hot on its own species for a line cell, zero for the
+// padding of a staged batch); the accumulator holds F[16 bins][16 species]
+// in four registers per lane (lane l, register v: bin l / 16 + 4 v, species
+// l % 16; layouts checked on the device).  Cells come from the compacted hull groups that meet the
+// tile and are staged through LDS as in the 1-D fold, each with its
+// tile-relative exponent about the reference point of either half-tile (the
+// 32 bins that a 1-D fold tile spans): {A lower, B, Eref lower, A upper,
+// Eref upper, 0} (A depends on the reference for the Gaussian families).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One staged batch of nb cells (a multiple of 4: padding slots hold zero
+// weights) against the wave's 16 bins; ao / eo: the slots of the wave's
+// half-tile's A and Eref in a staged cell.
+__device__ __forceinline__ dbl4 folds_batch(const double *srec, const double *swt, int nb, int ao, int eo, double u,
+                                            double v, const ExpK &ec, dbl4 acc) {
+  const int lane = threadIdx.x & 63, kc = lane >> 4, q = lane & 15;
+  for (int c4 = 0; c4 < nb; c4 += 4) {
+    const double *r = srec + 6 * (c4 + kc);
+    const double k = dexp(rel_exponent(r[ao], r[1], r[eo], u, v), ec);
+    const double w = swt[(c4 + kc) * GS_MAX_SPECIES + q];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(k, w, acc, 0, 0, 0);
   }
+  return acc;
 }
 
 // Weight vector of cell i over the internal species (grid species, then lines).
@@ -519,18 +516,19 @@ __device__ __forceinline__ double cell_weight(const ShapeDev &Sh, int i, int q) 
 
 // Cells of a staged batch: either the listed groups of grid cells (list !=
 // NULL, clipped to [c_lo, c_hi)) or the cell range [c_lo, c_hi).  Thread t
-// stages cell t % kStage against the reference of half-tile t / kStage.
+// stages cell t % kStage against the reference point rh of its half-tile
+// (t / kStage) and a share of the batch's species weights.  Nothing is
+// prefetched across the MFMA loop, so it keeps few registers live: the staging
+// loads' latency is hidden by the other workgroups on the compute unit.
 template <int FAM>
-__device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
-                                            int n_list, int c_lo, int c_hi, double *srec, double *swt, int wave,
-                                            const TileRef (&ref)[2], const Off2 &o, const ExpK &ec,
-                                            double (&a0)[GS_MAX_SPECIES], double (&a1)[GS_MAX_SPECIES]) {
+__device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
+                                            int n_list, int c_lo, int c_hi, double *srec, double *swt,
+                                            const TileRef &rh, int ao, int eo, double u, double v,
+                                            const ExpK &ec, dbl4 acc) {
   static_assert(2 * kStage == kWaves * 64, "one staged cell and half-tile per thread");
   constexpr int kGPB = kStage / kGroup;
   constexpr int kT = kWaves * 64;
   const int tid = threadIdx.x, S = Sh.S, cs = tid % kStage, half = tid / kStage;
-  // grid cells weigh only the grid species (a line cell one species of its own)
-  const int nq = list ? Sh.Sg : S;
   auto cell_of = [&](int bi, int c) {  // cell at slot c of batch bi, or -1
     if (list) {
       const int li = bi * kGPB + c / kGroup;
@@ -541,26 +539,16 @@ __device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__
     return cell < c_hi ? cell : -1;
   };
   const int n_batch = list ? (n_list + kGPB - 1) / kGPB : (c_hi - c_lo + kStage - 1) / kStage;
-  double2 f[3];
-  double wv[kStage * GS_MAX_SPECIES / kT];
-  auto fetch = [&](int bi) {
-    stage_load<FAM>(R, cell_of(bi, cs), f);
-#pragma unroll
-    for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) {
-      const int e = tid + u * kT, c = e / GS_MAX_SPECIES, q = e % GS_MAX_SPECIES;
-      const int cell = cell_of(bi, c);
-      wv[u] = cell >= 0 && q < S ? cell_weight(Sh, cell, q) : 0.0;
-    }
-  };
-  if (n_batch > 0) fetch(0);
   for (int bi = 0; bi < n_batch; bi++) {
     const int rem = list ? (n_list - bi * kGPB) * kGroup : c_hi - c_lo - bi * kStage;
-    const int nb = (min(kStage, rem) + 1) & ~1;  // whole cell pairs; pad slots hold zero cells
+    const int nb = (min(kStage, rem) + 3) & ~3;  // whole MFMA steps; padding slots carry zero weights
+    double2 f[3];
+    stage_load<FAM>(R, cell_of(bi, cs), f);
     __syncthreads();  // every wave is done with the previous batch
     {
       // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W}
       const double rc[6] = {f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, f[2].y};
-      const RelCell q = rel_cell(FAM, rc, ref[half].x, ref[half].Lh, ref[half].Ll);
+      const RelCell q = rel_cell(FAM, rc, rh.x, rh.Lh, rh.Ll);
       if (half == 0) {
         ((double2 *)srec)[3 * cs] = make_double2(q.A, q.B);
         srec[6 * cs + 2] = q.Eref;
@@ -569,12 +557,15 @@ __device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__
         ((double2 *)srec)[3 * cs + 2] = make_double2(q.Eref, 0.0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < kStage * GS_MAX_SPECIES / kT; u++) swt[tid + u * kT] = wv[u];
+    for (int e = tid; e < kStage * GS_MAX_SPECIES; e += kT) {
+      const int c = e / GS_MAX_SPECIES, q = e % GS_MAX_SPECIES;
+      const int cell = cell_of(bi, c);
+      swt[e] = cell >= 0 && q < S ? cell_weight(Sh, cell, q) : 0.0;
+    }
     __syncthreads();
-    if (bi + 1 < n_batch) fetch(bi + 1);
-    folds_batch(srec, swt, nq, nb, wave, o, ec, a0, a1);
+    acc = folds_batch(srec, swt, nb, ao, eo, u, v, ec, acc);
   }
+  return acc;
 }
 
 __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ items, int n_items,
@@ -584,7 +575,6 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
                                                 double *__restrict__ out) {
   __shared__ __align__(16) double srec[kStage * 6];
   __shared__ __align__(16) double swt[kStage * GS_MAX_SPECIES];
-  __shared__ double red[kFoldTile][GS_MAX_SPECIES];
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
   const ExpK ec = exp_consts();
@@ -596,53 +586,43 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   if (mode >= 0 && T.two_d != mode) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int b0 = it.bin0 + (lane & 31), b1 = b0 + 32;
-  const double *bp0 = Sh.bins + (size_t)(T.lo + min(b0, T.L - 1)) * kBinLen;
-  const double *bp1 = Sh.bins + (size_t)(T.lo + min(b1, T.L - 1)) * kBinLen;
-  const TileRef ref[2] = {tile_ref(Sh, T, it.bin0, kFoldTile / 2), tile_ref(Sh, T, it.bin0 + kFoldTile / 2, kFoldTile / 2)};
-  Off2 o;
-  rel_offsets(Sh.family, bp0[0], bp0[2], bp0[3], ref[0].x, ref[0].Lh, ref[0].Ll, o.u0, o.v0);
-  rel_offsets(Sh.family, bp1[0], bp1[2], bp1[3], ref[1].x, ref[1].Lh, ref[1].Ll, o.u1, o.v1);
+  // the lane's bin as a row of the A operand, clipped to the window
+  const int b = it.bin0 + 16 * wave + (lane & 15);
+  const double *bp = Sh.bins + (size_t)(T.lo + min(b, T.L - 1)) * kBinLen;
+  // waves 0, 1 take the lower half-tile's reference point, waves 2, 3 the upper's; a thread
+  // stages cells against the half-tile threadIdx.x / kStage (the same split)
+  const int half = wave >> 1;
+  const TileRef rh = tile_ref(Sh, T, it.bin0 + half * (kFoldTile / 2), kFoldTile / 2);
+  double u, v;
+  rel_offsets(Sh.family, bp[0], bp[2], bp[3], rh.x, rh.Lh, rh.Ll, u, v);
+  const int ao = half ? 3 : 0, eo = half ? 4 : 2;
   const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile, T.L);
   const double *R = rec + T.cell_off * kRecLen;
   const int g_end = min(it.cell1, Sh.n_true);
   const int l_lo = max(it.cell0, Sh.n_true), l_hi = it.cell1;  // line cells: few, all evaluated
   const bool gamma = Sh.family == kGammaPE;
-  const bool z0 = gamma && !(bp0[0] > 0.0), z1 = gamma && !(bp1[0] > 0.0);  // outside the gamma support
-  double a0[GS_MAX_SPECIES], a1[GS_MAX_SPECIES];
-#pragma unroll
-  for (int q = 0; q < GS_MAX_SPECIES; q++) a0[q] = a1[q] = 0.0;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int gb = it.cell0 / kGroup; gb * kGroup < g_end; gb += kWaves * 64) {
     const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
                              glist, gcnt);
     if (gamma)
-      folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, ref, o, ec, a0, a1);
+      acc = folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, ao, eo, u, v, ec, acc);
     else
-      folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, wave, ref, o, ec, a0, a1);
+      acc = folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, ao, eo, u, v, ec, acc);
   }
   if (gamma)
-    folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, ref, o, ec, a0, a1);
+    acc = folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, ao, eo, u, v, ec, acc);
   else
-    folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, wave, ref, o, ec, a0, a1);
-  // the two half-waves cover the same bins: combine them, then the waves in a fixed order
+    acc = folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, ao, eo, u, v, ec, acc);
+  // lane l, register r: bin l / 16 + 4 r of the wave's 16, species l % 16
+  const int q = lane & 15, S = T.S;
 #pragma unroll
-  for (int q = 0; q < GS_MAX_SPECIES; q++) {
-    a0[q] = z0 ? 0.0 : a0[q] + __shfl_xor(a0[q], 32, 64);
-    a1[q] = z1 ? 0.0 : a1[q] + __shfl_xor(a1[q], 32, 64);
-  }
-  for (int w = 0; w < kWaves; w++) {
-    if (wave == w && lane < 32)
-#pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++) {
-        red[lane][q] = w == 0 ? a0[q] : red[lane][q] + a0[q];
-        red[lane + 32][q] = w == 0 ? a1[q] : red[lane + 32][q] + a1[q];
-      }
-    __syncthreads();
-  }
-  const int S = T.S;
-  for (int e = threadIdx.x; e < kFoldTile * S; e += blockDim.x) {
-    const int bb = e / S, q = e - bb * S, b = it.bin0 + bb;
-    if (b < T.L) out[T.fs_off + ((long long)it.chunk * T.L + b) * S + q] = red[bb][q];
+  for (int r = 0; r < 4; r++) {
+    const int bb = it.bin0 + 16 * wave + (lane >> 4) + 4 * r;
+    if (bb < T.L && q < S) {
+      const bool outside = gamma && !(Sh.bins[(size_t)(T.lo + bb) * kBinLen] > 0.0);  // outside the gamma support
+      out[T.fs_off + ((long long)it.chunk * T.L + bb) * S + q] = outside ? 0.0 : acc[r];
+    }
   }
 }
 
@@ -896,98 +876,14 @@ __device__ __forceinline__ void adj_bins(const double *__restrict__ rc, const do
   }
 }
 
-// Per-species adjoint (secondary observable): the seed of pair (j, i) is
-// Z_ji = sum_s H_js R_s w_si with H_js = dx_j sum_k P_sk Gam_jk, so each lane
-// keeps R_s w_si of its cell and each bin brings its H row.
-template <int FAM, int NW>
-__device__ __forceinline__ void adj_bins_s(const double *__restrict__ rc, const double (&rw)[GS_MAX_SPECIES], int S,
-                                           int nq, const double *__restrict__ BR, const double *__restrict__ BF,
-                                           const double *__restrict__ HR, int b0, int b1, int wave, const ExpK &ec,
-                                           double (*sref)[kTile], double &A0, double &A1, double &A2) {
-  if (b0 >= b1) return;
-  if (FAM == kGammaPE) {
-    const int lane = threadIdx.x & 63;
-    const double A = rc[0], B = -rc[1];
-    const int q_end = (b1 + kABlock - 1) / kABlock;
-    for (int qa = b0 / kABlock; qa < q_end; qa += kRefBlocks) {
-      const int qb = min(qa + kRefBlocks, q_end);
-      if (NW > 1) stage_refs<NW>(rc, BF, qa, qb, wave, sref);
-      for (int q = qa; q < qb; q++) {
-        const int lo = max(b0, q * kABlock), hi = min(b1, (q + 1) * kABlock);
-        int b = lo + ((b0 + wave - lo) & (NW - 1));
-        if (b >= hi) continue;
-        double Eref;
-        if (NW > 1) {
-          Eref = sref[q - qa][lane];
-        } else {
-          const double *r = BF + (size_t)q * 4;
-          Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
-        }
-        // a bin outside the gamma support (x <= 0) has H = 0 and offsets whose
-        // exponent underflows (see block_offsets), so it adds exactly zero: no
-        // test per bin
-        for (; b + NW < hi; b += 2 * NW) {
-          const double *br = BR + (size_t)b * kBinRecLen, *br2 = br + NW * kBinRecLen;
-          const double *h = HR + (size_t)b * S, *h2 = h + NW * S;
-          double Z = 0.0, Z2 = 0.0;
-#pragma unroll
-          for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
-            if (q2 < nq) {
-              Z = __fma_rn(h[q2], rw[q2], Z);
-              Z2 = __fma_rn(h2[q2], rw[q2], Z2);
-            }
-          const double Gr = Z * dexp(rel_exponent(A, B, Eref, br[6], br[7]), ec);
-          const double Gr2 = Z2 * dexp(rel_exponent(A, B, Eref, br2[6], br2[7]), ec);
-          A0 += Gr;
-          A1 = __fma_rn(Gr, br[1], A1);
-          A2 = __fma_rn(Gr, br[0], A2);
-          A0 += Gr2;
-          A1 = __fma_rn(Gr2, br2[1], A1);
-          A2 = __fma_rn(Gr2, br2[0], A2);
-        }
-        if (b < hi) {
-          const double *br = BR + (size_t)b * kBinRecLen;
-          const double *h = HR + (size_t)b * S;
-          double Z = 0.0;
-#pragma unroll
-          for (int q2 = 0; q2 < GS_MAX_SPECIES; q2++)
-            if (q2 < nq) Z = __fma_rn(h[q2], rw[q2], Z);
-          const double Gr = Z * dexp(rel_exponent(A, B, Eref, br[6], br[7]), ec);
-          A0 += Gr;
-          A1 = __fma_rn(Gr, br[1], A1);
-          A2 = __fma_rn(Gr, br[0], A2);
-        }
-      }
-    }
-    return;
-  }
-  for (int b = b0 + wave; b < b1; b += NW) {
-    const double *br = BR + (size_t)b * kBinRecLen;
-    const double x = br[0];
-    const double *h = HR + (size_t)b * S;
-    double Z = 0.0;
-#pragma unroll
-    for (int q = 0; q < GS_MAX_SPECIES; q++)
-      if (q < nq) Z = __fma_rn(h[q], rw[q], Z);
-    double z;
-    const double Gr = Z * dexp(gauss_exponent(rc[0], rc[1], rc[2], x, z), ec);
-    const double Grz = Gr * z;
-    A0 += Gr;
-    A1 += Grz;
-    A2 = __fma_rn(Grz, z, A2);
-  }
-}
-
 // NW = kWaves waves of a workgroup share one item (interleaving its bins), or,
 // for NW = 1, each of the kAdjGroupWaves waves takes an item of its own and
 // walks all of its bins (no LDS and no barrier).
-template <bool PS, int NW>
+template <int NW>
 __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj(const AdjItem *__restrict__ items, int n_items,
                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
-                                             const double *__restrict__ theta, int stride,
                                              const double *__restrict__ rec, const double *__restrict__ binrec,
-                                             const double *__restrict__ bref, const double *__restrict__ H,
-                                             const uint8_t *__restrict__ active,
+                                             const double *__restrict__ bref, const uint8_t *__restrict__ active,
                                              double *__restrict__ apart) {
   __shared__ double red[NW * kTile * 3];
   __shared__ double sref[NW > 1 ? kRefBlocks : 1][kTile];
@@ -1001,7 +897,7 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
   if (active && !active[it.toy]) return;
   const int wave = NW > 1 ? wave_uniform(threadIdx.x >> 6) : 0;  // this wave's place within its item
   const ToyDev &T = toys[it.toy];
-  if (T.two_d != (PS ? 1 : 0)) return;
+  if (T.two_d) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int i = it.cell0 + lane;
   const bool valid = i < T.n_cell;
@@ -1020,35 +916,10 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
   const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
   const double *BR = binrec + T.win_off * kBinRecLen, *BF = bref + T.bref_off * 4;
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
-  if (!PS) {
-    if (Sh.family == kGammaPE)
-      adj_bins<kGammaPE, NW>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
-    else
-      adj_bins<kGaussE, NW>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
-  } else {
-    const double *th = theta + (size_t)it.toy * stride;
-    double rw[GS_MAX_SPECIES];
-#pragma unroll
-    for (int q = 0; q < GS_MAX_SPECIES; q++) rw[q] = 0.0;
-    if (ic < Sh.n_true) {
-      const double *w = Sh.wcellT + ic;
-#pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q < Sh.Sg) rw[q] = th[Sh.sp_of[q]] * w[(size_t)q * Sh.n_true];
-    } else {
-      const int ql = Sh.Sg + (ic - Sh.n_true);
-#pragma unroll
-      for (int q = 0; q < GS_MAX_SPECIES; q++)
-        if (q == ql) rw[q] = th[Sh.sp_of[q]];
-    }
-    const double *HR = H + T.win_off * T.S;
-    // a tile of grid cells only: their weights cover the grid species alone
-    const int nq = it.cell0 + kTile <= Sh.n_true ? Sh.Sg : T.S;
-    if (Sh.family == kGammaPE)
-      adj_bins_s<kGammaPE, NW>(rc, rw, T.S, nq, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
-    else
-      adj_bins_s<kGaussE, NW>(rc, rw, T.S, nq, BR, BF, HR, b0, b1, wave, ec, sref, A0, A1, A2);
-  }
+  if (Sh.family == kGammaPE)
+    adj_bins<kGammaPE, NW>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
+  else
+    adj_bins<kGaussE, NW>(rc, BR, BF, b0, b1, wave, ec, sref, A0, A1, A2);
   if (NW == 1) {
     if (valid) {
       double *o = apart + T.apart_off + ((long long)it.chunk * T.n_cell + i) * 3;
@@ -1072,30 +943,149 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
   }
 }
 
+// ---------------------------------------------------- per-species adjoint --
+// Secondary-observable toys: the seed of pair (j, i) is
+// Z_ji = sum_s H_js R_s w_si (H_js = dx_j sum_k P_sk Gam_jk, from k_hseed), a
+// dense contraction over the species that runs on the FP64 matrix cores.  A
+// workgroup takes an adjoint item (64 cells x a window-bin range) and each of
+// its 4 waves 16 of the cells; a wave walks the union of its cells' supports
+// in steps of 16 bins.  Per step, v_mfma_f64_16x16x4f64 forms Z for 16 bins x
+// 16 cells from H (A operand, lane l: bin l % 16, species 4 k + l / 16) and
+// R_s w_si (B operand, lane l: species 4 k + l / 16, cell l % 16; held in
+// registers), k over the species in fours.  Lane l then holds Z for its cell
+// l % 16 at the bins l / 16 + 4 v (v = 0..3), evaluates those four pairs'
+// responses on the VALU and adds Z r {1, ln x, x} (gamma) or Z r {1, z, z^2}
+// (Gaussian) to its cell's sums; the four lanes of a cell are combined at the
+// end.  A gamma cell's exponent is formed about the reference point of each
+// kABlock-bin block (as in the 1-D adjoint); bins outside the walked range
+// carry a zero seed.
+__global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict__ items, int n_items,
+                                                       const ToyDev *__restrict__ toys,
+                                                       const ShapeDev *__restrict__ shapes,
+                                                       const double *__restrict__ theta, int stride,
+                                                       const double *__restrict__ rec,
+                                                       const double *__restrict__ binrec,
+                                                       const double *__restrict__ bref, const double *__restrict__ H,
+                                                       const uint8_t *__restrict__ active,
+                                                       double *__restrict__ apart) {
+  const ExpK ec = exp_consts();
+  const int w_item = xcd_item(blockIdx.x, n_items);
+  if (w_item >= n_items) return;
+  const AdjItem it = items[w_item];
+  if (active && !active[it.toy]) return;
+  const ToyDev &T = toys[it.toy];
+  if (!T.two_d) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  const int c0 = it.cell0 + 16 * wave;  // the wave's first cell
+  const int i = c0 + col;               // the lane's cell
+  const bool valid = i < T.n_cell;
+  const int ic = valid ? i : T.n_cell - 1;
+  const double *rp = rec + (T.cell_off + ic) * kRecLen;
+  double rc[kRecLen];
+#pragma unroll
+  for (int q = 0; q < kRecLen; q++) rc[q] = rp[q];
+  // B operand: R_s w_si of the lane's cell for the species 4 k + grp; grid
+  // cells weigh only the grid species, a line cell its own species alone
+  const double *th = theta + (size_t)it.toy * stride;
+  const int nq = c0 + 16 <= Sh.n_true ? Sh.Sg : T.S;
+  const int nk = (nq + 3) >> 2;
+  double rwk[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int sp = 4 * k + grp;
+    double w = 0.0;
+    if (valid && sp < T.S) {
+      if (ic < Sh.n_true)
+        w = sp < Sh.Sg ? th[Sh.sp_of[sp]] * Sh.wcellT[(size_t)sp * Sh.n_true + ic] : 0.0;
+      else
+        w = sp == Sh.Sg + (ic - Sh.n_true) ? th[Sh.sp_of[sp]] : 0.0;
+    }
+    rwk[k] = w;
+  }
+  // union of the wave's 16 cells' supports, as window-relative bins, clipped to the chunk
+  const int2 sp = get_support(rc);
+  int lo = valid ? sp.x : 0x7fffffff, hi = valid ? sp.y : -1;
+  for (int o = 8; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
+  const double *BR = binrec + T.win_off * kBinRecLen, *BF = bref + T.bref_off * 4, *HR = H + T.win_off * T.S;
+  const bool gamma = Sh.family == kGammaPE;
+  double A0 = 0.0, A1 = 0.0, A2 = 0.0, Eref = 0.0;
+  int qref = -1;
+  for (int jb = b0 & ~15; jb < b1; jb += 16) {
+    const int ja = jb + col;  // the A operand's bin
+    dbl4 Z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (k < nk) {
+        const int s4 = 4 * k + grp;
+        const double h = ja >= b0 && ja < b1 && s4 < T.S ? HR[(size_t)ja * T.S + s4] : 0.0;
+        Z = __builtin_amdgcn_mfma_f64_16x16x4f64(h, rwk[k], Z, 0, 0, 0);
+      }
+    if (gamma && jb / kABlock != qref) {  // a 16-bin step lies inside one reference block
+      qref = jb / kABlock;
+      const double *r = BF + (size_t)qref * 4;
+      Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      // bin of register v; outside [b0, b1) its seed is zero and a bin inside stands in
+      const int bb = min(max(jb + grp + 4 * v, b0), b1 - 1);
+      const double *br = BR + (size_t)bb * kBinRecLen;
+      if (gamma) {
+        const double Gr = Z[v] * dexp(rel_exponent(rc[0], -rc[1], Eref, br[6], br[7]), ec);
+        A0 += Gr;
+        A1 = __fma_rn(Gr, br[1], A1);
+        A2 = __fma_rn(Gr, br[0], A2);
+      } else {
+        double z;
+        const double Gr = Z[v] * dexp(gauss_exponent(rc[0], rc[1], rc[2], br[0], z), ec);
+        const double Grz = Gr * z;
+        A0 += Gr;
+        A1 += Grz;
+        A2 = __fma_rn(Grz, z, A2);
+      }
+    }
+  }
+  // the four lanes of a cell (l, l ^ 16, l ^ 32, l ^ 48) in a fixed order
+  A0 += __shfl_xor(A0, 16, 64);
+  A1 += __shfl_xor(A1, 16, 64);
+  A2 += __shfl_xor(A2, 16, 64);
+  A0 += __shfl_xor(A0, 32, 64);
+  A1 += __shfl_xor(A1, 32, 64);
+  A2 += __shfl_xor(A2, 32, 64);
+  if (grp == 0 && valid) {
+    double *o = apart + T.apart_off + ((long long)it.chunk * T.n_cell + i) * 3;
+    o[0] = A0;
+    o[1] = A1;
+    o[2] = A2;
+  }
+}
+
 hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *active, hipStream_t st) {
   const AdjItem *it = per_species ? v.adj2 : v.adj1;
   const int n = per_species ? v.n_adj2 : v.n_adj1;
   if (n == 0) return hipSuccess;
+  if (per_species) {
+    hipLaunchKernelGGL(k_adj_s, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes, v.theta_dev,
+                       v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
+    return hipGetLastError();
+  }
   // one wave per item walks all bins of its cells, kAdjGroupWaves items per
   // workgroup (large batches: the fixed per-wave work spreads over four times
   // the pairs); kWaves waves interleave an item's bins (small batches, where
   // the grid must fill the GPU)
   const int groups = (n + kAdjGroupWaves - 1) / kAdjGroupWaves;
-  if (per_species) {
-    if (v.adj_waves == 1)
-      hipLaunchKernelGGL((k_adj<true, 1>), dim3(xcd_grid(groups)), dim3(kAdjGroupWaves * 64), 0, st, it, n, v.toys,
-                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
-    else
-      hipLaunchKernelGGL((k_adj<true, kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys,
-                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
-  } else {
-    if (v.adj_waves == 1)
-      hipLaunchKernelGGL((k_adj<false, 1>), dim3(xcd_grid(groups)), dim3(kAdjGroupWaves * 64), 0, st, it, n, v.toys,
-                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
-    else
-      hipLaunchKernelGGL((k_adj<false, kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys,
-                         v.shapes, v.theta_dev, v.stride, v.rec, v.binrec, v.bref, v.H, active, v.apart);
-  }
+  if (v.adj_waves == 1)
+    hipLaunchKernelGGL((k_adj<1>), dim3(xcd_grid(groups)), dim3(kAdjGroupWaves * 64), 0, st, it, n, v.toys, v.shapes,
+                       v.rec, v.binrec, v.bref, active, v.apart);
+  else
+    hipLaunchKernelGGL((k_adj<kWaves>), dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes, v.rec,
+                       v.binrec, v.bref, active, v.apart);
   return hipGetLastError();
 }
 
