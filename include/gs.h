@@ -211,6 +211,20 @@ int32_t gs_batch_param_stride(const gs_batch *b);
 gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad,
                               uint32_t *d_status, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as gs_nll_grad_batched (same kernels, same layout, bitwise the
+ * same results), with the split-K and block partials of the evaluation in a
+ * fixed workspace of 64 MiB that the loaded library holds on every device it
+ * runs on until the process ends, instead of the batch's own buffers.  It
+ * calls no allocating routine.  Batches whose partials do not fit (more than
+ * a few hundred Borexino-scale toys) return GS_ERR_UNSUPPORTED.  Every call
+ * on one device shares that device's workspace: calls that overlap in time on
+ * one device (different streams, threads or batches) race and must be ordered
+ * by the caller.  Pointers and stream as for gs_nll_grad_batched. */
+gs_status gs_nll_grad_batched_noalloc(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad,
+                                      uint32_t *d_status, void *hip_stream);
+
 /* Batched fits: every toy runs its own BFGS state machine on the device;
  * the evaluation and update kernels of several iterations are captured in
  * one HIP graph that is replayed until all toys stop.  Device pointers as

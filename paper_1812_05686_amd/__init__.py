@@ -51,7 +51,7 @@ EXPORTS = ["gs_last_error", "gs_desc_validate", "gs_model_create", "gs_model_des
            "gs_batch_num_toys", "gs_batch_param_stride", "gs_nll_grad_batched", "gs_fit_batched",
            "gs_batch_set_profiling", "gs_batch_kernel_times", "gs_batch_set_log_cut", "gs_model_set_log_cut",
            "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs", "gs_batch_fit_trace",
-           "gs_batch_set_layout", "gs_batch_autotune", "gs_batch_layout"]
+           "gs_batch_set_layout", "gs_batch_autotune", "gs_batch_layout", "gs_nll_grad_batched_noalloc"]
 KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish", "adj_s"]
 
 _lib = None
@@ -100,6 +100,8 @@ def lib():
         L.gs_batch_param_stride.argtypes = [vp]
         L.gs_nll_grad_batched.restype = C.c_int
         L.gs_nll_grad_batched.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.gs_nll_grad_batched_noalloc.restype = C.c_int
+        L.gs_nll_grad_batched_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.gs_fit_batched.restype = C.c_int
         L.gs_fit_batched.argtypes = [vp, vp, vp, vp, C.POINTER(gs_fit_opts), vp, vp, vp, vp, vp, vp]
         L.gs_batch_set_profiling.restype = C.c_int
@@ -295,6 +297,17 @@ class Batch:
         _check(lib().gs_nll_grad_batched(self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(nll.data_ptr()),
                                          C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()),
                                          self._stream()), "gs_nll_grad_batched")
+        return nll, grad, status
+
+    def nll_grad_noalloc(self, theta, nll, grad, status):
+        """gs_nll_grad_batched_noalloc into caller-provided tensors (the library's fixed
+        workspace holds the partials; nothing is allocated)."""
+        import torch
+        assert theta.dtype == torch.float64 and theta.is_cuda and theta.is_contiguous()
+        assert tuple(theta.shape) == (self.n, self.stride)
+        _check(lib().gs_nll_grad_batched_noalloc(self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(nll.data_ptr()),
+                                                 C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()),
+                                                 self._stream()), "gs_nll_grad_batched_noalloc")
         return nll, grad, status
 
     def set_log_cut(self, log_cut: float):

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <chrono>
@@ -168,7 +169,7 @@ struct gs_batch {
   // capacities (largest candidate) the work buffers and item arrays hold
   Knobs knobs{};
   std::vector<Knobs> candidates;
-  LayoutSizes cap{};
+  LayoutSizes cap{}, cur{};  // largest candidate; the layout in force
   FoldItem *d_fold_items = nullptr;
   AdjItem *d_adj_items = nullptr;
   ToyDev *d_toys = nullptr;
@@ -585,7 +586,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   B->knobs = default_knobs(B);
   LayoutSizes cap{};
   for (const Knobs &k : B->candidates) grow(cap, layout(B, k));
-  grow(cap, layout(B, B->knobs));
+  B->cur = layout(B, B->knobs);
+  grow(cap, B->cur);
   B->cap = cap;
   v.n_toys = n_toys;
   v.toy_list = nullptr;
@@ -730,6 +732,69 @@ gs_status gs_nll_grad_batched(gs_batch *b, const double *d_theta, double *d_nll,
   return enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, (hipStream_t)hip_stream);
 }
 
+// ------------------------------------------- evaluation without allocation ---
+// Workspace of gs_nll_grad_batched_noalloc: the split-K and block partials of
+// one evaluation live in this fixed array instead of the batch's own buffers.
+// The loaded library holds one copy on every device it runs on until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: kernels get the address that hipGetSymbolAddress returns for
+// the current device (kept per device below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_ptr;  // device -> address of its copy of scratch
+
+// The device address of this device's scratch (looked up once per device, with
+// the device current).
+gs_status scratch_ptr(int device, unsigned char **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return GS_OK;
+  }
+  void *p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[device] = (unsigned char *)p;
+  *out = (unsigned char *)p;
+  return GS_OK;
+}
+}  // namespace
+
+gs_status gs_nll_grad_batched_noalloc(gs_batch *b, const double *d_theta, double *d_nll, double *d_grad,
+                                      uint32_t *d_status, void *hip_stream) {
+  if (!b || !d_theta || !d_nll || !d_status) return fail(GS_ERR_ARG, "null argument");
+  HIP_TRY(hipSetDevice(b->device));
+  unsigned char *base = nullptr;
+  gs_status s = scratch_ptr(b->device, &base);
+  if (s != GS_OK) return s;
+  // carve the partials of the layout in force out of the array, each 256-byte aligned
+  const LayoutSizes &z = b->cur;
+  const auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  const size_t nb[8] = {al(8 * (size_t)std::max<long long>(z.fpart, 1)), al(8 * (size_t)std::max<long long>(z.fspart, 1)),
+                        al(8 * (size_t)std::max<long long>(z.apart, 1)), al(8 * (size_t)std::max<long long>(z.nllp, 1)),
+                        al(4 * (size_t)std::max<long long>(z.nllp, 1)),
+                        al(8 * (size_t)std::max<long long>(z.gpart, 1) * kGradLen),
+                        al(8 * (size_t)std::max<long long>(z.vpart, 1) * kVLen), 0};
+  size_t need = 0;
+  for (int k = 0; k < 7; k++) need += nb[k];
+  if (need > kScratchBytes)
+    return fail(GS_ERR_UNSUPPORTED, "gs_nll_grad_batched_noalloc: this batch's partials need %zu bytes, more than "
+                "the %zu of the fixed workspace; use gs_nll_grad_batched", need, kScratchBytes);
+  BatchView v = b->v;
+  size_t off = 0;
+  v.fpart = (double *)(base + off), off += nb[0];
+  v.fspart = (double *)(base + off), off += nb[1];
+  v.apart = (double *)(base + off), off += nb[2];
+  v.nllp = (double *)(base + off), off += nb[3];
+  v.badp = (uint32_t *)(base + off), off += nb[4];
+  v.gpart = (double *)(base + off), off += nb[5];
+  v.vpart = (double *)(base + off), off += nb[6];
+  return enqueue_nll_grad(b, d_theta, d_nll, d_grad, d_status, nullptr, (hipStream_t)hip_stream, nullptr, &v);
+}
+
 // Puts layout k in force: host layout, then the toys and work items uploaded
 // (synchronously); a captured fit graph, which holds the old layout, is dropped.
 static gs_status apply_layout(gs_batch *B, const Knobs &k) {
@@ -741,6 +806,7 @@ static gs_status apply_layout(gs_batch *B, const Knobs &k) {
   gs_status us = upload_items(B, B->fold_h, B->fold1_h, B->adj_h, B->d_fold_items, B->d_adj_items, B->v, nullptr);
   if (us != GS_OK) return us;
   B->knobs = k;
+  B->cur = z;
   if (B->graph) {
     HIP_TRY(hipGraphExecDestroy(B->graph));
     B->graph = nullptr;
