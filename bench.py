@@ -386,6 +386,66 @@ def single_model(gs, torch, m, reps=200, fits=True):
     return out
 
 
+def discovery_study(gs, gsgen, torch, n_toys):
+    """The profile-likelihood discovery test (section 4.2, Eq.5) over null pseudo-experiments of
+    the Gaussian-signal model: two batched fits per toy (signal free; signal fixed at 0)."""
+    from scipy import stats
+    toys = gsgen.discovery_toys(n_toys)
+    batch = gs.Batch(toys)
+    th0 = torch.tensor(theta_of(toys, batch.stride, "theta0"), dtype=torch.float64, device="cuda")
+    sc, free = batch.scales(toys), batch.free_masks(toys)
+    gs.discovery(batch, th0, sc, [0] * len(toys), free=free)  # warm: captures the fit graphs
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = gs.discovery(batch, th0, sc, [0] * len(toys), free=free)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ta
+    t = r["t"].cpu().numpy()
+    ok = np.isfinite(t)
+    return {"toys": len(toys), "tests_per_s": round(len(toys) / el, 1), "seconds": round(el, 4),
+            "fits_per_s": round(2 * len(toys) / el, 1), "both_converged": int(ok.sum()),
+            "t_mean": round(float(t[ok].mean()), 4),
+            "ks_pvalue_vs_chi2_1": float(stats.kstest(np.maximum(t[ok], 0.0), stats.chi2(1).cdf).pvalue)}
+
+
+def template_study(gs, gsgen, torch, args):
+    """The Monte Carlo template fit (section 3.2, Eq.1): toys of the pulse-shape model's
+    templates flattened to 45,000 bins, 12 rates each; mu = templates x rates, no fold.  The
+    kernel streams each toy's counts once: its roofline is HBM bandwidth."""
+    base = gsgen.template_model(flat2d=True)
+    toys = gsgen.template_toys(args.template_toys, base)
+    batch = gs.Batch(toys)
+    theta = torch.tensor(theta_of(toys, batch.stride), dtype=torch.float64, device="cuda")
+    nll, grad, st = buffers(len(toys), batch.stride, torch)
+    el = timed_steps(batch, theta, nll, grad, st, args.steps, args.warmup, torch)
+    kt = profiled_kernels(batch, theta, nll, grad, st, args.steps, torch)
+    ms, n = kt["tmpl"]
+    avg = ms / n
+    bins = sum(m.win_hi - m.win_lo for m in toys)
+    S = base.n_species
+    # algorithmic bytes per evaluation: each toy's counts (FP64) once, the shared templates once
+    byts = 8.0 * bins + 8.0 * S * base.n_reco
+    gbs = byts / (avg * 1e-3) / 1e9
+    out = {"toys": len(toys), "bins_per_toy": base.n_reco, "species": S,
+           "evals_per_s": round(len(toys) * args.steps / el, 1), "ms_per_step": round(el * 1e3 / args.steps, 4),
+           "kernel": {"kernel": "k_tmpl", "avg_launch_ms": round(avg, 4), "bytes_per_launch": byts,
+                      "achieved_gbs": round(gbs, 1), "peak_gbs": 8000.0, "frac": round(gbs / 8000.0, 4),
+                      "bound": "hbm"},
+           "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in kt.items() if v[1]},
+           "status_nonzero": int((st != 0).sum().item())}
+    if not args.no_fits:
+        th0 = torch.tensor(theta_of(toys, batch.stride, "theta0"), dtype=torch.float64, device="cuda")
+        batch.fit(th0, base.fd_scale)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = batch.fit(th0, base.fd_scale)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ta
+        out["fits"] = {"fits_per_s": round(len(toys) / el, 1), "seconds": round(el, 4),
+                       "converged": int(np.sum(r["status"].cpu().numpy() & 32 != 0))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +453,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--toys", type=int, default=4096, help="pseudo-experiments of the Borexino-scale toy study")
     ap.add_argument("--mixed-toys", type=int, default=16384, help="toys of the uneven mix (the headline)")
+    ap.add_argument("--template-toys", type=int, default=4096, help="toys of the Monte Carlo template study")
+    ap.add_argument("--discovery-toys", type=int, default=4096, help="null toys of the discovery test")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fits", action="store_true")
@@ -439,9 +501,19 @@ def main():
         log(f"bench: study {json.dumps(study)}")
         singles = {}
         for key, fn in (("c0_energy_family", gsgen.config0), ("c1_borexino_scale", gsgen.config1),
-                        ("c2_pulse_shape", gsgen.config2)):
+                        ("c2_pulse_shape", gsgen.config2), ("template_900_bins", gsgen.template_model)):
             singles[key] = single_model(gs, torch, fn(), fits=not args.no_fits)
             log(f"bench: {key} {json.dumps(singles[key])}")
+        log("bench: Monte Carlo template study")
+        templates = template_study(gs, gsgen, torch, args)
+        log(f"bench: templates {json.dumps(templates)}")
+        discovery = None
+        if not args.no_fits:
+            log("bench: discovery test")
+            discovery = discovery_study(gs, gsgen, torch, args.discovery_toys)
+            log(f"bench: discovery {json.dumps(discovery)}")
+        singles["template_study"] = templates
+        singles["discovery_test"] = discovery
 
     cpu = parity = None
     if not args.no_cpu:

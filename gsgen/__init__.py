@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy import special
 
-GAUSS_E, GAUSS_PE, GAMMA_PE = 0, 1, 2
+GAUSS_E, GAUSS_PE, GAMMA_PE, TEMPLATE = 0, 1, 2, 3
 M_E = 0.51099895  # electron mass, MeV
 BIRKS_A = 2.0     # synthetic stopping-power constant, MeV^1.5/cm
 
@@ -82,7 +82,8 @@ class Model:
 
     @property
     def n_params(self) -> int:
-        return self.n_species + (2 if self.family == GAUSS_E else 5) + (3 if self.n_psd else 0)
+        n_resp = 0 if self.family == TEMPLATE else 2 if self.family == GAUSS_E else 5
+        return self.n_species + n_resp + (3 if self.n_psd else 0)
 
     def replace(self, **kw) -> "Model":
         return dataclasses.replace(self, **kw)
@@ -534,6 +535,72 @@ def config4(n_toys: int = 16384, n_shapes_a: int = 8, n_shapes_b: int = 9, fract
                            counts=np.zeros((D, 900, 50)), theta_true=theta, theta0=c2.theta_true.copy())
             m.counts = draw_counts(nature_expected(m, theta, c_hist), _rng(4, 0, t))
         toys.append(m)
+    return toys
+
+
+def template_model(flat2d: bool = False, seed: int = 0) -> Model:
+    """A Monte Carlo template fit (section 3.2): each species' reco spectrum at unit rate is
+    given as a template (here nature's exact bin integrals at the nominal response of the
+    Borexino-scale model, i.e. a noiseless Monte Carlo histogram), so the fit has no response
+    parameters and no fold.  flat2d: the templates of the pulse-shape model's 900 energy x 50
+    pulse-shape bins, flattened to 45,000 bins (one dataset).  Parameters: the 12 rates, with
+    the pull of config 1 on the 600 keV exponential's rate."""
+    base = config2() if flat2d else config1()
+    S = base.n_species
+    hist = nature_species_hist(base, base.theta_true[S:S + 5])  # [n_reco, S]
+    if flat2d:
+        P = nature_psd_probs(base.psd_edges, base.psd_mix)      # [S, K]
+        tmpl = np.einsum("js,sk->sjk", hist, P).reshape(S, -1)
+    else:
+        tmpl = np.ascontiguousarray(hist.T)
+    n = tmpl.shape[1]
+    rates = base.theta_true[:S]
+    ps = np.zeros(S)
+    ps[S - 1] = 500.0
+    m = Model(name="tmpl2d" if flat2d else "tmpl", family=TEMPLATE, n_true=n, e_lo=0.0, e_step=1.0,
+              spectra=np.ascontiguousarray(tmpl), line_energy=np.full(S, np.nan),
+              reco_edges=np.arange(n + 1.0), exposure=np.ones(1), counts=np.zeros((1, n, 1)), win_lo=0, win_hi=n,
+              pull_centre=rates.copy(), pull_sigma=ps, theta_true=rates.copy(),
+              theta0=rates * _rng(7, 1, seed).uniform(0.9, 1.1, S), fd_scale=np.sqrt(rates),
+              species=list(base.species))
+    m.counts = draw_counts((tmpl.T @ rates)[None, :, None], _rng(7, 0, seed))
+    return m
+
+
+def template_toys(n_toys: int, base: Model | None = None) -> list[Model]:
+    """Pseudo-experiments of a template fit: rates drawn +-20% uniform around nominal, own
+    Poisson data over the full histogram, fits from the nominal rates; the templates are
+    shared arrays."""
+    base = template_model() if base is None else base
+    mu_s = base.spectra.T  # [n, S]
+    toys = []
+    for t in range(n_toys):
+        g = _rng(8, 1, t)
+        th = base.theta_true * g.uniform(0.8, 1.2, base.n_species)
+        counts = draw_counts((mu_s @ th)[None, :, None], _rng(8, 0, t))
+        toys.append(base.replace(name=f"tmpl/{t}", counts=counts, theta_true=th, theta0=base.theta_true.copy()))
+    return toys
+
+
+def discovery_toys(n_toys: int, base: Model | None = None, signal: int = 0, study: int = 5) -> list[Model]:
+    """Pseudo-experiments of the null hypothesis for the discovery test (section 4.2): the base
+    model (config 0 by default: a Gaussian line on a flat and an exponential background, the
+    paper's signal-plus-background example) with the signal species' rate at zero and data
+    drawn per toy; the rates are free, the response parameters fixed at their nominal values;
+    fits start at the nominal rates with the signal at zero.  Seeds: study index `study`."""
+    base = config0() if base is None else base
+    S = base.n_species
+    nr = 2 if base.family == GAUSS_E else 5
+    th = base.theta_true.copy()
+    th[signal] = 0.0
+    hist = nature_species_hist(base, th[S:S + nr])
+    free = np.zeros(base.n_params, bool)
+    free[:S] = True
+    toys = []
+    for t in range(n_toys):
+        counts = draw_counts(nature_expected(base, th, hist), _rng(study, 0, t))
+        toys.append(base.replace(name=f"null/{t}", counts=counts, theta_true=th.copy(), theta0=th.copy(),
+                                 free=free.copy()))
     return toys
 
 

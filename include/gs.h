@@ -40,6 +40,7 @@
  *   GS_RESP_GAUSS_E  : (a, b)            m = E, s^2 = a^2 + b E
  *   GS_RESP_GAUSS_PE : (LY, kB, a, b, c) m = LY Q(E; kB) E, s^2 = a^2 + b m + c^2 m^2
  *   GS_RESP_GAMMA_PE : same moments, gamma density with mean m, variance s^2
+ *   GS_RESP_TEMPLATE : none (Monte Carlo templates, see gs_family)
  *   Q(E; kB) = 1 - 2/y + 2 ln(1 + y)/y^2, y = sqrt(E)/(kB * birks_A)  (Birks'
  *   law integrated with dE/dx = birks_A/sqrt(E); E in MeV for the pe families).
  *   Pulse shape of species s (2-D): two Gaussians (w1, mean1, sigma1) and
@@ -83,7 +84,13 @@ typedef enum {
  * evaluation is refused, -ln L and the gradient are NaN. */
 #define GS_ST_UNRESOLVED 128u
 
-typedef enum { GS_RESP_GAUSS_E = 0, GS_RESP_GAUSS_PE = 1, GS_RESP_GAMMA_PE = 2 } gs_family;
+/* GS_RESP_TEMPLATE: the Monte Carlo fit of section 3.2 (cost model Eq.1): each
+ * species' reco spectrum at unit rate and exposure is given as a template, so
+ * there is no response and no fold: mu_dj = eps_d sum_s R_s T_sj.  The
+ * descriptor's spectra hold the templates [n_species][n_reco] (n_true =
+ * n_reco; e_lo, e_step and birks_A are not used, every line_energy is NaN,
+ * n_psd = 0), and theta holds the rates alone. */
+typedef enum { GS_RESP_GAUSS_E = 0, GS_RESP_GAUSS_PE = 1, GS_RESP_GAMMA_PE = 2, GS_RESP_TEMPLATE = 3 } gs_family;
 
 /* Limits of this implementation (GS_ERR_UNSUPPORTED beyond them). */
 #define GS_MAX_SPECIES 16
@@ -242,6 +249,23 @@ gs_status gs_fit_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_f
                          double *d_theta_hat, double *d_nll_hat, double *d_sigma, int32_t *d_iters,
                          uint32_t *d_status, void *hip_stream);
 
+/* Profile-likelihood discovery test over the batch's toys (section 4.2,
+ * Eq.5): per toy, a fit with every free parameter free (start d_theta0, mask
+ * d_free) and a fit with the toy's signal parameter d_signal[t] (an index into
+ * its theta) fixed at 0 (same start otherwise), and the statistic
+ * t = -2 ln(L_null / L_free) = 2 (-ln L_null - (-ln L_free)) >= 0, NaN unless
+ * both fits converged.  (Eq.5 prints the ratio the other way up; the paper's
+ * own recipe takes the difference of the two fits' likelihoods, which this
+ * follows.)  Device arrays as for gs_fit_batched: d_signal[n_toys] (int32),
+ * d_t[n_toys], d_theta_free / d_theta_null [n_toys][stride], d_nll_free /
+ * d_nll_null [n_toys], d_status_free / d_status_null [n_toys] (GS_ST_* of
+ * each fit).  Scales as for gs_fit_batched.  The first call on a batch
+ * allocates the null fit's start and mask.  Synchronises `hip_stream`. */
+gs_status gs_discovery_batched(gs_batch *b, const double *d_theta0, const uint8_t *d_free, const double *d_scale,
+                               const int32_t *d_signal, const gs_fit_opts *o, double *d_t, double *d_theta_free,
+                               double *d_nll_free, uint32_t *d_status_free, double *d_theta_null, double *d_nll_null,
+                               uint32_t *d_status_null, void *hip_stream);
+
 /* ------------------------------------------------------- mesh banding --- */
 /* Pairs (reco bin j, true cell i) whose log-density ln r(xbar_j | E_i) is
  * below log_cut are skipped (default -52).  Each cell's support, the bins
@@ -267,7 +291,8 @@ gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
 #define GS_K_QN 8      /* device quasi-Newton step                         */
 #define GS_K_FINISH 9  /* per-problem totals, pulls, status                */
 #define GS_K_ADJS 10   /* per-species adjoint (secondary-observable toys)   */
-#define GS_K_COUNT 11
+#define GS_K_TMPL 11   /* Monte Carlo template likelihood and rate gradient */
+#define GS_K_COUNT 12
 
 /* Work layout of a batch (the batch scheduler's tuning knobs for the toy
  * studies of section 4.2): the split-K target (work-groups the fold and the

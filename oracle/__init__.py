@@ -91,6 +91,9 @@ def lib():
         L.orc_nll_grad.argtypes = [C.POINTER(_Model), dp, dp, C.POINTER(C.c_uint32)]
         L.orc_fit.restype = C.c_int32
         L.orc_fit.argtypes = [C.POINTER(_Model), dp, C.POINTER(_FitOpts), dp, dp, C.POINTER(_FitRes)]
+        L.orc_discovery.restype = C.c_int32
+        L.orc_discovery.argtypes = [C.POINTER(_Model), dp, C.POINTER(_FitOpts), C.c_int32, dp, dp, dp,
+                                    C.POINTER(_FitRes), C.POINTER(_FitRes)]
         _lib = L
     return _lib
 
@@ -156,6 +159,23 @@ class Oracle:
         ok = lib().orc_fit(C.byref(self.s), _p(th0), C.byref(o), _p(th), _p(sg), C.byref(r))
         return dict(ok=bool(ok), theta=th, sigma=sg, nll=r.nll, edm=r.edm, iters=r.iters,
                     n_eval=r.n_eval, status=r.status)
+
+
+    def discovery(self, signal, theta0=None, free=None, scale=None, max_iter=500, edm_tol=1e-9):
+        """Profile-likelihood discovery statistic t = 2 (-ln L_null - -ln L_free) (section 4.2, Eq.5)
+        with parameter `signal` fixed at 0 in the null fit."""
+        m = self.model
+        th0 = _c(m.theta0 if theta0 is None else theta0)
+        sc = _c(m.fd_scale if scale is None else scale)
+        fm = None if free is None else np.ascontiguousarray(free, dtype=np.uint8)
+        o = _FitOpts(max_iter, edm_tol, 0, _p(sc), None if fm is None else fm.ctypes.data_as(C.POINTER(C.c_uint8)), 0)
+        t = C.c_double()
+        tf, tn = np.zeros(self.P), np.zeros(self.P)
+        rf, rn = _FitRes(), _FitRes()
+        ok = lib().orc_discovery(C.byref(self.s), _p(th0), C.byref(o), int(signal), C.byref(t), _p(tf), _p(tn),
+                                 C.byref(rf), C.byref(rn))
+        return dict(ok=bool(ok), t=t.value, theta_free=tf, theta_null=tn, nll_free=rf.nll, nll_null=rn.nll,
+                    status_free=rf.status, status_null=rn.status)
 
 
 def quench(e, kb, a=2.0):

@@ -45,7 +45,7 @@
 typedef long double ld;
 static const ld PI_L = 3.141592653589793238462643383279502884L;
 
-static int n_resp(int fam) { return fam == ORC_GAUSS_E ? 2 : 5; }
+static int n_resp(int fam) { return fam == ORC_TEMPLATE ? 0 : fam == ORC_GAUSS_E ? 2 : 5; }
 
 int32_t orc_num_params(const orc_model *M) {
   return M->n_species + n_resp(M->family) + (M->n_psd > 0 ? 3 : 0);
@@ -227,7 +227,13 @@ static int fold_l(const orc_model *M, const double *theta, ld *F, ld *dF) {
   const int S = M->n_species, J = M->n_reco, fam = M->family, nr = n_resp(fam);
   const double *resp = theta + S;
   memset(F, 0, sizeof(ld) * (size_t)J * S);
-  if (dF) memset(dF, 0, sizeof(ld) * (size_t)J * S * nr);
+  if (dF && nr > 0) memset(dF, 0, sizeof(ld) * (size_t)J * S * nr);
+  if (fam == ORC_TEMPLATE) {
+    /* Monte Carlo fit (section 3.2): the template is the species' reco spectrum */
+    for (int j = 0; j < J; j++)
+      for (int s = 0; s < S; s++) F[(size_t)j * S + s] = M->spectra[(size_t)s * M->n_true + j];
+    return 1;
+  }
   ld *xb = malloc(sizeof(ld) * J), *dx = malloc(sizeof(ld) * J), *lx = malloc(sizeof(ld) * J);
   ld *w = malloc(sizeof(ld) * S);
   for (int j = 0; j < J; j++) {
@@ -708,3 +714,31 @@ int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o,
   free(Hy);
   return isfinite(f) && !no_grad && !(st & (ORC_ST_LS_FAIL | ORC_ST_MAXITER));
 }
+
+/* ------------------------------------------------- discovery test (Eq.5) -- */
+/* Eq.5 writes the profile likelihood ratio with the free fit in the numerator
+ * and a minus sign in front, which would make t <= 0; read as the ratio of the
+ * null fit's likelihood to the free fit's, t = -2 ln(L_null / L_free) =
+ * 2 (NLL_null - NLL_free) >= 0, the form the paper's own recipe prints (the
+ * difference of the two fits' likelihoods).  Two plain fits, one after the
+ * other. */
+int32_t orc_discovery(const orc_model *M, const double *theta0, const orc_fit_opts *o, int32_t signal,
+                      double *t, double *theta_free, double *theta_null, orc_fit_result *res_free,
+                      orc_fit_result *res_null) {
+  const int P = orc_num_params(M);
+  if (signal < 0 || signal >= P) return 0;
+  int ok_free = orc_fit(M, theta0, o, theta_free, NULL, res_free);
+  double *th0 = malloc(sizeof(double) * P);
+  uint8_t *fm = malloc((size_t)P);
+  memcpy(th0, theta0, sizeof(double) * P);
+  th0[signal] = 0.0;
+  for (int p = 0; p < P; p++) fm[p] = (uint8_t)((!o->free_mask || o->free_mask[p]) && p != signal);
+  orc_fit_opts on = *o;
+  on.free_mask = fm;
+  int ok_null = orc_fit(M, th0, &on, theta_null, NULL, res_null);
+  *t = 2.0 * (res_null->nll - res_free->nll);
+  free(th0);
+  free(fm);
+  return ok_free && ok_null;
+}
+

@@ -22,7 +22,11 @@
 extern "C" {
 #endif
 
-enum { ORC_GAUSS_E = 0, ORC_GAUSS_PE = 1, ORC_GAMMA_PE = 2 };
+/* ORC_TEMPLATE: Monte Carlo templates (section 3.2, the Monte Carlo fit): each
+ * species' spectrum is already its reco histogram at unit rate, spectra
+ * [n_species][n_reco] (n_true = n_reco), so there is no fold and no response
+ * parameter. */
+enum { ORC_GAUSS_E = 0, ORC_GAUSS_PE = 1, ORC_GAMMA_PE = 2, ORC_TEMPLATE = 3 };
 enum { ORC_ST_DOMAIN = 1u, ORC_ST_NONFINITE = 2u, ORC_ST_LS_FAIL = 4u,
        ORC_ST_MAXITER = 8u, ORC_ST_BFGS_RESET = 16u, ORC_ST_GRAD_RANGE = 64u };
 
@@ -86,6 +90,15 @@ typedef struct {
 
 int32_t orc_fit(const orc_model *M, const double *theta0, const orc_fit_opts *o,
                 double *theta_hat, double *sigma, orc_fit_result *res);
+
+/* Profile-likelihood discovery statistic (section 4.2, Eq.5): t = 2 (-ln L of the
+ * fit with parameter `signal` fixed at 0  -  -ln L of the fit with it free), the
+ * other free parameters profiled in both.  The free fit starts at theta0; the
+ * null fit at theta0 with theta0[signal] set to 0.  o->free_mask (or all) gives
+ * the free parameters of the free fit.  Returns 1 when both fits converged. */
+int32_t orc_discovery(const orc_model *M, const double *theta0, const orc_fit_opts *o, int32_t signal,
+                      double *t, double *theta_free, double *theta_null, orc_fit_result *res_free,
+                      orc_fit_result *res_null);
 
 #ifdef __cplusplus
 }

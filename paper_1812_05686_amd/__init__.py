@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(PKG, "libgs.so")
 GS_OK, GS_ERR_ARG, GS_ERR_DEVICE, GS_ERR_OOM, GS_ERR_UNSUPPORTED = range(5)
 ST_DOMAIN, ST_NONFINITE, ST_LS_FAIL, ST_MAXITER, ST_BFGS_RESET, ST_CONVERGED = 1, 2, 4, 8, 16, 32
 ST_GRAD_RANGE, ST_UNRESOLVED = 64, 128
-GAUSS_E, GAUSS_PE, GAMMA_PE = 0, 1, 2
+GAUSS_E, GAUSS_PE, GAMMA_PE, TEMPLATE = 0, 1, 2, 3
 
 _dp = C.POINTER(C.c_double)
 
@@ -51,8 +51,9 @@ EXPORTS = ["gs_last_error", "gs_desc_validate", "gs_model_create", "gs_model_des
            "gs_batch_num_toys", "gs_batch_param_stride", "gs_nll_grad_batched", "gs_fit_batched",
            "gs_batch_set_profiling", "gs_batch_kernel_times", "gs_batch_set_log_cut", "gs_model_set_log_cut",
            "gs_batch_mesh_pairs", "gs_species_spectra", "gs_psd_probs", "gs_batch_fit_trace",
-           "gs_batch_set_layout", "gs_batch_autotune", "gs_batch_layout", "gs_nll_grad_batched_noalloc"]
-KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish", "adj_s"]
+           "gs_batch_set_layout", "gs_batch_autotune", "gs_batch_layout", "gs_nll_grad_batched_noalloc",
+           "gs_discovery_batched"]
+KERNELS = ["cells", "fold", "nll", "adj", "grad", "folds", "reduce_f", "nll_f", "qn", "finish", "adj_s", "tmpl"]
 
 _lib = None
 
@@ -102,6 +103,8 @@ def lib():
         L.gs_nll_grad_batched.argtypes = [vp, vp, vp, vp, vp, vp]
         L.gs_nll_grad_batched_noalloc.restype = C.c_int
         L.gs_nll_grad_batched_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.gs_discovery_batched.restype = C.c_int
+        L.gs_discovery_batched.argtypes = [vp, vp, vp, vp, vp, C.POINTER(gs_fit_opts), vp, vp, vp, vp, vp, vp, vp, vp]
         L.gs_fit_batched.restype = C.c_int
         L.gs_fit_batched.argtypes = [vp, vp, vp, vp, C.POINTER(gs_fit_opts), vp, vp, vp, vp, vp, vp]
         L.gs_batch_set_profiling.restype = C.c_int
@@ -416,6 +419,38 @@ class Batch:
                                     C.c_void_p(iters.data_ptr()), C.c_void_p(st.data_ptr()), self._stream()),
                "gs_fit_batched")
         return dict(theta=th, nll=nll, sigma=sig, iters=iters, status=st)
+
+
+def discovery(batch, theta0, scale, signal, free=None, max_iter=500, edm_tol=1e-9):
+    """Profile-likelihood discovery test of every toy of a Batch (gs_discovery_batched):
+    theta0 [n, stride] start, scale [n, stride] device tensor or one host row, signal [n]
+    parameter index per toy, free optional uint8 [n, stride].  Returns a dict of tensors:
+    t, theta_free, nll_free, status_free, theta_null, nll_null, status_null."""
+    import torch
+    dev = theta0.device
+    n, P = batch.n, batch.stride
+    d_scale = None
+    if isinstance(scale, torch.Tensor) and scale.dim() == 2:
+        d_scale = scale.to(device=dev, dtype=torch.float64).contiguous()
+        scale = np.ones(P)
+    if free is not None:
+        free = free.to(device=dev, dtype=torch.uint8).contiguous()
+    sig = torch.as_tensor(np.asarray(signal, dtype=np.int32)).to(dev)
+    out = dict(t=torch.empty(n, dtype=torch.float64, device=dev),
+               theta_free=torch.empty(n, P, dtype=torch.float64, device=dev),
+               nll_free=torch.empty(n, dtype=torch.float64, device=dev),
+               status_free=torch.empty(n, dtype=torch.int32, device=dev),
+               theta_null=torch.empty(n, P, dtype=torch.float64, device=dev),
+               nll_null=torch.empty(n, dtype=torch.float64, device=dev),
+               status_null=torch.empty(n, dtype=torch.int32, device=dev))
+    sc = _arr(scale)
+    o = gs_fit_opts(max_iter, edm_tol, 0, _ptr(sc), None, 0)
+    vp = lambda x: None if x is None else C.c_void_p(x.data_ptr())
+    _check(lib().gs_discovery_batched(batch.h, vp(theta0), vp(free), vp(d_scale), vp(sig), C.byref(o), vp(out["t"]),
+                                      vp(out["theta_free"]), vp(out["nll_free"]), vp(out["status_free"]),
+                                      vp(out["theta_null"]), vp(out["nll_null"]), vp(out["status_null"]),
+                                      batch._stream()), "gs_discovery_batched")
+    return out
 
 
 def _autograd_fn():

@@ -44,7 +44,7 @@ gs_status fail(gs_status s, const char *fmt, ...) {
                   hipGetErrorString(e_), __FILE__, __LINE__);                            \
   } while (0)
 
-int n_resp(int fam) { return fam == GS_RESP_GAUSS_E ? 2 : 5; }
+int n_resp(int fam) { return fam == GS_RESP_TEMPLATE ? 0 : fam == GS_RESP_GAUSS_E ? 2 : 5; }
 
 int num_params(const gs_model_desc *d) {
   return d->n_species + n_resp(d->family) + (d->n_psd > 0 ? 3 : 0);
@@ -59,7 +59,7 @@ int validate(const gs_model_desc *d) {
     return -1;
   };
   if (!d) return bad("null descriptor");
-  if (d->family < 0 || d->family > 2) return bad("unknown response family %d", d->family);
+  if (d->family < 0 || d->family > 3) return bad("unknown response family %d", d->family);
   if (d->n_species < 1 || d->n_species > GS_MAX_SPECIES)
     return bad("n_species %d outside 1..%d", d->n_species, GS_MAX_SPECIES);
   if (d->n_true < 1) return bad("n_true %d < 1", d->n_true);
@@ -74,6 +74,11 @@ int validate(const gs_model_desc *d) {
     }
   }
   if (n_grid > 0 && !d->spectra) return bad("spectra is NULL");
+  if (d->family == GS_RESP_TEMPLATE) {
+    if (n_grid != d->n_species) return bad("template models have no line species");
+    if (d->n_true != d->n_reco) return bad("templates need n_true == n_reco (%d != %d)", d->n_true, d->n_reco);
+    if (d->n_psd != 0) return bad("template models are one-dimensional (n_psd = 0)");
+  }
   for (int s = 0; s < d->n_species; s++) {
     if (!std::isnan(d->line_energy[s])) continue;
     for (int i = 0; i < d->n_true; i++) {
@@ -114,7 +119,8 @@ int validate(const gs_model_desc *d) {
         double n = d->counts[((size_t)k * d->n_reco + j) * K + q];
         if (!(n >= 0) || !std::isfinite(n)) return bad("count (%d,%d,%d) negative or not finite", k, j, q);
       }
-  if (d->family != GS_RESP_GAUSS_E && !(d->birks_A > 0)) return bad("birks_A must be > 0");
+  if ((d->family == GS_RESP_GAUSS_PE || d->family == GS_RESP_GAMMA_PE) && !(d->birks_A > 0))
+    return bad("birks_A must be > 0");
   const int P = num_params(d);
   if (d->pull_sigma)
     for (int p = 0; p < P; p++)
@@ -201,7 +207,11 @@ struct gs_batch {
   double graph_tol = -1.0;
   bool graph_compact = false;  // the instantiated graph covers a compacted toy list
   // compacted toy and work-item lists of a batched fit (device copies)
-  int *d_toy_list = nullptr, *d_list1 = nullptr, *d_list2 = nullptr;
+  int *d_toy_list = nullptr, *d_list1 = nullptr, *d_list2 = nullptr, *d_listt = nullptr;
+  // discovery test: the null fit's start and free mask, iteration counts
+  double *d_th0_null = nullptr;
+  uint8_t *d_free_null = nullptr;
+  int32_t *d_iters_tmp = nullptr;
   FoldItem *d_fold_c = nullptr;
   AdjItem *d_adj_c = nullptr;
 
@@ -309,6 +319,8 @@ static std::vector<Knobs> layout_candidates(const gs_batch *B) {
     tiles_f += (T.L + kFoldTile - 1) / kFoldTile;
     tiles_a += (T.n_cell + kTile - 1) / kTile;
   }
+  tiles_f = std::max(tiles_f, 1LL);  // template toys have no cells (and a batch of them no fold)
+  tiles_a = std::max(tiles_a, 1LL);
   std::vector<std::pair<long long, long long>> seen;
   std::vector<Knobs> c;
   for (int wg : {kTargetWG, 1024, 4096, 8192}) {
@@ -362,12 +374,15 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     tiles_f += (T.L + kFoldTile - 1) / kFoldTile;
     tiles_a += (T.n_cell + kTile - 1) / kTile;
   }
+  tiles_f = std::max(tiles_f, 1LL);  // template toys have no cells (and a batch of them no fold)
+  tiles_a = std::max(tiles_a, 1LL);
   const int nch_f = (int)std::max<long long>(1, (k.target_wg + tiles_f - 1) / tiles_f);
   const int nch_a = (int)std::max<long long>(1, (k.target_wg + tiles_a - 1) / tiles_a);
   v.grad_cells = k.grad_cells;
   v.iter2 = k.iter2;
   v.adj_waves = k.adj_waves;
   v.max_cell_blocks = v.max_bin_blocks = v.max_bin_blocks1 = v.max_bin_blocks2 = v.max_hblocks = 0;
+  v.max_bin_blocks_t = 0;
   B->fold_h.clear();
   B->fold1_h.clear();
   B->adj_h.clear();
@@ -381,9 +396,12 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
     const long long c2 = (long long)kBlock * k.iter2;
-    T.bin_blocks = T.two_d ? (int)(((long long)T.L * T.K + c2 - 1) / c2) : (T.L + kBlock - 1) / kBlock;
+    T.bin_blocks = T.two_d  ? (int)(((long long)T.L * T.K + c2 - 1) / c2)
+                   : T.tmpl ? (T.L + kBlock * kTmplIter - 1) / (kBlock * kTmplIter)
+                            : (T.L + kBlock - 1) / kBlock;
     T.hblocks = T.two_d ? (T.L + kHTile * k.iter2 - 1) / (kHTile * k.iter2) : 0;
-    T.cell_blocks = (sh.n_cell + k.grad_cells - 1) / k.grad_cells;
+    // template toys keep one rate-gradient row per bin block where other toys keep one per cell block
+    T.cell_blocks = T.tmpl ? T.bin_blocks : (sh.n_cell + k.grad_cells - 1) / k.grad_cells;
     T.vpart_off = z.vpart;
     T.fpart_off = z.fpart;
     T.fs_off = z.fspart;
@@ -406,10 +424,10 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     z.apart += (long long)T.adj_chunks * sh.n_cell * 3;
     z.nllp += T.bin_blocks;
     z.gpart += T.cell_blocks;
-    v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
+    if (!T.tmpl) v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
     v.max_bin_blocks = std::max(v.max_bin_blocks, T.bin_blocks);
-    (T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1) =
-        std::max(T.two_d ? v.max_bin_blocks2 : v.max_bin_blocks1, T.bin_blocks);
+    int &mb = T.two_d ? v.max_bin_blocks2 : T.tmpl ? v.max_bin_blocks_t : v.max_bin_blocks1;
+    mb = std::max(mb, T.bin_blocks);
     v.max_hblocks = std::max(v.max_hblocks, T.hblocks);
   }
   z.n_fold = B->fold_h.size() + B->fold1_h.size();
@@ -466,13 +484,15 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     for (int q = 0; q < d.n_species; q++) (std::isnan(d.line_energy[q]) ? grid : line).push_back(q);
     sh.Sg = (int)grid.size();
     sh.n_line = (int)line.size();
-    sh.n_cell = d.n_true + sh.n_line;
+    sh.n_cell = d.family == GS_RESP_TEMPLATE ? 0 : d.n_true + sh.n_line;  // templates: no cells
     for (int q = 0; q < sh.Sg; q++) sh.sp_of[q] = grid[q];
     for (int q = 0; q < sh.n_line; q++) sh.sp_of[sh.Sg + q] = line[q];
     std::vector<double> cellE(sh.n_cell), wcell((size_t)d.n_true * std::max(sh.Sg, 1), 0.0);
     std::vector<double> wcellT(wcell.size(), 0.0);
-    for (int i = 0; i < d.n_true; i++) cellE[i] = d.e_lo + (i + 0.5) * d.e_step;
-    for (int q = 0; q < sh.n_line; q++) cellE[d.n_true + q] = d.line_energy[line[q]];
+    if (sh.n_cell > 0) {  // template shapes have no cells
+      for (int i = 0; i < d.n_true; i++) cellE[i] = d.e_lo + (i + 0.5) * d.e_step;
+      for (int q = 0; q < sh.n_line; q++) cellE[d.n_true + q] = d.line_energy[line[q]];
+    }
     for (int i = 0; i < d.n_true; i++)
       for (int q = 0; q < sh.Sg; q++) {
         wcell[(size_t)i * sh.Sg + q] = d.spectra[(size_t)grid[q] * d.n_true + i];
@@ -540,10 +560,13 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.P = P[t];
     T.K = std::max(d.n_psd, 1);
     T.two_d = d.n_psd > 0 ? 1 : 0;
+    T.tmpl = d.family == GS_RESP_TEMPLATE ? 1 : 0;
     T.psd_off = psd_off;
     if (T.two_d) {
       psd_off += (long long)sh.S * T.K;
       v.has_2d = true;
+    } else if (T.tmpl) {
+      v.has_tmpl = true;
     } else {
       v.has_1d = true;
     }
@@ -592,9 +615,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   v.n_toys = n_toys;
   v.toy_list = nullptr;
   v.n_list = n_toys;
-  v.list1d = v.list2d = nullptr;
-  v.n1d = v.n2d = 0;
-  for (const ToyDev &T : B->toys_h) (T.two_d ? v.n2d : v.n1d)++;
+  v.list1d = v.list2d = v.listt = nullptr;
+  v.n1d = v.n2d = v.nt = 0;
+  for (const ToyDev &T : B->toys_h) (T.two_d ? v.n2d : T.tmpl ? v.nt : v.n1d)++;
   v.stride = B->stride;
   v.log_cut = kDefaultLogCut;
   ShapeDev *shd;
@@ -639,16 +662,19 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     gs_status us = upload_items(B, B->fold_h, B->fold1_h, B->adj_h, fi, ai, v, nullptr);
     if (us != GS_OK) return us;
   }
-  if (v.n1d > 0 && v.n2d > 0) {  // a mixed batch: kernels of one kind take their toys from a list
-    std::vector<int> l1, l2;
-    for (int t = 0; t < n_toys; t++) (B->toys_h[t].two_d ? l2 : l1).push_back(t);
-    int *d1, *d2;
+  if ((v.n1d > 0) + (v.n2d > 0) + (v.nt > 0) > 1) {  // a mixed batch: kernels of one kind take their toys from a list
+    std::vector<int> l1, l2, lt;
+    for (int t = 0; t < n_toys; t++) (B->toys_h[t].two_d ? l2 : B->toys_h[t].tmpl ? lt : l1).push_back(t);
+    int *d1, *d2, *dt;
     HIP_TRY(B->alloc(&d1, l1.size()));
     HIP_TRY(B->alloc(&d2, l2.size()));
-    HIP_TRY(hipMemcpy(d1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice));
+    HIP_TRY(B->alloc(&dt, lt.size()));
+    if (!l1.empty()) HIP_TRY(hipMemcpy(d1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice));
+    if (!l2.empty()) HIP_TRY(hipMemcpy(d2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice));
+    if (!lt.empty()) HIP_TRY(hipMemcpy(dt, lt.data(), sizeof(int) * lt.size(), hipMemcpyHostToDevice));
     v.list1d = d1;
     v.list2d = d2;
+    v.listt = dt;
   }
   HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(pc, pc_h.data(), pc_h.size() * 8, hipMemcpyHostToDevice));
@@ -685,7 +711,8 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
   BatchView v = view ? *view : B->v;
   v.theta_dev = d_theta;
   B->v.theta_dev = d_theta;
-  HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, active, st); }));
+  if (v.has_1d || v.has_2d) HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, active, st); }));
+  if (v.has_tmpl) HIP_TRY(timed(B, GS_K_TMPL, st, [&] { return launch_tmpl(v, d_theta, d_mu, active, st); }));
   if (v.has_1d) {
     HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold(v, false, kOnly1D, active, st); }));
     HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins1(v, d_mu, active, st); }));
@@ -699,7 +726,8 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
   if (d_grad) {
     if (v.has_1d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
     if (v.has_2d) HIP_TRY(timed(B, GS_K_ADJS, st, [&] { return launch_adj(v, true, active, st); }));
-    HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_cellgrad(v, d_theta, active, st); }));
+    if (v.has_1d || v.has_2d)
+      HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_cellgrad(v, d_theta, active, st); }));
   }
   HIP_TRY(timed(B, GS_K_FINISH, st,
                 [&] { return launch_finish(v, d_theta, d_nll, d_grad, d_status, active, st); }));
@@ -1129,12 +1157,19 @@ gs_status gs_species_spectra(gs_model *M, const double *theta, double *F) {
   if (s != GS_OK) return s;
   const ToyDev &T = B->toys_h[0];
   const ShapeDev &sh = B->shapes_h[0];
-  HIP_TRY(launch_cells(B->v, M->d_theta, nullptr, M->stream));
-  HIP_TRY(launch_fold(B->v, true, kAllToys, nullptr, M->stream));
-  HIP_TRY(launch_reduceF(B->v, kAllToys, nullptr, M->stream));
   std::vector<double> f((size_t)T.L * T.S);
-  HIP_TRY(hipMemcpyAsync(f.data(), B->v.F, sizeof(double) * f.size(), hipMemcpyDeviceToHost, M->stream));
-  HIP_TRY(hipStreamSynchronize(M->stream));
+  if (B->v.has_tmpl) {  // the species spectra are the templates themselves
+    std::vector<double> w((size_t)sh.Sg * sh.n_true);
+    HIP_TRY(hipMemcpy(w.data(), sh.wcellT, sizeof(double) * w.size(), hipMemcpyDeviceToHost));
+    for (int b = 0; b < T.L; b++)
+      for (int q = 0; q < T.S; q++) f[(size_t)b * T.S + q] = w[(size_t)q * sh.n_true + T.lo + b];
+  } else {
+    HIP_TRY(launch_cells(B->v, M->d_theta, nullptr, M->stream));
+    HIP_TRY(launch_fold(B->v, true, kAllToys, nullptr, M->stream));
+    HIP_TRY(launch_reduceF(B->v, kAllToys, nullptr, M->stream));
+    HIP_TRY(hipMemcpyAsync(f.data(), B->v.F, sizeof(double) * f.size(), hipMemcpyDeviceToHost, M->stream));
+    HIP_TRY(hipStreamSynchronize(M->stream));
+  }
   M->cache_valid = false;
   for (int b = 0; b < T.L; b++)
     for (int q = 0; q < T.S; q++) F[(size_t)b * T.S + sh.sp_of[q]] = f[(size_t)b * T.S + q];
@@ -1164,10 +1199,20 @@ gs_status gs_nll(gs_model *M, const double *theta, double *nll, uint32_t *st) {
   gs_batch *B = M->b;
   HIP_TRY(hipSetDevice(B->device));
   const ShapeDev &sh = B->shapes_h[0];
-  const int nr = sh.family == GS_RESP_GAUSS_E ? 2 : 5;
+  const int nr = n_resp(sh.family);
   std::vector<double> resp(theta + sh.S, theta + sh.S + nr);
   gs_status s = upload_theta(M, theta);
   if (s != GS_OK) return s;
+  if (B->v.has_tmpl) {  // templates: nothing to fold or cache; one pass gives -ln L
+    s = enqueue_nll_grad(B, M->d_theta, M->d_nll, nullptr, M->d_status, nullptr, M->stream);
+    if (s != GS_OK) return s;
+    HIP_TRY(hipMemcpyAsync(M->h_out, M->d_nll, sizeof(double), hipMemcpyDeviceToHost, M->stream));
+    HIP_TRY(hipMemcpyAsync(M->h_status, M->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, M->stream));
+    HIP_TRY(hipStreamSynchronize(M->stream));
+    *nll = M->h_out[0];
+    if (st) *st = *M->h_status;
+    return GS_OK;
+  }
   const bool refold = !M->cache_valid || std::memcmp(resp.data(), M->cached_resp.data(), nr * 8) != 0;
   B->v.theta_dev = M->d_theta;
   if (refold) {
@@ -1230,6 +1275,7 @@ static gs_status qn_setup(gs_batch *B) {
   HIP_TRY(B->alloc(&B->d_toy_list, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list1, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list2, (size_t)n));
+  HIP_TRY(B->alloc(&B->d_listt, (size_t)n));
   HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->cap.n_fold, 1)));
   HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->cap.n_adj, 1)));
   std::vector<int> np(n);
@@ -1294,11 +1340,11 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
   std::vector<uint8_t> act((size_t)B->n_toys);
   HIP_TRY(hipMemcpyAsync(act.data(), B->q.active, act.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  std::vector<int> list, l1, l2;
+  std::vector<int> list, l1, l2, lt;
   for (int t = 0; t < B->n_toys; t++)
     if (act[t]) {
       list.push_back(t);
-      (B->toys_h[t].two_d ? l2 : l1).push_back(t);
+      (B->toys_h[t].two_d ? l2 : B->toys_h[t].tmpl ? lt : l1).push_back(t);
     }
   std::vector<FoldItem> fi, fi1;
   std::vector<AdjItem> ai;
@@ -1313,6 +1359,7 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
     HIP_TRY(hipMemcpyAsync(B->d_toy_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, st));
   if (!l1.empty()) HIP_TRY(hipMemcpyAsync(B->d_list1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice, st));
   if (!l2.empty()) HIP_TRY(hipMemcpyAsync(B->d_list2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice, st));
+  if (!lt.empty()) HIP_TRY(hipMemcpyAsync(B->d_listt, lt.data(), sizeof(int) * lt.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
   gs_status us = upload_items(B, fi, fi1, ai, B->d_fold_c, B->d_adj_c, out, st);
   if (us != GS_OK) return us;
@@ -1322,6 +1369,8 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
   out.n1d = (int)l1.size();
   out.list2d = B->d_list2;
   out.n2d = (int)l2.size();
+  out.listt = B->d_listt;
+  out.nt = (int)lt.size();
   return GS_OK;
 }
 
@@ -1375,6 +1424,33 @@ gs_status gs_fit_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_f
   HIP_TRY(hipEventRecord(B->ev_out, st));
   HIP_TRY(hipStreamWaitEvent(caller, B->ev_out, 0));
   HIP_TRY(hipStreamSynchronize(caller));
+  return GS_OK;
+}
+
+gs_status gs_discovery_batched(gs_batch *B, const double *d_theta0, const uint8_t *d_free, const double *d_scale,
+                               const int32_t *d_signal, const gs_fit_opts *o, double *d_t, double *d_theta_free,
+                               double *d_nll_free, uint32_t *d_status_free, double *d_theta_null, double *d_nll_null,
+                               uint32_t *d_status_null, void *hip_stream) {
+  if (!B || !d_theta0 || !d_signal || !o || !d_t || !d_theta_free || !d_nll_free || !d_status_free || !d_theta_null ||
+      !d_nll_null || !d_status_null)
+    return fail(GS_ERR_ARG, "null argument");
+  HIP_TRY(hipSetDevice(B->device));
+  const int n = B->n_toys, P = B->stride;
+  if (!B->d_th0_null) {
+    HIP_TRY(B->alloc(&B->d_th0_null, (size_t)n * P));
+    HIP_TRY(B->alloc(&B->d_free_null, (size_t)n * P));
+    HIP_TRY(B->alloc(&B->d_iters_tmp, (size_t)n));
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(launch_null_start(n, P, d_theta0, d_free, d_signal, B->d_th0_null, B->d_free_null, st));
+  gs_status s = gs_fit_batched(B, d_theta0, d_free, d_scale, o, d_theta_free, d_nll_free, nullptr, B->d_iters_tmp,
+                               d_status_free, hip_stream);
+  if (s != GS_OK) return s;
+  s = gs_fit_batched(B, B->d_th0_null, B->d_free_null, d_scale, o, d_theta_null, d_nll_null, nullptr, B->d_iters_tmp,
+                     d_status_null, hip_stream);
+  if (s != GS_OK) return s;
+  HIP_TRY(launch_discovery_t(n, d_nll_free, d_status_free, d_nll_null, d_status_null, d_t, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return GS_OK;
 }
 

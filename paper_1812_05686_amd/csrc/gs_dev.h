@@ -34,7 +34,7 @@ constexpr double kHalfLn2Pi = 0.91893853320467274178032973640561764;  // ln(2 pi
 constexpr double kLn2Hi = 0.6931471805599453094;   // 0x1.62e42fefa39efp-1
 constexpr double kLn2Lo = 2.319046813846299558e-17;
 
-enum Family : int { kGaussE = 0, kGaussPE = 1, kGammaPE = 2 };
+enum Family : int { kGaussE = 0, kGaussPE = 1, kGammaPE = 2, kTemplate = 3 };
 
 struct dd {
   double hi, lo;

@@ -32,7 +32,8 @@ constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response
 // the grid must fill the GPU, 4 * kBlock for large ones (one reduction per
 // 1024 cells); BatchView::grad_cells holds the choice
 constexpr int kGradCellsLarge = 1024;
-constexpr int kGradLargeBlocks = 16384;  // batches with at least this many kBlock-cell blocks use kGradCellsLarge
+constexpr int kGradLargeBlocks = 16384;
+constexpr int kTmplIter = 4;  // window bins per k_tmpl thread (kBlock * kTmplIter per block)  // batches with at least this many kBlock-cell blocks use kGradCellsLarge
 
 // Structure shared by every toy of one shape (spectra, grid, binning).
 // Species are stored in internal order: grid species first, then lines;
@@ -54,6 +55,7 @@ struct ShapeDev {
 struct ToyDev {
   int shape, D, lo, L, P, K, n_cell, S;
   int two_d;                    // 1: pulse-shape (secondary observable) model
+  int tmpl;                     // 1: Monte Carlo template model (no fold, no response)
   int fold_chunks, adj_chunks;
   int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: iter2 * kBlock bin x pulse-shape cells each) / cells (k_cellgrad)
   int hblocks;                  // 2-D: k_hseed blocks (kHTile window bins each)
@@ -92,8 +94,8 @@ struct BatchView {
   const int *toy_list;  // per-toy grids cover toy_list[0 .. n_list) (NULL: every toy, n_list = n_toys)
   int n_list;
   // the same toys split by kind, for kernels of one kind (NULL list: toy_list / n_list)
-  const int *list1d, *list2d;
-  int n1d, n2d;
+  const int *list1d, *list2d, *listt;
+  int n1d, n2d, nt;  // 1-D analytic, 2-D and template toys
   int max_cells, max_cell_blocks, max_bin_blocks;
   int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)
   int iter2;       // rounds per k_bins2 / k_hseed block (1 or kIter2Large)
@@ -136,7 +138,8 @@ struct BatchView {
   double *vpart;    // per k_bins2 block: sum_j F_js sum_k P_sk Gam_jk (s), nuisance pieces
   uint32_t *pflag;  // [toy]: invalid pulse-shape nuisance
   const double *theta_dev;  // parameters of the evaluation in flight (per-species adjoint)
-  bool has_1d, has_2d;
+  int max_bin_blocks_t;  // k_tmpl grid
+  bool has_1d, has_2d, has_tmpl;
 };
 
 // Which toys a launch covers.
@@ -154,6 +157,7 @@ hipError_t launch_finish(const BatchView &v, const double *theta, double *nll, d
 hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st);
 hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out, hipStream_t st);
 hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st);
+hipError_t launch_tmpl(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st);
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st);
 

@@ -707,7 +707,7 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
-  if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
+  if ((int)blockIdx.x >= T.bin_blocks || T.two_d || T.tmpl) return;
   const ShapeDev &Sh = shapes[T.shape];
   if (threadIdx.x == 0) bad_s = 0u;
   __syncthreads();
@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
-  if ((int)blockIdx.x >= T.cell_blocks) return;
+  if ((int)blockIdx.x >= T.cell_blocks || T.tmpl) return;
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
   const int fam = Sh.family, nr = fam == kGaussE ? 2 : 5;
@@ -1220,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
   // fixed butterfly), so no lane walks a long serial chain of loads.
   const int p = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   if (grad) {
-    const int nr = Sh.family == kGaussE ? 2 : 5;
+    const int nr = Sh.family == kTemplate ? 0 : Sh.family == kGaussE ? 2 : 5;
     const double *vp = vpart + T.vpart_off * kVLen;
     for (int pp = wave; pp < T.P; pp += kWaves) {  // wave-uniform
       double a = 0.0;
@@ -1365,7 +1365,7 @@ __global__ __launch_bounds__(256) void k_binsF(const int *__restrict__ toy_list,
   __shared__ uint32_t bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   const ToyDev &T = toys[t];
-  if ((int)blockIdx.x >= T.bin_blocks || T.two_d) return;
+  if ((int)blockIdx.x >= T.bin_blocks || T.two_d || T.tmpl) return;
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
   if (threadIdx.x == 0) bad_s = 0u;
@@ -1402,6 +1402,92 @@ hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out,
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------- Monte Carlo templates --
+// The Monte Carlo fit (section 3.2, cost model Eq.1): each species' reco
+// spectrum at unit rate is a template T_sj (the response is already in it),
+// so mu_dj = eps_d sum_s R_s T_sj needs no fold.  kBlock threads per block,
+// kTmplIter window bins per thread: mu, the Poisson terms of Eq.4, and the
+// block partials of -ln L and of the rate gradient
+// sum_j (sum_d eps_d (1 - n_dj/mu_dj)) T_sj, in a fixed order.  The toys of a
+// shape share its templates (species-major, so threads on consecutive bins
+// read consecutive doubles; they stay in cache); each toy's counts stream once.
+__global__ __launch_bounds__(256) void k_tmpl(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                              const ShapeDev *__restrict__ shapes, const double *__restrict__ theta,
+                                              int stride, const double *__restrict__ cnt,
+                                              const uint8_t *__restrict__ active, double *__restrict__ nllp,
+                                              uint32_t *__restrict__ badp, double *__restrict__ gpart,
+                                              double *__restrict__ mu_out) {
+  __shared__ double lds[8];
+  __shared__ double part[kBlock / 64][GS_MAX_SPECIES];
+  __shared__ uint32_t bad_s;
+  // grid x: toys, y: bin blocks, so that consecutive workgroups (spread over
+  // the XCDs) are different toys on the same bins: each XCD reads a template
+  // tile once for all the toys that follow it instead of once per toy
+  const int t = toy_of(toy_list, blockIdx.x), blk = blockIdx.y;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if (blk >= T.bin_blocks || !T.tmpl) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const double *th = theta + (size_t)t * stride;
+  const int S = Sh.S;
+  if (threadIdx.x == 0) bad_s = 0u;
+  __syncthreads();
+  double rate[GS_MAX_SPECIES], g[GS_MAX_SPECIES];
+#pragma unroll
+  for (int s = 0; s < GS_MAX_SPECIES; s++) {
+    rate[s] = s < S ? th[Sh.sp_of[s]] : 0.0;
+    g[s] = 0.0;
+  }
+  double sum = 0.0;
+  uint32_t bad = 0u;
+  for (int c = 0; c < kTmplIter; c++) {
+    const int b = (blk * kTmplIter + c) * kBlock + threadIdx.x;
+    if (b >= T.L) break;
+    const double *tj = Sh.wcellT + T.lo + b;
+    double mu1 = 0.0;
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++)
+      if (s < S) mu1 = __fma_rn(rate[s], tj[(size_t)s * Sh.n_true], mu1);
+    double G = 0.0;
+    for (int d = 0; d < T.D; d++) {
+      const double mu = T.exposure[d] * mu1;
+      const double n = cnt[T.cnt_off + (long long)d * T.L + b];
+      double term, gg;
+      bad |= poisson_term(mu, n, term, gg);
+      sum += term;
+      G = __fma_rn(T.exposure[d], gg, G);
+      if (mu_out) mu_out[(long long)d * T.L + b] = mu;
+    }
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++)
+      if (s < S) g[s] = __fma_rn(G, tj[(size_t)s * Sh.n_true], g[s]);
+  }
+  if (bad) atomicOr(&bad_s, bad);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  wave_sum_n(g, S);
+  if (lane == 0)
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++)
+      if (s < S) part[wv][s] = g[s];
+  const double tot = block_sum(sum, lds);  // its barriers also order part and bad_s
+  if (threadIdx.x < S) {
+    double v = part[0][threadIdx.x];
+    for (int w = 1; w < kBlock / 64; w++) v += part[w][threadIdx.x];
+    gpart[(T.gpart_off + blk) * kGradLen + Sh.sp_of[threadIdx.x]] = v;
+  }
+  if (threadIdx.x == 0) {
+    nllp[T.nllp_off + blk] = tot;
+    badp[T.nllp_off + blk] = bad_s;
+  }
+}
+
+hipError_t launch_tmpl(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st) {
+  if (v.nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tmpl, dim3(v.nt, v.max_bin_blocks_t), dim3(kBlock), 0, st, v.listt, v.toys, v.shapes, theta,
+                     v.stride, v.cnt, active, v.nllp, v.badp, v.gpart, mu_out);
+  return hipGetLastError();
+}
 
 // ------------------------------------------- secondary observable (2-D) --
 // Pulse-shape probabilities of every species (section 2.4): a two-Gaussian

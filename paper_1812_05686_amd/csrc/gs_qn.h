@@ -26,6 +26,13 @@ hipError_t launch_qn_step(const QNView &q, int n, const int *toy_list, const dou
                           const double *grad_eval, const uint32_t *st_eval, double edm_tol, int max_iter,
                           hipStream_t st);
 hipError_t launch_qn_count(const uint8_t *active, int n, int *out, hipStream_t st);
+// Start of the null fit of the discovery test: theta0 and the free mask with
+// each toy's signal parameter set to 0 and fixed.
+hipError_t launch_null_start(int n, int stride, const double *theta0, const uint8_t *free_mask, const int32_t *signal,
+                             double *theta0_null, uint8_t *free_null, hipStream_t st);
+// t = 2 (nll_null - nll_free) where both fits converged, else NaN.
+hipError_t launch_discovery_t(int n, const double *nll_free, const uint32_t *st_free, const double *nll_null,
+                              const uint32_t *st_null, double *t, hipStream_t st);
 hipError_t launch_qn_final(const QNView &q, int n, double *theta_hat, double *nll, double *sigma, int32_t *iters,
                            uint32_t *status, hipStream_t st);
 

@@ -201,6 +201,44 @@ __global__ __launch_bounds__(64) void k_qn_final(QNView q, double *__restrict__ 
   }
 }
 
+// ------------------------------------------------------- discovery test --
+// Profile-likelihood ratio of section 4.2 (Eq.5): a fit with every free
+// parameter free and a fit with the signal parameter fixed at zero, per toy.
+__global__ __launch_bounds__(64) void k_null_start(int stride, const double *__restrict__ theta0,
+                                                   const uint8_t *__restrict__ free_mask,
+                                                   const int32_t *__restrict__ signal, double *__restrict__ theta0_null,
+                                                   uint8_t *__restrict__ free_null) {
+  const int t = blockIdx.x, sig = signal[t];
+  for (int p = threadIdx.x; p < stride; p += 64) {
+    const size_t r = (size_t)t * stride + p;
+    theta0_null[r] = p == sig ? 0.0 : theta0[r];
+    free_null[r] = p == sig ? 0 : (free_mask ? free_mask[r] : 1);
+  }
+}
+
+// t = -2 ln(L_null / L_free) = 2 (NLL_null - NLL_free); NaN unless both fits converged.
+__global__ __launch_bounds__(256) void k_discovery_t(int n, const double *__restrict__ nll_free,
+                                                     const uint32_t *__restrict__ st_free,
+                                                     const double *__restrict__ nll_null,
+                                                     const uint32_t *__restrict__ st_null, double *__restrict__ t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool ok = (st_free[i] & GS_ST_CONVERGED) && (st_null[i] & GS_ST_CONVERGED);
+  t[i] = ok ? 2.0 * (nll_null[i] - nll_free[i]) : __builtin_nan("");
+}
+
+hipError_t launch_null_start(int n, int stride, const double *theta0, const uint8_t *free_mask, const int32_t *signal,
+                             double *theta0_null, uint8_t *free_null, hipStream_t st) {
+  hipLaunchKernelGGL(k_null_start, dim3(n), dim3(64), 0, st, stride, theta0, free_mask, signal, theta0_null, free_null);
+  return hipGetLastError();
+}
+
+hipError_t launch_discovery_t(int n, const double *nll_free, const uint32_t *st_free, const double *nll_null,
+                              const uint32_t *st_null, double *t, hipStream_t st) {
+  hipLaunchKernelGGL(k_discovery_t, dim3((n + 255) / 256), dim3(256), 0, st, n, nll_free, st_free, nll_null, st_null, t);
+  return hipGetLastError();
+}
+
 hipError_t launch_qn_init(const QNView &q, int n, const double *theta0, const uint8_t *free_mask,
                           const double *scale, int scale_stride, hipStream_t st) {
   hipLaunchKernelGGL(k_qn_init, dim3(n), dim3(64), 0, st, q, theta0, free_mask, scale, scale_stride);

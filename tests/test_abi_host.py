@@ -58,3 +58,26 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(gs, "_lib", None)
     with pytest.raises(gs.GSError):
         gs.lib()
+
+
+def test_validator_templates(gs):
+    """Monte Carlo template models: the rates are the only parameters; templates need
+    n_true == n_reco, no line species and no secondary observable."""
+    t = gsgen.template_model()
+    assert gs.gs_desc_validate(t) == t.n_species == 12
+    bad = [(t.replace(n_true=t.n_true - 1, spectra=t.spectra[:, :-1].copy()), "n_true == n_reco"),
+           (t.replace(line_energy=np.concatenate([[1.0], t.line_energy[1:]])), "line species"),
+           (t.replace(psd_edges=np.linspace(0, 1, 4), psd_mix=np.tile([0.5, 0.3, 0.1, 0.6, 0.1], (12, 1)),
+                      counts=np.zeros((1, t.n_reco, 3))), "one-dimensional")]
+    for m, msg in bad:
+        assert gs.gs_desc_validate(m) == -1 and msg in gs.gs_last_error(), msg
+
+
+def test_validator_rejects_nonfinite_first_edges(gs, c0):
+    e = c0.reco_edges.copy()
+    e[0] = -np.inf
+    assert gs.gs_desc_validate(c0.replace(reco_edges=e)) == -1
+    m = gsgen.small_gamma_model(n_true=50, n_reco=20, n_psd=5)
+    pe = m.psd_edges.copy()
+    pe[-1] = np.inf
+    assert gs.gs_desc_validate(m.replace(psd_edges=pe)) == -1

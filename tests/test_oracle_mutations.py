@@ -35,6 +35,8 @@ MUTANTS = {
     "line_at_grid_energy": ("E = (ld)M->line_energy[line_s];", "E = (ld)M->line_energy[line_s] + 0.5 * M->e_step;"),
     "tiny_mu_domain": ("if (n > 0 && !isfinite((double)n / (double)mu)) *range = 1;",
                        "if (n > 0 && !isfinite((double)n / (double)mu)) return 0;"),
+    "discovery_sign": ("*t = 2.0 * (res_null->nll - res_free->nll);", "*t = 2.0 * (res_free->nll - res_null->nll);"),
+    "discovery_signal_left_free": ("&& p != signal);", ");"),
     "bfgs_update_sign": ("(rho * rho * yHy + rho) * sv[i] * sv[j]", "(rho * rho * yHy - rho) * sv[i] * sv[j]"),
 }
 

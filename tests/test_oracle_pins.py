@@ -532,3 +532,94 @@ def test_fd_fit_agrees_with_analytic_fit(orc, c0, which):
     rf = o.fit(use_fd=True)
     assert ra["ok"] and rf["ok"]
     assert np.all(np.abs(ra["theta"] - rf["theta"]) <= 1e-3 * ra["sigma"])
+
+
+# ------------------------------------------------------ discovery test -------
+def test_discovery_counting_closed_form(orc, c0):
+    """Eq.5 on a one-bin counting experiment: with only the signal rate free (backgrounds and
+    response fixed), the free fit reaches mu = n exactly and the null fit has mu = b, the
+    backgrounds' expectation, so t = 2 (n ln(n/b) - (n - b)), the textbook closed form of the
+    Poisson likelihood ratio (reading: t = 2 (NLL_null - NLL_free) >= 0)."""
+    th = c0.theta_true.copy()
+    free = np.zeros(c0.n_params, np.uint8)
+    free[0] = 1
+    bkg = th.copy()
+    bkg[0] = 0.0
+    mu_b = orc.Oracle(c0).expected(bkg)[0, :, 0]
+    # bins where the signal's folded content is large enough to determine its rate (n < b: a negative rate)
+    for j, n in ((86, 5200.0), (90, 3000.0), (80, 2500.0), (95, 100.0)):
+        cnt = np.zeros_like(c0.counts)
+        cnt[0, j, 0] = n
+        m = c0.replace(counts=cnt, win_lo=j, win_hi=j + 1)
+        r = orc.Oracle(m).discovery(0, theta0=th, free=free)
+        assert r["ok"], r
+        b = mu_b[j]
+        ref = 2.0 * (n * math.log(n / b) - (n - b))
+        assert abs(r["t"] - ref) <= 1e-8 * max(1.0, ref), (j, r["t"], ref)
+        assert r["theta_null"][0] == 0.0 and np.array_equal(r["theta_null"][1:], th[1:])
+
+
+def test_discovery_null_distribution_is_chi2(orc):
+    """Under the null hypothesis (data without signal) and with the signal rate unbounded, t
+    follows the chi-square law with one degree of freedom asymptotically (Wilks): 240 null toys
+    of the Gaussian-signal model, rates profiled, against chi2(1) by a Kolmogorov-Smirnov test
+    and by its mean (1 +- 4 standard errors); every t >= 0."""
+    from concurrent.futures import ThreadPoolExecutor
+    toys = gsgen.discovery_toys(240)
+
+    def one(m):
+        return orc.Oracle(m).discovery(0, free=m.free_mask())
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        res = list(ex.map(one, toys))
+    assert all(r["ok"] for r in res)
+    t = np.array([r["t"] for r in res])
+    assert t.min() >= -1e-8
+    assert stats.kstest(np.maximum(t, 0.0), stats.chi2(1).cdf).pvalue > 1e-3
+    assert abs(t.mean() - 1.0) <= 4.0 * math.sqrt(2.0 / len(t))
+
+
+# ------------------------------------------------------ Monte Carlo templates ----
+def test_template_single_species_closed_form(orc):
+    """A template fit with one species: mu_j = R T_j is linear in R, so the maximum-likelihood
+    rate is sum_j n_j / sum_j T_j over the window (exposure 1), and -ln L there is
+    sum (mu - n ln mu) at that rate."""
+    base = gsgen.template_model()
+    T_all = base.spectra[6:7].copy()  # the 1.32 MeV beta
+    cnt = np.random.default_rng(3).poisson(base.theta_true[6] * T_all[0]).astype(float)[None, :, None]
+    m = base.replace(spectra=T_all, line_energy=base.line_energy[6:7], counts=cnt,
+                     theta_true=base.theta_true[6:7], theta0=base.theta_true[6:7] * 1.3,
+                     pull_centre=base.theta_true[6:7], pull_sigma=np.zeros(1), fd_scale=base.fd_scale[6:7],
+                     win_lo=100, win_hi=700)
+    r = orc.Oracle(m).fit()
+    assert r["ok"]
+    T = m.spectra[0, 100:700]
+    n = m.counts[0, 100:700, 0]
+    R = n.sum() / T.sum()
+    sigma = R / math.sqrt(n.sum())  # the Poisson error of the rate
+    assert abs(r["theta"][0] - R) <= 1e-3 * sigma
+    mu = R * T
+    ref = math.fsum(mu - np.where(n > 0, n * np.log(mu), 0.0))
+    assert abs(r["nll"] - ref) <= 1e-8
+
+
+def test_template_equals_analytic_at_fixed_response(orc, c1):
+    """Templates equal to the analytic model's own folded spectra at a fixed response give the
+    same -ln L and the same rate gradient at any rates (the Monte Carlo fit and the analytic
+    fit share the likelihood and differ only in where the spectra come from)."""
+    o = orc.Oracle(c1)
+    F = o.species_fold(c1.theta_true)  # [n_reco, S], unit rate, bin width included
+    S = c1.n_species
+    m = c1.replace(family=gsgen.TEMPLATE, n_true=c1.n_reco, e_lo=0.0, e_step=1.0, spectra=np.ascontiguousarray(F.T),
+                   line_energy=np.full(S, np.nan), pull_centre=c1.pull_centre[:S], pull_sigma=c1.pull_sigma[:S],
+                   theta_true=c1.theta_true[:S], theta0=c1.theta0[:S], fd_scale=c1.fd_scale[:S])
+    ot = orc.Oracle(m)
+    for seed in (1, 2):
+        rates = c1.theta_true[:S] * gsgen._rng(500, 1, seed).uniform(0.8, 1.2, S)
+        th = np.concatenate([rates, c1.theta_true[S:]])
+        v, g, st = o.nll_grad(th)
+        vt, gt, stt = ot.nll_grad(rates)
+        assert st == stt == 0
+        # the template path rounds F to FP64 once; the analytic path keeps it in long double
+        assert vt == pytest.approx(v, rel=1e-14)
+        np.testing.assert_allclose(gt, g[:S], rtol=1e-9, atol=1e-9)
