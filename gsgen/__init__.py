@@ -63,6 +63,7 @@ class Model:
     psd_mix: np.ndarray | None = None     # [S, 5] = (w1, mean1, sigma1, mean2, sigma2)
     species: list = field(default_factory=list)
     free: np.ndarray | None = None        # [P] bool, parameters a fit may move (None: all)
+    slice_edges: np.ndarray | None = None  # [n_slices + 1] energy-bin edges of the multivariate slices
 
     @property
     def n_species(self) -> int:
@@ -536,6 +537,15 @@ def config4(n_toys: int = 16384, n_shapes_a: int = 8, n_shapes_b: int = 9, fract
             m.counts = draw_counts(nature_expected(m, theta, c_hist), _rng(4, 0, t))
         toys.append(m)
     return toys
+
+
+def multivariate_model(base: Model | None = None, slice_width: int = 90) -> Model:
+    """The multivariate slice likelihood of section 2.4 on the pulse-shape model (config 2 by
+    default): the same data, the energy likelihood over the window plus one pulse-shape piece
+    per slice of `slice_width` energy bins (the last slice takes the remainder)."""
+    base = config2() if base is None else base
+    edges = list(range(base.win_lo, base.win_hi, slice_width)) + [base.win_hi]
+    return base.replace(name=base.name + "/mv", slice_edges=np.array(edges, dtype=np.int32))
 
 
 def template_model(flat2d: bool = False, seed: int = 0) -> Model:

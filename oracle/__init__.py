@@ -45,7 +45,8 @@ class _Model(C.Structure):
                 ("n_datasets", C.c_int32), ("exposure", C.POINTER(C.c_double)),
                 ("counts", C.POINTER(C.c_double)), ("win_lo", C.c_int32), ("win_hi", C.c_int32),
                 ("family", C.c_int32), ("birks_A", C.c_double),
-                ("pull_centre", C.POINTER(C.c_double)), ("pull_sigma", C.POINTER(C.c_double))]
+                ("pull_centre", C.POINTER(C.c_double)), ("pull_sigma", C.POINTER(C.c_double)),
+                ("n_slices", C.c_int32), ("slice_edges", C.POINTER(C.c_int32))]
 
 
 class _FitOpts(C.Structure):
@@ -114,9 +115,13 @@ class Oracle:
         self._keep = [_c(m.spectra), _c(m.line_energy), _c(m.reco_edges), _c(m.psd_edges),
                       _c(m.psd_mix), _c(m.exposure), _c(m.counts), _c(m.pull_centre), _c(m.pull_sigma)]
         sp, le, re_, pe, pm, ex, cn, pc, ps = self._keep
+        se = getattr(m, "slice_edges", None)
+        se = None if se is None else np.ascontiguousarray(se, dtype=np.int32)
+        self._keep.append(se)
         self.s = _Model(m.n_true, m.e_lo, m.e_step, m.n_species, _p(sp), _p(le), m.n_reco, _p(re_),
                         m.n_psd, _p(pe), _p(pm), m.n_datasets, _p(ex), _p(cn), m.win_lo, m.win_hi,
-                        m.family, m.birks_A, _p(pc), _p(ps))
+                        m.family, m.birks_A, _p(pc), _p(ps), 0 if se is None else len(se) - 1,
+                        None if se is None else se.ctypes.data_as(C.POINTER(C.c_int32)))
         self.P = lib().orc_num_params(C.byref(self.s))
         assert self.P == m.n_params
 

@@ -35,6 +35,12 @@
  *  R12 secondary observable (section 2.4): per-species two-Gaussian mixture at
  *      the bin midpoint, renormalised over the bins, with nuisances
  *      (mean shift delta, width scale kappa, logit shift eta of weight 1).
+ *  R17 multivariate slice likelihood (section 2.4, cost model Eq.3): the energy
+ *      histogram's Poisson likelihood plus, per energy slice, the likelihood of
+ *      the slice's secondary-observable histogram given its total (multinomial:
+ *      n_i. ln mu_i. - sum_k n_ik ln mu_ik), so that the energy information is
+ *      not counted twice; with one slice per energy bin it equals the joint 2-D
+ *      likelihood.
  */
 #include "oracle.h"
 
@@ -414,6 +420,71 @@ static int poisson_term(ld mu, ld n, ld *term, ld *g, int *range) {
   return 0;
 }
 
+/* R17: the multivariate slice likelihood, added into *nll and (if gr) the
+ * gradient.  Energy part: mu_dj = eps_d sum_s R_s F_js against n_dj = sum_k
+ * n_djk; slice i: N_si = sum_{j in i} F_js, mu_dik = eps_d sum_s R_s N_si P_sk,
+ * mu_di. = sum_k mu_dik, n_dik = sum_{j in i} n_djk, piece
+ * n_di. ln mu_di. - sum_k n_dik ln mu_dik.  Returns 0 on a domain error. */
+static int mv_terms(const orc_model *M, const double *theta, const ld *F, const ld *dF, const ld *P, const ld *dP,
+                    ld *nll, ld *gr, int *range) {
+  const int S = M->n_species, J = M->n_reco, K = M->n_psd, nr = n_resp(M->family);
+  for (int d = 0; d < M->n_datasets; d++) {
+    const ld eps = M->exposure[d];
+    for (int j = M->win_lo; j < M->win_hi; j++) {
+      ld mu = 0, n = 0;
+      for (int s = 0; s < S; s++) mu += (ld)theta[s] * F[(size_t)j * S + s];
+      mu = (double)(eps * mu);
+      for (int k = 0; k < K; k++) n += M->counts[((size_t)d * J + j) * K + k];
+      ld term, g;
+      if (!poisson_term(mu, n, &term, &g, range)) return 0;
+      *nll += term;
+      if (!gr) continue;
+      for (int s = 0; s < S; s++) {
+        gr[s] += g * eps * F[(size_t)j * S + s];
+        for (int p = 0; p < nr; p++) gr[S + p] += g * eps * theta[s] * dF[((size_t)j * S + s) * nr + p];
+      }
+    }
+    for (int i = 0; i < M->n_slices; i++) {
+      const int j0 = M->slice_edges[i], j1 = M->slice_edges[i + 1];
+      for (int k0 = 0; k0 <= K; k0++) {
+        /* k0 < K: the bin k0 of the slice's histogram (weight -n_ik); k0 = K: its
+         * total (weight +n_i.) */
+        ld mu = 0, n = 0;
+        for (int s = 0; s < S; s++) {
+          ld Ns = 0;
+          for (int j = j0; j < j1; j++) Ns += F[(size_t)j * S + s];
+          mu += (ld)theta[s] * Ns * (k0 < K ? P[(size_t)s * K + k0] : 1);
+        }
+        mu = (double)(eps * mu);
+        for (int j = j0; j < j1; j++)
+          for (int k = 0; k < K; k++)
+            if (k0 == K || k == k0) n += M->counts[((size_t)d * J + j) * K + k];
+        if (n == 0) continue;
+        if (!(mu > 0)) return 0;
+        if (!isfinite((double)n / (double)mu)) *range = 1;
+        const ld sign = k0 < K ? -1 : 1;
+        *nll += sign * n * logl(mu);
+        if (!gr) continue;
+        const ld g = sign * n / mu; /* d piece / d mu */
+        for (int s = 0; s < S; s++) {
+          const ld pk = k0 < K ? P[(size_t)s * K + k0] : 1;
+          ld Ns = 0;
+          for (int j = j0; j < j1; j++) Ns += F[(size_t)j * S + s];
+          gr[s] += g * eps * Ns * pk;
+          for (int p = 0; p < nr; p++) {
+            ld dN = 0;
+            for (int j = j0; j < j1; j++) dN += dF[((size_t)j * S + s) * nr + p];
+            gr[S + p] += g * eps * theta[s] * dN * pk;
+          }
+          if (k0 < K)
+            for (int v = 0; v < 3; v++) gr[S + nr + v] += g * eps * theta[s] * Ns * dP[((size_t)s * K + k0) * 3 + v];
+        }
+      }
+    }
+  }
+  return 1;
+}
+
 double orc_nll_grad(const orc_model *M, const double *theta, double *grad, uint32_t *st) {
   const int S = M->n_species, J = M->n_reco, fam = M->family, nr = n_resp(fam);
   const int K = M->n_psd > 0 ? M->n_psd : 1, Pn = orc_num_params(M);
@@ -436,6 +507,9 @@ double orc_nll_grad(const orc_model *M, const double *theta, double *grad, uint3
   ld nll = 0;
   int range = 0;
   ld *gr = calloc((size_t)Pn, sizeof(ld));
+  if (ok && M->n_slices > 0) {
+    ok = mv_terms(M, theta, F, dF, P, dP, &nll, grad ? gr : NULL, &range);
+  } else
   for (int d = 0; d < M->n_datasets && ok; d++) {
     ld eps = M->exposure[d];
     for (int j = M->win_lo; j < M->win_hi && ok; j++)

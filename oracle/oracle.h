@@ -49,6 +49,13 @@ typedef struct {
   double birks_A;
   const double *pull_centre; /* [n_params]                                            */
   const double *pull_sigma;  /* [n_params]; <= 0 means no pull                        */
+  /* Multivariate slice likelihood (section 2.4; n_psd > 0): 0 = the joint 2-D
+   * likelihood over every (energy, pulse-shape) bin; n > 0 = the energy
+   * likelihood plus one secondary-observable piece per energy slice, slice i
+   * covering reco bins [slice_edges[i], slice_edges[i+1]), the slices tiling
+   * the window. */
+  int32_t n_slices;
+  const int32_t *slice_edges;  /* [n_slices + 1]                                        */
 } orc_model;
 
 int32_t orc_num_params(const orc_model *M);

@@ -37,6 +37,8 @@ MUTANTS = {
                        "if (n > 0 && !isfinite((double)n / (double)mu)) return 0;"),
     "discovery_sign": ("*t = 2.0 * (res_null->nll - res_free->nll);", "*t = 2.0 * (res_free->nll - res_null->nll);"),
     "discovery_signal_left_free": ("&& p != signal);", ");"),
+    "mv_piece_sign": ("const ld sign = k0 < K ? -1 : 1;", "const ld sign = k0 < K ? 1 : -1;"),
+    "mv_total_dropped": ("if (k0 == K || k == k0) n +=", "if (k == k0) n +="),
     "bfgs_update_sign": ("(rho * rho * yHy + rho) * sv[i] * sv[j]", "(rho * rho * yHy - rho) * sv[i] * sv[j]"),
 }
 

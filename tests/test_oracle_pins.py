@@ -623,3 +623,69 @@ def test_template_equals_analytic_at_fixed_response(orc, c1):
         # the template path rounds F to FP64 once; the analytic path keeps it in long double
         assert vt == pytest.approx(v, rel=1e-14)
         np.testing.assert_allclose(gt, g[:S], rtol=1e-9, atol=1e-9)
+
+
+# ------------------------------------------ multivariate slice likelihood ----
+def _mv_small(slice_width, n_datasets=2, species=None):
+    m = gsgen.small_gamma_model(n_true=150, n_reco=60, seed=9, n_psd=13, n_datasets=n_datasets).replace(
+        win_lo=3, win_hi=57)
+    if species is not None:
+        S = m.n_species
+        keep = np.r_[species, S:m.n_params]
+        m = m.replace(spectra=m.spectra[species:species + 1], line_energy=m.line_energy[species:species + 1],
+                      psd_mix=m.psd_mix[species:species + 1], theta_true=m.theta_true[keep],
+                      theta0=m.theta0[keep], pull_centre=m.pull_centre[keep], pull_sigma=m.pull_sigma[keep],
+                      fd_scale=m.fd_scale[keep])
+    return gsgen.multivariate_model(m, slice_width)
+
+
+def test_mv_single_bin_slices_equal_joint_2d(orc):
+    """R17: with one slice per energy bin, the energy likelihood plus the slices' pieces is the
+    joint 2-D Poisson likelihood, term by term (a Poisson histogram factorises into the Poisson
+    total times the multinomial of its bins): -ln L and the gradient agree."""
+    mv = _mv_small(1)
+    joint = mv.replace(slice_edges=None)
+    for th in (mv.theta_true, gsgen.offset_point(mv, 2.0, seed=4)):
+        th = th.copy()
+        th[-3:] = (0.03, 1.08, -0.2)
+        v, g, st = orc.Oracle(mv).nll_grad(th)
+        vj, gj, stj = orc.Oracle(joint).nll_grad(th)
+        assert st == stj == 0
+        assert v == pytest.approx(vj, rel=1e-13)
+        np.testing.assert_allclose(g, gj, rtol=1e-10, atol=1e-8)
+
+
+def test_mv_slice_piece_one_species_closed_form(orc):
+    """With one species the slice's expected pulse-shape shape is the species' own
+    probabilities, so each slice contributes -sum_k n_ik ln P_k: -ln L = the energy histogram's
+    Poisson terms (the joint expectation summed over pulse-shape bins) + that sum, with P from
+    the pulse-shape probabilities (pinned against the mixture's CDFs)."""
+    mv = _mv_small(9, species=2)
+    o = orc.Oracle(mv)
+    th = mv.theta_true.copy()
+    th[-3:] = (-0.02, 0.95, 0.3)
+    mu = orc.Oracle(mv.replace(slice_edges=None)).expected(th)  # [D][J][K]
+    P = o.psd_probs(th)[0]
+    ref = []
+    for d in range(mv.n_datasets):
+        for j in range(mv.win_lo, mv.win_hi):
+            n, m_ = mv.counts[d, j].sum(), mu[d, j].sum()
+            ref.append(m_ - (n * math.log(m_) if n > 0 else 0.0))
+        for i in range(len(mv.slice_edges) - 1):
+            nk = mv.counts[d, mv.slice_edges[i]:mv.slice_edges[i + 1]].sum(axis=0)
+            ref.extend(-nk[nk > 0] * np.log(P[nk > 0]))
+    v, st = o.nll(th)
+    assert st == 0 and v == pytest.approx(math.fsum(ref), rel=1e-13)
+
+
+def test_mv_gradient_vs_richardson(orc):
+    mv = _mv_small(7)
+    o = orc.Oracle(mv)
+    th = gsgen.offset_point(mv, 1.5, seed=6)
+    th[-3:] = (0.01, 1.05, 0.1)
+    v, g, st = o.nll_grad(th)
+    assert st == 0
+    f = lambda t: o.nll(t)[0]
+    for p in range(mv.n_params):
+        fd = _richardson(f, th, p, 1e-4 * mv.fd_scale[p])
+        assert abs(g[p] - fd) * mv.fd_scale[p] <= 1e-6 * max(abs(fd) * mv.fd_scale[p], 1.0), (p, g[p], fd)
