@@ -501,7 +501,9 @@ def main():
         log(f"bench: study {json.dumps(study)}")
         singles = {}
         for key, fn in (("c0_energy_family", gsgen.config0), ("c1_borexino_scale", gsgen.config1),
-                        ("c2_pulse_shape", gsgen.config2), ("template_900_bins", gsgen.template_model)):
+                        ("c2_pulse_shape", gsgen.config2),
+                        ("c2_multivariate_10_slices", lambda: gsgen.multivariate_model(gsgen.config2(), 90)),
+                        ("template_900_bins", gsgen.template_model)):
             singles[key] = single_model(gs, torch, fn(), fits=not args.no_fits)
             log(f"bench: {key} {json.dumps(singles[key])}")
         log("bench: Monte Carlo template study")

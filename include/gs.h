@@ -121,6 +121,17 @@ typedef struct {
   double birks_A;             /* stopping-power constant of the quenching model (> 0)      */
   const double *pull_centre;  /* [n_params] or NULL (no pulls)                             */
   const double *pull_sigma;   /* [n_params] or NULL; sigma <= 0 means no pull on that one  */
+  /* Multivariate slice likelihood (section 2.4, cost model Eq.3), for n_psd > 0:
+   * n_slices = 0 gives the joint likelihood over every (energy, pulse-shape)
+   * bin; n_slices > 0 gives the energy histogram's likelihood (counts summed
+   * over the pulse-shape bins) plus, for each energy slice i (reco bins
+   * [slice_edges[i], slice_edges[i+1]), the slices tiling [win_lo, win_hi)),
+   * the likelihood of the slice's pulse-shape histogram given its total:
+   * n_i. ln mu_i. - sum_k n_ik ln mu_ik with mu_ik = eps sum_s R_s P_sk
+   * sum_{j in i} F_js.  With one slice per bin this equals the joint
+   * likelihood; fewer slices cost fewer bins. */
+  int32_t n_slices;
+  const int32_t *slice_edges; /* [n_slices + 1] or NULL (n_slices = 0)                     */
 } gs_model_desc;
 
 typedef struct gs_model gs_model;

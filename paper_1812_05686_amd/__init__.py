@@ -33,7 +33,16 @@ class gs_model_desc(C.Structure):
                 ("psd_edges", _dp), ("psd_mix", _dp), ("n_datasets", C.c_int32),
                 ("exposure", _dp), ("counts", _dp), ("win_lo", C.c_int32), ("win_hi", C.c_int32),
                 ("family", C.c_int32), ("birks_A", C.c_double), ("pull_centre", _dp),
-                ("pull_sigma", _dp)]
+                ("pull_sigma", _dp), ("n_slices", C.c_int32), ("slice_edges", C.POINTER(C.c_int32))]
+
+
+def _slices(m):
+    se = getattr(m, "slice_edges", None)
+    return None if se is None else np.ascontiguousarray(se, dtype=np.int32)
+
+
+def _sptr(se):
+    return None if se is None else se.ctypes.data_as(C.POINTER(C.c_int32))
 
 
 class gs_fit_opts(C.Structure):
@@ -151,12 +160,12 @@ def make_desc(m):
     """Marshal a model description (any object with the gsgen.Model fields) into the C struct.
     Returns (desc, keepalive) -- keep `keepalive` referenced while the struct is used."""
     keep = [_arr(m.spectra), _arr(m.line_energy), _arr(m.reco_edges), _arr(m.psd_edges), _arr(m.psd_mix),
-            _arr(m.exposure), _arr(m.counts), _arr(m.pull_centre), _arr(m.pull_sigma)]
-    sp, le, re_, pe, pm, ex, cn, pc, ps = keep
+            _arr(m.exposure), _arr(m.counts), _arr(m.pull_centre), _arr(m.pull_sigma), _slices(m)]
+    sp, le, re_, pe, pm, ex, cn, pc, ps, se = keep
     d = gs_model_desc(int(m.n_true), float(m.e_lo), float(m.e_step), int(sp.shape[0]), _ptr(sp), _ptr(le),
                       int(len(re_) - 1), _ptr(re_), 0 if pe is None else int(len(pe) - 1), _ptr(pe), _ptr(pm),
                       int(len(ex)), _ptr(ex), _ptr(cn), int(m.win_lo), int(m.win_hi), int(m.family),
-                      float(m.birks_A), _ptr(pc), _ptr(ps))
+                      float(m.birks_A), _ptr(pc), _ptr(ps), 0 if se is None else len(se) - 1, _sptr(se))
     return d, keep
 
 
@@ -257,13 +266,15 @@ class Batch:
 
         for t, m in enumerate(models):
             arrs = [shared(m.spectra), shared(m.line_energy), shared(m.reco_edges), shared(m.psd_edges),
-                    shared(m.psd_mix), _arr(m.exposure), _arr(m.counts), _arr(m.pull_centre), _arr(m.pull_sigma)]
+                    shared(m.psd_mix), _arr(m.exposure), _arr(m.counts), _arr(m.pull_centre), _arr(m.pull_sigma),
+                    _slices(m)]
             self._keep.append(arrs)
-            sp, le, re_, pe, pm, ex, cn, pc, ps = arrs
+            sp, le, re_, pe, pm, ex, cn, pc, ps, se = arrs
             descs[t] = gs_model_desc(int(m.n_true), float(m.e_lo), float(m.e_step), int(sp.shape[0]), _ptr(sp),
                                      _ptr(le), int(len(re_) - 1), _ptr(re_), 0 if pe is None else int(len(pe) - 1),
                                      _ptr(pe), _ptr(pm), int(len(ex)), _ptr(ex), _ptr(cn), int(m.win_lo),
-                                     int(m.win_hi), int(m.family), float(m.birks_A), _ptr(pc), _ptr(ps))
+                                     int(m.win_hi), int(m.family), float(m.birks_A), _ptr(pc), _ptr(ps),
+                                     0 if se is None else len(se) - 1, _sptr(se))
         h = C.c_void_p()
         _check(lib().gs_batch_create(descs, len(models), device, C.byref(h)), "gs_batch_create")
         self._keep = None  # the library copied everything

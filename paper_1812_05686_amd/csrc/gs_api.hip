@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <tuple>
 #include <chrono>
 #include <vector>
 
@@ -103,6 +104,15 @@ int validate(const gs_model_desc *d) {
       if (!(m[0] > 0 && m[0] < 1) || !(m[2] > 0) || !(m[4] > 0) || !std::isfinite(m[1]) || !std::isfinite(m[3]))
         return bad("psd_mix of species %d invalid", s);
     }
+  }
+  if (d->n_slices < 0) return bad("n_slices < 0");
+  if (d->n_slices > 0) {
+    if (d->n_psd < 1) return bad("energy slices need a secondary observable (n_psd > 0)");
+    if (!d->slice_edges) return bad("slice_edges is NULL");
+    if (d->slice_edges[0] != d->win_lo || d->slice_edges[d->n_slices] != d->win_hi)
+      return bad("slice_edges must start at win_lo and end at win_hi");
+    for (int i = 0; i < d->n_slices; i++)
+      if (!(d->slice_edges[i + 1] > d->slice_edges[i])) return bad("slice_edges not strictly increasing at %d", i);
   }
   if (d->n_datasets < 1 || d->n_datasets > GS_MAX_DATASETS)
     return bad("n_datasets %d outside 1..%d", d->n_datasets, GS_MAX_DATASETS);
@@ -207,7 +217,7 @@ struct gs_batch {
   double graph_tol = -1.0;
   bool graph_compact = false;  // the instantiated graph covers a compacted toy list
   // compacted toy and work-item lists of a batched fit (device copies)
-  int *d_toy_list = nullptr, *d_list1 = nullptr, *d_list2 = nullptr, *d_listt = nullptr;
+  int *d_toy_list = nullptr, *d_list1 = nullptr, *d_list2 = nullptr, *d_listt = nullptr, *d_tgroup = nullptr;
   // discovery test: the null fit's start and free mask, iteration counts
   double *d_th0_null = nullptr;
   uint8_t *d_free_null = nullptr;
@@ -383,6 +393,7 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
   v.adj_waves = k.adj_waves;
   v.max_cell_blocks = v.max_bin_blocks = v.max_bin_blocks1 = v.max_bin_blocks2 = v.max_hblocks = 0;
   v.max_bin_blocks_t = 0;
+  v.max_eblocks = 0;
   B->fold_h.clear();
   B->fold1_h.clear();
   B->adj_h.clear();
@@ -397,9 +408,14 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     T.adj_chunks = (T.L + bpc - 1) / bpc;
     const long long c2 = (long long)kBlock * k.iter2;
     T.bin_blocks = T.two_d  ? (int)(((long long)T.L * T.K + c2 - 1) / c2)
-                   : T.tmpl ? (T.L + kBlock * kTmplIter - 1) / (kBlock * kTmplIter)
+                   : T.tmpl ? (T.L + kTmplBlockBins - 1) / kTmplBlockBins
                             : (T.L + kBlock - 1) / kBlock;
     T.hblocks = T.two_d ? (T.L + kHTile * k.iter2 - 1) / (kHTile * k.iter2) : 0;
+    if (T.mv) {  // rows of k_mv_bins (energy blocks), then one per slice (k_mv_slice)
+      T.eblocks = (T.L + kHTile - 1) / kHTile;
+      T.hblocks = T.eblocks;
+      T.bin_blocks = T.eblocks + T.n_slices;
+    }
     // template toys keep one rate-gradient row per bin block where other toys keep one per cell block
     T.cell_blocks = T.tmpl ? T.bin_blocks : (sh.n_cell + k.grad_cells - 1) / k.grad_cells;
     T.vpart_off = z.vpart;
@@ -426,13 +442,37 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     z.gpart += T.cell_blocks;
     if (!T.tmpl) v.max_cell_blocks = std::max(v.max_cell_blocks, T.cell_blocks);
     v.max_bin_blocks = std::max(v.max_bin_blocks, T.bin_blocks);
-    int &mb = T.two_d ? v.max_bin_blocks2 : T.tmpl ? v.max_bin_blocks_t : v.max_bin_blocks1;
-    mb = std::max(mb, T.bin_blocks);
-    v.max_hblocks = std::max(v.max_hblocks, T.hblocks);
+    if (T.mv) {
+      v.max_eblocks = std::max(v.max_eblocks, T.eblocks);
+    } else {
+      int &mb = T.two_d ? v.max_bin_blocks2 : T.tmpl ? v.max_bin_blocks_t : v.max_bin_blocks1;
+      mb = std::max(mb, T.bin_blocks);
+      v.max_hblocks = std::max(v.max_hblocks, T.hblocks);
+    }
   }
   z.n_fold = B->fold_h.size() + B->fold1_h.size();
   z.n_adj = B->adj_h.size();
   return z;
+}
+
+// Template toys in the order k_tmpl takes them: stably sorted by (shape,
+// window, datasets), cut into groups of at most kTmplGroup that agree on all
+// three; grp receives (first position in lt, count) per group.
+static void tmpl_groups(const std::vector<ToyDev> &toys, std::vector<int> &lt, std::vector<int> &grp) {
+  auto key = [&](int t) {
+    const ToyDev &T = toys[t];
+    return std::make_tuple(T.shape, T.lo, T.L, T.D);
+  };
+  std::stable_sort(lt.begin(), lt.end(), [&](int a, int b) { return key(a) < key(b); });
+  grp.clear();
+  for (int i = 0; i < (int)lt.size(); i++) {
+    if (!grp.empty() && grp.back() < kTmplGroup && key(lt[grp[grp.size() - 2]]) == key(lt[i])) {
+      grp.back()++;
+    } else {
+      grp.push_back(i);
+      grp.push_back(1);
+    }
+  }
 }
 
 gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_batch **out) {
@@ -546,8 +586,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
 
   // ---- toys: the fields and offsets that do not depend on the layout knobs ----
   long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0;
-  long long cflag_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0;
+  long long cflag_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0, slice_off = 0, sig_n = 0;
   std::vector<double> cnt_h, pc_h, ps_h;
+  std::vector<int> sedge_h;
   BatchView &v = B->v;
   for (int t = 0; t < n_toys; t++) {
     const gs_model_desc &d = descs[t];
@@ -561,6 +602,18 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.K = std::max(d.n_psd, 1);
     T.two_d = d.n_psd > 0 ? 1 : 0;
     T.tmpl = d.family == GS_RESP_TEMPLATE ? 1 : 0;
+    T.mv = d.n_slices > 0 ? 1 : 0;
+    T.n_slices = d.n_slices;
+    T.slice_off = slice_off;
+    T.sig_off = sig_n;
+    if (T.mv) {
+      sig_n += (long long)d.n_slices * sh.S;
+      for (int i = 0; i <= d.n_slices; i++) sedge_h.push_back(d.slice_edges[i] - d.win_lo);
+      slice_off += d.n_slices + 1;
+      v.has_mv = true;
+      v.max_slices = std::max(v.max_slices, d.n_slices);
+      v.max_mv_cells = std::max(v.max_mv_cells, (d.win_hi - d.win_lo) * d.n_psd);
+    }
     T.psd_off = psd_off;
     if (T.two_d) {
       psd_off += (long long)sh.S * T.K;
@@ -583,9 +636,27 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.bref_off = bref_off;
     T.cnt_off = cnt_off;
     T.pull_off = pull_off;
-    for (int k = 0; k < T.D; k++)
-      for (int j = d.win_lo; j < d.win_hi; j++)
-        for (int q = 0; q < T.K; q++) cnt_h.push_back(d.counts[((size_t)k * d.n_reco + j) * T.K + q]);
+    if (T.mv) {
+      // the energy histogram [d][j], then each slice's pulse-shape histogram [d][i][k]
+      for (int k = 0; k < T.D; k++)
+        for (int j = d.win_lo; j < d.win_hi; j++) {
+          double n = 0.0;
+          for (int q = 0; q < T.K; q++) n += d.counts[((size_t)k * d.n_reco + j) * T.K + q];
+          cnt_h.push_back(n);
+        }
+      for (int k = 0; k < T.D; k++)
+        for (int i = 0; i < d.n_slices; i++)
+          for (int q = 0; q < T.K; q++) {
+            double n = 0.0;
+            for (int j = d.slice_edges[i]; j < d.slice_edges[i + 1]; j++)
+              n += d.counts[((size_t)k * d.n_reco + j) * T.K + q];
+            cnt_h.push_back(n);
+          }
+    } else {
+      for (int k = 0; k < T.D; k++)
+        for (int j = d.win_lo; j < d.win_hi; j++)
+          for (int q = 0; q < T.K; q++) cnt_h.push_back(d.counts[((size_t)k * d.n_reco + j) * T.K + q]);
+    }
     for (int p = 0; p < T.P; p++) {
       const bool has = d.pull_sigma && d.pull_sigma[p] > 0;
       pc_h.push_back(has ? d.pull_centre[p] : 0.0);
@@ -594,7 +665,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     cell_off += sh.n_cell;
     win_off += T.L;
     bref_off += (T.L + kABlock - 1) / kABlock;
-    cnt_off += (long long)T.D * T.L * T.K;
+    cnt_off += T.mv ? (long long)T.D * (T.L + (long long)T.n_slices * T.K) : (long long)T.D * T.L * T.K;
     cflag_off += T.cflag_blocks;
     ghull_off += (sh.n_true + kGroup - 1) / kGroup;
     pull_off += T.P;
@@ -637,6 +708,13 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.sup, (size_t)cell_off));
   HIP_TRY(B->alloc(&v.ghull, (size_t)std::max<long long>(ghull_off, 1)));
   HIP_TRY(B->alloc(&v.pflag, (size_t)n_toys));
+  if (v.has_mv) {
+    int *se;
+    HIP_TRY(B->alloc(&se, sedge_h.size()));
+    HIP_TRY(hipMemcpy(se, sedge_h.data(), sizeof(int) * sedge_h.size(), hipMemcpyHostToDevice));
+    v.sedge = se;
+    HIP_TRY(B->alloc(&v.sig, (size_t)sig_n));
+  }
   if (v.has_2d) {
     HIP_TRY(B->alloc(&v.H, (size_t)win_off * GS_MAX_SPECIES));
     HIP_TRY(B->alloc(&v.P, (size_t)psd_off));
@@ -663,18 +741,32 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     if (us != GS_OK) return us;
   }
   if ((v.n1d > 0) + (v.n2d > 0) + (v.nt > 0) > 1) {  // a mixed batch: kernels of one kind take their toys from a list
-    std::vector<int> l1, l2, lt;
-    for (int t = 0; t < n_toys; t++) (B->toys_h[t].two_d ? l2 : B->toys_h[t].tmpl ? lt : l1).push_back(t);
-    int *d1, *d2, *dt;
+    std::vector<int> l1, l2;
+    for (int t = 0; t < n_toys; t++)
+      if (!B->toys_h[t].tmpl) (B->toys_h[t].two_d ? l2 : l1).push_back(t);
+    int *d1, *d2;
     HIP_TRY(B->alloc(&d1, l1.size()));
     HIP_TRY(B->alloc(&d2, l2.size()));
-    HIP_TRY(B->alloc(&dt, lt.size()));
     if (!l1.empty()) HIP_TRY(hipMemcpy(d1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice));
     if (!l2.empty()) HIP_TRY(hipMemcpy(d2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice));
-    if (!lt.empty()) HIP_TRY(hipMemcpy(dt, lt.data(), sizeof(int) * lt.size(), hipMemcpyHostToDevice));
     v.list1d = d1;
     v.list2d = d2;
+  }
+  v.tgroup = nullptr;
+  v.n_tgroup = 0;
+  if (v.nt > 0) {  // template toys always go through a list: k_tmpl groups them by template
+    std::vector<int> lt, grp;
+    for (int t = 0; t < n_toys; t++)
+      if (B->toys_h[t].tmpl) lt.push_back(t);
+    tmpl_groups(B->toys_h, lt, grp);
+    int *dt, *dg;
+    HIP_TRY(B->alloc(&dt, lt.size()));
+    HIP_TRY(B->alloc(&dg, grp.size()));
+    HIP_TRY(hipMemcpy(dt, lt.data(), sizeof(int) * lt.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dg, grp.data(), sizeof(int) * grp.size(), hipMemcpyHostToDevice));
     v.listt = dt;
+    v.tgroup = dg;
+    v.n_tgroup = (int)grp.size() / 2;
   }
   HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(pc, pc_h.data(), pc_h.size() * 8, hipMemcpyHostToDevice));
@@ -722,6 +814,7 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
     HIP_TRY(timed(B, GS_K_REDF, st, [&] { return launch_reduceF(v, kOnly2D, active, st); }));
     HIP_TRY(launch_psd(v, d_theta, active, st));
     HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins2(v, d_theta, d_mu, active, st); }));
+    if (v.has_mv) HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_mv(v, d_theta, d_mu, active, st); }));
   }
   if (d_grad) {
     if (v.has_1d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
@@ -1226,6 +1319,7 @@ gs_status gs_nll(gs_model *M, const double *theta, double *nll, uint32_t *st) {
     HIP_TRY(launch_psd(B->v, M->d_theta, nullptr, M->stream));
     HIP_TRY(timed(B, GS_K_NLLF, M->stream,
                   [&] { return launch_bins2(B->v, M->d_theta, nullptr, nullptr, M->stream); }));
+    HIP_TRY(launch_mv(B->v, M->d_theta, nullptr, nullptr, M->stream));
   } else {
     HIP_TRY(timed(B, GS_K_NLLF, M->stream, [&] { return launch_binsF(B->v, M->d_theta, nullptr, M->stream); }));
   }
@@ -1276,6 +1370,7 @@ static gs_status qn_setup(gs_batch *B) {
   HIP_TRY(B->alloc(&B->d_list1, (size_t)n));
   HIP_TRY(B->alloc(&B->d_list2, (size_t)n));
   HIP_TRY(B->alloc(&B->d_listt, (size_t)n));
+  HIP_TRY(B->alloc(&B->d_tgroup, (size_t)n * 2));
   HIP_TRY(B->alloc(&B->d_fold_c, std::max<size_t>(B->cap.n_fold, 1)));
   HIP_TRY(B->alloc(&B->d_adj_c, std::max<size_t>(B->cap.n_adj, 1)));
   std::vector<int> np(n);
@@ -1359,7 +1454,10 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
     HIP_TRY(hipMemcpyAsync(B->d_toy_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, st));
   if (!l1.empty()) HIP_TRY(hipMemcpyAsync(B->d_list1, l1.data(), sizeof(int) * l1.size(), hipMemcpyHostToDevice, st));
   if (!l2.empty()) HIP_TRY(hipMemcpyAsync(B->d_list2, l2.data(), sizeof(int) * l2.size(), hipMemcpyHostToDevice, st));
+  std::vector<int> grp;
+  tmpl_groups(B->toys_h, lt, grp);
   if (!lt.empty()) HIP_TRY(hipMemcpyAsync(B->d_listt, lt.data(), sizeof(int) * lt.size(), hipMemcpyHostToDevice, st));
+  if (!grp.empty()) HIP_TRY(hipMemcpyAsync(B->d_tgroup, grp.data(), sizeof(int) * grp.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
   gs_status us = upload_items(B, fi, fi1, ai, B->d_fold_c, B->d_adj_c, out, st);
   if (us != GS_OK) return us;
@@ -1371,6 +1469,8 @@ static gs_status compact_view(gs_batch *B, hipStream_t st, BatchView &out) {
   out.n2d = (int)l2.size();
   out.listt = B->d_listt;
   out.nt = (int)lt.size();
+  out.tgroup = B->d_tgroup;
+  out.n_tgroup = (int)grp.size() / 2;
   return GS_OK;
 }
 

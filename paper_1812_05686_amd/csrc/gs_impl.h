@@ -33,7 +33,8 @@ constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response
 // 1024 cells); BatchView::grad_cells holds the choice
 constexpr int kGradCellsLarge = 1024;
 constexpr int kGradLargeBlocks = 16384;
-constexpr int kTmplIter = 4;  // window bins per k_tmpl thread (kBlock * kTmplIter per block)  // batches with at least this many kBlock-cell blocks use kGradCellsLarge
+constexpr int kTmplBlockBins = 1024;  // window bins per k_tmpl block (one partial row per toy and block)
+constexpr int kTmplGroup = 16;        // toys per k_tmpl group (the columns of its matrix products)
 
 // Structure shared by every toy of one shape (spectra, grid, binning).
 // Species are stored in internal order: grid species first, then lines;
@@ -56,6 +57,8 @@ struct ToyDev {
   int shape, D, lo, L, P, K, n_cell, S;
   int two_d;                    // 1: pulse-shape (secondary observable) model
   int tmpl;                     // 1: Monte Carlo template model (no fold, no response)
+  int mv;                       // 1: multivariate slice likelihood (2-D toys with energy slices)
+  int n_slices, eblocks;        // mv: energy slices; k_mv_bins blocks (kHTile window bins each)
   int fold_chunks, adj_chunks;
   int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: iter2 * kBlock bin x pulse-shape cells each) / cells (k_cellgrad)
   int hblocks;                  // 2-D: k_hseed blocks (kHTile window bins each)
@@ -75,6 +78,8 @@ struct ToyDev {
   long long vpart_off;  // 2-D: vpart[(vpart_off + r) * kVLen + e], rows: hblocks of k_hseed, then bin_blocks of k_bins2
   long long gam_off;    // 2-D: Gam[gam_off + b * K + k] = sum_d eps_d (1 - n/mu)
   long long psd_off;    // 2-D: P[psd_off + s * K + k], dP[(psd_off + s * K + k) * 3 + v]
+  long long slice_off;  // mv: slice edges sedge[slice_off + i] (window bins, n_slices + 1)
+  long long sig_off;    // mv: slice seeds sig[sig_off + i * S + s]
   double exposure[GS_MAX_DATASETS];
 };
 
@@ -95,6 +100,10 @@ struct BatchView {
   int n_list;
   // the same toys split by kind, for kernels of one kind (NULL list: toy_list / n_list)
   const int *list1d, *list2d, *listt;
+  // k_tmpl groups: pairs (first position in listt, count) of toys sharing
+  // shape, window and datasets
+  const int *tgroup;
+  int n_tgroup;
   int n1d, n2d, nt;  // 1-D analytic, 2-D and template toys
   int max_cells, max_cell_blocks, max_bin_blocks;
   int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)
@@ -139,6 +148,10 @@ struct BatchView {
   uint32_t *pflag;  // [toy]: invalid pulse-shape nuisance
   const double *theta_dev;  // parameters of the evaluation in flight (per-species adjoint)
   int max_bin_blocks_t;  // k_tmpl grid
+  int max_slices, max_eblocks, max_mv_cells;  // mv grids (slices; energy blocks; window bins x pulse-shape bins)
+  const int *sedge;      // mv: slice edges per toy
+  double *sig;           // mv: per (slice, species) seeds of the slice pieces
+  bool has_mv;
   bool has_1d, has_2d, has_tmpl;
 };
 
@@ -157,6 +170,7 @@ hipError_t launch_finish(const BatchView &v, const double *theta, double *nll, d
 hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st);
 hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out, hipStream_t st);
 hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st);
+hipError_t launch_mv(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st);
 hipError_t launch_tmpl(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st);
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st);

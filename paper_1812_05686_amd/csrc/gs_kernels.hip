@@ -1406,86 +1406,146 @@ hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out,
 // ---------------------------------------------------- Monte Carlo templates --
 // The Monte Carlo fit (section 3.2, cost model Eq.1): each species' reco
 // spectrum at unit rate is a template T_sj (the response is already in it),
-// so mu_dj = eps_d sum_s R_s T_sj needs no fold.  kBlock threads per block,
-// kTmplIter window bins per thread: mu, the Poisson terms of Eq.4, and the
-// block partials of -ln L and of the rate gradient
-// sum_j (sum_d eps_d (1 - n_dj/mu_dj)) T_sj, in a fixed order.  The toys of a
-// shape share its templates (species-major, so threads on consecutive bins
-// read consecutive doubles; they stay in cache); each toy's counts stream once.
-__global__ __launch_bounds__(256) void k_tmpl(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
-                                              const ShapeDev *__restrict__ shapes, const double *__restrict__ theta,
-                                              int stride, const double *__restrict__ cnt,
-                                              const uint8_t *__restrict__ active, double *__restrict__ nllp,
-                                              uint32_t *__restrict__ badp, double *__restrict__ gpart,
-                                              double *__restrict__ mu_out) {
-  __shared__ double lds[8];
-  __shared__ double part[kBlock / 64][GS_MAX_SPECIES];
-  __shared__ uint32_t bad_s;
-  // grid x: toys, y: bin blocks, so that consecutive workgroups (spread over
-  // the XCDs) are different toys on the same bins: each XCD reads a template
-  // tile once for all the toys that follow it instead of once per toy
-  const int t = toy_of(toy_list, blockIdx.x), blk = blockIdx.y;
-  if (active && !active[t]) return;
-  const ToyDev &T = toys[t];
-  if (blk >= T.bin_blocks || !T.tmpl) return;
-  const ShapeDev &Sh = shapes[T.shape];
-  const double *th = theta + (size_t)t * stride;
-  const int S = Sh.S;
-  if (threadIdx.x == 0) bad_s = 0u;
-  __syncthreads();
-  double rate[GS_MAX_SPECIES], g[GS_MAX_SPECIES];
+// so mu_dj = eps_d sum_s R_s T_sj needs no fold.  Toys that share a template
+// and window (a group of at most 16, formed on the host) make both sums dense
+// contractions over the shared T, which run on v_mfma_f64_16x16x4f64:
+//   mu^T[j][q]  = sum_s T[s][j] R[s][q]              (bins x toys, K = species)
+//   grad[s][q] += sum_j T[s][j] G[q][j],  G = sum_d eps_d (1 - n_dj/mu_dj)
+// A wave walks kTmplWaveBins bins of its group in chunks of 16.  Chunk row r
+// (0..15) stands for bin 4 (r % 4) + r / 4, so that the first product leaves
+// lane l with toy l % 16 at the four consecutive bins 4 (l / 16) + v of its
+// registers v (its counts are one 32-byte run), and register v is then the
+// B operand of the second product's step v as it stands (k = l / 16 is bin
+// 4k + v).  Padding species, bins past the window and empty toy slots carry
+// zeros into both products.  The four waves of a block cover kTmplBlockBins
+// consecutive bins and fold their partials through LDS in a fixed order into
+// one row per toy and block.
+constexpr int kTmplWaveBins = kTmplBlockBins / kWaves;
+static_assert(kTmplWaveBins % 16 == 0, "template chunks are 16 bins");
+
+__global__ __launch_bounds__(256) void k_tmpl(const int *__restrict__ toy_list, const int *__restrict__ groups,
+                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                              const double *__restrict__ theta, int stride,
+                                              const double *__restrict__ cnt, const uint8_t *__restrict__ active,
+                                              double *__restrict__ nllp, uint32_t *__restrict__ badp,
+                                              double *__restrict__ gpart, double *__restrict__ mu_out) {
+  __shared__ double gsh[kWaves][4][64];
+  __shared__ double nsh[kWaves][16];
+  __shared__ uint32_t bsh[kWaves][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane & 15, k4 = lane >> 4;
+  const int first = groups[2 * blockIdx.x], count = groups[2 * blockIdx.x + 1];
+  const int blk = blockIdx.y;
+  const ToyDev &L0 = toys[toy_of(toy_list, first)];  // the group shares shape, window and datasets
+  if (blk >= L0.bin_blocks) return;
+  const ShapeDev &Sh = shapes[L0.shape];
+  const int S = Sh.S, L = L0.L, D = L0.D;
+  // this lane's toy (column q of both products)
+  const int t = q < count ? toy_of(toy_list, first + q) : -1;
+  const bool live = t >= 0 && !(active && !active[t]);
+  const ToyDev &T = toys[live ? t : toy_of(toy_list, first)];
+  const double *tT = Sh.wcellT + L0.lo;  // T[s][j] at tT[s * n_true + j]
+  const size_t nt = (size_t)Sh.n_true;
+  // B operand of the first product: R[s = 4i + l/16][q]
+  double rB[4];
 #pragma unroll
-  for (int s = 0; s < GS_MAX_SPECIES; s++) {
-    rate[s] = s < S ? th[Sh.sp_of[s]] : 0.0;
-    g[s] = 0.0;
+  for (int i = 0; i < 4; i++) {
+    const int s = 4 * i + k4;
+    rB[i] = live && s < S ? theta[(size_t)t * stride + Sh.sp_of[s]] : 0.0;
   }
+  const double *cq = cnt + T.cnt_off;
+  const int nsteps = (S + 3) >> 2;  // first-product steps of 4 species
+  // first-product row r = l % 16 is bin 4 (r % 4) + r / 4 of the chunk
+  const int jA = 4 * (q & 3) + (q >> 2);
+  dbl4 gacc = {0.0, 0.0, 0.0, 0.0};
   double sum = 0.0;
   uint32_t bad = 0u;
-  for (int c = 0; c < kTmplIter; c++) {
-    const int b = (blk * kTmplIter + c) * kBlock + threadIdx.x;
-    if (b >= T.L) break;
-    const double *tj = Sh.wcellT + T.lo + b;
-    double mu1 = 0.0;
+  const int w0 = blk * kTmplBlockBins + wv * kTmplWaveBins;
+  // loads use clamped (in-bounds) indices and are unconditional, so that a
+  // chunk's loads issue together; what lies outside is zeroed by selects
+  const int sA[4] = {min(k4, S - 1), min(4 + k4, S - 1), min(8 + k4, S - 1), min(12 + k4, S - 1)};
+  const int sq = min(q, S - 1);
+  for (int c = 0; c < kTmplWaveBins; c += 16) {
+    const int n0 = w0 + c;
+    if (n0 >= L) break;
+    const int jb = n0 + 4 * k4;  // lane l: toy q at bins jb + v, v = 0..3
+    const bool inA = n0 + jA < L;
+    const int jAc = min(n0 + jA, L - 1);
+    double a[4], tA[4];
 #pragma unroll
-    for (int s = 0; s < GS_MAX_SPECIES; s++)
-      if (s < S) mu1 = __fma_rn(rate[s], tj[(size_t)s * Sh.n_true], mu1);
-    double G = 0.0;
-    for (int d = 0; d < T.D; d++) {
-      const double mu = T.exposure[d] * mu1;
-      const double n = cnt[T.cnt_off + (long long)d * T.L + b];
-      double term, gg;
-      bad |= poisson_term(mu, n, term, gg);
-      sum += term;
-      G = __fma_rn(T.exposure[d], gg, G);
-      if (mu_out) mu_out[(long long)d * T.L + b] = mu;
+    for (int i = 0; i < 4; i++) {
+      const double x = tT[sA[i] * nt + jAc];
+      a[i] = inA && 4 * i + k4 < S ? x : 0.0;
     }
 #pragma unroll
-    for (int s = 0; s < GS_MAX_SPECIES; s++)
-      if (s < S) g[s] = __fma_rn(G, tj[(size_t)s * Sh.n_true], g[s]);
-  }
-  if (bad) atomicOr(&bad_s, bad);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  wave_sum_n(g, S);
-  if (lane == 0)
+    for (int v = 0; v < 4; v++) {
+      const double x = tT[sq * nt + min(jb + v, L - 1)];
+      tA[v] = jb + v < L && q < S ? x : 0.0;
+    }
+    dbl4 mu1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s = 0; s < GS_MAX_SPECIES; s++)
-      if (s < S) part[wv][s] = g[s];
-  const double tot = block_sum(sum, lds);  // its barriers also order part and bad_s
-  if (threadIdx.x < S) {
-    double v = part[0][threadIdx.x];
-    for (int w = 1; w < kBlock / 64; w++) v += part[w][threadIdx.x];
-    gpart[(T.gpart_off + blk) * kGradLen + Sh.sp_of[threadIdx.x]] = v;
+    for (int i = 0; i < 4; i++)
+      if (i < nsteps) mu1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], rB[i], mu1, 0, 0, 0);
+    double G[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < D; d++) {
+      const double e = T.exposure[d];
+      const double *cd = cq + (long long)d * L;
+      double n[4];
+#pragma unroll
+      for (int v = 0; v < 4; v++) n[v] = cd[min(jb + v, L - 1)];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const bool ok = live && jb + v < L;
+        const double mu = e * mu1[v];
+        double term, gg;
+        const uint32_t f = poisson_term(mu, n[v], term, gg);
+        bad |= ok ? f : 0u;
+        sum += ok ? term : 0.0;
+        G[v] = ok ? __fma_rn(e, gg, G[v]) : 0.0;
+        if (mu_out && q == 0 && ok) mu_out[(long long)d * L + jb + v] = mu;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tA[v], G[v], gacc, 0, 0, 0);
   }
-  if (threadIdx.x == 0) {
+  // toy q's -ln L and flags over the four lanes that hold it
+  sum += __shfl_xor(sum, 16);
+  sum += __shfl_xor(sum, 32);
+  bad |= __shfl_xor(bad, 16);
+  bad |= __shfl_xor(bad, 32);
+#pragma unroll
+  for (int v = 0; v < 4; v++) gsh[wv][v][lane] = gacc[v];
+  if (k4 == 0) {
+    nsh[wv][q] = sum;
+    bsh[wv][q] = bad;
+  }
+  __syncthreads();
+  if (wv != 0 || !live) return;
+  // gacc register v of lane l is grad[s = l/16 + 4v][toy q]
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const int s = k4 + 4 * v;
+    if (s < S) {
+      double g = gsh[0][v][lane];
+      for (int w = 1; w < kWaves; w++) g += gsh[w][v][lane];
+      gpart[(T.gpart_off + blk) * kGradLen + Sh.sp_of[s]] = g;
+    }
+  }
+  if (k4 == 0) {
+    double tot = nsh[0][q];
+    uint32_t b = bsh[0][q];
+    for (int w = 1; w < kWaves; w++) {
+      tot += nsh[w][q];
+      b |= bsh[w][q];
+    }
     nllp[T.nllp_off + blk] = tot;
-    badp[T.nllp_off + blk] = bad_s;
+    badp[T.nllp_off + blk] = b;
   }
 }
 
 hipError_t launch_tmpl(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st) {
-  if (v.nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tmpl, dim3(v.nt, v.max_bin_blocks_t), dim3(kBlock), 0, st, v.listt, v.toys, v.shapes, theta,
-                     v.stride, v.cnt, active, v.nllp, v.badp, v.gpart, mu_out);
+  if (v.nt == 0 || v.n_tgroup == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tmpl, dim3(v.n_tgroup, v.max_bin_blocks_t), dim3(kBlock), 0, st, v.listt, v.tgroup, v.toys,
+                     v.shapes, theta, v.stride, v.cnt, active, v.nllp, v.badp, v.gpart, mu_out);
   return hipGetLastError();
 }
 
@@ -1590,7 +1650,7 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
-  if ((int)blockIdx.x >= T.bin_blocks || !T.two_d) return;
+  if ((int)blockIdx.x >= T.bin_blocks || !T.two_d || T.mv) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int S = T.S, K = T.K, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x == 0) bad_s = 0u;
@@ -1669,7 +1729,7 @@ __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list,
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
-  if ((int)blockIdx.x >= T.hblocks || !T.two_d) return;
+  if ((int)blockIdx.x >= T.hblocks || !T.two_d || T.mv) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int S = T.S, K = T.K;
   for (int e = threadIdx.x; e < S * K; e += blockDim.x) ps[e] = P[T.psd_off + e];
@@ -1709,7 +1769,7 @@ __global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list,
 
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st) {
-  if (v.n2d == 0) return hipSuccess;
+  if (v.n2d == 0 || v.max_bin_blocks2 == 0) return hipSuccess;  // no joint 2-D toys (all multivariate)
   hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), sizeof(double) * 4 * v.max_psd_sk, st,
                      v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, v.iter2, active, v.Gam, v.nllp,
                      v.badp, v.vpart, mu_out);
@@ -1721,4 +1781,252 @@ hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out,
   return hipGetLastError();
 }
 
+// ------------------------------------------ multivariate slice likelihood --
+// The paper's multivariate likelihood (section 2.4, cost model Eq.3): the
+// energy histogram's Poisson likelihood (counts summed over the pulse-shape
+// bins) plus, per energy slice i, the likelihood of the slice's pulse-shape
+// histogram n_ik given its total n_i.: n_i. ln mu_i. - sum_k n_ik ln mu_ik with
+// mu_ik = eps sum_s R_s N_si P_sk and N_si = sum_{j in i} F_js.  Its gradient
+// with respect to F_js is R_s c_js, c_js = sum_d eps_d (1 - n_dj/mu_dj) +
+// sigma_s(slice of j), so the per-species adjoint takes H_js = dx_j c_js as
+// for the joint 2-D likelihood.  Counts of a multivariate toy are stored as
+// its energy histogram [d][j] followed by its slices' histograms [d][i][k].
+
+// Deterministic OR over a wavefront.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  uint32_t r = 0u;
+  for (uint32_t bit = 1u; bit <= 2u; bit <<= 1)
+    if (__ballot((v & bit) != 0u) != 0ull) r |= bit;
+  return r;
+}
+
+// One wave per (toy, slice): lane s sums N_si over the slice's bins; lanes over
+// k form the piece, the seeds sigma_si = sum_d eps_d (n_di./mu_di. -
+// sum_k n_dik P_sk/mu_dik) and the slice's partial of the pulse-shape
+// nuisance gradient, -sum_dk eps_d (n_dik/mu_dik) sum_s R_s N_si dP_sk/dnu.
+__global__ __launch_bounds__(64) void k_mv_slice(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                                 const ShapeDev *__restrict__ shapes, const double *__restrict__ theta,
+                                                 int stride, const double *__restrict__ F, const double *__restrict__ P,
+                                                 const double *__restrict__ dP, const double *__restrict__ cnt,
+                                                 const int *__restrict__ sedge, const uint8_t *__restrict__ active,
+                                                 double *__restrict__ sig, double *__restrict__ nllp,
+                                                 uint32_t *__restrict__ badp, double *__restrict__ vpart) {
+  const int t = toy_of(toy_list, blockIdx.y), i = blockIdx.x, lane = threadIdx.x;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if (!T.mv || i >= T.n_slices) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int S = T.S, K = T.K;
+  const double *th = theta + (size_t)t * stride;
+  const int j0 = sedge[T.slice_off + i], j1 = sedge[T.slice_off + i + 1];
+  double N = 0.0;
+  if (lane < S)
+    for (int j = j0; j < j1; j++) N += F[(T.win_off + j) * S + lane];
+  const double RN = lane < S ? th[Sh.sp_of[lane]] * N : 0.0;
+  double rn[GS_MAX_SPECIES];
+#pragma unroll
+  for (int s = 0; s < GS_MAX_SPECIES; s++) rn[s] = __shfl(RN, s, 64);  // R_s N_si, wave-uniform
+  const double *Pt = P + T.psd_off, *dPt = dP + 3 * T.psd_off;
+  const double *sc = cnt + T.cnt_off + (long long)T.D * T.L;  // the slices' histograms [d][slice][k]
+  double piece = 0.0, a[3] = {0.0, 0.0, 0.0}, sigma[GS_MAX_SPECIES];
+#pragma unroll
+  for (int s = 0; s < GS_MAX_SPECIES; s++) sigma[s] = 0.0;
+  uint32_t bad = 0u;
+  for (int d = 0; d < T.D; d++) {
+    const double eps = T.exposure[d];
+    double sg[GS_MAX_SPECIES], nsum = 0.0;
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++) sg[s] = 0.0;
+    for (int k = lane; k < K; k += 64) {
+      const double n = sc[((long long)d * T.n_slices + i) * K + k];
+      nsum += n;
+      if (!(n > 0.0)) continue;
+      double m = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+      for (int s = 0; s < GS_MAX_SPECIES; s++)
+        if (s < S) {
+          m = __fma_rn(rn[s], Pt[(size_t)s * K + k], m);
+          const double *dp = dPt + ((size_t)s * K + k) * 3;
+          m0 = __fma_rn(rn[s], dp[0], m0);
+          m1 = __fma_rn(rn[s], dp[1], m1);
+          m2 = __fma_rn(rn[s], dp[2], m2);
+        }
+      const double mu = eps * m;
+      if (!(mu > 0.0)) {
+        bad |= kBadDomain;
+        continue;
+      }
+      piece = __fma_rn(-n, log(mu), piece);
+      double q = n / mu;
+      if (!isfinite(q)) {
+        bad |= kBadRange;
+        q = 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < GS_MAX_SPECIES; s++)
+        if (s < S) sg[s] = __fma_rn(-q, Pt[(size_t)s * K + k], sg[s]);
+      a[0] = __fma_rn(-q * eps, m0, a[0]);
+      a[1] = __fma_rn(-q * eps, m1, a[1]);
+      a[2] = __fma_rn(-q * eps, m2, a[2]);
+    }
+    wave_sum_n(sg, S);
+    const double nd = wave_sum(nsum);  // n_di.
+    double tot = 0.0;
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++) tot += rn[s];
+    const double mud = eps * tot;       // mu_di.
+    double q0 = 0.0;
+    if (nd > 0.0) {
+      if (!(mud > 0.0)) {
+        bad |= kBadDomain;
+      } else {
+        if (lane == 0) piece = __fma_rn(nd, log(mud), piece);
+        q0 = nd / mud;
+        if (!isfinite(q0)) {
+          bad |= kBadRange;
+          q0 = 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++) sigma[s] = __fma_rn(eps, sg[s] + q0, sigma[s]);
+  }
+  piece = wave_sum(piece);
+  a[0] = wave_sum(a[0]);
+  a[1] = wave_sum(a[1]);
+  a[2] = wave_sum(a[2]);
+  bad = wave_or(bad);
+  if (lane < S) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < GS_MAX_SPECIES; s++) v = s == lane ? sigma[s] : v;
+    sig[T.sig_off + (long long)i * S + lane] = v;
+  }
+  if (lane == 0) {
+    nllp[T.nllp_off + T.eblocks + i] = piece;
+    badp[T.nllp_off + T.eblocks + i] = bad;
+    double *vp = vpart + (T.vpart_off + T.hblocks + T.eblocks + i) * kVLen + GS_MAX_SPECIES;
+    vp[0] = a[0];
+    vp[1] = a[1];
+    vp[2] = a[2];
+  }
+}
+
+// One thread per (window bin j, species slot q), kHTile bins per block: the
+// energy histogram's Poisson terms (block partial of -ln L), the per-species
+// seeds H_jq = dx_j c_jq for the adjoint, the bin record, and the block
+// partial of the rate gradient sum_j F_jq c_jq.
+__global__ __launch_bounds__(256) void k_mv_bins(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                                 const ShapeDev *__restrict__ shapes, const double *__restrict__ theta,
+                                                 int stride, const double *__restrict__ F, const double *__restrict__ cnt,
+                                                 const int *__restrict__ sedge, const double *__restrict__ sig,
+                                                 const uint8_t *__restrict__ active, double *__restrict__ binrec,
+                                                 double *__restrict__ bref, double *__restrict__ H,
+                                                 double *__restrict__ nllp, uint32_t *__restrict__ badp,
+                                                 double *__restrict__ vpart) {
+  __shared__ double red[kHTile][GS_MAX_SPECIES];
+  __shared__ double lds[8];
+  __shared__ uint32_t bad_s;
+  const int t = toy_of(toy_list, blockIdx.y), blk = blockIdx.x;
+  if (active && !active[t]) return;
+  const ToyDev &T = toys[t];
+  if (!T.mv || blk >= T.eblocks) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int S = T.S, jj = threadIdx.x / GS_MAX_SPECIES, q = threadIdx.x % GS_MAX_SPECIES;
+  const double *th = theta + (size_t)t * stride;
+  if (threadIdx.x == 0) bad_s = 0u;
+  __syncthreads();
+  const int b = blk * kHTile + jj;
+  double a = 0.0, term_sum = 0.0;
+  if (b < T.L) {
+    const double *Fr = F + (T.win_off + b) * S;
+    double mu1 = 0.0;
+    for (int s = 0; s < S; s++) mu1 = __fma_rn(th[Sh.sp_of[s]], Fr[s], mu1);
+    double e = 0.0;
+    uint32_t bad = 0u;
+    for (int d = 0; d < T.D; d++) {
+      const double mu = T.exposure[d] * mu1;
+      const double n = cnt[T.cnt_off + (long long)d * T.L + b];
+      double term, g;
+      bad |= poisson_term(mu, n, term, g);
+      if (q == 0) term_sum += term;
+      e = __fma_rn(T.exposure[d], g, e);
+    }
+    if (bad && q == 0) atomicOr(&bad_s, bad);
+    // the slice of bin b: the last slice edge at or below it
+    int lo = 0, hi = T.n_slices;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sedge[T.slice_off + mid] <= b) lo = mid; else hi = mid;
+    }
+    const double *bn = Sh.bins + (size_t)(T.lo + b) * kBinLen;
+    const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
+    if (q < S) {
+      const double c = e + sig[T.sig_off + (long long)lo * S + q];
+      H[(T.win_off + b) * S + q] = outside ? 0.0 : bn[1] * c;
+      a = Fr[q] * c;
+    }
+    if (q == 0) {
+      double *br = binrec + (T.win_off + b) * kBinRecLen;
+      br[0] = bn[0];
+      br[1] = bn[2];
+      br[2] = bn[3];
+      br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
+      br[4] = 0.0;
+      br[5] = 0.0;
+      block_offsets(Sh, T, b, bn, br[6], br[7], bref);
+    }
+  }
+  red[jj][q] = a;
+  const double tot = block_sum(term_sum, lds);  // its barriers also order red and bad_s
+  if (threadIdx.x < S) {
+    double v = red[0][threadIdx.x];
+    for (int j = 1; j < kHTile; j++) v += red[j][threadIdx.x];
+    vpart[(T.vpart_off + blk) * kVLen + threadIdx.x] = v;
+  }
+  if (threadIdx.x < 3) vpart[(T.vpart_off + T.hblocks + blk) * kVLen + GS_MAX_SPECIES + threadIdx.x] = 0.0;
+  if (threadIdx.x == 0) {
+    nllp[T.nllp_off + blk] = tot;
+    badp[T.nllp_off + blk] = bad_s;
+  }
+}
+
+// Expected counts of multivariate toys (the same joint expectation mu_djk as the
+// 2-D model's), for gs_expected: one thread per (window bin, pulse-shape bin).
+__global__ __launch_bounds__(256) void k_mv_expect(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+                                                   const ShapeDev *__restrict__ shapes,
+                                                   const double *__restrict__ theta, int stride,
+                                                   const double *__restrict__ F, const double *__restrict__ P,
+                                                   double *__restrict__ mu_out) {
+  const int t = toy_of(toy_list, blockIdx.y);
+  const ToyDev &T = toys[t];
+  if (!T.mv) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)T.L * T.K) return;
+  const int b = (int)(e / T.K), k = (int)(e - (long long)b * T.K);
+  const double *th = theta + (size_t)t * stride;
+  double M = 0.0;
+  for (int s = 0; s < T.S; s++)
+    M = __fma_rn(th[Sh.sp_of[s]] * F[(T.win_off + b) * T.S + s], P[T.psd_off + (long long)s * T.K + k], M);
+  for (int d = 0; d < T.D; d++) mu_out[((long long)d * T.L + b) * T.K + k] = T.exposure[d] * M;
+}
+
+hipError_t launch_mv(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st) {
+  if (!v.has_mv || v.n2d == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mv_slice, dim3(v.max_slices, v.n2d), dim3(64), 0, st, v.list2d, v.toys, v.shapes, theta,
+                     v.stride, v.F, v.P, v.dP, v.cnt, v.sedge, active, v.sig, v.nllp, v.badp, v.vpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mv_bins, dim3(v.max_eblocks, v.n2d), dim3(kHTile * GS_MAX_SPECIES), 0, st, v.list2d, v.toys,
+                     v.shapes, theta, v.stride, v.F, v.cnt, v.sedge, v.sig, active, v.binrec, v.bref, v.H, v.nllp,
+                     v.badp, v.vpart);
+  e = hipGetLastError();
+  if (e != hipSuccess || !mu_out) return e;
+  hipLaunchKernelGGL(k_mv_expect, dim3((v.max_mv_cells + kBlock - 1) / kBlock, v.n2d), dim3(kBlock), 0, st,
+                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, mu_out);
+  return hipGetLastError();
+}
+
 }  // namespace gs
+
