@@ -32,6 +32,7 @@ import numpy as np
 from scipy import special
 
 GAUSS_E, GAUSS_PE, GAMMA_PE, TEMPLATE = 0, 1, 2, 3
+GENGAMMA_PE, SPOIS_PE, EMG_PE = 4, 5, 6  # generalized gamma, scaled Poisson, modified Gaussian
 M_E = 0.51099895  # electron mass, MeV
 BIRKS_A = 2.0     # synthetic stopping-power constant, MeV^1.5/cm
 
@@ -64,6 +65,8 @@ class Model:
     species: list = field(default_factory=list)
     free: np.ndarray | None = None        # [P] bool, parameters a fit may move (None: all)
     slice_edges: np.ndarray | None = None  # [n_slices + 1] energy-bin edges of the multivariate slices
+    exact_bins: int = 0          # 1: reco-bin contents are the response's bin integrals
+    shape: float = 0.0           # generalized gamma power p / modified Gaussian tail fraction f
 
     @property
     def n_species(self) -> int:
@@ -161,12 +164,23 @@ def _nature_moments(model_family: int, e: np.ndarray, resp: np.ndarray, birks_a:
     return m, np.sqrt(a * a + b * m + c * c * m * m)
 
 
-def _nature_bin_probs(family: int, edges: np.ndarray, m: np.ndarray, s: np.ndarray) -> np.ndarray:
-    """[n_reco, n_cells] probability that a deposit with response moments (m, s) lands in each bin."""
-    if family == GAMMA_PE:
+def _nature_bin_probs(family: int, edges: np.ndarray, m: np.ndarray, s: np.ndarray, shape: float = 0.0) -> np.ndarray:
+    """[n_reco, n_cells] probability that a deposit with response moments (m, s) lands in each bin.
+    The scaled-Poisson family's data are drawn from the gamma law of the same moments."""
+    if family in (GAMMA_PE, SPOIS_PE):
         k = (m / s) ** 2
         th = s * s / m
         cdf = special.gammainc(k[None, :], np.maximum(edges, 0.0)[:, None] / th[None, :])
+    elif family == GENGAMMA_PE:
+        p = shape
+        k = (m / (p * s)) ** 2
+        th = m * np.exp(special.gammaln(k) - special.gammaln(k + 1.0 / p))
+        cdf = special.gammainc(k[None, :], (np.maximum(edges, 0.0)[:, None] / th[None, :]) ** p)
+    elif family == EMG_PE:
+        from scipy import stats
+        f = shape
+        sg = s * np.sqrt(1.0 - f * f)
+        cdf = stats.exponnorm.cdf(edges[:, None], (f * s / sg)[None, :], loc=(m - f * s)[None, :], scale=sg[None, :])
     else:
         cdf = special.ndtr((edges[:, None] - m[None, :]) / s[None, :])
     return np.diff(cdf, axis=0)
@@ -181,11 +195,11 @@ def nature_species_hist(model: Model, resp: np.ndarray) -> np.ndarray:
     grid = np.isnan(model.line_energy)
     for c0 in range(0, model.n_true, 1000):
         sl = slice(c0, min(c0 + 1000, model.n_true))
-        pr = _nature_bin_probs(model.family, model.reco_edges, m[sl], s[sl])
+        pr = _nature_bin_probs(model.family, model.reco_edges, m[sl], s[sl], model.shape)
         out[:, grid] += pr @ model.spectra[grid][:, sl].T
     for sp in np.nonzero(~grid)[0]:
         ml, sl_ = _nature_moments(model.family, np.array([model.line_energy[sp]]), resp, model.birks_A)
-        out[:, sp] = _nature_bin_probs(model.family, model.reco_edges, ml, sl_)[:, 0]
+        out[:, sp] = _nature_bin_probs(model.family, model.reco_edges, ml, sl_, model.shape)[:, 0]
     return out
 
 
@@ -619,7 +633,8 @@ def asimov(model: Model, mu: np.ndarray) -> Model:
     return model.replace(counts=np.asarray(mu, dtype=np.float64).reshape(model.counts.shape).copy())
 
 
-def small_gamma_model(n_true=300, n_reco=64, seed=7, n_psd=0, n_datasets=1, family=GAMMA_PE) -> Model:
+def small_gamma_model(n_true=300, n_reco=64, seed=7, n_psd=0, n_datasets=1, family=GAMMA_PE, shape=0.0,
+                      exact_bins=0) -> Model:
     """A small photoelectron-family model (lines, betas, exponentials) that the oracle
     evaluates in milliseconds; used for oracle pins and ragged GPU parity cases."""
     e_step = 3.0 / n_true
@@ -634,7 +649,8 @@ def small_gamma_model(n_true=300, n_reco=64, seed=7, n_psd=0, n_datasets=1, fami
               spectra=spectra, line_energy=le, reco_edges=edges, exposure=np.ones(n_datasets),
               counts=np.zeros((n_datasets, n_reco, max(n_psd, 1))), win_lo=0, win_hi=n_reco,
               pull_centre=theta.copy(), pull_sigma=np.zeros(S + 5), theta_true=theta,
-              theta0=theta.copy(), fd_scale=_scales_pe(S, rates), species=names)
+              theta0=theta.copy(), fd_scale=_scales_pe(S, rates), species=names, shape=shape,
+              exact_bins=exact_bins)
     if n_psd:
         mix = np.stack([g.uniform(0.3, 0.7, S), g.uniform(0.2, 0.8, S), g.uniform(0.05, 0.15, S),
                         g.uniform(0.2, 0.8, S), g.uniform(0.05, 0.15, S)], axis=1)
@@ -655,3 +671,13 @@ def offset_point(model: Model, sigma_mult: float = 2.0, seed: int = 0) -> np.nda
     """An off-minimum parameter point theta_true + sigma_mult * scale * u, u ~ U(-1, 1)."""
     u = _rng(200 + seed, 1).uniform(-1.0, 1.0, model.n_params)
     return model.theta_true + sigma_mult * model.fd_scale * u
+
+
+def family_model(family: int, shape: float = 0.0, exact_bins: int = 0, base: Model | None = None) -> Model:
+    """The Borexino-scale model (config 1 shape, 12 species on 4000 cells, 900 bins of 1.6 pe) with
+    another response family and/or exact bin contents, its data drawn from nature for that family."""
+    base = base or config1()
+    m = base.replace(name=f"{base.name}_f{family}" + ("x" if exact_bins else ""), family=family, shape=shape,
+                     exact_bins=exact_bins)
+    m.counts = draw_counts(nature_expected(m, m.theta_true), _rng(1, 0, 10 + family))
+    return m

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 ST_DOMAIN, ST_NONFINITE, ST_LS_FAIL, ST_MAXITER, ST_BFGS_RESET, ST_GRAD_RANGE = 1, 2, 4, 8, 16, 64
+GAUSS_E, GAUSS_PE, GAMMA_PE, TEMPLATE, GENGAMMA_PE, SPOIS_PE, EMG_PE = 0, 1, 2, 3, 4, 5, 6
 
 
 def build(force: bool = True, src: str | None = None, out: str | None = None) -> str:
@@ -46,7 +47,8 @@ class _Model(C.Structure):
                 ("counts", C.POINTER(C.c_double)), ("win_lo", C.c_int32), ("win_hi", C.c_int32),
                 ("family", C.c_int32), ("birks_A", C.c_double),
                 ("pull_centre", C.POINTER(C.c_double)), ("pull_sigma", C.POINTER(C.c_double)),
-                ("n_slices", C.c_int32), ("slice_edges", C.POINTER(C.c_int32))]
+                ("n_slices", C.c_int32), ("slice_edges", C.POINTER(C.c_int32)),
+                ("exact_bins", C.c_int32), ("shape", C.c_double)]
 
 
 class _FitOpts(C.Structure):
@@ -83,6 +85,15 @@ def lib():
         L.orc_density.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double]
         L.orc_density_dms.restype = None
         L.orc_density_dms.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_density3.restype = C.c_double
+        L.orc_density3.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_density_dms3.restype = None
+        L.orc_density_dms3.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_bin_content.restype = C.c_int32
+        L.orc_bin_content.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, dp, dp, dp]
+        L.orc_igam.restype = C.c_int32
+        L.orc_igam.argtypes = [C.c_double, C.c_double, dp, dp, dp]
         for fn in ("orc_species_fold", "orc_psd_probs", "orc_expected"):
             getattr(L, fn).restype = C.c_int32
             getattr(L, fn).argtypes = [C.POINTER(_Model), dp, dp]
@@ -121,7 +132,8 @@ class Oracle:
         self.s = _Model(m.n_true, m.e_lo, m.e_step, m.n_species, _p(sp), _p(le), m.n_reco, _p(re_),
                         m.n_psd, _p(pe), _p(pm), m.n_datasets, _p(ex), _p(cn), m.win_lo, m.win_hi,
                         m.family, m.birks_A, _p(pc), _p(ps), 0 if se is None else len(se) - 1,
-                        None if se is None else se.ctypes.data_as(C.POINTER(C.c_int32)))
+                        None if se is None else se.ctypes.data_as(C.POINTER(C.c_int32)),
+                        int(getattr(m, "exact_bins", 0)), float(getattr(m, "shape", 0.0)))
         self.P = lib().orc_num_params(C.byref(self.s))
         assert self.P == m.n_params
 
@@ -210,3 +222,29 @@ def density_dms(family, x, m, s):
     a, b = C.c_double(), C.c_double()
     lib().orc_density_dms(family, x, m, s, C.byref(a), C.byref(b))
     return a.value, b.value
+
+
+def density3(family, shape, x, m, s):
+    """Response density of any family (shape: the generalized gamma's power or the modified
+    Gaussian's tail fraction)."""
+    return lib().orc_density3(family, shape, x, m, s)
+
+
+def density_dms3(family, shape, x, m, s):
+    a, b = C.c_double(), C.c_double()
+    lib().orc_density_dms3(family, shape, x, m, s, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def bin_content(family, shape, exact, xlo, xhi, m, s):
+    """(K, dK/dm, dK/ds) of reco bin [xlo, xhi) for a deposit with response moments (m, s), or None."""
+    k, a, b = C.c_double(), C.c_double(), C.c_double()
+    ok = lib().orc_bin_content(family, shape, int(exact), xlo, xhi, m, s, C.byref(k), C.byref(a), C.byref(b))
+    return (k.value, a.value, b.value) if ok else None
+
+
+def igam(k, u):
+    """Regularised incomplete gamma (P, Q, dP/dk)."""
+    p, q, d = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_igam(k, u, C.byref(p), C.byref(q), C.byref(d))
+    return p.value, q.value, d.value

@@ -41,6 +41,21 @@
  *      n_i. ln mu_i. - sum_k n_ik ln mu_ik), so that the energy information is
  *      not counted twice; with one slice per energy bin it equals the joint 2-D
  *      likelihood.
+ *  R18 exact bin contents (section 2.5 evaluates the response on the mesh; a
+ *      model may ask for the bin integral instead of the midpoint rule): the
+ *      difference of the distribution function at the bin edges (erfc for the
+ *      Gaussian families, the regularised incomplete gamma for the gamma
+ *      families, a closed form for the modified Gaussian); none for the
+ *      scaled Poisson, whose continued density has no closed-form integral.
+ *  R19 generalized gamma (section 2.3 cites it without a formula): Stacy's
+ *      three-parameter form with the power p fixed per model, shape
+ *      k = m^2/(p^2 s^2) and the scale that makes the mean m.
+ *  R20 scaled Poisson (cited without a formula): x/g ~ Poisson(lambda) with
+ *      g = s^2/m, lambda = m^2/s^2, continued to real x >= 0 through the Gamma
+ *      function and not renormalised.
+ *  R21 modified Gaussian (cited without a formula): the exponentially
+ *      modified Gaussian with tail fraction f = tau/s fixed per model, mean m
+ *      and variance s^2.
  */
 #include "oracle.h"
 
@@ -136,7 +151,7 @@ static int moments_l(int fam, const double *resp, double A, ld E, mom_t *o) {
   ld m = LY * Q * E;
   ld s2 = a * a + b * m + c * c * m * m;
   if (!(s2 > 0) || !isfinite((double)s2)) return 0;
-  if (fam == ORC_GAMMA_PE && !(m > 0)) return 0;
+  if ((fam == ORC_GAMMA_PE || fam == ORC_GENGAMMA_PE || fam == ORC_SPOIS_PE) && !(m > 0)) return 0;
   ld s = sqrtl(s2);
   o->m = m;
   o->s = s;
@@ -160,67 +175,319 @@ int32_t orc_moments(int32_t family, const double *resp, double A, double E, doub
 }
 
 /* ------------------------------------------------------------ R8 shapes -- */
-/* Per-cell constants of the response density, computed once per true cell. */
+/* Regularised incomplete gamma P(k, u) = int_0^u t^(k-1) e^-t dt / Gamma(k),
+ * Q = 1 - P, and dP/dk (R18: the exact bin content of the gamma-type
+ * families).  Below u = k + 1 the series
+ *   P = e^-u u^k / Gamma(k+1) * sum_n prod_{i=1..n} u / (k + i)
+ * whose k-derivative is taken term by term; above it Legendre's continued
+ * fraction for Gamma(k, u) e^u u^-k, evaluated by the modified Lentz method
+ * with the derivative of every convergent w.r.t. k carried along. */
+static void igam_l(ld k, ld u, ld *P, ld *Q, ld *dP) {
+  if (!(u > 0)) {
+    *P = 0;
+    *Q = 1;
+    *dP = 0;
+    return;
+  }
+  const ld lu = logl(u);
+  if (u < k + 1) {
+    ld c = 1, S = 1, H = 0, dS = 0;
+    for (int n = 1; n < 100000; n++) {
+      H += 1 / (k + n);
+      c *= u / (k + n);
+      S += c;
+      dS -= c * H;
+      if (c < 1e-21L * S && c * H <= 1e-21L * fabsl(dS)) break;
+    }
+    const ld pre = expl(k * lu - u - lgammal(k + 1));
+    *P = pre * S;
+    *Q = 1 - *P;
+    *dP = pre * ((lu - digamma_l(k + 1)) * S + dS);
+    return;
+  }
+  const ld tiny = 1e-4000L;
+  ld b = u + 1 - k, db = -1;
+  ld c = 1 / tiny, dc = 0;
+  ld d = 1 / b, dd = 1 / (b * b);
+  ld h = d, dh = dd;
+  for (int i = 1; i < 100000; i++) {
+    const ld an = -(ld)i * (i - k), dan = i;
+    b += 2;
+    ld den = an * d + b;
+    const ld dden = dan * d + an * dd + db;
+    if (fabsl(den) < tiny) den = tiny;
+    const ld dn = 1 / den, ddn = -dden * dn * dn;
+    ld cn = b + an / c;
+    const ld dcn = db + dan / c - an * dc / (c * c);
+    if (fabsl(cn) < tiny) cn = tiny;
+    d = dn;
+    dd = ddn;
+    c = cn;
+    dc = dcn;
+    const ld del = d * c, ddel = dd * c + d * dc;
+    dh = dh * del + h * ddel;
+    h *= del;
+    if (fabsl(del - 1) < 1e-21L && fabsl(ddel * h) <= 1e-21L * fabsl(dh)) break;
+  }
+  const ld pre = expl(k * lu - u - lgammal(k));
+  *Q = pre * h;
+  *P = 1 - *Q;
+  *dP = -pre * ((lu - digamma_l(k)) * h + dh);
+}
+
+/* Per-cell constants of the response density, computed once per true cell.
+ * Families (R8, R19-R21), all with mean m and standard deviation s:
+ *  Gaussian        N(x; m, s^2)
+ *  gamma           shape k = m^2/s^2, scale th = s^2/m
+ *  gen. gamma      p x^(kp-1) exp(-(x/th)^p) / (Gamma(k) th^(kp)), power p
+ *                  (the model's shape parameter), k = m^2/(p^2 s^2),
+ *                  th = m Gamma(k) / Gamma(k + 1/p) (mean exactly m; the
+ *                  variance is s^2 up to O(1/k); p = 1 is the gamma family)
+ *  scaled Poisson  Poisson(x/g; lambda) / g continued to real x >= 0 by the
+ *                  Gamma function, g = s^2/m, lambda = m^2/s^2, not
+ *                  renormalised (its integral falls short of 1 by
+ *                  e^-lambda int_0^inf e^-lambda t / (t (pi^2 + ln^2 t)) dt)
+ *  mod. Gaussian   exponentially modified Gaussian: N(mu_g, sg^2) convolved
+ *                  with an exponential of mean tau, tau = f s,
+ *                  sg = s sqrt(1 - f^2), mu_g = m - tau (f: the model's
+ *                  shape parameter, 0 < f < 1). */
 typedef struct {
+  int fam;
   ld m, s;
-  ld k, th, lgk, lth, psik; /* gamma family */
-  ld norm;                  /* Gaussian family: 1/(s sqrt(2 pi)) */
+  ld k, th, lgk, lth, psik; /* gamma, generalized gamma */
+  ld p, dk_dm, dk_ds, dth_dm, dth_ds; /* generalized gamma */
+  ld g, lam, llam;          /* scaled Poisson */
+  ld mug, sg, tau, f;       /* modified Gaussian */
+  ld norm;                  /* Gaussian: 1/(s sqrt(2 pi)) */
 } dens_t;
 
-static void dens_prep(int fam, ld m, ld s, dens_t *d) {
+static int pe_positive(int fam) {
+  return fam == ORC_GAMMA_PE || fam == ORC_GENGAMMA_PE || fam == ORC_SPOIS_PE;
+}
+
+static int dens_prep(int fam, ld shape, ld m, ld s, dens_t *d) {
+  memset(d, 0, sizeof *d);
+  d->fam = fam;
   d->m = m;
   d->s = s;
-  if (fam == ORC_GAMMA_PE) {
-    ld s2 = s * s;
-    d->k = m * m / s2;
-    d->th = s2 / m;
-    d->lgk = lgammal(d->k);
-    d->lth = logl(d->th);
-    d->psik = digamma_l(d->k);
-  } else {
-    d->norm = 1 / (s * sqrtl(2 * PI_L));
+  if (!(s > 0) || !isfinite((double)m) || !isfinite((double)s)) return 0;
+  if (pe_positive(fam) && !(m > 0)) return 0;
+  ld s2 = s * s;
+  switch (fam) {
+    case ORC_GAMMA_PE:
+      d->k = m * m / s2;
+      d->th = s2 / m;
+      d->lgk = lgammal(d->k);
+      d->lth = logl(d->th);
+      d->psik = digamma_l(d->k);
+      d->dk_dm = 2 * m / s2;
+      d->dk_ds = -2 * m * m / (s2 * s);
+      d->dth_dm = -s2 / (m * m);
+      d->dth_ds = 2 * s / m;
+      return 1;
+    case ORC_GENGAMMA_PE: {
+      if (!(shape > 0) || !isfinite((double)shape)) return 0;
+      ld p = shape, k = m * m / (p * p * s2);
+      ld D = lgammal(k + 1 / p) - lgammal(k), dD = digamma_l(k + 1 / p) - digamma_l(k);
+      d->p = p;
+      d->k = k;
+      d->th = m * expl(-D);
+      d->lgk = lgammal(k);
+      d->lth = logl(d->th);
+      d->psik = digamma_l(k);
+      d->dk_dm = 2 * k / m;
+      d->dk_ds = -2 * k / s;
+      d->dth_dm = d->th / m - d->th * dD * d->dk_dm;
+      d->dth_ds = -d->th * dD * d->dk_ds;
+      return 1;
+    }
+    case ORC_SPOIS_PE:
+      d->g = s2 / m;
+      d->lam = m * m / s2;
+      d->llam = logl(d->lam);
+      return 1;
+    case ORC_EMG_PE:
+      if (!(shape > 0 && shape < 1)) return 0;
+      d->f = shape;
+      d->tau = shape * s;
+      d->sg = s * sqrtl(1 - shape * shape);
+      d->mug = m - d->tau;
+      return 1;
+    default:
+      d->norm = 1 / (s * sqrtl(2 * PI_L));
+      return 1;
   }
 }
 
-/* r(x | m, s) and d ln r / dm, d ln r / ds.  Gamma: shape k = m^2/s^2, scale
- * th = s^2/m, r = x^(k-1) exp(-x/th) / (Gamma(k) th^k) for x > 0. */
-static ld dens_eval(int fam, const dens_t *d, ld x, ld lx, ld *dm, ld *ds) {
-  if (fam == ORC_GAMMA_PE) {
-    if (!(x > 0)) {
-      if (dm) *dm = *ds = 0;
+/* Modified Gaussian: density r, the Gaussian factor phi = N(x; mu_g, sg^2)
+ * and dr / d(mu_g, sg, tau). */
+static ld emg_r(const dens_t *d, ld x, ld *phi, ld *rm, ld *rsg, ld *rt) {
+  const ld y = x - d->mug, sg = d->sg, t = d->tau;
+  const ld r = expl(-y / t + sg * sg / (2 * t * t)) * erfcl((sg * sg / t - y) / (sqrtl(2) * sg)) / (2 * t);
+  const ld ph = expl(-y * y / (2 * sg * sg)) / (sg * sqrtl(2 * PI_L));
+  *phi = ph;
+  *rm = (r - ph) / t;
+  *rsg = sg / (t * t) * (r - ph) - y / (sg * t) * ph;
+  *rt = r * (-1 / t + y / (t * t) - sg * sg / (t * t * t)) + sg * sg / (t * t * t) * ph;
+  return r;
+}
+
+/* r(x | m, s) and dr/dm, dr/ds. */
+static ld dens_eval(const dens_t *d, ld x, ld *dm, ld *ds) {
+  ld r, a, b;
+  switch (d->fam) {
+    case ORC_GAMMA_PE:
+    case ORC_GENGAMMA_PE: {
+      if (!(x > 0)) {
+        *dm = *ds = 0;
+        return 0;
+      }
+      const ld p = d->fam == ORC_GAMMA_PE ? 1 : d->p;
+      const ld y = logl(x) - d->lth, xp = expl(p * y); /* (x/th)^p */
+      r = p * expl((d->k * p - 1) * y - xp - d->lgk - d->lth);
+      a = p * y - d->psik;                   /* d ln r / dk     */
+      b = (p * xp - d->k * p) / d->th;       /* d ln r / dtheta */
+      *dm = r * (a * d->dk_dm + b * d->dth_dm);
+      *ds = r * (a * d->dk_ds + b * d->dth_ds);
+      return r;
+    }
+    case ORC_SPOIS_PE: {
+      if (x < 0) {
+        *dm = *ds = 0;
+        return 0;
+      }
+      const ld t = x / d->g, g = d->g, lam = d->lam;
+      r = expl(t * d->llam - lam - lgammal(t + 1)) / g;
+      a = -1 / g - t / g * (d->llam - digamma_l(t + 1)); /* d ln r / dg      */
+      b = t / lam - 1;                                  /* d ln r / dlambda */
+      *dm = r * (a * (-g / d->m) + b * (2 * lam / d->m));
+      *ds = r * (a * (2 * g / d->s) + b * (-2 * lam / d->s));
+      return r;
+    }
+    case ORC_EMG_PE: {
+      ld ph, rm, rsg, rt;
+      r = emg_r(d, x, &ph, &rm, &rsg, &rt);
+      *dm = rm;
+      *ds = -d->f * rm + sqrtl(1 - d->f * d->f) * rsg + d->f * rt;
+      return r;
+    }
+    default: {
+      const ld z = (x - d->m) / d->s;
+      r = d->norm * expl(-0.5L * z * z);
+      *dm = r * z / d->s;
+      *ds = r * (z * z - 1) / d->s;
+      return r;
+    }
+  }
+}
+
+/* Distribution function at x: F, Fc = 1 - F (each formed without
+ * cancellation), and dF/dm, dF/ds.  Returns 0 for the scaled Poisson, whose
+ * continued density has no closed-form integral (R18 offers it no exact bin
+ * content). */
+static int cdf_eval(const dens_t *d, ld x, ld *F, ld *Fc, ld *dm, ld *ds) {
+  switch (d->fam) {
+    case ORC_GAMMA_PE:
+    case ORC_GENGAMMA_PE: {
+      if (!(x > 0)) {
+        *F = 0;
+        *Fc = 1;
+        *dm = *ds = 0;
+        return 1;
+      }
+      const ld p = d->fam == ORC_GAMMA_PE ? 1 : d->p;
+      const ld u = expl(p * (logl(x) - d->lth));
+      ld dPk;
+      igam_l(d->k, u, F, Fc, &dPk);
+      const ld dPth = -p * expl(d->k * logl(u) - u - d->lgk) / d->th;
+      *dm = dPk * d->dk_dm + dPth * d->dth_dm;
+      *ds = dPk * d->dk_ds + dPth * d->dth_ds;
+      return 1;
+    }
+    case ORC_EMG_PE: {
+      ld ph, rm, rsg, rt;
+      const ld r = emg_r(d, x, &ph, &rm, &rsg, &rt), y = x - d->mug, sg = d->sg, t = d->tau;
+      *F = 0.5L * erfcl(-y / (sqrtl(2) * sg)) - t * r;
+      *Fc = 0.5L * erfcl(y / (sqrtl(2) * sg)) + t * r;
+      const ld Fm = -r, Fsg = -y / sg * ph - t * rsg, Ft = -r - t * rt;
+      *dm = Fm;
+      *ds = -d->f * Fm + sqrtl(1 - d->f * d->f) * Fsg + d->f * Ft;
+      return 1;
+    }
+    case ORC_SPOIS_PE:
       return 0;
+    default: {
+      const ld z = (x - d->m) / d->s, r = d->norm * expl(-0.5L * z * z);
+      *F = 0.5L * erfcl(-z / sqrtl(2));
+      *Fc = 0.5L * erfcl(z / sqrtl(2));
+      *dm = -r;
+      *ds = -z * r;
+      return 1;
     }
-    ld r = expl((d->k - 1) * lx - x / d->th - d->lgk - d->k * d->lth);
-    if (dm) {
-      ld s2 = d->s * d->s, m = d->m;
-      ld dk = lx - d->psik - d->lth;            /* d ln r / dk     */
-      ld dth = x / (d->th * d->th) - d->k / d->th; /* d ln r / dtheta */
-      *dm = dk * (2 * m / s2) + dth * (-s2 / (m * m));
-      *ds = dk * (-2 * m * m / (s2 * d->s)) + dth * (2 * d->s / m);
-    }
-    return r;
   }
-  ld z = (x - d->m) / d->s;
-  if (dm) {
-    *dm = z / d->s;
-    *ds = (z * z - 1) / d->s;
-  }
-  return d->norm * expl(-0.5L * z * z);
 }
 
-double orc_density(int32_t family, double x, double m, double s) {
+/* Content of reco bin [xlo, xhi) (midpoint xm, width dx) of a unit deposit,
+ * K = dx r(xm) (R3), or with exact bins (R18) the integral of r over the bin
+ * as a difference of distribution functions (taken on the lower or upper
+ * tail, whichever is the smaller); dK/dm, dK/ds.  Returns 0 if the family has
+ * no exact bin content. */
+static int bin_content(const dens_t *d, int exact, ld xlo, ld xhi, ld xm, ld dx, ld *K, ld *dm, ld *ds) {
+  if (!exact) {
+    ld a, b;
+    *K = dx * dens_eval(d, xm, &a, &b);
+    *dm = dx * a;
+    *ds = dx * b;
+    return 1;
+  }
+  ld Fl, Fcl, ml, sl, Fh, Fch, mh, sh;
+  if (!cdf_eval(d, xlo, &Fl, &Fcl, &ml, &sl) || !cdf_eval(d, xhi, &Fh, &Fch, &mh, &sh)) return 0;
+  *K = Fh < 0.5L ? Fh - Fl : Fcl - Fch;
+  *dm = mh - ml;
+  *ds = sh - sl;
+  return 1;
+}
+
+double orc_density(int32_t family, double x, double m, double s) { return orc_density3(family, 0.0, x, m, s); }
+
+double orc_density3(int32_t family, double shape, double x, double m, double s) {
   dens_t d;
-  dens_prep(family, m, s, &d);
-  return (double)dens_eval(family, &d, x, x > 0 ? logl(x) : 0, NULL, NULL);
+  ld a, b;
+  if (!dens_prep(family, shape, m, s, &d)) return NAN;
+  return (double)dens_eval(&d, x, &a, &b);
 }
 
 void orc_density_dms(int32_t family, double x, double m, double s, double *dm, double *ds) {
+  orc_density_dms3(family, 0.0, x, m, s, dm, ds);
+}
+
+void orc_density_dms3(int32_t family, double shape, double x, double m, double s, double *dm, double *ds) {
   dens_t d;
-  ld a, b;
-  dens_prep(family, m, s, &d);
-  dens_eval(family, &d, x, x > 0 ? logl(x) : 0, &a, &b);
-  *dm = (double)a;
-  *ds = (double)b;
+  ld a = NAN, b = NAN;
+  ld r = dens_prep(family, shape, m, s, &d) ? dens_eval(&d, x, &a, &b) : NAN;
+  *dm = r != 0 ? (double)(a / r) : 0.0;
+  *ds = r != 0 ? (double)(b / r) : 0.0;
+}
+
+int32_t orc_bin_content(int32_t family, double shape, int32_t exact, double xlo, double xhi, double m, double s,
+                        double *K, double *dKdm, double *dKds) {
+  dens_t d;
+  ld k, a, b;
+  if (!dens_prep(family, shape, m, s, &d)) return 0;
+  if (!bin_content(&d, exact, xlo, xhi, ((ld)xlo + xhi) / 2, (ld)xhi - xlo, &k, &a, &b)) return 0;
+  *K = (double)k;
+  *dKdm = (double)a;
+  *dKds = (double)b;
+  return 1;
+}
+
+int32_t orc_igam(double k, double u, double *P, double *Q, double *dPdk) {
+  ld p, q, d;
+  igam_l(k, u, &p, &q, &d);
+  *P = (double)p;
+  *Q = (double)q;
+  *dPdk = (double)d;
+  return 1;
 }
 
 /* ---------------------------------------------------------- fold (Eq.2) -- */
@@ -240,13 +507,11 @@ static int fold_l(const orc_model *M, const double *theta, ld *F, ld *dF) {
       for (int s = 0; s < S; s++) F[(size_t)j * S + s] = M->spectra[(size_t)s * M->n_true + j];
     return 1;
   }
-  ld *xb = malloc(sizeof(ld) * J), *dx = malloc(sizeof(ld) * J), *lx = malloc(sizeof(ld) * J);
+  ld *xb = malloc(sizeof(ld) * J), *dx = malloc(sizeof(ld) * J);
   ld *w = malloc(sizeof(ld) * S);
   for (int j = 0; j < J; j++) {
-    double c = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;
-    xb[j] = c;
+    xb[j] = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;
     dx[j] = (ld)M->reco_edges[j + 1] - (ld)M->reco_edges[j];
-    lx[j] = c > 0 ? logl(c) : 0;
   }
   int n_grid = 0;
   for (int s = 0; s < S; s++) n_grid += isnan(M->line_energy[s]) ? 1 : 0;
@@ -276,22 +541,24 @@ static int fold_l(const orc_model *M, const double *theta, ld *F, ld *dF) {
       break;
     }
     dens_t d;
-    dens_prep(fam, mo.m, mo.s, &d);
-    for (int j = 0; j < J; j++) {
-      ld dlm, dls;
-      ld K = dx[j] * dens_eval(fam, &d, xb[j], lx[j], dF ? &dlm : NULL, dF ? &dls : NULL);
-      for (int s = 0; s < S; s++) {
+    if (!dens_prep(fam, M->shape, mo.m, mo.s, &d)) {
+      ok = 0;
+      break;
+    }
+    for (int j = 0; j < J && ok; j++) {
+      ld K, dKm, dKs;
+      ok = bin_content(&d, M->exact_bins, M->reco_edges[j], M->reco_edges[j + 1], xb[j], dx[j], &K, &dKm, &dKs);
+      for (int s = 0; s < S && ok; s++) {
         if (w[s] == 0) continue;
         F[(size_t)j * S + s] += w[s] * K;
         if (dF)
           for (int p = 0; p < nr; p++)
-            dF[((size_t)j * S + s) * nr + p] += w[s] * K * (dlm * mo.dm[p] + dls * mo.ds[p]);
+            dF[((size_t)j * S + s) * nr + p] += w[s] * (dKm * mo.dm[p] + dKs * mo.ds[p]);
       }
     }
   }
   free(xb);
   free(dx);
-  free(lx);
   free(w);
   return ok;
 }

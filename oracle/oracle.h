@@ -26,7 +26,8 @@ extern "C" {
  * species' spectrum is already its reco histogram at unit rate, spectra
  * [n_species][n_reco] (n_true = n_reco), so there is no fold and no response
  * parameter. */
-enum { ORC_GAUSS_E = 0, ORC_GAUSS_PE = 1, ORC_GAMMA_PE = 2, ORC_TEMPLATE = 3 };
+enum { ORC_GAUSS_E = 0, ORC_GAUSS_PE = 1, ORC_GAMMA_PE = 2, ORC_TEMPLATE = 3,
+       ORC_GENGAMMA_PE = 4, ORC_SPOIS_PE = 5, ORC_EMG_PE = 6 };
 enum { ORC_ST_DOMAIN = 1u, ORC_ST_NONFINITE = 2u, ORC_ST_LS_FAIL = 4u,
        ORC_ST_MAXITER = 8u, ORC_ST_BFGS_RESET = 16u, ORC_ST_GRAD_RANGE = 64u };
 
@@ -56,6 +57,13 @@ typedef struct {
    * the window. */
   int32_t n_slices;
   const int32_t *slice_edges;  /* [n_slices + 1]                                        */
+  /* Reco-bin content (section 2.5 mesh): 0 = bin width x density at the
+   * midpoint, 1 = the density's integral over the bin (distribution-function
+   * differences; not for the scaled Poisson). */
+  int32_t exact_bins;
+  /* Shape parameter of the family: the power p of the generalized gamma,
+   * the tail fraction f = tau/s of the modified Gaussian; unused otherwise. */
+  double shape;
 } orc_model;
 
 int32_t orc_num_params(const orc_model *M);
@@ -69,6 +77,13 @@ int32_t orc_moments(int32_t family, const double *resp, double birks_A, double E
                     double *m, double *s);
 double orc_density(int32_t family, double x, double m, double s);
 void orc_density_dms(int32_t family, double x, double m, double s, double *dlnr_dm, double *dlnr_ds);
+double orc_density3(int32_t family, double shape, double x, double m, double s);
+void orc_density_dms3(int32_t family, double shape, double x, double m, double s, double *dlnr_dm, double *dlnr_ds);
+/* Content of reco bin [xlo, xhi) for a deposit with response moments (m, s), and its derivatives. */
+int32_t orc_bin_content(int32_t family, double shape, int32_t exact, double xlo, double xhi, double m, double s,
+                        double *K, double *dKdm, double *dKds);
+/* Regularised incomplete gamma P(k, u), Q = 1 - P and dP/dk. */
+int32_t orc_igam(double k, double u, double *P, double *Q, double *dPdk);
 
 /* F[j][s]: per-species reco spectrum at unit rate and exposure, all reco bins. */
 int32_t orc_species_fold(const orc_model *M, const double *theta, double *F);

@@ -13,16 +13,29 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 
 MUTANTS = {
-    "gamma_exponent_sign": ("- d->lgk - d->k * d->lth", "- d->lgk + d->k * d->lth"),
-    "gamma_dk_factor": ("*dm = dk * (2 * m / s2)", "*dm = dk * (m / s2)"),
+    "gamma_exponent_sign": ("- xp - d->lgk - d->lth);", "- xp - d->lgk + d->lth);"),
+    "gamma_dk_factor": ("d->dk_dm = 2 * m / s2;", "d->dk_dm = m / s2;"),
     "gamma_shape_transposed": ("d->k = m * m / s2;", "d->k = s2 / m;"),
     "quench_power": ("Q = 1 - 2 / y + 2 * L / (y * y);", "Q = 1 - 2 / y + 2 * L / y;"),
     "quench_deriv_sign": ("*dQ_dkB = dQdy * (-y / kB);", "*dQ_dkB = dQdy * (y / kB);"),
     "resolution_b_term": ("o->ds[3] = m / (2 * s);", "o->ds[3] = m / s;"),
     "resolution_c_dropped": ("ld s2 = a * a + b * m + c * c * m * m;", "ld s2 = a * a + b * m;"),
-    "bin_width_dropped": ("ld K = dx[j] * dens_eval(", "ld K = dens_eval("),
-    "bin_centre_edge": ("double c = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;",
-                        "double c = M->reco_edges[j];"),
+    "bin_width_dropped": ("*K = dx * dens_eval(d, xm, &a, &b);", "*K = dens_eval(d, xm, &a, &b);"),
+    "bin_centre_edge": ("xb[j] = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;", "xb[j] = M->reco_edges[j];"),
+    "gengamma_shape_power": ("k = m * m / (p * p * s2);", "k = m * m / (p * s2);"),
+    "gengamma_scale_shift": ("D = lgammal(k + 1 / p) - lgammal(k)", "D = lgammal(k + p) - lgammal(k)"),
+    "gengamma_scale_chain": ("d->dth_dm = d->th / m - d->th * dD * d->dk_dm;", "d->dth_dm = d->th / m;"),
+    "spois_scale_transposed": ("d->g = s2 / m;", "d->g = m / s2;"),
+    "spois_digamma_shift": ("(d->llam - digamma_l(t + 1))", "(d->llam - digamma_l(t))"),
+    "emg_shift_sign": ("d->mug = m - d->tau;", "d->mug = m + d->tau;"),
+    "emg_width_unreduced": ("d->sg = s * sqrtl(1 - shape * shape);", "d->sg = s;"),
+    "emg_dsigma_sign": ("*rsg = sg / (t * t) * (r - ph) - y / (sg * t) * ph;",
+                        "*rsg = sg / (t * t) * (r - ph) + y / (sg * t) * ph;"),
+    "emg_cdf_tail_sign": ("*F = 0.5L * erfcl(-y / (sqrtl(2) * sg)) - t * r;", "*F = 0.5L * erfcl(-y / (sqrtl(2) * sg)) + t * r;"),
+    "igam_series_deriv_sign": ("dS -= c * H;", "dS += c * H;"),
+    "igam_cf_deriv": ("dan = i;", "dan = -i;"),
+    "exact_bins_one_sided": ("*K = Fh < 0.5L ? Fh - Fl : Fcl - Fch;", "*K = Fh - Fl;"),
+    "gauss_cdf_ds_sign": ("*ds = -z * r;", "*ds = z * r;"),
     "psd_not_renormalised": ("P[(size_t)s * K + k] = p[k] / Z;", "P[(size_t)s * K + k] = p[k];"),
     "psd_kappa_inverted": ("sg = mx[2 + 2 * c] * kappa;", "sg = mx[2 + 2 * c] / kappa;"),
     "psd_eta_sign": ("logl(w1 / (1 - w1)) + eta", "logl(w1 / (1 - w1)) - eta"),
@@ -56,7 +69,8 @@ def _run(name, tmp):
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, os.path.join(d, "oracle.c"), "-lm"])
     env = dict(os.environ, GS_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_families.py")], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
