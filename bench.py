@@ -446,6 +446,46 @@ def template_study(gs, gsgen, torch, args):
     return out
 
 
+FAMILY_CASES = (("gengamma_p1.6", "GENGAMMA_PE", 1.6, 0), ("scaled_poisson", "SPOIS_PE", 0.0, 0),
+                 ("mod_gauss_f0.35", "EMG_PE", 0.35, 0), ("gamma_exact_bins", "GAMMA_PE", 0.0, 1),
+                 ("gauss_exact_bins", "GAUSS_PE", 0.0, 1), ("gengamma_p1.6_exact_bins", "GENGAMMA_PE", 1.6, 1),
+                 ("mod_gauss_f0.35_exact_bins", "EMG_PE", 0.35, 1))
+
+
+def families_study(gs, gsgen, torch, args):
+    """The further response families and exact bin contents (section 2.3, section 2.5) on the
+    Borexino-scale model (4000 cells x 900 bins): the direct per-pair path's evaluation latency,
+    its fold and adjoint kernels per banded pair, and one fit each way; then 256 toys of the
+    generalized-gamma model in one batch."""
+    out = {}
+    for key, fam, shape, exact in FAMILY_CASES:
+        m = gsgen.family_model(getattr(gsgen, fam), shape, exact_bins=exact)
+        r = single_model(gs, torch, m, reps=50, fits=not args.no_fits)
+        b = gs.Batch([m])
+        band1 = b.mesh_counts()[3]
+        del b
+        for k in ("fold", "adj"):
+            if k in r["kernel_us"]:
+                r[f"{k}_ns_per_pair"] = round(r["kernel_us"][k] * 1e3 / max(band1, 1), 4)
+        r["banded_pairs"] = band1
+        r.pop("kernels", None)  # the FP64 pair count of the fast path does not apply here
+        out[key] = r
+        log(f"bench: family {key} {json.dumps(r)}")
+    base = gsgen.family_model(gsgen.GENGAMMA_PE, 1.6)
+    toys = gsgen.config3(256, base=base)
+    batch = gs.Batch(toys)
+    theta = torch.tensor(theta_of(toys, batch.stride), dtype=torch.float64, device="cuda")
+    nll, grad, st = buffers(len(toys), batch.stride, torch)
+    el = timed_steps(batch, theta, nll, grad, st, max(4, args.steps // 4), 2, torch)
+    kt = profiled_kernels(batch, theta, nll, grad, st, 4, torch)
+    band1 = batch.mesh_counts()[3]
+    out["gengamma_256_toys"] = {"evals_per_s": round(len(toys) * max(4, args.steps // 4) / el, 1),
+                                "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in kt.items() if v[1]},
+                                "banded_pairs": band1, "status_nonzero": int((st != 0).sum().item())}
+    log(f"bench: family batch {json.dumps(out['gengamma_256_toys'])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +556,8 @@ def main():
             log(f"bench: discovery {json.dumps(discovery)}")
         singles["template_study"] = templates
         singles["discovery_test"] = discovery
+        log("bench: response families and exact bins")
+        singles["response_families"] = families_study(gs, gsgen, torch, args)
 
     cpu = parity = None
     if not args.no_cpu:

@@ -40,6 +40,8 @@
  *   GS_RESP_GAUSS_E  : (a, b)            m = E, s^2 = a^2 + b E
  *   GS_RESP_GAUSS_PE : (LY, kB, a, b, c) m = LY Q(E; kB) E, s^2 = a^2 + b m + c^2 m^2
  *   GS_RESP_GAMMA_PE : same moments, gamma density with mean m, variance s^2
+ *   GS_RESP_GENGAMMA_PE, GS_RESP_SPOIS_PE, GS_RESP_EMG_PE: same parameters
+ *                      and moments, the further densities of gs_family
  *   GS_RESP_TEMPLATE : none (Monte Carlo templates, see gs_family)
  *   Q(E; kB) = 1 - 2/y + 2 ln(1 + y)/y^2, y = sqrt(E)/(kB * birks_A)  (Birks'
  *   law integrated with dE/dx = birks_A/sqrt(E); E in MeV for the pe families).
@@ -90,7 +92,36 @@ typedef enum {
  * descriptor's spectra hold the templates [n_species][n_reco] (n_true =
  * n_reco; e_lo, e_step and birks_A are not used, every line_energy is NaN,
  * n_psd = 0), and theta holds the rates alone. */
-typedef enum { GS_RESP_GAUSS_E = 0, GS_RESP_GAUSS_PE = 1, GS_RESP_GAMMA_PE = 2, GS_RESP_TEMPLATE = 3 } gs_family;
+/* Section 2.3 names three further response functions without formulas; the
+ * library takes them as follows (mean m and width s from the photoelectron
+ * moments above, `shape` from the descriptor):
+ *   GS_RESP_GENGAMMA_PE: the generalized gamma p x^(kp-1) exp(-(x/th)^p) /
+ *     (Gamma(k) th^(kp)), power p = shape > 0, k = m^2/(p^2 s^2),
+ *     th = m Gamma(k)/Gamma(k + 1/p): mean m, variance s^2 up to O(1/k);
+ *     p = 1 is GS_RESP_GAMMA_PE.
+ *   GS_RESP_SPOIS_PE: the scaled Poisson, x/g ~ Poisson(lambda) with
+ *     g = s^2/m, lambda = m^2/s^2, continued to real x >= 0 through the
+ *     Gamma function and not renormalised (its integral falls short of 1 by
+ *     e^-lambda int_0^inf e^(-lambda t) dt / (t (pi^2 + ln^2 t))).
+ *   GS_RESP_EMG_PE: the modified Gaussian, a Gaussian convolved with an
+ *     exponential of mean tau = f s, f = shape in (0, 1), Gaussian width
+ *     s sqrt(1 - f^2) and mean m - tau.
+ * These families, and any model with exact_bins = 1, go through a direct
+ * per-pair evaluation (one-dimensional models only, GS_ERR_ARG for
+ * n_psd > 0).  Their admitted range (GS_ST_UNRESOLVED outside, as above):
+ * m <= 300 s for the gamma-type families and the scaled Poisson, m <= 600 s
+ * for the Gaussian photoelectron family and the modified Gaussian, none for
+ * the energy family (its mean is the cell energy); the bin width is not
+ * limited. */
+typedef enum {
+  GS_RESP_GAUSS_E = 0,
+  GS_RESP_GAUSS_PE = 1,
+  GS_RESP_GAMMA_PE = 2,
+  GS_RESP_TEMPLATE = 3,
+  GS_RESP_GENGAMMA_PE = 4,
+  GS_RESP_SPOIS_PE = 5,
+  GS_RESP_EMG_PE = 6
+} gs_family;
 
 /* Limits of this implementation (GS_ERR_UNSUPPORTED beyond them). */
 #define GS_MAX_SPECIES 16
@@ -132,6 +163,14 @@ typedef struct {
    * likelihood; fewer slices cost fewer bins. */
   int32_t n_slices;
   const int32_t *slice_edges; /* [n_slices + 1] or NULL (n_slices = 0)                     */
+  /* Reco-bin content of a deposit (section 2.5 evaluates the response on the
+   * visible x true mesh): 0 = bin width x density at the bin midpoint; 1 = the
+   * density's integral over the bin, as a difference of the distribution
+   * function at the edges (erfc for the Gaussian families, the regularised
+   * incomplete gamma for the gamma-type families, a closed form for the
+   * modified Gaussian).  Not for GS_RESP_SPOIS_PE or templates. */
+  int32_t exact_bins;
+  double shape;               /* GENGAMMA_PE: the power p; EMG_PE: the tail fraction f     */
 } gs_model_desc;
 
 typedef struct gs_model gs_model;

@@ -27,12 +27,12 @@ def build(force: bool = True, src: str | None = None, out: str | None = None) ->
     src = src or os.path.join(HERE, "oracle.c")
     if out is not None:
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-I", HERE, "-o", out, src, "-lm"])
+                               "-I", HERE, "-o", out, src, "-lquadmath", "-lm"])
         return out
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-Wall", "-o", tmp, src, "-lm"])
+                               "-Wall", "-o", tmp, src, "-lquadmath", "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

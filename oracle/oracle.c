@@ -60,6 +60,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <quadmath.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -288,7 +289,10 @@ static int dens_prep(int fam, ld shape, ld m, ld s, dens_t *d) {
     case ORC_GENGAMMA_PE: {
       if (!(shape > 0) || !isfinite((double)shape)) return 0;
       ld p = shape, k = m * m / (p * p * s2);
-      ld D = lgammal(k + 1 / p) - lgammal(k), dD = digamma_l(k + 1 / p) - digamma_l(k);
+      /* ln Gamma(k + 1/p) - ln Gamma(k) in quadruple precision: the two terms
+       * reach ~k ln k and cancel to ~ln(k)/p */
+      ld D = (ld)(lgammaq((__float128)k + (__float128)(1 / p)) - lgammaq((__float128)k));
+      ld dD = digamma_l(k + 1 / p) - digamma_l(k);
       d->p = p;
       d->k = k;
       d->th = m * expl(-D);

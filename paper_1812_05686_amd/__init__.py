@@ -22,6 +22,7 @@ GS_OK, GS_ERR_ARG, GS_ERR_DEVICE, GS_ERR_OOM, GS_ERR_UNSUPPORTED = range(5)
 ST_DOMAIN, ST_NONFINITE, ST_LS_FAIL, ST_MAXITER, ST_BFGS_RESET, ST_CONVERGED = 1, 2, 4, 8, 16, 32
 ST_GRAD_RANGE, ST_UNRESOLVED = 64, 128
 GAUSS_E, GAUSS_PE, GAMMA_PE, TEMPLATE = 0, 1, 2, 3
+GENGAMMA_PE, SPOIS_PE, EMG_PE = 4, 5, 6  # generalized gamma, scaled Poisson, modified Gaussian
 
 _dp = C.POINTER(C.c_double)
 
@@ -33,7 +34,8 @@ class gs_model_desc(C.Structure):
                 ("psd_edges", _dp), ("psd_mix", _dp), ("n_datasets", C.c_int32),
                 ("exposure", _dp), ("counts", _dp), ("win_lo", C.c_int32), ("win_hi", C.c_int32),
                 ("family", C.c_int32), ("birks_A", C.c_double), ("pull_centre", _dp),
-                ("pull_sigma", _dp), ("n_slices", C.c_int32), ("slice_edges", C.POINTER(C.c_int32))]
+                ("pull_sigma", _dp), ("n_slices", C.c_int32), ("slice_edges", C.POINTER(C.c_int32)),
+                ("exact_bins", C.c_int32), ("shape", C.c_double)]
 
 
 def _slices(m):
@@ -165,7 +167,8 @@ def make_desc(m):
     d = gs_model_desc(int(m.n_true), float(m.e_lo), float(m.e_step), int(sp.shape[0]), _ptr(sp), _ptr(le),
                       int(len(re_) - 1), _ptr(re_), 0 if pe is None else int(len(pe) - 1), _ptr(pe), _ptr(pm),
                       int(len(ex)), _ptr(ex), _ptr(cn), int(m.win_lo), int(m.win_hi), int(m.family),
-                      float(m.birks_A), _ptr(pc), _ptr(ps), 0 if se is None else len(se) - 1, _sptr(se))
+                      float(m.birks_A), _ptr(pc), _ptr(ps), 0 if se is None else len(se) - 1, _sptr(se),
+                      int(getattr(m, "exact_bins", 0)), float(getattr(m, "shape", 0.0)))
     return d, keep
 
 
@@ -274,7 +277,8 @@ class Batch:
                                      _ptr(le), int(len(re_) - 1), _ptr(re_), 0 if pe is None else int(len(pe) - 1),
                                      _ptr(pe), _ptr(pm), int(len(ex)), _ptr(ex), _ptr(cn), int(m.win_lo),
                                      int(m.win_hi), int(m.family), float(m.birks_A), _ptr(pc), _ptr(ps),
-                                     0 if se is None else len(se) - 1, _sptr(se))
+                                     0 if se is None else len(se) - 1, _sptr(se),
+                                     int(getattr(m, "exact_bins", 0)), float(getattr(m, "shape", 0.0)))
         h = C.c_void_p()
         _check(lib().gs_batch_create(descs, len(models), device, C.byref(h)), "gs_batch_create")
         self._keep = None  # the library copied everything

@@ -60,7 +60,17 @@ int validate(const gs_model_desc *d) {
     return -1;
   };
   if (!d) return bad("null descriptor");
-  if (d->family < 0 || d->family > 3) return bad("unknown response family %d", d->family);
+  if (d->family < 0 || d->family > GS_RESP_EMG_PE) return bad("unknown response family %d", d->family);
+  if (d->exact_bins != 0 && d->exact_bins != 1) return bad("exact_bins must be 0 or 1");
+  if (d->family >= GS_RESP_GENGAMMA_PE || d->exact_bins) {
+    if (d->n_psd != 0) return bad("family %d / exact bins: one-dimensional models only", d->family);
+    if (d->family == GS_RESP_TEMPLATE) return bad("templates have no bin integrals");
+    if (d->family == GS_RESP_SPOIS_PE && d->exact_bins) return bad("the scaled Poisson has no exact bin content");
+  }
+  if (d->family == GS_RESP_GENGAMMA_PE && !(d->shape > 0 && std::isfinite(d->shape)))
+    return bad("generalized gamma power %g must be positive", d->shape);
+  if (d->family == GS_RESP_EMG_PE && !(d->shape > 0 && d->shape < 1))
+    return bad("modified Gaussian tail fraction %g outside (0, 1)", d->shape);
   if (d->n_species < 1 || d->n_species > GS_MAX_SPECIES)
     return bad("n_species %d outside 1..%d", d->n_species, GS_MAX_SPECIES);
   if (d->n_true < 1) return bad("n_true %d < 1", d->n_true);
@@ -129,7 +139,7 @@ int validate(const gs_model_desc *d) {
         double n = d->counts[((size_t)k * d->n_reco + j) * K + q];
         if (!(n >= 0) || !std::isfinite(n)) return bad("count (%d,%d,%d) negative or not finite", k, j, q);
       }
-  if ((d->family == GS_RESP_GAUSS_PE || d->family == GS_RESP_GAMMA_PE) && !(d->birks_A > 0))
+  if (d->family != GS_RESP_GAUSS_E && d->family != GS_RESP_TEMPLATE && !(d->birks_A > 0))
     return bad("birks_A must be > 0");
   const int P = num_params(d);
   if (d->pull_sigma)
@@ -144,10 +154,12 @@ struct ShapeKey {
   const void *spectra, *lines, *edges, *pe, *pm;
   int fam, n_true, S, n_reco, n_psd;
   double e_lo, e_step, A;
+  int exact;
+  double shape;
   bool operator<(const ShapeKey &o) const {
-    return std::tie(spectra, lines, edges, pe, pm, fam, n_true, S, n_reco, n_psd, e_lo, e_step, A) <
+    return std::tie(spectra, lines, edges, pe, pm, fam, n_true, S, n_reco, n_psd, e_lo, e_step, A, exact, shape) <
            std::tie(o.spectra, o.lines, o.edges, o.pe, o.pm, o.fam, o.n_true, o.S, o.n_reco, o.n_psd, o.e_lo,
-                    o.e_step, o.A);
+                    o.e_step, o.A, o.exact, o.shape);
   }
 };
 
@@ -503,8 +515,10 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   std::vector<int> toy_shape(n_toys);
   for (int t = 0; t < n_toys; t++) {
     const gs_model_desc &d = descs[t];
+    const bool shaped = d.family == GS_RESP_GENGAMMA_PE || d.family == GS_RESP_EMG_PE;
     ShapeKey k{d.spectra, d.line_energy, d.reco_edges, d.psd_edges, d.psd_mix, d.family, d.n_true,
-               d.n_species, d.n_reco, d.n_psd, d.e_lo, d.e_step, d.family == GS_RESP_GAUSS_E ? 0.0 : d.birks_A};
+               d.n_species, d.n_reco, d.n_psd, d.e_lo, d.e_step, d.family == GS_RESP_GAUSS_E ? 0.0 : d.birks_A,
+               d.exact_bins, shaped ? d.shape : 0.0};
     auto it = shape_of.find(k);
     if (it != shape_of.end()) {
       toy_shape[t] = it->second;
@@ -520,6 +534,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     sh.n_reco = d.n_reco;
     sh.n_psd = d.n_psd;
     sh.birks_A = d.birks_A;
+    sh.exact = d.exact_bins;
+    sh.shape = d.shape;
+    sh.gen = d.family >= GS_RESP_GENGAMMA_PE || d.exact_bins ? 1 : 0;
     std::vector<int> grid, line;
     for (int q = 0; q < d.n_species; q++) (std::isnan(d.line_energy[q]) ? grid : line).push_back(q);
     sh.Sg = (int)grid.size();
@@ -553,6 +570,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     sh.wcell = wc;
     sh.wcellT = wct;
     sh.bins = bins;
+    sh.edges = edges;
     // uniform binning (midpoints within 1e-6 of a bin width of a lattice): the
     // support search guesses bin indices arithmetically
     sh.bx0 = 0.5 * (d.reco_edges[0] + d.reco_edges[1]);
@@ -623,6 +641,8 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     } else {
       v.has_1d = true;
     }
+    T.gen = sh.gen;
+    if (T.gen) v.has_gen = true;
     T.n_cell = sh.n_cell;
     T.S = sh.S;
     for (int k = 0; k < T.D; k++) T.exposure[k] = d.exposure[k];

@@ -34,7 +34,10 @@ constexpr double kHalfLn2Pi = 0.91893853320467274178032973640561764;  // ln(2 pi
 constexpr double kLn2Hi = 0.6931471805599453094;   // 0x1.62e42fefa39efp-1
 constexpr double kLn2Lo = 2.319046813846299558e-17;
 
-enum Family : int { kGaussE = 0, kGaussPE = 1, kGammaPE = 2, kTemplate = 3 };
+enum Family : int {
+  kGaussE = 0, kGaussPE = 1, kGammaPE = 2, kTemplate = 3,
+  kGenGammaPE = 4, kSPoisPE = 5, kEmgPE = 6  // evaluated by the direct per-pair path (gs_gen.h)
+};
 
 struct dd {
   double hi, lo;
@@ -204,7 +207,7 @@ GS_HD inline bool moments(int fam, const double *resp, double A, double E, Momen
   o.ds[3] = 0.5 * m / s;
   o.ds[4] = c * m * m / s;
   bool ok = s2 > 0.0 && s2 < 1e300;
-  if (fam == kGammaPE) ok = ok && m > 0.0;
+  if (fam == kGammaPE || fam == kGenGammaPE || fam == kSPoisPE) ok = ok && m > 0.0;
   return ok;
 }
 

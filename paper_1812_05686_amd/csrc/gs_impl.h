@@ -47,6 +47,10 @@ struct ShapeDev {
   const double *wcellT;  // [Sg][n_true]: the same, species-major (lanes on consecutive cells read coalesced)
   const double *bins;   // [n_reco][kBinLen]: xbar, dx, ln xbar (hi, lo)
   double bx0, bw;       // uniform binning: xbar_j = bx0 + j bw (bw = 0: not uniform)
+  const double *edges;  // [n_reco + 1] reco-bin edges
+  int gen;              // 1: the direct per-pair path (families >= kGenGammaPE, or exact bins)
+  int exact;            // 1: reco-bin contents are the response's bin integrals
+  double shape;         // generalized gamma power / modified Gaussian tail fraction
   const double *psd;    // [n_psd][2]: ybar, dy
   const double *mix;    // [S][5], internal species order
   int sp_of[GS_MAX_SPECIES];
@@ -58,6 +62,7 @@ struct ToyDev {
   int two_d;                    // 1: pulse-shape (secondary observable) model
   int tmpl;                     // 1: Monte Carlo template model (no fold, no response)
   int mv;                       // 1: multivariate slice likelihood (2-D toys with energy slices)
+  int gen;                      // 1: response through the direct per-pair path (k_foldg, k_adjg)
   int n_slices, eblocks;        // mv: energy slices; k_mv_bins blocks (kHTile window bins each)
   int fold_chunks, adj_chunks;
   int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: iter2 * kBlock bin x pulse-shape cells each) / cells (k_cellgrad)
@@ -152,7 +157,7 @@ struct BatchView {
   const int *sedge;      // mv: slice edges per toy
   double *sig;           // mv: per (slice, species) seeds of the slice pieces
   bool has_mv;
-  bool has_1d, has_2d, has_tmpl;
+  bool has_1d, has_2d, has_tmpl, has_gen;
 };
 
 // Which toys a launch covers.

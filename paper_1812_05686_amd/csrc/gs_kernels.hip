@@ -25,6 +25,7 @@
 
 #include "gs_impl.h"
 #include "gs_support.h"
+#include "gs_gen.h"
 
 namespace gs {
 
@@ -145,6 +146,15 @@ __device__ __forceinline__ bool admitted(int fam, double m, double s, double w) 
   return kAdmitGaussW * s >= w;
 }
 
+// Admitted range of the direct per-pair path (no tile-relative exponent, so no
+// bin-width limit): the conditioning of a density on its FP64 mean, as for the
+// fast path; the energy family's mean is the cell energy itself (no rounding).
+__device__ __forceinline__ bool gen_admitted(int fam, double m, double s) {
+  if (fam == kGaussE) return true;
+  if (fam == kGammaPE || fam == kGenGammaPE || fam == kSPoisPE) return m <= kAdmitCondGamma * s;
+  return m <= kAdmitCondGauss * s;
+}
+
 // Per-block flags of k_cells (cflag): an invalid response, a refused one.
 constexpr uint32_t kCellInvalid = 1u, kCellUnresolved = 2u;
 
@@ -177,10 +187,29 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
     }
     ok = ok && isfinite(W);
     double r[kRecLen];
-    cell_record(Sh.family, mo.m, mo.s, W, ok, r);
-    const Span spn = cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, Sh.bx0, Sh.bw, log_cut);
-    const int2 sp = make_int2(spn.x, spn.y);
-    if (ok && sp.y > T.lo && sp.x < T.lo + T.L) {  // the response reaches the window
+    int2 sp;
+    if (Sh.gen) {  // direct path: {m, s, W, a, b, c, support, d} (GenCell constants)
+      GenCell gc;
+      ok = ok && gen_cell(Sh.family, Sh.shape, mo.m, mo.s, gc);
+#pragma unroll
+      for (int q = 0; q < kRecLen; q++) r[q] = 0.0;
+      if (ok) {
+        r[0] = gc.m;
+        r[1] = gc.s;
+        r[2] = W;
+        r[3] = gc.a;
+        r[4] = gc.b;
+        r[5] = gc.c;
+        r[7] = gc.d;
+      }
+      sp = ok ? gen_support(Sh.family, Sh.shape, gc, Sh.edges, Sh.n_reco, log_cut) : make_int2(0, 0);
+      if (ok && sp.y > T.lo && sp.x < T.lo + T.L) unresolved = !gen_admitted(Sh.family, mo.m, mo.s);
+    } else {
+      cell_record(Sh.family, mo.m, mo.s, W, ok, r);
+      const Span spn = cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, Sh.bx0, Sh.bw, log_cut);
+      sp = make_int2(spn.x, spn.y);
+    }
+    if (!Sh.gen && ok && sp.y > T.lo && sp.x < T.lo + T.L) {  // the response reaches the window
       // the widths of the bins the response covers (the binning's width if uniform)
       double w = Sh.bw;
       if (!(w > 0.0)) {
@@ -419,7 +448,7 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   const FoldItem it = items[w_item];
   if (active && !active[it.toy]) return;
   const ToyDev &T = toys[it.toy];
-  if (T.two_d) return;
+  if (T.two_d || T.gen) return;
   const ShapeDev &Sh = shapes[T.shape];
   // A gamma tile whose first bin lies at x <= 0 always takes the clamped
   // exponential: such a bin's offsets stand in for ln x = 0, so the exponent
@@ -583,7 +612,7 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   const FoldItem it = items[w_item];
   if (active && !active[it.toy]) return;
   const ToyDev &T = toys[it.toy];
-  if (mode >= 0 && T.two_d != mode) return;
+  if ((mode >= 0 && T.two_d != mode) || T.gen) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // the lane's bin as a row of the A operand, clipped to the window
@@ -626,6 +655,80 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   }
 }
 
+// ------------------------------------------------ direct per-pair fold ----
+// Toys of the further response families, or with exact bin contents (gs_gen.h):
+// each pair (window bin, cell) evaluates the bin content K_ji itself.  A
+// workgroup takes one fold item: `tile` window bins, one per thread of a
+// stream, against the item's cells dealt round-robin to the 256 / tile
+// streams; the lanes of a stream read the same cell record (a broadcast) and
+// skip a cell whose support misses their bin.  The partials are bin contents
+// (no width factor): PS = false sums W_i K_ji into fpart, PS = true sums
+// w_si K_ji per species into fspart; the streams are added in a fixed order.
+template <bool PS>
+__global__ __launch_bounds__(256) void k_foldg(const FoldItem *__restrict__ items, int n_items, int tile,
+                                               const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                               const double *__restrict__ rec, const uint8_t *__restrict__ active,
+                                               double *__restrict__ out) {
+  constexpr int NQ = PS ? GS_MAX_SPECIES : 1;
+  __shared__ double red[256 * NQ];
+  const int w_item = xcd_item(blockIdx.x, n_items);
+  if (w_item >= n_items) return;
+  const FoldItem it = items[w_item];
+  if (active && !active[it.toy]) return;
+  const ToyDev &T = toys[it.toy];
+  if (!T.gen) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int nstream = 256 / tile, stream = threadIdx.x / tile, jb = threadIdx.x - stream * tile;
+  const int b = it.bin0 + jb;
+  const bool in = b < T.L;
+  const int j = T.lo + min(b, T.L - 1);
+  const double xlo = Sh.edges[j], xhi = Sh.edges[j + 1];
+  const double xm = Sh.bins[(size_t)j * kBinLen], dx = Sh.bins[(size_t)j * kBinLen + 1];
+  const int fam = Sh.family, S = T.S;
+  const bool ex = Sh.exact != 0;
+  const double p = Sh.shape;
+  const GenChain ch{0.0, 0.0, 0.0, 0.0};  // no derivatives in the forward fold
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) acc[q] = 0.0;
+  const double *R = rec + T.cell_off * kRecLen;
+  for (int i = it.cell0 + stream; i < it.cell1; i += nstream) {
+    const double *rc = R + (size_t)i * kRecLen;
+    const int2 sp = get_support(rc);
+    if (!in || j < sp.x || j >= sp.y) continue;
+    const GenCell g{rc[0], rc[1], rc[3], rc[4], rc[5], rc[7]};
+    double K, d1, d2;
+    if (ex) {
+      const Edge lo = gen_edge(fam, p, g, ch, xlo, false), hi = gen_edge(fam, p, g, ch, xhi, false);
+      K = edge_content(lo, hi, d1, d2);
+    } else {
+      K = dx * gen_density(fam, p, g, ch, xm, false, d1, d2);
+    }
+    if (PS) {
+#pragma unroll
+      for (int q = 0; q < NQ; q++)
+        if (q < S) acc[q] = fma(cell_weight(Sh, i, q), K, acc[q]);
+    } else {
+      acc[0] = fma(rc[2], K, acc[0]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; q++) red[threadIdx.x * NQ + q] = acc[q];
+  __syncthreads();
+  if (stream != 0 || !in) return;
+  if (PS) {
+    for (int q = 0; q < S; q++) {
+      double v = red[jb * NQ + q];
+      for (int w = 1; w < nstream; w++) v += red[(w * tile + jb) * NQ + q];
+      out[T.fs_off + ((long long)it.chunk * T.L + b) * S + q] = v;
+    }
+  } else {
+    double v = red[jb];
+    for (int w = 1; w < nstream; w++) v += red[w * tile + jb];
+    out[T.fpart_off + (long long)it.chunk * T.L + b] = v;
+  }
+}
+
 hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uint8_t *active, hipStream_t st) {
   if (per_species) {
     // the per-species fold serves the 2-D toys, or every toy (plain path)
@@ -634,10 +737,16 @@ hipError_t launch_fold(const BatchView &v, bool per_species, int mode, const uin
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fold_s, dim3(xcd_grid(n)), dim3(kWaves * 64), 0, st, it, n, v.toys, v.shapes, v.rec,
                        v.ghull, mode, active, v.fspart);
+    if (v.has_gen && mode != kOnly2D)
+      hipLaunchKernelGGL(k_foldg<true>, dim3(xcd_grid(n)), dim3(256), 0, st, it, n, kFoldTile, v.toys, v.shapes,
+                         v.rec, active, v.fspart);
   } else {
     if (v.n_fold1 == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fold1, dim3(xcd_grid(v.n_fold1)), dim3(kWaves * 64), 0, st, v.fold1, v.n_fold1, v.toys,
                        v.shapes, v.rec, v.ghull, active, v.fpart);
+    if (v.has_gen)
+      hipLaunchKernelGGL(k_foldg<false>, dim3(xcd_grid(v.n_fold1)), dim3(256), 0, st, v.fold1, v.n_fold1, kFoldTile1,
+                         v.toys, v.shapes, v.rec, active, v.fpart);
   }
   return hipGetLastError();
 }
@@ -726,7 +835,7 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
       s1 = (((s1 + p0) + p1) + p2) + p3;
     }
     for (; c < T.fold_chunks; c++) s1 += fp[(long long)c * T.L];
-    const double mu1 = dx * s1;
+    const double mu1 = T.gen ? s1 : dx * s1;  // the direct path's partials are bin contents already
     double G = 0.0;
     uint32_t bad = 0u;
     for (int d = 0; d < T.D; d++) {
@@ -738,9 +847,9 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
       G = __fma_rn(T.exposure[d], g, G);
       if (mu_out) mu_out[(long long)d * T.L + b] = mu;
     }
-    if (Sh.family == kGammaPE && !(bn[0] > 0.0)) G = 0.0;
+    if (Sh.family == kGammaPE && !T.gen && !(bn[0] > 0.0)) G = 0.0;
     double *br = binrec + (T.win_off + b) * kBinRecLen;
-    const double Gd = G * dx;
+    const double Gd = T.gen ? G : G * dx;
     br[0] = bn[0];
     br[1] = bn[2];
     br[2] = bn[3];
@@ -897,7 +1006,7 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
   if (active && !active[it.toy]) return;
   const int wave = NW > 1 ? wave_uniform(threadIdx.x >> 6) : 0;  // this wave's place within its item
   const ToyDev &T = toys[it.toy];
-  if (T.two_d) return;
+  if (T.two_d || T.gen) return;
   const ShapeDev &Sh = shapes[T.shape];
   const int i = it.cell0 + lane;
   const bool valid = i < T.n_cell;
@@ -1066,6 +1175,64 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict
   }
 }
 
+// --------------------------------------------- direct per-pair adjoint ----
+// One wave per adjoint item, lane = cell, walking the window bins of the
+// cell's own support inside the item's range: per-cell sums G K, G dK/dm and
+// G dK/ds (G = sum_d eps_d (1 - n/mu) from the window-bin record, without a
+// width factor), which k_cellgrad chains to the parameters.  With exact bins
+// a bin's upper edge is the next bin's lower edge, evaluated once.
+__global__ __launch_bounds__(256) void k_adjg(const AdjItem *__restrict__ items, int n_items,
+                                              const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+                                              const double *__restrict__ rec, const double *__restrict__ binrec,
+                                              const uint8_t *__restrict__ active, double *__restrict__ apart) {
+  const int w_item = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w_item >= n_items) return;
+  const AdjItem it = items[w_item];
+  if (active && !active[it.toy]) return;
+  const ToyDev &T = toys[it.toy];
+  if (!T.gen) return;
+  const ShapeDev &Sh = shapes[T.shape];
+  const int i = it.cell0 + lane;
+  if (i >= T.n_cell) return;
+  const double *rc = rec + (T.cell_off + i) * kRecLen;
+  const int2 sp = get_support(rc);
+  const int b0 = max(it.bin0, sp.x - T.lo), b1 = min(it.bin1, sp.y - T.lo);
+  double A0 = 0.0, A1 = 0.0, A2 = 0.0;
+  if (b0 < b1) {
+    const int fam = Sh.family;
+    const double p = Sh.shape;
+    const GenCell g{rc[0], rc[1], rc[3], rc[4], rc[5], rc[7]};
+    const GenChain ch = gen_chain(fam, p, g);
+    const double *BR = binrec + T.win_off * kBinRecLen;
+    if (Sh.exact) {
+      Edge lo = gen_edge(fam, p, g, ch, Sh.edges[T.lo + b0], true);
+      for (int b = b0; b < b1; b++) {
+        const Edge hi = gen_edge(fam, p, g, ch, Sh.edges[T.lo + b + 1], true);
+        double dm, ds;
+        const double K = edge_content(lo, hi, dm, ds), G = BR[(size_t)b * kBinRecLen + 3];
+        A0 = fma(G, K, A0);
+        A1 = fma(G, dm, A1);
+        A2 = fma(G, ds, A2);
+        lo = hi;
+      }
+    } else {
+      for (int b = b0; b < b1; b++) {
+        const double *bn = Sh.bins + (size_t)(T.lo + b) * kBinLen;
+        double dm, ds;
+        const double r = gen_density(fam, p, g, ch, bn[0], true, dm, ds);
+        const double Gd = BR[(size_t)b * kBinRecLen + 3] * bn[1];
+        A0 = fma(Gd, r, A0);
+        A1 = fma(Gd, dm, A1);
+        A2 = fma(Gd, ds, A2);
+      }
+    }
+  }
+  double *o = apart + T.apart_off + ((long long)it.chunk * T.n_cell + i) * 3;
+  o[0] = A0;
+  o[1] = A1;
+  o[2] = A2;
+}
+
 hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *active, hipStream_t st) {
   const AdjItem *it = per_species ? v.adj2 : v.adj1;
   const int n = per_species ? v.n_adj2 : v.n_adj1;
@@ -1079,6 +1246,9 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
   // workgroup (large batches: the fixed per-wave work spreads over four times
   // the pairs); kWaves waves interleave an item's bins (small batches, where
   // the grid must fill the GPU)
+  if (v.has_gen)
+    hipLaunchKernelGGL(k_adjg, dim3((n + 3) / 4), dim3(256), 0, st, it, n, v.toys, v.shapes, v.rec, v.binrec, active,
+                       v.apart);
   const int groups = (n + kAdjGroupWaves - 1) / kAdjGroupWaves;
   if (v.adj_waves == 1)
     hipLaunchKernelGGL((k_adj<1>), dim3(xcd_grid(groups)), dim3(kAdjGroupWaves * 64), 0, st, it, n, v.toys, v.shapes,
@@ -1134,7 +1304,10 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
       }
     }
     double dNdm, dNds;
-    if (fam == kGammaPE) {
+    if (Sh.gen) {  // direct path: the sums are of G dK/dm and G dK/ds themselves
+      dNdm = W * A1;
+      dNds = W * A2;
+    } else if (fam == kGammaPE) {
       const double m = mo.m, s = mo.s, s2 = s * s;
       const double k = m * m / s2, thg = s2 / m, mk = k * thg;
       // shift the sums of ln x and x to ln x - ln(k th) and x - k th
@@ -1343,7 +1516,7 @@ __global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_lis
   const double dx = Sh.bins[(size_t)(T.lo + b) * kBinLen + 1];
   double acc = 0.0;
   for (int c = 0; c < T.fold_chunks; c++) acc += fspart[T.fs_off + ((long long)c * T.L + b) * T.S + sp];
-  F[(T.win_off + b) * T.S + sp] = dx * acc;
+  F[(T.win_off + b) * T.S + sp] = T.gen ? acc : dx * acc;
 }
 
 hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st) {

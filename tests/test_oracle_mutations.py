@@ -23,7 +23,7 @@ MUTANTS = {
     "bin_width_dropped": ("*K = dx * dens_eval(d, xm, &a, &b);", "*K = dens_eval(d, xm, &a, &b);"),
     "bin_centre_edge": ("xb[j] = (M->reco_edges[j] + M->reco_edges[j + 1]) * 0.5;", "xb[j] = M->reco_edges[j];"),
     "gengamma_shape_power": ("k = m * m / (p * p * s2);", "k = m * m / (p * s2);"),
-    "gengamma_scale_shift": ("D = lgammal(k + 1 / p) - lgammal(k)", "D = lgammal(k + p) - lgammal(k)"),
+    "gengamma_scale_shift": ("lgammaq((__float128)k + (__float128)(1 / p))", "lgammaq((__float128)k + (__float128)p)"),
     "gengamma_scale_chain": ("d->dth_dm = d->th / m - d->th * dD * d->dk_dm;", "d->dth_dm = d->th / m;"),
     "spois_scale_transposed": ("d->g = s2 / m;", "d->g = m / s2;"),
     "spois_digamma_shift": ("(d->llam - digamma_l(t + 1))", "(d->llam - digamma_l(t))"),
@@ -66,7 +66,8 @@ def _run(name, tmp):
     with open(os.path.join(d, "oracle.c"), "w") as f:
         f.write(src.replace(a, b) if a else src)
     lib = os.path.join(d, "liboracle.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, os.path.join(d, "oracle.c"), "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, os.path.join(d, "oracle.c"),
+                           "-lquadmath", "-lm"])
     env = dict(os.environ, GS_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
