@@ -43,7 +43,7 @@ ALGO_FLOPS_PER_PAIR = 26.5
 # relative exponent 2 FMA, exponential 11 FMA + MAX + SUB + LDEXP, accumulation 1 FMA; adjoint:
 # 3 accumulating FMAs): context only.
 INSTR_FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
-KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj<false>", "folds": "k_fold_s", "adj_s": "k_adj<true>"}
+KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj", "folds": "k_fold_s", "adj_s": "k_adj_s"}
 # HBM bytes per launch on the 4096-toy Borexino-scale batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
 # plain 512 MiB device copy (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the
