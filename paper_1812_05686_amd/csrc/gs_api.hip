@@ -410,6 +410,16 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
   B->fold1_h.clear();
   B->adj_h.clear();
   LayoutSizes z{};
+  // template blocks: the largest size whose launch still has kTmplMinBlocks
+  // blocks (toys in groups of up to 16 share a block)
+  v.tmpl_bins = kTmplBlockBins;
+  for (int tb : {kTmplBlockBins, 256, 64}) {
+    long long nb = 0;
+    for (const ToyDev &T : B->toys_h)
+      if (T.tmpl) nb += (T.L + tb - 1) / tb;
+    v.tmpl_bins = tb;
+    if (nb / kTmplGroup >= kTmplMinBlocks) break;
+  }
   for (int t = 0; t < (int)B->toys_h.size(); t++) {
     ToyDev &T = B->toys_h[t];
     const ShapeDev &sh = B->shapes_h[T.shape];
@@ -420,7 +430,7 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     T.adj_chunks = (T.L + bpc - 1) / bpc;
     const long long c2 = (long long)kBlock * k.iter2;
     T.bin_blocks = T.two_d  ? (int)(((long long)T.L * T.K + c2 - 1) / c2)
-                   : T.tmpl ? (T.L + kTmplBlockBins - 1) / kTmplBlockBins
+                   : T.tmpl ? (T.L + v.tmpl_bins - 1) / v.tmpl_bins
                             : (T.L + kBlock - 1) / kBlock;
     T.hblocks = T.two_d ? (T.L + kHTile * k.iter2 - 1) / (kHTile * k.iter2) : 0;
     if (T.mv) {  // rows of k_mv_bins (energy blocks), then one per slice (k_mv_slice)
@@ -569,6 +579,16 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     sh.cellE = cE;
     sh.wcell = wc;
     sh.wcellT = wct;
+    {  // padded per-cell weights over the internal species, for the per-species fold's staging
+      std::vector<double> w16((size_t)std::max(sh.n_cell, 1) * GS_MAX_SPECIES, 0.0);
+      for (int i = 0; i < d.n_true && i < sh.n_cell; i++)
+        for (int q = 0; q < sh.Sg; q++) w16[(size_t)i * GS_MAX_SPECIES + q] = wcell[(size_t)i * sh.Sg + q];
+      for (int q = 0; q < sh.n_line; q++) w16[(size_t)(d.n_true + q) * GS_MAX_SPECIES + sh.Sg + q] = 1.0;
+      double *wd;
+      HIP_TRY(B->alloc(&wd, w16.size()));
+      HIP_TRY(hipMemcpy(wd, w16.data(), w16.size() * 8, hipMemcpyHostToDevice));
+      sh.w16 = wd;
+    }
     sh.bins = bins;
     sh.edges = edges;
     // uniform binning (midpoints within 1e-6 of a bin width of a lattice): the
@@ -683,7 +703,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
       ps_h.push_back(has ? d.pull_sigma[p] : 0.0);
     }
     cell_off += sh.n_cell;
-    win_off += T.L;
+    win_off += T.L + kWinPad;
     bref_off += (T.L + kABlock - 1) / kABlock;
     cnt_off += T.mv ? (long long)T.D * (T.L + (long long)T.n_slices * T.K) : (long long)T.D * T.L * T.K;
     cflag_off += T.cflag_blocks;
@@ -747,6 +767,7 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
   HIP_TRY(B->alloc(&v.apart, (size_t)cap.apart));
   HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinRecLen));
+  HIP_TRY(hipMemset(v.binrec, 0, (size_t)win_off * kBinRecLen * sizeof(double)));  // the padding rows stay zero
   HIP_TRY(B->alloc(&v.bref, (size_t)bref_off * 4));
   HIP_TRY(B->alloc(&v.nllp, (size_t)cap.nllp));
   HIP_TRY(B->alloc(&v.badp, (size_t)cap.nllp));

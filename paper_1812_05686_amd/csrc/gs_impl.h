@@ -27,13 +27,19 @@ constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed roun
 // it; small ones one round, so that one model still fills the GPU
 constexpr int kIter2Large = 8;
 constexpr int kGradLen = GS_MAX_PARAMS;
+// Zeroed window-bin rows after each toy's window: kernels that walk bins in
+// steps of 16 read whole steps without clamping the bin index
+constexpr int kWinPad = 16;
 constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response flag each)
 // cells per k_cellgrad block: kBlock (one per thread) for small batches, where
 // the grid must fill the GPU, 4 * kBlock for large ones (one reduction per
 // 1024 cells); BatchView::grad_cells holds the choice
 constexpr int kGradCellsLarge = 1024;
 constexpr int kGradLargeBlocks = 16384;
-constexpr int kTmplBlockBins = 1024;  // window bins per k_tmpl block (one partial row per toy and block)
+// window bins per k_tmpl block (one partial row per toy and block): 1024 for
+// large template batches, 256 or 64 when fewer blocks would leave the GPU idle
+constexpr int kTmplBlockBins = 1024;
+constexpr int kTmplMinBlocks = 1024;  // blocks a template launch aims for before it shrinks the block
 constexpr int kTmplGroup = 16;        // toys per k_tmpl group (the columns of its matrix products)
 
 // Structure shared by every toy of one shape (spectra, grid, binning).
@@ -45,6 +51,7 @@ struct ShapeDev {
   const double *cellE;  // [n_cell]: grid-cell centres, then line energies
   const double *wcell;   // [n_true][Sg]: grid-species weights, cell-major
   const double *wcellT;  // [Sg][n_true]: the same, species-major (lanes on consecutive cells read coalesced)
+  const double *w16;     // [n_cell][GS_MAX_SPECIES]: every cell's weights over the internal species (lines one-hot), zero-padded
   const double *bins;   // [n_reco][kBinLen]: xbar, dx, ln xbar (hi, lo)
   double bx0, bw;       // uniform binning: xbar_j = bx0 + j bw (bw = 0: not uniform)
   const double *edges;  // [n_reco + 1] reco-bin edges
@@ -109,6 +116,7 @@ struct BatchView {
   // shape, window and datasets
   const int *tgroup;
   int n_tgroup;
+  int tmpl_bins;  // window bins per k_tmpl block (kTmplBlockBins, 256 or 64)
   int n1d, n2d, nt;  // 1-D analytic, 2-D and template toys
   int max_cells, max_cell_blocks, max_bin_blocks;
   int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)

@@ -556,8 +556,7 @@ __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__
                                             const ExpK &ec, dbl4 acc) {
   static_assert(2 * kStage == kWaves * 64, "one staged cell and half-tile per thread");
   constexpr int kGPB = kStage / kGroup;
-  constexpr int kT = kWaves * 64;
-  const int tid = threadIdx.x, S = Sh.S, cs = tid % kStage, half = tid / kStage;
+  const int tid = threadIdx.x, cs = tid % kStage, half = tid / kStage;
   auto cell_of = [&](int bi, int c) {  // cell at slot c of batch bi, or -1
     if (list) {
       const int li = bi * kGPB + c / kGroup;
@@ -572,7 +571,13 @@ __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__
     const int rem = list ? (n_list - bi * kGPB) * kGroup : c_hi - c_lo - bi * kStage;
     const int nb = (min(kStage, rem) + 3) & ~3;  // whole MFMA steps; padding slots carry zero weights
     double2 f[3];
-    stage_load<FAM>(R, cell_of(bi, cs), f);
+    const int cell = cell_of(bi, cs);
+    stage_load<FAM>(R, cell, f);
+    // this thread's half of its cell's weights (species 8 half .. 8 half + 7)
+    double2 wq[4];
+    const double2 *wsrc = (const double2 *)(Sh.w16 + (size_t)max(cell, 0) * GS_MAX_SPECIES + 8 * half);
+#pragma unroll
+    for (int e = 0; e < 4; e++) wq[e] = cell >= 0 ? wsrc[e] : make_double2(0.0, 0.0);
     __syncthreads();  // every wave is done with the previous batch
     {
       // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W}
@@ -586,11 +591,8 @@ __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__
         ((double2 *)srec)[3 * cs + 2] = make_double2(q.Eref, 0.0);
       }
     }
-    for (int e = tid; e < kStage * GS_MAX_SPECIES; e += kT) {
-      const int c = e / GS_MAX_SPECIES, q = e % GS_MAX_SPECIES;
-      const int cell = cell_of(bi, c);
-      swt[e] = cell >= 0 && q < S ? cell_weight(Sh, cell, q) : 0.0;
-    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) ((double2 *)swt)[(cs * GS_MAX_SPECIES + 8 * half) / 2 + e] = wq[e];
     __syncthreads();
     acc = folds_batch(srec, swt, nb, ao, eo, u, v, ec, acc);
   }
@@ -1068,6 +1070,60 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
 // end.  A gamma cell's exponent is formed about the reference point of each
 // kABlock-bin block (as in the 1-D adjoint); bins outside the walked range
 // carry a zero seed.
+// One step of the walk: 16 bins from jb against the wave's 16 cells.  The
+// lane's four bin records (bins jb + grp + 4 v; rows past the window are
+// zero padding, and their Z is zero) are loaded before the contraction, so
+// their latency overlaps the MFMA chain.
+template <int FAM>
+__device__ __forceinline__ void adj_s_walk(const double *__restrict__ BR, const double *__restrict__ BF,
+                                           const double *__restrict__ HR, int S, int nk, int b0, int b1,
+                                           const double (&rc)[kRecLen], const double (&rwk)[4], const ExpK &ec,
+                                           double &A0, double &A1, double &A2) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  double Eref = 0.0;
+  int qref = -1;
+  for (int jb = b0 & ~15; jb < b1; jb += 16) {
+    const double *br = BR + (size_t)(jb + grp) * kBinRecLen;
+    double2 xl[4], uv[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      xl[v] = *(const double2 *)(br + 4 * v * kBinRecLen);  // x, ln x (hi)
+      if (FAM == kGammaPE) uv[v] = *(const double2 *)(br + 4 * v * kBinRecLen + 6);  // block offsets u, v
+    }
+    const int ja = jb + col;  // the A operand's bin
+    const bool in = ja >= b0 && ja < b1;
+    dbl4 Z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (k < nk) {
+        const int s4 = 4 * k + grp;
+        const double h = in && s4 < S ? HR[(size_t)ja * S + s4] : 0.0;
+        Z = __builtin_amdgcn_mfma_f64_16x16x4f64(h, rwk[k], Z, 0, 0, 0);
+      }
+    if (FAM == kGammaPE && jb / kABlock != qref) {  // a 16-bin step lies inside one reference block
+      qref = jb / kABlock;
+      const double *r = BF + (size_t)qref * 4;
+      Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      if (FAM == kGammaPE) {
+        const double Gr = Z[v] * dexp(rel_exponent(rc[0], -rc[1], Eref, uv[v].x, uv[v].y), ec);
+        A0 += Gr;
+        A1 = __fma_rn(Gr, xl[v].y, A1);
+        A2 = __fma_rn(Gr, xl[v].x, A2);
+      } else {
+        double z;
+        const double Gr = Z[v] * dexp(gauss_exponent(rc[0], rc[1], rc[2], xl[v].x, z), ec);
+        const double Grz = Gr * z;
+        A0 += Gr;
+        A1 += Grz;
+        A2 = __fma_rn(Grz, z, A2);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict__ items, int n_items,
                                                        const ToyDev *__restrict__ toys,
                                                        const ShapeDev *__restrict__ shapes,
@@ -1122,44 +1178,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict
   }
   const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
   const double *BR = binrec + T.win_off * kBinRecLen, *BF = bref + T.bref_off * 4, *HR = H + T.win_off * T.S;
-  const bool gamma = Sh.family == kGammaPE;
-  double A0 = 0.0, A1 = 0.0, A2 = 0.0, Eref = 0.0;
-  int qref = -1;
-  for (int jb = b0 & ~15; jb < b1; jb += 16) {
-    const int ja = jb + col;  // the A operand's bin
-    dbl4 Z = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (k < nk) {
-        const int s4 = 4 * k + grp;
-        const double h = ja >= b0 && ja < b1 && s4 < T.S ? HR[(size_t)ja * T.S + s4] : 0.0;
-        Z = __builtin_amdgcn_mfma_f64_16x16x4f64(h, rwk[k], Z, 0, 0, 0);
-      }
-    if (gamma && jb / kABlock != qref) {  // a 16-bin step lies inside one reference block
-      qref = jb / kABlock;
-      const double *r = BF + (size_t)qref * 4;
-      Eref = rel_cell(kGammaPE, rc, r[0], r[1], r[2]).Eref;
-    }
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      // bin of register v; outside [b0, b1) its seed is zero and a bin inside stands in
-      const int bb = min(max(jb + grp + 4 * v, b0), b1 - 1);
-      const double *br = BR + (size_t)bb * kBinRecLen;
-      if (gamma) {
-        const double Gr = Z[v] * dexp(rel_exponent(rc[0], -rc[1], Eref, br[6], br[7]), ec);
-        A0 += Gr;
-        A1 = __fma_rn(Gr, br[1], A1);
-        A2 = __fma_rn(Gr, br[0], A2);
-      } else {
-        double z;
-        const double Gr = Z[v] * dexp(gauss_exponent(rc[0], rc[1], rc[2], br[0], z), ec);
-        const double Grz = Gr * z;
-        A0 += Gr;
-        A1 += Grz;
-        A2 = __fma_rn(Grz, z, A2);
-      }
-    }
-  }
+  double A0 = 0.0, A1 = 0.0, A2 = 0.0;
+  if (Sh.family == kGammaPE)
+    adj_s_walk<kGammaPE>(BR, BF, HR, T.S, nk, b0, b1, rc, rwk, ec, A0, A1, A2);
+  else
+    adj_s_walk<kGaussE>(BR, BF, HR, T.S, nk, b0, b1, rc, rwk, ec, A0, A1, A2);
   // the four lanes of a cell (l, l ^ 16, l ^ 32, l ^ 48) in a fixed order
   A0 += __shfl_xor(A0, 16, 64);
   A1 += __shfl_xor(A1, 16, 64);
@@ -1584,18 +1607,16 @@ hipError_t launch_binsF(const BatchView &v, const double *theta, double *mu_out,
 // contractions over the shared T, which run on v_mfma_f64_16x16x4f64:
 //   mu^T[j][q]  = sum_s T[s][j] R[s][q]              (bins x toys, K = species)
 //   grad[s][q] += sum_j T[s][j] G[q][j],  G = sum_d eps_d (1 - n_dj/mu_dj)
-// A wave walks kTmplWaveBins bins of its group in chunks of 16.  Chunk row r
+// A wave walks WB bins of its group in chunks of 16.  Chunk row r
 // (0..15) stands for bin 4 (r % 4) + r / 4, so that the first product leaves
 // lane l with toy l % 16 at the four consecutive bins 4 (l / 16) + v of its
 // registers v (its counts are one 32-byte run), and register v is then the
 // B operand of the second product's step v as it stands (k = l / 16 is bin
 // 4k + v).  Padding species, bins past the window and empty toy slots carry
-// zeros into both products.  The four waves of a block cover kTmplBlockBins
+// zeros into both products.  The four waves of a block cover 4 WB
 // consecutive bins and fold their partials through LDS in a fixed order into
 // one row per toy and block.
-constexpr int kTmplWaveBins = kTmplBlockBins / kWaves;
-static_assert(kTmplWaveBins % 16 == 0, "template chunks are 16 bins");
-
+template <int WB>
 __global__ __launch_bounds__(256) void k_tmpl(const int *__restrict__ toy_list, const int *__restrict__ groups,
                                               const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                               const double *__restrict__ theta, int stride,
@@ -1632,12 +1653,13 @@ __global__ __launch_bounds__(256) void k_tmpl(const int *__restrict__ toy_list, 
   dbl4 gacc = {0.0, 0.0, 0.0, 0.0};
   double sum = 0.0;
   uint32_t bad = 0u;
-  const int w0 = blk * kTmplBlockBins + wv * kTmplWaveBins;
+  static_assert(WB % 16 == 0, "template chunks are 16 bins");
+  const int w0 = blk * kWaves * WB + wv * WB;
   // loads use clamped (in-bounds) indices and are unconditional, so that a
   // chunk's loads issue together; what lies outside is zeroed by selects
   const int sA[4] = {min(k4, S - 1), min(4 + k4, S - 1), min(8 + k4, S - 1), min(12 + k4, S - 1)};
   const int sq = min(q, S - 1);
-  for (int c = 0; c < kTmplWaveBins; c += 16) {
+  for (int c = 0; c < WB; c += 16) {
     const int n0 = w0 + c;
     if (n0 >= L) break;
     const int jb = n0 + 4 * k4;  // lane l: toy q at bins jb + v, v = 0..3
@@ -1717,8 +1739,16 @@ __global__ __launch_bounds__(256) void k_tmpl(const int *__restrict__ toy_list, 
 
 hipError_t launch_tmpl(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active, hipStream_t st) {
   if (v.nt == 0 || v.n_tgroup == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tmpl, dim3(v.n_tgroup, v.max_bin_blocks_t), dim3(kBlock), 0, st, v.listt, v.tgroup, v.toys,
-                     v.shapes, theta, v.stride, v.cnt, active, v.nllp, v.badp, v.gpart, mu_out);
+  const dim3 grid(v.n_tgroup, v.max_bin_blocks_t), block(kBlock);
+  if (v.tmpl_bins == kTmplBlockBins)
+    hipLaunchKernelGGL(k_tmpl<kTmplBlockBins / kWaves>, grid, block, 0, st, v.listt, v.tgroup, v.toys, v.shapes,
+                       theta, v.stride, v.cnt, active, v.nllp, v.badp, v.gpart, mu_out);
+  else if (v.tmpl_bins == 256)
+    hipLaunchKernelGGL(k_tmpl<64>, grid, block, 0, st, v.listt, v.tgroup, v.toys, v.shapes, theta, v.stride, v.cnt,
+                       active, v.nllp, v.badp, v.gpart, mu_out);
+  else
+    hipLaunchKernelGGL(k_tmpl<16>, grid, block, 0, st, v.listt, v.tgroup, v.toys, v.shapes, theta, v.stride, v.cnt,
+                       active, v.nllp, v.badp, v.gpart, mu_out);
   return hipGetLastError();
 }
 
