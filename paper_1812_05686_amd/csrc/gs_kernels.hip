@@ -518,19 +518,22 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
 // l % 16; layouts checked on the device).  Cells come from the compacted hull groups that meet the
 // tile and are staged through LDS as in the 1-D fold, each with its
 // tile-relative exponent about the reference point of either half-tile (the
-// 32 bins that a 1-D fold tile spans): {A lower, B, Eref lower, A upper,
-// Eref upper, 0} (A depends on the reference for the Gaussian families).
+// 32 bins that a 1-D fold tile spans): {A, Eref, B} of the lower half-tile,
+// then of the upper one (A and B depend on the reference for the Gaussian
+// families).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // One staged batch of nb cells (a multiple of 4: padding slots hold zero
-// weights) against the wave's 16 bins; ao / eo: the slots of the wave's
-// half-tile's A and Eref in a staged cell.
-__device__ __forceinline__ dbl4 folds_batch(const double *srec, const double *swt, int nb, int ao, int eo, double u,
-                                            double v, const ExpK &ec, dbl4 acc) {
+// weights) against the wave's 16 bins; sb: the staged records offset to the
+// wave's half-tile (3 half), so that a cell's {A, Eref, B} sit at one address
+// plus immediate offsets.
+template <bool CLAMP>
+__device__ __forceinline__ dbl4 folds_batch(const double *sb, const double *swt, int nb, double u, double v,
+                                            const ExpK &ec, dbl4 acc) {
   const int lane = threadIdx.x & 63, kc = lane >> 4, q = lane & 15;
   for (int c4 = 0; c4 < nb; c4 += 4) {
-    const double *r = srec + 6 * (c4 + kc);
-    const double k = dexp(rel_exponent(r[ao], r[1], r[eo], u, v), ec);
+    const double *r = sb + 6 * (c4 + kc);
+    const double k = dexp<CLAMP>(rel_exponent(r[0], r[2], r[1], u, v), ec);
     const double w = swt[(c4 + kc) * GS_MAX_SPECIES + q];
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(k, w, acc, 0, 0, 0);
   }
@@ -552,8 +555,8 @@ __device__ __forceinline__ double cell_weight(const ShapeDev &Sh, int i, int q) 
 template <int FAM>
 __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
                                             int n_list, int c_lo, int c_hi, double *srec, double *swt,
-                                            const TileRef &rh, int ao, int eo, double u, double v,
-                                            const ExpK &ec, dbl4 acc) {
+                                            const TileRef &rh, const TileEnds &te, int *sclamp, double u,
+                                            double v, const ExpK &ec, dbl4 acc) {
   static_assert(2 * kStage == kWaves * 64, "one staged cell and half-tile per thread");
   constexpr int kGPB = kStage / kGroup;
   const int tid = threadIdx.x, cs = tid % kStage, half = tid / kStage;
@@ -580,26 +583,27 @@ __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__
     for (int e = 0; e < 4; e++) wq[e] = cell >= 0 ? wsrc[e] : make_double2(0.0, 0.0);
     __syncthreads();  // every wave is done with the previous batch
     {
-      // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W}
+      // record {k - 1, 1/th hi, lo, C hi, lo, W} (gamma) or {m, 1/s, c0, W};
+      // staged per half-tile as {A, Eref, B} at slots 3 half .. 3 half + 2
       const double rc[6] = {f[0].x, f[0].y, f[1].x, f[1].y, f[2].x, f[2].y};
       const RelCell q = rel_cell(FAM, rc, rh.x, rh.Lh, rh.Ll);
-      if (half == 0) {
-        ((double2 *)srec)[3 * cs] = make_double2(q.A, q.B);
-        srec[6 * cs + 2] = q.Eref;
-      } else {
-        srec[6 * cs + 3] = q.A;
-        ((double2 *)srec)[3 * cs + 2] = make_double2(q.Eref, 0.0);
-      }
+      double *o = srec + 6 * cs + 3 * half;
+      o[0] = q.A;
+      o[1] = q.Eref;
+      o[2] = q.B;
+      // a staged cell whose exponent may leave [kExpNoClampMin, inf) on its half-tile
+      if (cell >= 0 && !exp_args_bounded(q.A, q.B, q.Eref, te.uf, te.vf, te.ul, te.vl)) *sclamp = 1;
     }
 #pragma unroll
     for (int e = 0; e < 4; e++) ((double2 *)swt)[(cs * GS_MAX_SPECIES + 8 * half) / 2 + e] = wq[e];
     __syncthreads();
-    acc = folds_batch(srec, swt, nb, ao, eo, u, v, ec, acc);
+    const double *sb = srec + 3 * (int)(threadIdx.x >> 6 >> 1);
+    acc = *sclamp ? folds_batch<true>(sb, swt, nb, u, v, ec, acc) : folds_batch<false>(sb, swt, nb, u, v, ec, acc);
   }
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ items, int n_items,
+__global__ __launch_bounds__(256, 6) void k_fold_s(const FoldItem *__restrict__ items, int n_items,
                                                 const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                 const double *__restrict__ rec, const int2 *__restrict__ ghull,
                                                 int mode, const uint8_t *__restrict__ active,
@@ -608,6 +612,7 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   __shared__ __align__(16) double swt[kStage * GS_MAX_SPECIES];
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
+  __shared__ int sclamp;
   const ExpK ec = exp_consts();
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
@@ -626,7 +631,21 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
   const TileRef rh = tile_ref(Sh, T, it.bin0 + half * (kFoldTile / 2), kFoldTile / 2);
   double u, v;
   rel_offsets(Sh.family, bp[0], bp[2], bp[3], rh.x, rh.Lh, rh.Ll, u, v);
-  const int ao = half ? 3 : 0, eo = half ? 4 : 2;
+  // offsets of the half-tile's first and last window bins, for the staging's
+  // range check; a gamma tile whose first bin lies at x <= 0 always clamps
+  // (offsets there stand in for ln x = 0, so the exponent is not concave)
+  TileEnds te;
+  {
+    const int fb = min(it.bin0 + half * (kFoldTile / 2), T.L - 1);
+    const int lb = min(it.bin0 + half * (kFoldTile / 2) + kFoldTile / 2 - 1, T.L - 1);
+    const double *bf = Sh.bins + (size_t)(T.lo + fb) * kBinLen, *bl = Sh.bins + (size_t)(T.lo + lb) * kBinLen;
+    rel_offsets(Sh.family, bf[0], bf[2], bf[3], rh.x, rh.Lh, rh.Ll, te.uf, te.vf);
+    rel_offsets(Sh.family, bl[0], bl[2], bl[3], rh.x, rh.Lh, rh.Ll, te.ul, te.vl);
+    // wave-uniform: keep them in scalar registers
+    te = {read_lane(te.uf, 0), read_lane(te.vf, 0), read_lane(te.ul, 0), read_lane(te.vl, 0)};
+  }
+  if (threadIdx.x == 0)
+    sclamp = Sh.family == kGammaPE && !(Sh.bins[(size_t)(T.lo + it.bin0) * kBinLen] > 0.0) ? 1 : 0;
   const int j0 = T.lo + it.bin0, j1 = T.lo + min(it.bin0 + kFoldTile, T.L);
   const double *R = rec + T.cell_off * kRecLen;
   const int g_end = min(it.cell1, Sh.n_true);
@@ -637,14 +656,14 @@ __global__ __launch_bounds__(256) void k_fold_s(const FoldItem *__restrict__ ite
     const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
                              glist, gcnt);
     if (gamma)
-      acc = folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, ao, eo, u, v, ec, acc);
+      acc = folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, te, &sclamp, u, v, ec, acc);
     else
-      acc = folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, ao, eo, u, v, ec, acc);
+      acc = folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, te, &sclamp, u, v, ec, acc);
   }
   if (gamma)
-    acc = folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, ao, eo, u, v, ec, acc);
+    acc = folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, te, &sclamp, u, v, ec, acc);
   else
-    acc = folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, ao, eo, u, v, ec, acc);
+    acc = folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, te, &sclamp, u, v, ec, acc);
   // lane l, register r: bin l / 16 + 4 r of the wave's 16, species l % 16
   const int q = lane & 15, S = T.S;
 #pragma unroll
