@@ -1059,6 +1059,10 @@ gs_status gs_batch_layout(const gs_batch *b, int32_t *out) {
 gs_status gs_batch_set_log_cut(gs_batch *b, double log_cut) {
   if (!b || std::isnan(log_cut)) return fail(GS_ERR_ARG, "bad argument");
   b->v.log_cut = log_cut;
+  if (b->graph) {  // a captured fit graph holds the old cut
+    HIP_TRY(hipGraphExecDestroy(b->graph));
+    b->graph = nullptr;
+  }
   return GS_OK;
 }
 

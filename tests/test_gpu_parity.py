@@ -650,3 +650,34 @@ def test_full_size_mixed_batch(gs, orc):
     nll, grad, st = nll.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
     assert (st == 0).all() and np.isfinite(nll).all()
     _sampled_oracle_check(orc, toys, nll, grad, st, _mixed_sample(toys, 1))
+
+
+@pytest.mark.parametrize("which", ["c1", "small2d_ragged"])
+def test_model_evaluation_matches_batched(gs, which):
+    """gs_nll_grad of a model, at changing parameters and with other work of the same model
+    (plain path, expected counts) in between, equals the batched evaluation of a one-toy batch
+    bit for bit, also after both take a new log cut."""
+    import torch
+    m = CASES[which]()
+    model = gs.Model(m)
+    batch = gs.Batch([m])
+    pts = [gsgen.offset_point(m, 1.0, seed=s) for s in (1, 2, 3)] + [m.theta_true]
+
+    def eager(th):
+        t = torch.tensor(th[None, :], dtype=torch.float64, device="cuda")
+        n, g, s = batch.nll_grad(t)
+        torch.cuda.synchronize()
+        return float(n[0]), g[0, : m.n_params].cpu().numpy(), int(s[0])
+
+    for rep in range(2):
+        for th in pts:
+            v, g, st = model.nll_grad(th)
+            ev, eg, est = eager(th)
+            assert st == est and v == ev and np.array_equal(g, eg), (which, rep)
+            model.nll(th * 1.001)
+            model.expected(th)
+    model.set_log_cut(-20.0)
+    batch.set_log_cut(-20.0)
+    v, g, st = model.nll_grad(pts[0])
+    ev, eg, est = eager(pts[0])
+    assert v == ev and np.array_equal(g, eg)
