@@ -161,6 +161,9 @@ constexpr uint32_t kCellInvalid = 1u, kCellUnresolved = 2u;
 __device__ __forceinline__ void put_support(double *rc, int2 s) { *(int2 *)(rc + 6) = s; }
 __device__ __forceinline__ int2 get_support(const double *rc) { return *(const int2 *)(rc + 6); }
 
+// GEN selects the shapes of the direct path (a launch of its own, so that the
+// direct path's register use does not lower the fast path's occupancy).
+template <bool GEN>
 __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride, double log_cut,
                                                const uint8_t *__restrict__ active, double *__restrict__ rec,
@@ -171,6 +174,7 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.cflag_blocks) return;
   const ShapeDev &Sh = shapes[T.shape];
+  if ((Sh.gen != 0) != GEN) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool ok = true, unresolved = false;
   int hx = 0x7fffffff, hy = -1;  // this cell's contribution to its group's support hull
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
     ok = ok && isfinite(W);
     double r[kRecLen];
     int2 sp;
-    if (Sh.gen) {  // direct path: {m, s, W, a, b, c, support, d} (GenCell constants)
+    if constexpr (GEN) {  // direct path: {m, s, W, a, b, c, support, d} (GenCell constants)
       GenCell gc;
       ok = ok && gen_cell(Sh.family, Sh.shape, mo.m, mo.s, gc);
 #pragma unroll
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
       const Span spn = cell_support(Sh.family, r, mo.m, mo.s, ok, Sh.bins, Sh.n_reco, Sh.bx0, Sh.bw, log_cut);
       sp = make_int2(spn.x, spn.y);
     }
-    if (!Sh.gen && ok && sp.y > T.lo && sp.x < T.lo + T.L) {  // the response reaches the window
+    if (!GEN && ok && sp.y > T.lo && sp.x < T.lo + T.L) {  // the response reaches the window
       // the widths of the bins the response covers (the binning's width if uniform)
       double w = Sh.bw;
       if (!(w > 0.0)) {
@@ -243,8 +247,11 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
 
 hipError_t launch_cells(const BatchView &v, const double *theta, const uint8_t *active, hipStream_t st) {
   dim3 grid(v.max_cflag_blocks, v.n_list);
-  hipLaunchKernelGGL(k_cells, grid, dim3(kCellBlock), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, v.log_cut, active,
-                     v.rec, v.sup, v.ghull, v.cflag);
+  hipLaunchKernelGGL(k_cells<false>, grid, dim3(kCellBlock), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride, v.log_cut,
+                     active, v.rec, v.sup, v.ghull, v.cflag);
+  if (v.has_gen)
+    hipLaunchKernelGGL(k_cells<true>, grid, dim3(kCellBlock), 0, st, v.toy_list, v.toys, v.shapes, theta, v.stride,
+                       v.log_cut, active, v.rec, v.sup, v.ghull, v.cflag);
   return hipGetLastError();
 }
 
