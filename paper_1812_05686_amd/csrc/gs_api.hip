@@ -428,11 +428,13 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
     const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
-    const long long c2 = (long long)kBlock * k.iter2;
-    T.bin_blocks = T.two_d  ? (int)(((long long)T.L * T.K + c2 - 1) / c2)
+    // 2-D: k_bins2 blocks of iter2 rounds of kWaves x 16 window bins; each writes a row of
+    // rate pieces (the first hblocks rows) and a row of nuisance pieces (the next bin_blocks)
+    const int c2 = kWaves * 16 * k.iter2;
+    T.bin_blocks = T.two_d  ? (T.L + c2 - 1) / c2
                    : T.tmpl ? (T.L + v.tmpl_bins - 1) / v.tmpl_bins
                             : (T.L + kBlock - 1) / kBlock;
-    T.hblocks = T.two_d ? (T.L + kHTile * k.iter2 - 1) / (kHTile * k.iter2) : 0;
+    T.hblocks = T.two_d ? T.bin_blocks : 0;
     if (T.mv) {  // rows of k_mv_bins (energy blocks), then one per slice (k_mv_slice)
       T.eblocks = (T.L + kHTile - 1) / kHTile;
       T.hblocks = T.eblocks;
@@ -623,9 +625,9 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
   }
 
   // ---- toys: the fields and offsets that do not depend on the layout knobs ----
-  long long cell_off = 0, win_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0;
-  long long cflag_off = 0, psd_off = 0, ghull_off = 0, gam_off = 0, slice_off = 0, sig_n = 0;
-  std::vector<double> cnt_h, pc_h, ps_h;
+  long long cell_off = 0, win_off = 0, fh_off = 0, bref_off = 0, cnt_off = 0, pull_off = 0;
+  long long cflag_off = 0, psd_off = 0, ghull_off = 0, slice_off = 0, sig_n = 0;
+  std::vector<double> cnt_h, nsum_h, pc_h, ps_h;
   std::vector<int> sedge_h;
   BatchView &v = B->v;
   for (int t = 0; t < n_toys; t++) {
@@ -666,13 +668,12 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     T.n_cell = sh.n_cell;
     T.S = sh.S;
     for (int k = 0; k < T.D; k++) T.exposure[k] = d.exposure[k];
-    T.gam_off = gam_off;
-    if (T.two_d) gam_off += (long long)T.L * T.K;
     T.cflag_blocks = (sh.n_cell + kCellBlock - 1) / kCellBlock;
     T.cflag_off = cflag_off;
     T.ghull_off = ghull_off;
     T.cell_off = cell_off;
     T.win_off = win_off;
+    T.fh_off = fh_off;
     T.bref_off = bref_off;
     T.cnt_off = cnt_off;
     T.pull_off = pull_off;
@@ -697,13 +698,30 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
         for (int j = d.win_lo; j < d.win_hi; j++)
           for (int q = 0; q < T.K; q++) cnt_h.push_back(d.counts[((size_t)k * d.n_reco + j) * T.K + q]);
     }
+    T.nsum_off = (long long)nsum_h.size();
+    T.cnl = 0.0;
+    if (T.two_d && !T.mv) {  // the constants k_bins2 takes: summed counts, sum of n ln eps (long double)
+      long double c = 0.0L;
+      for (int j = d.win_lo; j < d.win_hi; j++)
+        for (int q = 0; q < T.K; q++) {
+          double n = 0.0;
+          for (int k = 0; k < T.D; k++) {
+            const double nk = d.counts[((size_t)k * d.n_reco + j) * T.K + q];
+            n += nk;
+            c += (long double)nk * std::log((long double)d.exposure[k]);
+          }
+          nsum_h.push_back(n);
+        }
+      T.cnl = (double)c;
+    }
     for (int p = 0; p < T.P; p++) {
       const bool has = d.pull_sigma && d.pull_sigma[p] > 0;
       pc_h.push_back(has ? d.pull_centre[p] : 0.0);
       ps_h.push_back(has ? d.pull_sigma[p] : 0.0);
     }
     cell_off += sh.n_cell;
-    win_off += T.L + kWinPad;
+    win_off += win_rows(T.L);
+    fh_off += (long long)win_rows(T.L) * T.S;
     bref_off += (T.L + kABlock - 1) / kABlock;
     cnt_off += T.mv ? (long long)T.D * (T.L + (long long)T.n_slices * T.K) : (long long)T.D * T.L * T.K;
     cflag_off += T.cflag_blocks;
@@ -756,15 +774,14 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     HIP_TRY(B->alloc(&v.sig, (size_t)sig_n));
   }
   if (v.has_2d) {
-    HIP_TRY(B->alloc(&v.H, (size_t)win_off * GS_MAX_SPECIES));
+    HIP_TRY(B->alloc(&v.H, (size_t)fh_off));
     HIP_TRY(B->alloc(&v.P, (size_t)psd_off));
     HIP_TRY(B->alloc(&v.dP, (size_t)psd_off * 3));
     HIP_TRY(B->alloc(&v.vpart, (size_t)cap.vpart * kVLen));
-    HIP_TRY(B->alloc(&v.Gam, (size_t)gam_off));
   }
   HIP_TRY(B->alloc(&v.fpart, (size_t)cap.fpart));
   HIP_TRY(B->alloc(&v.fspart, (size_t)cap.fspart));
-  HIP_TRY(B->alloc(&v.F, (size_t)win_off * GS_MAX_SPECIES));
+  HIP_TRY(B->alloc(&v.F, (size_t)std::max<long long>(fh_off, 1)));
   HIP_TRY(B->alloc(&v.apart, (size_t)cap.apart));
   HIP_TRY(B->alloc(&v.binrec, (size_t)win_off * kBinRecLen));
   HIP_TRY(hipMemset(v.binrec, 0, (size_t)win_off * kBinRecLen * sizeof(double)));  // the padding rows stay zero
@@ -810,6 +827,12 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     v.n_tgroup = (int)grp.size() / 2;
   }
   HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
+  if (!nsum_h.empty()) {
+    double *ns;
+    HIP_TRY(B->alloc(&ns, nsum_h.size()));
+    HIP_TRY(hipMemcpy(ns, nsum_h.data(), nsum_h.size() * 8, hipMemcpyHostToDevice));
+    v.nsum = ns;
+  }
   HIP_TRY(hipMemcpy(pc, pc_h.data(), pc_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ps, ps_h.data(), ps_h.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipDeviceSynchronize());
@@ -1295,7 +1318,7 @@ gs_status gs_species_spectra(gs_model *M, const double *theta, double *F) {
   if (s != GS_OK) return s;
   const ToyDev &T = B->toys_h[0];
   const ShapeDev &sh = B->shapes_h[0];
-  std::vector<double> f((size_t)T.L * T.S);
+  std::vector<double> f((size_t)T.L * T.S);  // the device's F rows (fh_off = 0: the model's only toy)
   if (B->v.has_tmpl) {  // the species spectra are the templates themselves
     std::vector<double> w((size_t)sh.Sg * sh.n_true);
     HIP_TRY(hipMemcpy(w.data(), sh.wcellT, sizeof(double) * w.size(), hipMemcpyDeviceToHost));

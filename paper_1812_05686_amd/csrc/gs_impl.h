@@ -20,16 +20,19 @@ constexpr int kVLen = GS_MAX_SPECIES + 4;  // 2-D gradient partials per block: s
 constexpr int kWaves = 4;       // wavefronts per workgroup cooperating on one tile
 constexpr int kAdjGroupWaves = 2;  // workgroup size of the adjoint that gives each wave its own item
 constexpr int kBlock = 256;     // threads per reduction block
-constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_hseed round (2-D models)
-// k_bins2 and k_hseed rounds per block (BatchView::iter2): each block stages
-// the toy's pulse-shape table, so large batches give a block kIter2Large
-// rounds (kBlock (bin, pulse-shape bin) cells, or kHTile bins, each) to pay for
-// it; small ones one round, so that one model still fills the GPU
+constexpr int kHTile = kBlock / GS_MAX_SPECIES;  // energy bins per k_mv_bins block (multivariate models)
+// k_bins2 rounds per block (BatchView::iter2): each block stages the toy's
+// pulse-shape table, so large batches give a block kIter2Large rounds
+// (kWaves x 16 window bins each) to pay for it; small ones one round, so that
+// one model still fills the GPU
 constexpr int kIter2Large = 8;
 constexpr int kGradLen = GS_MAX_PARAMS;
 // Zeroed window-bin rows after each toy's window: kernels that walk bins in
 // steps of 16 read whole steps without clamping the bin index
 constexpr int kWinPad = 16;
+// Window rows a toy owns (binrec, F, H): its window, at least kWinPad zeroed
+// rows, rounded up to a multiple of 16
+constexpr int win_rows(int L) { return (L + kWinPad + 15) & ~15; }
 constexpr int kCellBlock = 64;  // cells per k_cells block (one invalid-response flag each)
 // cells per k_cellgrad block: kBlock (one per thread) for small batches, where
 // the grid must fill the GPU, 4 * kBlock for large ones (one reduction per
@@ -72,13 +75,16 @@ struct ToyDev {
   int gen;                      // 1: response through the direct per-pair path (k_foldg, k_adjg)
   int n_slices, eblocks;        // mv: energy slices; k_mv_bins blocks (kHTile window bins each)
   int fold_chunks, adj_chunks;
-  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: iter2 * kBlock bin x pulse-shape cells each) / cells (k_cellgrad)
-  int hblocks;                  // 2-D: k_hseed blocks (kHTile window bins each)
+  int bin_blocks, cell_blocks;  // reduction blocks over window bins (2-D: k_bins2 blocks) / cells (k_cellgrad)
+  int hblocks;                  // 2-D: rows of rate pieces in vpart (joint: bin_blocks; multivariate: eblocks)
   int cflag_blocks;             // k_cells blocks (kCellBlock cells each)
   long long cell_off;   // rec[(cell_off + i) * kRecLen]
-  long long win_off;    // binrec[(win_off + b) * kBinRecLen], F[(win_off + b) * S]
+  long long win_off;    // binrec[(win_off + b) * kBinRecLen]
+  long long fh_off;     // per-species window arrays: F[fh_off + b * S + s], H likewise (win_rows(L) rows of S)
   long long bref_off;   // adjoint block references: bref[(bref_off + q) * 4], q = b / kABlock
   long long cnt_off;    // counts of the window: cnt[cnt_off + (d * L + b) * K + k]
+  long long nsum_off;   // joint 2-D: nsum[nsum_off + b * K + k] = sum_d n_dbk
+  double cnl;           // joint 2-D: sum over the window's cells and datasets of n ln eps_d (k_finish subtracts it)
   long long fpart_off;  // fold partials: fpart[fpart_off + chunk * L + b]
   long long fs_off;     // per-species fold partials: fspart[fs_off + (chunk * L + b) * S + s]
   long long apart_off;  // adjoint partials: apart[apart_off + (chunk * n_cell + i) * 3 + q]
@@ -87,8 +93,7 @@ struct ToyDev {
   long long cflag_off;  // per k_cells block: cflag[cflag_off + blk]
   long long ghull_off;  // per kGroup grid cells: union of their supports, ghull[ghull_off + g]
   long long pull_off;   // pull centres / widths [P]
-  long long vpart_off;  // 2-D: vpart[(vpart_off + r) * kVLen + e], rows: hblocks of k_hseed, then bin_blocks of k_bins2
-  long long gam_off;    // 2-D: Gam[gam_off + b * K + k] = sum_d eps_d (1 - n/mu)
+  long long vpart_off;  // 2-D: vpart[(vpart_off + r) * kVLen + e], rows: hblocks of rate pieces, then bin_blocks of nuisance pieces
   long long psd_off;    // 2-D: P[psd_off + s * K + k], dP[(psd_off + s * K + k) * 3 + v]
   long long slice_off;  // mv: slice edges sedge[slice_off + i] (window bins, n_slices + 1)
   long long sig_off;    // mv: slice seeds sig[sig_off + i * S + s]
@@ -120,12 +125,12 @@ struct BatchView {
   int n1d, n2d, nt;  // 1-D analytic, 2-D and template toys
   int max_cells, max_cell_blocks, max_bin_blocks;
   int grad_cells;  // cells per k_cellgrad block (kBlock or kGradCellsLarge)
-  int iter2;       // rounds per k_bins2 / k_hseed block (1 or kIter2Large)
+  int iter2;       // rounds per k_bins2 block (1 or kIter2Large)
   int adj_waves;   // waves per adjoint workgroup (1 or kWaves)
   int max_bin_blocks1, max_bin_blocks2;  // the same over 1-D / 2-D toys
   int max_ls_blocks;  // kBlock blocks over (window bin, species) pairs
   int max_psd_sk;     // largest S x K of a 2-D toy (P, dP are staged in LDS)
-  int max_hblocks;    // k_hseed grid
+  int max_hblocks;    // largest hblocks over the joint 2-D toys
   double log_cut;   // pairs whose log-density is below this are skipped
   const ToyDev *toys;
   const ShapeDev *shapes;
@@ -136,7 +141,7 @@ struct BatchView {
   int max_cflag_blocks;
   double *fpart;    // fold partials (combined weight)
   double *fspart;   // fold partials per species
-  double *F;        // per-species spectra of the window, bin width included
+  double *F;        // per toy [win_rows(L)][S] from fh_off: per-species spectra of the window, bin width included
   double *apart;    // adjoint partials
   double *binrec;   // window bins: xbar, ln xbar hi, lo, G, G ln xbar, G xbar, block offsets u, v
   double *bref;     // per block of kABlock window bins: reference xbar, ln xbar (hi, lo), 0
@@ -144,6 +149,7 @@ struct BatchView {
   double *gpart;    // gradient partials
   uint32_t *badp;   // domain flags per bin block
   const double *cnt;
+  const double *nsum;  // joint 2-D toys: counts summed over the datasets
   const double *pull_c, *pull_s;
   const FoldItem *fold_items;  // every toy's per-species fold items (kFoldTile bins): 1-D toys first, then 2-D
   int n_fold_items, n_fold1s;  // all of them / those of 1-D toys
@@ -154,8 +160,7 @@ struct BatchView {
   const AdjItem *adj1, *adj2;
   int n_fold1, n_fold2, n_adj1, n_adj2;
   // secondary observable (2-D) models
-  double *H;        // [win bins][S]: dx_j sum_k P_sk Gam_jk
-  double *Gam;      // [win bins][K]
+  double *H;        // per toy [win_rows(L)][S] from fh_off: dx_j sum_k P_sk Gam_jk
   double *P, *dP;   // pulse-shape probabilities and their nuisance derivatives
   double *vpart;    // per k_bins2 block: sum_j F_js sum_k P_sk Gam_jk (s), nuisance pieces
   uint32_t *pflag;  // [toy]: invalid pulse-shape nuisance

@@ -161,6 +161,12 @@ constexpr uint32_t kCellInvalid = 1u, kCellUnresolved = 2u;
 __device__ __forceinline__ void put_support(double *rc, int2 s) { *(int2 *)(rc + 6) = s; }
 __device__ __forceinline__ int2 get_support(const double *rc) { return *(const int2 *)(rc + 6); }
 
+// Entry (species s, window bin b) of a toy's per-species window array (F, H):
+// rows of the toy's S species from fh_off.
+__device__ __forceinline__ long long fh_at(const ToyDev &T, int s, int b) {
+  return T.fh_off + (long long)b * T.S + s;
+}
+
 // GEN selects the shapes of the direct path (a launch of its own, so that the
 // direct path's register use does not lower the fast path's occupancy).
 template <bool GEN>
@@ -1203,7 +1209,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict
     hi = max(hi, __shfl_xor(hi, o, 64));
   }
   const int b0 = max(it.bin0, wave_uniform(lo) - T.lo), b1 = min(it.bin1, wave_uniform(hi) - T.lo);
-  const double *BR = binrec + T.win_off * kBinRecLen, *BF = bref + T.bref_off * 4, *HR = H + T.win_off * T.S;
+  const double *BR = binrec + T.win_off * kBinRecLen, *BF = bref + T.bref_off * 4, *HR = H + T.fh_off;
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
   if (Sh.family == kGammaPE)
     adj_s_walk<kGammaPE>(BR, BF, HR, T.S, nk, b0, b1, rc, rwk, ec, A0, A1, A2);
@@ -1490,7 +1496,7 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
     const bool any_range = __ballot(range) != 0ull, any_unres = __ballot(unres) != 0ull;
     if (p == 0) {
       uint32_t st = 0;
-      double sum = nll_bins + pull;
+      double sum = nll_bins + pull - T.cnl;  // cnl: the parameter-free part k_bins2 leaves out
       if (any_dom || (T.two_d && pflag[t])) st |= GS_ST_DOMAIN;  // pflag: invalid pulse-shape nuisance
       if (any_nonfin) st |= GS_ST_NONFINITE;
       if (any_unres) st |= GS_ST_UNRESOLVED;
@@ -1549,7 +1555,7 @@ hipError_t launch_bins_setup(double *bins, const double *edges, int n_reco, hipS
 }
 
 // ---------------------------------------------- per-species (plain path) --
-// F[(win_off + b) * S + s] = dx_b * sum over chunks (fixed order); one thread per (bin, species).
+// F (species s, window bin b) = dx_b * sum over chunks (fixed order); one thread per (bin, species).
 __global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
                                                  const ShapeDev *__restrict__ shapes,
                                                  const double *__restrict__ fspart, int mode,
@@ -1565,7 +1571,7 @@ __global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_lis
   const double dx = Sh.bins[(size_t)(T.lo + b) * kBinLen + 1];
   double acc = 0.0;
   for (int c = 0; c < T.fold_chunks; c++) acc += fspart[T.fs_off + ((long long)c * T.L + b) * T.S + sp];
-  F[(T.win_off + b) * T.S + sp] = T.gen ? acc : dx * acc;
+  F[fh_at(T, sp, b)] = T.gen ? acc : dx * acc;
 }
 
 hipError_t launch_reduceF(const BatchView &v, int mode, const uint8_t *active, hipStream_t st) {
@@ -1595,7 +1601,7 @@ __global__ __launch_bounds__(256) void k_binsF(const int *__restrict__ toy_list,
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double sum = 0.0;
   if (b < T.L) {
-    const double *f = F + (T.win_off + b) * T.S;
+    const double *f = F + fh_at(T, 0, b);
     double mu1 = 0.0;
     for (int s = 0; s < Sh.S; s++) mu1 = __fma_rn(th[Sh.sp_of[s]], f[s], mu1);
     uint32_t bad = 0u;
@@ -1856,33 +1862,50 @@ hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *ac
   return hipGetLastError();
 }
 
-// 2-D likelihood over the (window bin j, pulse-shape bin k) cells of a toy,
-// iter2 * kBlock per block, cells threadIdx.x, + kBlock, ... per thread:
-// mu_djk = eps_d sum_s R_s F_js P_sk, the Poisson terms (block partial of
-// -ln L), Gam_jk = sum_d eps_d (1 - n_djk/mu_djk), and the block partial of
-// the nuisance-gradient pieces that need no fold,
-// sum_jk Gam_jk sum_s R_s F_js dP_sk/dnu.  P and dP are staged in LDS as
-// [s][4][k].
-__global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
+// Joint 2-D likelihood of a toy (section 2.4) with its adjoint seeds, on
+// v_mfma_f64_16x16x4f64.  With RF_js = R_s F_js the expected counts of the
+// (window bin j, pulse-shape bin k) cells are mu_djk = eps_d M_jk, M = RF P (a
+// sum over species), and Gam_jk = sum_d eps_d (1 - n_djk/mu_djk).  A wave takes
+// 16 window bins at a time and, per tile of 16 pulse-shape bins, forms
+//   M^T = P^T RF^T  (A: P from LDS; B: rows of F times the rates),
+//   the Poisson terms and Gam^T, in M^T's accumulator layout (lane l, register
+//        v: k = l/16 + 4v, j = l%16),
+//   h^T += P Gam^T: that accumulator layout is this product's B operand
+//        layout (lane l: k = l/16 + 4c, j = l%16), so Gam stays in registers,
+//   D_v^T = dP_v^T RF^T and A_v += sum_jk D_v^T Gam^T, the pieces of the
+//        pulse-shape nuisance gradient that need no fold (v: delta, kappa, eta),
+// then H_js = dx_j h_js (h_js = sum_k P_sk Gam_jk), the bin record, and the
+// rate-gradient piece a_s = sum_j F_js h_js.  Pulse-shape bins past K and
+// window bins past the window take Gam = 0 and zero B operands; their A
+// operands are clamped (finite) reads.  Block blk covers iter2 rounds of
+// kWaves x 16 window bins; it writes the -ln L partial nllp[blk], the rate
+// pieces to vpart row blk and the nuisance pieces to row hblocks + blk.
+// P and dP are staged in LDS as [s][4][k].
+__global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
                                                const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
                                                const double *__restrict__ F, const double *__restrict__ P,
                                                const double *__restrict__ dP, const double *__restrict__ cnt,
-                                               int iter2, const uint8_t *__restrict__ active,
-                                               double *__restrict__ Gam, double *__restrict__ nllp,
-                                               uint32_t *__restrict__ badp, double *__restrict__ vpart,
+                                               const double *__restrict__ nsum, int iter2,
+                                               const uint8_t *__restrict__ active,
+                                               double *__restrict__ nllp, uint32_t *__restrict__ badp,
+                                               double *__restrict__ binrec, double *__restrict__ bref,
+                                               double *__restrict__ H, double *__restrict__ vpart,
                                                double *__restrict__ mu_out) {
-  extern __shared__ double pd[];  // [S][4][K]: P_sk, dP_sk/d(delta, kappa, eta); lanes on consecutive k read consecutive doubles
-  __shared__ double ared[kWaves][3];
+  extern __shared__ double pd[];  // [S][4][K]: P_sk, dP_sk/d(delta, kappa, eta)
+  __shared__ double red[kWaves][kVLen];
   __shared__ double lds[8];
+  __shared__ double leps[GS_MAX_DATASETS];
   __shared__ uint32_t bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
   const ToyDev &T = toys[t];
   if ((int)blockIdx.x >= T.bin_blocks || !T.two_d || T.mv) return;
   const ShapeDev &Sh = shapes[T.shape];
-  const int S = T.S, K = T.K, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int S = T.S, K = T.K, L = T.L;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
   if (threadIdx.x == 0) bad_s = 0u;
+  if (threadIdx.x < T.D) leps[threadIdx.x] = log(T.exposure[threadIdx.x]);
   for (int e = threadIdx.x; e < S * K; e += blockDim.x) {
     const long long o = T.psd_off + e;
     const int q = e / K, k = e - q * K;
@@ -1894,105 +1917,154 @@ __global__ __launch_bounds__(256) void k_bins2(const int *__restrict__ toy_list,
   }
   __syncthreads();
   const double *th = theta + (size_t)t * stride;
-  double sum = 0.0, A0 = 0.0, A1 = 0.0, A2 = 0.0;
-  uint32_t bad = 0u;
-  const long long n_e = (long long)T.L * K;
-  for (int c = 0; c < iter2; c++) {
-    const long long e = ((long long)blockIdx.x * iter2 + c) * kBlock + threadIdx.x;
-    if (e >= n_e) break;
-    const int b = (int)(e / K), k = (int)(e - (long long)b * K);
-    const double *Fr = F + (T.win_off + b) * S;
-    double M = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
-    for (int q = 0; q < S; q++) {
-      const double rf = th[Sh.sp_of[q]] * Fr[q];
-      const double *cq = pd + (size_t)q * 4 * K + k;
-      M = __fma_rn(rf, cq[0], M);
-      D0 = __fma_rn(rf, cq[K], D0);
-      D1 = __fma_rn(rf, cq[2 * K], D1);
-      D2 = __fma_rn(rf, cq[3 * K], D2);
-    }
-    double gam = 0.0;
-    for (int d = 0; d < T.D; d++) {
-      const double mu = T.exposure[d] * M;
-      const double n = cnt[T.cnt_off + ((long long)d * T.L + b) * K + k];
-      double term, g;
-      bad |= poisson_term(mu, n, term, g);
-      sum += term;
-      gam = __fma_rn(T.exposure[d], g, gam);
-      if (mu_out) mu_out[((long long)d * T.L + b) * K + k] = mu;
-    }
-    Gam[T.gam_off + (long long)b * K + k] = gam;
-    A0 = __fma_rn(D0, gam, A0);
-    A1 = __fma_rn(D1, gam, A1);
-    A2 = __fma_rn(D2, gam, A2);
+  const int QS = (S + 3) >> 2, NT = (K + 15) >> 4;
+  // With mu_d = eps_d M: sum_d (mu_d - n_d ln mu_d) = E M - N ln M - sum_d n_d ln eps_d
+  // and Gam = sum_d eps_d (1 - n_d / mu_d) = E - N / M (E = sum_d eps_d, N = sum_d n_d,
+  // from nsum): one load, one logarithm and one division per cell.  The last sum
+  // does not depend on the parameters: T.cnl holds it over the whole window and
+  // k_finish subtracts it.  Cells with M <= 0, or a quotient n_d / mu_d that may
+  // overflow, take the terms dataset by dataset (poisson_term) and add their own
+  // sum_d n_d ln eps_d back.
+  double E = 0.0, emin = T.exposure[0];
+  for (int d = 0; d < T.D; d++) {
+    E += T.exposure[d];
+    emin = fmin(emin, T.exposure[d]);
   }
+  const double q_max = 1e300 * emin;
+  const long long LK = (long long)L * K;
+  double R[4];  // rates of this lane's B-operand species s = 4q + grp
+#pragma unroll
+  for (int q = 0; q < 4; q++) R[q] = 4 * q + grp < S ? th[Sh.sp_of[4 * q + grp]] : 0.0;
+  const int sa = min(col, S - 1);  // A row (species) of P Gam^T
+  const double *F0 = F + T.fh_off;
+  double *H0 = H + T.fh_off;
+  const double *cn = cnt + T.cnt_off, *ns = nsum + T.nsum_off;
+  double sum = 0.0, A0 = 0.0, A1 = 0.0, A2 = 0.0, a[4] = {0.0, 0.0, 0.0, 0.0};
+  uint32_t bad = 0u;
+  for (int r = 0; r < iter2; r++) {
+    const int j0 = ((blockIdx.x * iter2 + r) * kWaves + wave) * 16;
+    if (j0 >= L) break;  // wave-uniform
+    const int jb = j0 + col;  // this lane's window bin (B column, accumulator column)
+    const bool jin = jb < L;
+    double f[4], rf[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      f[q] = jin && 4 * q + grp < S ? F0[(size_t)jb * S + 4 * q + grp] : 0.0;
+      rf[q] = R[q] * f[q];
+    }
+    dbl4 hT = {0.0, 0.0, 0.0, 0.0};
+    // summed counts of the lane's cells (clamped addresses): tile 0 now, tile nt + 1 during tile nt
+    const double *nr = ns + (size_t)min(jb, L - 1) * K;
+    double Nn[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) Nn[v] = nr[min(grp + 4 * v, K - 1)];
+    for (int nt = 0; nt < NT; nt++) {
+      const int ka = min(16 * nt + col, K - 1);  // A row (pulse-shape bin) of P^T and dP^T
+      double Nc[4];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        Nc[v] = Nn[v];
+        if (nt + 1 < NT) Nn[v] = nr[min(16 * (nt + 1) + grp + 4 * v, K - 1)];
+      }
+      dbl4 Mt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (q < QS) Mt = __builtin_amdgcn_mfma_f64_16x16x4f64(pd[(size_t)min(4 * q + grp, S - 1) * 4 * K + ka], rf[q], Mt, 0, 0, 0);
+      double gam[4];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int k = 16 * nt + grp + 4 * v;
+        double gs = 0.0;
+        if (jin && k < K) {
+          const double M = Mt[v], N = Nc[v];
+          const long long o0 = (long long)jb * K + k;
+          const double q = N / M;
+          if (M > 0.0 && q <= q_max) {
+            sum += E * M - N * log(M);
+            gs = E - q;
+          } else {
+            for (int d = 0; d < T.D; d++) {
+              const double n = cn[o0 + d * LK];
+              double term, g;
+              bad |= poisson_term(T.exposure[d] * M, n, term, g);
+              sum += __fma_rn(n, leps[d], term);
+              gs = __fma_rn(T.exposure[d], g, gs);
+            }
+          }
+          if (mu_out)
+            for (int d = 0; d < T.D; d++) mu_out[o0 + d * LK] = T.exposure[d] * M;
+        }
+        gam[v] = gs;
+      }
+#pragma unroll
+      for (int w = 0; w < 3; w++) {
+        dbl4 Dt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          if (q < QS)
+            Dt = __builtin_amdgcn_mfma_f64_16x16x4f64(pd[((size_t)min(4 * q + grp, S - 1) * 4 + 1 + w) * K + ka], rf[q],
+                                                      Dt, 0, 0, 0);
+        double acc = Dt[0] * gam[0];
+        acc = __fma_rn(Dt[1], gam[1], acc);
+        acc = __fma_rn(Dt[2], gam[2], acc);
+        acc = __fma_rn(Dt[3], gam[3], acc);
+        if (w == 0) A0 += acc;
+        if (w == 1) A1 += acc;
+        if (w == 2) A2 += acc;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+        hT = __builtin_amdgcn_mfma_f64_16x16x4f64(pd[(size_t)sa * 4 * K + min(16 * nt + 4 * c + grp, K - 1)], gam[c], hT,
+                                                  0, 0, 0);
+    }
+    if (jin) {  // hT register v: species grp + 4v of bin jb
+      const double *bn = Sh.bins + (size_t)(T.lo + jb) * kBinLen;
+      const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
+#pragma unroll
+      for (int v = 0; v < 4; v++)
+        if (grp + 4 * v < S) {
+          H0[(size_t)jb * S + grp + 4 * v] = outside ? 0.0 : bn[1] * hT[v];
+          a[v] = __fma_rn(f[v], hT[v], a[v]);
+        }
+      if (grp == 0) {
+        double *br = binrec + (T.win_off + jb) * kBinRecLen;
+        br[0] = bn[0];
+        br[1] = bn[2];
+        br[2] = bn[3];
+        br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
+        br[4] = 0.0;
+        br[5] = 0.0;
+        block_offsets(Sh, T, jb, bn, br[6], br[7], bref);
+      }
+    }
+  }
+  // rate pieces: sum over the 16 bins (lanes col) of each species grp + 4v
+#pragma unroll
+  for (int v = 0; v < 4; v++)
+    for (int o = 1; o < 16; o <<= 1) a[v] += __shfl_xor(a[v], o, 64);
   A0 = wave_sum(A0);
   A1 = wave_sum(A1);
   A2 = wave_sum(A2);
+  if (col == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; v++) red[wave][grp + 4 * v] = a[v];
+  }
   if (lane == 0) {
-    ared[wave][0] = A0;
-    ared[wave][1] = A1;
-    ared[wave][2] = A2;
+    red[wave][GS_MAX_SPECIES] = A0;
+    red[wave][GS_MAX_SPECIES + 1] = A1;
+    red[wave][GS_MAX_SPECIES + 2] = A2;
   }
   if (bad) atomicOr(&bad_s, bad);
-  const double tot = block_sum(sum, lds);  // its barriers also order ared and bad_s
+  const double tot = block_sum(sum, lds);  // its barriers also order red and bad_s
   if (threadIdx.x == 0) {
     nllp[T.nllp_off + blockIdx.x] = tot;
     badp[T.nllp_off + blockIdx.x] = bad_s;
-    double *vp = vpart + (T.vpart_off + T.hblocks + blockIdx.x) * kVLen + GS_MAX_SPECIES;
-    for (int v = 0; v < 3; v++) vp[v] = ared[0][v] + ared[1][v] + ared[2][v] + ared[3][v];
   }
-}
-
-// 2-D adjoint seeds, one thread per (window bin j, species slot s) of a toy,
-// iter2 rounds of kHTile bins per block: h_js = sum_k P_sk Gam_jk, H_js = dx_j h_js, the bin
-// record, and the block partial of the rate-gradient piece sum_j F_js h_js.
-__global__ __launch_bounds__(256) void k_hseed(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
-                                               const ShapeDev *__restrict__ shapes, const double *__restrict__ F,
-                                               const double *__restrict__ P, const double *__restrict__ Gam,
-                                               int iter2, const uint8_t *__restrict__ active,
-                                               double *__restrict__ binrec, double *__restrict__ bref,
-                                               double *__restrict__ H, double *__restrict__ vpart) {
-  extern __shared__ double ps[];  // [S][K]
-  __shared__ double red[kHTile][GS_MAX_SPECIES];
-  const int t = toy_of(toy_list, blockIdx.y);
-  if (active && !active[t]) return;
-  const ToyDev &T = toys[t];
-  if ((int)blockIdx.x >= T.hblocks || !T.two_d || T.mv) return;
-  const ShapeDev &Sh = shapes[T.shape];
-  const int S = T.S, K = T.K;
-  for (int e = threadIdx.x; e < S * K; e += blockDim.x) ps[e] = P[T.psd_off + e];
-  __syncthreads();
-  const int jj = threadIdx.x / GS_MAX_SPECIES, q = threadIdx.x % GS_MAX_SPECIES;
-  double a = 0.0;
-  for (int c = 0; c < iter2; c++) {
-    const int b = (blockIdx.x * iter2 + c) * kHTile + jj;
-    if (!(b < T.L && q < S)) continue;
-    const double *g = Gam + T.gam_off + (long long)b * K;
-    const double *pq = ps + (size_t)q * K;
-    double h = 0.0;
-    for (int k = 0; k < K; k++) h = __fma_rn(pq[k], g[k], h);
-    const double *bn = Sh.bins + (size_t)(T.lo + b) * kBinLen;
-    const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
-    H[(T.win_off + b) * S + q] = outside ? 0.0 : bn[1] * h;
-    a = __fma_rn(F[(T.win_off + b) * S + q], h, a);
-    if (q == 0) {
-      double *br = binrec + (T.win_off + b) * kBinRecLen;
-      br[0] = bn[0];
-      br[1] = bn[2];
-      br[2] = bn[3];
-      br[3] = outside ? 0.0 : 1.0;  // the seed itself is per species (H)
-      br[4] = 0.0;
-      br[5] = 0.0;
-      block_offsets(Sh, T, b, bn, br[6], br[7], bref);
-    }
-  }
-  red[jj][q] = a;
-  __syncthreads();
-  if (threadIdx.x < S) {
-    double v = red[0][threadIdx.x];
-    for (int j = 1; j < kHTile; j++) v += red[j][threadIdx.x];
-    vpart[(T.vpart_off + blockIdx.x) * kVLen + threadIdx.x] = v;
+  const int e = threadIdx.x;
+  if (e < S || (e >= GS_MAX_SPECIES && e < GS_MAX_SPECIES + 3)) {
+    const double s = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    const long long row = T.vpart_off + (e < GS_MAX_SPECIES ? 0 : T.hblocks) + blockIdx.x;
+    vpart[row * kVLen + e] = s;
   }
 }
 
@@ -2000,13 +2072,8 @@ hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out,
                         hipStream_t st) {
   if (v.n2d == 0 || v.max_bin_blocks2 == 0) return hipSuccess;  // no joint 2-D toys (all multivariate)
   hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), sizeof(double) * 4 * v.max_psd_sk, st,
-                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, v.iter2, active, v.Gam, v.nllp,
-                     v.badp, v.vpart, mu_out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hseed, dim3(v.max_hblocks, v.n2d), dim3(kHTile * GS_MAX_SPECIES),
-                     sizeof(double) * v.max_psd_sk, st, v.list2d, v.toys, v.shapes, v.F, v.P, v.Gam, v.iter2, active,
-                     v.binrec, v.bref, v.H, v.vpart);
+                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, v.nsum, v.iter2, active, v.nllp, v.badp,
+                     v.binrec, v.bref, v.H, v.vpart, mu_out);
   return hipGetLastError();
 }
 
@@ -2050,7 +2117,7 @@ __global__ __launch_bounds__(64) void k_mv_slice(const int *__restrict__ toy_lis
   const int j0 = sedge[T.slice_off + i], j1 = sedge[T.slice_off + i + 1];
   double N = 0.0;
   if (lane < S)
-    for (int j = j0; j < j1; j++) N += F[(T.win_off + j) * S + lane];
+    for (int j = j0; j < j1; j++) N += F[fh_at(T, lane, j)];
   const double RN = lane < S ? th[Sh.sp_of[lane]] * N : 0.0;
   double rn[GS_MAX_SPECIES];
 #pragma unroll
@@ -2168,7 +2235,7 @@ __global__ __launch_bounds__(256) void k_mv_bins(const int *__restrict__ toy_lis
   const int b = blk * kHTile + jj;
   double a = 0.0, term_sum = 0.0;
   if (b < T.L) {
-    const double *Fr = F + (T.win_off + b) * S;
+    const double *Fr = F + fh_at(T, 0, b);
     double mu1 = 0.0;
     for (int s = 0; s < S; s++) mu1 = __fma_rn(th[Sh.sp_of[s]], Fr[s], mu1);
     double e = 0.0;
@@ -2192,7 +2259,7 @@ __global__ __launch_bounds__(256) void k_mv_bins(const int *__restrict__ toy_lis
     const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
     if (q < S) {
       const double c = e + sig[T.sig_off + (long long)lo * S + q];
-      H[(T.win_off + b) * S + q] = outside ? 0.0 : bn[1] * c;
+      H[fh_at(T, q, b)] = outside ? 0.0 : bn[1] * c;
       a = Fr[q] * c;
     }
     if (q == 0) {
@@ -2237,7 +2304,7 @@ __global__ __launch_bounds__(256) void k_mv_expect(const int *__restrict__ toy_l
   const double *th = theta + (size_t)t * stride;
   double M = 0.0;
   for (int s = 0; s < T.S; s++)
-    M = __fma_rn(th[Sh.sp_of[s]] * F[(T.win_off + b) * T.S + s], P[T.psd_off + (long long)s * T.K + k], M);
+    M = __fma_rn(th[Sh.sp_of[s]] * F[fh_at(T, s, b)], P[T.psd_off + (long long)s * T.K + k], M);
   for (int d = 0; d < T.D; d++) mu_out[((long long)d * T.L + b) * T.K + k] = T.exposure[d] * M;
 }
 

@@ -526,6 +526,34 @@ def test_mixed_batch_matches_oracle(gs, orc):
         assert _grad_err(grad[t, : m.n_params], og, m.fd_scale) <= GRAD_TOL, (m.name, _grad_err(grad[t, : m.n_params], og, m.fd_scale))
 
 
+def test_batch_of_2d_toys_with_different_species_counts(gs, orc):
+    """Pulse-shape toys with 12 and with 5 species in one batch, the larger first (per-species
+    window rows of consecutive toys collide unless every toy keeps the same row stride): each
+    toy equals its own single-model evaluation, and the small ones the oracle."""
+    import torch
+    small = gsgen.small_gamma_model(n_true=150, n_reco=90, seed=9, n_psd=13, n_datasets=2).replace(win_lo=11, win_hi=77)
+    toys = [gsgen.config2(), small, gsgen.multivariate_model(small, 7),
+            gsgen.small_gamma_model(n_true=120, n_reco=70, seed=3, n_psd=9, n_datasets=1)]
+    batch = gs.Batch(toys)
+    th = np.zeros((len(toys), batch.stride))
+    pts = []
+    for t, m in enumerate(toys):
+        pts.append(gsgen.offset_point(m, 1.0, seed=20 + t))
+        th[t, : m.n_params] = pts[t]
+    nll, grad, st = batch.nll_grad(torch.tensor(th, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    nll, grad, st = nll.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    for t, m in enumerate(toys):
+        v, g, s = gs.Model(m).nll_grad(pts[t])
+        assert st[t] == s == 0, (t, st[t], s)
+        assert abs(nll[t] - v) <= 1e-13 * abs(v), (t, nll[t], v)
+        np.testing.assert_allclose(grad[t, : m.n_params], g, rtol=1e-10, atol=1e-9)
+        if t > 0:
+            ov, og, _ = orc.Oracle(m).nll_grad(pts[t])
+            assert abs(nll[t] - ov) / abs(ov) <= NLL_TOL, (t, nll[t], ov)
+            assert _grad_err(grad[t, : m.n_params], og, m.fd_scale) <= GRAD_TOL, t
+
+
 def test_mixed_batch_fits(gs):
     """Device BFGS over the uneven mix: every toy converges, and sampled toys of every class
     land within 1e-3 sigma of the host BFGS on the same GPU evaluations."""
