@@ -191,7 +191,9 @@ __global__ __launch_bounds__(64) void k_cells(const int *__restrict__ toy_list, 
     double W = 0.0;
     if (i < Sh.n_true) {
       const double *w = Sh.wcellT + i;
-      for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[(size_t)s * Sh.n_true], W);
+#pragma unroll
+      for (int s = 0; s < GS_MAX_SPECIES; s++)
+        if (s < Sh.Sg) W = __fma_rn(th[Sh.sp_of[s]], w[(size_t)s * Sh.n_true], W);
     } else {
       W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
     }
@@ -1316,7 +1318,7 @@ hipError_t launch_adj(const BatchView &v, bool per_species, const uint8_t *activ
 
 // ----------------------------------------------------------- k_cellgrad ---
 template <int CPT>
-__global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
+__global__ __launch_bounds__(256, 4) void k_cellgrad(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys, const ShapeDev *__restrict__ shapes,
                                                   const double *__restrict__ theta, int stride,
                                                   const double *__restrict__ rec, const double *__restrict__ apart,
                                                   const uint8_t *__restrict__ active, double *__restrict__ gpart) {
@@ -1328,9 +1330,12 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
   const ShapeDev &Sh = shapes[T.shape];
   const double *th = theta + (size_t)t * stride;
   const int fam = Sh.family, nr = fam == kGaussE ? 2 : 5;
-  double gR[GS_MAX_SPECIES], gP[5];
+  double gR[GS_MAX_SPECIES], gP[5], R[GS_MAX_SPECIES];  // R: grid species' rates (uniform)
 #pragma unroll
-  for (int s = 0; s < GS_MAX_SPECIES; s++) gR[s] = 0.0;
+  for (int s = 0; s < GS_MAX_SPECIES; s++) {
+    gR[s] = 0.0;
+    R[s] = s < Sh.Sg ? th[Sh.sp_of[s]] : 0.0;
+  }
 #pragma unroll
   for (int p = 0; p < 5; p++) gP[p] = 0.0;
   // CPT * kBlock consecutive cells per block: cells threadIdx.x, + kBlock, ... per thread
@@ -1346,16 +1351,28 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
     }
     Moments mo;
     moments(fam, th + Sh.S, Sh.birks_A, Sh.cellE[i], mo);
-    // the 1-D combined weight W_i = sum_s R_s w_si, recomputed from the shape's weights
-    // (shared by every toy of the shape) rather than read back from the cell record
+    // 1-D toys: the combined weight W_i = sum_s R_s w_si, recomputed from the shape's
+    // weights (shared by every toy of the shape) rather than read back from the cell
+    // record, and in the same walk the rate gradients sum_i w_si A0_i; a line cell
+    // weighs its own species alone
     double W = 1.0;
     if (!T.two_d) {
       if (i < Sh.n_true) {
         const double *w = Sh.wcellT + i;
         W = 0.0;
-        for (int s = 0; s < Sh.Sg; s++) W = __fma_rn(th[Sh.sp_of[s]], w[(size_t)s * Sh.n_true], W);
+#pragma unroll
+        for (int s = 0; s < GS_MAX_SPECIES; s++)
+          if (s < Sh.Sg) {
+            const double ws = w[(size_t)s * Sh.n_true];
+            W = __fma_rn(R[s], ws, W);
+            gR[s] = __fma_rn(ws, A0, gR[s]);
+          }
       } else {
-        W = th[Sh.sp_of[Sh.Sg + (i - Sh.n_true)]];
+        const int q = Sh.Sg + (i - Sh.n_true);
+        W = th[Sh.sp_of[q]];
+#pragma unroll
+        for (int s = 0; s < GS_MAX_SPECIES; s++)
+          if (s == q) gR[s] += A0;
       }
     }
     double dNdm, dNds;
@@ -1378,19 +1395,7 @@ __global__ __launch_bounds__(256) void k_cellgrad(const int *__restrict__ toy_li
     }
 #pragma unroll
     for (int p = 0; p < 5; p++) gP[p] = __fma_rn(dNdm, mo.dm[p], __fma_rn(dNds, mo.ds[p], gP[p]));
-    if (T.two_d) {
-      // rate gradients of 2-D models come from the pulse-shape contraction (k_hseed)
-    } else if (i < Sh.n_true) {
-      const double *w = Sh.wcellT + i;
-#pragma unroll
-      for (int s = 0; s < GS_MAX_SPECIES; s++)
-        if (s < Sh.Sg) gR[s] = __fma_rn(w[(size_t)s * Sh.n_true], A0, gR[s]);
-    } else {
-      const int q = Sh.Sg + (i - Sh.n_true);
-#pragma unroll
-      for (int s = 0; s < GS_MAX_SPECIES; s++)
-        if (s == q) gR[s] += A0;
-    }
+    // (rate gradients of 2-D models come from the pulse-shape contraction, k_bins2)
   }
   // every entry summed over the wave, then over the block's waves in a fixed order
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
