@@ -81,4 +81,66 @@ GS_HD inline double exp_cw(double x, const double *c, double c0, double mg) {
 
 GS_HD inline double exp_cw(double x, const double *c) { return exp_cw(x, c, c[0], c[GS_EXP_SHIFT]); }
 
+// Table-driven variant, used by the pair loops: x = n ln2/64 + r with n =
+// 64 e + j (0 <= j < 64) rounded as above and |r| <= ln2/128, so
+// exp(x) = 2^e 2^(j/64) q(r).  q is the degree-4 polynomial that minimises
+// the relative error of exp(r) on [-ln2/128, ln2/128] (remez_exp.py 4 64:
+// 2.44e-15 after its coefficients are rounded; its constant term rounds to
+// 1), and the table holds 2^(j/64) rounded to double (remez_exp.py prints it
+// from 80-digit values).  ln2/64 is rounded to double (error 3.6e-19), so
+// the relative error is below 2.9e-15 + |n| 3.7e-19: 5e-15 for arguments
+// above -60 (exp_cw: 1.7e-14), in four FP64 operations fewer than exp_cw.
+// The table index is the low six bits of n, so every argument, NaN
+// included, reads inside the table.  Arguments below -1000 are raised to
+// -1000 as for exp_cw (a NaN argument gives 0).
+#define GS_EXPT_COEFS                                                                                   \
+  { 0.041666615756061516, 0.1666669721299421, 0.5000000000026126, 0.9999999999977606,                 \
+    92.33248261689366, 0.010830424696249145, 6755399441055744.0 }
+#define GS_EXPT_NCOEF 7
+#define GS_EXPT_INV (4)    // 64 / ln2
+#define GS_EXPT_LN2 (5)    // ln2 / 64
+#define GS_EXPT_SHIFT (6)  // 1.5 * 2^52
+#define GS_EXPT_TABLE                                                                                   \
+  {                                                                                                     \
+        1.0, 1.0108892860517005, 1.0218971486541166, 1.0330248790212284,                          \
+        1.0442737824274138, 1.0556451783605572, 1.0671404006768237, 1.0787607977571199,           \
+        1.0905077326652577, 1.102382583307841, 1.1143867425958924, 1.1265216186082418,            \
+        1.1387886347566916, 1.1511892299529827, 1.1637248587775775, 1.1763969916502812,           \
+        1.189207115002721, 1.202156731452703, 1.215247359980469, 1.22848053610687,                \
+        1.241857812073484, 1.255380757024691, 1.2690509571917332, 1.2828700160787783,             \
+        1.2968395546510096, 1.3109612115247644, 1.3252366431597413, 1.339667524053303,            \
+        1.3542555469368927, 1.3690024229745905, 1.383909881963832, 1.3989796725383112,            \
+        1.4142135623730951, 1.42961333839197, 1.4451808069770467, 1.460917794180647,              \
+        1.4768261459394993, 1.4929077282912648, 1.5091644275934228, 1.5255981507445384,           \
+        1.5422108254079407, 1.559004400237837, 1.5759808451078865, 1.593142151342267,             \
+        1.6104903319492543, 1.6280274218573478, 1.645755478153965, 1.6636765803267364,            \
+        1.681792830507429, 1.7001063537185235, 1.718619298122478, 1.7373338352737062,             \
+        1.7562521603732995, 1.7753764925265212, 1.7947090750031072, 1.8142521755003989,           \
+        1.8340080864093424, 1.8539791250833855, 1.8741676341103, 1.8945759815869656,              \
+        1.9152065613971474, 1.9360617934922943, 1.9571441241754002, 1.978456026387951             \
+  }
+
+// Arguments at or above kExpTbNoClampMin may skip the lower clamp: there n
+// is below 2^31 in magnitude (64 |x| / ln2 < 2^31) and the result already
+// underflows to 0 below about -745.
+constexpr double kExpTbNoClampMin = -1.0e7;
+
+// c: the coefficients (c[0] = the degree-4 one, meeting another scalar operand,
+// is passed again as c4), tb: the table, mg = c[GS_EXPT_SHIFT].
+GS_HD inline double exp_tb_unclamped(double x, const double *c, double c4, const double *tb, double mg) {
+  const double t = fma(x, c[GS_EXPT_INV], mg);
+  const double n = t - mg;
+  const double r = fma(-n, c[GS_EXPT_LN2], x);
+  double q = fma(c4, r, c[1]);
+  q = fma(q, r, c[2]);
+  q = fma(q, r, c[3]);
+  q = fma(q, r, 1.0);
+  const int ni = (int)(unsigned)__builtin_bit_cast(unsigned long long, t);
+  return ldexp(q * tb[ni & 63], ni >> 6);
+}
+
+GS_HD inline double exp_tb(double x, const double *c, double c4, const double *tb, double mg) {
+  return exp_tb_unclamped(fmax(x, -1000.0), c, c4, tb, mg);
+}
+
 }  // namespace gs

@@ -29,38 +29,44 @@
 
 namespace gs {
 
-// Coefficients of exp_cw; read through scalar loads so they live in SGPRs.
-__constant__ double kExpC[GS_EXP_NCOEF] = GS_EXP_COEFS;
+// Coefficients of exp_tb, read through scalar loads so they live in SGPRs,
+// and its table of 2^(j/64), which every pair kernel copies into LDS.
+__constant__ double kExpC[GS_EXPT_NCOEF] = GS_EXPT_COEFS;
+__constant__ double kExpTable[64] = GS_EXPT_TABLE;
 
-// exp_cw's coefficients as the pair loops use them: the table (scalar
-// registers) plus the two constants that meet another scalar operand, copied
-// once per thread into vector registers (the empty asm hides the copy from
-// the optimiser, which would otherwise rematerialise it inside the loop).
+// exp_tb's constants as the pair loops use them: the coefficients (scalar
+// registers) plus the two that meet another scalar operand, copied once per
+// thread into vector registers (the empty asm hides the copy from the
+// optimiser, which would otherwise rematerialise it inside the loop), and the
+// table in LDS.  exp_consts fills the table: every thread of the workgroup
+// calls it first, before any return.
 struct ExpK {
-  const double *c;
-  double c0, mg;
+  const double *c, *tb;
+  double c4, mg;
 };
-__device__ __forceinline__ ExpK exp_consts() {
-  ExpK e{kExpC, kExpC[0], kExpC[GS_EXP_SHIFT]};
-  asm volatile("" : "+v"(e.c0));
+__device__ __forceinline__ ExpK exp_consts(double *stb) {
+  if (threadIdx.x < 64) stb[threadIdx.x] = kExpTable[threadIdx.x];
+  __syncthreads();
+  ExpK e{kExpC, stb, kExpC[0], kExpC[GS_EXPT_SHIFT]};
+  asm volatile("" : "+v"(e.c4));
   asm volatile("" : "+v"(e.mg));
   return e;
 }
-__device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_cw(x, e.c, e.c0, e.mg); }
-// CLAMP = false: every argument is known to be finite and >= kExpNoClampMin.
+__device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_tb(x, e.c, e.c4, e.tb, e.mg); }
+// CLAMP = false: every argument is known to be finite and >= kExpTbNoClampMin.
 template <bool CLAMP>
 __device__ __forceinline__ double dexp(double x, const ExpK &e) {
-  return CLAMP ? exp_cw(x, e.c, e.c0, e.mg) : exp_cw_unclamped(x, e.c, e.c0, e.mg);
+  return CLAMP ? exp_tb(x, e.c, e.c4, e.tb, e.mg) : exp_tb_unclamped(x, e.c, e.c4, e.tb, e.mg);
 }
 
 // Whether a pair exponent E = Eref + A u + B v stays finite and at or above
-// kExpNoClampMin over bins whose offsets run from (uf, vf) to (ul, vl) in
+// kExpTbNoClampMin over bins whose offsets run from (uf, vf) to (ul, vl) in
 // increasing x.  E is concave in x or monotone on the bins in between (gamma
 // with k >= 1: (k-1) ln x - x/th; k < 1: decreasing; Gaussian families: a
 // downward parabola), so its minimum over them is at one of the two ends.
 __device__ __forceinline__ bool exp_args_bounded(double A, double B, double Eref, double uf, double vf, double ul,
                                                  double vl) {
-  return rel_exponent(A, B, Eref, uf, vf) >= kExpNoClampMin && rel_exponent(A, B, Eref, ul, vl) >= kExpNoClampMin;
+  return rel_exponent(A, B, Eref, uf, vf) >= kExpTbNoClampMin && rel_exponent(A, B, Eref, ul, vl) >= kExpTbNoClampMin;
 }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -329,7 +335,7 @@ __device__ __forceinline__ void fold_batch(const double *srec, int nb, int wave,
 
 // The staged batch's pairs, through the unclamped exponential unless a cell
 // staged into this workgroup so far may reach an exponent below
-// kExpNoClampMin on the tile (the LDS flag set by stage_store, read after the
+// kExpTbNoClampMin on the tile (the LDS flag set by stage_store, read after the
 // barrier that follows staging, so the branch is uniform).
 __device__ __forceinline__ void fold_batch_any(const double *srec, int nb, int wave, const Off2 &o, const ExpK &ec,
                                                const int *sclamp, double &a0, double &a1) {
@@ -363,7 +369,7 @@ __device__ __forceinline__ double read_lane(double x, int l) {
 }
 
 // Staged cell c = {A, B, Eref, W} about the tile's reference point.  Sets
-// *sclamp when the cell's exponent may leave [kExpNoClampMin, inf) on the
+// *sclamp when the cell's exponent may leave [kExpTbNoClampMin, inf) on the
 // tile.
 template <int FAM>
 __device__ __forceinline__ void stage_store(double *srec, int c, const double2 (&f)[3], const TileRef &ref,
@@ -457,7 +463,8 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
   __shared__ int sclamp;
-  const ExpK ec = exp_consts();
+  __shared__ double s_exp[64];
+  const ExpK ec = exp_consts(s_exp);
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
   const FoldItem it = items[w_item];
@@ -606,7 +613,7 @@ __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__
       o[0] = q.A;
       o[1] = q.Eref;
       o[2] = q.B;
-      // a staged cell whose exponent may leave [kExpNoClampMin, inf) on its half-tile
+      // a staged cell whose exponent may leave [kExpTbNoClampMin, inf) on its half-tile
       if (cell >= 0 && !exp_args_bounded(q.A, q.B, q.Eref, te.uf, te.vf, te.ul, te.vl)) *sclamp = 1;
     }
 #pragma unroll
@@ -628,7 +635,8 @@ __global__ __launch_bounds__(256, 6) void k_fold_s(const FoldItem *__restrict__ 
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
   __shared__ int sclamp;
-  const ExpK ec = exp_consts();
+  __shared__ double s_exp[64];
+  const ExpK ec = exp_consts(s_exp);
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
   const FoldItem it = items[w_item];
@@ -963,7 +971,7 @@ __device__ __forceinline__ void adj_block(const double *__restrict__ BR, int b, 
   }
 }
 
-// Whether any lane's gamma exponent may leave [kExpNoClampMin, inf) on the
+// Whether any lane's gamma exponent may leave [kExpTbNoClampMin, inf) on the
 // bins [lo, hi) of a block (wave-uniform): checked at the two end bins.  A
 // block starting at x <= 0 always needs the clamp: offsets there stand in for
 // ln x = 0, so the exponent at that end is not the concave function.
@@ -1032,7 +1040,8 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
                                              double *__restrict__ apart) {
   __shared__ double red[NW * kTile * 3];
   __shared__ double sref[NW > 1 ? kRefBlocks : 1][kTile];
-  const ExpK ec = exp_consts();
+  __shared__ double s_exp[64];
+  const ExpK ec = exp_consts(s_exp);
   const int lane = threadIdx.x & 63;
   const int w_item = NW > 1 ? xcd_item(blockIdx.x, n_items)
                             : xcd_item(blockIdx.x, (n_items + kAdjGroupWaves - 1) / kAdjGroupWaves) * kAdjGroupWaves +
@@ -1167,7 +1176,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict
                                                        const double *__restrict__ bref, const double *__restrict__ H,
                                                        const uint8_t *__restrict__ active,
                                                        double *__restrict__ apart) {
-  const ExpK ec = exp_consts();
+  __shared__ double s_exp[64];
+  const ExpK ec = exp_consts(s_exp);
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
   const AdjItem it = items[w_item];

@@ -1,10 +1,12 @@
 """Coefficients of the polynomial p of degree n that minimises the relative
-error max |p(r) / e^r - 1| on [-ln2/2, ln2/2], by the Remez exchange
+error max |p(r) / e^r - 1| on [-ln2/(2N), ln2/(2N)], by the Remez exchange
 algorithm (equioscillation at n + 2 points), in 80-digit arithmetic; used for
-the exponentials in gs_exp.h.  Prints the coefficients (highest degree first)
-and the relative error before and after rounding them to double.
+the exponentials in gs_exp.h (N = 1: the plain reduction; N = 64: the
+table-driven one).  Prints the coefficients (highest degree first) and the
+relative error before and after rounding them to double.
 
-    python remez_exp.py 10
+    python remez_exp.py 9        # degree 9 on [-ln2/2, ln2/2]
+    python remez_exp.py 5 64     # degree 5 on [-ln2/128, ln2/128]
 """
 import sys
 
@@ -59,7 +61,8 @@ def remez(n, a, iters=40):
 
 def main():
     n = int(sys.argv[1]) if len(sys.argv) > 1 else 10
-    a = mp.log(2) / 2
+    N = int(sys.argv[2]) if len(sys.argv) > 2 else 1
+    a = mp.log(2) / (2 * N)
     coef, e = remez(n, a)
     cd = [float(c) for c in coef]
     ed = max(abs((mp.polyval([mp.mpf(c) for c in cd[::-1]], x) - mp.e ** x) / mp.e ** x)
@@ -67,6 +70,9 @@ def main():
     print("degree", n, "minimax relative error", mp.nstr(e, 3), "after rounding to double", mp.nstr(ed, 3))
     for c in cd[::-1]:
         print(repr(c))
+    if N > 1:  # the reduction constants and the table 2^(j/N), rounded to double
+        print("N/ln2", repr(float(N / mp.log(2))), "ln2/N", repr(float(mp.log(2) / N)))
+        print("table", ", ".join(repr(float(mp.power(2, mp.mpf(j) / N))) for j in range(N)))
 
 
 if __name__ == "__main__":
