@@ -224,6 +224,11 @@ struct gs_batch {
   std::vector<double> trace_ms;   // and the host time since the call started
   hipStream_t fit_stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // batches with both 1-D and 2-D toys: the 2-D chain runs on a stream of its
+  // own, forked from the caller's stream after the cell records and joined
+  // before the gradient chain (default priority, as every stream here)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t graph = nullptr;
   int graph_k = 0, graph_max_iter = -1;
   double graph_tol = -1.0;
@@ -240,6 +245,9 @@ struct gs_batch {
   ~gs_batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (fit_stream) (void)hipStreamDestroy(fit_stream);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (h_count) (void)hipHostFree(h_count);
@@ -827,6 +835,11 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     v.n_tgroup = (int)grp.size() / 2;
   }
   HIP_TRY(hipMemcpy(cnt, cnt_h.data(), cnt_h.size() * 8, hipMemcpyHostToDevice));
+  if (v.has_1d && v.has_2d) {
+    HIP_TRY(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
+  }
   if (!nsum_h.empty()) {
     double *ns;
     HIP_TRY(B->alloc(&ns, nsum_h.size()));
@@ -860,6 +873,10 @@ hipError_t timed(gs_batch *B, int kernel, hipStream_t st, F f) {
 // One adjoint-path evaluation of every toy: cells, fold, -ln L, adjoint,
 // gradient.  One-dimensional toys fold with the combined weight; toys with a
 // secondary observable fold per species and expand over the pulse-shape bins.
+// The two chains write disjoint parts of every buffer (each toy its own), so
+// in a batch that has both the 2-D chain runs on the side stream alongside
+// the 1-D one: the per-species kernels lean on the matrix cores, the 1-D ones
+// on the vector units.  Kernel timing keeps them in one stream.
 // view: the batch's own (every toy) or a compacted copy of it.
 gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, double *d_grad, uint32_t *d_status,
                            double *d_mu, hipStream_t st, const uint8_t *active = nullptr,
@@ -869,23 +886,31 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
   B->v.theta_dev = d_theta;
   if (v.has_1d || v.has_2d) HIP_TRY(timed(B, GS_K_CELLS, st, [&] { return launch_cells(v, d_theta, active, st); }));
   if (v.has_tmpl) HIP_TRY(timed(B, GS_K_TMPL, st, [&] { return launch_tmpl(v, d_theta, d_mu, active, st); }));
+  const bool fork = B->side && !B->prof && v.has_1d && v.has_2d;
+  hipStream_t s2 = fork ? B->side : st;  // the 2-D chain's stream
+  if (fork) {
+    HIP_TRY(hipEventRecord(B->ev_fork, st));
+    HIP_TRY(hipStreamWaitEvent(s2, B->ev_fork, 0));
+  }
+  if (v.has_2d) {
+    HIP_TRY(timed(B, GS_K_FOLDS, s2, [&] { return launch_fold(v, true, kOnly2D, active, s2); }));
+    HIP_TRY(timed(B, GS_K_REDF, s2, [&] { return launch_reduceF(v, kOnly2D, active, s2); }));
+    HIP_TRY(launch_psd(v, d_theta, active, s2));
+    HIP_TRY(timed(B, GS_K_NLL, s2, [&] { return launch_bins2(v, d_theta, d_mu, active, s2); }));
+    if (v.has_mv) HIP_TRY(timed(B, GS_K_NLL, s2, [&] { return launch_mv(v, d_theta, d_mu, active, s2); }));
+    if (d_grad) HIP_TRY(timed(B, GS_K_ADJS, s2, [&] { return launch_adj(v, true, active, s2); }));
+  }
   if (v.has_1d) {
     HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold(v, false, kOnly1D, active, st); }));
     HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins1(v, d_mu, active, st); }));
+    if (d_grad) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
   }
-  if (v.has_2d) {
-    HIP_TRY(timed(B, GS_K_FOLDS, st, [&] { return launch_fold(v, true, kOnly2D, active, st); }));
-    HIP_TRY(timed(B, GS_K_REDF, st, [&] { return launch_reduceF(v, kOnly2D, active, st); }));
-    HIP_TRY(launch_psd(v, d_theta, active, st));
-    HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins2(v, d_theta, d_mu, active, st); }));
-    if (v.has_mv) HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_mv(v, d_theta, d_mu, active, st); }));
+  if (fork) {
+    HIP_TRY(hipEventRecord(B->ev_join, s2));
+    HIP_TRY(hipStreamWaitEvent(st, B->ev_join, 0));
   }
-  if (d_grad) {
-    if (v.has_1d) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
-    if (v.has_2d) HIP_TRY(timed(B, GS_K_ADJS, st, [&] { return launch_adj(v, true, active, st); }));
-    if (v.has_1d || v.has_2d)
-      HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_cellgrad(v, d_theta, active, st); }));
-  }
+  if (d_grad && (v.has_1d || v.has_2d))
+    HIP_TRY(timed(B, GS_K_GRAD, st, [&] { return launch_cellgrad(v, d_theta, active, st); }));
   HIP_TRY(timed(B, GS_K_FINISH, st,
                 [&] { return launch_finish(v, d_theta, d_nll, d_grad, d_status, active, st); }));
   return GS_OK;
