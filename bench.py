@@ -40,18 +40,24 @@ FP64_PEAK_TFLOPS = 78.6
 # adjoint.
 ALGO_FLOPS_PER_PAIR = 26.5
 # The same, counted from the kernels' own gfx950 instruction mix with an FMA as 2 (fold: tile-
-# relative exponent 2 FMA, exponential 11 FMA + MAX + SUB + LDEXP, accumulation 1 FMA; adjoint:
-# 3 accumulating FMAs): context only.
-INSTR_FLOPS_PER_PAIR = {"fold": 31, "adj": 35}
-KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj", "folds": "k_fold_s", "adj_s": "k_adj_s"}
+# relative exponent 2 FMA, table-driven exponential 6 FMA + SUB + MUL + LDEXP, accumulation
+# 1 FMA; adjoint: 3 accumulating FMAs; the clamped tiles add a MAX): context only.
+INSTR_FLOPS_PER_PAIR = {"fold": 21, "adj": 25}
+KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj<1>", "folds": "k_fold_s", "adj_s": "k_adj_s"}
+
+
+def kernel_names(adj_waves):
+    """The pair kernels' names; the 1-D adjoint is the template the batch's layout runs."""
+    return dict(KERNEL_NAMES, adj=f"k_adj<{adj_waves}>")
 # HBM bytes per launch of the pair kernels on the 16384-toy mixed batch (the headline step, in
 # the layout the autotuner keeps), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE;
 # KiB per dispatch) scaled by what the same counters read for a plain 512 MiB device copy
 # (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the kernel sources they were
 # taken on: any change to those sources reports traffic as null.
-TRAFFIC = {"sources_sha256": "163044cb883f66111d85c66296f0ca3894f608788318f8fda94e828c1dd72ef8",
-           "workload": "mix16384", "kernels": {"k_fold1": 1361157385, "k_adj": 2412476819,
-                                                "k_fold_s": 603964275, "k_adj_s": 800103595}}
+TRAFFIC = {"sources_sha256": "3a0dfd29c992a41480ddac38b0dfaf97e7020d73e37c023bfd4841f5fcd8946d",
+           "workload": "mix16384", "kernels": {"k_fold1": 1184102638, "k_adj<1>": 2424374767,
+                                                "k_adj<4>": 2360040756, "k_fold_s": 601102754,
+                                                "k_adj_s": 799916383}}
 
 
 def strip_c_comments(text):
@@ -126,7 +132,7 @@ def host_info():
     return info
 
 
-def kernel_rooflines(kt, counts):
+def kernel_rooflines(kt, counts, adj_waves=1):
     """Achieved TFLOP/s and fraction of the FP64 vector peak of the pair kernels, from their
     average launch time (HIP events) and the algorithmic work of one launch: banded pairs x
     26.5 (+ 2 per species of the pair's cell for the per-species kernels)."""
@@ -142,7 +148,7 @@ def kernel_rooflines(kt, counts):
             continue
         avg = ms / n
         tf = flops / (avg * 1e-3) / 1e12
-        out[k] = {"kernel": KERNEL_NAMES[k], "avg_launch_ms": round(avg, 4), "pairs_per_launch": pairs,
+        out[k] = {"kernel": kernel_names(adj_waves)[k], "avg_launch_ms": round(avg, 4), "pairs_per_launch": pairs,
                   "flops_per_launch": flops, "achieved_tflops": round(tf, 3),
                   "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
     return out
@@ -256,7 +262,7 @@ def mixed_batch(gs, gsgen, torch, args):
     el = timed_steps(batch, theta, nll, grad, st, args.steps, args.warmup, torch)
     kt = profiled_kernels(batch, theta, nll, grad, st, max(2, args.steps // 4), torch)
     counts = batch.mesh_counts()
-    roof = kernel_rooflines(kt, counts)
+    roof = kernel_rooflines(kt, counts, batch.layout()["adj_waves"])
     out = {"toys": len(toys), "classes": {c: classes.count(c) for c in sorted(set(classes))},
            "evals_per_s": len(toys) * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
            "generator_s": round(gen_s, 1), "status_nonzero": int((st != 0).sum().item()), "autotune": tune,
@@ -294,7 +300,7 @@ def mixed_batch(gs, gsgen, torch, args):
                         "ms_per_step": round(el_c * 1e3 / args.steps, 3),
                         "status_nonzero": int((s_c != 0).sum().item()),
                         "kernel_ms": {k: round(v[0] / v[1], 4) for k, v in kt_c.items() if v[1]},
-                        "kernels": kernel_rooflines(kt_c, b_c.mesh_counts())}
+                        "kernels": kernel_rooflines(kt_c, b_c.mesh_counts(), b_c.layout()["adj_waves"])}
         del b_c
     out["per_class"] = per_class
     return out, toys, classes, gpu_nll, gpu_grad
@@ -311,7 +317,7 @@ def toy_study(gs, gsgen, torch, args):
     el = timed_steps(batch, theta, nll, grad, st, args.steps, args.warmup, torch)
     kt = profiled_kernels(batch, theta, nll, grad, st, args.steps, torch)
     counts = batch.mesh_counts()
-    roof = kernel_rooflines(kt, counts)
+    roof = kernel_rooflines(kt, counts, batch.layout()["adj_waves"])
     for k in ("fold", "adj"):
         if k in roof:
             roof[k]["instr_flops_per_pair"] = INSTR_FLOPS_PER_PAIR[k]
@@ -370,7 +376,7 @@ def single_model(gs, torch, m, reps=200, fits=True):
     kt = profiled_kernels(b, th, n1, g1, s1, 20, torch)
     out = {"us_per_eval": round(el * 1e6 / reps, 2), "evals_per_s": round(reps / el, 1),
            "kernel_us": {k: round(v[0] * 1e3 / v[1], 2) for k, v in kt.items() if v[1]},
-           "kernels": kernel_rooflines(kt, b.mesh_counts())}
+           "kernels": kernel_rooflines(kt, b.mesh_counts(), b.layout()["adj_waves"])}
     del b
     if fits:
         model = gs.Model(m)
