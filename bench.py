@@ -40,9 +40,9 @@ FP64_PEAK_TFLOPS = 78.6
 # adjoint.
 ALGO_FLOPS_PER_PAIR = 26.5
 # The same, counted from the kernels' own gfx950 instruction mix with an FMA as 2 (fold: tile-
-# relative exponent 2 FMA, table-driven exponential 6 FMA + SUB + MUL + LDEXP, accumulation
+# relative exponent 2 FMA, table-driven exponential 5 FMA + SUB + MUL + LDEXP, accumulation
 # 1 FMA; adjoint: 3 accumulating FMAs; the clamped tiles add a MAX): context only.
-INSTR_FLOPS_PER_PAIR = {"fold": 21, "adj": 25}
+INSTR_FLOPS_PER_PAIR = {"fold": 19, "adj": 23}
 KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj<1>", "folds": "k_fold_s", "adj_s": "k_adj_s"}
 
 

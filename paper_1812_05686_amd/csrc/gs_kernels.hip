@@ -30,9 +30,9 @@
 namespace gs {
 
 // Coefficients of exp_tb, read through scalar loads so they live in SGPRs,
-// and its table of 2^(j/64), which every pair kernel copies into LDS.
+// and its table of 2^(j/256), which every pair kernel copies into LDS.
 __constant__ double kExpC[GS_EXPT_NCOEF] = GS_EXPT_COEFS;
-__constant__ double kExpTable[64] = GS_EXPT_TABLE;
+__constant__ double kExpTable[GS_EXPT_N] = GS_EXPT_TABLE;
 
 // exp_tb's constants as the pair loops use them: the coefficients (scalar
 // registers) plus the two that meet another scalar operand, copied once per
@@ -42,21 +42,21 @@ __constant__ double kExpTable[64] = GS_EXPT_TABLE;
 // calls it first, before any return.
 struct ExpK {
   const double *c, *tb;
-  double c4, mg;
+  double c3, mg;
 };
 __device__ __forceinline__ ExpK exp_consts(double *stb) {
-  if (threadIdx.x < 64) stb[threadIdx.x] = kExpTable[threadIdx.x];
+  for (int i = threadIdx.x; i < GS_EXPT_N; i += blockDim.x) stb[i] = kExpTable[i];
   __syncthreads();
   ExpK e{kExpC, stb, kExpC[0], kExpC[GS_EXPT_SHIFT]};
-  asm volatile("" : "+v"(e.c4));
+  asm volatile("" : "+v"(e.c3));
   asm volatile("" : "+v"(e.mg));
   return e;
 }
-__device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_tb(x, e.c, e.c4, e.tb, e.mg); }
+__device__ __forceinline__ double dexp(double x, const ExpK &e) { return exp_tb(x, e.c, e.c3, e.tb, e.mg); }
 // CLAMP = false: every argument is known to be finite and >= kExpTbNoClampMin.
 template <bool CLAMP>
 __device__ __forceinline__ double dexp(double x, const ExpK &e) {
-  return CLAMP ? exp_tb(x, e.c, e.c4, e.tb, e.mg) : exp_tb_unclamped(x, e.c, e.c4, e.tb, e.mg);
+  return CLAMP ? exp_tb(x, e.c, e.c3, e.tb, e.mg) : exp_tb_unclamped(x, e.c, e.c3, e.tb, e.mg);
 }
 
 // Whether a pair exponent E = Eref + A u + B v stays finite and at or above
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
   __shared__ int sclamp;
-  __shared__ double s_exp[64];
+  __shared__ double s_exp[GS_EXPT_N];
   const ExpK ec = exp_consts(s_exp);
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(256, 6) void k_fold_s(const FoldItem *__restrict__ 
   __shared__ int glist[kWaves * 64];
   __shared__ int gcnt[kWaves];
   __shared__ int sclamp;
-  __shared__ double s_exp[64];
+  __shared__ double s_exp[GS_EXPT_N];
   const ExpK ec = exp_consts(s_exp);
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
                                              double *__restrict__ apart) {
   __shared__ double red[NW * kTile * 3];
   __shared__ double sref[NW > 1 ? kRefBlocks : 1][kTile];
-  __shared__ double s_exp[64];
+  __shared__ double s_exp[GS_EXPT_N];
   const ExpK ec = exp_consts(s_exp);
   const int lane = threadIdx.x & 63;
   const int w_item = NW > 1 ? xcd_item(blockIdx.x, n_items)
@@ -1176,7 +1176,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_adj_s(const AdjItem *__restrict
                                                        const double *__restrict__ bref, const double *__restrict__ H,
                                                        const uint8_t *__restrict__ active,
                                                        double *__restrict__ apart) {
-  __shared__ double s_exp[64];
+  __shared__ double s_exp[GS_EXPT_N];
   const ExpK ec = exp_consts(s_exp);
   const int w_item = xcd_item(blockIdx.x, n_items);
   if (w_item >= n_items) return;
