@@ -634,13 +634,16 @@ def asimov(model: Model, mu: np.ndarray) -> Model:
 
 
 def small_gamma_model(n_true=300, n_reco=64, seed=7, n_psd=0, n_datasets=1, family=GAMMA_PE, shape=0.0,
-                      exact_bins=0) -> Model:
+                      exact_bins=0, wide=False) -> Model:
     """A small photoelectron-family model (lines, betas, exponentials) that the oracle
-    evaluates in milliseconds; used for oracle pins and ragged GPU parity cases."""
+    evaluates in milliseconds; used for oracle pins and ragged GPU parity cases.  wide: the
+    16 species of the mixed batch's pool (4 lines, 8 betas, 4 exponentials) instead of 5."""
     e_step = 3.0 / n_true
-    spectra, le, rates, names, _ = _c1_shape(n_true=n_true, e_step=e_step, family=family,
-                                             lines=[(0.862, 1e4), (1.46, 5e3)],
-                                             betas=[(0.76, 5e4), (1.88, 3e4)], exps=[(0.6, 1e4)])
+    if wide:
+        pools = dict(lines=C4_B_LINES, betas=C4_B_BETAS, exps=C4_B_EXPS)
+    else:
+        pools = dict(lines=[(0.862, 1e4), (1.46, 5e3)], betas=[(0.76, 5e4), (1.88, 3e4)], exps=[(0.6, 1e4)])
+    spectra, le, rates, names, _ = _c1_shape(n_true=n_true, e_step=e_step, family=family, **pools)
     edges = np.linspace(0.0, 1440.0, n_reco + 1)
     S = len(rates)
     theta = np.concatenate([rates, C1_RESP])

@@ -40,6 +40,10 @@ def _cases():
     yield "c2", lambda: gsgen.config2()
     yield "small2d_ragged", lambda: gsgen.small_gamma_model(n_true=150, n_reco=90, seed=9, n_psd=13,
                                                             n_datasets=2).replace(win_lo=11, win_hi=77)
+    # 16 species (the largest count; 4 species per matrix-core step, four steps) on 20 pulse-shape
+    # bins (two 16-bin tiles, the second ragged), two datasets, ragged window
+    yield "small2d_16_species", lambda: gsgen.small_gamma_model(n_true=160, n_reco=96, seed=21, n_psd=20,
+                                                                n_datasets=2, wide=True).replace(win_lo=5, win_hi=83)
 
 
 CASES = dict(_cases())
