@@ -436,9 +436,10 @@ static LayoutSizes layout(gs_batch *B, const Knobs &k) {
     T.fold_chunks = (sh.n_cell + cpc - 1) / cpc;
     const int bpc = std::max(64, (T.L + nch_a - 1) / nch_a);
     T.adj_chunks = (T.L + bpc - 1) / bpc;
-    // 2-D: k_bins2 blocks of iter2 rounds of kWaves x 16 window bins; each writes a row of
-    // rate pieces (the first hblocks rows) and a row of nuisance pieces (the next bin_blocks)
-    const int c2 = kWaves * 16 * k.iter2;
+    // 2-D: k_bins2 blocks of iter2 rounds of kWaves x 16 window bins (one round: 16 bins, the
+    // waves splitting the pulse-shape tiles); each writes a row of rate pieces (the first
+    // hblocks rows) and a row of nuisance pieces (the next bin_blocks)
+    const int c2 = k.iter2 == 1 ? 16 : kWaves * 16 * k.iter2;
     T.bin_blocks = T.two_d  ? (T.L + c2 - 1) / c2
                    : T.tmpl ? (T.L + v.tmpl_bins - 1) / v.tmpl_bins
                             : (T.L + kBlock - 1) / kBlock;

@@ -1895,7 +1895,12 @@ hipError_t launch_psd(const BatchView &v, const double *theta, const uint8_t *ac
 // operands are clamped (finite) reads.  Block blk covers iter2 rounds of
 // kWaves x 16 window bins; it writes the -ln L partial nllp[blk], the rate
 // pieces to vpart row blk and the nuisance pieces to row hblocks + blk.
-// P and dP are staged in LDS as [s][4][k].
+// SPLIT (one round per block: small batches, where one model must fill the
+// GPU): the block's waves share 16 window bins and take its pulse-shape tiles
+// in turn (wave w: tiles w, w + kWaves, ...); wave 0 adds their h^T in wave
+// order through LDS and writes the seeds.  P and dP are staged in LDS as
+// [s][4][k].
+template <bool SPLIT>
 __global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_list, const ToyDev *__restrict__ toys,
                                                const ShapeDev *__restrict__ shapes,
                                                const double *__restrict__ theta, int stride,
@@ -1911,6 +1916,7 @@ __global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_li
   __shared__ double red[kWaves][kVLen];
   __shared__ double lds[8];
   __shared__ double leps[GS_MAX_DATASETS];
+  __shared__ dbl4 hred[SPLIT ? kWaves * 64 : 1];
   __shared__ uint32_t bad_s;
   const int t = toy_of(toy_list, blockIdx.y);
   if (active && !active[t]) return;
@@ -1956,9 +1962,10 @@ __global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_li
   const double *cn = cnt + T.cnt_off, *ns = nsum + T.nsum_off;
   double sum = 0.0, A0 = 0.0, A1 = 0.0, A2 = 0.0, a[4] = {0.0, 0.0, 0.0, 0.0};
   uint32_t bad = 0u;
-  for (int r = 0; r < iter2; r++) {
-    const int j0 = ((blockIdx.x * iter2 + r) * kWaves + wave) * 16;
-    if (j0 >= L) break;  // wave-uniform
+  const int nt0 = SPLIT ? wave : 0, nts = SPLIT ? kWaves : 1;  // this wave's pulse-shape tiles
+  for (int r = 0; r < (SPLIT ? 1 : iter2); r++) {
+    const int j0 = SPLIT ? blockIdx.x * 16 : ((blockIdx.x * iter2 + r) * kWaves + wave) * 16;
+    if (j0 >= L) break;  // wave-uniform (block-uniform with SPLIT)
     const int jb = j0 + col;  // this lane's window bin (B column, accumulator column)
     const bool jin = jb < L;
     double f[4], rf[4];
@@ -1968,18 +1975,19 @@ __global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_li
       rf[q] = R[q] * f[q];
     }
     dbl4 hT = {0.0, 0.0, 0.0, 0.0};
-    // summed counts of the lane's cells (clamped addresses): tile 0 now, tile nt + 1 during tile nt
+    // summed counts of the lane's cells (clamped addresses): the wave's first tile now, its
+    // next tile during the current one
     const double *nr = ns + (size_t)min(jb, L - 1) * K;
     double Nn[4];
 #pragma unroll
-    for (int v = 0; v < 4; v++) Nn[v] = nr[min(grp + 4 * v, K - 1)];
-    for (int nt = 0; nt < NT; nt++) {
+    for (int v = 0; v < 4; v++) Nn[v] = nr[min(16 * nt0 + grp + 4 * v, K - 1)];
+    for (int nt = nt0; nt < NT; nt += nts) {
       const int ka = min(16 * nt + col, K - 1);  // A row (pulse-shape bin) of P^T and dP^T
       double Nc[4];
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         Nc[v] = Nn[v];
-        if (nt + 1 < NT) Nn[v] = nr[min(16 * (nt + 1) + grp + 4 * v, K - 1)];
+        if (nt + nts < NT) Nn[v] = nr[min(16 * (nt + nts) + grp + 4 * v, K - 1)];
       }
       dbl4 Mt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -2032,7 +2040,15 @@ __global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_li
         hT = __builtin_amdgcn_mfma_f64_16x16x4f64(pd[(size_t)sa * 4 * K + min(16 * nt + 4 * c + grp, K - 1)], gam[c], hT,
                                                   0, 0, 0);
     }
-    if (jin) {  // hT register v: species grp + 4v of bin jb
+    if (SPLIT) {  // the waves' partial h^T, added in wave order
+      hred[wave * 64 + lane] = hT;
+      __syncthreads();
+      if (wave == 0) {
+        hT = hred[lane];
+        for (int w = 1; w < kWaves; w++) hT += hred[w * 64 + lane];
+      }
+    }
+    if (jin && (!SPLIT || wave == 0)) {  // hT register v: species grp + 4v of bin jb
       const double *bn = Sh.bins + (size_t)(T.lo + jb) * kBinLen;
       const bool outside = Sh.family == kGammaPE && !(bn[0] > 0.0);
 #pragma unroll
@@ -2086,9 +2102,15 @@ __global__ __launch_bounds__(256, 3) void k_bins2(const int *__restrict__ toy_li
 hipError_t launch_bins2(const BatchView &v, const double *theta, double *mu_out, const uint8_t *active,
                         hipStream_t st) {
   if (v.n2d == 0 || v.max_bin_blocks2 == 0) return hipSuccess;  // no joint 2-D toys (all multivariate)
-  hipLaunchKernelGGL(k_bins2, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), sizeof(double) * 4 * v.max_psd_sk, st,
-                     v.list2d, v.toys, v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, v.nsum, v.iter2, active, v.nllp, v.badp,
-                     v.binrec, v.bref, v.H, v.vpart, mu_out);
+  const size_t lds = sizeof(double) * 4 * v.max_psd_sk;
+  if (v.iter2 == 1)
+    hipLaunchKernelGGL(k_bins2<true>, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), lds, st, v.list2d, v.toys, v.shapes,
+                       theta, v.stride, v.F, v.P, v.dP, v.cnt, v.nsum, v.iter2, active, v.nllp, v.badp, v.binrec, v.bref,
+                       v.H, v.vpart, mu_out);
+  else
+    hipLaunchKernelGGL(k_bins2<false>, dim3(v.max_bin_blocks2, v.n2d), dim3(kBlock), lds, st, v.list2d, v.toys,
+                       v.shapes, theta, v.stride, v.F, v.P, v.dP, v.cnt, v.nsum, v.iter2, active, v.nllp, v.badp,
+                       v.binrec, v.bref, v.H, v.vpart, mu_out);
   return hipGetLastError();
 }
 
