@@ -1,6 +1,9 @@
-// gs_exp.h -- FP64 exponential for the per-pair response evaluation.
+// gs_exp.h -- FP64 exponentials for the per-pair response evaluation: exp_tb
+// (below; table-driven, what the pair loops call) and exp_cw, the plain
+// Cody-Waite form it replaced (no table), kept with its own host accuracy
+// test.
 //
-// exp(x) = 2^n p(r), x = n ln2 + r, |r| <= ln2/2 (Cody & Waite argument
+// exp_cw: exp(x) = 2^n p(r), x = n ln2 + r, |r| <= ln2/2 (Cody & Waite argument
 // reduction, with a one-term ln2): n is rounded by adding 1.5 * 2^52 to
 // x / ln2 in one fused operation (the sum has unit spacing, so it holds the
 // nearest integer n, whose two's complement is its low 32 bits), and
