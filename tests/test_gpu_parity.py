@@ -558,6 +558,30 @@ def test_batch_of_2d_toys_with_different_species_counts(gs, orc):
             assert _grad_err(grad[t, : m.n_params], og, m.fd_scale) <= GRAD_TOL, t
 
 
+def test_two_streams_match_one(gs):
+    """A batch with both 1-D and 2-D toys runs its 2-D chain on a second stream; with kernel
+    timing on it keeps one stream. Each toy's arithmetic does not depend on that scheduling, so
+    the two evaluations agree bit for bit, and a repeated evaluation reproduces them."""
+    import torch
+    toys = gsgen.config4(48)
+    batch = gs.Batch(toys)
+    th = np.zeros((len(toys), batch.stride))
+    for t, m in enumerate(toys):
+        th[t, : m.n_params] = gsgen.offset_point(m, 0.5, seed=40 + t)
+    T = torch.tensor(th, dtype=torch.float64, device="cuda")
+    runs = []
+    for prof in (False, True, False):
+        batch.set_profiling(prof)
+        n, g, st = batch.nll_grad(T)
+        torch.cuda.synchronize()
+        runs.append((n.cpu().numpy().copy(), g.cpu().numpy().copy(), st.cpu().numpy().copy()))
+    batch.set_profiling(False)
+    assert (runs[0][2] == 0).all()
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_mixed_batch_fits(gs):
     """Device BFGS over the uneven mix: every toy converges, and sampled toys of every class
     land within 1e-3 sigma of the host BFGS on the same GPU evaluations."""
