@@ -530,14 +530,19 @@ __global__ __launch_bounds__(256, 6) void k_fold1(const FoldItem *__restrict__ i
 // Per-species fold (plain path and the secondary-observable model):
 // F_js = sum_i K_ji w_si, a dense contraction over the cells, runs on the FP64
 // matrix cores.  A workgroup owns kFoldTile = 64 window bins and its 4 waves
-// 16 bins each.  Per step of v_mfma_f64_16x16x4f64 the VALU forms the
-// response of the wave's 16 bins x 4 cells, one pair per lane, as the A
-// operand (lane l: bin l % 16, cell l / 16 of the step); the B operand holds
-// the 4 cells' species weights (lane l: species l % 16 of cell l / 16: w_si
-// for a grid cell, one-hot on its own species for a line cell, zero for the
-// padding of a staged batch); the accumulator holds F[16 bins][16 species]
-// in four registers per lane (lane l, register v: bin l / 16 + 4 v, species
-// l % 16; layouts checked on the device).  Cells come from the compacted hull groups that meet the
+// 16 bins each.  Per step the VALU forms the response of the wave's 16 bins x
+// 4 cells, one pair per lane, as the A operand (lane l: bin l % 16, cell l / 16
+// of the step).  v_mfma_f64_4x4x4f64 takes the A and B operands in the lane
+// layouts of the 16x16x4 form but forms only the four diagonal 4 x 4 blocks of
+// their product: lane l holds row 4 b + l / 16 and column 4 b + l % 4, with
+// b = (l % 16) / 4 (layout checked on the device).  So a B operand that gives
+// every column block the same four species g .. g + 3 (lane l: species
+// 4 g + l % 4 of cell l / 16: w_si for a grid cell, one-hot on its own species
+// for a line cell, zero for the padding of a staged batch) makes one
+// instruction F[16 bins][4 species]: a grid cell of the pulse-shape model,
+// which weighs 8 species, takes two instead of a 16x16x4 over 16 species
+// columns, half of them zero.  The accumulator holds one register per group
+// of four species.  Cells come from the compacted hull groups that meet the
 // tile and are staged through LDS as in the 1-D fold, each with its
 // tile-relative exponent about the reference point of either half-tile (the
 // 32 bins that a 1-D fold tile spans): {A, Eref, B} of the lower half-tile,
@@ -548,18 +553,20 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // One staged batch of nb cells (a multiple of 4: padding slots hold zero
 // weights) against the wave's 16 bins; sb: the staged records offset to the
 // wave's half-tile (3 half), so that a cell's {A, Eref, B} sit at one address
-// plus immediate offsets.
+// plus immediate offsets; ng: the groups of four species the batch's cells
+// weigh (wave-uniform).
 template <bool CLAMP>
-__device__ __forceinline__ dbl4 folds_batch(const double *sb, const double *swt, int nb, double u, double v,
-                                            const ExpK &ec, dbl4 acc) {
-  const int lane = threadIdx.x & 63, kc = lane >> 4, q = lane & 15;
+__device__ __forceinline__ void folds_batch(const double *sb, const double *swt, int nb, int ng, double u, double v,
+                                            const ExpK &ec, double (&acc)[GS_MAX_SPECIES / 4]) {
+  const int lane = threadIdx.x & 63, kc = lane >> 4, q = lane & 3;
   for (int c4 = 0; c4 < nb; c4 += 4) {
     const double *r = sb + 6 * (c4 + kc);
     const double k = dexp<CLAMP>(rel_exponent(r[0], r[2], r[1], u, v), ec);
-    const double w = swt[(c4 + kc) * GS_MAX_SPECIES + q];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(k, w, acc, 0, 0, 0);
+    const double *w = swt + (c4 + kc) * GS_MAX_SPECIES + q;
+#pragma unroll
+    for (int g = 0; g < GS_MAX_SPECIES / 4; g++)
+      if (g < ng) acc[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(k, w[4 * g], acc[g], 0, 0, 0);
   }
-  return acc;
 }
 
 // Weight vector of cell i over the internal species (grid species, then lines).
@@ -575,10 +582,10 @@ __device__ __forceinline__ double cell_weight(const ShapeDev &Sh, int i, int q) 
 // prefetched across the MFMA loop, so it keeps few registers live: the staging
 // loads' latency is hidden by the other workgroups on the compute unit.
 template <int FAM>
-__device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
+__device__ __forceinline__ void folds_cells(const ShapeDev &Sh, const double *__restrict__ R, const int *list,
                                             int n_list, int c_lo, int c_hi, double *srec, double *swt,
                                             const TileRef &rh, const TileEnds &te, int *sclamp, double u,
-                                            double v, const ExpK &ec, dbl4 acc) {
+                                            double v, const ExpK &ec, int ng, double (&acc)[GS_MAX_SPECIES / 4]) {
   static_assert(2 * kStage == kWaves * 64, "one staged cell and half-tile per thread");
   constexpr int kGPB = kStage / kGroup;
   const int tid = threadIdx.x, cs = tid % kStage, half = tid / kStage;
@@ -620,9 +627,11 @@ __device__ __forceinline__ dbl4 folds_cells(const ShapeDev &Sh, const double *__
     for (int e = 0; e < 4; e++) ((double2 *)swt)[(cs * GS_MAX_SPECIES + 8 * half) / 2 + e] = wq[e];
     __syncthreads();
     const double *sb = srec + 3 * (int)(threadIdx.x >> 6 >> 1);
-    acc = *sclamp ? folds_batch<true>(sb, swt, nb, u, v, ec, acc) : folds_batch<false>(sb, swt, nb, u, v, ec, acc);
+    if (*sclamp)
+      folds_batch<true>(sb, swt, nb, ng, u, v, ec, acc);
+    else
+      folds_batch<false>(sb, swt, nb, ng, u, v, ec, acc);
   }
-  return acc;
 }
 
 __global__ __launch_bounds__(256, 6) void k_fold_s(const FoldItem *__restrict__ items, int n_items,
@@ -674,27 +683,29 @@ __global__ __launch_bounds__(256, 6) void k_fold_s(const FoldItem *__restrict__ 
   const int g_end = min(it.cell1, Sh.n_true);
   const int l_lo = max(it.cell0, Sh.n_true), l_hi = it.cell1;  // line cells: few, all evaluated
   const bool gamma = Sh.family == kGammaPE;
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  double acc[GS_MAX_SPECIES / 4] = {0.0, 0.0, 0.0, 0.0};
+  const int S = T.S, ngg = (Sh.Sg + 3) >> 2, ngl = (S + 3) >> 2;  // species groups of grid / line cells
   for (int gb = it.cell0 / kGroup; gb * kGroup < g_end; gb += kWaves * 64) {
     const int n = group_list(ghull + T.ghull_off, gb, min(gb + kWaves * 64, (g_end + kGroup - 1) / kGroup), j0, j1,
                              glist, gcnt);
     if (gamma)
-      acc = folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, te, &sclamp, u, v, ec, acc);
+      folds_cells<kGammaPE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, te, &sclamp, u, v, ec, ngg, acc);
     else
-      acc = folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, te, &sclamp, u, v, ec, acc);
+      folds_cells<kGaussE>(Sh, R, glist, n, it.cell0, g_end, srec, swt, rh, te, &sclamp, u, v, ec, ngg, acc);
   }
   if (gamma)
-    acc = folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, te, &sclamp, u, v, ec, acc);
+    folds_cells<kGammaPE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, te, &sclamp, u, v, ec, ngl, acc);
   else
-    acc = folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, te, &sclamp, u, v, ec, acc);
-  // lane l, register r: bin l / 16 + 4 r of the wave's 16, species l % 16
-  const int q = lane & 15, S = T.S;
+    folds_cells<kGaussE>(Sh, R, nullptr, 0, l_lo, l_hi, srec, swt, rh, te, &sclamp, u, v, ec, ngl, acc);
+  // lane l, register g: bin 4 ((l % 16) / 4) + l / 16 of the wave's 16, species 4 g + l % 4
+  const int bb = it.bin0 + 16 * wave + 4 * ((lane & 15) >> 2) + (lane >> 4);
+  if (bb < T.L) {
+    const bool outside = gamma && !(Sh.bins[(size_t)(T.lo + bb) * kBinLen] > 0.0);  // outside the gamma support
+    double *o = out + T.fs_off + ((long long)it.chunk * T.L + bb) * S;
 #pragma unroll
-  for (int r = 0; r < 4; r++) {
-    const int bb = it.bin0 + 16 * wave + (lane >> 4) + 4 * r;
-    if (bb < T.L && q < S) {
-      const bool outside = gamma && !(Sh.bins[(size_t)(T.lo + bb) * kBinLen] > 0.0);  // outside the gamma support
-      out[T.fs_off + ((long long)it.chunk * T.L + bb) * S + q] = outside ? 0.0 : acc[r];
+    for (int g = 0; g < GS_MAX_SPECIES / 4; g++) {
+      const int sp = 4 * g + (lane & 3);
+      if (sp < S) o[sp] = outside ? 0.0 : acc[g];
     }
   }
 }
