@@ -175,7 +175,7 @@ struct DevBuf {
 
 // Layout knobs of a batch: the split-K target (work-groups the fold and the
 // adjoint aim for when the batch alone is smaller), cells per k_cellgrad block,
-// rounds per k_bins2 / k_hseed block, and waves per adjoint workgroup.
+// rounds of window bins per k_bins2 block, and waves per adjoint workgroup.
 struct Knobs {
   int target_wg, grad_cells, iter2, adj_waves;
 };

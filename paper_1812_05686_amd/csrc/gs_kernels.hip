@@ -1110,7 +1110,7 @@ __global__ __launch_bounds__((NW > 1 ? kWaves : kAdjGroupWaves) * 64) void k_adj
 
 // ---------------------------------------------------- per-species adjoint --
 // Secondary-observable toys: the seed of pair (j, i) is
-// Z_ji = sum_s H_js R_s w_si (H_js = dx_j sum_k P_sk Gam_jk, from k_hseed), a
+// Z_ji = sum_s H_js R_s w_si (H_js = dx_j sum_k P_sk Gam_jk, from k_bins2), a
 // dense contraction over the species that runs on the FP64 matrix cores.  A
 // workgroup takes an adjoint item (64 cells x a window-bin range) and each of
 // its 4 waves 16 of the cells; a wave walks the union of its cells' supports
@@ -1488,9 +1488,9 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
         } else if (pp >= Sh.S + nr) {
           e = GS_MAX_SPECIES + (pp - Sh.S - nr);
         }
-        if (e >= 0 && e < GS_MAX_SPECIES)  // rows of k_hseed
+        if (e >= 0 && e < GS_MAX_SPECIES)  // rate pieces: the first hblocks rows
           for (int blk = p; blk < T.hblocks; blk += 64) a += vp[(size_t)blk * kVLen + e];
-        else if (e >= 0)  // rows of k_bins2
+        else if (e >= 0)  // nuisance pieces: the next bin_blocks rows
           for (int blk = p; blk < T.bin_blocks; blk += 64) a += vp[(size_t)(T.hblocks + blk) * kVLen + e];
       }
       a = wave_sum(a);
