@@ -49,15 +49,15 @@ KERNEL_NAMES = {"fold": "k_fold1", "adj": "k_adj<1>", "folds": "k_fold_s", "adj_
 def kernel_names(adj_waves):
     """The pair kernels' names; the 1-D adjoint is the template the batch's layout runs."""
     return dict(KERNEL_NAMES, adj=f"k_adj<{adj_waves}>")
-# HBM bytes per launch of the pair kernels on the 16384-toy mixed batch (the headline step, in
-# the layout the autotuner keeps), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE;
+# HBM bytes per launch of the pair kernels on the 16384-toy mixed batch (the headline step; both
+# 1-D adjoint layouts the autotuner chooses between), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE;
 # KiB per dispatch) scaled by what the same counters read for a plain 512 MiB device copy
 # (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the kernel sources they were
 # taken on: any change to those sources reports traffic as null.
-TRAFFIC = {"sources_sha256": "544b3f8283c2e0fac536dd2026c06d7c9012993e7f1a8fa8584aab4b10afe49c",
-           "workload": "mix16384", "kernels": {"k_fold1": 1342833203, "k_adj<1>": 2430154916,
-                                                "k_adj<4>": 2360073505, "k_fold_s": 598600699,
-                                                "k_adj_s": 799931884}}
+TRAFFIC = {"sources_sha256": "c44a4c6988a63db344f0a866657465e34f78effa3f42b548812cdf4cb5defcd8",
+           "workload": "mix16384", "kernels": {"k_fold1": 1342136539, "k_adj<1>": 2430287354,
+                                                "k_adj<4>": 2360074048, "k_fold_s": 599757676,
+                                                "k_adj_s": 799932300}}
 
 
 def strip_c_comments(text):
@@ -257,7 +257,11 @@ def mixed_batch(gs, gsgen, torch, args):
     batch = gs.Batch(toys)
     theta = torch.tensor(theta_of(toys, batch.stride), dtype=torch.float64, device="cuda")
     nll, grad, st = buffers(len(toys), batch.stride, torch)
-    tune = batch.autotune(theta, reps=2)
+    if args.mix_layout:
+        batch.set_layout(*(int(x) for x in args.mix_layout.split(",")))
+        tune = dict(batch.layout(), forced=True)
+    else:
+        tune = batch.autotune(theta, reps=2)
     log(f"bench: mix autotune {tune}")
     el = timed_steps(batch, theta, nll, grad, st, args.steps, args.warmup, torch)
     kt = profiled_kernels(batch, theta, nll, grad, st, max(2, args.steps // 4), torch)
@@ -505,6 +509,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fits", action="store_true")
     ap.add_argument("--no-study", action="store_true", help="skip the 4096-toy study and the single models")
+    ap.add_argument("--mix-layout", type=str, default="", metavar="TW,GC,IT,AW",
+                    help="put this work layout in force for the mix instead of autotuning it (one of its candidates: "
+                         "split-K target, cells per gradient block, rounds per 2-D block, waves per 1-D adjoint item)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (reference for HBM byte counters)")
     args = ap.parse_args()
