@@ -226,10 +226,9 @@ struct gs_batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // batches with both 1-D and 2-D toys: the 2-D chain runs on a stream of its
   // own, forked from the caller's stream after the cell records and joined
-  // before the gradient chain (default priority, as every stream here);
-  // ev_mid holds the 1-D adjoint until the 2-D seeds are formed
+  // before the gradient chain (default priority, as every stream here)
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t graph = nullptr;
   int graph_k = 0, graph_max_iter = -1;
   double graph_tol = -1.0;
@@ -249,7 +248,6 @@ struct gs_batch {
     if (side) (void)hipStreamDestroy(side);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
-    if (ev_mid) (void)hipEventDestroy(ev_mid);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (h_count) (void)hipHostFree(h_count);
@@ -842,7 +840,6 @@ gs_status build_batch(const gs_model_desc *descs, int n_toys, int device, gs_bat
     HIP_TRY(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&B->ev_mid, hipEventDisableTiming));
   }
   if (!nsum_h.empty()) {
     double *ns;
@@ -902,15 +899,11 @@ gs_status enqueue_nll_grad(gs_batch *B, const double *d_theta, double *d_nll, do
     HIP_TRY(launch_psd(v, d_theta, active, s2));
     HIP_TRY(timed(B, GS_K_NLL, s2, [&] { return launch_bins2(v, d_theta, d_mu, active, s2); }));
     if (v.has_mv) HIP_TRY(timed(B, GS_K_NLL, s2, [&] { return launch_mv(v, d_theta, d_mu, active, s2); }));
-    if (fork && d_grad) HIP_TRY(hipEventRecord(B->ev_mid, s2));
     if (d_grad) HIP_TRY(timed(B, GS_K_ADJS, s2, [&] { return launch_adj(v, true, active, s2); }));
   }
   if (v.has_1d) {
     HIP_TRY(timed(B, GS_K_FOLD, st, [&] { return launch_fold(v, false, kOnly1D, active, st); }));
     HIP_TRY(timed(B, GS_K_NLL, st, [&] { return launch_bins1(v, d_mu, active, st); }));
-    // the 1-D adjoint waits for the 2-D seeds: run beside it, the short
-    // k_bins2 found few free slots and held back the per-species adjoint
-    if (fork && d_grad) HIP_TRY(hipStreamWaitEvent(st, B->ev_mid, 0));
     if (d_grad) HIP_TRY(timed(B, GS_K_ADJ, st, [&] { return launch_adj(v, false, active, st); }));
   }
   if (fork) {
