@@ -381,6 +381,17 @@ def single_model(gs, torch, m, reps=200, fits=True):
     out = {"us_per_eval": round(el * 1e6 / reps, 2), "evals_per_s": round(reps / el, 1),
            "kernel_us": {k: round(v[0] * 1e3 / v[1], 2) for k, v in kt.items() if v[1]},
            "kernels": kernel_rooflines(kt, b.mesh_counts(), b.layout()["adj_waves"])}
+    if fits:  # the same fit on the device BFGS (graph of evaluation + step launches), as a batch of one
+        th0 = torch.tensor(theta_of([m], b.stride, "theta0"), dtype=torch.float64, device="cuda")
+        free, sc = b.free_masks([m]), b.scales([m])
+        b.fit(th0, sc, free=free)  # warm: builds the captured graph
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = b.fit(th0, sc, free=free)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ta
+        out["device_fit"] = dict(fits_per_s=round(1.0 / el, 3), seconds=round(el, 5), iters=int(r["iters"][0]),
+                                 converged=bool(int(r["status"][0]) & 32), nll=float(r["nll"][0]))
     del b
     if fits:
         model = gs.Model(m)
