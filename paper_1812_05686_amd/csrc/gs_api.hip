@@ -1434,6 +1434,7 @@ gs_status gs_fit(gs_model *M, const double *theta0, const gs_fit_opts *o, double
 static gs_status qn_setup(gs_batch *B) {
   if (B->qn_ready) return GS_OK;
   const int n = B->n_toys, P = B->stride;
+  if (P > GS_MAX_PARAMS) return fail(GS_ERR_UNSUPPORTED, "%d parameters per toy (at most %d)", P, GS_MAX_PARAMS);
   QNView &q = B->q;
   q.P = P;
   q.stride = P;

@@ -884,10 +884,12 @@ __global__ __launch_bounds__(256) void k_bins1(const int *__restrict__ toy_list,
     const double *fp = fpart + T.fpart_off + b;
     double s1 = 0.0;
     int c = 0;
-    for (; c + 4 <= T.fold_chunks; c += 4) {
-      const double p0 = fp[(long long)c * T.L], p1 = fp[(long long)(c + 1) * T.L], p2 = fp[(long long)(c + 2) * T.L],
-                   p3 = fp[(long long)(c + 3) * T.L];
-      s1 = (((s1 + p0) + p1) + p2) + p3;
+    for (; c + 8 <= T.fold_chunks; c += 8) {  // eight chunks' loads before their adds (in chunk order)
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) pv[u] = fp[(long long)(c + u) * T.L];
+#pragma unroll
+      for (int u = 0; u < 8; u++) s1 += pv[u];
     }
     for (; c < T.fold_chunks; c++) s1 += fp[(long long)c * T.L];
     const double mu1 = T.gen ? s1 : dx * s1;  // the direct path's partials are bin contents already
@@ -1363,12 +1365,31 @@ __global__ __launch_bounds__(256, 4) void k_cellgrad(const int *__restrict__ toy
   for (int c = 0; c < CPT; c++) {
     const int i = (blockIdx.x * CPT + c) * kBlock + threadIdx.x;
     if (i >= Sh.n_cell) break;
+    // the adjoint chunks' partials, summed in chunk order; U chunks' loads are
+    // issued before their adds, so a single model's many chunks (split-K) do not
+    // wait out one load latency each
+    constexpr int U = CPT == 1 ? 8 : 2;
+    const double *ap = apart + T.apart_off + (long long)i * 3;
+    const long long cs = (long long)T.n_cell * 3;
     double A0 = 0.0, A1 = 0.0, A2 = 0.0;
-    for (int c = 0; c < T.adj_chunks; c++) {
-      const double *a = apart + T.apart_off + ((long long)c * T.n_cell + i) * 3;
-      A0 += a[0];
-      A1 += a[1];
-      A2 += a[2];
+    int k = 0;
+    for (; k + U <= T.adj_chunks; k += U) {
+      double a[U][3];
+#pragma unroll
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int q = 0; q < 3; q++) a[u][q] = ap[(k + u) * cs + q];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        A0 += a[u][0];
+        A1 += a[u][1];
+        A2 += a[u][2];
+      }
+    }
+    for (; k < T.adj_chunks; k++) {
+      A0 += ap[k * cs];
+      A1 += ap[k * cs + 1];
+      A2 += ap[k * cs + 2];
     }
     Moments mo;
     moments(fam, th + Sh.S, Sh.birks_A, Sh.cellE[i], mo);
@@ -1476,26 +1497,43 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
   if (grad) {
     const int nr = Sh.family == kTemplate ? 0 : Sh.family == kGaussE ? 2 : 5;
     const double *vp = vpart + T.vpart_off * kVLen;
-    for (int pp = wave; pp < T.P; pp += kWaves) {  // wave-uniform
-      double a = 0.0;
-      if (pp < Sh.S + nr)
-        for (int b = p; b < T.cell_blocks; b += 64) a += gpart[(T.gpart_off + b) * kGradLen + pp];
-      if (T.two_d) {  // pieces that need no fold, from the 2-D block partials
+    // this wave's entries pp = wave + kWaves q, q < nq; the cell-gradient block
+    // partials of all of them are loaded in one pass over the blocks, so their
+    // loads are in flight together
+    constexpr int kPW = (kGradLen + kWaves - 1) / kWaves;
+    const int nq = T.P > wave ? (T.P - wave + kWaves - 1) / kWaves : 0;
+    double a[kPW];
+#pragma unroll
+    for (int q = 0; q < kPW; q++) a[q] = 0.0;
+    for (int b = p; b < T.cell_blocks; b += 64) {
+      const double *g = gpart + (T.gpart_off + b) * kGradLen;
+#pragma unroll
+      for (int q = 0; q < kPW; q++)
+        if (q < nq && wave + kWaves * q < Sh.S + nr) a[q] += g[wave + kWaves * q];
+    }
+    if (T.two_d) {  // pieces that need no fold, from the 2-D block partials
+#pragma unroll
+      for (int q = 0; q < kPW; q++) {
+        const int pp = wave + kWaves * q;
         int e = -1;
-        if (pp < Sh.S) {
-          for (int q = 0; q < Sh.S; q++)
-            if (Sh.sp_of[q] == pp) e = q;
+        if (q >= nq) {
+        } else if (pp < Sh.S) {
+          for (int r = 0; r < Sh.S; r++)
+            if (Sh.sp_of[r] == pp) e = r;
         } else if (pp >= Sh.S + nr) {
           e = GS_MAX_SPECIES + (pp - Sh.S - nr);
         }
         if (e >= 0 && e < GS_MAX_SPECIES)  // rate pieces: the first hblocks rows
-          for (int blk = p; blk < T.hblocks; blk += 64) a += vp[(size_t)blk * kVLen + e];
+          for (int blk = p; blk < T.hblocks; blk += 64) a[q] += vp[(size_t)blk * kVLen + e];
         else if (e >= 0)  // nuisance pieces: the next bin_blocks rows
-          for (int blk = p; blk < T.bin_blocks; blk += 64) a += vp[(size_t)(T.hblocks + blk) * kVLen + e];
+          for (int blk = p; blk < T.bin_blocks; blk += 64) a[q] += vp[(size_t)(T.hblocks + blk) * kVLen + e];
       }
-      a = wave_sum(a);
-      if (p == 0) gsum[pp] = a;
     }
+    wave_sum_n(a, nq);
+    if (p == 0)
+#pragma unroll
+      for (int q = 0; q < kPW; q++)
+        if (q < nq) gsum[wave + kWaves * q] = a[q];
   }
   if (wave == 0) {
     double part = 0.0;
@@ -1595,8 +1633,19 @@ __global__ __launch_bounds__(256) void k_reduceF(const int *__restrict__ toy_lis
   if (e >= T.L * T.S) return;
   const int b = e / T.S, sp = e - b * T.S;
   const double dx = Sh.bins[(size_t)(T.lo + b) * kBinLen + 1];
+  // the fold chunks' partials in chunk order, eight chunks' loads issued before their adds
+  const double *fp = fspart + T.fs_off + (long long)b * T.S + sp;
+  const long long cs = (long long)T.L * T.S;
   double acc = 0.0;
-  for (int c = 0; c < T.fold_chunks; c++) acc += fspart[T.fs_off + ((long long)c * T.L + b) * T.S + sp];
+  int c = 0;
+  for (; c + 8 <= T.fold_chunks; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = fp[(c + u) * cs];
+#pragma unroll
+    for (int u = 0; u < 8; u++) acc += v[u];
+  }
+  for (; c < T.fold_chunks; c++) acc += fp[c * cs];
   F[fh_at(T, sp, b)] = T.gen ? acc : dx * acc;
 }
 

@@ -60,6 +60,25 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
   uint32_t status = q.status[t];
   int phase = q.phase[t], iter = q.iter[t];
   bool new_direction = false;
+  // lane p's row of the inverse Hessian, held in registers from its first use
+  // in this step to its one write-back (P <= GS_MAX_PARAMS)
+  double Hr[GS_MAX_PARAMS];
+  bool have_row = false;
+  auto load_row = [&] {
+#pragma unroll
+    for (int c = 0; c < GS_MAX_PARAMS; c++) Hr[c] = lane && c < P ? q.H[(r + p) * P + c] : 0.0;
+    have_row = true;
+  };
+  auto store_row = [&] {
+#pragma unroll
+    for (int c = 0; c < GS_MAX_PARAMS; c++)
+      if (lane && c < P) q.H[(r + p) * P + c] = Hr[c];
+  };
+  auto reset_row = [&] {  // the diagonal metric (lanes past P read nothing)
+    const double h0p = lane ? q.h0[r + p] : 0.0;
+#pragma unroll
+    for (int c = 0; c < GS_MAX_PARAMS; c++) Hr[c] = c == p ? h0p : 0.0;
+  };
   // a point whose gradient has no FP64 value (GS_ST_GRAD_RANGE) is not taken
   const bool usable = isfinite(ft) && !(st_eval[t] & GS_ST_GRAD_RANGE);
   if (phase == kPhaseInit) {
@@ -80,27 +99,29 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
       // accept the trial point; BFGS update of the inverse Hessian
       const double s = fr ? xtp - xp : 0.0, y = fr ? gtp - gp : 0.0;
       const double sy = wave_sum(s * y), ss = wave_sum(s * s), yy = wave_sum(y * y);
+      load_row();
       if (sy > 1e-12 * sqrt(ss * yy)) {
         // Hy_p = sum_c H_pc y_c: lane p needs every y_c, read through shuffles
         double hy = 0.0;
-        for (int c = 0; c < P; c++) {
-          const double yc = __shfl(y, c, 64);
-          if (lane) hy = __fma_rn(q.H[(r + p) * P + c], yc, hy);
-        }
+#pragma unroll
+        for (int c = 0; c < GS_MAX_PARAMS; c++)
+          if (c < P) {
+            const double yc = __shfl(y, c, 64);
+            if (lane) hy = __fma_rn(Hr[c], yc, hy);
+          }
         const double yHy = wave_sum(y * hy);
         const double rho = 1.0 / sy, k2 = rho + rho * rho * yHy;
-        for (int c = 0; c < P; c++) {
-          const double sc = __shfl(s, c, 64), hyc = __shfl(hy, c, 64);
-          if (lane) {
-            double &h = q.H[(r + p) * P + c];
-            h += k2 * s * sc - rho * (hy * sc + s * hyc);
+#pragma unroll
+        for (int c = 0; c < GS_MAX_PARAMS; c++)
+          if (c < P) {
+            const double sc = __shfl(s, c, 64), hyc = __shfl(hy, c, 64);
+            if (lane) Hr[c] += k2 * s * sc - rho * (hy * sc + s * hyc);
           }
-        }
       } else {
-        for (int c = 0; c < P; c++)
-          if (lane) q.H[(r + p) * P + c] = c == p ? q.h0[r + p] : 0.0;
+        reset_row();
         status |= GS_ST_BFGS_RESET;
       }
+      store_row();
       xp = xtp;
       f = ft;
       gp = gtp;
@@ -132,11 +153,14 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
   }
   // new search direction d = -H g from the accepted point
   if (new_direction) {
+    if (!have_row) load_row();
     double hg = 0.0;
-    for (int c = 0; c < P; c++) {
-      const double gc = __shfl(gp, c, 64);
-      if (lane) hg = __fma_rn(q.H[(r + p) * P + c], gc, hg);
-    }
+#pragma unroll
+    for (int c = 0; c < GS_MAX_PARAMS; c++)
+      if (c < P) {
+        const double gc = __shfl(gp, c, 64);
+        if (lane) hg = __fma_rn(Hr[c], gc, hg);
+      }
     double d = fr ? -hg : 0.0;
     const double edm = -0.5 * wave_sum(gp * d);
     uint32_t done = 0;
@@ -146,8 +170,8 @@ __global__ __launch_bounds__(64) void k_qn_step(QNView q, const int *__restrict_
       done = GS_ST_MAXITER;
     double slope = wave_sum(gp * d);
     if (!done && !(slope < 0.0)) {  // not a descent direction: restart from the diagonal metric
-      for (int c = 0; c < P; c++)
-        if (lane) q.H[(r + p) * P + c] = c == p ? q.h0[r + p] : 0.0;
+      reset_row();
+      store_row();
       status |= GS_ST_BFGS_RESET;
       d = fr ? -q.h0[r + p] * gp : 0.0;
       slope = wave_sum(gp * d);
