@@ -102,21 +102,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // The same for the first n of N values (n wave-uniform): the six butterfly
-// addresses are formed once and shared; the values go one after another, so
-// only one value's partial sums are live at a time.
-template <int N>
+// addresses are formed once and shared.  G values go through the butterfly
+// together (their exchanges in flight at once, for latency); G = 1 keeps only
+// one value's partial sums live at a time (for registers).  Every value takes
+// the same six steps in the same order whatever G is.
+template <int N, int G = 1>
 __device__ __forceinline__ void wave_sum_n(double (&v)[N], int n) {
   const int lane = lane_id();
   int addr[6];
 #pragma unroll
   for (int k = 0; k < 6; k++) addr[k] = (lane ^ (32 >> k)) << 2;
 #pragma unroll
-  for (int q = 0; q < N; q++)
-    if (q < n) {
-      double x = v[q];
+  for (int q0 = 0; q0 < N; q0 += G)
+    if (q0 < n) {
 #pragma unroll
-      for (int k = 0; k < 6; k++) x += xor_fetch(x, addr[k]);
-      v[q] = x;
+      for (int k = 0; k < 6; k++) {
+        double f[G];
+#pragma unroll
+        for (int u = 0; u < G; u++)
+          if (q0 + u < N && q0 + u < n) f[u] = xor_fetch(v[q0 + u], addr[k]);
+#pragma unroll
+        for (int u = 0; u < G; u++)
+          if (q0 + u < N && q0 + u < n) v[q0 + u] += f[u];
+      }
     }
 }
 
@@ -1441,8 +1449,10 @@ __global__ __launch_bounds__(256, 4) void k_cellgrad(const int *__restrict__ toy
   }
   // every entry summed over the wave, then over the block's waves in a fixed order
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  wave_sum_n(gR, Sh.S);
-  wave_sum_n(gP, nr);
+  // (one cell per thread: a small batch or one model, where the reduction's
+  // latency shows; four values go through the butterfly together)
+  wave_sum_n<GS_MAX_SPECIES, CPT == 1 ? 4 : 1>(gR, Sh.S);
+  wave_sum_n<5, CPT == 1 ? 4 : 1>(gP, nr);
   if (lane == 0) {
 #pragma unroll
     for (int s = 0; s < GS_MAX_SPECIES; s++)
@@ -1529,7 +1539,7 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
           for (int blk = p; blk < T.bin_blocks; blk += 64) a[q] += vp[(size_t)(T.hblocks + blk) * kVLen + e];
       }
     }
-    wave_sum_n(a, nq);
+    wave_sum_n<kPW, 3>(a, nq);
     if (p == 0)
 #pragma unroll
       for (int q = 0; q < kPW; q++)
