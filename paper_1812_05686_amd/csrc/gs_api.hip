@@ -371,16 +371,23 @@ static std::vector<Knobs> layout_candidates(const gs_batch *B) {
 // The default layout: a split-K target of kTargetWG work-groups; four cells per
 // k_cellgrad thread, kIter2Large 2-D rounds and one-wave adjoint workgroups
 // once the batch gives at least kGradLargeBlocks blocks of kBlock cells, cell
-// tiles of the adjoint (so one model still fills the GPU).
+// tiles of the adjoint (so one model still fills the GPU).  A batch with both
+// 1-D and 2-D toys keeps four-wave adjoint workgroups: beside the 2-D chain on
+// the second stream they gave the faster step and, by more, the faster batched
+// fits (their graphs run the same layout).
 static Knobs default_knobs(const gs_batch *B) {
   long long grad_blocks = 0, bins2_blocks = 0, adj_tiles = 0;
+  bool has_1d = false;
   for (const ToyDev &T : B->toys_h) {
     grad_blocks += (T.n_cell + kBlock - 1) / kBlock;
     adj_tiles += (T.n_cell + kTile - 1) / kTile;
     if (T.two_d) bins2_blocks += ((long long)T.L * T.K + kBlock - 1) / kBlock;
+    has_1d = has_1d || (!T.two_d && !T.tmpl);
   }
+  const bool forked = has_1d && bins2_blocks > 0;
   return {kTargetWG, grad_blocks >= kGradLargeBlocks ? kGradCellsLarge : kBlock,
-          bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1, adj_tiles >= kGradLargeBlocks ? 1 : kWaves};
+          bins2_blocks >= kGradLargeBlocks ? kIter2Large : 1,
+          adj_tiles >= kGradLargeBlocks && !forked ? 1 : kWaves};
 }
 
 static void grow(LayoutSizes &a, const LayoutSizes &b) {
