@@ -354,8 +354,10 @@ gs_status gs_model_set_log_cut(gs_model *m, double log_cut);
  * candidate in the product {2048, 1024, 4096, 8192} x {256, 1024} x {1, 8
  * (secondary-observable batches only)} x {1, 4}, where a target that splits
  * the batch into the same chunk counts as an earlier one is left out; the
- * default is target 2048 with the other three chosen from the batch's size.  Results do not depend
- * on the layout beyond the order of floating-point sums.
+ * default is target 2048 with the other three chosen from the batch's size
+ * (four waves per adjoint workgroup whenever the batch holds both 1-D and
+ * secondary-observable toys).  Results do not depend on the layout beyond
+ * the order of floating-point sums.
  *
  * gs_batch_set_layout puts one candidate in force (GS_ERR_ARG if it is not a
  * candidate).  gs_batch_autotune times gs_nll_grad_batched at d_theta under
