@@ -52,9 +52,10 @@ def kernel_names(adj_waves):
 # HBM bytes per launch of the pair kernels on the 16384-toy mixed batch (the headline step; both
 # 1-D adjoint layouts the autotuner chooses between), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE;
 # KiB per dispatch) scaled by what the same counters read for a plain 512 MiB device copy
-# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the kernel sources they were
-# taken on: any change to those sources reports traffic as null.
-TRAFFIC = {"sources_sha256": "731dd1f5b65838fb771e926a53df57c97756ca2474694fe75260bb0491ef8d48",
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  They hold only for the kernel sources named by the
+# sha (taken on sources that build to the same library byte for byte): any change to those
+# sources reports traffic as null.
+TRAFFIC = {"sources_sha256": "cc0e859ce3cb040b256f17f9714b75003478ff57a68098b013f524e53f93fa6d",
            "workload": "mix16384", "kernels": {"k_fold1": 1342681031, "k_adj<1>": 2430168712,
                                                 "k_adj<4>": 2360077300, "k_fold_s": 598661994,
                                                 "k_adj_s": 799931802}}

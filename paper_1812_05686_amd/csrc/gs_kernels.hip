@@ -1525,12 +1525,11 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ toy_list
 #pragma unroll
       for (int q = 0; q < kPW; q++) {
         const int pp = wave + kWaves * q;
-        int e = -1;
-        if (q >= nq) {
-        } else if (pp < Sh.S) {
+        int e = -1;  // the entry's column of the 2-D partials (none past this wave's entries)
+        if (q < nq && pp < Sh.S) {
           for (int r = 0; r < Sh.S; r++)
             if (Sh.sp_of[r] == pp) e = r;
-        } else if (pp >= Sh.S + nr) {
+        } else if (q < nq && pp >= Sh.S + nr) {
           e = GS_MAX_SPECIES + (pp - Sh.S - nr);
         }
         if (e >= 0 && e < GS_MAX_SPECIES)  // rate pieces: the first hblocks rows
